@@ -1,0 +1,225 @@
+"""Benchmark: pipelined block Krylov time stepping on one MI355X.
+
+Workload (the 128^3 heterogeneous-diffusion case): 3-D unit cube, 128^3 cell-centred FV cells,
+7-point diffusion with a lognormal coefficient (log-mean 0, log-std 2, Gaussian correlation
+length 8 cells, seed 0, harmonic face means), homogeneous Dirichlet boundary, implicit Euler
+with tau = 1e-3 from u0 = sin(pi x) sin(pi y) sin(pi z).  All inputs are seeded and synthetic.
+
+A "step" is one accepted time step of Algorithm 1 (residual, block solves, shift), each step
+converged to a front-column relative residual of 1e-8.  The block form uses k time columns
+with FP32 block-CG inner solves (Jacobi) inside the FP64 outer refinement; the plain form is the
+same library at k = 1 in FP64 (inner = outer = 1e-8, i.e. one solve per step).
+
+Prints ONE JSON line.  `value` = DOF * accepted steps / second of the block form, inputs resident
+in HBM before the timed region; `roofline` is the block operator (SpMM) kernel of the inner
+solves, its average launch time measured with HIP events inside the library over the timed
+region; `cpu_baseline` is the FP64 CPU oracle stepping a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=16)
+    p.add_argument("--warmup", type=int, default=16)
+    p.add_argument("--n", type=int, default=128)
+    p.add_argument("--k", type=int, default=16)
+    p.add_argument("--precision", choices=["f32", "f64"], default="f32")
+    p.add_argument("--inner-rtol", type=float, default=1e-2)
+    p.add_argument("--plain-steps", type=int, default=8)
+    p.add_argument("--no-plain", action="store_true")
+    p.add_argument("--no-cpu", action="store_true")
+    p.add_argument("--cpu-steps", type=int, default=1)
+    p.add_argument("--sweep", type=str, default="", help="comma list of extra k values to time (block form)")
+    return p.parse_args()
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_table(bkts, ctx):
+    out = {}
+    for name in bkts.KERNELS:
+        n, ms, by = bkts.bkts_profile_query(ctx, name)
+        if n:
+            out[name] = {"launches": n, "avg_us": 1e3 * ms / n, "total_ms": ms,
+                         "GBps": (by / 1e9) / (ms / 1e3) if ms > 0 else None}
+    return out
+
+
+def traffic_for(kernel_src, launches_bytes):
+    """Counter-based HBM bytes per launch, if a committed counter summary matches this kernel source."""
+    path = os.path.join(ROOT, "profiles", "spmm_counters.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        d = json.load(open(path))
+        sha = hashlib.sha256(open(kernel_src, "rb").read()).hexdigest()
+        if d.get("source_sha256") != sha:
+            return None
+        return d.get("hbm_bytes_per_launch")
+    except Exception:
+        return None
+
+
+def run_form(torch, bkts, ctx, op, y0, k, precision, inner_rtol, warmup, steps, profile):
+    """Time `steps` accepted steps of a persistent stepper after `warmup` untimed ones."""
+    tc = bkts.bkts_tc_create(ctx, bkts.BKTS_IE, k, 1e-3)
+    st = bkts.bkts_stepper_create(ctx, op, tc, y0)
+    prec = bkts.BKTS_PRECISION_F32_REFINE if precision == "f32" else bkts.BKTS_PRECISION_F64
+    inner = bkts.solve_opts(precision=prec, rtol=inner_rtol, inner_rtol=inner_rtol, maxit=100000)
+    N = y0.numel()
+    try:
+        if warmup:
+            bkts.bkts_stepper_advance(st, warmup, inner=inner, outer_rtol=1e-8, max_outer=400)
+        hist = torch.empty((steps, N), dtype=torch.float64, device="cuda")
+        bkts.bkts_profile_enable(ctx, profile)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        info = bkts.bkts_stepper_advance(st, steps, inner=inner, outer_rtol=1e-8, max_outer=400, y_hist=hist)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        kt = kernel_table(bkts, ctx) if profile else {}
+        bkts.bkts_profile_enable(ctx, False)
+        return dict(seconds=dt, info=info, kernels=kt, hist=hist, value=N * steps / dt)
+    finally:
+        bkts.bkts_stepper_destroy(st)
+        bkts.bkts_tc_destroy(tc)
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only: the sharded path (halo exchange over RCCL, "
+                                   "k x k all-reduce) is designed but not built; run with --gpus 1"}))
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_2504_02117_amd import bkts, inputs
+
+    n = (a.n, a.n, a.n)
+    N = a.n ** 3
+    log(f"inputs {n}")
+    kap = inputs.lognormal_field(n, 0.0, 2.0, 8.0, 0)
+    u0 = inputs.sin_product(n)
+    ctx = bkts.bkts_ctx_create(0, torch.cuda.current_stream())
+    kd = torch.from_numpy(kap).cuda()
+    y0 = torch.from_numpy(u0).cuda()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    op = bkts.bkts_fv_assemble(ctx, n, kappa=kd, fmt=bkts.BKTS_FMT_SELL)
+    setup_s = time.perf_counter() - t
+    _, nnz = bkts.bkts_op_info(op)
+
+    log(f"block form k={a.k} {a.precision}: warmup {a.warmup}, timed {a.steps}")
+    blk = run_form(torch, bkts, ctx, op, y0, a.k, a.precision, a.inner_rtol, a.warmup, a.steps, True)
+    log(f"  {blk['value']:.4g} DOF*steps/s, outer={blk['info'].outer_iterations} "
+        f"krylov={blk['info'].krylov_iterations}")
+    result_hist = blk["hist"][-2:].double().cpu().numpy() if a.steps >= 2 else None
+
+    plain = None
+    if not a.no_plain:
+        log(f"plain form k=1 f64: timed {a.plain_steps}")
+        pl = run_form(torch, bkts, ctx, op, y0, 1, "f64", 1e-8, 1, a.plain_steps, False)
+        plain = {"value": pl["value"], "ms_per_step": 1e3 * pl["seconds"] / a.plain_steps,
+                 "krylov_iterations_per_step": pl["info"].krylov_iterations / a.plain_steps,
+                 "config": "k=1, FP64 block CG (= CG) + Jacobi, inner = outer = 1e-8"}
+        log(f"  {pl['value']:.4g} DOF*steps/s")
+
+    sweep = {}
+    for ks in [int(v) for v in a.sweep.split(",") if v.strip()]:
+        r = run_form(torch, bkts, ctx, op, y0, ks, a.precision, a.inner_rtol, a.warmup, a.steps, False)
+        sweep[str(ks)] = {"value": r["value"], "outer": r["info"].outer_iterations,
+                          "krylov": r["info"].krylov_iterations}
+        log(f"  sweep k={ks}: {r['value']:.4g}")
+
+    spmm = blk["kernels"].get("spmm")
+    roof = None
+    if spmm:
+        sv = 4 if a.precision == "f32" else 8
+        bytes_per_launch = nnz * (sv + 4) + 4 * (N + 1) + 2 * N * a.k * sv
+        avg_s = spmm["avg_us"] * 1e-6
+        achieved = bytes_per_launch / avg_s / 1e9
+        roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS,
+                "traffic": traffic_for(os.path.join(ROOT, "paper_2504_02117_amd", "csrc", "spmm.hip"), None),
+                "kernel": f"spmm_kernel<{'float' if sv == 4 else 'double'},{a.k},{16 // sv},SELL>",
+                "algorithmic_bytes_per_launch": bytes_per_launch, "avg_launch_us": spmm["avg_us"],
+                "launches": spmm["launches"]}
+
+    cpu = None
+    err = None
+    if not a.no_cpu or result_hist is not None:
+        from oracle import fv, stepping
+        log("oracle assembly (CPU)")
+        K, b = fv.assemble_linear(n, kappa=kap)
+        if result_hist is not None:
+            # FP64 oracle residual of the last accepted step of the timed block run
+            import scipy.sparse as sp
+            J = (sp.identity(N) / 1e-3 + K).tocsr()
+            r = J @ result_hist[1] - result_hist[0] / 1e-3 - b
+            err = float(np.linalg.norm(r) / np.linalg.norm(result_hist[0] / 1e-3 + b))
+        if not a.no_cpu:
+            from threadpoolctl import threadpool_limits
+            log(f"oracle time stepping on the host: {a.cpu_steps} IE step(s), Jacobi-CG to 1e-8")
+            with threadpool_limits(1):
+                t = time.perf_counter()
+                stepping.dirk_linear(K, b, u0, 1e-3, "ie", a.cpu_steps, solver="cg", rtol=1e-8)
+                cs = time.perf_counter() - t
+            cpu = {"value": N * a.cpu_steps / cs, "unit": "DOF*timesteps/s", "cores": 1, "kind": "oracle",
+                   "sample": f"{a.cpu_steps} implicit-Euler step(s) of the same 128^3 workload, scipy Jacobi-CG "
+                             f"to a 1e-8 relative residual, {cs:.1f} s, 1 thread (BLAS limited to 1)",
+                   "cpu_model": _cpu_model(), "nproc": os.cpu_count()}
+
+    out = {
+        "metric": "DOF·timesteps/s to 1e-8 residual (block vs plain); SpMM HBM GB/s; p50/p99",
+        "value": blk["value"], "unit": "DOF*timesteps/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+        "ms_per_step": 1e3 * blk["seconds"] / a.steps, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32 inner / f64 outer" if a.precision == "f32" else "f64",
+        "data": "synthetic (seeded lognormal field, sin-product initial state)",
+        "config": {"workload": f"heterogeneous diffusion {a.n}^3 FV 7-point, lognormal kappa (log-std 2, corr. 8 "
+                               f"cells), implicit Euler tau=1e-3, block width k={a.k}, "
+                               f"{'FP32-inner + FP64 refinement' if a.precision == 'f32' else 'FP64'} to 1e-8",
+                   "N": N, "nnz": nnz, "k": a.k, "inner_rtol": a.inner_rtol, "setup_s": setup_s},
+        "outer_iterations": blk["info"].outer_iterations, "krylov_iterations": blk["info"].krylov_iterations,
+        "oracle_rel_residual_last_step": err,
+        "plain": plain,
+        "speedup_vs_plain": (blk["value"] / plain["value"]) if plain else None,
+        "sweep": sweep or None,
+        "roofline": roof,
+        "kernels": blk["kernels"],
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+    bkts.bkts_op_destroy(op)
+    torch.cuda.synchronize()
+    bkts.bkts_ctx_destroy(ctx)
+
+
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,267 @@
+/*
+ * bkts.h -- Block Krylov Time Stepping on AMD Instinct MI355X (gfx950).
+ *
+ * C ABI of the hot path of the vectorised parallel-in-time integrator of
+ * Engwer, Schell and Dreier, "Vectorized Parallel in Time methods for
+ * low-order discretizations with application to Porous Media problems"
+ * (arXiv 2504.02117).  Several consecutive implicit time steps (or DIRK
+ * stages) of M y' + K y = b (Sec. 1, eq. problem) are collected as the k
+ * columns of an N x k block Y and solved together as the matrix equation of
+ * Sec. 2.1 with a block Krylov method.
+ *
+ * Conventions shared by every call:
+ *  - Block vectors are ROW-MAJOR N x k arrays with leading dimension ld >= k
+ *    (element (r, c) at p[r*ld + c]); they live in device memory (HBM) unless
+ *    a parameter says "host".  torch's contiguous (N, k) tensors qualify.
+ *  - The caller owns every data pointer.  The library owns only the handles it
+ *    creates (ctx, op, tc, nlop, server) and the device workspace behind them;
+ *    each handle has a *_destroy call.
+ *  - All device work is enqueued on the context's stream, in order.  Calls
+ *    that return values to the host (norms, iteration counts, exported arrays)
+ *    synchronise that stream before returning; the others are asynchronous.
+ *  - Every call returns a bkts_status.  On failure the message is available
+ *    from bkts_last_error() (thread-local, valid until the next failing call
+ *    on the same thread).  Shapes are validated before any launch: k < 1,
+ *    k > BKTS_MAX_K, ld < k, N mismatches or NULL pointers return BKTS_EINVAL
+ *    and enqueue nothing.  HIP runtime errors return BKTS_EDEVICE.  No C++
+ *    exception crosses this boundary.
+ *  - One context per host thread.  Handles must be used with the context that
+ *    created them.
+ *  - The mass matrix is the identity: every operator built here is scaled per
+ *    unit cell volume.
+ */
+#ifndef BKTS_H
+#define BKTS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define BKTS_MAX_K 32
+
+typedef enum bkts_status {
+  BKTS_OK = 0,
+  BKTS_EINVAL = -1,      /* invalid argument or shape; nothing was enqueued     */
+  BKTS_ENOMEM = -2,      /* device or host allocation failed                   */
+  BKTS_EDEVICE = -3,     /* HIP runtime error                                  */
+  BKTS_EBREAKDOWN = -4,  /* Krylov breakdown that deflation could not absorb   */
+  BKTS_ENOCONV = -5,     /* iteration limit reached; outputs hold the last iterate */
+  BKTS_EBUSY = -6        /* resource temporarily full (server admission)       */
+} bkts_status;
+
+typedef struct bkts_ctx_s* bkts_ctx;
+typedef struct bkts_op_s* bkts_op;
+typedef struct bkts_tc_s* bkts_tc;
+typedef struct bkts_nlop_s* bkts_nlop;
+typedef struct bkts_server_s* bkts_server;
+
+/* element types of block vectors */
+enum { BKTS_F64 = 0, BKTS_F32 = 1 };
+/* sparse storage formats of an operator */
+enum { BKTS_FMT_CSR = 0, BKTS_FMT_SELL = 1 };
+
+/* ------------------------------------------------------------------ context */
+
+/* Create a context on HIP device `device`.  `hip_stream` is an existing
+ * hipStream_t to enqueue on (e.g. torch.cuda.current_stream().cuda_stream) or
+ * NULL for the null stream.  The stream is borrowed, never destroyed. */
+bkts_status bkts_ctx_create(int device, void* hip_stream, bkts_ctx* out);
+void bkts_ctx_destroy(bkts_ctx ctx);
+/* Block until all work enqueued through `ctx` has finished. */
+bkts_status bkts_ctx_synchronize(bkts_ctx ctx);
+/* Thread-local message of the last failing call ("" if none). */
+const char* bkts_last_error(void);
+const char* bkts_version(void);
+
+/* Per-kernel device timers.  When enabled, every launch of the kernels below is
+ * bracketed by HIP events on the context stream and its algorithmic bytes (the
+ * traffic the kernel must move by its definition, e.g. for the block operator
+ * nnz*(s+4) + 4(N+1) + 2*N*k*s with s the element size) are accumulated.
+ * bkts_profile_enable(ctx, 1) resets the counters; bkts_profile_query
+ * synchronises and returns the totals for one kernel id. */
+enum {
+  BKTS_K_SPMM = 0,       /* block operator Y = aX + bKX                      */
+  BKTS_K_GRAM = 1,       /* X^T Y                                             */
+  BKTS_K_NORMS = 2,      /* column norms                                      */
+  BKTS_K_CG_UPDATE = 3,  /* X += P a, R -= Q a with Gram epilogues            */
+  BKTS_K_CG_PUPDATE = 4, /* P = D^-1 R + P b                                  */
+  BKTS_K_RESIDUAL = 5,   /* fused all-at-once residual                        */
+  BKTS_K_SMALL = 6,      /* k x k device kernels and partial-sum folding      */
+  BKTS_K_CAST = 7,       /* precision casts / strided copies                  */
+  BKTS_K_OTHER = 8,      /* vector helpers of the time-stepping loop          */
+  BKTS_K_COUNT = 9
+};
+bkts_status bkts_profile_enable(bkts_ctx ctx, int enable);
+bkts_status bkts_profile_query(bkts_ctx ctx, int kernel, int64_t* launches, double* total_ms,
+                               double* algorithmic_bytes);
+
+/* ---------------------------------------------------------------- operators */
+
+typedef struct bkts_grid {
+  int dim;   /* 1, 2 or 3 */
+  int n[3];  /* cells per axis, x first; unused axes ignored.  Unit square/cube, h_d = 1/n_d.
+                Linear cell index ix + n0*iy + n0*n1*iz. */
+} bkts_grid;
+
+enum { BKTS_BC_DIRICHLET = 0, BKTS_BC_NEUMANN = 1 };
+
+typedef struct bkts_fv_coeffs {
+  const double* kappa;   /* device, one diffusion coefficient per cell, or NULL: use kappa_const */
+  double kappa_const;
+  double velocity[3];    /* constant convection velocity (first-order upwind) */
+  int bc_type[6];        /* face 2*axis + side (side 0 = low): BKTS_BC_DIRICHLET or BKTS_BC_NEUMANN */
+  double bc_value[6];    /* Dirichlet value g of each face */
+} bkts_fv_coeffs;
+
+/* Assemble the cell-centred finite-volume operator K and source b of
+ * u_t + div(v u - kappa grad u) = 0 (Sec. 4.1 uses a cell-centred FV scheme;
+ * the fluxes are this library's reading): interior faces carry the harmonic
+ * mean 2 kP kQ / (kP + kQ) / h^2, Dirichlet faces 2 kP / h^2 with b += 2 kP g / h^2,
+ * convection is first-order upwind (boundary inflow moves w g / h into b).
+ * Runs on the device from the device array `kappa`.  `format` selects the
+ * storage used by the block operator (CSR is always kept for export). */
+bkts_status bkts_fv_assemble(bkts_ctx ctx, const bkts_grid* grid, const bkts_fv_coeffs* coeffs,
+                             int format, bkts_op* out);
+
+/* Wrap a caller-provided square CSR matrix (device arrays, int32 indices,
+ * sorted or unsorted columns, no duplicates required) as an operator.  The
+ * library copies the arrays; the source vector b is zero. */
+bkts_status bkts_op_create_csr(bkts_ctx ctx, int64_t N, int64_t nnz, const int32_t* rowptr,
+                               const int32_t* col, const double* val, int format, bkts_op* out);
+bkts_status bkts_op_info(bkts_op op, int64_t* N, int64_t* nnz);
+/* Copy the CSR arrays and source b to HOST buffers (sizes N+1, nnz, nnz, N; any may be NULL).
+ * Synchronises. */
+bkts_status bkts_op_export_csr(bkts_op op, int32_t* rowptr, int32_t* col, double* val, double* b);
+void bkts_op_destroy(bkts_op op);
+
+/* Block operator ("BOP", Sec. 3): Y = alpha * X + beta * K X for N x k blocks
+ * of element type `dtype` (BKTS_F64, or BKTS_F32 with FP32 matrix values and
+ * FP32 accumulation).  Each matrix entry is read once per block of k columns. */
+bkts_status bkts_spmm(bkts_ctx ctx, bkts_op op, int dtype, int k, double alpha, double beta,
+                      const void* X, int ldx, void* Y, int ldy);
+
+/* Gram matrix G = X^T Y (k x k, row-major, FP64, DEVICE pointer) of two N x k
+ * blocks of type `dtype`, accumulated in FP64 in a fixed order (bitwise
+ * reproducible). */
+bkts_status bkts_gram(bkts_ctx ctx, int dtype, int64_t N, int k, const void* X, int ldx,
+                      const void* Y, int ldy, double* G);
+
+/* ------------------------------------------------------------ time coupling */
+
+enum { BKTS_IE = 0, BKTS_THETA = 1, BKTS_SDIRK2 = 2, BKTS_DIRK_CUSTOM = 3 };
+
+typedef struct bkts_tc_desc {
+  int method;        /* BKTS_IE, BKTS_THETA, BKTS_SDIRK2 or BKTS_DIRK_CUSTOM */
+  double theta;      /* BKTS_THETA only */
+  int stages;        /* BKTS_DIRK_CUSTOM: number of stages m (<= 8) */
+  const double* A;   /* BKTS_DIRK_CUSTOM: host, m x m row-major, lower triangular, stiffly accurate */
+  const double* c;   /* BKTS_DIRK_CUSTOM: host, m */
+  int k;             /* block width: number of stage columns in one window (1..BKTS_MAX_K) */
+  double tau;        /* time step */
+} bkts_tc_desc;
+
+/* Build the time coupling of a stiffly accurate DIRK method (Sec. 2, eq.
+ * stiffly-accurate-DIRK; b = last row of A).  A first stage with a zero row
+ * is eliminated (Sec. 2.1).  The theta method is the 2-stage scheme
+ * [[0,0],[1-theta,theta]]; SDIRK2 is the L-stable 2-stage SDIRK with
+ * gamma = 1 - 1/sqrt(2).  The time coupling is a host object: `ctx` may be
+ * NULL, and a tc can be used with any context. */
+bkts_status bkts_tc_create(bkts_ctx ctx, const bkts_tc_desc* desc, bkts_tc* out);
+/* Window matrices of eq. time-stepping-matrices-multiple-parallel-time-steps
+ * taken from diagonal index `phase` (Sec. 2.2, pipelining): A1, A2 (HOST,
+ * k x k row-major) and beta = A2[0][0] (eq. matrix-splitting).  `phase` is the
+ * implicit-stage index of the front column within its step (0 <= phase < m_impl).
+ * Any output may be NULL. */
+bkts_status bkts_tc_get(bkts_tc tc, int phase, double* A1, double* A2, double* beta, int* k, int* m_impl);
+void bkts_tc_destroy(bkts_tc tc);
+
+/* All-at-once residual (Sec. 2.2; the sign of the F term is read so that it
+ * matches the linear system of eq. general-system-time-steps):
+ *     R = Y A1^T + (K Y - b 1^T) A2^T - B0,       col_norms2[j] = ||R_j||_2^2
+ * for the window matrices of `phase`.  Y, R: device N x k (k = the tc's k).
+ * B0: device N x nb0 (the first nb0 window columns; the rest are zero) or
+ * NULL.  col_norms2: HOST array of k doubles or NULL (synchronises when given).
+ * One fused pass: the sparse product, both right multiplications and the norms. */
+bkts_status bkts_residual(bkts_ctx ctx, bkts_op op, bkts_tc tc, int phase, const double* Y, int ldy,
+                          const double* B0, int ldb0, int nb0, double* R, int ldr, double* col_norms2);
+
+/* ------------------------------------------------------------- block solve */
+
+enum { BKTS_CG = 0, BKTS_GMRES = 1, BKTS_BICGSTAB = 2 };
+enum { BKTS_PREC_NONE = 0, BKTS_PREC_JACOBI = 1 };
+enum { BKTS_PRECISION_F64 = 0, BKTS_PRECISION_F32_REFINE = 1 };
+
+typedef struct bkts_solve_opts {
+  int krylov;        /* BKTS_CG (SPD operators), BKTS_GMRES, BKTS_BICGSTAB */
+  int precond;       /* BKTS_PREC_NONE or BKTS_PREC_JACOBI */
+  int precision;     /* BKTS_PRECISION_F64, or FP32 Krylov iterations inside an FP64
+                        iterative-refinement loop (residuals in FP64) */
+  double rtol;       /* per column: stop when ||r_j|| <= rtol * ||b_j - A x0_j|| for every j */
+  int maxit;         /* iteration limit (all inner iterations counted) */
+  int restart;       /* GMRES: block Krylov dimension per cycle (in blocks) */
+  double inner_rtol; /* F32_REFINE: relative reduction per FP32 inner solve (e.g. 1e-4) */
+} bkts_solve_opts;
+
+typedef struct bkts_solve_info {
+  int iterations;          /* block Krylov iterations (one block operator application each) */
+  int refinements;         /* F32_REFINE: outer FP64 refinement steps */
+  int converged;           /* 1 if every column met rtol */
+  int deflations;          /* directions dropped as numerically dependent */
+  double max_rel_residual; /* max_j ||r_j|| / ||r0_j|| at exit */
+} bkts_solve_info;
+
+/* Solve (alpha I + beta K) X = B for an N x k block with a block Krylov method
+ * (block methods: Sec. 1, eq. basic-matrix-equation).  B and X are FP64
+ * device blocks; X holds the initial guess on entry and the solution on exit.
+ * Convergence is per column; rank deficiency of the block is handled by
+ * deflating dependent directions.  Synchronises (reads convergence state). */
+bkts_status bkts_block_solve(bkts_ctx ctx, bkts_op op, double alpha, double beta, int k,
+                             const double* B, int ldb, double* X, int ldx,
+                             const bkts_solve_opts* opts, bkts_solve_info* info);
+
+/* ------------------------------------------------- Algorithm 1 (linear case) */
+
+typedef struct bkts_run_info {
+  int accepted_steps;
+  int outer_iterations;       /* residual evaluations + block solves (Algorithm 1 inner loop) */
+  int krylov_iterations;      /* total block Krylov iterations */
+  int refinements;
+  double final_front_rel_residual;
+} bkts_run_info;
+
+/* Called after each accepted step with the step number (1-based), its time and
+ * a DEVICE pointer to y^{n} (N doubles, valid only during the call). */
+typedef void (*bkts_step_cb)(int step, double t, const double* y_device, void* user);
+
+/* Algorithm 1 ("Block Krylov Time Stepping with Pipelining") for the linear
+ * problem y' + K y = b: a window of k stage columns is iterated with
+ * Y <- Y - J^{-1} R(Y), J = I/tau + beta K, until the front column's residual
+ * satisfies ||R_0|| <= outer_rtol * ||rhs_0||; the front stage is then
+ * accepted and the window shifted (shift(Y_1..Y_k) = (Y_2..Y_k, Y_k)).
+ * `y` (device, N) holds y^0 on entry and y^{n_steps} on exit.  `y_hist`
+ * (device, n_steps x N, may be NULL) receives every accepted y^n.  `cb` may
+ * be NULL.  Synchronises. */
+bkts_status bkts_advance(bkts_ctx ctx, bkts_op op, bkts_tc tc, double* y, int n_steps,
+                         const bkts_solve_opts* inner, double outer_rtol, int max_outer,
+                         double* y_hist, bkts_step_cb cb, void* user, bkts_run_info* info);
+
+/* A persistent Algorithm 1 pipeline: the window of k stages and the history
+ * of the front step survive between calls, so consecutive
+ * bkts_stepper_advance calls continue one time integration (bkts_advance is
+ * create + advance + destroy).  y0: device, N doubles, copied at creation. */
+typedef struct bkts_stepper_s* bkts_stepper;
+bkts_status bkts_stepper_create(bkts_ctx ctx, bkts_op op, bkts_tc tc, const double* y0, bkts_stepper* out);
+bkts_status bkts_stepper_advance(bkts_stepper st, int n_steps, const bkts_solve_opts* inner, double outer_rtol,
+                                 int max_outer, double* y_hist, bkts_step_cb cb, void* user, bkts_run_info* info);
+/* Copy the last accepted y^n to the device array y (N doubles; may be NULL) and
+ * return the number of steps accepted since creation.  Synchronises. */
+bkts_status bkts_stepper_state(bkts_stepper st, double* y, int64_t* accepted);
+void bkts_stepper_destroy(bkts_stepper st);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BKTS_H */

@@ -1,0 +1,199 @@
+// Algorithm 1 (Block Krylov Time Stepping with Pipelining) for the linear problem y' + K y = b.
+//
+// The window Y holds k consecutive implicit stages.  Each outer iteration forms the fused FP64
+// residual R(Y) = Y A1^T + (K Y - b 1^T) A2^T - B0, tests the front column, and applies the
+// Newton/splitting update Y <- Y - J^{-1} R with J = I/tau + beta K (in the linear case this
+// update is exactly one sweep of eq. matrix-fixed-point-equation).  When the front stage has
+// converged it is accepted and the window is shifted, shift(Y_1..Y_k) = (Y_2..Y_k, Y_k).
+//
+// The window is a ring buffer: logical column i lives in physical column (off + i) mod k, so a
+// shift costs one column copy instead of moving the whole block; the k x k couplings and the B0
+// columns are permuted to the physical order instead.  A stepper keeps the window between calls,
+// so consecutive advance calls continue one pipeline.
+#include <cmath>
+#include <cstring>
+
+#include "advance.hpp"
+#include "krylov.hpp"
+#include "vecops.hpp"
+
+namespace bkts {
+
+void upload_window(bkts_ctx ctx, const bkts_tc_s& tc, int phase, int off, double* A1p, double* A2p, double* rsp) {
+  const int k = tc.k;
+  double* h = ctx->host_stage(2 * k * k + k);
+  ctx->sync();  // the staging buffer may still be the target of an earlier read-back
+  for (int i = 0; i < k; ++i) {
+    const int pi = (off + i) % k;
+    double rs = 0.0;
+    for (int j = 0; j < k; ++j) {
+      const int pj = (off + j) % k;
+      h[pi * k + pj] = tc.A1[phase][i * k + j];
+      h[k * k + pi * k + pj] = tc.A2[phase][i * k + j];
+      rs += tc.A2[phase][i * k + j];
+    }
+    h[2 * k * k + pi] = rs;
+  }
+  BKTS_HIP(hipMemcpyAsync(A1p, h, sizeof(double) * (2 * k * k + k), hipMemcpyHostToDevice, ctx->stream));
+  (void)A2p;
+  (void)rsp;
+  ctx->sync();
+}
+
+void window_residual(bkts_ctx ctx, const bkts_op_s& op, const bkts_tc_s& tc, int phase, int off, const double* Y,
+                     int ldy, const double* B0, int ldb0, int nb0, double* R, int ldr, double* nrm_dev,
+                     double* mats) {
+  const int k = tc.k;
+  if (!mats) {
+    mats = ctx->ws.get<double>("win_mats", 2 * k * k + k);
+    upload_window(ctx, tc, phase, off, mats, mats + k * k, mats + 2 * k * k);
+  }
+  int cols[8];
+  for (int i = 0; i < nb0 && i < 8; ++i) cols[i] = (off + i) % k;
+  residual(ctx, op, k, Y, ldy, mats, mats + k * k, mats + 2 * k * k, B0, ldb0, nb0, cols, R, ldr, nrm_dev);
+}
+
+static void read_vec(bkts_ctx ctx, const double* dev, int n, std::vector<double>& out) {
+  double* h = ctx->host_stage(n);
+  BKTS_HIP(hipMemcpyAsync(h, dev, sizeof(double) * n, hipMemcpyDeviceToHost, ctx->stream));
+  ctx->sync();
+  out.assign(h, h + n);
+}
+
+}  // namespace bkts
+
+bkts_stepper_s::bkts_stepper_s(bkts_ctx c, bkts_op o, bkts_tc t, const double* y0) : ctx(c), op(o), tc(t) {
+  using namespace bkts;
+  const int64_t N = op->N;
+  const int k = tc->k;
+  const int mi = tc->m_impl;
+  Y.alloc(sizeof(double) * N * k);
+  R.alloc(sizeof(double) * N * k);
+  V.alloc(sizeof(double) * N * k);
+  B0.alloc(sizeof(double) * N * mi);
+  fst.alloc(sizeof(double) * N * mi);
+  yprev.alloc(sizeof(double) * N);
+  fyn.alloc(sizeof(double) * N);
+  tmp.alloc(sizeof(double) * N);
+  nrm.alloc(sizeof(double) * (k + 1));
+  mats.alloc(sizeof(double) * (2 * k * k + k));
+  // Algorithm 1 starts from Y = (y0, ..., y0)
+  broadcast_cols(ctx, N, k, y0, Y.as<double>(), k);
+  BKTS_HIP(hipMemcpyAsync(yprev.p, y0, sizeof(double) * N, hipMemcpyDeviceToDevice, ctx->stream));
+  if (tc->explicit_first) eval_f(yprev.as<double>(), 1, fyn.as<double>(), 1);
+  ctx->sync();
+}
+
+void bkts_stepper_s::eval_f(const double* x, int ldx, double* out, int ldo) {  // f(x) = K x - b
+  const double* bsrc = op->b_nonzero ? op->b.as<double>() : nullptr;
+  bkts::spmm(ctx, *op, BKTS_F64, 1, -1.0, bsrc, 1, 0.0, x, ldx, 1.0, out, ldo);
+}
+
+bkts_status bkts_stepper_s::advance(int n_steps, const bkts_solve_opts& inner, double outer_rtol, int max_outer,
+                                    double* y_hist, bkts_step_cb cb, void* user, bkts_run_info* info) {
+  using namespace bkts;
+  const int64_t N = op->N;
+  const int k = tc->k;
+  const int mi = tc->m_impl;
+  const double tau = tc->tau;
+  const double* bsrc = op->b_nonzero ? op->b.as<double>() : nullptr;
+  double* Yp = Y.as<double>();
+  double* Rp = R.as<double>();
+  double* Vp = V.as<double>();
+  double* B0p = B0.as<double>();
+  double* fstp = fst.as<double>();
+  double* yp = yprev.as<double>();
+  double* nrmp = nrm.as<double>();
+  bkts_run_info ri{};
+  std::vector<double> hn;
+  bkts_status status = BKTS_OK;
+  int done = 0;
+  while (done < n_steps) {
+    // B0 columns of the window: stages q = phase + i of the front step (Sec. 2.2)
+    const int nb0 = std::min(mi - phase, k);
+    for (int i = 0; i < nb0; ++i) {
+      const int q = phase + i;
+      LinComb lc;
+      lc.add(1.0 / tau, yp, 1);
+      for (int j = 0; j < phase; ++j) lc.add(-tc->Ai[q * mi + j], fstp + j, mi);
+      if (tc->explicit_first) lc.add(-tc->ae[q], fyn.as<double>(), 1);
+      lincomb(ctx, N, lc, B0p + i, mi);
+    }
+    // scale of the front equation: ||(B A2^T)_0 + B0_0||
+    {
+      LinComb lc;
+      double rs0 = 0.0;
+      for (int j = 0; j < k; ++j) rs0 += tc->A2[phase][j];
+      if (bsrc) lc.add(rs0, bsrc, 1);
+      lc.add(1.0, B0p, mi);
+      lincomb(ctx, N, lc, tmp.as<double>(), 1);
+      colnorms2(ctx, BKTS_F64, N, 1, tmp.as<double>(), 1, nrmp + k);
+    }
+    upload_window(ctx, *tc, phase, off, mats.as<double>(), nullptr, nullptr);
+    const double beta = tc->A2[phase][0];
+    bool front_ok = false;
+    for (int it = 0;; ++it) {
+      window_residual(ctx, *op, *tc, phase, off, Yp, k, B0p, mi, nb0, Rp, k, nrmp, mats.as<double>());
+      read_vec(ctx, nrmp, k + 1, hn);
+      const double rhs0 = std::sqrt(hn[k]);
+      const double front = std::sqrt(hn[off]);
+      ri.final_front_rel_residual = rhs0 > 0.0 ? front / rhs0 : front;
+      if (!std::isfinite(front)) throw Error{BKTS_EBREAKDOWN, "non-finite residual in the time window"};
+      if (front <= outer_rtol * rhs0) {
+        front_ok = true;
+        break;
+      }
+      if (it >= max_outer) break;
+      KrylovStats ks;
+      solve(ctx, *op, 1.0 / tau, beta, k, Rp, Vp, true, inner, true, ks);
+      ri.krylov_iterations += ks.iterations;
+      ri.refinements += ks.refinements;
+      ++ri.outer_iterations;
+      axpby(ctx, N * k, -1.0, Vp, 1.0, Yp);  // Y <- Y - V
+    }
+    if (!front_ok) {
+      status = BKTS_ENOCONV;
+      set_last_error(fmt("front stage not converged after %d outer iterations (rel. residual %.3e)", max_outer,
+                         ri.final_front_rel_residual));
+      break;
+    }
+    // accept the front stage
+    if (phase == mi - 1) {
+      extract_col(ctx, N, Yp, k, off, yp);
+      ++done;
+      ++accepted;
+      if (y_hist)
+        BKTS_HIP(hipMemcpyAsync(y_hist + (size_t)(done - 1) * N, yp, sizeof(double) * N, hipMemcpyDeviceToDevice,
+                                ctx->stream));
+      if (cb) {
+        ctx->sync();
+        cb(accepted, accepted * tau, yp, user);
+      }
+      if (tc->explicit_first) eval_f(yp, 1, fyn.as<double>(), 1);
+      phase = 0;
+    } else {
+      eval_f(Yp + off, k, fstp + phase, mi);
+      ++phase;
+    }
+    copy_col(ctx, N, Yp, k, (off + k - 1) % k, off);  // shift: duplicate the last column
+    off = (off + 1) % k;
+  }
+  ctx->sync();
+  ri.accepted_steps = done;
+  if (info) *info = ri;
+  return status;
+}
+
+namespace bkts {
+
+bkts_status advance(bkts_ctx ctx, bkts_op op, bkts_tc tc, double* y, int n_steps, const bkts_solve_opts& inner,
+                    double outer_rtol, int max_outer, double* y_hist, bkts_step_cb cb, void* user,
+                    bkts_run_info* info) {
+  bkts_stepper_s st(ctx, op, tc, y);
+  bkts_status s = st.advance(n_steps, inner, outer_rtol, max_outer, y_hist, cb, user, info);
+  BKTS_HIP(hipMemcpyAsync(y, st.yprev.p, sizeof(double) * op->N, hipMemcpyDeviceToDevice, ctx->stream));
+  ctx->sync();
+  return s;
+}
+
+}  // namespace bkts

@@ -1,0 +1,434 @@
+// Block-vector kernels on row tiles: Gram matrices X^T Y and column norms (FP64 accumulation,
+// deterministic two-pass reduction), the fused block-CG updates with their Gram epilogues, the
+// k x k right multiplication, scaled precision casts and small elementwise helpers.
+//
+// A tile is RT = 2048/KP rows of a block padded to KP columns.  Thread t owns column t % KP of
+// eight rows, loads them with coalesced accesses and keeps them in registers; the tile is also
+// staged in LDS so that a thread can read whole rows (for right multiplications by k x k
+// matrices and for Gram accumulation).  Each persistent workgroup walks one contiguous range of
+// tiles (XCD-aware) and leaves one partial k x k result; finalize_partials() folds the partials in
+// a fixed order, so results are bitwise reproducible.
+#include "devcommon.hpp"
+#include "internal.hpp"
+
+namespace bkts {
+namespace {
+
+using dev::TileGeom;
+
+template <int KP>
+constexpr int lds_doubles(int ntiles) {
+  return (ntiles * TileGeom<KP>::LDS_DOUBLES > 4 * KP * KP) ? ntiles * TileGeom<KP>::LDS_DOUBLES : 4 * KP * KP;
+}
+
+struct Slots {
+  int64_t ntiles, nslots, tps;  // tiles, workgroups, tiles per workgroup
+};
+
+template <int KP>
+Slots make_slots(bkts_ctx ctx, int64_t N) {
+  Slots s;
+  s.ntiles = (N + TileGeom<KP>::RT - 1) / TileGeom<KP>::RT;
+  const int64_t cap = 2 * (int64_t)ctx->num_cu;
+  s.nslots = s.ntiles < cap ? s.ntiles : cap;
+  if (s.nslots < 1) s.nslots = 1;
+  s.tps = (s.ntiles + s.nslots - 1) / s.nslots;
+  return s;
+}
+
+// ---------------------------------------------------------------- Gram / norms
+
+template <typename T, int KP>
+__global__ __launch_bounds__(256) void gram_kernel(int64_t N, int k, const T* __restrict__ X, int ldx,
+                                                   const T* __restrict__ Y, int ldy, double* partials,
+                                                   int64_t tps) {
+  using G = TileGeom<KP>;
+  __shared__ __align__(16) double lds[lds_doubles<KP>(1)];
+  const int t = threadIdx.x, c = t % KP, r0 = t / KP;
+  const int64_t slot = dev::xcd_slot(blockIdx.x, gridDim.x);
+  const int64_t ntiles = (N + G::RT - 1) / G::RT;
+  double acc[KP];
+#pragma unroll
+  for (int a = 0; a < KP; ++a) acc[a] = 0.0;
+  const int64_t tend = (slot + 1) * tps < ntiles ? (slot + 1) * tps : ntiles;
+  for (int64_t tile = slot * tps; tile < tend; ++tile) {
+    const int64_t row0 = tile * G::RT;
+    double y[G::RPT];
+#pragma unroll
+    for (int i = 0; i < G::RPT; ++i) {
+      const int row = r0 + i * G::RS;
+      const int64_t gr = row0 + row;
+      const bool ok = gr < N && c < k;
+      lds[row * G::LDL + c] = ok ? dev::ld_d(X + gr * ldx + c) : 0.0;
+      y[i] = ok ? dev::ld_d(Y + gr * ldy + c) : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < G::RPT; ++i) dev::lds_row_axpy<KP>(lds, r0 + i * G::RS, y[i], acc);
+    __syncthreads();
+  }
+  dev::block_reduce_store<KP, KP>(acc, lds, partials, gridDim.x, slot);
+}
+
+template <typename T, int KP>
+__global__ __launch_bounds__(256) void colnorm_kernel(int64_t N, int k, const T* __restrict__ X, int ldx,
+                                                      double* partials, int64_t tps) {
+  using G = TileGeom<KP>;
+  __shared__ double red[4 * KP];
+  const int t = threadIdx.x, c = t % KP, r0 = t / KP;
+  const int64_t slot = dev::xcd_slot(blockIdx.x, gridDim.x);
+  const int64_t ntiles = (N + G::RT - 1) / G::RT;
+  double acc[1] = {0.0};
+  const int64_t tend = (slot + 1) * tps < ntiles ? (slot + 1) * tps : ntiles;
+  for (int64_t tile = slot * tps; tile < tend; ++tile) {
+    const int64_t row0 = tile * G::RT;
+#pragma unroll
+    for (int i = 0; i < G::RPT; ++i) {
+      const int64_t gr = row0 + r0 + i * G::RS;
+      const double v = (gr < N && c < k) ? dev::ld_d(X + gr * ldx + c) : 0.0;
+      acc[0] = fma(v, v, acc[0]);
+    }
+  }
+  dev::block_reduce_store<KP, 1>(acc, red, partials, gridDim.x, slot);
+}
+
+// out[i] = sum over slots of partials[e(i)][slot], e(i) = (i / kout) * KP + i % kout for the
+// Gram layout (nrow = kout) or e(i) = i for vectors (nrow = 1).  One workgroup per output entry,
+// fixed summation order.
+__global__ __launch_bounds__(256) void finalize_kernel(const double* partials, int64_t nslots, int kout, int KPin,
+                                                       int vector_mode, double* out) {
+  __shared__ double s[256];
+  const int i = blockIdx.x;
+  const int e = vector_mode ? i : (i / kout) * KPin + i % kout;
+  const double* p = partials + (int64_t)e * nslots;
+  double acc = 0.0;
+  for (int64_t j = threadIdx.x; j < nslots; j += 256) acc += p[j];
+  s[threadIdx.x] = acc;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (threadIdx.x < off) s[threadIdx.x] += s[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[i] = s[0];
+}
+
+// ---------------------------------------------------------------- block CG updates
+
+// Load the k x k matrix M (row-major, device) column c into registers: col[j] = M[j][c].
+template <int KP>
+__device__ __forceinline__ void load_col(const double* M, int k, int c, double (&col)[KP]) {
+#pragma unroll
+  for (int j = 0; j < KP; ++j) col[j] = (j < k && c < k) ? M[j * k + c] : 0.0;
+}
+
+__device__ __forceinline__ double jacobi_inv(bool jacobi, const double* diagK, int64_t r, double a_shift,
+                                             double b_scale) {
+  return jacobi ? 1.0 / (a_shift + b_scale * diagK[r]) : 1.0;
+}
+
+// X += P alpha; R -= Q alpha; Z = Dinv R; gamma = R^T Z; T = Q^T Z; nrm = diag(R^T R).
+template <typename T, int KP>
+__global__ __launch_bounds__(256) void cg_update_kernel(int64_t N, int k, T* __restrict__ X, const T* __restrict__ P,
+                                                        T* __restrict__ R, const T* __restrict__ Q,
+                                                        const double* __restrict__ alpha, const double* diagK,
+                                                        double a_shift, double b_scale, int jacobi,
+                                                        double* pg, double* pt, double* pn, int64_t tps) {
+  using G = TileGeom<KP>;
+  __shared__ __align__(16) double lds[lds_doubles<KP>(2)];
+  double* Pl = lds;
+  double* Ql = lds + G::LDS_DOUBLES;
+  const int t = threadIdx.x, c = t % KP, r0 = t / KP;
+  const int64_t slot = dev::xcd_slot(blockIdx.x, gridDim.x);
+  const int64_t ntiles = (N + G::RT - 1) / G::RT;
+  double acol[KP];
+  load_col<KP>(alpha, k, c, acol);
+  double gacc[KP], tacc[KP], nacc[1] = {0.0};
+#pragma unroll
+  for (int a = 0; a < KP; ++a) gacc[a] = tacc[a] = 0.0;
+  const int64_t tend = (slot + 1) * tps < ntiles ? (slot + 1) * tps : ntiles;
+  for (int64_t tile = slot * tps; tile < tend; ++tile) {
+    const int64_t row0 = tile * G::RT;
+    double x[G::RPT], r[G::RPT], z[G::RPT];
+#pragma unroll
+    for (int i = 0; i < G::RPT; ++i) {
+      const int row = r0 + i * G::RS;
+      const int64_t gr = row0 + row;
+      const bool ok = gr < N && c < k;
+      const int64_t e = gr * k + c;
+      Pl[row * G::LDL + c] = ok ? dev::ld_d(P + e) : 0.0;
+      Ql[row * G::LDL + c] = ok ? dev::ld_d(Q + e) : 0.0;
+      x[i] = ok ? dev::ld_d(X + e) : 0.0;
+      r[i] = ok ? dev::ld_d(R + e) : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < G::RPT; ++i) {
+      const int row = r0 + i * G::RS;
+      const int64_t gr = row0 + row;
+      x[i] += dev::lds_row_dot<KP>(Pl, row, acol);
+      r[i] -= dev::lds_row_dot<KP>(Ql, row, acol);
+      const bool ok = gr < N && c < k;
+      z[i] = ok ? r[i] * jacobi_inv(jacobi, diagK, gr, a_shift, b_scale) : 0.0;
+      if (ok) {
+        X[gr * k + c] = (T)x[i];
+        R[gr * k + c] = (T)r[i];
+      } else {
+        r[i] = 0.0;
+      }
+      nacc[0] = fma(r[i], r[i], nacc[0]);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < G::RPT; ++i) Pl[(r0 + i * G::RS) * G::LDL + c] = r[i];  // R tile replaces P tile
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < G::RPT; ++i) {
+      const int row = r0 + i * G::RS;
+      dev::lds_row_axpy<KP>(Pl, row, z[i], gacc);
+      dev::lds_row_axpy<KP>(Ql, row, z[i], tacc);
+    }
+    __syncthreads();
+  }
+  dev::block_reduce_store<KP, KP>(gacc, lds, pg, gridDim.x, slot);
+  dev::block_reduce_store<KP, KP>(tacc, lds, pt, gridDim.x, slot);
+  dev::block_reduce_store<KP, 1>(nacc, lds, pn, gridDim.x, slot);
+}
+
+// P = Dinv R + P beta   (beta == nullptr: P = Dinv R)
+template <typename T, int KP>
+__global__ __launch_bounds__(256) void cg_pupdate_kernel(int64_t N, int k, T* __restrict__ P, const T* __restrict__ R,
+                                                         const double* __restrict__ beta, const double* diagK,
+                                                         double a_shift, double b_scale, int jacobi, int64_t tps) {
+  using G = TileGeom<KP>;
+  __shared__ __align__(16) double lds[lds_doubles<KP>(1)];
+  const int t = threadIdx.x, c = t % KP, r0 = t / KP;
+  const int64_t slot = dev::xcd_slot(blockIdx.x, gridDim.x);
+  const int64_t ntiles = (N + G::RT - 1) / G::RT;
+  double bcol[KP];
+  if (beta) load_col<KP>(beta, k, c, bcol);
+  const int64_t tend = (slot + 1) * tps < ntiles ? (slot + 1) * tps : ntiles;
+  for (int64_t tile = slot * tps; tile < tend; ++tile) {
+    const int64_t row0 = tile * G::RT;
+    double r[G::RPT];
+#pragma unroll
+    for (int i = 0; i < G::RPT; ++i) {
+      const int row = r0 + i * G::RS;
+      const int64_t gr = row0 + row;
+      const bool ok = gr < N && c < k;
+      if (beta) lds[row * G::LDL + c] = ok ? dev::ld_d(P + gr * k + c) : 0.0;
+      r[i] = ok ? dev::ld_d(R + gr * k + c) * jacobi_inv(jacobi, diagK, gr, a_shift, b_scale) : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < G::RPT; ++i) {
+      const int row = r0 + i * G::RS;
+      const int64_t gr = row0 + row;
+      double p = r[i];
+      if (beta) p += dev::lds_row_dot<KP>(lds, row, bcol);
+      if (gr < N && c < k) P[gr * k + c] = (T)p;
+    }
+    __syncthreads();
+  }
+}
+
+// Y = c0 Y + c1 X C
+template <typename T, int KP>
+__global__ __launch_bounds__(256) void rmul_kernel(int64_t N, int k, const T* __restrict__ X, int ldx,
+                                                   const double* __restrict__ C, double c0, double c1, T* Y, int ldy,
+                                                   int64_t tps) {
+  using G = TileGeom<KP>;
+  __shared__ __align__(16) double lds[lds_doubles<KP>(1)];
+  const int t = threadIdx.x, c = t % KP, r0 = t / KP;
+  const int64_t slot = dev::xcd_slot(blockIdx.x, gridDim.x);
+  const int64_t ntiles = (N + G::RT - 1) / G::RT;
+  double ccol[KP];
+  load_col<KP>(C, k, c, ccol);
+  const int64_t tend = (slot + 1) * tps < ntiles ? (slot + 1) * tps : ntiles;
+  for (int64_t tile = slot * tps; tile < tend; ++tile) {
+    const int64_t row0 = tile * G::RT;
+#pragma unroll
+    for (int i = 0; i < G::RPT; ++i) {
+      const int row = r0 + i * G::RS;
+      const int64_t gr = row0 + row;
+      lds[row * G::LDL + c] = (gr < N && c < k) ? dev::ld_d(X + gr * ldx + c) : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < G::RPT; ++i) {
+      const int row = r0 + i * G::RS;
+      const int64_t gr = row0 + row;
+      if (gr < N && c < k) {
+        double y = c1 * dev::lds_row_dot<KP>(lds, row, ccol);
+        if (c0 != 0.0) y = fma(c0, dev::ld_d(Y + gr * ldy + c), y);
+        Y[gr * ldy + c] = (T)y;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------- casts / elementwise
+
+template <typename S, typename D>
+__global__ void cast_scale_kernel(int64_t N, int k, const S* src, int lds_, D* dst, int ldd, const double* s,
+                                  int invert, int accumulate) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N * k) return;
+  const int64_t r = i / k;
+  const int c = (int)(i % k);
+  double v = (double)src[r * lds_ + c];
+  if (s) v = invert ? v / s[c] : v * s[c];
+  if (accumulate) v += (double)dst[r * ldd + c];
+  dst[r * ldd + c] = (D)v;
+}
+
+template <int KP>
+void launch_gram_t(bkts_ctx ctx, int dtype, int64_t N, int k, const void* X, int ldx, const void* Y, int ldy,
+                   double* G) {
+  Slots s = make_slots<KP>(ctx, N);
+  double* part = ctx->ws.get<double>("gram_partials", (size_t)KP * KP * s.nslots);
+  ProfScope prof(ctx, BKTS_K_GRAM, 2.0 * N * k * esize(dtype));
+  if (dtype == BKTS_F64)
+    hipLaunchKernelGGL((gram_kernel<double, KP>), dim3(s.nslots), dim3(256), 0, ctx->stream, N, k,
+                       static_cast<const double*>(X), ldx, static_cast<const double*>(Y), ldy, part, s.tps);
+  else
+    hipLaunchKernelGGL((gram_kernel<float, KP>), dim3(s.nslots), dim3(256), 0, ctx->stream, N, k,
+                       static_cast<const float*>(X), ldx, static_cast<const float*>(Y), ldy, part, s.tps);
+  BKTS_HIP(hipGetLastError());
+  hipLaunchKernelGGL(finalize_kernel, dim3(k * k), dim3(256), 0, ctx->stream, part, s.nslots, k, KP, 0, G);
+  BKTS_HIP(hipGetLastError());
+}
+
+template <int KP>
+void launch_colnorm_t(bkts_ctx ctx, int dtype, int64_t N, int k, const void* X, int ldx, double* out) {
+  Slots s = make_slots<KP>(ctx, N);
+  double* part = ctx->ws.get<double>("norm_partials", (size_t)KP * s.nslots);
+  ProfScope prof(ctx, BKTS_K_NORMS, 1.0 * N * k * esize(dtype));
+  if (dtype == BKTS_F64)
+    hipLaunchKernelGGL((colnorm_kernel<double, KP>), dim3(s.nslots), dim3(256), 0, ctx->stream, N, k,
+                       static_cast<const double*>(X), ldx, part, s.tps);
+  else
+    hipLaunchKernelGGL((colnorm_kernel<float, KP>), dim3(s.nslots), dim3(256), 0, ctx->stream, N, k,
+                       static_cast<const float*>(X), ldx, part, s.tps);
+  BKTS_HIP(hipGetLastError());
+  hipLaunchKernelGGL(finalize_kernel, dim3(k), dim3(256), 0, ctx->stream, part, s.nslots, k, KP, 1, out);
+  BKTS_HIP(hipGetLastError());
+}
+
+template <typename T, int KP>
+void launch_cg_update_t(bkts_ctx ctx, int64_t N, int k, void* X, const void* P, void* R, const void* Q,
+                        const double* alpha, const double* diagK, double a_shift, double b_scale, bool jacobi,
+                        double* gamma, double* Tm, double* nrm) {
+  Slots s = make_slots<KP>(ctx, N);
+  const size_t np = (size_t)KP * KP * s.nslots;
+  double* pg = ctx->ws.get<double>("cg_pg", np);
+  double* pt = ctx->ws.get<double>("cg_pt", np);
+  double* pn = ctx->ws.get<double>("cg_pn", (size_t)KP * s.nslots);
+  ProfScope prof(ctx, BKTS_K_CG_UPDATE, 6.0 * N * k * sizeof(T) + (jacobi ? 8.0 * N : 0.0));
+  hipLaunchKernelGGL((cg_update_kernel<T, KP>), dim3(s.nslots), dim3(256), 0, ctx->stream, N, k, static_cast<T*>(X),
+                     static_cast<const T*>(P), static_cast<T*>(R), static_cast<const T*>(Q), alpha, diagK, a_shift,
+                     b_scale, (int)jacobi, pg, pt, pn, s.tps);
+  BKTS_HIP(hipGetLastError());
+  hipLaunchKernelGGL(finalize_kernel, dim3(k * k), dim3(256), 0, ctx->stream, pg, s.nslots, k, KP, 0, gamma);
+  hipLaunchKernelGGL(finalize_kernel, dim3(k * k), dim3(256), 0, ctx->stream, pt, s.nslots, k, KP, 0, Tm);
+  hipLaunchKernelGGL(finalize_kernel, dim3(k), dim3(256), 0, ctx->stream, pn, s.nslots, k, KP, 1, nrm);
+  BKTS_HIP(hipGetLastError());
+}
+
+template <typename T, int KP>
+void launch_cg_pupdate_t(bkts_ctx ctx, int64_t N, int k, void* P, const void* R, const double* beta,
+                         const double* diagK, double a_shift, double b_scale, bool jacobi) {
+  Slots s = make_slots<KP>(ctx, N);
+  ProfScope prof(ctx, BKTS_K_CG_PUPDATE, (beta ? 3.0 : 2.0) * N * k * sizeof(T) + (jacobi ? 8.0 * N : 0.0));
+  hipLaunchKernelGGL((cg_pupdate_kernel<T, KP>), dim3(s.nslots), dim3(256), 0, ctx->stream, N, k, static_cast<T*>(P),
+                     static_cast<const T*>(R), beta, diagK, a_shift, b_scale, (int)jacobi, s.tps);
+  BKTS_HIP(hipGetLastError());
+}
+
+template <typename T, int KP>
+void launch_rmul_t(bkts_ctx ctx, int64_t N, int k, const void* X, int ldx, const double* C, double c0, double c1,
+                   void* Y, int ldy) {
+  Slots s = make_slots<KP>(ctx, N);
+  ProfScope prof(ctx, BKTS_K_OTHER, (c0 != 0.0 ? 3.0 : 2.0) * N * k * sizeof(T));
+  hipLaunchKernelGGL((rmul_kernel<T, KP>), dim3(s.nslots), dim3(256), 0, ctx->stream, N, k, static_cast<const T*>(X),
+                     ldx, C, c0, c1, static_cast<T*>(Y), ldy, s.tps);
+  BKTS_HIP(hipGetLastError());
+}
+
+#define BKTS_KP_DISPATCH(k, CALL)                                    \
+  do {                                                               \
+    if ((k) <= 1) { constexpr int KP = 1; CALL; }                    \
+    else if ((k) <= 2) { constexpr int KP = 2; CALL; }               \
+    else if ((k) <= 4) { constexpr int KP = 4; CALL; }               \
+    else if ((k) <= 8) { constexpr int KP = 8; CALL; }               \
+    else if ((k) <= 16) { constexpr int KP = 16; CALL; }             \
+    else if ((k) <= 32) { constexpr int KP = 32; CALL; }             \
+    else throw Error{BKTS_EINVAL, fmt("k=%d exceeds BKTS_MAX_K", (int)(k))}; \
+  } while (0)
+
+}  // namespace
+
+void finalize_partials(bkts_ctx ctx, const double* partials, int nblocks, int nentries, double* out) {
+  ProfScope prof(ctx, BKTS_K_SMALL, 8.0 * nblocks * nentries);
+  hipLaunchKernelGGL(finalize_kernel, dim3(nentries), dim3(256), 0, ctx->stream, partials, (int64_t)nblocks, 1, 1, 1,
+                     out);
+  BKTS_HIP(hipGetLastError());
+}
+
+void gram(bkts_ctx ctx, int dtype, int64_t N, int k, const void* X, int ldx, const void* Y, int ldy, double* G) {
+  BKTS_KP_DISPATCH(k, (launch_gram_t<KP>(ctx, dtype, N, k, X, ldx, Y, ldy, G)));
+}
+
+void colnorms2(bkts_ctx ctx, int dtype, int64_t N, int k, const void* X, int ldx, double* out) {
+  BKTS_KP_DISPATCH(k, (launch_colnorm_t<KP>(ctx, dtype, N, k, X, ldx, out)));
+}
+
+void cg_update(bkts_ctx ctx, int dtype, int64_t N, int k, void* X, const void* P, void* R, const void* Q,
+               const double* alpha, const double* diagK, double a_shift, double b_scale, bool jacobi, double* gamma,
+               double* Tm, double* nrm) {
+  if (dtype == BKTS_F64)
+    BKTS_KP_DISPATCH(k, (launch_cg_update_t<double, KP>(ctx, N, k, X, P, R, Q, alpha, diagK, a_shift, b_scale, jacobi,
+                                                        gamma, Tm, nrm)));
+  else
+    BKTS_KP_DISPATCH(k, (launch_cg_update_t<float, KP>(ctx, N, k, X, P, R, Q, alpha, diagK, a_shift, b_scale, jacobi,
+                                                       gamma, Tm, nrm)));
+}
+
+void cg_pupdate(bkts_ctx ctx, int dtype, int64_t N, int k, void* P, const void* R, const double* beta,
+                const double* diagK, double a_shift, double b_scale, bool jacobi) {
+  if (dtype == BKTS_F64)
+    BKTS_KP_DISPATCH(k, (launch_cg_pupdate_t<double, KP>(ctx, N, k, P, R, beta, diagK, a_shift, b_scale, jacobi)));
+  else
+    BKTS_KP_DISPATCH(k, (launch_cg_pupdate_t<float, KP>(ctx, N, k, P, R, beta, diagK, a_shift, b_scale, jacobi)));
+}
+
+void block_rmul(bkts_ctx ctx, int dtype, int64_t N, int k, const void* X, int ldx, const double* C, double c0,
+                double c1, void* Y, int ldy) {
+  if (dtype == BKTS_F64)
+    BKTS_KP_DISPATCH(k, (launch_rmul_t<double, KP>(ctx, N, k, X, ldx, C, c0, c1, Y, ldy)));
+  else
+    BKTS_KP_DISPATCH(k, (launch_rmul_t<float, KP>(ctx, N, k, X, ldx, C, c0, c1, Y, ldy)));
+}
+
+void block_cast_scale(bkts_ctx ctx, int64_t N, int k, int src_t, const void* src, int lds_, int dst_t, void* dst,
+                      int ldd, const double* s, bool invert_s, bool accumulate) {
+  const int64_t n = N * k;
+  if (n == 0) return;
+  dim3 g((n + 255) / 256), b(256);
+  ProfScope prof(ctx, BKTS_K_CAST, (double)n * (esize(src_t) + esize(dst_t) * (accumulate ? 2 : 1)));
+  if (src_t == BKTS_F64 && dst_t == BKTS_F32)
+    hipLaunchKernelGGL((cast_scale_kernel<double, float>), g, b, 0, ctx->stream, N, k, static_cast<const double*>(src),
+                       lds_, static_cast<float*>(dst), ldd, s, (int)invert_s, (int)accumulate);
+  else if (src_t == BKTS_F32 && dst_t == BKTS_F64)
+    hipLaunchKernelGGL((cast_scale_kernel<float, double>), g, b, 0, ctx->stream, N, k, static_cast<const float*>(src),
+                       lds_, static_cast<double*>(dst), ldd, s, (int)invert_s, (int)accumulate);
+  else if (src_t == BKTS_F64 && dst_t == BKTS_F64)
+    hipLaunchKernelGGL((cast_scale_kernel<double, double>), g, b, 0, ctx->stream, N, k, static_cast<const double*>(src),
+                       lds_, static_cast<double*>(dst), ldd, s, (int)invert_s, (int)accumulate);
+  else
+    hipLaunchKernelGGL((cast_scale_kernel<float, float>), g, b, 0, ctx->stream, N, k, static_cast<const float*>(src),
+                       lds_, static_cast<float*>(dst), ldd, s, (int)invert_s, (int)accumulate);
+  BKTS_HIP(hipGetLastError());
+}
+
+}  // namespace bkts

@@ -1,0 +1,198 @@
+// Host-side internals of the bkts library: handle layouts, workspace, error plumbing and the
+// launchers every translation unit shares.  Nothing here is part of the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdint>
+#include <cstdio>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/bkts.h"
+
+namespace bkts {
+
+struct Error {
+  bkts_status status;
+  std::string msg;
+};
+
+std::string fmt(const char* f, ...);
+void set_last_error(const std::string& m);
+
+#define BKTS_HIP(x)                                                                              \
+  do {                                                                                           \
+    hipError_t e_ = (x);                                                                         \
+    if (e_ != hipSuccess)                                                                        \
+      throw ::bkts::Error{BKTS_EDEVICE, std::string(#x) + " failed: " + hipGetErrorString(e_)};  \
+  } while (0)
+
+#define BKTS_REQUIRE(cond, ...)                                            \
+  do {                                                                     \
+    if (!(cond)) throw ::bkts::Error{BKTS_EINVAL, ::bkts::fmt(__VA_ARGS__)}; \
+  } while (0)
+
+// Owning device allocation.
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  DevBuf(DevBuf&& o) noexcept : p(o.p), bytes(o.bytes) { o.p = nullptr; o.bytes = 0; }
+  DevBuf& operator=(DevBuf&& o) noexcept {
+    release();
+    p = o.p; bytes = o.bytes; o.p = nullptr; o.bytes = 0;
+    return *this;
+  }
+  ~DevBuf() { release(); }
+  void alloc(size_t n);
+  void release();
+  template <typename T> T* as() const { return static_cast<T*>(p); }
+};
+
+// Named scratch buffers that only grow.  A buffer's contents are undefined on return from get().
+struct Workspace {
+  std::map<std::string, DevBuf> bufs;
+  void* get(const std::string& name, size_t bytes);
+  template <typename T> T* get(const std::string& name, size_t count) {
+    return static_cast<T*>(get(name, count * sizeof(T)));
+  }
+  size_t total_bytes() const;
+};
+
+inline size_t esize(int dtype) { return dtype == BKTS_F32 ? 4 : 8; }
+
+}  // namespace bkts
+
+namespace bkts {
+// Per-kernel device timers: HIP events recorded around each launch on the context stream, plus the
+// algorithmic bytes the launch moves (the kernel's own traffic model, not hardware counters).
+struct Profiler {
+  struct Rec {
+    int kid;
+    hipEvent_t a, b;
+  };
+  struct Acc {
+    int64_t launches = 0;
+    double ms = 0.0;
+    double bytes = 0.0;
+  };
+  bool enabled = false;
+  std::vector<hipEvent_t> pool;
+  std::vector<Rec> pending;
+  Acc acc[BKTS_K_COUNT];
+  hipEvent_t take();
+  void resolve();  // waits for pending events and folds them into acc
+  void reset();
+  ~Profiler();
+};
+}  // namespace bkts
+
+struct bkts_ctx_s {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  int num_cu = 256;
+  bkts::Workspace ws;
+  double* h_pinned = nullptr;  // pinned host staging for small read-backs
+  size_t h_pinned_bytes = 0;
+  bkts::Profiler prof;
+  double* host_stage(size_t count);  // pinned buffer of at least `count` doubles
+  void sync();
+};
+
+struct bkts_op_s {
+  bkts_ctx ctx = nullptr;
+  int64_t N = 0, nnz = 0;
+  int format = BKTS_FMT_CSR;
+  bkts_grid grid{};  // dim == 0 when the operator came from a raw CSR
+  // CSR (always present)
+  bkts::DevBuf rowptr, col, val, val32;
+  bkts::DevBuf diag;  // K_rr (double), used for Jacobi
+  bkts::DevBuf b;     // source vector (double, N), zero unless assembled with nonzero boundary data
+  bool b_nonzero = false;
+  // SELL-C (sigma = 1): slice s covers rows [s*C, s*C+C), width w_s, entry (row, j) at
+  // sell_ptr[s] + j*C + (row - s*C); padding entries have col = row and val = 0.
+  int sell_C = 64;
+  int64_t nslices = 0, sell_nnz = 0;
+  bkts::DevBuf sell_ptr, sell_w, sell_col, sell_val, sell_val32;
+};
+
+struct bkts_tc_s {
+  bkts_ctx ctx = nullptr;
+  int k = 1;
+  int m_impl = 1;       // implicit stages per step
+  int explicit_first = 0;
+  double tau = 1.0;
+  std::vector<double> Ai;  // m_impl x m_impl implicit part of the tableau
+  std::vector<double> ae;  // couplings of implicit stages to the eliminated explicit stage
+  std::vector<double> ci;
+  // window matrices for each phase, row-major k x k
+  std::vector<std::vector<double>> A1, A2;
+};
+
+namespace bkts {
+
+// RAII timer around the launches of one kernel (no-op unless profiling is enabled).
+struct ProfScope {
+  bkts_ctx ctx;
+  int kid;
+  hipEvent_t b = nullptr;
+  ProfScope(bkts_ctx c, int k, double bytes);
+  ~ProfScope();
+};
+
+// ---- operator building (op.hip)
+void op_build_sell(bkts_op op);
+void op_finish(bkts_op op);  // diag, fp32 copies, SELL if requested
+
+// ---- kernels (launchers). All enqueue on ctx->stream.
+// Y = cb*B + alpha*X + beta*K X   (B may be null). dtype F64/F32 for X, Y, B.
+void spmm(bkts_ctx ctx, const bkts_op_s& op, int dtype, int k, double cb, const void* B, int ldb,
+          double alpha, const void* X, int ldx, double beta, void* Y, int ldy);
+
+// Reductions produce per-block partials that finalize_partials() folds, in a fixed order.
+int reduce_blocks(bkts_ctx ctx, int64_t N, int k);
+void finalize_partials(bkts_ctx ctx, const double* partials, int nblocks, int nentries, double* out);
+
+// G = X^T Y (device, k x k row-major)
+void gram(bkts_ctx ctx, int dtype, int64_t N, int k, const void* X, int ldx, const void* Y, int ldy,
+          double* G);
+
+// Column sums of squares: out[j] = sum_r X[r, j]^2 (device, k)
+void colnorms2(bkts_ctx ctx, int dtype, int64_t N, int k, const void* X, int ldx, double* out);
+
+// Block CG update (all blocks N x k, same dtype, ld = k):
+//   X += P*alpha ; R -= Q*alpha ; Z = Dinv R ;  gamma = R^T Z ; T = Q^T Z ; nrm[j] = ||R_j||^2
+// alpha (k x k) read from device memory; outputs gamma, T, nrm in device memory.
+void cg_update(bkts_ctx ctx, int dtype, int64_t N, int k, void* X, const void* P, void* R, const void* Q,
+               const double* alpha_dev, const double* diagK, double a_shift, double b_scale, bool jacobi,
+               double* gamma, double* T, double* nrm);
+// P = Dinv R + P*beta
+void cg_pupdate(bkts_ctx ctx, int dtype, int64_t N, int k, void* P, const void* R, const double* beta_dev,
+                const double* diagK, double a_shift, double b_scale, bool jacobi);
+
+// General right-multiply-accumulate: Y = c0*Y + c1*X*C  (C: device k x k, row-major)
+void block_rmul(bkts_ctx ctx, int dtype, int64_t N, int k, const void* X, int ldx, const double* C,
+                double c0, double c1, void* Y, int ldy);
+
+// Scaled casts: dst = src * diag(s) (s device, k; null = ones), between F64 and F32 blocks.
+void block_cast_scale(bkts_ctx ctx, int64_t N, int k, int src_t, const void* src, int lds, int dst_t,
+                      void* dst, int ldd, const double* s, bool invert_s, bool accumulate);
+
+// All-at-once residual (fused).  A1t, A2t: device k x k transposed window matrices (A^T, row-major).
+// b0cols: host list of (b0 column index -> R column index).
+void residual(bkts_ctx ctx, const bkts_op_s& op, int k, const double* Y, int ldy, const double* A1t,
+              const double* A2t, const double* b_rowsum, const double* B0, int ldb0, int nb0,
+              const int* b0_to_col, double* R, int ldr, double* nrm);
+
+// k x k dense kernels on one workgroup (small.hip).
+// alpha = G^+ S with truncated Cholesky of the Jacobi-scaled G (threshold `eps`); writes
+// ndefl (device int) = number of deflated directions.  sign = +1 or -1 multiplies the result.
+void small_spd_solve(bkts_ctx ctx, int k, const double* G, const double* S, double sign, double eps,
+                     double* out, int* ndefl);
+
+}  // namespace bkts

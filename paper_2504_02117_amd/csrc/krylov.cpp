@@ -1,0 +1,201 @@
+// Block Krylov solvers for (a I + b K) X = B on the device (block methods: Sec. 1,
+// eq. basic-matrix-equation; block CG after O'Leary).  Every coefficient matrix is k x k FP64 and
+// stays on the GPU; the host only reads the k column norms to decide convergence.
+//
+// Block CG in conjugate-direction form, with the Jacobi-preconditioned residual Z = D^-1 R:
+//   Q = A P;  G = P^T Q;  alpha = G^+ gamma;  X += P alpha;  R -= Q alpha;
+//   gamma = R^T Z;  T = Q^T Z;  beta = -G^+ T;  P = Z + P beta.
+// G^+ is a truncated Cholesky inverse of the Jacobi-scaled G: directions that have become
+// numerically dependent (columns that converged, duplicated columns after a pipelining shift)
+// are dropped instead of breaking the iteration.
+#include "krylov.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "vecops.hpp"
+
+namespace bkts {
+
+namespace {
+
+struct Small {
+  double *G, *gamma, *T, *alpha, *beta, *nrm, *nrm0;
+  int* ndefl;
+};
+
+Small small_bufs(bkts_ctx ctx, const std::string& tag, int k) {
+  const size_t kk = (size_t)k * k;
+  double* base = ctx->ws.get<double>("small_" + tag, 5 * kk + 2 * k + 2);
+  Small s;
+  s.G = base;
+  s.gamma = base + kk;
+  s.T = base + 2 * kk;
+  s.alpha = base + 3 * kk;
+  s.beta = base + 4 * kk;
+  s.nrm = base + 5 * kk;
+  s.nrm0 = s.nrm + k;
+  s.ndefl = reinterpret_cast<int*>(s.nrm0 + k);
+  return s;
+}
+
+void read_norms(bkts_ctx ctx, const double* dev, int k, std::vector<double>& out, const int* ndefl_dev = nullptr,
+                int* ndefl = nullptr) {
+  double* h = ctx->host_stage(k + 1);
+  BKTS_HIP(hipMemcpyAsync(h, dev, sizeof(double) * k, hipMemcpyDeviceToHost, ctx->stream));
+  if (ndefl_dev)
+    BKTS_HIP(hipMemcpyAsync(reinterpret_cast<int*>(h + k), ndefl_dev, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+  ctx->sync();
+  out.assign(h, h + k);
+  if (ndefl && ndefl_dev) *ndefl = *reinterpret_cast<int*>(h + k);
+}
+
+bool all_converged(const std::vector<double>& nrm, const std::vector<double>& nrm0, double rtol, double* maxrel) {
+  bool ok = true;
+  double mr = 0.0;
+  for (size_t j = 0; j < nrm.size(); ++j) {
+    if (!std::isfinite(nrm[j])) throw Error{BKTS_EBREAKDOWN, fmt("non-finite residual in column %zu", j)};
+    const double rel = nrm0[j] > 0.0 ? std::sqrt(nrm[j] / nrm0[j]) : (nrm[j] > 0.0 ? INFINITY : 0.0);
+    mr = std::max(mr, rel);
+    if (!(nrm[j] <= rtol * rtol * nrm0[j])) ok = false;
+  }
+  if (maxrel) *maxrel = mr;
+  return ok;
+}
+
+}  // namespace
+
+// Block CG on contiguous (ld = k) blocks of element type dtype.
+void block_cg(bkts_ctx ctx, const bkts_op_s& op, int dtype, int k, double a, double b, const void* B, void* X,
+              bool x0_zero, bool jacobi, double rtol, int maxit, KrylovStats& st) {
+  const int64_t N = op.N;
+  const size_t es = esize(dtype);
+  const std::string tag = dtype == BKTS_F64 ? "d" : "s";
+  void* R = ctx->ws.get("cg_R_" + tag, es * N * k);
+  void* P = ctx->ws.get("cg_P_" + tag, es * N * k);
+  void* Q = ctx->ws.get("cg_Q_" + tag, es * N * k);
+  Small s = small_bufs(ctx, "cg" + tag, k);
+  const double eps = dtype == BKTS_F64 ? 1e-13 : 1e-6;
+  const double* dK = op.diag.as<double>();
+
+  if (x0_zero) {
+    BKTS_HIP(hipMemsetAsync(X, 0, es * N * k, ctx->stream));
+    BKTS_HIP(hipMemcpyAsync(R, B, es * N * k, hipMemcpyDeviceToDevice, ctx->stream));
+  } else
+    spmm(ctx, op, dtype, k, 1.0, B, k, -a, X, k, -b, R, k);
+  colnorms2(ctx, dtype, N, k, R, k, s.nrm0);
+  std::vector<double> nrm0, nrm;
+  read_norms(ctx, s.nrm0, k, nrm0);
+  st.iterations = 0;
+  st.deflations = 0;
+  st.converged = all_converged(nrm0, nrm0, rtol, &st.max_rel) ? 1 : 0;
+  if (st.converged) return;
+
+  cg_pupdate(ctx, dtype, N, k, P, R, nullptr, dK, a, b, jacobi);
+  gram(ctx, dtype, N, k, R, k, P, k, s.gamma);
+  int restarts = 0;
+  for (int it = 1; it <= maxit; ++it) {
+    spmm(ctx, op, dtype, k, 0.0, nullptr, k, a, P, k, b, Q, k);
+    gram(ctx, dtype, N, k, P, k, Q, k, s.G);
+    small_spd_solve(ctx, k, s.G, s.gamma, 1.0, eps, s.alpha, s.ndefl);
+    cg_update(ctx, dtype, N, k, X, P, R, Q, s.alpha, dK, a, b, jacobi, s.gamma, s.T, s.nrm);
+    int nd = 0;
+    read_norms(ctx, s.nrm, k, nrm, s.ndefl, &nd);
+    st.iterations = it;
+    st.deflations = std::max(st.deflations, nd);
+    if (all_converged(nrm, nrm0, rtol, &st.max_rel)) {
+      st.converged = 1;
+      return;
+    }
+    if (nd >= k) {  // every search direction collapsed: restart from the preconditioned residual
+      if (++restarts > 3) throw Error{BKTS_EBREAKDOWN, "block CG: search space collapsed repeatedly"};
+      cg_pupdate(ctx, dtype, N, k, P, R, nullptr, dK, a, b, jacobi);
+      gram(ctx, dtype, N, k, R, k, P, k, s.gamma);
+      continue;
+    }
+    restarts = 0;
+    small_spd_solve(ctx, k, s.G, s.T, -1.0, eps, s.beta, nullptr);
+    cg_pupdate(ctx, dtype, N, k, P, R, s.beta, dK, a, b, jacobi);
+  }
+  st.converged = 0;
+}
+
+// One FP32 block CG solve of (a I + b K) V = R64 for FP64 blocks: R64 is scaled per column to
+// unit norm, cast to FP32, solved to `rtol`, and the FP32 correction is scaled back and added to
+// V64 (which need not be zero).
+void f32_correction(bkts_ctx ctx, const bkts_op_s& op, int k, double a, double b, const double* R64,
+                    const double* nrm2, double* V64, bool jacobi, double rtol, int maxit, KrylovStats& st) {
+  const int64_t N = op.N;
+  double* scale = ctx->ws.get<double>("f32_scale", k);
+  std::vector<double> hs(k);
+  for (int j = 0; j < k; ++j) hs[j] = nrm2[j] > 0.0 ? std::sqrt(nrm2[j]) : 1.0;
+  BKTS_HIP(hipMemcpyAsync(scale, hs.data(), sizeof(double) * k, hipMemcpyHostToDevice, ctx->stream));
+  float* R32 = ctx->ws.get<float>("f32_R", (size_t)N * k);
+  float* V32 = ctx->ws.get<float>("f32_V", (size_t)N * k);
+  block_cast_scale(ctx, N, k, BKTS_F64, R64, k, BKTS_F32, R32, k, scale, true, false);
+  BKTS_HIP(hipMemsetAsync(V32, 0, sizeof(float) * N * k, ctx->stream));
+  block_cg(ctx, op, BKTS_F32, k, a, b, R32, V32, true, jacobi, rtol, maxit, st);
+  block_cast_scale(ctx, N, k, BKTS_F32, V32, k, BKTS_F64, V64, k, scale, false, true);
+  ctx->sync();  // hs must outlive the async upload
+}
+
+void solve(bkts_ctx ctx, const bkts_op_s& op, double a, double b, int k, const double* B, double* X, bool x0_zero,
+           const bkts_solve_opts& o, bool single_f32_pass, KrylovStats& st) {
+  BKTS_REQUIRE(o.krylov == BKTS_CG, "only BKTS_CG is available in this build (got %d)", o.krylov);
+  const bool jacobi = o.precond == BKTS_PREC_JACOBI;
+  const int maxit = o.maxit > 0 ? o.maxit : 10000;
+  if (o.precision == BKTS_PRECISION_F64) {
+    block_cg(ctx, op, BKTS_F64, k, a, b, B, X, x0_zero, jacobi, o.rtol, maxit, st);
+    st.refinements = 0;
+    return;
+  }
+  BKTS_REQUIRE(o.precision == BKTS_PRECISION_F32_REFINE, "unknown precision %d", o.precision);
+  const int64_t N = op.N;
+  const double inner = o.inner_rtol > 0.0 ? o.inner_rtol : 1e-4;
+  double* n2 = ctx->ws.get<double>("ref_n2", k);
+  if (single_f32_pass) {
+    // the caller's outer loop supplies FP64 residuals: one scaled FP32 correction of X = 0
+    BKTS_REQUIRE(x0_zero, "single FP32 pass needs a zero initial guess");
+    BKTS_HIP(hipMemsetAsync(X, 0, sizeof(double) * N * k, ctx->stream));
+    colnorms2(ctx, BKTS_F64, N, k, B, k, n2);
+    std::vector<double> nb;
+    read_norms(ctx, n2, k, nb);
+    st = KrylovStats{};
+    f32_correction(ctx, op, k, a, b, B, nb.data(), X, jacobi, std::max(o.rtol, inner), maxit, st);
+    st.refinements = 1;
+    return;
+  }
+  double* R64 = ctx->ws.get<double>("ref_R", (size_t)N * k);
+  if (x0_zero) {
+    BKTS_HIP(hipMemsetAsync(X, 0, sizeof(double) * N * k, ctx->stream));
+    BKTS_HIP(hipMemcpyAsync(R64, B, sizeof(double) * N * k, hipMemcpyDeviceToDevice, ctx->stream));
+  } else {
+    spmm(ctx, op, BKTS_F64, k, 1.0, B, k, -a, X, k, -b, R64, k);
+  }
+  colnorms2(ctx, BKTS_F64, N, k, R64, k, n2);
+  std::vector<double> nrm0, nrm;
+  read_norms(ctx, n2, k, nrm0);
+  nrm = nrm0;
+  st = KrylovStats{};
+  int total = 0;
+  for (int ref = 0; ref < 60; ++ref) {
+    if (all_converged(nrm, nrm0, o.rtol, &st.max_rel)) {
+      st.converged = 1;
+      return;
+    }
+    KrylovStats in;
+    f32_correction(ctx, op, k, a, b, R64, nrm.data(), X, jacobi, inner, maxit - total, in);
+    total += in.iterations;
+    st.iterations = total;
+    st.refinements = ref + 1;
+    st.deflations = std::max(st.deflations, in.deflations);
+    spmm(ctx, op, BKTS_F64, k, 1.0, B, k, -a, X, k, -b, R64, k);
+    colnorms2(ctx, BKTS_F64, N, k, R64, k, n2);
+    read_norms(ctx, n2, k, nrm);
+    if (total >= maxit) break;
+  }
+  st.converged = all_converged(nrm, nrm0, o.rtol, &st.max_rel) ? 1 : 0;
+}
+
+}  // namespace bkts

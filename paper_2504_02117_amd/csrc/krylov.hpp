@@ -1,0 +1,27 @@
+// Block Krylov solvers (krylov.cpp).
+#pragma once
+
+#include "internal.hpp"
+
+namespace bkts {
+
+struct KrylovStats {
+  int iterations = 0;
+  int refinements = 0;
+  int converged = 0;
+  int deflations = 0;
+  double max_rel = 0.0;
+};
+
+// Block CG for (a I + b K) X = B on contiguous blocks of type dtype.  X is the initial guess
+// (ignored and treated as zero when x0_zero).  Per-column relative tolerance rtol.
+void block_cg(bkts_ctx ctx, const bkts_op_s& op, int dtype, int k, double a, double b, const void* B, void* X,
+              bool x0_zero, bool jacobi, double rtol, int maxit, KrylovStats& st);
+
+// FP64 solve entry: F64 block CG, or FP32 block CG inside FP64 iterative refinement.  With
+// single_f32_pass the refinement loop makes one FP32 correction (the caller's own outer loop
+// computes FP64 residuals).
+void solve(bkts_ctx ctx, const bkts_op_s& op, double a, double b, int k, const double* B, double* X, bool x0_zero,
+           const bkts_solve_opts& o, bool single_f32_pass, KrylovStats& st);
+
+}  // namespace bkts

@@ -1,0 +1,170 @@
+// Fused all-at-once residual R = Y A1^T + (K Y - b 1^T) A2^T - B0 with per-column norms
+// (Sec. 2.2; the k x k couplings act from the right, eq. general-system-time-steps with the
+// identity (C (x) A) vec X = vec(A X C^T)).  One pass over Y: the sparse product of the tile rows
+// is formed in registers and staged in LDS next to the Y tile, both right multiplications read
+// whole rows from LDS, and the squared column norms are reduced deterministically.
+#include "devcommon.hpp"
+#include "internal.hpp"
+
+namespace bkts {
+namespace {
+
+using dev::TileGeom;
+
+constexpr int kMaxB0 = 8;
+
+struct ResArgs {
+  int64_t N;
+  int k;
+  const int32_t* rowptr;
+  const int32_t* col;
+  const double* val;
+  const int64_t* sptr;
+  const int32_t* sw;
+  int C;
+  const double* Y;
+  int ldy;
+  const double* A1;    // row-major k x k (physical column order)
+  const double* A2;
+  const double* b;     // source or null
+  const double* rs;    // row sums of A2 (device, k) used with b
+  const double* B0;
+  int ldb0, nb0;
+  int b0col[kMaxB0];
+  double* R;
+  int ldr;
+  double* partials;
+  int64_t tps;
+};
+
+template <int KP>
+constexpr int res_lds() {
+  return (2 * TileGeom<KP>::LDS_DOUBLES > 4 * KP) ? 2 * TileGeom<KP>::LDS_DOUBLES : 4 * KP;
+}
+
+template <int KP, bool SELL>
+__global__ __launch_bounds__(256) void residual_kernel(ResArgs a) {
+  using G = TileGeom<KP>;
+  __shared__ __align__(16) double lds[res_lds<KP>()];
+  double* Yl = lds;
+  double* KYl = lds + G::LDS_DOUBLES;
+  const int t = threadIdx.x, c = t % KP, r0 = t / KP;
+  const int64_t slot = dev::xcd_slot(blockIdx.x, gridDim.x);
+  const int64_t ntiles = (a.N + G::RT - 1) / G::RT;
+  const bool cok = c < a.k;
+  double a1[KP], a2[KP];
+#pragma unroll
+  for (int j = 0; j < KP; ++j) {
+    a1[j] = (cok && j < a.k) ? a.A1[c * a.k + j] : 0.0;
+    a2[j] = (cok && j < a.k) ? a.A2[c * a.k + j] : 0.0;
+  }
+  const double rsc = (a.b && cok) ? a.rs[c] : 0.0;
+  int b0j = -1;
+  for (int j = 0; j < a.nb0; ++j)
+    if (a.b0col[j] == c) b0j = j;
+  double nacc[1] = {0.0};
+  const int64_t tend = (slot + 1) * a.tps < ntiles ? (slot + 1) * a.tps : ntiles;
+  for (int64_t tile = slot * a.tps; tile < tend; ++tile) {
+    const int64_t row0 = tile * G::RT;
+#pragma unroll 2
+    for (int i = 0; i < G::RPT; ++i) {
+      const int row = r0 + i * G::RS;
+      const int64_t gr = row0 + row;
+      double yv = 0.0, ky = 0.0;
+      if (gr < a.N && cok) {
+        yv = a.Y[gr * a.ldy + c];
+        int64_t base, stride, len;
+        if constexpr (SELL) {
+          const int64_t s = gr / a.C;
+          base = a.sptr[s] + (gr - s * a.C);
+          stride = a.C;
+          len = a.sw[s];
+        } else {
+          base = a.rowptr[gr];
+          stride = 1;
+          len = a.rowptr[gr + 1] - base;
+        }
+        for (int64_t j = 0; j < len; ++j) {
+          const int64_t e = base + j * stride;
+          ky = fma(a.val[e], a.Y[(int64_t)a.col[e] * a.ldy + c], ky);
+        }
+      }
+      Yl[row * G::LDL + c] = yv;
+      KYl[row * G::LDL + c] = ky;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < G::RPT; ++i) {
+      const int row = r0 + i * G::RS;
+      const int64_t gr = row0 + row;
+      if (gr < a.N && cok) {
+        double r = dev::lds_row_dot<KP>(Yl, row, a1) + dev::lds_row_dot<KP>(KYl, row, a2);
+        if (a.b) r -= a.b[gr] * rsc;
+        if (b0j >= 0) r -= a.B0[gr * a.ldb0 + b0j];
+        a.R[gr * a.ldr + c] = r;
+        nacc[0] = fma(r, r, nacc[0]);
+      }
+    }
+    __syncthreads();
+  }
+  dev::block_reduce_store<KP, 1>(nacc, lds, a.partials, gridDim.x, slot);
+}
+
+template <int KP>
+void launch_res(bkts_ctx ctx, const bkts_op_s& op, ResArgs a, double* nrm) {
+  using G = TileGeom<KP>;
+  const int64_t ntiles = (a.N + G::RT - 1) / G::RT;
+  const int64_t cap = 2 * (int64_t)ctx->num_cu;
+  int64_t ns = ntiles < cap ? ntiles : cap;
+  if (ns < 1) ns = 1;
+  a.tps = (ntiles + ns - 1) / ns;
+  a.partials = ctx->ws.get<double>("res_partials", (size_t)KP * ns);
+  ProfScope prof(ctx, BKTS_K_RESIDUAL,
+                 op.nnz * 12.0 + 4.0 * (op.N + 1) + 16.0 * op.N * a.k + (a.b ? 8.0 * op.N : 0.0) + 8.0 * op.N * a.nb0);
+  if (op.format == BKTS_FMT_SELL)
+    hipLaunchKernelGGL((residual_kernel<KP, true>), dim3(ns), dim3(256), 0, ctx->stream, a);
+  else
+    hipLaunchKernelGGL((residual_kernel<KP, false>), dim3(ns), dim3(256), 0, ctx->stream, a);
+  BKTS_HIP(hipGetLastError());
+  finalize_partials(ctx, a.partials, (int)ns, a.k, nrm);
+}
+
+}  // namespace
+
+void residual(bkts_ctx ctx, const bkts_op_s& op, int k, const double* Y, int ldy, const double* A1t,
+              const double* A2t, const double* b_rowsum, const double* B0, int ldb0, int nb0, const int* b0_to_col,
+              double* R, int ldr, double* nrm) {
+  BKTS_REQUIRE(nb0 >= 0 && nb0 <= kMaxB0, "at most %d B0 columns", kMaxB0);
+  ResArgs a{};
+  a.N = op.N;
+  a.k = k;
+  a.rowptr = op.rowptr.as<int32_t>();
+  const bool sell = op.format == BKTS_FMT_SELL;
+  a.col = sell ? op.sell_col.as<int32_t>() : op.col.as<int32_t>();
+  a.val = sell ? op.sell_val.as<double>() : op.val.as<double>();
+  a.sptr = op.sell_ptr.as<int64_t>();
+  a.sw = op.sell_w.as<int32_t>();
+  a.C = op.sell_C;
+  a.Y = Y;
+  a.ldy = ldy;
+  a.A1 = A1t;
+  a.A2 = A2t;
+  a.b = op.b_nonzero ? op.b.as<double>() : nullptr;
+  a.rs = b_rowsum;
+  a.B0 = B0;
+  a.ldb0 = ldb0;
+  a.nb0 = B0 ? nb0 : 0;
+  for (int j = 0; j < kMaxB0; ++j) a.b0col[j] = j < a.nb0 ? b0_to_col[j] : -1;
+  a.R = R;
+  a.ldr = ldr;
+  switch (k <= 1 ? 1 : k <= 2 ? 2 : k <= 4 ? 4 : k <= 8 ? 8 : k <= 16 ? 16 : 32) {
+    case 1: launch_res<1>(ctx, op, a, nrm); break;
+    case 2: launch_res<2>(ctx, op, a, nrm); break;
+    case 4: launch_res<4>(ctx, op, a, nrm); break;
+    case 8: launch_res<8>(ctx, op, a, nrm); break;
+    case 16: launch_res<16>(ctx, op, a, nrm); break;
+    default: launch_res<32>(ctx, op, a, nrm); break;
+  }
+}
+
+}  // namespace bkts

@@ -1,0 +1,222 @@
+// Block operator Y = cb*B + alpha*X + beta*K X for row-major N x k blocks (Sec. 3, "BOP").
+//
+// Each row of K is handled by LPR = KP/VEC lanes of one wave64; every lane owns VEC consecutive
+// columns.  The LPR lanes of a row read the same matrix entry (one memory transaction per wave
+// instruction), so each value/index pair streams from HBM once per block of k columns, while the
+// X rows of the neighbours are read as contiguous k-element segments.  SELL-C (C = 64, sigma = 1)
+// stores the entries slice-column-major so that the row groups of a wave read consecutive
+// addresses; CSR is the general fallback.  Workgroups are remapped so that each XCD streams one
+// contiguous row range, which keeps the X rows of nearby stencil neighbours in that XCD's L2.
+#include "devcommon.hpp"
+#include "internal.hpp"
+
+namespace bkts {
+namespace {
+
+template <typename T, int V>
+struct Vec {
+  T v[V];
+};
+
+template <typename T, int V>
+__device__ __forceinline__ Vec<T, V> vload(const T* p) {
+  Vec<T, V> r;
+  if constexpr (V == 1) {
+    r.v[0] = *p;
+  } else if constexpr (sizeof(T) * V == 16) {
+    if constexpr (sizeof(T) == 8) {
+      const double2 q = *reinterpret_cast<const double2*>(p);
+      r.v[0] = q.x;
+      r.v[1] = q.y;
+    } else {
+      const float4 q = *reinterpret_cast<const float4*>(p);
+      r.v[0] = q.x;
+      r.v[1] = q.y;
+      r.v[2] = q.z;
+      r.v[3] = q.w;
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < V; ++i) r.v[i] = p[i];
+  }
+  return r;
+}
+
+template <typename T, int V>
+__device__ __forceinline__ void vstore(T* p, const Vec<T, V>& r) {
+  if constexpr (V == 1) {
+    *p = r.v[0];
+  } else if constexpr (sizeof(T) * V == 16) {
+    if constexpr (sizeof(T) == 8) {
+      *reinterpret_cast<double2*>(p) = double2{r.v[0], r.v[1]};
+    } else {
+      *reinterpret_cast<float4*>(p) = float4{r.v[0], r.v[1], r.v[2], r.v[3]};
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < V; ++i) p[i] = r.v[i];
+  }
+}
+
+template <typename T>
+struct SpmmArgs {
+  int64_t N;
+  int k;
+  const int32_t* rowptr;  // CSR
+  const int32_t* col;
+  const T* val;
+  const int64_t* sptr;    // SELL
+  const int32_t* sw;
+  int C;
+  T cb, alpha, beta;
+  const T* B;
+  int ldb;
+  const T* X;
+  int ldx;
+  T* Y;
+  int ldy;
+};
+
+constexpr int kUnroll = 8;
+
+template <typename T, int KP, int VEC, bool SELL>
+__global__ __launch_bounds__(256) void spmm_kernel(SpmmArgs<T> a) {
+  constexpr int LPR = KP / VEC;
+  constexpr int RPB = dev::kThreads / LPR;
+  const int t = threadIdx.x;
+  const int c0 = (t % LPR) * VEC;
+  const int64_t tile = dev::xcd_slot(blockIdx.x, gridDim.x);
+  const int64_t r = tile * RPB + t / LPR;
+  if (r >= a.N) return;
+  const bool active = c0 < a.k;
+  Vec<T, VEC> acc;
+#pragma unroll
+  for (int i = 0; i < VEC; ++i) acc.v[i] = T(0);
+
+  int64_t base, stride, len;
+  if constexpr (SELL) {
+    const int64_t s = r / a.C;
+    base = a.sptr[s] + (r - s * a.C);
+    stride = a.C;
+    len = a.sw[s];
+  } else {
+    base = a.rowptr[r];
+    stride = 1;
+    len = a.rowptr[r + 1] - base;
+  }
+  for (int64_t j0 = 0; j0 < len; j0 += kUnroll) {
+    T v[kUnroll];
+    int32_t cidx[kUnroll];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      const bool ok = j0 + u < len;
+      const int64_t e = base + (j0 + u) * stride;
+      v[u] = ok ? a.val[e] : T(0);
+      cidx[u] = ok ? a.col[e] : (int32_t)r;
+    }
+    if (active) {
+      Vec<T, VEC> x[kUnroll];
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) x[u] = vload<T, VEC>(a.X + (int64_t)cidx[u] * a.ldx + c0);
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u)
+#pragma unroll
+        for (int i = 0; i < VEC; ++i) acc.v[i] = fma(v[u], x[u].v[i], acc.v[i]);
+    }
+  }
+  if (!active) return;
+  Vec<T, VEC> out;
+  const Vec<T, VEC> xr = vload<T, VEC>(a.X + r * a.ldx + c0);
+#pragma unroll
+  for (int i = 0; i < VEC; ++i) out.v[i] = a.beta * acc.v[i] + a.alpha * xr.v[i];
+  if (a.B) {
+    const Vec<T, VEC> br = vload<T, VEC>(a.B + r * a.ldb + c0);
+#pragma unroll
+    for (int i = 0; i < VEC; ++i) out.v[i] = fma(a.cb, br.v[i], out.v[i]);
+  }
+  vstore<T, VEC>(a.Y + r * a.ldy + c0, out);
+}
+
+template <typename T, int KP, int VEC>
+void launch_fmt(bkts_ctx ctx, const bkts_op_s& op, const SpmmArgs<T>& a) {
+  constexpr int LPR = KP / VEC;
+  constexpr int RPB = dev::kThreads / LPR;
+  const int64_t nb = (a.N + RPB - 1) / RPB;
+  if (op.format == BKTS_FMT_SELL)
+    hipLaunchKernelGGL((spmm_kernel<T, KP, VEC, true>), dim3(nb), dim3(dev::kThreads), 0, ctx->stream, a);
+  else
+    hipLaunchKernelGGL((spmm_kernel<T, KP, VEC, false>), dim3(nb), dim3(dev::kThreads), 0, ctx->stream, a);
+}
+
+template <typename T, int KP>
+void launch_kp(bkts_ctx ctx, const bkts_op_s& op, const SpmmArgs<T>& a, bool vec_ok) {
+  constexpr int VMAX = 16 / sizeof(T);
+  if constexpr (KP >= VMAX) {
+    if (vec_ok) return launch_fmt<T, KP, VMAX>(ctx, op, a);
+  }
+  launch_fmt<T, KP, 1>(ctx, op, a);
+}
+
+inline int padded_k(int k) {
+  int kp = 1;
+  while (kp < k) kp <<= 1;
+  return kp;
+}
+
+template <typename T>
+void spmm_t(bkts_ctx ctx, const bkts_op_s& op, int k, double cb, const void* B, int ldb, double alpha,
+            const void* X, int ldx, double beta, void* Y, int ldy) {
+  SpmmArgs<T> a{};
+  a.N = op.N;
+  a.k = k;
+  a.rowptr = op.rowptr.as<int32_t>();
+  const bool sell = op.format == BKTS_FMT_SELL;
+  a.col = sell ? op.sell_col.as<int32_t>() : op.col.as<int32_t>();
+  if constexpr (sizeof(T) == 8)
+    a.val = sell ? op.sell_val.as<double>() : op.val.as<double>();
+  else
+    a.val = sell ? op.sell_val32.as<float>() : op.val32.as<float>();
+  a.sptr = op.sell_ptr.as<int64_t>();
+  a.sw = op.sell_w.as<int32_t>();
+  a.C = op.sell_C;
+  a.cb = (T)cb;
+  a.alpha = (T)alpha;
+  a.beta = (T)beta;
+  a.B = static_cast<const T*>(B);
+  a.ldb = ldb;
+  a.X = static_cast<const T*>(X);
+  a.ldx = ldx;
+  a.Y = static_cast<T*>(Y);
+  a.ldy = ldy;
+  const int kp = padded_k(k);
+  constexpr int VMAX = 16 / sizeof(T);
+  const double sv = sizeof(T);
+  ProfScope prof(ctx, BKTS_K_SPMM,
+                 op.nnz * (sv + 4.0) + 4.0 * (op.N + 1) + (2.0 + (B ? 1.0 : 0.0)) * op.N * k * sv);
+  auto aligned = [](const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; };
+  const bool vec_ok = k == kp && ldx % VMAX == 0 && ldy % VMAX == 0 && aligned(X) && aligned(Y) &&
+                      (!B || (ldb % VMAX == 0 && aligned(B)));
+  switch (kp) {
+    case 1: launch_kp<T, 1>(ctx, op, a, vec_ok); break;
+    case 2: launch_kp<T, 2>(ctx, op, a, vec_ok); break;
+    case 4: launch_kp<T, 4>(ctx, op, a, vec_ok); break;
+    case 8: launch_kp<T, 8>(ctx, op, a, vec_ok); break;
+    case 16: launch_kp<T, 16>(ctx, op, a, vec_ok); break;
+    case 32: launch_kp<T, 32>(ctx, op, a, vec_ok); break;
+    default: throw Error{BKTS_EINVAL, fmt("k=%d exceeds BKTS_MAX_K", k)};
+  }
+  BKTS_HIP(hipGetLastError());
+}
+
+}  // namespace
+
+void spmm(bkts_ctx ctx, const bkts_op_s& op, int dtype, int k, double cb, const void* B, int ldb, double alpha,
+          const void* X, int ldx, double beta, void* Y, int ldy) {
+  if (op.N == 0) return;
+  if (dtype == BKTS_F64)
+    spmm_t<double>(ctx, op, k, cb, B, ldb, alpha, X, ldx, beta, Y, ldy);
+  else
+    spmm_t<float>(ctx, op, k, cb, B, ldb, alpha, X, ldx, beta, Y, ldy);
+}
+
+}  // namespace bkts

@@ -1,0 +1,99 @@
+// Time coupling of a stiffly accurate DIRK method (Sec. 2, eq. stiffly-accurate-DIRK; Sec. 2.1):
+// tableau, elimination of an explicit first stage, and the k x k window matrices A1, A2 of
+// eq. time-stepping-matrices-multiple-parallel-time-steps taken from the diagonal position of the
+// window's front stage (Sec. 2.2, pipelining).
+#include <cmath>
+
+#include "internal.hpp"
+#include "timecoupling.hpp"
+
+namespace bkts {
+
+// Entry (qi, qj) of the unbounded stage-coupling matrices, with global stage indices counted from
+// the first implicit stage of the front step.  A1 = I/tau plus -1/tau from every stage of step
+// s >= 1 to the last stage of step s-1 (that stage is y^{n+s}); A2 = block-diagonal implicit
+// tableau plus, when an explicit first stage was eliminated, its couplings a_{i,1} at the
+// positions of those -1/tau entries.
+static void coupling_entry(const bkts_tc_s& tc, int qi, int qj, double& a1, double& a2) {
+  const int mi = tc.m_impl;
+  const int si = qi / mi, sj = qj / mi;
+  const int li = qi % mi, lj = qj % mi;
+  a1 = (qi == qj) ? 1.0 / tc.tau : 0.0;
+  a2 = (si == sj) ? tc.Ai[li * mi + lj] : 0.0;
+  if (si >= 1 && qj == si * mi - 1) {
+    a1 += -1.0 / tc.tau;
+    if (tc.explicit_first) a2 += tc.ae[li];
+  }
+}
+
+bkts_tc tc_create(bkts_ctx ctx, const bkts_tc_desc* d) {
+  BKTS_REQUIRE(d, "desc must not be NULL");
+  BKTS_REQUIRE(d->k >= 1 && d->k <= BKTS_MAX_K, "k must be in 1..%d (got %d)", BKTS_MAX_K, d->k);
+  BKTS_REQUIRE(d->tau > 0.0 && std::isfinite(d->tau), "tau must be positive");
+  int m = 0;
+  std::vector<double> A, c;
+  switch (d->method) {
+    case BKTS_IE:
+      m = 1;
+      A = {1.0};
+      c = {1.0};
+      break;
+    case BKTS_THETA:
+      BKTS_REQUIRE(d->theta > 0.0 && d->theta <= 1.0, "theta must be in (0, 1]");
+      m = 2;
+      A = {0.0, 0.0, 1.0 - d->theta, d->theta};
+      c = {0.0, 1.0};
+      break;
+    case BKTS_SDIRK2: {
+      const double g = 1.0 - 1.0 / std::sqrt(2.0);
+      m = 2;
+      A = {g, 0.0, 1.0 - g, g};
+      c = {g, 1.0};
+      break;
+    }
+    case BKTS_DIRK_CUSTOM:
+      BKTS_REQUIRE(d->stages >= 1 && d->stages <= 8 && d->A && d->c, "custom tableau needs 1..8 stages, A and c");
+      m = d->stages;
+      A.assign(d->A, d->A + m * m);
+      c.assign(d->c, d->c + m);
+      for (int i = 0; i < m; ++i)
+        for (int j = i + 1; j < m; ++j) BKTS_REQUIRE(A[i * m + j] == 0.0, "tableau must be lower triangular");
+      break;
+    default:
+      throw Error{BKTS_EINVAL, fmt("unknown method %d", d->method)};
+  }
+  bkts_tc t = new bkts_tc_s();
+  t->ctx = ctx;
+  t->k = d->k;
+  t->tau = d->tau;
+  bool expl = true;
+  for (int j = 0; j < m; ++j) expl = expl && A[j] == 0.0;
+  expl = expl && m > 1;
+  t->explicit_first = expl ? 1 : 0;
+  const int off = expl ? 1 : 0;
+  const int mi = m - off;
+  t->m_impl = mi;
+  t->Ai.assign(mi * mi, 0.0);
+  t->ae.assign(mi, 0.0);
+  t->ci.assign(mi, 0.0);
+  for (int i = 0; i < mi; ++i) {
+    for (int j = 0; j < mi; ++j) t->Ai[i * mi + j] = A[(i + off) * m + (j + off)];
+    if (expl) t->ae[i] = A[(i + off) * m];
+    t->ci[i] = c[i + off];
+  }
+  for (int i = 0; i < mi; ++i) {
+    if (!(t->Ai[i * mi + i] > 0.0)) {
+      delete t;
+      throw Error{BKTS_EINVAL, "implicit stages need a positive diagonal entry"};
+    }
+  }
+  const int k = d->k;
+  t->A1.assign(mi, std::vector<double>(k * k));
+  t->A2.assign(mi, std::vector<double>(k * k));
+  for (int p = 0; p < mi; ++p)
+    for (int i = 0; i < k; ++i)
+      for (int j = 0; j < k; ++j) coupling_entry(*t, p + i, p + j, t->A1[p][i * k + j], t->A2[p][i * k + j]);
+  return t;
+}
+
+}  // namespace bkts

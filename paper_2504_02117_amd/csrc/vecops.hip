@@ -1,0 +1,80 @@
+// Streaming helpers on FP64 vectors and block columns used by the time-stepping loop: window
+// initialisation, the pipelining shift, column extraction, linear combinations and AXPY.
+#include "devcommon.hpp"
+#include "internal.hpp"
+#include "vecops.hpp"
+
+namespace bkts {
+namespace {
+
+__global__ void broadcast_cols_kernel(int64_t N, int k, const double* y, double* Y, int ld) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N * k) return;
+  const int64_t r = i / k;
+  Y[r * ld + (i % k)] = y[r];
+}
+
+__global__ void copy_col_kernel(int64_t N, double* Y, int ld, int src, int dst) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < N) Y[r * ld + dst] = Y[r * ld + src];
+}
+
+__global__ void extract_col_kernel(int64_t N, const double* Y, int ld, int c, double* out) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < N) out[r] = Y[r * ld + c];
+}
+
+__global__ void lincomb_kernel(int64_t N, LinComb lc, double* out, int ldo) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= N) return;
+  double s = 0.0;
+  for (int i = 0; i < lc.m; ++i) s = fma(lc.a[i], lc.v[i][r * lc.s[i]], s);
+  out[r * ldo] = s;
+}
+
+__global__ void axpby_kernel(int64_t n, double a, const double* x, double b, double* y) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = fma(a, x[i], b * y[i]);
+}
+
+inline dim3 grid1(int64_t n) { return dim3((unsigned)((n + 255) / 256)); }
+
+}  // namespace
+
+void broadcast_cols(bkts_ctx ctx, int64_t N, int k, const double* y, double* Y, int ld) {
+  if (N * k == 0) return;
+  ProfScope prof(ctx, BKTS_K_OTHER, 16.0 * N * k);
+  hipLaunchKernelGGL(broadcast_cols_kernel, grid1(N * k), dim3(256), 0, ctx->stream, N, k, y, Y, ld);
+  BKTS_HIP(hipGetLastError());
+}
+
+void copy_col(bkts_ctx ctx, int64_t N, double* Y, int ld, int src, int dst) {
+  if (N == 0 || src == dst) return;
+  ProfScope prof(ctx, BKTS_K_OTHER, 16.0 * N);
+  hipLaunchKernelGGL(copy_col_kernel, grid1(N), dim3(256), 0, ctx->stream, N, Y, ld, src, dst);
+  BKTS_HIP(hipGetLastError());
+}
+
+void extract_col(bkts_ctx ctx, int64_t N, const double* Y, int ld, int c, double* out) {
+  if (N == 0) return;
+  ProfScope prof(ctx, BKTS_K_OTHER, 16.0 * N);
+  hipLaunchKernelGGL(extract_col_kernel, grid1(N), dim3(256), 0, ctx->stream, N, Y, ld, c, out);
+  BKTS_HIP(hipGetLastError());
+}
+
+void lincomb(bkts_ctx ctx, int64_t N, const LinComb& lc, double* out, int ldo) {
+  BKTS_REQUIRE(lc.m >= 0 && lc.m <= LinComb::kMax, "too many terms");
+  if (N == 0) return;
+  ProfScope prof(ctx, BKTS_K_OTHER, 8.0 * N * (lc.m + 1));
+  hipLaunchKernelGGL(lincomb_kernel, grid1(N), dim3(256), 0, ctx->stream, N, lc, out, ldo);
+  BKTS_HIP(hipGetLastError());
+}
+
+void axpby(bkts_ctx ctx, int64_t n, double a, const double* x, double b, double* y) {
+  if (n == 0) return;
+  ProfScope prof(ctx, BKTS_K_OTHER, 24.0 * n);
+  hipLaunchKernelGGL(axpby_kernel, grid1(n), dim3(256), 0, ctx->stream, n, a, x, b, y);
+  BKTS_HIP(hipGetLastError());
+}
+
+}  // namespace bkts
