@@ -36,14 +36,15 @@ def parse():
     p.add_argument("--steps", type=int, default=16)
     p.add_argument("--warmup", type=int, default=16)
     p.add_argument("--n", type=int, default=128)
-    p.add_argument("--k", type=int, default=16)
+    p.add_argument("--k", type=int, default=4)
     p.add_argument("--precision", choices=["f32", "f64"], default="f32")
     p.add_argument("--inner-rtol", type=float, default=1e-2)
     p.add_argument("--plain-steps", type=int, default=8)
     p.add_argument("--no-plain", action="store_true")
     p.add_argument("--no-cpu", action="store_true")
     p.add_argument("--cpu-steps", type=int, default=1)
-    p.add_argument("--sweep", type=str, default="", help="comma list of extra k values to time (block form)")
+    p.add_argument("--sweep", type=str, default="1f32,4f64,8,16,32",
+                   help="comma list of extra block forms to time: <k>[f32|f64] (default precision: --precision)")
     return p.parse_args()
 
 
@@ -142,11 +143,24 @@ def main():
         log(f"  {pl['value']:.4g} DOF*steps/s")
 
     sweep = {}
-    for ks in [int(v) for v in a.sweep.split(",") if v.strip()]:
-        r = run_form(torch, bkts, ctx, op, y0, ks, a.precision, a.inner_rtol, a.warmup, a.steps, False)
-        sweep[str(ks)] = {"value": r["value"], "outer": r["info"].outer_iterations,
-                          "krylov": r["info"].krylov_iterations}
-        log(f"  sweep k={ks}: {r['value']:.4g}")
+    for item in [v.strip() for v in a.sweep.split(",") if v.strip()]:
+        prec = a.precision
+        if item.endswith("f32") or item.endswith("f64"):
+            prec, item = item[-3:], item[:-3]
+        ks = int(item)
+        r = run_form(torch, bkts, ctx, op, y0, ks, prec, a.inner_rtol, a.warmup, a.steps, True)
+        sp = r["kernels"].get("spmm", {})
+        sv = 4 if prec == "f32" else 8
+        bpl = nnz * (sv + 4) + 4 * (N + 1) + 2 * N * ks * sv
+        dom = max(r["kernels"].items(), key=lambda kv: kv[1]["total_ms"])[0] if r["kernels"] else None
+        sweep[f"k={ks} {prec}"] = {
+            "value": r["value"], "outer": r["info"].outer_iterations, "krylov": r["info"].krylov_iterations,
+            "spmm_avg_us": sp.get("avg_us"),
+            "spmm_GBps": (bpl / (sp["avg_us"] * 1e-6) / 1e9) if sp else None,
+            "spmm_frac": (bpl / (sp["avg_us"] * 1e-6) / 1e9 / HBM_PEAK_GBS) if sp else None,
+            "dominant_kernel": dom,
+            "kernels": {kk: {"avg_us": vv["avg_us"], "GBps": vv["GBps"]} for kk, vv in r["kernels"].items()}}
+        log(f"  sweep k={ks} {prec}: {r['value']:.4g} DOF*steps/s (spmm {sp.get('avg_us', 0):.1f} us)")
 
     spmm = blk["kernels"].get("spmm")
     roof = None

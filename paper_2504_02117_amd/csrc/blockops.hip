@@ -121,17 +121,13 @@ __device__ __forceinline__ void load_col(const double* M, int k, int c, double (
   for (int j = 0; j < KP; ++j) col[j] = (j < k && c < k) ? M[j * k + c] : 0.0;
 }
 
-__device__ __forceinline__ double jacobi_inv(bool jacobi, const double* diagK, int64_t r, double a_shift,
-                                             double b_scale) {
-  return jacobi ? 1.0 / (a_shift + b_scale * diagK[r]) : 1.0;
-}
+__device__ __forceinline__ double dinv_at(const double* dinv, int64_t r) { return dinv ? dinv[r] : 1.0; }
 
 // X += P alpha; R -= Q alpha; Z = Dinv R; gamma = R^T Z; T = Q^T Z; nrm = diag(R^T R).
 template <typename T, int KP>
 __global__ __launch_bounds__(256) void cg_update_kernel(int64_t N, int k, T* __restrict__ X, const T* __restrict__ P,
                                                         T* __restrict__ R, const T* __restrict__ Q,
-                                                        const double* __restrict__ alpha, const double* diagK,
-                                                        double a_shift, double b_scale, int jacobi,
+                                                        const double* __restrict__ alpha, const double* dinv,
                                                         double* pg, double* pt, double* pn, int64_t tps) {
   using G = TileGeom<KP>;
   __shared__ __align__(16) double lds[lds_doubles<KP>(2)];
@@ -168,7 +164,7 @@ __global__ __launch_bounds__(256) void cg_update_kernel(int64_t N, int k, T* __r
       x[i] += dev::lds_row_dot<KP>(Pl, row, acol);
       r[i] -= dev::lds_row_dot<KP>(Ql, row, acol);
       const bool ok = gr < N && c < k;
-      z[i] = ok ? r[i] * jacobi_inv(jacobi, diagK, gr, a_shift, b_scale) : 0.0;
+      z[i] = ok ? r[i] * dinv_at(dinv, gr) : 0.0;
       if (ok) {
         X[gr * k + c] = (T)x[i];
         R[gr * k + c] = (T)r[i];
@@ -197,8 +193,8 @@ __global__ __launch_bounds__(256) void cg_update_kernel(int64_t N, int k, T* __r
 // P = Dinv R + P beta   (beta == nullptr: P = Dinv R)
 template <typename T, int KP>
 __global__ __launch_bounds__(256) void cg_pupdate_kernel(int64_t N, int k, T* __restrict__ P, const T* __restrict__ R,
-                                                         const double* __restrict__ beta, const double* diagK,
-                                                         double a_shift, double b_scale, int jacobi, int64_t tps) {
+                                                         const double* __restrict__ beta, const double* dinv,
+                                                         int64_t tps) {
   using G = TileGeom<KP>;
   __shared__ __align__(16) double lds[lds_doubles<KP>(1)];
   const int t = threadIdx.x, c = t % KP, r0 = t / KP;
@@ -216,7 +212,7 @@ __global__ __launch_bounds__(256) void cg_pupdate_kernel(int64_t N, int k, T* __
       const int64_t gr = row0 + row;
       const bool ok = gr < N && c < k;
       if (beta) lds[row * G::LDL + c] = ok ? dev::ld_d(P + gr * k + c) : 0.0;
-      r[i] = ok ? dev::ld_d(R + gr * k + c) * jacobi_inv(jacobi, diagK, gr, a_shift, b_scale) : 0.0;
+      r[i] = ok ? dev::ld_d(R + gr * k + c) * dinv_at(dinv, gr) : 0.0;
     }
     __syncthreads();
 #pragma unroll
@@ -295,7 +291,8 @@ void launch_gram_t(bkts_ctx ctx, int dtype, int64_t N, int k, const void* X, int
     hipLaunchKernelGGL((gram_kernel<float, KP>), dim3(s.nslots), dim3(256), 0, ctx->stream, N, k,
                        static_cast<const float*>(X), ldx, static_cast<const float*>(Y), ldy, part, s.tps);
   BKTS_HIP(hipGetLastError());
-  hipLaunchKernelGGL(finalize_kernel, dim3(k * k), dim3(256), 0, ctx->stream, part, s.nslots, k, KP, 0, G);
+  prof.end();
+  finalize_gram(ctx, part, (int)s.nslots, k, KP, G);
   BKTS_HIP(hipGetLastError());
 }
 
@@ -311,37 +308,38 @@ void launch_colnorm_t(bkts_ctx ctx, int dtype, int64_t N, int k, const void* X, 
     hipLaunchKernelGGL((colnorm_kernel<float, KP>), dim3(s.nslots), dim3(256), 0, ctx->stream, N, k,
                        static_cast<const float*>(X), ldx, part, s.tps);
   BKTS_HIP(hipGetLastError());
-  hipLaunchKernelGGL(finalize_kernel, dim3(k), dim3(256), 0, ctx->stream, part, s.nslots, k, KP, 1, out);
+  prof.end();
+  finalize_partials(ctx, part, (int)s.nslots, k, out);
   BKTS_HIP(hipGetLastError());
 }
 
 template <typename T, int KP>
 void launch_cg_update_t(bkts_ctx ctx, int64_t N, int k, void* X, const void* P, void* R, const void* Q,
-                        const double* alpha, const double* diagK, double a_shift, double b_scale, bool jacobi,
+                        const double* alpha, const double* dinv,
                         double* gamma, double* Tm, double* nrm) {
   Slots s = make_slots<KP>(ctx, N);
   const size_t np = (size_t)KP * KP * s.nslots;
   double* pg = ctx->ws.get<double>("cg_pg", np);
   double* pt = ctx->ws.get<double>("cg_pt", np);
   double* pn = ctx->ws.get<double>("cg_pn", (size_t)KP * s.nslots);
-  ProfScope prof(ctx, BKTS_K_CG_UPDATE, 6.0 * N * k * sizeof(T) + (jacobi ? 8.0 * N : 0.0));
+  ProfScope prof(ctx, BKTS_K_CG_UPDATE, 6.0 * N * k * sizeof(T) + (dinv ? 8.0 * N : 0.0));
   hipLaunchKernelGGL((cg_update_kernel<T, KP>), dim3(s.nslots), dim3(256), 0, ctx->stream, N, k, static_cast<T*>(X),
-                     static_cast<const T*>(P), static_cast<T*>(R), static_cast<const T*>(Q), alpha, diagK, a_shift,
-                     b_scale, (int)jacobi, pg, pt, pn, s.tps);
+                     static_cast<const T*>(P), static_cast<T*>(R), static_cast<const T*>(Q), alpha, dinv, pg, pt, pn, s.tps);
   BKTS_HIP(hipGetLastError());
-  hipLaunchKernelGGL(finalize_kernel, dim3(k * k), dim3(256), 0, ctx->stream, pg, s.nslots, k, KP, 0, gamma);
-  hipLaunchKernelGGL(finalize_kernel, dim3(k * k), dim3(256), 0, ctx->stream, pt, s.nslots, k, KP, 0, Tm);
-  hipLaunchKernelGGL(finalize_kernel, dim3(k), dim3(256), 0, ctx->stream, pn, s.nslots, k, KP, 1, nrm);
+  prof.end();
+  finalize_gram(ctx, pg, (int)s.nslots, k, KP, gamma);
+  finalize_gram(ctx, pt, (int)s.nslots, k, KP, Tm);
+  finalize_partials(ctx, pn, (int)s.nslots, k, nrm);
   BKTS_HIP(hipGetLastError());
 }
 
 template <typename T, int KP>
 void launch_cg_pupdate_t(bkts_ctx ctx, int64_t N, int k, void* P, const void* R, const double* beta,
-                         const double* diagK, double a_shift, double b_scale, bool jacobi) {
+                         const double* dinv) {
   Slots s = make_slots<KP>(ctx, N);
-  ProfScope prof(ctx, BKTS_K_CG_PUPDATE, (beta ? 3.0 : 2.0) * N * k * sizeof(T) + (jacobi ? 8.0 * N : 0.0));
+  ProfScope prof(ctx, BKTS_K_CG_PUPDATE, (beta ? 3.0 : 2.0) * N * k * sizeof(T) + (dinv ? 8.0 * N : 0.0));
   hipLaunchKernelGGL((cg_pupdate_kernel<T, KP>), dim3(s.nslots), dim3(256), 0, ctx->stream, N, k, static_cast<T*>(P),
-                     static_cast<const T*>(R), beta, diagK, a_shift, b_scale, (int)jacobi, s.tps);
+                     static_cast<const T*>(R), beta, dinv, s.tps);
   BKTS_HIP(hipGetLastError());
 }
 
@@ -375,7 +373,17 @@ void finalize_partials(bkts_ctx ctx, const double* partials, int nblocks, int ne
   BKTS_HIP(hipGetLastError());
 }
 
+void finalize_gram(bkts_ctx ctx, const double* partials, int nblocks, int k, int KP, double* out) {
+  ProfScope prof(ctx, BKTS_K_SMALL, 8.0 * nblocks * k * k);
+  hipLaunchKernelGGL(finalize_kernel, dim3(k * k), dim3(256), 0, ctx->stream, partials, (int64_t)nblocks, k, KP, 0,
+                     out);
+  BKTS_HIP(hipGetLastError());
+}
+
 void gram(bkts_ctx ctx, int dtype, int64_t N, int k, const void* X, int ldx, const void* Y, int ldy, double* G) {
+  if (mf_eligible(k)) return mf_gram(ctx, dtype, N, k, X, ldx, Y, ldy, G);
+  auto al16 = [](const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; };
+  if (rk_eligible(k) && ldx == k && ldy == k && al16(X) && al16(Y)) return rk_gram(ctx, dtype, N, k, X, Y, G);
   BKTS_KP_DISPATCH(k, (launch_gram_t<KP>(ctx, dtype, N, k, X, ldx, Y, ldy, G)));
 }
 
@@ -384,26 +392,33 @@ void colnorms2(bkts_ctx ctx, int dtype, int64_t N, int k, const void* X, int ldx
 }
 
 void cg_update(bkts_ctx ctx, int dtype, int64_t N, int k, void* X, const void* P, void* R, const void* Q,
-               const double* alpha, const double* diagK, double a_shift, double b_scale, bool jacobi, double* gamma,
+               const double* alpha, const double* dinv, double* gamma,
                double* Tm, double* nrm) {
+  if (mf_eligible(k)) return mf_cg_update(ctx, dtype, N, k, X, P, R, Q, alpha, dinv, gamma,
+                                          Tm, nrm);
+  if (rk_eligible(k)) return rk_cg_update(ctx, dtype, N, k, X, P, R, Q, alpha, dinv, gamma, Tm, nrm);
   if (dtype == BKTS_F64)
-    BKTS_KP_DISPATCH(k, (launch_cg_update_t<double, KP>(ctx, N, k, X, P, R, Q, alpha, diagK, a_shift, b_scale, jacobi,
+    BKTS_KP_DISPATCH(k, (launch_cg_update_t<double, KP>(ctx, N, k, X, P, R, Q, alpha, dinv,
                                                         gamma, Tm, nrm)));
   else
-    BKTS_KP_DISPATCH(k, (launch_cg_update_t<float, KP>(ctx, N, k, X, P, R, Q, alpha, diagK, a_shift, b_scale, jacobi,
+    BKTS_KP_DISPATCH(k, (launch_cg_update_t<float, KP>(ctx, N, k, X, P, R, Q, alpha, dinv,
                                                        gamma, Tm, nrm)));
 }
 
 void cg_pupdate(bkts_ctx ctx, int dtype, int64_t N, int k, void* P, const void* R, const double* beta,
-                const double* diagK, double a_shift, double b_scale, bool jacobi) {
+                const double* dinv) {
+  if (mf_eligible(k)) return mf_cg_pupdate(ctx, dtype, N, k, P, R, beta, dinv);
+  if (rk_eligible(k)) return rk_cg_pupdate(ctx, dtype, N, k, P, R, beta, dinv);
   if (dtype == BKTS_F64)
-    BKTS_KP_DISPATCH(k, (launch_cg_pupdate_t<double, KP>(ctx, N, k, P, R, beta, diagK, a_shift, b_scale, jacobi)));
+    BKTS_KP_DISPATCH(k, (launch_cg_pupdate_t<double, KP>(ctx, N, k, P, R, beta, dinv)));
   else
-    BKTS_KP_DISPATCH(k, (launch_cg_pupdate_t<float, KP>(ctx, N, k, P, R, beta, diagK, a_shift, b_scale, jacobi)));
+    BKTS_KP_DISPATCH(k, (launch_cg_pupdate_t<float, KP>(ctx, N, k, P, R, beta, dinv)));
 }
 
 void block_rmul(bkts_ctx ctx, int dtype, int64_t N, int k, const void* X, int ldx, const double* C, double c0,
                 double c1, void* Y, int ldy) {
+  if (mf_eligible(k) && ldx == k && ldy == k) return mf_rmul(ctx, dtype, N, k, X, C, c0, c1, Y);
+  if (rk_eligible(k) && ldx == k && ldy == k) return rk_rmul(ctx, dtype, N, k, X, C, c0, c1, Y);
   if (dtype == BKTS_F64)
     BKTS_KP_DISPATCH(k, (launch_rmul_t<double, KP>(ctx, N, k, X, ldx, C, c0, c1, Y, ldy)));
   else

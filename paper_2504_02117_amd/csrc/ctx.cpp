@@ -88,17 +88,32 @@ Profiler::~Profiler() {
 ProfScope::ProfScope(bkts_ctx c, int k, double bytes) : ctx(c), kid(k) {
   if (!ctx->prof.enabled) return;
   Profiler& p = ctx->prof;
-  if (p.pending.size() > 8192) p.resolve();
+  if (p.pending.size() > 8192 && p.open == 0) p.resolve();  // only when every end event is recorded
   hipEvent_t a = p.take();
   b = p.take();
   BKTS_HIP(hipEventRecord(a, ctx->stream));
   p.pending.push_back({k, a, b});
   p.acc[k].launches += 1;
   p.acc[k].bytes += bytes;
+  p.open += 1;
 }
 
-ProfScope::~ProfScope() {
-  if (b) (void)hipEventRecord(b, ctx->stream);
+void ProfScope::end() {
+  if (b) {
+    (void)hipEventRecord(b, ctx->stream);
+    ctx->prof.open -= 1;
+    b = nullptr;
+  }
+}
+
+int blocks_per_cu(const void* kernel) {
+  static thread_local std::map<const void*, int> cache;
+  auto it = cache.find(kernel);
+  if (it != cache.end()) return it->second;
+  int n = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kernel, 256, 0) != hipSuccess || n < 1) n = 2;
+  cache[kernel] = n;
+  return n;
 }
 
 }  // namespace bkts

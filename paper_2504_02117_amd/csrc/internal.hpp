@@ -66,6 +66,9 @@ struct Workspace {
 
 inline size_t esize(int dtype) { return dtype == BKTS_F32 ? 4 : 8; }
 
+// Resident workgroups per CU of a kernel with 256-thread workgroups (cached per kernel).
+int blocks_per_cu(const void* kernel);
+
 }  // namespace bkts
 
 namespace bkts {
@@ -82,6 +85,7 @@ struct Profiler {
     double bytes = 0.0;
   };
   bool enabled = false;
+  int open = 0;  // scopes whose end event is not recorded yet (they nest)
   std::vector<hipEvent_t> pool;
   std::vector<Rec> pending;
   Acc acc[BKTS_K_COUNT];
@@ -117,7 +121,12 @@ struct bkts_op_s {
   // SELL-C (sigma = 1): slice s covers rows [s*C, s*C+C), width w_s, entry (row, j) at
   // sell_ptr[s] + j*C + (row - s*C); padding entries have col = row and val = 0.
   int sell_C = 64;
+  int sell_uniform_w = 0;  // > 0: every slice has this width, sell_ptr[s] = s*C*w (no pointer loads needed)
   int64_t nslices = 0, sell_nnz = 0;
+  // Reuse distance of the block operator in rows (a z-plane of a 3-D grid, an x-line of a 2-D
+  // grid); used to schedule one strip of every period per XCD so the +-1 period neighbours stay in
+  // that XCD's L2.  0 = unknown.
+  int64_t strip_period = 0;
   bkts::DevBuf sell_ptr, sell_w, sell_col, sell_val, sell_val32;
 };
 
@@ -142,11 +151,14 @@ struct ProfScope {
   int kid;
   hipEvent_t b = nullptr;
   ProfScope(bkts_ctx c, int k, double bytes);
-  ~ProfScope();
+  void end();  // record the end event now (the scope covers only what was enqueued so far)
+  ~ProfScope() { end(); }
 };
 
 // ---- operator building (op.hip)
 void op_build_sell(bkts_op op);
+// dinv[r] = 1 / (a + b K_rr): inverse diagonal of a I + b K (Jacobi preconditioner)
+void jacobi_inverse(bkts_ctx ctx, const bkts_op_s& op, double a, double b, double* dinv);
 void op_finish(bkts_op op);  // diag, fp32 copies, SELL if requested
 
 // ---- kernels (launchers). All enqueue on ctx->stream.
@@ -157,6 +169,33 @@ void spmm(bkts_ctx ctx, const bkts_op_s& op, int dtype, int k, double cb, const 
 // Reductions produce per-block partials that finalize_partials() folds, in a fixed order.
 int reduce_blocks(bkts_ctx ctx, int64_t N, int k);
 void finalize_partials(bkts_ctx ctx, const double* partials, int nblocks, int nentries, double* out);
+// k x k result from partials laid out as entry (a*KP + b) x nblocks
+void finalize_gram(bkts_ctx ctx, const double* partials, int nblocks, int k, int KP, double* out);
+
+// Row-per-thread block kernels for k in {1, 2, 4} (rowk.hip); contiguous blocks (ld = k).
+bool rk_eligible(int k);
+void rk_spmm_gram(bkts_ctx ctx, const bkts_op_s& op, int dtype, int k, double alpha, const void* P, double beta,
+                  void* Q, double* G);  // Q = alpha P + beta K P, G = P^T Q
+void rk_cg_update(bkts_ctx ctx, int dtype, int64_t N, int k, void* X, const void* P, void* R, const void* Q,
+                  const double* alpha, const double* dinv, double* gamma, double* Tm, double* nrm);
+void rk_cg_pupdate(bkts_ctx ctx, int dtype, int64_t N, int k, void* P, const void* R, const double* beta,
+                   const double* dinv);
+void rk_gram(bkts_ctx ctx, int dtype, int64_t N, int k, const void* X, const void* Y, double* G);
+void rk_rmul(bkts_ctx ctx, int dtype, int64_t N, int k, const void* X, const double* C, double c0, double c1,
+             void* Y);
+
+// MFMA-based block kernels for 8 <= k <= 32 (mfma.hip); contiguous blocks (ld = k) unless noted.
+bool mf_eligible(int k);
+void mf_gram(bkts_ctx ctx, int dtype, int64_t N, int k, const void* X, int ldx, const void* Y, int ldy, double* G);
+void mf_spmm_gram(bkts_ctx ctx, const bkts_op_s& op, int dtype, int k, double alpha, const void* P, double beta,
+                  void* Q, double* G);  // Q = alpha P + beta K P, G = P^T Q
+void mf_cg_update(bkts_ctx ctx, int dtype, int64_t N, int k, void* X, const void* P, void* R, const void* Q,
+                  const double* alpha, const double* dinv, double* gamma,
+                  double* Tm, double* nrm);
+void mf_cg_pupdate(bkts_ctx ctx, int dtype, int64_t N, int k, void* P, const void* R, const double* beta,
+                   const double* dinv);
+void mf_rmul(bkts_ctx ctx, int dtype, int64_t N, int k, const void* X, const double* C, double c0, double c1,
+             void* Y);
 
 // G = X^T Y (device, k x k row-major)
 void gram(bkts_ctx ctx, int dtype, int64_t N, int k, const void* X, int ldx, const void* Y, int ldy,
@@ -169,11 +208,11 @@ void colnorms2(bkts_ctx ctx, int dtype, int64_t N, int k, const void* X, int ldx
 //   X += P*alpha ; R -= Q*alpha ; Z = Dinv R ;  gamma = R^T Z ; T = Q^T Z ; nrm[j] = ||R_j||^2
 // alpha (k x k) read from device memory; outputs gamma, T, nrm in device memory.
 void cg_update(bkts_ctx ctx, int dtype, int64_t N, int k, void* X, const void* P, void* R, const void* Q,
-               const double* alpha_dev, const double* diagK, double a_shift, double b_scale, bool jacobi,
+               const double* alpha_dev, const double* dinv,
                double* gamma, double* T, double* nrm);
 // P = Dinv R + P*beta
 void cg_pupdate(bkts_ctx ctx, int dtype, int64_t N, int k, void* P, const void* R, const double* beta_dev,
-                const double* diagK, double a_shift, double b_scale, bool jacobi);
+                const double* dinv);
 
 // General right-multiply-accumulate: Y = c0*Y + c1*X*C  (C: device k x k, row-major)
 void block_rmul(bkts_ctx ctx, int dtype, int64_t N, int k, const void* X, int ldx, const double* C,

@@ -77,7 +77,12 @@ void block_cg(bkts_ctx ctx, const bkts_op_s& op, int dtype, int k, double a, dou
   void* Q = ctx->ws.get("cg_Q_" + tag, es * N * k);
   Small s = small_bufs(ctx, "cg" + tag, k);
   const double eps = dtype == BKTS_F64 ? 1e-13 : 1e-6;
-  const double* dK = op.diag.as<double>();
+  const double* dK = nullptr;  // inverse Jacobi diagonal of a I + b K, computed once per solve
+  if (jacobi) {
+    double* d = ctx->ws.get<double>("cg_dinv", N);
+    jacobi_inverse(ctx, op, a, b, d);
+    dK = d;
+  }
 
   if (x0_zero) {
     BKTS_HIP(hipMemsetAsync(X, 0, es * N * k, ctx->stream));
@@ -92,31 +97,69 @@ void block_cg(bkts_ctx ctx, const bkts_op_s& op, int dtype, int k, double a, dou
   st.converged = all_converged(nrm0, nrm0, rtol, &st.max_rel) ? 1 : 0;
   if (st.converged) return;
 
-  cg_pupdate(ctx, dtype, N, k, P, R, nullptr, dK, a, b, jacobi);
+  cg_pupdate(ctx, dtype, N, k, P, R, nullptr, dK);
   gram(ctx, dtype, N, k, R, k, P, k, s.gamma);
-  int restarts = 0;
-  for (int it = 1; it <= maxit; ++it) {
-    spmm(ctx, op, dtype, k, 0.0, nullptr, k, a, P, k, b, Q, k);
-    gram(ctx, dtype, N, k, P, k, Q, k, s.G);
-    small_spd_solve(ctx, k, s.G, s.gamma, 1.0, eps, s.alpha, s.ndefl);
-    cg_update(ctx, dtype, N, k, X, P, R, Q, s.alpha, dK, a, b, jacobi, s.gamma, s.T, s.nrm);
-    int nd = 0;
-    read_norms(ctx, s.nrm, k, nrm, s.ndefl, &nd);
+  // Convergence is read back one iteration late: the norms of iteration it are copied to pinned
+  // memory behind an event while iteration it+1 is already enqueued, so the GPU never waits for
+  // the host.  Stopping one iteration after the test passes only adds a valid CG step.
+  double* hbuf = ctx->host_stage(2 * (k + 2));
+  ctx->sync();
+  hipEvent_t ev[2];
+  BKTS_HIP(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
+  BKTS_HIP(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
+  struct EvGuard {
+    hipEvent_t* e;
+    ~EvGuard() { (void)hipEventDestroy(e[0]); (void)hipEventDestroy(e[1]); }
+  } guard{ev};
+  auto check = [&](int it) -> int {  // 1 = converged, -1 = all directions deflated, 0 = continue
+    const int slot = it & 1;
+    BKTS_HIP(hipEventSynchronize(ev[slot]));
+    double* h = hbuf + slot * (k + 2);
+    nrm.assign(h, h + k);
+    const int nd = *reinterpret_cast<int*>(h + k);
     st.iterations = it;
     st.deflations = std::max(st.deflations, nd);
-    if (all_converged(nrm, nrm0, rtol, &st.max_rel)) {
+    if (all_converged(nrm, nrm0, rtol, &st.max_rel)) return 1;
+    return nd >= k ? -1 : 0;
+  };
+  int restarts = 0;
+  for (int it = 1; it <= maxit; ++it) {
+    if (rk_eligible(k)) {
+      rk_spmm_gram(ctx, op, dtype, k, a, P, b, Q, s.G);
+    } else {
+      spmm(ctx, op, dtype, k, 0.0, nullptr, k, a, P, k, b, Q, k);
+      gram(ctx, dtype, N, k, P, k, Q, k, s.G);
+    }
+    small_spd_solve(ctx, k, s.G, s.gamma, 1.0, eps, s.alpha, s.ndefl);
+    cg_update(ctx, dtype, N, k, X, P, R, Q, s.alpha, dK, s.gamma, s.T, s.nrm);
+    {
+      const int slot = it & 1;
+      double* h = hbuf + slot * (k + 2);
+      BKTS_HIP(hipMemcpyAsync(h, s.nrm, sizeof(double) * k, hipMemcpyDeviceToHost, ctx->stream));
+      BKTS_HIP(hipMemcpyAsync(reinterpret_cast<int*>(h + k), s.ndefl, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+      BKTS_HIP(hipEventRecord(ev[slot], ctx->stream));
+    }
+    int state = 0;
+    if (it > 1) state = check(it - 1);
+    if (state == 1) {
+      ctx->sync();  // iteration `it` is in flight; it only improves X
+      st.iterations = it;
       st.converged = 1;
       return;
     }
-    if (nd >= k) {  // every search direction collapsed: restart from the preconditioned residual
+    if (state == -1) {  // every search direction collapsed: restart from the preconditioned residual
       if (++restarts > 3) throw Error{BKTS_EBREAKDOWN, "block CG: search space collapsed repeatedly"};
-      cg_pupdate(ctx, dtype, N, k, P, R, nullptr, dK, a, b, jacobi);
+      cg_pupdate(ctx, dtype, N, k, P, R, nullptr, dK);
       gram(ctx, dtype, N, k, R, k, P, k, s.gamma);
       continue;
     }
     restarts = 0;
     small_spd_solve(ctx, k, s.G, s.T, -1.0, eps, s.beta, nullptr);
-    cg_pupdate(ctx, dtype, N, k, P, R, s.beta, dK, a, b, jacobi);
+    cg_pupdate(ctx, dtype, N, k, P, R, s.beta, dK);
+  }
+  if (check(maxit) == 1) {
+    st.converged = 1;
+    return;
   }
   st.converged = 0;
 }

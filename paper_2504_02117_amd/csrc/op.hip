@@ -256,6 +256,27 @@ void op_build_sell(bkts_op op) {
   hipLaunchKernelGGL(sell_widths, dim3((op->nslices + 255) / 256), dim3(256), 0, ctx->stream, N, C, op->nslices,
                      op->rowptr.as<int32_t>(), wC.as<int64_t>(), op->sell_w.as<int32_t>());
   BKTS_HIP(hipGetLastError());
+  // Uniform slice width when padding every slice to the widest costs at most 5%: the block operator
+  // then derives slice offsets arithmetically instead of loading them.
+  {
+    std::vector<int32_t> hw(op->nslices);
+    BKTS_HIP(hipMemcpyAsync(hw.data(), op->sell_w.p, sizeof(int32_t) * op->nslices, hipMemcpyDeviceToHost, ctx->stream));
+    ctx->sync();
+    int64_t sum = 0;
+    int32_t wmax = 0;
+    for (int32_t w : hw) {
+      sum += w;
+      wmax = w > wmax ? w : wmax;
+    }
+    if (wmax > 0 && (double)wmax * op->nslices <= 1.05 * (double)sum) {
+      op->sell_uniform_w = wmax;
+      std::vector<int64_t> hwc(op->nslices, (int64_t)wmax * C);
+      for (auto& w : hw) w = wmax;
+      BKTS_HIP(hipMemcpyAsync(op->sell_w.p, hw.data(), sizeof(int32_t) * op->nslices, hipMemcpyHostToDevice, ctx->stream));
+      BKTS_HIP(hipMemcpyAsync(wC.p, hwc.data(), sizeof(int64_t) * op->nslices, hipMemcpyHostToDevice, ctx->stream));
+      ctx->sync();
+    }
+  }
   op->sell_nnz = device_exclusive_scan(ctx, wC.as<int64_t>(), op->nslices, op->sell_ptr.as<int64_t>());
   BKTS_REQUIRE(op->sell_nnz < (int64_t)1 << 31, "SELL storage exceeds int32 indexing");
   op->sell_col.alloc(sizeof(int32_t) * op->sell_nnz);
@@ -339,6 +360,7 @@ bkts_op fv_assemble(bkts_ctx ctx, const bkts_grid* grid, const bkts_fv_coeffs* c
     for (int f = 0; f < 2 * grid->dim; ++f)
       if (c->bc_type[f] == BKTS_BC_DIRICHLET && c->bc_value[f] != 0.0) nz = true;
     op->b_nonzero = nz;
+    op->strip_period = grid->dim == 3 ? (int64_t)g.n[0] * g.n[1] : grid->dim == 2 ? g.n[0] : 0;
     op_finish(op);
   } catch (...) {
     delete op;

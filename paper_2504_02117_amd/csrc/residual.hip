@@ -126,6 +126,7 @@ void launch_res(bkts_ctx ctx, const bkts_op_s& op, ResArgs a, double* nrm) {
   else
     hipLaunchKernelGGL((residual_kernel<KP, false>), dim3(ns), dim3(256), 0, ctx->stream, a);
   BKTS_HIP(hipGetLastError());
+  prof.end();
   finalize_partials(ctx, a.partials, (int)ns, a.k, nrm);
 }
 

@@ -1,0 +1,446 @@
+// Block-vector kernels for narrow blocks (k <= 4): one thread owns one whole row of every block.
+// A row of k <= 4 values is one 4..32-byte vector load, the k x k right multiplications are
+// register-only, and each thread keeps its share of the k x k Gram accumulators (FP64) in
+// registers; consecutive threads own consecutive rows, so every access is coalesced and, for the
+// sparse operator in SELL-C layout (C = 64), the matrix stream is contiguous per wave.
+// Workgroups are persistent (sized to the resident capacity of the chip), each walks one
+// contiguous XCD-aware row range, and leaves one partial per Gram entry (fixed-order folding).
+#include "devcommon.hpp"
+#include "internal.hpp"
+
+namespace bkts {
+namespace {
+
+template <typename T, int KP>
+struct Row {
+  T v[KP];
+};
+
+template <typename T, int KP>
+__device__ __forceinline__ Row<T, KP> ld_row(const T* p, int k) {
+  Row<T, KP> r;
+  if constexpr (KP == 4 && sizeof(T) == 4) {
+    const float4 q = *reinterpret_cast<const float4*>(p);
+    r.v[0] = q.x; r.v[1] = q.y; r.v[2] = q.z; r.v[3] = q.w;
+  } else if constexpr (KP == 4 && sizeof(T) == 8) {
+    const double2 a = *reinterpret_cast<const double2*>(p);
+    const double2 b = *reinterpret_cast<const double2*>(p + 2);
+    r.v[0] = a.x; r.v[1] = a.y; r.v[2] = b.x; r.v[3] = b.y;
+  } else if constexpr (KP == 2 && sizeof(T) == 8) {
+    const double2 a = *reinterpret_cast<const double2*>(p);
+    r.v[0] = a.x; r.v[1] = a.y;
+  } else if constexpr (KP == 2 && sizeof(T) == 4) {
+    const float2 a = *reinterpret_cast<const float2*>(p);
+    r.v[0] = a.x; r.v[1] = a.y;
+  } else {
+#pragma unroll
+    for (int j = 0; j < KP; ++j) r.v[j] = p[j];
+  }
+  (void)k;
+  return r;
+}
+
+template <typename T, int KP>
+__device__ __forceinline__ void st_row(T* p, const Row<T, KP>& r) {
+  if constexpr (KP == 4 && sizeof(T) == 4) {
+    *reinterpret_cast<float4*>(p) = float4{r.v[0], r.v[1], r.v[2], r.v[3]};
+  } else if constexpr (KP == 4 && sizeof(T) == 8) {
+    *reinterpret_cast<double2*>(p) = double2{r.v[0], r.v[1]};
+    *reinterpret_cast<double2*>(p + 2) = double2{r.v[2], r.v[3]};
+  } else if constexpr (KP == 2 && sizeof(T) == 8) {
+    *reinterpret_cast<double2*>(p) = double2{r.v[0], r.v[1]};
+  } else if constexpr (KP == 2 && sizeof(T) == 4) {
+    *reinterpret_cast<float2*>(p) = float2{r.v[0], r.v[1]};
+  } else {
+#pragma unroll
+    for (int j = 0; j < KP; ++j) p[j] = r.v[j];
+  }
+}
+
+struct RowRange {
+  int64_t begin, end;
+};
+
+// Contiguous row range of this (XCD-remapped) workgroup, in whole 256-row chunks.
+__device__ __forceinline__ RowRange block_rows(int64_t N) {
+  const int64_t slot = dev::xcd_slot(blockIdx.x, gridDim.x);
+  const int64_t chunks = (N + 255) / 256;
+  const int64_t per = (chunks + gridDim.x - 1) / gridDim.x;
+  RowRange r;
+  r.begin = slot * per * 256;
+  r.end = (slot + 1) * per * 256;
+  if (r.begin > N) r.begin = N;
+  if (r.end > N) r.end = N;
+  return r;
+}
+
+// Fold acc[NA] (identical layout in every thread) over the workgroup in a fixed order and store
+// partials[e * nslots + slot].  Ends with a barrier.
+template <int NA>
+__device__ void fold_block(double (&acc)[NA], double* red, double* partials) {
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1)
+#pragma unroll
+    for (int a = 0; a < NA; ++a) acc[a] += __shfl_xor(acc[a], off);
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  if (l == 0) {
+#pragma unroll
+    for (int a = 0; a < NA; ++a) red[w * NA + a] = acc[a];
+  }
+  __syncthreads();
+  const int64_t slot = dev::xcd_slot(blockIdx.x, gridDim.x);
+  for (int e = threadIdx.x; e < NA; e += dev::kThreads)
+    partials[(int64_t)e * gridDim.x + slot] = ((red[e] + red[NA + e]) + red[2 * NA + e]) + red[3 * NA + e];
+  __syncthreads();
+}
+
+template <typename T>
+struct RkSpmmArgs {
+  int64_t N;
+  int k;
+  const int32_t* rowptr;
+  const int32_t* col;
+  const T* val;
+  const int64_t* sptr;
+  const int32_t* sw;
+  int C;
+  double alpha, beta;
+  const T* P;
+  T* Q;
+  double* partials;  // G = P^T Q, entries a*KP + b
+};
+
+// Q = alpha P + beta K P (arithmetic in T) and G = P^T Q (FP64).
+template <typename T, int KP, bool SELL>
+__global__ __launch_bounds__(256) void rk_spmm_gram_kernel(RkSpmmArgs<T> a) {
+  __shared__ double red[4 * KP * KP];
+  double g[KP * KP];
+#pragma unroll
+  for (int e = 0; e < KP * KP; ++e) g[e] = 0.0;
+  const RowRange rr = block_rows(a.N);
+  for (int64_t r = rr.begin + threadIdx.x; r < rr.end; r += dev::kThreads) {
+    int64_t base, stride, len;
+    if constexpr (SELL) {
+      const int64_t s = r / a.C;
+      base = a.sptr[s] + (r - s * a.C);
+      stride = a.C;
+      len = a.sw[s];
+    } else {
+      base = a.rowptr[r];
+      stride = 1;
+      len = a.rowptr[r + 1] - base;
+    }
+    T acc[KP];
+#pragma unroll
+    for (int j = 0; j < KP; ++j) acc[j] = T(0);
+    constexpr int U = 8;
+    for (int64_t j0 = 0; j0 < len; j0 += U) {
+      T v[U];
+      int32_t ci[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const bool ok = j0 + u < len;
+        const int64_t e = base + (j0 + u) * stride;
+        v[u] = ok ? a.val[e] : T(0);
+        ci[u] = ok ? a.col[e] : (int32_t)r;
+      }
+      Row<T, KP> x[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) x[u] = ld_row<T, KP>(a.P + (int64_t)ci[u] * KP, a.k);
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int j = 0; j < KP; ++j) acc[j] = fma(v[u], x[u].v[j], acc[j]);
+    }
+    const Row<T, KP> p = ld_row<T, KP>(a.P + r * KP, a.k);
+    Row<T, KP> q;
+#pragma unroll
+    for (int j = 0; j < KP; ++j) q.v[j] = (T)a.beta * acc[j] + (T)a.alpha * p.v[j];
+    st_row<T, KP>(a.Q + r * KP, q);
+#pragma unroll
+    for (int i = 0; i < KP; ++i)
+#pragma unroll
+      for (int j = 0; j < KP; ++j) g[i * KP + j] = fma((double)p.v[i], (double)q.v[j], g[i * KP + j]);
+  }
+  fold_block<KP * KP>(g, red, a.partials);
+}
+
+struct RkUpdArgs {
+  int64_t N;
+  void* X;
+  const void* P;
+  void* R;
+  const void* Q;
+  const double* alpha;
+  const double* dinv;  // inverse Jacobi diagonal, or null for no preconditioning
+  double* partials;  // [gamma (KP^2) | T (KP^2) | nrm (KP)] entries
+};
+
+// X += P alpha; R -= Q alpha; Z = D^-1 R; gamma = R^T Z; T = Q^T Z; nrm = diag(R^T R)
+template <typename T, int KP>
+__global__ __launch_bounds__(256) void rk_cg_update_kernel(RkUpdArgs a) {
+  constexpr int NA = 2 * KP * KP + KP;
+  __shared__ double red[4 * NA];
+  double al[KP * KP];
+#pragma unroll
+  for (int e = 0; e < KP * KP; ++e) al[e] = a.alpha[e];
+  double acc[NA];
+#pragma unroll
+  for (int e = 0; e < NA; ++e) acc[e] = 0.0;
+  const T* P = static_cast<const T*>(a.P);
+  const T* Q = static_cast<const T*>(a.Q);
+  T* X = static_cast<T*>(a.X);
+  T* R = static_cast<T*>(a.R);
+  const RowRange rr = block_rows(a.N);
+  for (int64_t r = rr.begin + threadIdx.x; r < rr.end; r += dev::kThreads) {
+    const Row<T, KP> p = ld_row<T, KP>(P + r * KP, KP);
+    const Row<T, KP> q = ld_row<T, KP>(Q + r * KP, KP);
+    Row<T, KP> x = ld_row<T, KP>(X + r * KP, KP);
+    Row<T, KP> rv = ld_row<T, KP>(R + r * KP, KP);
+    const double dv = a.dinv ? a.dinv[r] : 1.0;
+    double z[KP], rn[KP];
+#pragma unroll
+    for (int c = 0; c < KP; ++c) {
+      double xs = (double)x.v[c], rs = (double)rv.v[c];
+#pragma unroll
+      for (int j = 0; j < KP; ++j) {
+        xs = fma((double)p.v[j], al[j * KP + c], xs);
+        rs = fma(-(double)q.v[j], al[j * KP + c], rs);
+      }
+      x.v[c] = (T)xs;
+      rv.v[c] = (T)rs;
+      rn[c] = (double)rv.v[c];
+      z[c] = rn[c] * dv;
+    }
+    st_row<T, KP>(X + r * KP, x);
+    st_row<T, KP>(R + r * KP, rv);
+#pragma unroll
+    for (int i = 0; i < KP; ++i)
+#pragma unroll
+      for (int j = 0; j < KP; ++j) {
+        acc[i * KP + j] = fma(rn[i], z[j], acc[i * KP + j]);
+        acc[KP * KP + i * KP + j] = fma((double)q.v[i], z[j], acc[KP * KP + i * KP + j]);
+      }
+#pragma unroll
+    for (int c = 0; c < KP; ++c) acc[2 * KP * KP + c] = fma(rn[c], rn[c], acc[2 * KP * KP + c]);
+  }
+  fold_block<NA>(acc, red, a.partials);
+}
+
+// P = D^-1 R + P beta   (beta == nullptr: P = D^-1 R)
+template <typename T, int KP>
+__global__ __launch_bounds__(256) void rk_cg_pupdate_kernel(int64_t N, T* __restrict__ P, const T* __restrict__ R,
+                                                            const double* beta, const double* dinv) {
+  double be[KP * KP];
+#pragma unroll
+  for (int e = 0; e < KP * KP; ++e) be[e] = beta ? beta[e] : 0.0;
+  const RowRange rr = block_rows(N);
+  for (int64_t r = rr.begin + threadIdx.x; r < rr.end; r += dev::kThreads) {
+    const Row<T, KP> rv = ld_row<T, KP>(R + r * KP, KP);
+    const double dv = dinv ? dinv[r] : 1.0;
+    Row<T, KP> out;
+    if (beta) {
+      const Row<T, KP> p = ld_row<T, KP>(P + r * KP, KP);
+#pragma unroll
+      for (int c = 0; c < KP; ++c) {
+        double s = (double)rv.v[c] * dv;
+#pragma unroll
+        for (int j = 0; j < KP; ++j) s = fma((double)p.v[j], be[j * KP + c], s);
+        out.v[c] = (T)s;
+      }
+    } else {
+#pragma unroll
+      for (int c = 0; c < KP; ++c) out.v[c] = (T)((double)rv.v[c] * dv);
+    }
+    st_row<T, KP>(P + r * KP, out);
+  }
+}
+
+// G = X^T Y (contiguous blocks)
+template <typename T, int KP>
+__global__ __launch_bounds__(256) void rk_gram_kernel(int64_t N, const T* __restrict__ X, const T* __restrict__ Y,
+                                                      double* partials) {
+  __shared__ double red[4 * KP * KP];
+  double g[KP * KP];
+#pragma unroll
+  for (int e = 0; e < KP * KP; ++e) g[e] = 0.0;
+  const RowRange rr = block_rows(N);
+  for (int64_t r = rr.begin + threadIdx.x; r < rr.end; r += dev::kThreads) {
+    const Row<T, KP> x = ld_row<T, KP>(X + r * KP, KP);
+    const Row<T, KP> y = ld_row<T, KP>(Y + r * KP, KP);
+#pragma unroll
+    for (int i = 0; i < KP; ++i)
+#pragma unroll
+      for (int j = 0; j < KP; ++j) g[i * KP + j] = fma((double)x.v[i], (double)y.v[j], g[i * KP + j]);
+  }
+  fold_block<KP * KP>(g, red, partials);
+}
+
+// Y = c0 Y + c1 X C (contiguous blocks)
+template <typename T, int KP>
+__global__ __launch_bounds__(256) void rk_rmul_kernel(int64_t N, const T* __restrict__ X, const double* Cm, double c0,
+                                                      double c1, T* Y) {
+  double cm[KP * KP];
+#pragma unroll
+  for (int e = 0; e < KP * KP; ++e) cm[e] = c1 * Cm[e];
+  const RowRange rr = block_rows(N);
+  for (int64_t r = rr.begin + threadIdx.x; r < rr.end; r += dev::kThreads) {
+    const Row<T, KP> x = ld_row<T, KP>(X + r * KP, KP);
+    Row<T, KP> y;
+    if (c0 != 0.0) y = ld_row<T, KP>(Y + r * KP, KP);
+#pragma unroll
+    for (int c = 0; c < KP; ++c) {
+      double s = c0 != 0.0 ? c0 * (double)y.v[c] : 0.0;
+#pragma unroll
+      for (int j = 0; j < KP; ++j) s = fma((double)x.v[j], cm[j * KP + c], s);
+      y.v[c] = (T)s;
+    }
+    st_row<T, KP>(Y + r * KP, y);
+  }
+}
+
+// Persistent grid: the resident capacity of the chip for this kernel (occupancy x CUs), capped by
+// the number of 256-row chunks.
+template <typename K>
+int64_t rk_grid(bkts_ctx ctx, K kernel, int64_t N) {
+  int64_t nb = (int64_t)blocks_per_cu(reinterpret_cast<const void*>(kernel)) * ctx->num_cu;
+  const int64_t chunks = (N + 255) / 256;
+  if (nb > chunks) nb = chunks;
+  return nb < 1 ? 1 : nb;
+}
+
+}  // namespace
+
+bool rk_eligible(int k) { return k == 1 || k == 2 || k == 4; }
+
+#define BKTS_RK_DISPATCH(k, CALL)                 \
+  do {                                            \
+    if ((k) == 1) { constexpr int KP = 1; CALL; } \
+    else if ((k) == 2) { constexpr int KP = 2; CALL; } \
+    else { constexpr int KP = 4; CALL; }          \
+  } while (0)
+
+template <typename T, int KP>
+static void rk_spmm_gram_t(bkts_ctx ctx, const bkts_op_s& op, double alpha, const void* P, double beta, void* Q,
+                           double* G) {
+  const bool sell = op.format == BKTS_FMT_SELL;
+  RkSpmmArgs<T> a{};
+  a.N = op.N;
+  a.k = KP;
+  a.rowptr = op.rowptr.as<int32_t>();
+  a.col = sell ? op.sell_col.as<int32_t>() : op.col.as<int32_t>();
+  if constexpr (sizeof(T) == 8)
+    a.val = sell ? op.sell_val.as<double>() : op.val.as<double>();
+  else
+    a.val = sell ? op.sell_val32.as<float>() : op.val32.as<float>();
+  a.sptr = op.sell_ptr.as<int64_t>();
+  a.sw = op.sell_w.as<int32_t>();
+  a.C = op.sell_C;
+  a.alpha = alpha;
+  a.beta = beta;
+  a.P = static_cast<const T*>(P);
+  a.Q = static_cast<T*>(Q);
+  const double sv = sizeof(T);
+  ProfScope prof(ctx, BKTS_K_SPMM, op.nnz * (sv + 4.0) + 4.0 * (op.N + 1) + 2.0 * op.N * KP * sv);
+  int64_t nb;
+  if (sell) {
+    nb = rk_grid(ctx, rk_spmm_gram_kernel<T, KP, true>, op.N);
+    a.partials = ctx->ws.get<double>("rk_sg_part", (size_t)KP * KP * nb);
+    hipLaunchKernelGGL((rk_spmm_gram_kernel<T, KP, true>), dim3(nb), dim3(256), 0, ctx->stream, a);
+  } else {
+    nb = rk_grid(ctx, rk_spmm_gram_kernel<T, KP, false>, op.N);
+    a.partials = ctx->ws.get<double>("rk_sg_part", (size_t)KP * KP * nb);
+    hipLaunchKernelGGL((rk_spmm_gram_kernel<T, KP, false>), dim3(nb), dim3(256), 0, ctx->stream, a);
+  }
+  BKTS_HIP(hipGetLastError());
+  prof.end();
+  finalize_gram(ctx, a.partials, (int)nb, KP, KP, G);
+}
+
+void rk_spmm_gram(bkts_ctx ctx, const bkts_op_s& op, int dtype, int k, double alpha, const void* P, double beta,
+                  void* Q, double* G) {
+  if (dtype == BKTS_F64)
+    BKTS_RK_DISPATCH(k, (rk_spmm_gram_t<double, KP>(ctx, op, alpha, P, beta, Q, G)));
+  else
+    BKTS_RK_DISPATCH(k, (rk_spmm_gram_t<float, KP>(ctx, op, alpha, P, beta, Q, G)));
+}
+
+template <typename T, int KP>
+static void rk_cg_update_t(bkts_ctx ctx, int64_t N, void* X, const void* P, void* R, const void* Q,
+                           const double* alpha, const double* dinv,
+                           double* gamma, double* Tm, double* nrm) {
+  constexpr int NA = 2 * KP * KP + KP;
+  const int64_t nb = rk_grid(ctx, rk_cg_update_kernel<T, KP>, N);
+  double* part = ctx->ws.get<double>("rk_upd_part", (size_t)NA * nb);
+  RkUpdArgs a{N, X, P, R, Q, alpha, dinv, part};
+  ProfScope prof(ctx, BKTS_K_CG_UPDATE, 6.0 * N * KP * sizeof(T) + (dinv ? 8.0 * N : 0.0));
+  hipLaunchKernelGGL((rk_cg_update_kernel<T, KP>), dim3(nb), dim3(256), 0, ctx->stream, a);
+  BKTS_HIP(hipGetLastError());
+  prof.end();
+  finalize_gram(ctx, part, (int)nb, KP, KP, gamma);
+  finalize_gram(ctx, part + (size_t)KP * KP * nb, (int)nb, KP, KP, Tm);
+  finalize_partials(ctx, part + (size_t)2 * KP * KP * nb, (int)nb, KP, nrm);
+}
+
+void rk_cg_update(bkts_ctx ctx, int dtype, int64_t N, int k, void* X, const void* P, void* R, const void* Q,
+                  const double* alpha, const double* dinv, double* gamma, double* Tm, double* nrm) {
+  if (dtype == BKTS_F64)
+    BKTS_RK_DISPATCH(k, (rk_cg_update_t<double, KP>(ctx, N, X, P, R, Q, alpha, dinv, gamma, Tm, nrm)));
+  else
+    BKTS_RK_DISPATCH(k, (rk_cg_update_t<float, KP>(ctx, N, X, P, R, Q, alpha, dinv, gamma, Tm, nrm)));
+}
+
+template <typename T, int KP>
+static void rk_cg_pupdate_t(bkts_ctx ctx, int64_t N, void* P, const void* R, const double* beta, const double* dinv) {
+  const int64_t nb = rk_grid(ctx, rk_cg_pupdate_kernel<T, KP>, N);
+  ProfScope prof(ctx, BKTS_K_CG_PUPDATE, (beta ? 3.0 : 2.0) * N * KP * sizeof(T) + (dinv ? 8.0 * N : 0.0));
+  hipLaunchKernelGGL((rk_cg_pupdate_kernel<T, KP>), dim3(nb), dim3(256), 0, ctx->stream, N, static_cast<T*>(P),
+                     static_cast<const T*>(R), beta, dinv);
+  BKTS_HIP(hipGetLastError());
+}
+
+void rk_cg_pupdate(bkts_ctx ctx, int dtype, int64_t N, int k, void* P, const void* R, const double* beta,
+                   const double* dinv) {
+  if (dtype == BKTS_F64)
+    BKTS_RK_DISPATCH(k, (rk_cg_pupdate_t<double, KP>(ctx, N, P, R, beta, dinv)));
+  else
+    BKTS_RK_DISPATCH(k, (rk_cg_pupdate_t<float, KP>(ctx, N, P, R, beta, dinv)));
+}
+
+template <typename T, int KP>
+static void rk_gram_t(bkts_ctx ctx, int64_t N, const void* X, const void* Y, double* G) {
+  const int64_t nb = rk_grid(ctx, rk_gram_kernel<T, KP>, N);
+  double* part = ctx->ws.get<double>("rk_gram_part", (size_t)KP * KP * nb);
+  ProfScope prof(ctx, BKTS_K_GRAM, 2.0 * N * KP * sizeof(T));
+  hipLaunchKernelGGL((rk_gram_kernel<T, KP>), dim3(nb), dim3(256), 0, ctx->stream, N, static_cast<const T*>(X),
+                     static_cast<const T*>(Y), part);
+  BKTS_HIP(hipGetLastError());
+  prof.end();
+  finalize_gram(ctx, part, (int)nb, KP, KP, G);
+}
+
+void rk_gram(bkts_ctx ctx, int dtype, int64_t N, int k, const void* X, const void* Y, double* G) {
+  if (dtype == BKTS_F64)
+    BKTS_RK_DISPATCH(k, (rk_gram_t<double, KP>(ctx, N, X, Y, G)));
+  else
+    BKTS_RK_DISPATCH(k, (rk_gram_t<float, KP>(ctx, N, X, Y, G)));
+}
+
+template <typename T, int KP>
+static void rk_rmul_t(bkts_ctx ctx, int64_t N, const void* X, const double* C, double c0, double c1, void* Y) {
+  const int64_t nb = rk_grid(ctx, rk_rmul_kernel<T, KP>, N);
+  ProfScope prof(ctx, BKTS_K_OTHER, (c0 != 0.0 ? 3.0 : 2.0) * N * KP * sizeof(T));
+  hipLaunchKernelGGL((rk_rmul_kernel<T, KP>), dim3(nb), dim3(256), 0, ctx->stream, N, static_cast<const T*>(X), C, c0,
+                     c1, static_cast<T*>(Y));
+  BKTS_HIP(hipGetLastError());
+}
+
+void rk_rmul(bkts_ctx ctx, int dtype, int64_t N, int k, const void* X, const double* C, double c0, double c1,
+             void* Y) {
+  if (dtype == BKTS_F64)
+    BKTS_RK_DISPATCH(k, (rk_rmul_t<double, KP>(ctx, N, X, C, c0, c1, Y)));
+  else
+    BKTS_RK_DISPATCH(k, (rk_rmul_t<float, KP>(ctx, N, X, C, c0, c1, Y)));
+}
+
+}  // namespace bkts

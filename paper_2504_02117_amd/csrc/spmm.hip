@@ -68,6 +68,8 @@ struct SpmmArgs {
   const int64_t* sptr;    // SELL
   const int32_t* sw;
   int C;
+  int uw;                 // uniform SELL width (0: load per-slice pointers)
+  int64_t strip;          // > 0: XCD-strip schedule with this many blocks per strip
   T cb, alpha, beta;
   const T* B;
   int ldb;
@@ -85,7 +87,15 @@ __global__ __launch_bounds__(256) void spmm_kernel(SpmmArgs<T> a) {
   constexpr int RPB = dev::kThreads / LPR;
   const int t = threadIdx.x;
   const int c0 = (t % LPR) * VEC;
-  const int64_t tile = dev::xcd_slot(blockIdx.x, gridDim.x);
+  int64_t tile;
+  if (a.strip > 0) {
+    // XCD-strip schedule: XCD x (= dispatch index mod 8) takes strips x, x+8, x+16, ... in order, so
+    // the rows one reuse period away are processed by the same XCD shortly before/after.
+    const int64_t b = blockIdx.x, x = b % dev::kXcd, i = b / dev::kXcd;
+    tile = ((i / a.strip) * dev::kXcd + x) * a.strip + i % a.strip;
+  } else {
+    tile = dev::xcd_slot(blockIdx.x, gridDim.x);
+  }
   const int64_t r = tile * RPB + t / LPR;
   if (r >= a.N) return;
   const bool active = c0 < a.k;
@@ -96,9 +106,14 @@ __global__ __launch_bounds__(256) void spmm_kernel(SpmmArgs<T> a) {
   int64_t base, stride, len;
   if constexpr (SELL) {
     const int64_t s = r / a.C;
-    base = a.sptr[s] + (r - s * a.C);
+    if (a.uw > 0) {
+      base = s * a.C * a.uw + (r - s * a.C);
+      len = a.uw;
+    } else {
+      base = a.sptr[s] + (r - s * a.C);
+      len = a.sw[s];
+    }
     stride = a.C;
-    len = a.sw[s];
   } else {
     base = a.rowptr[r];
     stride = 1;
@@ -111,8 +126,13 @@ __global__ __launch_bounds__(256) void spmm_kernel(SpmmArgs<T> a) {
     for (int u = 0; u < kUnroll; ++u) {
       const bool ok = j0 + u < len;
       const int64_t e = base + (j0 + u) * stride;
-      v[u] = ok ? a.val[e] : T(0);
-      cidx[u] = ok ? a.col[e] : (int32_t)r;
+      if constexpr (SELL) {  // coalesced single-use stream: non-temporal, keeps L2 for the X rows
+        v[u] = ok ? __builtin_nontemporal_load(a.val + e) : T(0);
+        cidx[u] = ok ? __builtin_nontemporal_load(a.col + e) : (int32_t)r;
+      } else {
+        v[u] = ok ? a.val[e] : T(0);
+        cidx[u] = ok ? a.col[e] : (int32_t)r;
+      }
     }
     if (active) {
       Vec<T, VEC> x[kUnroll];
@@ -137,15 +157,92 @@ __global__ __launch_bounds__(256) void spmm_kernel(SpmmArgs<T> a) {
   vstore<T, VEC>(a.Y + r * a.ldy + c0, out);
 }
 
+// Uniform-width SELL (every slice padded to the same width W <= 8, as for stencil operators):
+// slice offsets are arithmetic and every thread carries G rows (RPB apart), so the matrix loads of
+// all G rows are in flight before their dependent X-row loads, which are again all in flight
+// before the first FMA.  Branch-free: padding entries and rows past N read a valid row with a
+// zero weight.
+template <typename T, int KP, int VEC, int G>
+__global__ __launch_bounds__(256) void spmm_ell_kernel(SpmmArgs<T> a) {
+  constexpr int LPR = KP / VEC;
+  constexpr int RPB = dev::kThreads / LPR;
+  const int t = threadIdx.x;
+  const int c0 = (t % LPR) * VEC;
+  int64_t tile;
+  if (a.strip > 0) {
+    const int64_t b = blockIdx.x, x = b % dev::kXcd, i = b / dev::kXcd;
+    tile = ((i / a.strip) * dev::kXcd + x) * a.strip + i % a.strip;
+  } else {
+    tile = dev::xcd_slot(blockIdx.x, gridDim.x);
+  }
+  if (c0 >= a.k) return;
+  const int W = a.uw;
+  const int64_t nslot_rows = ((a.N + a.C - 1) / a.C) * a.C;  // rows covered by slices (padding rows exist)
+  int64_t r[G];
+  T v[G][kUnroll];
+  int32_t ci[G][kUnroll];
+#pragma unroll
+  for (int g = 0; g < G; ++g) {
+    r[g] = (tile * G + g) * RPB + t / LPR;
+    const int64_t rs = r[g] < nslot_rows ? r[g] : nslot_rows - 1;
+    const int64_t s = rs / a.C;
+    const int64_t base = s * a.C * W + (rs - s * a.C);
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      const int64_t e = base + (int64_t)(u < W ? u : W - 1) * a.C;
+      v[g][u] = u < W ? __builtin_nontemporal_load(a.val + e) : T(0);
+      ci[g][u] = __builtin_nontemporal_load(a.col + e);
+    }
+  }
+  Vec<T, VEC> x[G][kUnroll];
+#pragma unroll
+  for (int g = 0; g < G; ++g)
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) x[g][u] = vload<T, VEC>(a.X + (int64_t)ci[g][u] * a.ldx + c0);
+#pragma unroll
+  for (int g = 0; g < G; ++g) {
+    if (r[g] >= a.N) continue;
+    Vec<T, VEC> acc;
+#pragma unroll
+    for (int i = 0; i < VEC; ++i) acc.v[i] = T(0);
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u)
+#pragma unroll
+      for (int i = 0; i < VEC; ++i) acc.v[i] = fma(v[g][u], x[g][u].v[i], acc.v[i]);
+    const Vec<T, VEC> xr = vload<T, VEC>(a.X + r[g] * a.ldx + c0);
+    Vec<T, VEC> out;
+#pragma unroll
+    for (int i = 0; i < VEC; ++i) out.v[i] = a.beta * acc.v[i] + a.alpha * xr.v[i];
+    if (a.B) {
+      const Vec<T, VEC> br = vload<T, VEC>(a.B + r[g] * a.ldb + c0);
+#pragma unroll
+      for (int i = 0; i < VEC; ++i) out.v[i] = fma(a.cb, br.v[i], out.v[i]);
+    }
+    vstore<T, VEC>(a.Y + r[g] * a.ldy + c0, out);
+  }
+}
+
 template <typename T, int KP, int VEC>
 void launch_fmt(bkts_ctx ctx, const bkts_op_s& op, const SpmmArgs<T>& a) {
   constexpr int LPR = KP / VEC;
-  constexpr int RPB = dev::kThreads / LPR;
-  const int64_t nb = (a.N + RPB - 1) / RPB;
-  if (op.format == BKTS_FMT_SELL)
-    hipLaunchKernelGGL((spmm_kernel<T, KP, VEC, true>), dim3(nb), dim3(dev::kThreads), 0, ctx->stream, a);
+  constexpr int G = sizeof(T) == 8 ? 1 : 2;  // rows per thread on the uniform-width path (FP64: registers)
+  const bool ell = op.format == BKTS_FMT_SELL && op.sell_uniform_w > 0 && op.sell_uniform_w <= kUnroll;
+  const int RPB = dev::kThreads / LPR * (ell ? G : 1);
+  const int64_t ntiles = (a.N + RPB - 1) / RPB;
+  int64_t nb = ntiles;
+  SpmmArgs<T> aa = a;
+  aa.strip = 0;
+  if (op.strip_period >= (int64_t)dev::kXcd * RPB) {
+    aa.strip = op.strip_period / dev::kXcd / RPB;
+    const int64_t per = dev::kXcd * aa.strip;
+    nb = (ntiles + per - 1) / per * per;  // whole rounds of 8 strips; blocks past the end exit
+  }
+  if (ell)
+    hipLaunchKernelGGL((spmm_ell_kernel<T, KP, VEC, G>), dim3(nb), dim3(dev::kThreads), 0, ctx->stream, aa);
+  else if (op.format == BKTS_FMT_SELL)
+    hipLaunchKernelGGL((spmm_kernel<T, KP, VEC, true>), dim3(nb), dim3(dev::kThreads), 0, ctx->stream, aa);
   else
-    hipLaunchKernelGGL((spmm_kernel<T, KP, VEC, false>), dim3(nb), dim3(dev::kThreads), 0, ctx->stream, a);
+    hipLaunchKernelGGL((spmm_kernel<T, KP, VEC, false>), dim3(nb), dim3(dev::kThreads), 0, ctx->stream, aa);
 }
 
 template <typename T, int KP>
@@ -179,6 +276,7 @@ void spmm_t(bkts_ctx ctx, const bkts_op_s& op, int k, double cb, const void* B, 
   a.sptr = op.sell_ptr.as<int64_t>();
   a.sw = op.sell_w.as<int32_t>();
   a.C = op.sell_C;
+  a.uw = op.sell_uniform_w;
   a.cb = (T)cb;
   a.alpha = (T)alpha;
   a.beta = (T)beta;

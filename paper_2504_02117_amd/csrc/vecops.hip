@@ -37,6 +37,11 @@ __global__ void axpby_kernel(int64_t n, double a, const double* x, double b, dou
   if (i < n) y[i] = fma(a, x[i], b * y[i]);
 }
 
+__global__ void jacobi_inverse_kernel(int64_t N, const double* diag, double a, double b, double* dinv) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < N) dinv[r] = 1.0 / (a + b * diag[r]);
+}
+
 inline dim3 grid1(int64_t n) { return dim3((unsigned)((n + 255) / 256)); }
 
 }  // namespace
@@ -67,6 +72,14 @@ void lincomb(bkts_ctx ctx, int64_t N, const LinComb& lc, double* out, int ldo) {
   if (N == 0) return;
   ProfScope prof(ctx, BKTS_K_OTHER, 8.0 * N * (lc.m + 1));
   hipLaunchKernelGGL(lincomb_kernel, grid1(N), dim3(256), 0, ctx->stream, N, lc, out, ldo);
+  BKTS_HIP(hipGetLastError());
+}
+
+void jacobi_inverse(bkts_ctx ctx, const bkts_op_s& op, double a, double b, double* dinv) {
+  if (op.N == 0) return;
+  ProfScope prof(ctx, BKTS_K_OTHER, 16.0 * op.N);
+  hipLaunchKernelGGL(jacobi_inverse_kernel, grid1(op.N), dim3(256), 0, ctx->stream, op.N, op.diag.as<double>(), a, b,
+                     dinv);
   BKTS_HIP(hipGetLastError());
 }
 

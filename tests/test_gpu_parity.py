@@ -148,7 +148,7 @@ def test_spmm_strided_and_fv(env, k):
         bkts.bkts_op_destroy(op)
 
 
-@pytest.mark.parametrize("k", [1, 3, 8, 16, 32])
+@pytest.mark.parametrize("k", [1, 3, 8, 12, 16, 20, 32])
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 def test_gram_parity_and_determinism(env, k, dtype):
     torch, bkts, ctx = env
@@ -204,7 +204,7 @@ def test_residual_parity(env, method, name, theta, k):
         bkts.bkts_op_destroy(op)
 
 
-@pytest.mark.parametrize("k", [1, 4, 16])
+@pytest.mark.parametrize("k", [1, 4, 12, 16, 24])
 @pytest.mark.parametrize("precision", [0, 1])
 def test_block_solve_parity(env, k, precision):
     torch, bkts, ctx = env
