@@ -112,6 +112,36 @@ __global__ __launch_bounds__(256) void finalize_kernel(const double* partials, i
   if (threadIdx.x == 0) out[i] = s[0];
 }
 
+struct FoldArgs {
+  FoldSet set[3];
+  int nsets;
+  int k;
+  int64_t nslots;
+};
+
+// One workgroup per output entry of all sets (fixed summation order, as finalize_kernel).
+__global__ __launch_bounds__(256) void finalize_sets_kernel(FoldArgs a) {
+  __shared__ double s[256];
+  int i = blockIdx.x, si = 0;
+  for (; si < a.nsets; ++si) {
+    const int E = a.set[si].vector ? a.k : a.k * a.k;
+    if (i < E) break;
+    i -= E;
+  }
+  const FoldSet& f = a.set[si];
+  const int e = f.vector ? i : (i / a.k) * f.KP + i % a.k;
+  const double* p = f.partials + (int64_t)e * a.nslots;
+  double acc = 0.0;
+  for (int64_t j = threadIdx.x; j < a.nslots; j += 256) acc += p[j];
+  s[threadIdx.x] = acc;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (threadIdx.x < off) s[threadIdx.x] += s[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) f.out[i] = s[0];
+}
+
 // ---------------------------------------------------------------- block CG updates
 
 // Load the k x k matrix M (row-major, device) column c into registers: col[j] = M[j][c].
@@ -377,6 +407,21 @@ void finalize_gram(bkts_ctx ctx, const double* partials, int nblocks, int k, int
   ProfScope prof(ctx, BKTS_K_SMALL, 8.0 * nblocks * k * k);
   hipLaunchKernelGGL(finalize_kernel, dim3(k * k), dim3(256), 0, ctx->stream, partials, (int64_t)nblocks, k, KP, 0,
                      out);
+  BKTS_HIP(hipGetLastError());
+}
+
+void finalize_sets(bkts_ctx ctx, int nblocks, int k, const FoldSet* sets, int nsets) {
+  FoldArgs a{};
+  a.nsets = nsets;
+  a.k = k;
+  a.nslots = nblocks;
+  int total = 0;
+  for (int i = 0; i < nsets; ++i) {
+    a.set[i] = sets[i];
+    total += sets[i].vector ? k : k * k;
+  }
+  ProfScope prof(ctx, BKTS_K_SMALL, 8.0 * nblocks * total);
+  hipLaunchKernelGGL(finalize_sets_kernel, dim3(total), dim3(256), 0, ctx->stream, a);
   BKTS_HIP(hipGetLastError());
 }
 

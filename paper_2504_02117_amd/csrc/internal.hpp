@@ -171,6 +171,14 @@ int reduce_blocks(bkts_ctx ctx, int64_t N, int k);
 void finalize_partials(bkts_ctx ctx, const double* partials, int nblocks, int nentries, double* out);
 // k x k result from partials laid out as entry (a*KP + b) x nblocks
 void finalize_gram(bkts_ctx ctx, const double* partials, int nblocks, int k, int KP, double* out);
+// Up to three folds in one launch: set i is a k x k Gram (vector == 0) or a k-vector (vector == 1).
+struct FoldSet {
+  const double* partials;
+  int KP;
+  int vector;
+  double* out;
+};
+void finalize_sets(bkts_ctx ctx, int nblocks, int k, const FoldSet* sets, int nsets);
 
 // Row-per-thread block kernels for k in {1, 2, 4} (rowk.hip); contiguous blocks (ld = k).
 bool rk_eligible(int k);
@@ -227,6 +235,16 @@ void block_cast_scale(bkts_ctx ctx, int64_t N, int k, int src_t, const void* src
 void residual(bkts_ctx ctx, const bkts_op_s& op, int k, const double* Y, int ldy, const double* A1t,
               const double* A2t, const double* b_rowsum, const double* B0, int ldb0, int nb0,
               const int* b0_to_col, double* R, int ldr, double* nrm);
+
+// Single-workgroup kernels for block GMRES / BiCGStab (small2.hip).
+void small_cholqr(bkts_ctx ctx, int k, const double* G, double eps, double* Rinv, double* R, int* ndefl);
+void small_gemm(bkts_ctx ctx, int k, const double* A, const double* B, double alpha, double* C);
+void small_lu_solve2(bkts_ctx ctx, int k, const double* M, const double* B1, double s1, double* X1, const double* B2,
+                     double s2, double* X2, double eps);
+void small_omega(bkts_ctx ctx, int k, const double* TS, const double* TT, double* out);
+int gmres_max_rows();
+void gmres_lsq(bkts_ctx ctx, int k, int nr, int nc, const double* H, int ldh, const double* S, double eps, double* Y,
+               double* resn);
 
 // k x k dense kernels on one workgroup (small.hip).
 // alpha = G^+ S with truncated Cholesky of the Jacobi-scaled G (threshold `eps`); writes

@@ -35,8 +35,8 @@ Small small_bufs(bkts_ctx ctx, const std::string& tag, int k) {
   s.alpha = base + 3 * kk;
   s.beta = base + 4 * kk;
   s.nrm = base + 5 * kk;
-  s.nrm0 = s.nrm + k;
-  s.ndefl = reinterpret_cast<int*>(s.nrm0 + k);
+  s.ndefl = reinterpret_cast<int*>(s.nrm + k);  // right after the norms: one read-back covers both
+  s.nrm0 = s.nrm + k + 1;
   return s;
 }
 
@@ -135,8 +135,7 @@ void block_cg(bkts_ctx ctx, const bkts_op_s& op, int dtype, int k, double a, dou
     {
       const int slot = it & 1;
       double* h = hbuf + slot * (k + 2);
-      BKTS_HIP(hipMemcpyAsync(h, s.nrm, sizeof(double) * k, hipMemcpyDeviceToHost, ctx->stream));
-      BKTS_HIP(hipMemcpyAsync(reinterpret_cast<int*>(h + k), s.ndefl, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+      BKTS_HIP(hipMemcpyAsync(h, s.nrm, sizeof(double) * (k + 1), hipMemcpyDeviceToHost, ctx->stream));
       BKTS_HIP(hipEventRecord(ev[slot], ctx->stream));
     }
     int state = 0;
@@ -167,8 +166,20 @@ void block_cg(bkts_ctx ctx, const bkts_op_s& op, int dtype, int k, double a, dou
 // One FP32 block CG solve of (a I + b K) V = R64 for FP64 blocks: R64 is scaled per column to
 // unit norm, cast to FP32, solved to `rtol`, and the FP32 correction is scaled back and added to
 // V64 (which need not be zero).
-void f32_correction(bkts_ctx ctx, const bkts_op_s& op, int k, double a, double b, const double* R64,
-                    const double* nrm2, double* V64, bool jacobi, double rtol, int maxit, KrylovStats& st) {
+// Dispatch on the Krylov method of the options.
+static void krylov_run(bkts_ctx ctx, const bkts_op_s& op, const bkts_solve_opts& o, int dtype, int k, double a,
+                       double b, const void* B, void* X, bool x0_zero, double rtol, int maxit, KrylovStats& st) {
+  const bool jacobi = o.precond == BKTS_PREC_JACOBI;
+  switch (o.krylov) {
+    case BKTS_CG: block_cg(ctx, op, dtype, k, a, b, B, X, x0_zero, jacobi, rtol, maxit, st); break;
+    case BKTS_GMRES: block_gmres(ctx, op, dtype, k, a, b, B, X, x0_zero, jacobi, rtol, o.restart, maxit, st); break;
+    case BKTS_BICGSTAB: block_bicgstab(ctx, op, dtype, k, a, b, B, X, x0_zero, jacobi, rtol, maxit, st); break;
+    default: throw Error{BKTS_EINVAL, fmt("unknown Krylov method %d", o.krylov)};
+  }
+}
+
+void f32_correction(bkts_ctx ctx, const bkts_op_s& op, const bkts_solve_opts& o, int k, double a, double b,
+                    const double* R64, const double* nrm2, double* V64, double rtol, int maxit, KrylovStats& st) {
   const int64_t N = op.N;
   double* scale = ctx->ws.get<double>("f32_scale", k);
   std::vector<double> hs(k);
@@ -178,18 +189,16 @@ void f32_correction(bkts_ctx ctx, const bkts_op_s& op, int k, double a, double b
   float* V32 = ctx->ws.get<float>("f32_V", (size_t)N * k);
   block_cast_scale(ctx, N, k, BKTS_F64, R64, k, BKTS_F32, R32, k, scale, true, false);
   BKTS_HIP(hipMemsetAsync(V32, 0, sizeof(float) * N * k, ctx->stream));
-  block_cg(ctx, op, BKTS_F32, k, a, b, R32, V32, true, jacobi, rtol, maxit, st);
+  krylov_run(ctx, op, o, BKTS_F32, k, a, b, R32, V32, true, rtol, maxit, st);
   block_cast_scale(ctx, N, k, BKTS_F32, V32, k, BKTS_F64, V64, k, scale, false, true);
   ctx->sync();  // hs must outlive the async upload
 }
 
 void solve(bkts_ctx ctx, const bkts_op_s& op, double a, double b, int k, const double* B, double* X, bool x0_zero,
            const bkts_solve_opts& o, bool single_f32_pass, KrylovStats& st) {
-  BKTS_REQUIRE(o.krylov == BKTS_CG, "only BKTS_CG is available in this build (got %d)", o.krylov);
-  const bool jacobi = o.precond == BKTS_PREC_JACOBI;
   const int maxit = o.maxit > 0 ? o.maxit : 10000;
   if (o.precision == BKTS_PRECISION_F64) {
-    block_cg(ctx, op, BKTS_F64, k, a, b, B, X, x0_zero, jacobi, o.rtol, maxit, st);
+    krylov_run(ctx, op, o, BKTS_F64, k, a, b, B, X, x0_zero, o.rtol, maxit, st);
     st.refinements = 0;
     return;
   }
@@ -205,7 +214,7 @@ void solve(bkts_ctx ctx, const bkts_op_s& op, double a, double b, int k, const d
     std::vector<double> nb;
     read_norms(ctx, n2, k, nb);
     st = KrylovStats{};
-    f32_correction(ctx, op, k, a, b, B, nb.data(), X, jacobi, std::max(o.rtol, inner), maxit, st);
+    f32_correction(ctx, op, o, k, a, b, B, nb.data(), X, std::max(o.rtol, inner), maxit, st);
     st.refinements = 1;
     return;
   }
@@ -228,7 +237,7 @@ void solve(bkts_ctx ctx, const bkts_op_s& op, double a, double b, int k, const d
       return;
     }
     KrylovStats in;
-    f32_correction(ctx, op, k, a, b, R64, nrm.data(), X, jacobi, inner, maxit - total, in);
+    f32_correction(ctx, op, o, k, a, b, R64, nrm.data(), X, inner, maxit - total, in);
     total += in.iterations;
     st.iterations = total;
     st.refinements = ref + 1;

@@ -18,6 +18,11 @@ struct KrylovStats {
 void block_cg(bkts_ctx ctx, const bkts_op_s& op, int dtype, int k, double a, double b, const void* B, void* X,
               bool x0_zero, bool jacobi, double rtol, int maxit, KrylovStats& st);
 
+void block_gmres(bkts_ctx ctx, const bkts_op_s& op, int dtype, int k, double a, double b, const void* B, void* X,
+                 bool x0_zero, bool jacobi, double rtol, int restart, int maxit, KrylovStats& st);
+void block_bicgstab(bkts_ctx ctx, const bkts_op_s& op, int dtype, int k, double a, double b, const void* B, void* X,
+                    bool x0_zero, bool jacobi, double rtol, int maxit, KrylovStats& st);
+
 // FP64 solve entry: F64 block CG, or FP32 block CG inside FP64 iterative refinement.  With
 // single_f32_pass the refinement loop makes one FP32 correction (the caller's own outer loop
 // computes FP64 residuals).

@@ -1,0 +1,234 @@
+// Block GMRES(m) and block BiCGStab for nonsymmetric (a I + b K) X = B (convection, Newton
+// Jacobians), right-preconditioned with Jacobi: A D^-1 U = B, X = D^-1 U.  All coefficient
+// matrices (block Hessenberg, CholQR factors, k x k systems) stay on the device in FP64; the host
+// reads only the k residual norms per iteration.
+//
+// Block GMRES: block Arnoldi with classical block Gram-Schmidt applied twice and CholQR2 for the
+// new block (directions that CholQR finds dependent are dropped), then the small least-squares
+// problem min || [S;0] - Hbar Y || by Householder QR on one workgroup.
+// Block BiCGStab (Guennouni-Jbilou-Sadok form): k x k alpha and beta from the shadow Gram
+// Rt^T V, a scalar omega = <T,S>_F / <T,T>_F.
+#include <algorithm>
+#include <cmath>
+
+#include "krylov.hpp"
+#include "vecops.hpp"
+
+namespace bkts {
+
+namespace {
+
+void read_host(bkts_ctx ctx, const double* dev, int n, std::vector<double>& out) {
+  double* h = ctx->host_stage(n);
+  BKTS_HIP(hipMemcpyAsync(h, dev, sizeof(double) * n, hipMemcpyDeviceToHost, ctx->stream));
+  ctx->sync();
+  out.assign(h, h + n);
+}
+
+bool converged(const std::vector<double>& nrm2, const std::vector<double>& nrm0, double rtol, double* maxrel,
+               bool squared) {
+  bool ok = true;
+  double mr = 0.0;
+  for (size_t j = 0; j < nrm2.size(); ++j) {
+    const double r = squared ? std::sqrt(nrm2[j]) : nrm2[j];
+    const double r0 = std::sqrt(nrm0[j]);
+    if (!std::isfinite(r)) throw Error{BKTS_EBREAKDOWN, fmt("non-finite residual in column %zu", j)};
+    const double rel = r0 > 0.0 ? r / r0 : (r > 0.0 ? INFINITY : 0.0);
+    mr = std::max(mr, rel);
+    if (!(r <= rtol * r0)) ok = false;
+  }
+  if (maxrel) *maxrel = mr;
+  return ok;
+}
+
+}  // namespace
+
+void block_gmres(bkts_ctx ctx, const bkts_op_s& op, int dtype, int k, double a, double b, const void* B, void* X,
+                 bool x0_zero, bool jacobi, double rtol, int restart, int maxit, KrylovStats& st) {
+  const int64_t N = op.N;
+  const size_t es = esize(dtype);
+  const size_t blk = es * N * k;
+  int m = std::max(1, std::min(restart > 0 ? restart : 30, gmres_max_rows() / k - 1));
+  BKTS_REQUIRE(m >= 1, "block GMRES needs k <= %d", gmres_max_rows() / 2);
+  const std::string tag = dtype == BKTS_F64 ? "d" : "s";
+  char* V = static_cast<char*>(ctx->ws.get("gm_V_" + tag, blk * (m + 1)));
+  void* W = ctx->ws.get("gm_W_" + tag, blk);
+  void* Z = ctx->ws.get("gm_Z_" + tag, blk);
+  const int ldh = (m + 1) * k;
+  const size_t kk = (size_t)k * k;
+  double* sm = ctx->ws.get<double>("gm_small", (size_t)ldh * m * k + 8 * kk + (size_t)m * k * k + 4 * k + 2);
+  double* H = sm;
+  double* S = H + (size_t)ldh * m * k;
+  double* Gm = S + kk;
+  double* Ri1 = Gm + kk;
+  double* R1 = Ri1 + kk;
+  double* Ri2 = R1 + kk;
+  double* R2 = Ri2 + kk;
+  double* Hb = R2 + kk;
+  double* Tm = Hb + kk;
+  double* Y = Tm + kk;
+  double* resn = Y + (size_t)m * k * k;
+  double* nrmd = resn + k;
+  const double eps = dtype == BKTS_F64 ? 1e-13 : 1e-6;
+  const double lsq_eps = dtype == BKTS_F64 ? 1e-14 : 1e-7;
+  const double* dinv = nullptr;
+  if (jacobi) {
+    double* d = ctx->ws.get<double>("gm_dinv", N);
+    jacobi_inverse(ctx, op, a, b, d);
+    dinv = d;
+  }
+  auto Vb = [&](int j) { return static_cast<void*>(V + blk * j); };
+  auto residual_into_W = [&]() {
+    if (x0_zero) {
+      BKTS_HIP(hipMemsetAsync(X, 0, blk, ctx->stream));
+      BKTS_HIP(hipMemcpyAsync(W, B, blk, hipMemcpyDeviceToDevice, ctx->stream));
+      x0_zero = false;
+    } else {
+      spmm(ctx, op, dtype, k, 1.0, B, k, -a, X, k, -b, W, k);
+    }
+  };
+  // CholQR2 of the block `src` into `dst` (may alias): dst R = src, R = R2 R1 stored in Rout.
+  auto cholqr2 = [&](void* src, void* dst, double* Rout) {
+    gram(ctx, dtype, N, k, src, k, src, k, Gm);
+    small_cholqr(ctx, k, Gm, eps, Ri1, R1, nullptr);
+    block_rmul(ctx, dtype, N, k, src, k, Ri1, 0.0, 1.0, dst, k);
+    gram(ctx, dtype, N, k, dst, k, dst, k, Gm);
+    small_cholqr(ctx, k, Gm, eps, Ri2, R2, nullptr);
+    block_rmul(ctx, dtype, N, k, dst, k, Ri2, 0.0, 1.0, dst, k);
+    small_gemm(ctx, k, R2, R1, 1.0, Rout);
+  };
+
+  residual_into_W();
+  colnorms2(ctx, dtype, N, k, W, k, nrmd);
+  std::vector<double> nrm0, res;
+  read_host(ctx, nrmd, k, nrm0);
+  st = KrylovStats{};
+  if (converged(nrm0, nrm0, rtol, &st.max_rel, true)) {
+    st.converged = 1;
+    return;
+  }
+  int total = 0;
+  while (total < maxit) {
+    cholqr2(W, Vb(0), S);  // R0 = V0 S
+    BKTS_HIP(hipMemsetAsync(H, 0, sizeof(double) * ldh * m * k, ctx->stream));
+    int jdone = 0;
+    bool conv = false;
+    for (int j = 0; j < m && total < maxit; ++j) {
+      scale_rows(ctx, dtype, N, k, dinv, Vb(j), Z);
+      spmm(ctx, op, dtype, k, 0.0, nullptr, k, a, Z, k, b, W, k);  // W = A D^-1 V_j
+      for (int pass = 0; pass < 2; ++pass) {                         // block CGS2
+        for (int i = 0; i <= j; ++i) {
+          gram(ctx, dtype, N, k, Vb(i), k, W, k, Hb);
+          hblock(ctx, k, Hb, H, ldh, i * k, j * k, pass > 0);
+          block_rmul(ctx, dtype, N, k, Vb(i), k, Hb, 1.0, -1.0, W, k);
+        }
+      }
+      cholqr2(W, Vb(j + 1), Tm);  // W = V_{j+1} H_{j+1,j}
+      hblock(ctx, k, Tm, H, ldh, (j + 1) * k, j * k, false);
+      gmres_lsq(ctx, k, (j + 2) * k, (j + 1) * k, H, ldh, S, lsq_eps, Y, resn);
+      read_host(ctx, resn, k, res);
+      ++total;
+      jdone = j + 1;
+      st.iterations = total;
+      if (converged(res, nrm0, rtol, &st.max_rel, false)) {
+        conv = true;
+        break;
+      }
+    }
+    // X += D^-1 sum_i V_i Y_i
+    BKTS_HIP(hipMemsetAsync(W, 0, blk, ctx->stream));
+    for (int i = 0; i < jdone; ++i) block_rmul(ctx, dtype, N, k, Vb(i), k, Y + (size_t)i * kk, 1.0, 1.0, W, k);
+    scale_rows(ctx, dtype, N, k, dinv, W, Z);
+    block_cast_scale(ctx, N, k, dtype, Z, k, dtype, X, k, nullptr, false, true);  // X += Z
+    // true residual for the next cycle (and the final check)
+    residual_into_W();
+    colnorms2(ctx, dtype, N, k, W, k, nrmd);
+    std::vector<double> nr;
+    read_host(ctx, nrmd, k, nr);
+    if (converged(nr, nrm0, rtol, &st.max_rel, true)) {
+      st.converged = 1;
+      return;
+    }
+    (void)conv;
+  }
+  st.converged = 0;
+}
+
+void block_bicgstab(bkts_ctx ctx, const bkts_op_s& op, int dtype, int k, double a, double b, const void* B, void* X,
+                    bool x0_zero, bool jacobi, double rtol, int maxit, KrylovStats& st) {
+  const int64_t N = op.N;
+  const size_t es = esize(dtype);
+  const size_t blk = es * N * k;
+  const std::string tag = dtype == BKTS_F64 ? "d" : "s";
+  void* R = ctx->ws.get("bs_R_" + tag, blk);
+  void* Rt = ctx->ws.get("bs_Rt_" + tag, blk);
+  void* P = ctx->ws.get("bs_P_" + tag, blk);
+  void* Pn = ctx->ws.get("bs_Pn_" + tag, blk);
+  void* Ph = ctx->ws.get("bs_Ph_" + tag, blk);
+  void* V = ctx->ws.get("bs_V_" + tag, blk);
+  void* Sb = ctx->ws.get("bs_S_" + tag, blk);
+  void* Sh = ctx->ws.get("bs_Sh_" + tag, blk);
+  void* T = ctx->ws.get("bs_T_" + tag, blk);
+  const size_t kk = (size_t)k * k;
+  double* sm = ctx->ws.get<double>("bs_small", 8 * kk + 2 * k + 2);
+  double *M1 = sm, *Mr = M1 + kk, *M3 = Mr + kk, *al = M3 + kk, *be = al + kk, *TS = be + kk, *TT = TS + kk;
+  double* om = TT + kk;
+  double* nrmd = om + 2;
+  const double lu_eps = dtype == BKTS_F64 ? 1e-14 : 1e-7;
+  const double* dinv = nullptr;
+  if (jacobi) {
+    double* d = ctx->ws.get<double>("bs_dinv", N);
+    jacobi_inverse(ctx, op, a, b, d);
+    dinv = d;
+  }
+  if (x0_zero) {
+    BKTS_HIP(hipMemsetAsync(X, 0, blk, ctx->stream));
+    BKTS_HIP(hipMemcpyAsync(R, B, blk, hipMemcpyDeviceToDevice, ctx->stream));
+  } else {
+    spmm(ctx, op, dtype, k, 1.0, B, k, -a, X, k, -b, R, k);
+  }
+  BKTS_HIP(hipMemcpyAsync(Rt, R, blk, hipMemcpyDeviceToDevice, ctx->stream));
+  BKTS_HIP(hipMemcpyAsync(P, R, blk, hipMemcpyDeviceToDevice, ctx->stream));
+  colnorms2(ctx, dtype, N, k, R, k, nrmd);
+  std::vector<double> nrm0, nrm;
+  read_host(ctx, nrmd, k, nrm0);
+  st = KrylovStats{};
+  if (converged(nrm0, nrm0, rtol, &st.max_rel, true)) {
+    st.converged = 1;
+    return;
+  }
+  for (int it = 1; it <= maxit; ++it) {
+    scale_rows(ctx, dtype, N, k, dinv, P, Ph);
+    spmm(ctx, op, dtype, k, 0.0, nullptr, k, a, Ph, k, b, V, k);  // V = A D^-1 P
+    gram(ctx, dtype, N, k, Rt, k, V, k, M1);
+    gram(ctx, dtype, N, k, Rt, k, R, k, Mr);
+    small_lu_solve2(ctx, k, M1, Mr, 1.0, al, nullptr, 0.0, nullptr, lu_eps);  // alpha = M1^-1 Rt^T R
+    BKTS_HIP(hipMemcpyAsync(Sb, R, blk, hipMemcpyDeviceToDevice, ctx->stream));
+    block_rmul(ctx, dtype, N, k, V, k, al, 1.0, -1.0, Sb, k);  // S = R - V alpha
+    scale_rows(ctx, dtype, N, k, dinv, Sb, Sh);
+    spmm(ctx, op, dtype, k, 0.0, nullptr, k, a, Sh, k, b, T, k);  // T = A D^-1 S
+    gram(ctx, dtype, N, k, T, k, Sb, k, TS);
+    gram(ctx, dtype, N, k, T, k, T, k, TT);
+    small_omega(ctx, k, TS, TT, om);
+    block_rmul(ctx, dtype, N, k, Ph, k, al, 1.0, 1.0, X, k);  // X += D^-1 P alpha
+    axpy_ds(ctx, dtype, N * k, om, 1.0, Sh, X);               //    + omega D^-1 S
+    BKTS_HIP(hipMemcpyAsync(R, Sb, blk, hipMemcpyDeviceToDevice, ctx->stream));
+    axpy_ds(ctx, dtype, N * k, om, -1.0, T, R);  // R = S - omega T
+    colnorms2(ctx, dtype, N, k, R, k, nrmd);
+    read_host(ctx, nrmd, k, nrm);
+    st.iterations = it;
+    if (converged(nrm, nrm0, rtol, &st.max_rel, true)) {
+      st.converged = 1;
+      return;
+    }
+    gram(ctx, dtype, N, k, Rt, k, T, k, M3);
+    small_lu_solve2(ctx, k, M1, M3, -1.0, be, nullptr, 0.0, nullptr, lu_eps);  // beta = -M1^-1 Rt^T T
+    axpy_ds(ctx, dtype, N * k, om, -1.0, V, P);                               // P - omega V
+    BKTS_HIP(hipMemcpyAsync(Pn, R, blk, hipMemcpyDeviceToDevice, ctx->stream));
+    block_rmul(ctx, dtype, N, k, P, k, be, 1.0, 1.0, Pn, k);  // P = R + (P - omega V) beta
+    std::swap(P, Pn);
+  }
+  st.converged = 0;
+}
+
+}  // namespace bkts

@@ -576,9 +576,8 @@ void mf_cg_update(bkts_ctx ctx, int dtype, int64_t N, int k, void* X, const void
                                             a));
   BKTS_HIP(hipGetLastError());
   prof.end();
-  finalize_gram(ctx, pg, (int)nb, k, KP, gamma);
-  finalize_gram(ctx, pt, (int)nb, k, KP, Tm);
-  finalize_partials(ctx, pn, (int)nb, k, nrm);
+  const FoldSet sets[3] = {{pg, KP, 0, gamma}, {pt, KP, 0, Tm}, {pn, KP, 1, nrm}};
+  finalize_sets(ctx, (int)nb, k, sets, 3);
 }
 
 void mf_cg_pupdate(bkts_ctx ctx, int dtype, int64_t N, int k, void* P, const void* R, const double* beta,

@@ -377,9 +377,9 @@ static void rk_cg_update_t(bkts_ctx ctx, int64_t N, void* X, const void* P, void
   hipLaunchKernelGGL((rk_cg_update_kernel<T, KP>), dim3(nb), dim3(256), 0, ctx->stream, a);
   BKTS_HIP(hipGetLastError());
   prof.end();
-  finalize_gram(ctx, part, (int)nb, KP, KP, gamma);
-  finalize_gram(ctx, part + (size_t)KP * KP * nb, (int)nb, KP, KP, Tm);
-  finalize_partials(ctx, part + (size_t)2 * KP * KP * nb, (int)nb, KP, nrm);
+  const FoldSet sets[3] = {{part, KP, 0, gamma}, {part + (size_t)KP * KP * nb, KP, 0, Tm},
+                           {part + (size_t)2 * KP * KP * nb, KP, 1, nrm}};
+  finalize_sets(ctx, (int)nb, KP, sets, 3);
 }
 
 void rk_cg_update(bkts_ctx ctx, int dtype, int64_t N, int k, void* X, const void* P, void* R, const void* Q,

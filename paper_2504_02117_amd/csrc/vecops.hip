@@ -42,6 +42,30 @@ __global__ void jacobi_inverse_kernel(int64_t N, const double* diag, double a, d
   if (r < N) dinv[r] = 1.0 / (a + b * diag[r]);
 }
 
+template <typename T>
+__global__ void scale_rows_kernel(int64_t N, int k, const double* dinv, const T* X, T* Y) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N * k) return;
+  const double d = dinv ? dinv[i / k] : 1.0;
+  Y[i] = (T)(d * (double)X[i]);
+}
+
+// Y += sign * s[0] * X with the scalar read from device memory
+template <typename T>
+__global__ void axpy_ds_kernel(int64_t n, const double* s, double sign, const T* X, T* Y) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) Y[i] = (T)fma(sign * s[0], (double)X[i], (double)Y[i]);
+}
+
+// H[(r0 + i) + (c0 + j) * ldh] (+)= M[i*k + j]  (store a k x k block into a column-major array)
+__global__ void hblock_kernel(int k, const double* M, double* H, int ldh, int r0, int c0, int accumulate) {
+  for (int e = threadIdx.x; e < k * k; e += blockDim.x) {
+    const int i = e / k, j = e % k;
+    double* h = H + (int64_t)(c0 + j) * ldh + (r0 + i);
+    *h = accumulate ? *h + M[e] : M[e];
+  }
+}
+
 inline dim3 grid1(int64_t n) { return dim3((unsigned)((n + 255) / 256)); }
 
 }  // namespace
@@ -80,6 +104,35 @@ void jacobi_inverse(bkts_ctx ctx, const bkts_op_s& op, double a, double b, doubl
   ProfScope prof(ctx, BKTS_K_OTHER, 16.0 * op.N);
   hipLaunchKernelGGL(jacobi_inverse_kernel, grid1(op.N), dim3(256), 0, ctx->stream, op.N, op.diag.as<double>(), a, b,
                      dinv);
+  BKTS_HIP(hipGetLastError());
+}
+
+void scale_rows(bkts_ctx ctx, int dtype, int64_t N, int k, const double* dinv, const void* X, void* Y) {
+  if (N * k == 0) return;
+  ProfScope prof(ctx, BKTS_K_OTHER, 2.0 * N * k * esize(dtype) + 8.0 * N);
+  if (dtype == BKTS_F64)
+    hipLaunchKernelGGL(scale_rows_kernel<double>, grid1(N * k), dim3(256), 0, ctx->stream, N, k, dinv,
+                       static_cast<const double*>(X), static_cast<double*>(Y));
+  else
+    hipLaunchKernelGGL(scale_rows_kernel<float>, grid1(N * k), dim3(256), 0, ctx->stream, N, k, dinv,
+                       static_cast<const float*>(X), static_cast<float*>(Y));
+  BKTS_HIP(hipGetLastError());
+}
+
+void axpy_ds(bkts_ctx ctx, int dtype, int64_t n, const double* s, double sign, const void* X, void* Y) {
+  if (n == 0) return;
+  ProfScope prof(ctx, BKTS_K_OTHER, 3.0 * n * esize(dtype));
+  if (dtype == BKTS_F64)
+    hipLaunchKernelGGL(axpy_ds_kernel<double>, grid1(n), dim3(256), 0, ctx->stream, n, s, sign,
+                       static_cast<const double*>(X), static_cast<double*>(Y));
+  else
+    hipLaunchKernelGGL(axpy_ds_kernel<float>, grid1(n), dim3(256), 0, ctx->stream, n, s, sign,
+                       static_cast<const float*>(X), static_cast<float*>(Y));
+  BKTS_HIP(hipGetLastError());
+}
+
+void hblock(bkts_ctx ctx, int k, const double* M, double* H, int ldh, int r0, int c0, bool accumulate) {
+  hipLaunchKernelGGL(hblock_kernel, dim3(1), dim3(256), 0, ctx->stream, k, M, H, ldh, r0, c0, (int)accumulate);
   BKTS_HIP(hipGetLastError());
 }
 

@@ -25,5 +25,11 @@ void copy_col(bkts_ctx ctx, int64_t N, double* Y, int ld, int src, int dst);
 void extract_col(bkts_ctx ctx, int64_t N, const double* Y, int ld, int c, double* out);
 void lincomb(bkts_ctx ctx, int64_t N, const LinComb& lc, double* out, int ldo);
 void axpby(bkts_ctx ctx, int64_t n, double a, const double* x, double b, double* y);  // y = a x + b y
+// Y = diag(dinv) X for N x k contiguous blocks of type dtype (dinv null: copy)
+void scale_rows(bkts_ctx ctx, int dtype, int64_t N, int k, const double* dinv, const void* X, void* Y);
+// Y += sign * s[0] * X (n elements; s is a device scalar)
+void axpy_ds(bkts_ctx ctx, int dtype, int64_t n, const double* s, double sign, const void* X, void* Y);
+// store (or add) a k x k row-major block into a column-major matrix at (r0, c0)
+void hblock(bkts_ctx ctx, int k, const double* M, double* H, int ldh, int r0, int c0, bool accumulate);
 
 }  // namespace bkts

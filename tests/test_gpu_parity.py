@@ -308,3 +308,59 @@ def test_full_size_128cubed_sampled(env):
         bkts.bkts_tc_destroy(tc)
     finally:
         bkts.bkts_op_destroy(op)
+
+
+@pytest.mark.parametrize("krylov", [1, 2])
+@pytest.mark.parametrize("k", [1, 3, 4, 8, 16])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_nonsymmetric_block_solve(env, krylov, k, precision):
+    """Block GMRES (1) and block BiCGStab (2) on an upwind convection-diffusion operator."""
+    torch, bkts, ctx = env
+    n = (12, 11, 10)
+    say(f"nonsymmetric solve krylov={krylov} k={k} precision={precision}")
+    op, K, _ = fv_op(env, n, inputs.lognormal_field(n, 0.0, 1.0, 2.0, 4), velocity=(40.0, -25.0, 10.0))
+    try:
+        N = K.shape[0]
+        B = inputs.random_block(N, k, 50)
+        if k >= 4:
+            B[:, 1] = B[:, 0]
+        alpha, beta = 200.0, 1.0
+        Xd = torch.zeros((N, k), dtype=torch.float64, device="cuda")
+        opts = bkts.solve_opts(krylov=krylov, precision=precision, rtol=1e-11, inner_rtol=1e-4, restart=30)
+        info = bkts.bkts_block_solve(ctx, op, alpha, beta, dev(torch, B), Xd, opts)
+        ref = blockops.block_solve(K, alpha, beta, B)
+        got = Xd.cpu().numpy()
+        err = np.linalg.norm(got - ref, axis=0) / np.linalg.norm(ref, axis=0)
+        say(f"  iterations={info.iterations} refinements={info.refinements} err={err.max():.2e}")
+        assert info.converged == 1 and err.max() < 1e-8
+    finally:
+        bkts.bkts_op_destroy(op)
+
+
+@pytest.mark.parametrize("krylov,method,name", [(1, 0, "ie"), (2, 0, "ie"), (1, 2, "sdirk2"), (2, 1, "theta")])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_advance_convection_diffusion(env, krylov, method, name, precision):
+    """32^2 convection-diffusion (D = 1, v = (1, 0.5)), k = 4 stage columns, the sequential oracle as truth."""
+    torch, bkts, ctx = env
+    n = (32, 32)
+    tau, steps, k = 1e-2, 8, 4
+    say(f"advance conv-diff krylov={krylov} {name} precision={precision}")
+    op, K, b = fv_op(env, n, None, velocity=(1.0, 0.5, 0.0))
+    tc = bkts.bkts_tc_create(ctx, method, k, tau, theta=0.5)
+    try:
+        N = K.shape[0]
+        y0 = inputs.sin_product(n)
+        yd = dev(torch, y0)
+        hist = torch.zeros((steps, N), dtype=torch.float64, device="cuda")
+        inner = bkts.solve_opts(krylov=krylov, precision=precision, rtol=1e-10 if precision == 0 else 1e-4,
+                                inner_rtol=1e-4, restart=15)
+        info = bkts.bkts_advance(ctx, op, tc, yd, steps, inner=inner, outer_rtol=1e-12, max_outer=100, y_hist=hist)
+        ys, _ = stepping.dirk_linear(K, b, y0, tau, name, steps, theta=0.5)
+        got = hist.cpu().numpy()
+        for s in range(steps):
+            rel = np.linalg.norm(got[s] - ys[s + 1]) / np.linalg.norm(ys[s + 1])
+            assert rel < 1e-8, (s, rel)
+        say(f"  outer={info.outer_iterations} krylov={info.krylov_iterations}")
+    finally:
+        bkts.bkts_tc_destroy(tc)
+        bkts.bkts_op_destroy(op)
