@@ -248,12 +248,48 @@ bkts_status bkts_advance(bkts_ctx ctx, bkts_op op, bkts_tc tc, double* y, int n_
                          const bkts_solve_opts* inner, double outer_rtol, int max_outer,
                          double* y_hist, bkts_step_cb cb, void* user, bkts_run_info* info);
 
+/* ---------------------------------------------- nonlinear problems (Sec. 2.2) */
+
+/* M y' + f(y) = 0 with f(u) = -div_h(D(u) grad_h u) - r(u) on a cell-centred FV grid,
+ * D(u) = sum_i dcoef[i] u^i and r(u) = sum_i rcoef[i] u^i (cubic at most).  Interior faces use
+ * the arithmetic mean (D(u_P) + D(u_Q))/2; a Dirichlet face with value g uses (D(u_P) + D(g))/2
+ * over half a cell; Neumann faces carry no flux. */
+typedef struct bkts_nl_coeffs {
+  double dcoef[4];
+  double rcoef[4];
+  int bc_type[6];      /* face 2*axis + side: BKTS_BC_DIRICHLET or BKTS_BC_NEUMANN */
+  double bc_value[6];
+} bkts_nl_coeffs;
+
+bkts_status bkts_nlop_create(bkts_ctx ctx, const bkts_grid* grid, const bkts_nl_coeffs* coeffs, bkts_nlop* out);
+void bkts_nlop_destroy(bkts_nlop nl);
+/* F[:, j] = f(Y[:, j]) for an N x k device block (row-major, leading dimensions ldy, ldf). */
+bkts_status bkts_nl_eval(bkts_ctx ctx, bkts_nlop nl, int k, const double* Y, int ldy, double* F, int ldf);
+/* Assemble J = alpha I + beta Df(u) on the stencil sparsity (u: device, N doubles) and return it as an
+ * operator handle owned by `nl` (valid until the next call or bkts_nlop_destroy; do not destroy it). */
+bkts_status bkts_nl_jacobian(bkts_ctx ctx, bkts_nlop nl, const double* u, double alpha, double beta, bkts_op* J);
+/* The nonlinear all-at-once residual R = Y A1^T + F(Y) A2^T - B0 (Sec. 2.2) for the window
+ * matrices of `phase`; arguments as bkts_residual. */
+bkts_status bkts_nl_residual(bkts_ctx ctx, bkts_nlop nl, bkts_tc tc, int phase, const double* Y, int ldy,
+                             const double* B0, int ldb0, int nb0, double* R, int ldr, double* col_norms2);
+/* One Newton iteration of Algorithm 1 on the window Y (device N x k, ld = k): R = R(Y);
+ * J = I/tau + a_kk Df(Y_0); solve J V = R to opts->rtol per column with the block Krylov method of
+ * `opts` (BKTS_PRECISION_F32_REFINE: FP32 inner solves inside FP64 iterative refinement, as
+ * bkts_block_solve); Y <- Y - V.
+ * col_norms2 (HOST, k, may be NULL) receives ||R_j||^2 of the residual BEFORE the update.
+ * Synchronises. */
+bkts_status bkts_newton_step(bkts_ctx ctx, bkts_nlop nl, bkts_tc tc, int phase, const double* B0, int ldb0, int nb0,
+                             double* Y, double* col_norms2, const bkts_solve_opts* opts, bkts_solve_info* info);
+
 /* A persistent Algorithm 1 pipeline: the window of k stages and the history
  * of the front step survive between calls, so consecutive
  * bkts_stepper_advance calls continue one time integration (bkts_advance is
  * create + advance + destroy).  y0: device, N doubles, copied at creation. */
 typedef struct bkts_stepper_s* bkts_stepper;
 bkts_status bkts_stepper_create(bkts_ctx ctx, bkts_op op, bkts_tc tc, const double* y0, bkts_stepper* out);
+/* The nonlinear pipeline (Algorithm 1 with Newton: the Jacobian at the front column is rebuilt
+ * every outer iteration and used for all columns). */
+bkts_status bkts_nl_stepper_create(bkts_ctx ctx, bkts_nlop nl, bkts_tc tc, const double* y0, bkts_stepper* out);
 bkts_status bkts_stepper_advance(bkts_stepper st, int n_steps, const bkts_solve_opts* inner, double outer_rtol,
                                  int max_outer, double* y_hist, bkts_step_cb cb, void* user, bkts_run_info* info);
 /* Copy the last accepted y^n to the device array y (N doubles; may be NULL) and

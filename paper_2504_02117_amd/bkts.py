@@ -70,6 +70,11 @@ class bkts_run_info(C.Structure):
                 ("refinements", C.c_int), ("final_front_rel_residual", C.c_double)]
 
 
+class bkts_nl_coeffs(C.Structure):
+    _fields_ = [("dcoef", C.c_double * 4), ("rcoef", C.c_double * 4), ("bc_type", C.c_int * 6),
+                ("bc_value", C.c_double * 6)]
+
+
 bkts_step_cb = C.CFUNCTYPE(None, C.c_int, C.c_double, C.c_void_p, C.c_void_p)
 
 _P, _I, _D, _I64 = C.c_void_p, C.c_int, C.c_double, C.c_int64
@@ -101,6 +106,14 @@ _SIGS = {
                                   C.POINTER(bkts_run_info)]),
     "bkts_stepper_state": (_I, [_P, _P, C.POINTER(_I64)]),
     "bkts_stepper_destroy": (None, [_P]),
+    "bkts_nlop_create": (_I, [_P, C.POINTER(bkts_grid), C.POINTER(bkts_nl_coeffs), C.POINTER(_P)]),
+    "bkts_nlop_destroy": (None, [_P]),
+    "bkts_nl_eval": (_I, [_P, _P, _I, _P, _I, _P, _I]),
+    "bkts_nl_jacobian": (_I, [_P, _P, _P, _D, _D, C.POINTER(_P)]),
+    "bkts_nl_residual": (_I, [_P, _P, _P, _I, _P, _I, _P, _I, _I, _P, _I, _P]),
+    "bkts_newton_step": (_I, [_P, _P, _P, _I, _P, _I, _I, _P, _P, C.POINTER(bkts_solve_opts),
+                              C.POINTER(bkts_solve_info)]),
+    "bkts_nl_stepper_create": (_I, [_P, _P, _P, _P, C.POINTER(_P)]),
 }
 
 EXPORTED = tuple(_SIGS)
@@ -332,3 +345,75 @@ def bkts_stepper_state(st, y=None):
 
 def bkts_stepper_destroy(st):
     _lib.bkts_stepper_destroy(st)
+
+
+def _grid(n):
+    g = bkts_grid()
+    g.dim = len(n)
+    for d in range(3):
+        g.n[d] = int(n[d]) if d < len(n) else 1
+    return g
+
+
+def bkts_nlop_create(ctx, n, dcoef=(1.0, 0.0, 0.0, 0.0), rcoef=(0.0, 0.0, 0.0, 0.0), bc_type=None, bc_value=None):
+    """Nonlinear FV operator f(u) = -div(D(u) grad u) - r(u); ``dcoef``/``rcoef`` are the
+    polynomial coefficients of D and r (constant term first); faces default to zero flux."""
+    c = bkts_nl_coeffs()
+    for i in range(4):
+        c.dcoef[i] = float(dcoef[i]) if i < len(dcoef) else 0.0
+        c.rcoef[i] = float(rcoef[i]) if i < len(rcoef) else 0.0
+    for f in range(6):
+        c.bc_type[f] = BKTS_BC_NEUMANN if bc_type is None else int(bc_type[f])
+        c.bc_value[f] = 0.0 if bc_value is None else float(bc_value[f])
+    g = _grid(n)
+    out = C.c_void_p()
+    _check(_lib.bkts_nlop_create(ctx, C.byref(g), C.byref(c), C.byref(out)))
+    return out.value
+
+
+def bkts_nlop_destroy(nl):
+    _lib.bkts_nlop_destroy(nl)
+
+
+def bkts_nl_eval(ctx, nl, Y, F):
+    """F[:, j] = f(Y[:, j]) for (N, k) float64 device tensors."""
+    k = Y.shape[1]
+    _check(_lib.bkts_nl_eval(ctx, nl, k, _ptr(Y), Y.stride(0), _ptr(F), F.stride(0)))
+
+
+def bkts_nl_jacobian(ctx, nl, u, alpha, beta):
+    """Operator handle of alpha I + beta Df(u), owned by ``nl``."""
+    out = C.c_void_p()
+    _check(_lib.bkts_nl_jacobian(ctx, nl, _ptr(u), alpha, beta, C.byref(out)))
+    return out.value
+
+
+def bkts_nl_residual(ctx, nl, tc, Y, R, B0=None, phase=0, want_norms=True):
+    import numpy as np
+    k = Y.shape[1]
+    norms = np.empty(k) if want_norms else None
+    nb0 = 0 if B0 is None else B0.shape[1]
+    ldb0 = 0 if B0 is None else B0.stride(0)
+    _check(_lib.bkts_nl_residual(ctx, nl, tc, phase, _ptr(Y), Y.stride(0), _ptr(B0), ldb0, nb0, _ptr(R),
+                                 R.stride(0), _ptr(norms)))
+    return norms
+
+
+def bkts_newton_step(ctx, nl, tc, Y, B0=None, phase=0, opts=None):
+    """One Newton iteration on the window Y (N, k) in place; returns (pre-update column norms^2, info)."""
+    import numpy as np
+    opts = opts or solve_opts(rtol=1e-2)
+    k = Y.shape[1]
+    norms = np.empty(k)
+    info = bkts_solve_info()
+    nb0 = 0 if B0 is None else B0.shape[1]
+    ldb0 = 0 if B0 is None else B0.stride(0)
+    _check(_lib.bkts_newton_step(ctx, nl, tc, phase, _ptr(B0), ldb0, nb0, _ptr(Y), _ptr(norms), C.byref(opts),
+                                 C.byref(info)))
+    return norms, info
+
+
+def bkts_nl_stepper_create(ctx, nl, tc, y0):
+    out = C.c_void_p()
+    _check(_lib.bkts_nl_stepper_create(ctx, nl, tc, _ptr(y0), C.byref(out)))
+    return out.value

@@ -62,7 +62,8 @@ static void read_vec(bkts_ctx ctx, const double* dev, int n, std::vector<double>
 
 }  // namespace bkts
 
-bkts_stepper_s::bkts_stepper_s(bkts_ctx c, bkts_op o, bkts_tc t, const double* y0) : ctx(c), op(o), tc(t) {
+bkts_stepper_s::bkts_stepper_s(bkts_ctx c, bkts_op o, bkts_tc t, const double* y0, bkts_nlop n)
+    : ctx(c), op(o), tc(t), nl(n) {
   using namespace bkts;
   const int64_t N = op->N;
   const int k = tc->k;
@@ -84,7 +85,8 @@ bkts_stepper_s::bkts_stepper_s(bkts_ctx c, bkts_op o, bkts_tc t, const double* y
   ctx->sync();
 }
 
-void bkts_stepper_s::eval_f(const double* x, int ldx, double* out, int ldo) {  // f(x) = K x - b
+void bkts_stepper_s::eval_f(const double* x, int ldx, double* out, int ldo) {  // f(x) = K x - b, or nonlinear f
+  if (nl) return bkts::nl_eval(ctx, *nl, 1, x, ldx, out, ldo);
   const double* bsrc = op->b_nonzero ? op->b.as<double>() : nullptr;
   bkts::spmm(ctx, *op, BKTS_F64, 1, -1.0, bsrc, 1, 0.0, x, ldx, 1.0, out, ldo);
 }
@@ -96,7 +98,7 @@ bkts_status bkts_stepper_s::advance(int n_steps, const bkts_solve_opts& inner, d
   const int k = tc->k;
   const int mi = tc->m_impl;
   const double tau = tc->tau;
-  const double* bsrc = op->b_nonzero ? op->b.as<double>() : nullptr;
+  const double* bsrc = (!nl && op->b_nonzero) ? op->b.as<double>() : nullptr;
   double* Yp = Y.as<double>();
   double* Rp = R.as<double>();
   double* Vp = V.as<double>();
@@ -133,7 +135,14 @@ bkts_status bkts_stepper_s::advance(int n_steps, const bkts_solve_opts& inner, d
     const double beta = tc->A2[phase][0];
     bool front_ok = false;
     for (int it = 0;; ++it) {
-      window_residual(ctx, *op, *tc, phase, off, Yp, k, B0p, mi, nb0, Rp, k, nrmp, mats.as<double>());
+      if (nl) {
+        int cols[8];
+        for (int i = 0; i < nb0 && i < 8; ++i) cols[i] = (off + i) % k;
+        double* m = mats.as<double>();
+        nl_residual(ctx, *nl, k, Yp, k, m, m + k * k, B0p, mi, nb0, cols, Rp, k, nrmp);
+      } else {
+        window_residual(ctx, *op, *tc, phase, off, Yp, k, B0p, mi, nb0, Rp, k, nrmp, mats.as<double>());
+      }
       read_vec(ctx, nrmp, k + 1, hn);
       const double rhs0 = std::sqrt(hn[k]);
       const double front = std::sqrt(hn[off]);
@@ -145,7 +154,12 @@ bkts_status bkts_stepper_s::advance(int n_steps, const bkts_solve_opts& inner, d
       }
       if (it >= max_outer) break;
       KrylovStats ks;
-      solve(ctx, *op, 1.0 / tau, beta, k, Rp, Vp, true, inner, true, ks);
+      if (nl) {  // Newton: J = I/tau + a_kk Df(front column), used for every column of the window
+        nl_jacobian(ctx, *nl, Yp + off, k, 1.0 / tau, beta);
+        solve(ctx, *nl->jac, 0.0, 1.0, k, Rp, Vp, true, inner, true, ks);
+      } else {
+        solve(ctx, *op, 1.0 / tau, beta, k, Rp, Vp, true, inner, true, ks);
+      }
       ri.krylov_iterations += ks.iterations;
       ri.refinements += ks.refinements;
       ++ri.outer_iterations;

@@ -6,13 +6,14 @@
 // Persistent pipeline state of Algorithm 1: the window and the history of the front step.
 struct bkts_stepper_s {
   bkts_ctx ctx;
-  bkts_op op;
+  bkts_op op;          // linear operator K, or the Jacobian storage of `nl`
   bkts_tc tc;
+  bkts_nlop nl = nullptr;  // nonlinear problem (Newton form) or null
   bkts::DevBuf Y, R, V, B0, fst, yprev, fyn, tmp, nrm, mats;
   int off = 0;       // physical column of logical column 0
   int phase = 0;     // implicit-stage index of the front column within its step
   long accepted = 0; // accepted steps since creation
-  bkts_stepper_s(bkts_ctx c, bkts_op o, bkts_tc t, const double* y0);
+  bkts_stepper_s(bkts_ctx c, bkts_op o, bkts_tc t, const double* y0, bkts_nlop n = nullptr);
   void eval_f(const double* x, int ldx, double* out, int ldo);
   bkts_status advance(int n_steps, const bkts_solve_opts& inner, double outer_rtol, int max_outer, double* y_hist,
                       bkts_step_cb cb, void* user, bkts_run_info* info);

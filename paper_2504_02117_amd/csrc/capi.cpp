@@ -6,11 +6,13 @@
 #include "internal.hpp"
 #include "krylov.hpp"
 #include "timecoupling.hpp"
+#include "vecops.hpp"
 
 namespace bkts {
 bkts_op fv_assemble(bkts_ctx ctx, const bkts_grid* grid, const bkts_fv_coeffs* c, int format);
 bkts_op op_from_csr(bkts_ctx ctx, int64_t N, int64_t nnz, const int32_t* rowptr, const int32_t* col,
                     const double* val, int format);
+void upload_window(bkts_ctx ctx, const bkts_tc_s& tc, int phase, int off, double* A1p, double* A2p, double* rsp);
 const char* last_error();
 }  // namespace bkts
 
@@ -341,6 +343,122 @@ bkts_status bkts_stepper_state(bkts_stepper st, double* y, int64_t* accepted) {
     BKTS_HIP(hipMemcpyAsync(y, st->yprev.p, sizeof(double) * st->op->N, hipMemcpyDeviceToDevice, st->ctx->stream));
   st->ctx->sync();
   if (accepted) *accepted = st->accepted;
+  BKTS_API_END
+}
+
+bkts_status bkts_nlop_create(bkts_ctx ctx, const bkts_grid* grid, const bkts_nl_coeffs* coeffs, bkts_nlop* out) {
+  BKTS_API_BEGIN
+  check_ctx(ctx);
+  BKTS_REQUIRE(out, "out must not be NULL");
+  *out = nullptr;
+  set_device(ctx);
+  *out = bkts::nlop_create(ctx, grid, coeffs);
+  BKTS_API_END
+}
+
+void bkts_nlop_destroy(bkts_nlop nl) {
+  if (!nl) return;
+  (void)hipSetDevice(nl->ctx->device);
+  (void)hipStreamSynchronize(nl->ctx->stream);
+  delete nl;
+}
+
+bkts_status bkts_nl_eval(bkts_ctx ctx, bkts_nlop nl, int k, const double* Y, int ldy, double* F, int ldf) {
+  BKTS_API_BEGIN
+  check_ctx(ctx);
+  BKTS_REQUIRE(nl && nl->ctx == ctx, "nl must belong to ctx");
+  check_k(k);
+  check_block(Y, k, ldy, "Y");
+  check_block(F, k, ldf, "F");
+  BKTS_REQUIRE(Y != F, "Y and F must not alias");
+  set_device(ctx);
+  bkts::nl_eval(ctx, *nl, k, Y, ldy, F, ldf);
+  BKTS_API_END
+}
+
+bkts_status bkts_nl_jacobian(bkts_ctx ctx, bkts_nlop nl, const double* u, double alpha, double beta, bkts_op* J) {
+  BKTS_API_BEGIN
+  check_ctx(ctx);
+  BKTS_REQUIRE(nl && nl->ctx == ctx, "nl must belong to ctx");
+  BKTS_REQUIRE(u && J, "u and J must not be NULL");
+  set_device(ctx);
+  bkts::nl_jacobian(ctx, *nl, u, 1, alpha, beta);
+  *J = nl->jac;
+  BKTS_API_END
+}
+
+bkts_status bkts_nl_residual(bkts_ctx ctx, bkts_nlop nl, bkts_tc tc, int phase, const double* Y, int ldy,
+                             const double* B0, int ldb0, int nb0, double* R, int ldr, double* col_norms2) {
+  BKTS_API_BEGIN
+  check_ctx(ctx);
+  BKTS_REQUIRE(nl && nl->ctx == ctx && tc, "nl must belong to ctx and tc must not be NULL");
+  BKTS_REQUIRE(phase >= 0 && phase < tc->m_impl, "phase must be in 0..%d", tc->m_impl - 1);
+  const int k = tc->k;
+  check_block(Y, k, ldy, "Y");
+  check_block(R, k, ldr, "R");
+  BKTS_REQUIRE(Y != R, "Y and R must not alias");
+  BKTS_REQUIRE(nb0 >= 0 && nb0 <= k && nb0 <= 8, "nb0 must be in 0..min(k, 8)");
+  if (B0 && nb0 > 0) BKTS_REQUIRE(ldb0 >= nb0, "ldb0 < nb0");
+  set_device(ctx);
+  double* mats = ctx->ws.get<double>("api_nl_mats", 2 * k * k + k);
+  double* nrm = ctx->ws.get<double>("api_res_nrm", k);
+  bkts::upload_window(ctx, *tc, phase, 0, mats, mats + k * k, mats + 2 * k * k);
+  int cols[8];
+  for (int i = 0; i < 8; ++i) cols[i] = i;
+  bkts::nl_residual(ctx, *nl, k, Y, ldy, mats, mats + k * k, B0, ldb0, B0 ? nb0 : 0, cols, R, ldr, nrm);
+  if (col_norms2) {
+    BKTS_HIP(hipMemcpyAsync(col_norms2, nrm, sizeof(double) * k, hipMemcpyDeviceToHost, ctx->stream));
+    ctx->sync();
+  }
+  BKTS_API_END
+}
+
+bkts_status bkts_newton_step(bkts_ctx ctx, bkts_nlop nl, bkts_tc tc, int phase, const double* B0, int ldb0, int nb0,
+                             double* Y, double* col_norms2, const bkts_solve_opts* opts, bkts_solve_info* info) {
+  BKTS_API_BEGIN
+  check_ctx(ctx);
+  BKTS_REQUIRE(nl && nl->ctx == ctx && tc, "nl must belong to ctx and tc must not be NULL");
+  BKTS_REQUIRE(phase >= 0 && phase < tc->m_impl, "phase must be in 0..%d", tc->m_impl - 1);
+  BKTS_REQUIRE(Y && opts, "Y and opts must not be NULL");
+  BKTS_REQUIRE(opts->rtol > 0.0 && opts->rtol < 1.0, "rtol must be in (0, 1)");
+  const int k = tc->k;
+  BKTS_REQUIRE(nb0 >= 0 && nb0 <= k && nb0 <= 8, "nb0 must be in 0..min(k, 8)");
+  if (B0 && nb0 > 0) BKTS_REQUIRE(ldb0 >= nb0, "ldb0 < nb0");
+  set_device(ctx);
+  const int64_t N = nl->N;
+  double* mats = ctx->ws.get<double>("api_nl_mats", 2 * k * k + k);
+  double* nrm = ctx->ws.get<double>("api_res_nrm", k);
+  double* R = ctx->ws.get<double>("api_newton_R", (size_t)N * k);
+  double* V = ctx->ws.get<double>("api_newton_V", (size_t)N * k);
+  bkts::upload_window(ctx, *tc, phase, 0, mats, mats + k * k, mats + 2 * k * k);
+  int cols[8];
+  for (int i = 0; i < 8; ++i) cols[i] = i;
+  bkts::nl_residual(ctx, *nl, k, Y, k, mats, mats + k * k, B0, ldb0, B0 ? nb0 : 0, cols, R, k, nrm);
+  if (col_norms2) BKTS_HIP(hipMemcpyAsync(col_norms2, nrm, sizeof(double) * k, hipMemcpyDeviceToHost, ctx->stream));
+  bkts::nl_jacobian(ctx, *nl, Y, k, 1.0 / tc->tau, tc->A2[phase][0]);
+  bkts::KrylovStats st;
+  bkts::solve(ctx, *nl->jac, 0.0, 1.0, k, R, V, true, *opts, false, st);
+  bkts::axpby(ctx, N * k, -1.0, V, 1.0, Y);
+  ctx->sync();
+  if (info) {
+    info->iterations = st.iterations;
+    info->refinements = st.refinements;
+    info->converged = st.converged;
+    info->deflations = st.deflations;
+    info->max_rel_residual = st.max_rel;
+  }
+  BKTS_API_END
+}
+
+bkts_status bkts_nl_stepper_create(bkts_ctx ctx, bkts_nlop nl, bkts_tc tc, const double* y0, bkts_stepper* out) {
+  BKTS_API_BEGIN
+  check_ctx(ctx);
+  BKTS_REQUIRE(out, "out must not be NULL");
+  *out = nullptr;
+  BKTS_REQUIRE(nl && nl->ctx == ctx && tc, "nl must belong to ctx and tc must not be NULL");
+  BKTS_REQUIRE(y0, "y0 must not be NULL");
+  set_device(ctx);
+  *out = new bkts_stepper_s(ctx, nl->jac, tc, y0, nl);
   BKTS_API_END
 }
 

@@ -130,6 +130,28 @@ struct bkts_op_s {
   bkts::DevBuf sell_ptr, sell_w, sell_col, sell_val, sell_val32;
 };
 
+// Nonlinear FV operator (nonlinear.hip).
+namespace bkts {
+
+struct NlDev {
+  int dim;
+  int n[3];
+  double w[3];  // 1 / h_d^2
+  double dc[4], rc[4];
+  int bc_type[6];
+  double bc_val[6];
+};
+
+}  // namespace bkts
+
+struct bkts_nlop_s {
+  bkts_ctx ctx = nullptr;
+  bkts::NlDev nd{};
+  int64_t N = 0;
+  bkts_op jac = nullptr;  // stencil sparsity; values overwritten by bkts_nl_jacobian
+  ~bkts_nlop_s() { delete jac; }
+};
+
 struct bkts_tc_s {
   bkts_ctx ctx = nullptr;
   int k = 1;
@@ -160,6 +182,18 @@ void op_build_sell(bkts_op op);
 // dinv[r] = 1 / (a + b K_rr): inverse diagonal of a I + b K (Jacobi preconditioner)
 void jacobi_inverse(bkts_ctx ctx, const bkts_op_s& op, double a, double b, double* dinv);
 void op_finish(bkts_op op);  // diag, fp32 copies, SELL if requested
+void op_refresh_values(bkts_op op);  // after CSR values changed: diag, SELL values, FP32 copies
+
+// ---- nonlinear operator (nonlinear.hip)
+bkts_nlop nlop_create(bkts_ctx ctx, const bkts_grid* grid, const bkts_nl_coeffs* c);
+// F[:, j] = f(Y[:, j]) for j < k
+void nl_eval(bkts_ctx ctx, const bkts_nlop_s& nl, int k, const double* Y, int ldy, double* F, int ldf);
+// nl.jac values = alpha I + beta Df(u) (u: column with stride ldu)
+void nl_jacobian(bkts_ctx ctx, bkts_nlop_s& nl, const double* u, int ldu, double alpha, double beta);
+// R = Y A1^T + F(Y) A2^T - B0 with column norms (A1, A2 device, row-major, physical order)
+void nl_residual(bkts_ctx ctx, const bkts_nlop_s& nl, int k, const double* Y, int ldy, const double* A1,
+                 const double* A2, const double* B0, int ldb0, int nb0, const int* b0_to_col, double* R, int ldr,
+                 double* nrm);
 
 // ---- kernels (launchers). All enqueue on ctx->stream.
 // Y = cb*B + alpha*X + beta*K X   (B may be null). dtype F64/F32 for X, Y, B.

@@ -1,0 +1,281 @@
+// Nonlinear FV operator for the Newton form of Algorithm 1 (Sec. 2.2): the column-wise
+// f(u) = -div_h(D(u) grad_h u) - r(u) with polynomial D and r on the structured grid, its exact
+// Jacobian assembled on the fixed stencil sparsity, and the fused window residual
+// R = Y A1^T + F(Y) A2^T - B0 (F_j = f(Y_j)).
+//
+// Fluxes (cell-centred, per unit volume): interior face P|Q along axis d contributes
+// (D(u_P) + D(u_Q))/2 * (u_P - u_Q) / h_d^2; a Dirichlet face with value g contributes
+// (D(u_P) + D(g))/2 * 2 (u_P - g) / h_d^2; zero-flux faces contribute nothing.
+#include "devcommon.hpp"
+#include "internal.hpp"
+
+namespace bkts {
+namespace {
+
+using dev::TileGeom;
+
+__device__ __forceinline__ double poly(const double (&c)[4], double u) { return ((c[3] * u + c[2]) * u + c[1]) * u + c[0]; }
+__device__ __forceinline__ double dpoly(const double (&c)[4], double u) { return (3.0 * c[3] * u + 2.0 * c[2]) * u + c[1]; }
+
+__device__ __forceinline__ void coords(const NlDev& g, int64_t r, int (&i)[3]) {
+  int64_t q = r;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    if (d < g.dim) {
+      i[d] = (int)(q % g.n[d]);
+      q /= g.n[d];
+    } else {
+      i[d] = 0;
+    }
+  }
+}
+
+__device__ __forceinline__ int64_t stride_of(const NlDev& g, int d) {
+  int64_t s = 1;
+  for (int e = 0; e < d; ++e) s *= g.n[e];
+  return s;
+}
+
+// f(u)_r for the column of u with stride ld (u[q * ld])
+__device__ double f_at(const NlDev& g, const double* u, int ld, int64_t r) {
+  int i[3];
+  coords(g, r, i);
+  const double up = u[r * ld];
+  const double Dp = poly(g.dc, up);
+  double f = -poly(g.rc, up);
+  for (int d = 0; d < g.dim; ++d) {
+    const int64_t st = stride_of(g, d);
+    for (int side = 0; side < 2; ++side) {
+      const bool interior = side == 0 ? i[d] > 0 : i[d] < g.n[d] - 1;
+      if (interior) {
+        const double uq = u[(side == 0 ? r - st : r + st) * ld];
+        f += 0.5 * (Dp + poly(g.dc, uq)) * (up - uq) * g.w[d];
+      } else if (g.bc_type[2 * d + side] == BKTS_BC_DIRICHLET) {
+        const double gv = g.bc_val[2 * d + side];
+        f += 0.5 * (Dp + poly(g.dc, gv)) * (up - gv) * 2.0 * g.w[d];
+      }
+    }
+  }
+  return f;
+}
+
+__global__ void nl_eval_kernel(NlDev g, int64_t N, int k, const double* Y, int ldy, double* F, int ldf) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N * k) return;
+  const int64_t r = i / k;
+  const int c = (int)(i % k);
+  F[r * ldf + c] = f_at(g, Y + c, ldy, r);
+}
+
+// Row r of J = alpha I + beta Df(u), written in the stencil's sorted column order
+// (z-, y-, x-, diagonal, x+, y+, z+) starting at val[rowptr[r]].
+__global__ void nl_jac_kernel(NlDev g, int64_t N, const double* u, int ldu, double alpha, double beta,
+                              const int32_t* rowptr, double* val) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= N) return;
+  int i[3];
+  coords(g, r, i);
+  const double up = u[r * ldu];
+  const double Dp = poly(g.dc, up), dDp = dpoly(g.dc, up);
+  double diag = -dpoly(g.rc, up);
+  double off[6];
+  bool has[6];
+  for (int f = 0; f < 6; ++f) has[f] = false;
+  for (int d = 0; d < g.dim; ++d) {
+    const int64_t st = stride_of(g, d);
+    for (int side = 0; side < 2; ++side) {
+      const int f = 2 * d + side;
+      const bool interior = side == 0 ? i[d] > 0 : i[d] < g.n[d] - 1;
+      if (interior) {
+        const double uq = u[(side == 0 ? r - st : r + st) * ldu];
+        const double Dq = poly(g.dc, uq), dDq = dpoly(g.dc, uq);
+        const double Df = 0.5 * (Dp + Dq), diff = up - uq;
+        diag += (Df + 0.5 * dDp * diff) * g.w[d];
+        off[f] = (-Df + 0.5 * dDq * diff) * g.w[d];
+        has[f] = true;
+      } else if (g.bc_type[f] == BKTS_BC_DIRICHLET) {
+        const double gv = g.bc_val[f];
+        diag += (0.5 * (Dp + poly(g.dc, gv)) + 0.5 * dDp * (up - gv)) * 2.0 * g.w[d];
+      }
+    }
+  }
+  int64_t p = rowptr[r];
+  for (int d = g.dim - 1; d >= 0; --d)
+    if (has[2 * d]) val[p++] = beta * off[2 * d];
+  val[p++] = alpha + beta * diag;
+  for (int d = 0; d < g.dim; ++d)
+    if (has[2 * d + 1]) val[p++] = beta * off[2 * d + 1];
+}
+
+struct NlResArgs {
+  NlDev g;
+  int64_t N;
+  int k;
+  const double* Y;
+  int ldy;
+  const double* A1;
+  const double* A2;
+  const double* B0;
+  int ldb0, nb0;
+  int b0col[8];
+  double* R;
+  int ldr;
+  double* partials;
+  int64_t tps;
+};
+
+template <int KP>
+constexpr int nlres_lds() {
+  return (2 * TileGeom<KP>::LDS_DOUBLES > 4 * KP) ? 2 * TileGeom<KP>::LDS_DOUBLES : 4 * KP;
+}
+
+template <int KP>
+__global__ __launch_bounds__(256) void nl_residual_kernel(NlResArgs a) {
+  using G = TileGeom<KP>;
+  __shared__ __align__(16) double lds[nlres_lds<KP>()];
+  double* Yl = lds;
+  double* Fl = lds + G::LDS_DOUBLES;
+  const int t = threadIdx.x, c = t % KP, r0 = t / KP;
+  const int64_t slot = dev::xcd_slot(blockIdx.x, gridDim.x);
+  const int64_t ntiles = (a.N + G::RT - 1) / G::RT;
+  const bool cok = c < a.k;
+  double a1[KP], a2[KP];
+#pragma unroll
+  for (int j = 0; j < KP; ++j) {
+    a1[j] = (cok && j < a.k) ? a.A1[c * a.k + j] : 0.0;
+    a2[j] = (cok && j < a.k) ? a.A2[c * a.k + j] : 0.0;
+  }
+  int b0j = -1;
+  for (int j = 0; j < a.nb0; ++j)
+    if (a.b0col[j] == c) b0j = j;
+  double nacc[1] = {0.0};
+  const int64_t tend = (slot + 1) * a.tps < ntiles ? (slot + 1) * a.tps : ntiles;
+  for (int64_t tile = slot * a.tps; tile < tend; ++tile) {
+    const int64_t row0 = tile * G::RT;
+    for (int i = 0; i < G::RPT; ++i) {
+      const int row = r0 + i * G::RS;
+      const int64_t gr = row0 + row;
+      const bool ok = gr < a.N && cok;
+      Yl[row * G::LDL + c] = ok ? a.Y[gr * a.ldy + c] : 0.0;
+      Fl[row * G::LDL + c] = ok ? f_at(a.g, a.Y + c, a.ldy, gr) : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < G::RPT; ++i) {
+      const int row = r0 + i * G::RS;
+      const int64_t gr = row0 + row;
+      if (gr < a.N && cok) {
+        double r = dev::lds_row_dot<KP>(Yl, row, a1) + dev::lds_row_dot<KP>(Fl, row, a2);
+        if (b0j >= 0) r -= a.B0[gr * a.ldb0 + b0j];
+        a.R[gr * a.ldr + c] = r;
+        nacc[0] = fma(r, r, nacc[0]);
+      }
+    }
+    __syncthreads();
+  }
+  dev::block_reduce_store<KP, 1>(nacc, lds, a.partials, gridDim.x, slot);
+}
+
+template <int KP>
+void launch_nlres(bkts_ctx ctx, NlResArgs a, double* nrm) {
+  using G = TileGeom<KP>;
+  const int64_t ntiles = (a.N + G::RT - 1) / G::RT;
+  const int64_t cap = 2 * (int64_t)ctx->num_cu;
+  int64_t ns = ntiles < cap ? ntiles : cap;
+  if (ns < 1) ns = 1;
+  a.tps = (ntiles + ns - 1) / ns;
+  a.partials = ctx->ws.get<double>("nlres_partials", (size_t)KP * ns);
+  ProfScope prof(ctx, BKTS_K_RESIDUAL, 16.0 * a.N * a.k + 8.0 * a.N * a.nb0);
+  hipLaunchKernelGGL((nl_residual_kernel<KP>), dim3(ns), dim3(256), 0, ctx->stream, a);
+  BKTS_HIP(hipGetLastError());
+  prof.end();
+  finalize_partials(ctx, a.partials, (int)ns, a.k, nrm);
+}
+
+}  // namespace
+
+bkts_op fv_assemble(bkts_ctx ctx, const bkts_grid* grid, const bkts_fv_coeffs* c, int format);
+
+bkts_nlop nlop_create(bkts_ctx ctx, const bkts_grid* grid, const bkts_nl_coeffs* c) {
+  BKTS_REQUIRE(grid && c, "grid and coeffs must not be NULL");
+  BKTS_REQUIRE(grid->dim >= 1 && grid->dim <= 3, "grid dim must be 1, 2 or 3");
+  auto* nl = new bkts_nlop_s();
+  try {
+    nl->ctx = ctx;
+    NlDev& g = nl->nd;
+    g.dim = grid->dim;
+    nl->N = 1;
+    for (int d = 0; d < 3; ++d) {
+      g.n[d] = d < grid->dim ? grid->n[d] : 1;
+      BKTS_REQUIRE(g.n[d] >= 1, "grid n[%d] must be >= 1", d);
+      g.w[d] = (double)g.n[d] * g.n[d];
+      nl->N *= g.n[d];
+    }
+    for (int i = 0; i < 4; ++i) {
+      g.dc[i] = c->dcoef[i];
+      g.rc[i] = c->rcoef[i];
+    }
+    bkts_fv_coeffs lc{};
+    lc.kappa_const = 1.0;
+    for (int f = 0; f < 6; ++f) {
+      BKTS_REQUIRE(c->bc_type[f] == BKTS_BC_DIRICHLET || c->bc_type[f] == BKTS_BC_NEUMANN, "bad bc_type[%d]", f);
+      g.bc_type[f] = c->bc_type[f];
+      g.bc_val[f] = c->bc_value[f];
+      lc.bc_type[f] = c->bc_type[f];
+    }
+    nl->jac = fv_assemble(ctx, grid, &lc, BKTS_FMT_SELL);  // the stencil sparsity
+  } catch (...) {
+    delete nl;
+    throw;
+  }
+  return nl;
+}
+
+void nl_eval(bkts_ctx ctx, const bkts_nlop_s& nl, int k, const double* Y, int ldy, double* F, int ldf) {
+  const int64_t n = nl.N * k;
+  if (n == 0) return;
+  ProfScope prof(ctx, BKTS_K_OTHER, 16.0 * n);
+  hipLaunchKernelGGL(nl_eval_kernel, dim3((n + 255) / 256), dim3(256), 0, ctx->stream, nl.nd, nl.N, k, Y, ldy, F, ldf);
+  BKTS_HIP(hipGetLastError());
+}
+
+void nl_jacobian(bkts_ctx ctx, bkts_nlop_s& nl, const double* u, int ldu, double alpha, double beta) {
+  bkts_op J = nl.jac;
+  {
+    ProfScope prof(ctx, BKTS_K_OTHER, 8.0 * J->nnz + 12.0 * nl.N);
+    hipLaunchKernelGGL(nl_jac_kernel, dim3((nl.N + 255) / 256), dim3(256), 0, ctx->stream, nl.nd, nl.N, u, ldu, alpha,
+                       beta, J->rowptr.as<int32_t>(), J->val.as<double>());
+    BKTS_HIP(hipGetLastError());
+  }
+  op_refresh_values(J);
+}
+
+void nl_residual(bkts_ctx ctx, const bkts_nlop_s& nl, int k, const double* Y, int ldy, const double* A1,
+                 const double* A2, const double* B0, int ldb0, int nb0, const int* b0_to_col, double* R, int ldr,
+                 double* nrm) {
+  BKTS_REQUIRE(nb0 >= 0 && nb0 <= 8, "at most 8 B0 columns");
+  NlResArgs a{};
+  a.g = nl.nd;
+  a.N = nl.N;
+  a.k = k;
+  a.Y = Y;
+  a.ldy = ldy;
+  a.A1 = A1;
+  a.A2 = A2;
+  a.B0 = B0;
+  a.ldb0 = ldb0;
+  a.nb0 = B0 ? nb0 : 0;
+  for (int j = 0; j < 8; ++j) a.b0col[j] = j < a.nb0 ? b0_to_col[j] : -1;
+  a.R = R;
+  a.ldr = ldr;
+  switch (k <= 1 ? 1 : k <= 2 ? 2 : k <= 4 ? 4 : k <= 8 ? 8 : k <= 16 ? 16 : 32) {
+    case 1: launch_nlres<1>(ctx, a, nrm); break;
+    case 2: launch_nlres<2>(ctx, a, nrm); break;
+    case 4: launch_nlres<4>(ctx, a, nrm); break;
+    case 8: launch_nlres<8>(ctx, a, nrm); break;
+    case 16: launch_nlres<16>(ctx, a, nrm); break;
+    default: launch_nlres<32>(ctx, a, nrm); break;
+  }
+}
+
+}  // namespace bkts

@@ -293,6 +293,26 @@ void op_build_sell(bkts_op op) {
   BKTS_HIP(hipGetLastError());
 }
 
+void op_refresh_values(bkts_op op) {
+  bkts_ctx ctx = op->ctx;
+  const int64_t N = op->N;
+  hipLaunchKernelGGL(csr_diag, dim3((N + 255) / 256), dim3(256), 0, ctx->stream, N, op->rowptr.as<int32_t>(),
+                     op->col.as<int32_t>(), op->val.as<double>(), op->diag.as<double>());
+  if (op->nnz > 0)
+    hipLaunchKernelGGL(to_f32, dim3((op->nnz + 255) / 256), dim3(256), 0, ctx->stream, op->nnz,
+                       op->val.as<double>(), op->val32.as<float>());
+  if (op->format == BKTS_FMT_SELL && op->sell_nnz > 0) {
+    const int64_t rows = op->nslices * op->sell_C;
+    hipLaunchKernelGGL(sell_fill, dim3((rows + 255) / 256), dim3(256), 0, ctx->stream, N, op->sell_C,
+                       op->rowptr.as<int32_t>(), op->col.as<int32_t>(), op->val.as<double>(),
+                       op->sell_ptr.as<int64_t>(), op->sell_w.as<int32_t>(), op->sell_col.as<int32_t>(),
+                       op->sell_val.as<double>());
+    hipLaunchKernelGGL(to_f32, dim3((op->sell_nnz + 255) / 256), dim3(256), 0, ctx->stream, op->sell_nnz,
+                       op->sell_val.as<double>(), op->sell_val32.as<float>());
+  }
+  BKTS_HIP(hipGetLastError());
+}
+
 void op_finish(bkts_op op) {
   bkts_ctx ctx = op->ctx;
   const int64_t N = op->N;
