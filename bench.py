@@ -43,6 +43,8 @@ def parse():
     p.add_argument("--no-plain", action="store_true")
     p.add_argument("--no-cpu", action="store_true")
     p.add_argument("--cpu-steps", type=int, default=1)
+    p.add_argument("--calibrate-copy", action="store_true",
+                   help="first run 3 plain 256 MiB device copies (reference dispatches for HBM counters)")
     p.add_argument("--sweep", type=str, default="1f32,4f64,8,16,32",
                    help="comma list of extra block forms to time: <k>[f32|f64] (default precision: --precision)")
     return p.parse_args()
@@ -57,24 +59,64 @@ def kernel_table(bkts, ctx):
     for name in bkts.KERNELS:
         n, ms, by = bkts.bkts_profile_query(ctx, name)
         if n:
-            out[name] = {"launches": n, "avg_us": 1e3 * ms / n, "total_ms": ms,
+            out[name] = {"launches": n, "avg_us": 1e3 * ms / n, "total_ms": ms, "bytes_per_launch": by / n,
                          "GBps": (by / 1e9) / (ms / 1e3) if ms > 0 else None}
+    tot = sum(v["total_ms"] for v in out.values())
+    for v in out.values():
+        v["share"] = v["total_ms"] / tot if tot > 0 else None
     return out
 
 
-def traffic_for(kernel_src, launches_bytes):
-    """Counter-based HBM bytes per launch, if a committed counter summary matches this kernel source."""
-    path = os.path.join(ROOT, "profiles", "spmm_counters.json")
+def kernel_name(cat, k):
+    """The kernel behind a profiling category in the block-CG inner solve at width k."""
+    row = k in (1, 2, 4)  # one thread per row; wider blocks use column tiles (MFMA for the updates)
+    return {"spmm": "rk_spmm_gram_kernel" if row else "spmm_ell_kernel",
+            "cg_update": "rk_cg_update_kernel" if row else "mf_cg_update_kernel",
+            "cg_pupdate": "rk_cg_pupdate_kernel" if row else "mf_cg_pupdate_kernel",
+            "gram": "rk_gram_kernel" if row else "mf_gram_kernel",
+            "residual": "residual_kernel", "norms": "colnorm_kernel", "cast": "cast_scale_kernel",
+            "small": "finalize / k x k kernels", "other": "vector kernels"}.get(cat, cat)
+
+
+def roofline_of(kt, cat, k, precision):
+    """HBM roofline of one profiling category: algorithmic bytes per launch / average launch time."""
+    v = kt[cat]
+    bpl = v["bytes_per_launch"]
+    achieved = bpl / (v["avg_us"] * 1e-6) / 1e9
+    name = kernel_name(cat, k)
+    return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_for(name, precision, k), "kernel": name,
+            "category": cat, "algorithmic_bytes_per_launch": bpl, "avg_launch_us": v["avg_us"],
+            "launches": v["launches"], "share_of_kernel_time": v["share"]}
+
+
+def traffic_for(kernel, precision, k):
+    """Counter-based HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated) from the committed
+    counter summary, or None when there is none for this kernel or its source changed since."""
+    path = os.path.join(ROOT, "profiles", "counters.json")
     if not os.path.exists(path):
         return None
     try:
         d = json.load(open(path))
-        sha = hashlib.sha256(open(kernel_src, "rb").read()).hexdigest()
-        if d.get("source_sha256") != sha:
+        e = d.get(f"{kernel} {precision} k={k}")
+        if not e:
             return None
-        return d.get("hbm_bytes_per_launch")
-    except Exception:
+        for src, sha in e["sources"].items():
+            if hashlib.sha256(open(os.path.join(ROOT, src), "rb").read()).hexdigest() != sha:
+                return None
+        return e["hbm_bytes_per_launch"]
+    except (OSError, ValueError, KeyError):
         return None
+
+
+def calibrate_copy(torch):
+    """Plain device-to-device copies of a known size (256 MiB), for scaling the HBM byte counters."""
+    a = torch.empty(1 << 25, dtype=torch.float64, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    del a, b
 
 
 def run_form(torch, bkts, ctx, op, y0, k, precision, inner_rtol, warmup, steps, profile):
@@ -115,6 +157,8 @@ def main():
 
     n = (a.n, a.n, a.n)
     N = a.n ** 3
+    if a.calibrate_copy:
+        calibrate_copy(torch)
     log(f"inputs {n}")
     kap = inputs.lognormal_field(n, 0.0, 2.0, 8.0, 0)
     u0 = inputs.sin_product(n)
@@ -158,23 +202,18 @@ def main():
             "spmm_avg_us": sp.get("avg_us"),
             "spmm_GBps": (bpl / (sp["avg_us"] * 1e-6) / 1e9) if sp else None,
             "spmm_frac": (bpl / (sp["avg_us"] * 1e-6) / 1e9 / HBM_PEAK_GBS) if sp else None,
+            "spmm_kernel": kernel_name("spmm", ks), "spmm_flop_per_byte": 2.0 * nnz * ks / bpl,
             "dominant_kernel": dom,
             "kernels": {kk: {"avg_us": vv["avg_us"], "GBps": vv["GBps"]} for kk, vv in r["kernels"].items()}}
         log(f"  sweep k={ks} {prec}: {r['value']:.4g} DOF*steps/s (spmm {sp.get('avg_us', 0):.1f} us)")
 
-    spmm = blk["kernels"].get("spmm")
-    roof = None
-    if spmm:
-        sv = 4 if a.precision == "f32" else 8
-        bytes_per_launch = nnz * (sv + 4) + 4 * (N + 1) + 2 * N * a.k * sv
-        avg_s = spmm["avg_us"] * 1e-6
-        achieved = bytes_per_launch / avg_s / 1e9
-        roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS,
-                "traffic": traffic_for(os.path.join(ROOT, "paper_2504_02117_amd", "csrc", "spmm.hip"), None),
-                "kernel": f"spmm_kernel<{'float' if sv == 4 else 'double'},{a.k},{16 // sv},SELL>",
-                "algorithmic_bytes_per_launch": bytes_per_launch, "avg_launch_us": spmm["avg_us"],
-                "launches": spmm["launches"]}
+    roof = spmm_roof = None
+    if blk["kernels"]:
+        dom = max((c for c in blk["kernels"] if c not in ("small", "other")),
+                  key=lambda c: blk["kernels"][c]["total_ms"])
+        roof = roofline_of(blk["kernels"], dom, a.k, a.precision)
+        if "spmm" in blk["kernels"]:
+            spmm_roof = roofline_of(blk["kernels"], "spmm", a.k, a.precision)
 
     cpu = None
     err = None
@@ -216,6 +255,7 @@ def main():
         "speedup_vs_plain": (blk["value"] / plain["value"]) if plain else None,
         "sweep": sweep or None,
         "roofline": roof,
+        "spmm_roofline": spmm_roof,
         "kernels": blk["kernels"],
         "cpu_baseline": cpu,
     }

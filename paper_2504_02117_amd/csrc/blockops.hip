@@ -315,10 +315,10 @@ void launch_gram_t(bkts_ctx ctx, int dtype, int64_t N, int k, const void* X, int
   double* part = ctx->ws.get<double>("gram_partials", (size_t)KP * KP * s.nslots);
   ProfScope prof(ctx, BKTS_K_GRAM, 2.0 * N * k * esize(dtype));
   if (dtype == BKTS_F64)
-    hipLaunchKernelGGL((gram_kernel<double, KP>), dim3(s.nslots), dim3(256), 0, ctx->stream, N, k,
+    launch(ctx, (gram_kernel<double, KP>), dim3(s.nslots), dim3(256), 0, N, k,
                        static_cast<const double*>(X), ldx, static_cast<const double*>(Y), ldy, part, s.tps);
   else
-    hipLaunchKernelGGL((gram_kernel<float, KP>), dim3(s.nslots), dim3(256), 0, ctx->stream, N, k,
+    launch(ctx, (gram_kernel<float, KP>), dim3(s.nslots), dim3(256), 0, N, k,
                        static_cast<const float*>(X), ldx, static_cast<const float*>(Y), ldy, part, s.tps);
   BKTS_HIP(hipGetLastError());
   prof.end();
@@ -332,10 +332,10 @@ void launch_colnorm_t(bkts_ctx ctx, int dtype, int64_t N, int k, const void* X, 
   double* part = ctx->ws.get<double>("norm_partials", (size_t)KP * s.nslots);
   ProfScope prof(ctx, BKTS_K_NORMS, 1.0 * N * k * esize(dtype));
   if (dtype == BKTS_F64)
-    hipLaunchKernelGGL((colnorm_kernel<double, KP>), dim3(s.nslots), dim3(256), 0, ctx->stream, N, k,
+    launch(ctx, (colnorm_kernel<double, KP>), dim3(s.nslots), dim3(256), 0, N, k,
                        static_cast<const double*>(X), ldx, part, s.tps);
   else
-    hipLaunchKernelGGL((colnorm_kernel<float, KP>), dim3(s.nslots), dim3(256), 0, ctx->stream, N, k,
+    launch(ctx, (colnorm_kernel<float, KP>), dim3(s.nslots), dim3(256), 0, N, k,
                        static_cast<const float*>(X), ldx, part, s.tps);
   BKTS_HIP(hipGetLastError());
   prof.end();
@@ -353,7 +353,7 @@ void launch_cg_update_t(bkts_ctx ctx, int64_t N, int k, void* X, const void* P, 
   double* pt = ctx->ws.get<double>("cg_pt", np);
   double* pn = ctx->ws.get<double>("cg_pn", (size_t)KP * s.nslots);
   ProfScope prof(ctx, BKTS_K_CG_UPDATE, 6.0 * N * k * sizeof(T) + (dinv ? 8.0 * N : 0.0));
-  hipLaunchKernelGGL((cg_update_kernel<T, KP>), dim3(s.nslots), dim3(256), 0, ctx->stream, N, k, static_cast<T*>(X),
+  launch(ctx, (cg_update_kernel<T, KP>), dim3(s.nslots), dim3(256), 0, N, k, static_cast<T*>(X),
                      static_cast<const T*>(P), static_cast<T*>(R), static_cast<const T*>(Q), alpha, dinv, pg, pt, pn, s.tps);
   BKTS_HIP(hipGetLastError());
   prof.end();
@@ -368,7 +368,7 @@ void launch_cg_pupdate_t(bkts_ctx ctx, int64_t N, int k, void* P, const void* R,
                          const double* dinv) {
   Slots s = make_slots<KP>(ctx, N);
   ProfScope prof(ctx, BKTS_K_CG_PUPDATE, (beta ? 3.0 : 2.0) * N * k * sizeof(T) + (dinv ? 8.0 * N : 0.0));
-  hipLaunchKernelGGL((cg_pupdate_kernel<T, KP>), dim3(s.nslots), dim3(256), 0, ctx->stream, N, k, static_cast<T*>(P),
+  launch(ctx, (cg_pupdate_kernel<T, KP>), dim3(s.nslots), dim3(256), 0, N, k, static_cast<T*>(P),
                      static_cast<const T*>(R), beta, dinv, s.tps);
   BKTS_HIP(hipGetLastError());
 }
@@ -378,7 +378,7 @@ void launch_rmul_t(bkts_ctx ctx, int64_t N, int k, const void* X, int ldx, const
                    void* Y, int ldy) {
   Slots s = make_slots<KP>(ctx, N);
   ProfScope prof(ctx, BKTS_K_OTHER, (c0 != 0.0 ? 3.0 : 2.0) * N * k * sizeof(T));
-  hipLaunchKernelGGL((rmul_kernel<T, KP>), dim3(s.nslots), dim3(256), 0, ctx->stream, N, k, static_cast<const T*>(X),
+  launch(ctx, (rmul_kernel<T, KP>), dim3(s.nslots), dim3(256), 0, N, k, static_cast<const T*>(X),
                      ldx, C, c0, c1, static_cast<T*>(Y), ldy, s.tps);
   BKTS_HIP(hipGetLastError());
 }
@@ -398,14 +398,14 @@ void launch_rmul_t(bkts_ctx ctx, int64_t N, int k, const void* X, int ldx, const
 
 void finalize_partials(bkts_ctx ctx, const double* partials, int nblocks, int nentries, double* out) {
   ProfScope prof(ctx, BKTS_K_SMALL, 8.0 * nblocks * nentries);
-  hipLaunchKernelGGL(finalize_kernel, dim3(nentries), dim3(256), 0, ctx->stream, partials, (int64_t)nblocks, 1, 1, 1,
+  launch(ctx, finalize_kernel, dim3(nentries), dim3(256), 0, partials, (int64_t)nblocks, 1, 1, 1,
                      out);
   BKTS_HIP(hipGetLastError());
 }
 
 void finalize_gram(bkts_ctx ctx, const double* partials, int nblocks, int k, int KP, double* out) {
   ProfScope prof(ctx, BKTS_K_SMALL, 8.0 * nblocks * k * k);
-  hipLaunchKernelGGL(finalize_kernel, dim3(k * k), dim3(256), 0, ctx->stream, partials, (int64_t)nblocks, k, KP, 0,
+  launch(ctx, finalize_kernel, dim3(k * k), dim3(256), 0, partials, (int64_t)nblocks, k, KP, 0,
                      out);
   BKTS_HIP(hipGetLastError());
 }
@@ -421,7 +421,7 @@ void finalize_sets(bkts_ctx ctx, int nblocks, int k, const FoldSet* sets, int ns
     total += sets[i].vector ? k : k * k;
   }
   ProfScope prof(ctx, BKTS_K_SMALL, 8.0 * nblocks * total);
-  hipLaunchKernelGGL(finalize_sets_kernel, dim3(total), dim3(256), 0, ctx->stream, a);
+  launch(ctx, finalize_sets_kernel, dim3(total), dim3(256), 0, a);
   BKTS_HIP(hipGetLastError());
 }
 
@@ -477,16 +477,16 @@ void block_cast_scale(bkts_ctx ctx, int64_t N, int k, int src_t, const void* src
   dim3 g((n + 255) / 256), b(256);
   ProfScope prof(ctx, BKTS_K_CAST, (double)n * (esize(src_t) + esize(dst_t) * (accumulate ? 2 : 1)));
   if (src_t == BKTS_F64 && dst_t == BKTS_F32)
-    hipLaunchKernelGGL((cast_scale_kernel<double, float>), g, b, 0, ctx->stream, N, k, static_cast<const double*>(src),
+    launch(ctx, (cast_scale_kernel<double, float>), g, b, 0, N, k, static_cast<const double*>(src),
                        lds_, static_cast<float*>(dst), ldd, s, (int)invert_s, (int)accumulate);
   else if (src_t == BKTS_F32 && dst_t == BKTS_F64)
-    hipLaunchKernelGGL((cast_scale_kernel<float, double>), g, b, 0, ctx->stream, N, k, static_cast<const float*>(src),
+    launch(ctx, (cast_scale_kernel<float, double>), g, b, 0, N, k, static_cast<const float*>(src),
                        lds_, static_cast<double*>(dst), ldd, s, (int)invert_s, (int)accumulate);
   else if (src_t == BKTS_F64 && dst_t == BKTS_F64)
-    hipLaunchKernelGGL((cast_scale_kernel<double, double>), g, b, 0, ctx->stream, N, k, static_cast<const double*>(src),
+    launch(ctx, (cast_scale_kernel<double, double>), g, b, 0, N, k, static_cast<const double*>(src),
                        lds_, static_cast<double*>(dst), ldd, s, (int)invert_s, (int)accumulate);
   else
-    hipLaunchKernelGGL((cast_scale_kernel<float, float>), g, b, 0, ctx->stream, N, k, static_cast<const float*>(src),
+    launch(ctx, (cast_scale_kernel<float, float>), g, b, 0, N, k, static_cast<const float*>(src),
                        lds_, static_cast<float*>(dst), ldd, s, (int)invert_s, (int)accumulate);
   BKTS_HIP(hipGetLastError());
 }

@@ -88,22 +88,33 @@ Profiler::~Profiler() {
 ProfScope::ProfScope(bkts_ctx c, int k, double bytes) : ctx(c), kid(k) {
   if (!ctx->prof.enabled) return;
   Profiler& p = ctx->prof;
-  if (p.pending.size() > 8192 && p.open == 0) p.resolve();  // only when every end event is recorded
-  hipEvent_t a = p.take();
+  if (p.pending.size() > 8192 && p.open == 0) p.resolve();  // only when every event is recorded
+  if (p.ext_a) {  // an enclosing scope has not launched its kernel: record its events as empty
+    BKTS_HIP(hipEventRecord(p.ext_a, ctx->stream));
+    BKTS_HIP(hipEventRecord(p.ext_b, ctx->stream));
+    p.ext_a = p.ext_b = nullptr;
+    p.open -= 1;
+  }
+  a = p.take();
   b = p.take();
-  BKTS_HIP(hipEventRecord(a, ctx->stream));
   p.pending.push_back({k, a, b});
   p.acc[k].launches += 1;
   p.acc[k].bytes += bytes;
+  p.ext_a = a;
+  p.ext_b = b;
   p.open += 1;
 }
 
 void ProfScope::end() {
-  if (b) {
+  if (!a) return;
+  Profiler& p = ctx->prof;
+  if (p.ext_a == a) {  // no kernel was launched in the scope
+    (void)hipEventRecord(a, ctx->stream);
     (void)hipEventRecord(b, ctx->stream);
-    ctx->prof.open -= 1;
-    b = nullptr;
+    p.ext_a = p.ext_b = nullptr;
+    p.open -= 1;
   }
+  a = b = nullptr;
 }
 
 int blocks_per_cu(const void* kernel) {

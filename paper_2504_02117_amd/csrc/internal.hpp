@@ -2,6 +2,7 @@
 // launchers every translation unit shares.  Nothing here is part of the C ABI.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cstdarg>
@@ -86,6 +87,9 @@ struct Profiler {
   };
   bool enabled = false;
   int open = 0;  // scopes whose end event is not recorded yet (they nest)
+  // Events of the innermost scope waiting for its kernel: the next launch() carries them in its
+  // dispatch packet, so their interval is that kernel's own execution (no queue gaps).
+  hipEvent_t ext_a = nullptr, ext_b = nullptr;
   std::vector<hipEvent_t> pool;
   std::vector<Rec> pending;
   Acc acc[BKTS_K_COUNT];
@@ -168,14 +172,29 @@ struct bkts_tc_s {
 namespace bkts {
 
 // RAII timer around the launches of one kernel (no-op unless profiling is enabled).
+// Times one kernel category.  The scope's interval is the execution of the next kernel started
+// with launch() (timestamps of that dispatch); if no kernel is launched before end(), the
+// interval is empty.
 struct ProfScope {
   bkts_ctx ctx;
   int kid;
-  hipEvent_t b = nullptr;
+  hipEvent_t a = nullptr, b = nullptr;
   ProfScope(bkts_ctx c, int k, double bytes);
-  void end();  // record the end event now (the scope covers only what was enqueued so far)
+  void end();
   ~ProfScope() { end(); }
 };
+
+// Launch on the context stream; a pending ProfScope's events travel with this dispatch.
+template <typename F, typename... Args>
+inline void launch(bkts_ctx ctx, F kernel, dim3 grid, dim3 block, uint32_t shmem, Args... args) {
+  Profiler& p = ctx->prof;
+  hipEvent_t ea = p.ext_a, eb = p.ext_b;
+  if (ea) {
+    p.ext_a = p.ext_b = nullptr;
+    p.open -= 1;
+  }
+  hipExtLaunchKernelGGL(kernel, grid, block, shmem, ctx->stream, ea, eb, 0, args...);
+}
 
 // ---- operator building (op.hip)
 void op_build_sell(bkts_op op);

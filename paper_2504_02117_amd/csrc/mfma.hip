@@ -492,11 +492,11 @@ void mf_gram(bkts_ctx ctx, int dtype, int64_t N, int k, const void* X, int ldx, 
   double* part = ctx->ws.get<double>("mf_gram_part", (size_t)KP * KP * nb);
   ProfScope prof(ctx, BKTS_K_GRAM, 2.0 * N * k * esize(dtype));
   if (dtype == BKTS_F64)
-    BKTS_NB_DISPATCH(k, hipLaunchKernelGGL((mf_gram_kernel<double, NB>), dim3(nb), dim3(256), 0, ctx->stream, N, k,
+    BKTS_NB_DISPATCH(k, launch(ctx, (mf_gram_kernel<double, NB>), dim3(nb), dim3(256), 0, N, k,
                                             static_cast<const double*>(X), ldx, static_cast<const double*>(Y), ldy,
                                             part));
   else
-    BKTS_NB_DISPATCH(k, hipLaunchKernelGGL((mf_gram_kernel<float, NB>), dim3(nb), dim3(256), 0, ctx->stream, N, k,
+    BKTS_NB_DISPATCH(k, launch(ctx, (mf_gram_kernel<float, NB>), dim3(nb), dim3(256), 0, N, k,
                                             static_cast<const float*>(X), ldx, static_cast<const float*>(Y), ldy,
                                             part));
   BKTS_HIP(hipGetLastError());
@@ -540,11 +540,11 @@ void mf_spmm_gram(bkts_ctx ctx, const bkts_op_s& op, int dtype, int k, double al
     a.Q = static_cast<T*>(Q);
     a.partials = part;
     if (sell)
-      BKTS_NB_DISPATCH(k, hipLaunchKernelGGL((mf_spmm_gram_kernel<T, NB, true>), dim3(nb), dim3(256), 0,
-                                              ctx->stream, a));
+      BKTS_NB_DISPATCH(k, launch(ctx, (mf_spmm_gram_kernel<T, NB, true>), dim3(nb), dim3(256), 0,
+                                              a));
     else
-      BKTS_NB_DISPATCH(k, hipLaunchKernelGGL((mf_spmm_gram_kernel<T, NB, false>), dim3(nb), dim3(256), 0,
-                                              ctx->stream, a));
+      BKTS_NB_DISPATCH(k, launch(ctx, (mf_spmm_gram_kernel<T, NB, false>), dim3(nb), dim3(256), 0,
+                                              a));
   };
   if (dtype == BKTS_F64)
     go(double{});
@@ -569,11 +569,9 @@ void mf_cg_update(bkts_ctx ctx, int dtype, int64_t N, int k, void* X, const void
   CgUpdArgs a{N, k, X, P, R, Q, alpha, dinv, pg, pt, pn};
   ProfScope prof(ctx, BKTS_K_CG_UPDATE, 6.0 * N * k * esize(dtype) + (dinv ? 8.0 * N : 0.0));
   if (dtype == BKTS_F64)
-    BKTS_NB_DISPATCH(k, hipLaunchKernelGGL((mf_cg_update_kernel<double, NB>), dim3(nb), dim3(256), 0, ctx->stream,
-                                            a));
+    BKTS_NB_DISPATCH(k, launch(ctx, (mf_cg_update_kernel<double, NB>), dim3(nb), dim3(256), 0, a));
   else
-    BKTS_NB_DISPATCH(k, hipLaunchKernelGGL((mf_cg_update_kernel<float, NB>), dim3(nb), dim3(256), 0, ctx->stream,
-                                            a));
+    BKTS_NB_DISPATCH(k, launch(ctx, (mf_cg_update_kernel<float, NB>), dim3(nb), dim3(256), 0, a));
   BKTS_HIP(hipGetLastError());
   prof.end();
   const FoldSet sets[3] = {{pg, KP, 0, gamma}, {pt, KP, 0, Tm}, {pn, KP, 1, nrm}};
@@ -587,11 +585,9 @@ void mf_cg_pupdate(bkts_ctx ctx, int dtype, int64_t N, int k, void* P, const voi
                                 (N + 15) / 16);
   ProfScope prof(ctx, BKTS_K_CG_PUPDATE, (beta ? 3.0 : 2.0) * N * k * esize(dtype) + (dinv ? 8.0 * N : 0.0));
   if (dtype == BKTS_F64)
-    BKTS_NB_DISPATCH(k, hipLaunchKernelGGL((mf_cg_pupdate_kernel<double, NB>), dim3(nb), dim3(256), 0, ctx->stream,
-                                            N, k, static_cast<double*>(P), static_cast<const double*>(R), beta, dinv));
+    BKTS_NB_DISPATCH(k, launch(ctx, (mf_cg_pupdate_kernel<double, NB>), dim3(nb), dim3(256), 0, N, k, static_cast<double*>(P), static_cast<const double*>(R), beta, dinv));
   else
-    BKTS_NB_DISPATCH(k, hipLaunchKernelGGL((mf_cg_pupdate_kernel<float, NB>), dim3(nb), dim3(256), 0, ctx->stream,
-                                            N, k, static_cast<float*>(P), static_cast<const float*>(R), beta, dinv));
+    BKTS_NB_DISPATCH(k, launch(ctx, (mf_cg_pupdate_kernel<float, NB>), dim3(nb), dim3(256), 0, N, k, static_cast<float*>(P), static_cast<const float*>(R), beta, dinv));
   BKTS_HIP(hipGetLastError());
 }
 
@@ -602,10 +598,10 @@ void mf_rmul(bkts_ctx ctx, int dtype, int64_t N, int k, const void* X, const dou
                                 (N + 15) / 16);
   ProfScope prof(ctx, BKTS_K_OTHER, (c0 != 0.0 ? 3.0 : 2.0) * N * k * esize(dtype));
   if (dtype == BKTS_F64)
-    BKTS_NB_DISPATCH(k, hipLaunchKernelGGL((mf_rmul_kernel<double, NB>), dim3(nb), dim3(256), 0, ctx->stream, N, k,
+    BKTS_NB_DISPATCH(k, launch(ctx, (mf_rmul_kernel<double, NB>), dim3(nb), dim3(256), 0, N, k,
                                             static_cast<const double*>(X), C, c0, c1, static_cast<double*>(Y)));
   else
-    BKTS_NB_DISPATCH(k, hipLaunchKernelGGL((mf_rmul_kernel<float, NB>), dim3(nb), dim3(256), 0, ctx->stream, N, k,
+    BKTS_NB_DISPATCH(k, launch(ctx, (mf_rmul_kernel<float, NB>), dim3(nb), dim3(256), 0, N, k,
                                             static_cast<const float*>(X), C, c0, c1, static_cast<float*>(Y)));
   BKTS_HIP(hipGetLastError());
 }

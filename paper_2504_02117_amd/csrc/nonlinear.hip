@@ -186,7 +186,7 @@ void launch_nlres(bkts_ctx ctx, NlResArgs a, double* nrm) {
   a.tps = (ntiles + ns - 1) / ns;
   a.partials = ctx->ws.get<double>("nlres_partials", (size_t)KP * ns);
   ProfScope prof(ctx, BKTS_K_RESIDUAL, 16.0 * a.N * a.k + 8.0 * a.N * a.nb0);
-  hipLaunchKernelGGL((nl_residual_kernel<KP>), dim3(ns), dim3(256), 0, ctx->stream, a);
+  launch(ctx, (nl_residual_kernel<KP>), dim3(ns), dim3(256), 0, a);
   BKTS_HIP(hipGetLastError());
   prof.end();
   finalize_partials(ctx, a.partials, (int)ns, a.k, nrm);
@@ -235,7 +235,7 @@ void nl_eval(bkts_ctx ctx, const bkts_nlop_s& nl, int k, const double* Y, int ld
   const int64_t n = nl.N * k;
   if (n == 0) return;
   ProfScope prof(ctx, BKTS_K_OTHER, 16.0 * n);
-  hipLaunchKernelGGL(nl_eval_kernel, dim3((n + 255) / 256), dim3(256), 0, ctx->stream, nl.nd, nl.N, k, Y, ldy, F, ldf);
+  launch(ctx, nl_eval_kernel, dim3((n + 255) / 256), dim3(256), 0, nl.nd, nl.N, k, Y, ldy, F, ldf);
   BKTS_HIP(hipGetLastError());
 }
 
@@ -243,7 +243,7 @@ void nl_jacobian(bkts_ctx ctx, bkts_nlop_s& nl, const double* u, int ldu, double
   bkts_op J = nl.jac;
   {
     ProfScope prof(ctx, BKTS_K_OTHER, 8.0 * J->nnz + 12.0 * nl.N);
-    hipLaunchKernelGGL(nl_jac_kernel, dim3((nl.N + 255) / 256), dim3(256), 0, ctx->stream, nl.nd, nl.N, u, ldu, alpha,
+    launch(ctx, nl_jac_kernel, dim3((nl.N + 255) / 256), dim3(256), 0, nl.nd, nl.N, u, ldu, alpha,
                        beta, J->rowptr.as<int32_t>(), J->val.as<double>());
     BKTS_HIP(hipGetLastError());
   }

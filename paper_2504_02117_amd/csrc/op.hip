@@ -73,9 +73,9 @@ int64_t device_exclusive_scan(bkts_ctx ctx, const int64_t* in, int64_t n, int64_
   const int64_t ntiles = (n + kScanTile - 1) / kScanTile;
   int64_t* totals = ctx->ws.get<int64_t>("scan_totals", ntiles + 1);
   if (n > 0) {
-    hipLaunchKernelGGL(scan_tiles, dim3(ntiles), dim3(256), 0, ctx->stream, in, n, out, totals);
-    hipLaunchKernelGGL(scan_totals, dim3(1), dim3(256), 0, ctx->stream, totals, ntiles, out + n);
-    hipLaunchKernelGGL(scan_add, dim3((n + 255) / 256), dim3(256), 0, ctx->stream, out, n, totals);
+    launch(ctx, scan_tiles, dim3(ntiles), dim3(256), 0, in, n, out, totals);
+    launch(ctx, scan_totals, dim3(1), dim3(256), 0, totals, ntiles, out + n);
+    launch(ctx, scan_add, dim3((n + 255) / 256), dim3(256), 0, out, n, totals);
   } else {
     BKTS_HIP(hipMemsetAsync(out, 0, sizeof(int64_t), ctx->stream));
   }
@@ -253,7 +253,7 @@ void op_build_sell(bkts_op op) {
   wC.alloc(sizeof(int64_t) * (op->nslices + 1));
   op->sell_w.alloc(sizeof(int32_t) * op->nslices);
   op->sell_ptr.alloc(sizeof(int64_t) * (op->nslices + 1));
-  hipLaunchKernelGGL(sell_widths, dim3((op->nslices + 255) / 256), dim3(256), 0, ctx->stream, N, C, op->nslices,
+  launch(ctx, sell_widths, dim3((op->nslices + 255) / 256), dim3(256), 0, N, C, op->nslices,
                      op->rowptr.as<int32_t>(), wC.as<int64_t>(), op->sell_w.as<int32_t>());
   BKTS_HIP(hipGetLastError());
   // Uniform slice width when padding every slice to the widest costs at most 5%: the block operator
@@ -284,11 +284,11 @@ void op_build_sell(bkts_op op) {
   op->sell_val32.alloc(sizeof(float) * op->sell_nnz);
   const int64_t rows = op->nslices * C;
   if (op->sell_nnz > 0)
-    hipLaunchKernelGGL(sell_fill, dim3((rows + 255) / 256), dim3(256), 0, ctx->stream, N, C, op->rowptr.as<int32_t>(),
+    launch(ctx, sell_fill, dim3((rows + 255) / 256), dim3(256), 0, N, C, op->rowptr.as<int32_t>(),
                      op->col.as<int32_t>(), op->val.as<double>(), op->sell_ptr.as<int64_t>(),
                      op->sell_w.as<int32_t>(), op->sell_col.as<int32_t>(), op->sell_val.as<double>());
   if (op->sell_nnz > 0)
-    hipLaunchKernelGGL(to_f32, dim3((op->sell_nnz + 255) / 256), dim3(256), 0, ctx->stream, op->sell_nnz,
+    launch(ctx, to_f32, dim3((op->sell_nnz + 255) / 256), dim3(256), 0, op->sell_nnz,
                        op->sell_val.as<double>(), op->sell_val32.as<float>());
   BKTS_HIP(hipGetLastError());
 }
@@ -296,18 +296,18 @@ void op_build_sell(bkts_op op) {
 void op_refresh_values(bkts_op op) {
   bkts_ctx ctx = op->ctx;
   const int64_t N = op->N;
-  hipLaunchKernelGGL(csr_diag, dim3((N + 255) / 256), dim3(256), 0, ctx->stream, N, op->rowptr.as<int32_t>(),
+  launch(ctx, csr_diag, dim3((N + 255) / 256), dim3(256), 0, N, op->rowptr.as<int32_t>(),
                      op->col.as<int32_t>(), op->val.as<double>(), op->diag.as<double>());
   if (op->nnz > 0)
-    hipLaunchKernelGGL(to_f32, dim3((op->nnz + 255) / 256), dim3(256), 0, ctx->stream, op->nnz,
+    launch(ctx, to_f32, dim3((op->nnz + 255) / 256), dim3(256), 0, op->nnz,
                        op->val.as<double>(), op->val32.as<float>());
   if (op->format == BKTS_FMT_SELL && op->sell_nnz > 0) {
     const int64_t rows = op->nslices * op->sell_C;
-    hipLaunchKernelGGL(sell_fill, dim3((rows + 255) / 256), dim3(256), 0, ctx->stream, N, op->sell_C,
+    launch(ctx, sell_fill, dim3((rows + 255) / 256), dim3(256), 0, N, op->sell_C,
                        op->rowptr.as<int32_t>(), op->col.as<int32_t>(), op->val.as<double>(),
                        op->sell_ptr.as<int64_t>(), op->sell_w.as<int32_t>(), op->sell_col.as<int32_t>(),
                        op->sell_val.as<double>());
-    hipLaunchKernelGGL(to_f32, dim3((op->sell_nnz + 255) / 256), dim3(256), 0, ctx->stream, op->sell_nnz,
+    launch(ctx, to_f32, dim3((op->sell_nnz + 255) / 256), dim3(256), 0, op->sell_nnz,
                        op->sell_val.as<double>(), op->sell_val32.as<float>());
   }
   BKTS_HIP(hipGetLastError());
@@ -317,11 +317,11 @@ void op_finish(bkts_op op) {
   bkts_ctx ctx = op->ctx;
   const int64_t N = op->N;
   op->diag.alloc(sizeof(double) * N);
-  hipLaunchKernelGGL(csr_diag, dim3((N + 255) / 256), dim3(256), 0, ctx->stream, N, op->rowptr.as<int32_t>(),
+  launch(ctx, csr_diag, dim3((N + 255) / 256), dim3(256), 0, N, op->rowptr.as<int32_t>(),
                      op->col.as<int32_t>(), op->val.as<double>(), op->diag.as<double>());
   op->val32.alloc(sizeof(float) * (op->nnz > 0 ? op->nnz : 1));
   if (op->nnz > 0)
-    hipLaunchKernelGGL(to_f32, dim3((op->nnz + 255) / 256), dim3(256), 0, ctx->stream, op->nnz,
+    launch(ctx, to_f32, dim3((op->nnz + 255) / 256), dim3(256), 0, op->nnz,
                        op->val.as<double>(), op->val32.as<float>());
   BKTS_HIP(hipGetLastError());
   if (op->format == BKTS_FMT_SELL) op_build_sell(op);
@@ -366,14 +366,14 @@ bkts_op fv_assemble(bkts_ctx ctx, const bkts_grid* grid, const bkts_fv_coeffs* c
     DevBuf len, rp64;
     len.alloc(sizeof(int64_t) * N);
     rp64.alloc(sizeof(int64_t) * (N + 1));
-    hipLaunchKernelGGL(fv_row_lengths, dim3((N + 255) / 256), dim3(256), 0, ctx->stream, g, N, len.as<int64_t>());
+    launch(ctx, fv_row_lengths, dim3((N + 255) / 256), dim3(256), 0, g, N, len.as<int64_t>());
     BKTS_HIP(hipGetLastError());
     op->nnz = device_exclusive_scan(ctx, len.as<int64_t>(), N, rp64.as<int64_t>());
     op->rowptr.alloc(sizeof(int32_t) * (N + 1));
     op->col.alloc(sizeof(int32_t) * op->nnz);
     op->val.alloc(sizeof(double) * op->nnz);
     op->b.alloc(sizeof(double) * N);
-    hipLaunchKernelGGL(fv_fill, dim3((N + 255) / 256), dim3(256), 0, ctx->stream, g, fd, N, rp64.as<int64_t>(),
+    launch(ctx, fv_fill, dim3((N + 255) / 256), dim3(256), 0, g, fd, N, rp64.as<int64_t>(),
                        op->rowptr.as<int32_t>(), op->col.as<int32_t>(), op->val.as<double>(), op->b.as<double>());
     BKTS_HIP(hipGetLastError());
     bool nz = false;

@@ -122,9 +122,9 @@ void launch_res(bkts_ctx ctx, const bkts_op_s& op, ResArgs a, double* nrm) {
   ProfScope prof(ctx, BKTS_K_RESIDUAL,
                  op.nnz * 12.0 + 4.0 * (op.N + 1) + 16.0 * op.N * a.k + (a.b ? 8.0 * op.N : 0.0) + 8.0 * op.N * a.nb0);
   if (op.format == BKTS_FMT_SELL)
-    hipLaunchKernelGGL((residual_kernel<KP, true>), dim3(ns), dim3(256), 0, ctx->stream, a);
+    launch(ctx, (residual_kernel<KP, true>), dim3(ns), dim3(256), 0, a);
   else
-    hipLaunchKernelGGL((residual_kernel<KP, false>), dim3(ns), dim3(256), 0, ctx->stream, a);
+    launch(ctx, (residual_kernel<KP, false>), dim3(ns), dim3(256), 0, a);
   BKTS_HIP(hipGetLastError());
   prof.end();
   finalize_partials(ctx, a.partials, (int)ns, a.k, nrm);

@@ -346,11 +346,11 @@ static void rk_spmm_gram_t(bkts_ctx ctx, const bkts_op_s& op, double alpha, cons
   if (sell) {
     nb = rk_grid(ctx, rk_spmm_gram_kernel<T, KP, true>, op.N);
     a.partials = ctx->ws.get<double>("rk_sg_part", (size_t)KP * KP * nb);
-    hipLaunchKernelGGL((rk_spmm_gram_kernel<T, KP, true>), dim3(nb), dim3(256), 0, ctx->stream, a);
+    launch(ctx, (rk_spmm_gram_kernel<T, KP, true>), dim3(nb), dim3(256), 0, a);
   } else {
     nb = rk_grid(ctx, rk_spmm_gram_kernel<T, KP, false>, op.N);
     a.partials = ctx->ws.get<double>("rk_sg_part", (size_t)KP * KP * nb);
-    hipLaunchKernelGGL((rk_spmm_gram_kernel<T, KP, false>), dim3(nb), dim3(256), 0, ctx->stream, a);
+    launch(ctx, (rk_spmm_gram_kernel<T, KP, false>), dim3(nb), dim3(256), 0, a);
   }
   BKTS_HIP(hipGetLastError());
   prof.end();
@@ -374,7 +374,7 @@ static void rk_cg_update_t(bkts_ctx ctx, int64_t N, void* X, const void* P, void
   double* part = ctx->ws.get<double>("rk_upd_part", (size_t)NA * nb);
   RkUpdArgs a{N, X, P, R, Q, alpha, dinv, part};
   ProfScope prof(ctx, BKTS_K_CG_UPDATE, 6.0 * N * KP * sizeof(T) + (dinv ? 8.0 * N : 0.0));
-  hipLaunchKernelGGL((rk_cg_update_kernel<T, KP>), dim3(nb), dim3(256), 0, ctx->stream, a);
+  launch(ctx, (rk_cg_update_kernel<T, KP>), dim3(nb), dim3(256), 0, a);
   BKTS_HIP(hipGetLastError());
   prof.end();
   const FoldSet sets[3] = {{part, KP, 0, gamma}, {part + (size_t)KP * KP * nb, KP, 0, Tm},
@@ -394,7 +394,7 @@ template <typename T, int KP>
 static void rk_cg_pupdate_t(bkts_ctx ctx, int64_t N, void* P, const void* R, const double* beta, const double* dinv) {
   const int64_t nb = rk_grid(ctx, rk_cg_pupdate_kernel<T, KP>, N);
   ProfScope prof(ctx, BKTS_K_CG_PUPDATE, (beta ? 3.0 : 2.0) * N * KP * sizeof(T) + (dinv ? 8.0 * N : 0.0));
-  hipLaunchKernelGGL((rk_cg_pupdate_kernel<T, KP>), dim3(nb), dim3(256), 0, ctx->stream, N, static_cast<T*>(P),
+  launch(ctx, (rk_cg_pupdate_kernel<T, KP>), dim3(nb), dim3(256), 0, N, static_cast<T*>(P),
                      static_cast<const T*>(R), beta, dinv);
   BKTS_HIP(hipGetLastError());
 }
@@ -412,7 +412,7 @@ static void rk_gram_t(bkts_ctx ctx, int64_t N, const void* X, const void* Y, dou
   const int64_t nb = rk_grid(ctx, rk_gram_kernel<T, KP>, N);
   double* part = ctx->ws.get<double>("rk_gram_part", (size_t)KP * KP * nb);
   ProfScope prof(ctx, BKTS_K_GRAM, 2.0 * N * KP * sizeof(T));
-  hipLaunchKernelGGL((rk_gram_kernel<T, KP>), dim3(nb), dim3(256), 0, ctx->stream, N, static_cast<const T*>(X),
+  launch(ctx, (rk_gram_kernel<T, KP>), dim3(nb), dim3(256), 0, N, static_cast<const T*>(X),
                      static_cast<const T*>(Y), part);
   BKTS_HIP(hipGetLastError());
   prof.end();
@@ -430,7 +430,7 @@ template <typename T, int KP>
 static void rk_rmul_t(bkts_ctx ctx, int64_t N, const void* X, const double* C, double c0, double c1, void* Y) {
   const int64_t nb = rk_grid(ctx, rk_rmul_kernel<T, KP>, N);
   ProfScope prof(ctx, BKTS_K_OTHER, (c0 != 0.0 ? 3.0 : 2.0) * N * KP * sizeof(T));
-  hipLaunchKernelGGL((rk_rmul_kernel<T, KP>), dim3(nb), dim3(256), 0, ctx->stream, N, static_cast<const T*>(X), C, c0,
+  launch(ctx, (rk_rmul_kernel<T, KP>), dim3(nb), dim3(256), 0, N, static_cast<const T*>(X), C, c0,
                      c1, static_cast<T*>(Y));
   BKTS_HIP(hipGetLastError());
 }

@@ -97,7 +97,7 @@ void small_spd_solve(bkts_ctx ctx, int k, const double* G, const double* S, doub
                      int* ndefl) {
   BKTS_REQUIRE(k >= 1 && k <= KM, "k out of range");
   ProfScope prof(ctx, BKTS_K_SMALL, 8.0 * 3 * k * k);
-  hipLaunchKernelGGL(spd_solve_kernel, dim3(1), dim3(64), 0, ctx->stream, k, G, S, sign, eps, out, ndefl);
+  launch(ctx, spd_solve_kernel, dim3(1), dim3(64), 0, k, G, S, sign, eps, out, ndefl);
   BKTS_HIP(hipGetLastError());
 }
 

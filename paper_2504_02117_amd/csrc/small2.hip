@@ -266,13 +266,13 @@ __global__ __launch_bounds__(256) void gmres_lsq_kernel(int k, int nr, int nc, c
 void small_cholqr(bkts_ctx ctx, int k, const double* G, double eps, double* Rinv, double* R, int* ndefl) {
   BKTS_REQUIRE(k >= 1 && k <= KM, "k out of range");
   ProfScope prof(ctx, BKTS_K_SMALL, 8.0 * 3 * k * k);
-  hipLaunchKernelGGL(cholqr_kernel, dim3(1), dim3(64), 0, ctx->stream, k, G, eps, Rinv, R, ndefl);
+  launch(ctx, cholqr_kernel, dim3(1), dim3(64), 0, k, G, eps, Rinv, R, ndefl);
   BKTS_HIP(hipGetLastError());
 }
 
 void small_gemm(bkts_ctx ctx, int k, const double* A, const double* B, double alpha, double* C) {
   ProfScope prof(ctx, BKTS_K_SMALL, 8.0 * 3 * k * k);
-  hipLaunchKernelGGL(small_gemm_kernel, dim3(1), dim3(256), 0, ctx->stream, k, A, B, alpha, C);
+  launch(ctx, small_gemm_kernel, dim3(1), dim3(256), 0, k, A, B, alpha, C);
   BKTS_HIP(hipGetLastError());
 }
 
@@ -280,13 +280,13 @@ void small_lu_solve2(bkts_ctx ctx, int k, const double* M, const double* B1, dou
                      double s2, double* X2, double eps) {
   BKTS_REQUIRE(k >= 1 && k <= KM, "k out of range");
   ProfScope prof(ctx, BKTS_K_SMALL, 8.0 * 5 * k * k);
-  hipLaunchKernelGGL(lu_solve2_kernel, dim3(1), dim3(64), 0, ctx->stream, k, M, B1, s1, X1, B2, s2, X2, eps);
+  launch(ctx, lu_solve2_kernel, dim3(1), dim3(64), 0, k, M, B1, s1, X1, B2, s2, X2, eps);
   BKTS_HIP(hipGetLastError());
 }
 
 void small_omega(bkts_ctx ctx, int k, const double* TS, const double* TT, double* out) {
   ProfScope prof(ctx, BKTS_K_SMALL, 16.0 * k * k);
-  hipLaunchKernelGGL(omega_kernel, dim3(1), dim3(64), 0, ctx->stream, k, TS, TT, out);
+  launch(ctx, omega_kernel, dim3(1), dim3(64), 0, k, TS, TT, out);
   BKTS_HIP(hipGetLastError());
 }
 
@@ -296,7 +296,7 @@ void gmres_lsq(bkts_ctx ctx, int k, int nr, int nc, const double* H, int ldh, co
                double* resn) {
   BKTS_REQUIRE(nr <= kLsqMax && nc < nr, "block Hessenberg system too large");
   ProfScope prof(ctx, BKTS_K_SMALL, 8.0 * nr * nc);
-  hipLaunchKernelGGL(gmres_lsq_kernel, dim3(1), dim3(256), 0, ctx->stream, k, nr, nc, H, ldh, S, eps, Y, resn);
+  launch(ctx, gmres_lsq_kernel, dim3(1), dim3(256), 0, k, nr, nc, H, ldh, S, eps, Y, resn);
   BKTS_HIP(hipGetLastError());
 }
 

@@ -238,11 +238,11 @@ void launch_fmt(bkts_ctx ctx, const bkts_op_s& op, const SpmmArgs<T>& a) {
     nb = (ntiles + per - 1) / per * per;  // whole rounds of 8 strips; blocks past the end exit
   }
   if (ell)
-    hipLaunchKernelGGL((spmm_ell_kernel<T, KP, VEC, G>), dim3(nb), dim3(dev::kThreads), 0, ctx->stream, aa);
+    launch(ctx, (spmm_ell_kernel<T, KP, VEC, G>), dim3(nb), dim3(dev::kThreads), 0, aa);
   else if (op.format == BKTS_FMT_SELL)
-    hipLaunchKernelGGL((spmm_kernel<T, KP, VEC, true>), dim3(nb), dim3(dev::kThreads), 0, ctx->stream, aa);
+    launch(ctx, (spmm_kernel<T, KP, VEC, true>), dim3(nb), dim3(dev::kThreads), 0, aa);
   else
-    hipLaunchKernelGGL((spmm_kernel<T, KP, VEC, false>), dim3(nb), dim3(dev::kThreads), 0, ctx->stream, aa);
+    launch(ctx, (spmm_kernel<T, KP, VEC, false>), dim3(nb), dim3(dev::kThreads), 0, aa);
 }
 
 template <typename T, int KP>

@@ -73,21 +73,21 @@ inline dim3 grid1(int64_t n) { return dim3((unsigned)((n + 255) / 256)); }
 void broadcast_cols(bkts_ctx ctx, int64_t N, int k, const double* y, double* Y, int ld) {
   if (N * k == 0) return;
   ProfScope prof(ctx, BKTS_K_OTHER, 16.0 * N * k);
-  hipLaunchKernelGGL(broadcast_cols_kernel, grid1(N * k), dim3(256), 0, ctx->stream, N, k, y, Y, ld);
+  launch(ctx, broadcast_cols_kernel, grid1(N * k), dim3(256), 0, N, k, y, Y, ld);
   BKTS_HIP(hipGetLastError());
 }
 
 void copy_col(bkts_ctx ctx, int64_t N, double* Y, int ld, int src, int dst) {
   if (N == 0 || src == dst) return;
   ProfScope prof(ctx, BKTS_K_OTHER, 16.0 * N);
-  hipLaunchKernelGGL(copy_col_kernel, grid1(N), dim3(256), 0, ctx->stream, N, Y, ld, src, dst);
+  launch(ctx, copy_col_kernel, grid1(N), dim3(256), 0, N, Y, ld, src, dst);
   BKTS_HIP(hipGetLastError());
 }
 
 void extract_col(bkts_ctx ctx, int64_t N, const double* Y, int ld, int c, double* out) {
   if (N == 0) return;
   ProfScope prof(ctx, BKTS_K_OTHER, 16.0 * N);
-  hipLaunchKernelGGL(extract_col_kernel, grid1(N), dim3(256), 0, ctx->stream, N, Y, ld, c, out);
+  launch(ctx, extract_col_kernel, grid1(N), dim3(256), 0, N, Y, ld, c, out);
   BKTS_HIP(hipGetLastError());
 }
 
@@ -95,14 +95,14 @@ void lincomb(bkts_ctx ctx, int64_t N, const LinComb& lc, double* out, int ldo) {
   BKTS_REQUIRE(lc.m >= 0 && lc.m <= LinComb::kMax, "too many terms");
   if (N == 0) return;
   ProfScope prof(ctx, BKTS_K_OTHER, 8.0 * N * (lc.m + 1));
-  hipLaunchKernelGGL(lincomb_kernel, grid1(N), dim3(256), 0, ctx->stream, N, lc, out, ldo);
+  launch(ctx, lincomb_kernel, grid1(N), dim3(256), 0, N, lc, out, ldo);
   BKTS_HIP(hipGetLastError());
 }
 
 void jacobi_inverse(bkts_ctx ctx, const bkts_op_s& op, double a, double b, double* dinv) {
   if (op.N == 0) return;
   ProfScope prof(ctx, BKTS_K_OTHER, 16.0 * op.N);
-  hipLaunchKernelGGL(jacobi_inverse_kernel, grid1(op.N), dim3(256), 0, ctx->stream, op.N, op.diag.as<double>(), a, b,
+  launch(ctx, jacobi_inverse_kernel, grid1(op.N), dim3(256), 0, op.N, op.diag.as<double>(), a, b,
                      dinv);
   BKTS_HIP(hipGetLastError());
 }
@@ -111,10 +111,10 @@ void scale_rows(bkts_ctx ctx, int dtype, int64_t N, int k, const double* dinv, c
   if (N * k == 0) return;
   ProfScope prof(ctx, BKTS_K_OTHER, 2.0 * N * k * esize(dtype) + 8.0 * N);
   if (dtype == BKTS_F64)
-    hipLaunchKernelGGL(scale_rows_kernel<double>, grid1(N * k), dim3(256), 0, ctx->stream, N, k, dinv,
+    launch(ctx, scale_rows_kernel<double>, grid1(N * k), dim3(256), 0, N, k, dinv,
                        static_cast<const double*>(X), static_cast<double*>(Y));
   else
-    hipLaunchKernelGGL(scale_rows_kernel<float>, grid1(N * k), dim3(256), 0, ctx->stream, N, k, dinv,
+    launch(ctx, scale_rows_kernel<float>, grid1(N * k), dim3(256), 0, N, k, dinv,
                        static_cast<const float*>(X), static_cast<float*>(Y));
   BKTS_HIP(hipGetLastError());
 }
@@ -123,23 +123,23 @@ void axpy_ds(bkts_ctx ctx, int dtype, int64_t n, const double* s, double sign, c
   if (n == 0) return;
   ProfScope prof(ctx, BKTS_K_OTHER, 3.0 * n * esize(dtype));
   if (dtype == BKTS_F64)
-    hipLaunchKernelGGL(axpy_ds_kernel<double>, grid1(n), dim3(256), 0, ctx->stream, n, s, sign,
+    launch(ctx, axpy_ds_kernel<double>, grid1(n), dim3(256), 0, n, s, sign,
                        static_cast<const double*>(X), static_cast<double*>(Y));
   else
-    hipLaunchKernelGGL(axpy_ds_kernel<float>, grid1(n), dim3(256), 0, ctx->stream, n, s, sign,
+    launch(ctx, axpy_ds_kernel<float>, grid1(n), dim3(256), 0, n, s, sign,
                        static_cast<const float*>(X), static_cast<float*>(Y));
   BKTS_HIP(hipGetLastError());
 }
 
 void hblock(bkts_ctx ctx, int k, const double* M, double* H, int ldh, int r0, int c0, bool accumulate) {
-  hipLaunchKernelGGL(hblock_kernel, dim3(1), dim3(256), 0, ctx->stream, k, M, H, ldh, r0, c0, (int)accumulate);
+  launch(ctx, hblock_kernel, dim3(1), dim3(256), 0, k, M, H, ldh, r0, c0, (int)accumulate);
   BKTS_HIP(hipGetLastError());
 }
 
 void axpby(bkts_ctx ctx, int64_t n, double a, const double* x, double b, double* y) {
   if (n == 0) return;
   ProfScope prof(ctx, BKTS_K_OTHER, 24.0 * n);
-  hipLaunchKernelGGL(axpby_kernel, grid1(n), dim3(256), 0, ctx->stream, n, a, x, b, y);
+  launch(ctx, axpby_kernel, grid1(n), dim3(256), 0, n, a, x, b, y);
   BKTS_HIP(hipGetLastError());
 }
 
