@@ -297,6 +297,80 @@ bkts_status bkts_stepper_advance(bkts_stepper st, int n_steps, const bkts_solve_
 bkts_status bkts_stepper_state(bkts_stepper st, double* y, int64_t* accepted);
 void bkts_stepper_destroy(bkts_stepper st);
 
+
+/* ---------------------------------------------------------------- serving */
+
+/* A persistent request loop for ensembles of solves (for example many permeability realisations
+ * of one problem).  A worker thread with its own stream admits requests in arrival order as soon
+ * as the HBM budget and a slot allow, keeps every admitted solve's state (operator, window, block
+ * Krylov vectors and coefficients) resident on the device, and advances all of them together:
+ * each round runs one grouped launch per block-CG kernel and block-width class over every solve
+ * inside its inner iteration, so requests that arrive while others run share those launches.
+ *
+ * A request assembles the FV operator of its grid and coefficient field and solves the
+ * all-at-once system of one window of k implicit stages from y0 (Sec. 2.1, eq.
+ * general-system-time-steps; for implicit Euler, k time steps) by the Newton/splitting iteration
+ * (eq. matrix-fixed-point-equation) until max_j ||R_j|| <= rtol ||rhs_0|| for every column j
+ * (rhs_0 = front column of B A2^T + B0).  Each correction is an FP32 block-CG solve (Jacobi) of
+ * the column-scaled FP64 residual to inner_rtol; residuals and updates are FP64.
+ *
+ * A request's result does not depend on the other requests in flight: every job keeps its own
+ * launch geometry and reduction order. */
+typedef struct bkts_server_s* bkts_server;
+
+typedef struct bkts_request {
+  bkts_grid grid;
+  const double* kappa;   /* device, one value per cell, or NULL for kappa_const */
+  double kappa_const;
+  int bc_type[6];        /* as bkts_fv_coeffs */
+  double bc_value[6];
+  const double* y0;      /* device, N values */
+  double* y_out;         /* device, N x k row-major: column j = stage j of the window */
+  int method;            /* BKTS_IE, BKTS_THETA or BKTS_SDIRK2 */
+  double theta;
+  int k;                 /* window width, 1..BKTS_MAX_K */
+  double tau;
+  double rtol;           /* outer tolerance, (0, 1) */
+  double inner_rtol;     /* FP32 block-CG per-column relative tolerance, (0, 1) */
+  int max_outer;         /* 0: 200 */
+  int max_inner;         /* per correction; 0: 2000 */
+  uint64_t tag;          /* returned in the result */
+} bkts_request;
+
+typedef struct bkts_result {
+  uint64_t ticket, tag;
+  int status;            /* BKTS_OK, BKTS_ENOCONV, BKTS_EBREAKDOWN, or the setup error */
+  int outer_iterations, krylov_iterations;
+  double rel_residual;   /* max_j ||R_j|| / ||rhs_0|| at exit */
+  double t_submit, t_admit, t_done;  /* seconds on the server clock (bkts_server_clock) */
+  size_t footprint_bytes;            /* HBM reserved for the request while it ran */
+} bkts_result;
+
+typedef struct bkts_server_stats {
+  int queued, active, done_unpolled, max_active;
+  long rounds, grouped_launches;
+  size_t bytes_in_use, bytes_peak;
+} bkts_server_stats;
+
+/* Start a server on ctx's device.  hbm_budget_bytes bounds the sum of the admitted requests'
+ * footprints; max_slots (1..256) bounds how many run at once. */
+bkts_status bkts_server_create(bkts_ctx ctx, size_t hbm_budget_bytes, int max_slots, bkts_server* out);
+/* Queue a request (non-blocking; thread-safe).  kappa, y0 and y_out must stay valid, and y0 and
+ * kappa must already hold their values (the server's stream does not wait for the caller's),
+ * until the request's result has been polled.  BKTS_EINVAL for a malformed request; BKTS_ENOMEM
+ * if it alone exceeds the budget. */
+bkts_status bkts_server_submit(bkts_server srv, const bkts_request* req, uint64_t* ticket);
+/* Move up to `max` finished results into out (non-blocking); *n_done = how many.  When a result is
+ * returned its y_out is complete.  BKTS_EDEVICE if the worker stopped on a device error. */
+bkts_status bkts_server_poll(bkts_server srv, bkts_result* out, int max, int* n_done);
+/* Block until at least n results are waiting to be polled or timeout_s passes; *n_ready = count. */
+bkts_status bkts_server_wait(bkts_server srv, int n, double timeout_s, int* n_ready);
+bkts_status bkts_server_stats_get(bkts_server srv, bkts_server_stats* out);
+/* Seconds since the server was created (the clock of bkts_result). */
+double bkts_server_clock(bkts_server srv);
+/* Finish the admitted requests, drop the queued ones, stop the worker and free everything. */
+void bkts_server_destroy(bkts_server srv);
+
 #ifdef __cplusplus
 }
 #endif

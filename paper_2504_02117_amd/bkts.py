@@ -75,6 +75,25 @@ class bkts_nl_coeffs(C.Structure):
                 ("bc_value", C.c_double * 6)]
 
 
+class bkts_request(C.Structure):
+    _fields_ = [("grid", bkts_grid), ("kappa", C.c_void_p), ("kappa_const", C.c_double), ("bc_type", C.c_int * 6),
+                ("bc_value", C.c_double * 6), ("y0", C.c_void_p), ("y_out", C.c_void_p), ("method", C.c_int),
+                ("theta", C.c_double), ("k", C.c_int), ("tau", C.c_double), ("rtol", C.c_double),
+                ("inner_rtol", C.c_double), ("max_outer", C.c_int), ("max_inner", C.c_int), ("tag", C.c_uint64)]
+
+
+class bkts_result(C.Structure):
+    _fields_ = [("ticket", C.c_uint64), ("tag", C.c_uint64), ("status", C.c_int), ("outer_iterations", C.c_int),
+                ("krylov_iterations", C.c_int), ("rel_residual", C.c_double), ("t_submit", C.c_double),
+                ("t_admit", C.c_double), ("t_done", C.c_double), ("footprint_bytes", C.c_size_t)]
+
+
+class bkts_server_stats(C.Structure):
+    _fields_ = [("queued", C.c_int), ("active", C.c_int), ("done_unpolled", C.c_int), ("max_active", C.c_int),
+                ("rounds", C.c_long), ("grouped_launches", C.c_long), ("bytes_in_use", C.c_size_t),
+                ("bytes_peak", C.c_size_t)]
+
+
 bkts_step_cb = C.CFUNCTYPE(None, C.c_int, C.c_double, C.c_void_p, C.c_void_p)
 
 _P, _I, _D, _I64 = C.c_void_p, C.c_int, C.c_double, C.c_int64
@@ -114,6 +133,13 @@ _SIGS = {
     "bkts_newton_step": (_I, [_P, _P, _P, _I, _P, _I, _I, _P, _P, C.POINTER(bkts_solve_opts),
                               C.POINTER(bkts_solve_info)]),
     "bkts_nl_stepper_create": (_I, [_P, _P, _P, _P, C.POINTER(_P)]),
+    "bkts_server_create": (_I, [_P, C.c_size_t, _I, C.POINTER(_P)]),
+    "bkts_server_submit": (_I, [_P, C.POINTER(bkts_request), C.POINTER(C.c_uint64)]),
+    "bkts_server_poll": (_I, [_P, C.POINTER(bkts_result), _I, C.POINTER(_I)]),
+    "bkts_server_wait": (_I, [_P, _I, _D, C.POINTER(_I)]),
+    "bkts_server_stats_get": (_I, [_P, C.POINTER(bkts_server_stats)]),
+    "bkts_server_clock": (_D, [_P]),
+    "bkts_server_destroy": (None, [_P]),
 }
 
 EXPORTED = tuple(_SIGS)
@@ -417,3 +443,58 @@ def bkts_nl_stepper_create(ctx, nl, tc, y0):
     out = C.c_void_p()
     _check(_lib.bkts_nl_stepper_create(ctx, nl, tc, _ptr(y0), C.byref(out)))
     return out.value
+
+
+def bkts_server_create(ctx, hbm_budget_bytes, max_slots=64):
+    out = C.c_void_p()
+    _check(_lib.bkts_server_create(ctx, int(hbm_budget_bytes), max_slots, C.byref(out)))
+    return out.value
+
+
+def make_request(n, y0, y_out, k, tau, kappa=None, kappa_const=1.0, method=BKTS_IE, theta=0.5, rtol=1e-8,
+                 inner_rtol=1e-2, bc_type=None, bc_value=None, max_outer=0, max_inner=0, tag=0):
+    """A serving request; device buffers are torch tensors (y_out: (N, k) float64)."""
+    r = bkts_request()
+    r.grid = _grid(n)
+    r.kappa = _ptr(kappa)
+    r.kappa_const = kappa_const
+    for f in range(6):
+        r.bc_type[f] = BKTS_BC_DIRICHLET if bc_type is None else int(bc_type[f])
+        r.bc_value[f] = 0.0 if bc_value is None else float(bc_value[f])
+    r.y0, r.y_out = _ptr(y0), _ptr(y_out)
+    r.method, r.theta, r.k, r.tau = method, theta, k, tau
+    r.rtol, r.inner_rtol, r.max_outer, r.max_inner, r.tag = rtol, inner_rtol, max_outer, max_inner, tag
+    return r
+
+
+def bkts_server_submit(srv, req):
+    t = C.c_uint64()
+    _check(_lib.bkts_server_submit(srv, C.byref(req), C.byref(t)))
+    return t.value
+
+
+def bkts_server_poll(srv, max_results=64):
+    buf = (bkts_result * max_results)()
+    n = C.c_int()
+    _check(_lib.bkts_server_poll(srv, buf, max_results, C.byref(n)))
+    return [buf[i] for i in range(n.value)]
+
+
+def bkts_server_wait(srv, n, timeout_s):
+    r = C.c_int()
+    _check(_lib.bkts_server_wait(srv, n, timeout_s, C.byref(r)))
+    return r.value
+
+
+def bkts_server_stats_get(srv):
+    s = bkts_server_stats()
+    _check(_lib.bkts_server_stats_get(srv, C.byref(s)))
+    return s
+
+
+def bkts_server_clock(srv):
+    return _lib.bkts_server_clock(srv)
+
+
+def bkts_server_destroy(srv):
+    _lib.bkts_server_destroy(srv)

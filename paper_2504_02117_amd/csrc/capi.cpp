@@ -5,6 +5,7 @@
 #include "advance.hpp"
 #include "internal.hpp"
 #include "krylov.hpp"
+#include "server.hpp"
 #include "timecoupling.hpp"
 #include "vecops.hpp"
 
@@ -468,5 +469,57 @@ void bkts_stepper_destroy(bkts_stepper st) {
   (void)hipStreamSynchronize(st->ctx->stream);
   delete st;
 }
+
+
+bkts_status bkts_server_create(bkts_ctx ctx, size_t hbm_budget_bytes, int max_slots, bkts_server* out) {
+  BKTS_API_BEGIN
+  check_ctx(ctx);
+  BKTS_REQUIRE(out, "out must not be NULL");
+  *out = nullptr;
+  BKTS_REQUIRE(max_slots >= 1 && max_slots <= 256, "max_slots must be in 1..256");
+  BKTS_REQUIRE(hbm_budget_bytes > 0, "hbm_budget_bytes must be > 0");
+  set_device(ctx);
+  *out = new bkts_server_s(ctx->device, hbm_budget_bytes, max_slots);
+  BKTS_API_END
+}
+
+bkts_status bkts_server_submit(bkts_server srv, const bkts_request* req, uint64_t* ticket) {
+  BKTS_API_BEGIN
+  BKTS_REQUIRE(srv && req, "srv and req must not be NULL");
+  const uint64_t t = srv->submit(*req);
+  if (ticket) *ticket = t;
+  BKTS_API_END
+}
+
+bkts_status bkts_server_poll(bkts_server srv, bkts_result* out, int max, int* n_done) {
+  BKTS_API_BEGIN
+  BKTS_REQUIRE(srv && n_done, "srv and n_done must not be NULL");
+  BKTS_REQUIRE(max >= 0 && (out || max == 0), "out must hold max results");
+  *n_done = srv->poll(out, max);
+  {
+    std::lock_guard<std::mutex> g(srv->mu);
+    if (srv->fatal && *n_done == 0) throw Error{BKTS_EDEVICE, "server stopped: " + srv->fatal_msg};
+  }
+  BKTS_API_END
+}
+
+bkts_status bkts_server_wait(bkts_server srv, int n, double timeout_s, int* n_ready) {
+  BKTS_API_BEGIN
+  BKTS_REQUIRE(srv, "srv must not be NULL");
+  const int r = srv->wait(n, timeout_s);
+  if (n_ready) *n_ready = r;
+  BKTS_API_END
+}
+
+bkts_status bkts_server_stats_get(bkts_server srv, bkts_server_stats* out) {
+  BKTS_API_BEGIN
+  BKTS_REQUIRE(srv && out, "srv and out must not be NULL");
+  *out = srv->stats();
+  BKTS_API_END
+}
+
+double bkts_server_clock(bkts_server srv) { return srv ? srv->now() : 0.0; }
+
+void bkts_server_destroy(bkts_server srv) { delete srv; }
 
 }  // extern "C"

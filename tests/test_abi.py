@@ -96,3 +96,19 @@ def test_null_handles_rejected():
     assert lib.bkts_spmm(None, None, 0, 4, 0.0, 1.0, None, 4, None, 4) == bkts.BKTS_EINVAL
     assert lib.bkts_ctx_synchronize(None) == bkts.BKTS_EINVAL
     assert "ctx" in bkts.bkts_last_error()
+
+
+def test_server_null_handles_rejected():
+    import ctypes as C
+    from paper_2504_02117_amd import bkts
+    lib = bkts._lib
+    out = C.c_void_p()
+    assert lib.bkts_server_create(None, 1 << 30, 8, C.byref(out)) == bkts.BKTS_EINVAL
+    req = bkts.bkts_request()
+    t = C.c_uint64()
+    assert lib.bkts_server_submit(None, C.byref(req), C.byref(t)) == bkts.BKTS_EINVAL
+    n = C.c_int()
+    assert lib.bkts_server_poll(None, None, 0, C.byref(n)) == bkts.BKTS_EINVAL
+    assert lib.bkts_server_clock(None) == 0.0
+    lib.bkts_server_destroy(None)
+    assert lib.bkts_nlop_create(None, None, None, C.byref(out)) == bkts.BKTS_EINVAL
