@@ -45,6 +45,11 @@ def parse():
     p.add_argument("--cpu-steps", type=int, default=1)
     p.add_argument("--calibrate-copy", action="store_true",
                    help="first run 3 plain 256 MiB device copies (reference dispatches for HBM counters)")
+    p.add_argument("--serve-requests", type=int, default=512,
+                   help="serving leg: Poisson-arrival requests (0 = skip)")
+    p.add_argument("--serve-rate", type=float, default=200.0, help="mean arrivals per second")
+    p.add_argument("--serve-budget-gib", type=float, default=4.0)
+    p.add_argument("--serve-slots", type=int, default=64)
     p.add_argument("--sweep", type=str, default="1f32,4f64,8,16,32",
                    help="comma list of extra block forms to time: <k>[f32|f64] (default precision: --precision)")
     return p.parse_args()
@@ -144,6 +149,87 @@ def run_form(torch, bkts, ctx, op, y0, k, precision, inner_rtol, warmup, steps, 
         bkts.bkts_tc_destroy(tc)
 
 
+def run_serving(torch, bkts, ctx, a):
+    """Replay a seeded Poisson trace of heterogeneous 2-D diffusion solves through the serving loop."""
+    import numpy as np
+
+    from paper_2504_02117_amd import inputs
+    rng = np.random.default_rng(0)
+    m = a.serve_requests
+    gaps = rng.exponential(1.0 / a.serve_rate, m)
+    arrivals = np.cumsum(gaps) - gaps[0]
+    sizes = rng.choice([64, 128, 256, 512], m)
+    widths = rng.choice([4, 8, 16, 32], m)
+    reqs = []
+    log(f"serving: building {m} requests")
+    y0s = {}
+    for i in range(m):
+        n = (int(sizes[i]), int(sizes[i]))
+        if n not in y0s:
+            y0s[n] = torch.from_numpy(inputs.sin_product(n)).cuda()
+        kd = torch.from_numpy(inputs.lognormal_field(n, 0.0, 2.0, 8.0, 1000 + i)).cuda()
+        out = torch.empty((n[0] * n[1], int(widths[i])), dtype=torch.float64, device="cuda")
+        reqs.append((n, kd, out))
+    torch.cuda.synchronize()
+    srv = bkts.bkts_server_create(ctx, int(a.serve_budget_gib * (1 << 30)), a.serve_slots)
+    results = {}
+    try:
+        t0 = bkts.bkts_server_clock(srv)
+        tickets = {}
+        for i, (n, kd, out) in enumerate(reqs):
+            while bkts.bkts_server_clock(srv) < t0 + arrivals[i]:
+                for r in bkts.bkts_server_poll(srv):
+                    results[r.ticket] = r
+                time.sleep(min(5e-4, max(0.0, t0 + arrivals[i] - bkts.bkts_server_clock(srv))))
+            req = bkts.make_request(n, y0s[n], out, int(widths[i]), 1e-3, kappa=kd, rtol=1e-8, inner_rtol=1e-2,
+                                    tag=i)
+            tickets[bkts.bkts_server_submit(srv, req)] = i
+        while len(results) < m:
+            bkts.bkts_server_wait(srv, 1, 1.0)
+            for r in bkts.bkts_server_poll(srv):
+                results[r.ticket] = r
+        st = bkts.bkts_server_stats_get(srv)
+    finally:
+        bkts.bkts_server_destroy(srv)
+    lat, wait, work, bad = [], [], [], 0
+    elem_it, outer_tot = 0.0, 0
+    t_end = 0.0
+    for t, r in results.items():
+        i = tickets[t]
+        arr = t0 + arrivals[i]
+        lat.append(r.t_done - arr)
+        wait.append(r.t_admit - arr)
+        t_end = max(t_end, r.t_done)
+        bad += r.status != 0
+        work.append(sizes[i] ** 2 * widths[i])
+        elem_it += float(r.krylov_iterations) * sizes[i] ** 2 * widths[i]
+        outer_tot += r.outer_iterations
+    makespan = t_end - t0
+    # oracle check of the smallest requests of the trace
+    from oracle import fv, stepping
+    errs = []
+    for i in [j for j in range(m) if sizes[j] == 64][:2]:
+        n, kd, out = reqs[i]
+        K, b = fv.assemble_linear(n, kappa=kd.cpu().numpy())
+        ys, _ = stepping.dirk_linear(K, b, y0s[n].cpu().numpy(), 1e-3, "ie", int(widths[i]))
+        got = out.cpu().numpy()
+        errs.append(max(np.linalg.norm(got[:, j] - ys[j + 1]) / np.linalg.norm(ys[j + 1]) for j in range(widths[i])))
+    return {"requests": m, "failed": int(bad), "rate_per_s": a.serve_rate, "makespan_s": makespan,
+            "throughput_dof_timesteps_per_s": float(np.sum(work)) / makespan,
+            "latency_p50_ms": 1e3 * float(np.percentile(lat, 50)), "latency_p99_ms": 1e3 * float(np.percentile(lat, 99)),
+            "queue_wait_p50_ms": 1e3 * float(np.percentile(wait, 50)),
+            "queue_wait_p99_ms": 1e3 * float(np.percentile(wait, 99)),
+            "rounds": st.rounds, "grouped_launches": st.grouped_launches, "max_active": st.max_active,
+            "mean_outer_iterations": outer_tot / m,
+            "krylov_element_iterations": elem_it,
+            "inner_stream_GBps": 44.0 * elem_it / makespan / 1e9,
+            "hbm_budget_bytes": int(a.serve_budget_gib * (1 << 30)), "hbm_peak_reserved_bytes": st.bytes_peak,
+            "oracle_max_rel_err_sampled": max(errs) if errs else None,
+            "workload": "2-D lognormal diffusion (log-std 2, corr. 8 cells, seed 1000+i), n in {64,128,256,512}, "
+                        "k in {4,8,16,32}, implicit Euler tau=1e-3, one window of k steps per request, "
+                        "FP32 block CG inside FP64 Newton to 1e-8, Poisson arrivals"}
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -215,6 +301,13 @@ def main():
         if "spmm" in blk["kernels"]:
             spmm_roof = roofline_of(blk["kernels"], "spmm", a.k, a.precision)
 
+    serving = None
+    if a.serve_requests > 0:
+        serving = run_serving(torch, bkts, ctx, a)
+        log(f"  serving: {serving['throughput_dof_timesteps_per_s']:.4g} DOF*steps/s, p50 "
+            f"{serving['latency_p50_ms']:.1f} ms, p99 {serving['latency_p99_ms']:.1f} ms, "
+            f"makespan {serving['makespan_s']:.1f} s")
+
     cpu = None
     err = None
     if not a.no_cpu or result_hist is not None:
@@ -258,6 +351,7 @@ def main():
         "spmm_roofline": spmm_roof,
         "kernels": blk["kernels"],
         "cpu_baseline": cpu,
+        "serving": serving,
     }
     print(json.dumps(out))
     bkts.bkts_op_destroy(op)

@@ -10,6 +10,7 @@
 // a fixed order, so results are bitwise reproducible.
 #include "devcommon.hpp"
 #include "internal.hpp"
+#include "wide.hpp"
 
 namespace bkts {
 namespace {
@@ -439,6 +440,9 @@ void colnorms2(bkts_ctx ctx, int dtype, int64_t N, int k, const void* X, int ldx
 void cg_update(bkts_ctx ctx, int dtype, int64_t N, int k, void* X, const void* P, void* R, const void* Q,
                const double* alpha, const double* dinv, double* gamma,
                double* Tm, double* nrm) {
+  if (wide_eligible(dtype, k))
+    return w_cg_update(ctx, N, k, static_cast<float*>(X), static_cast<const float*>(P), static_cast<float*>(R),
+                       static_cast<const float*>(Q), alpha, dinv, gamma, Tm, nrm);
   if (mf_eligible(k)) return mf_cg_update(ctx, dtype, N, k, X, P, R, Q, alpha, dinv, gamma,
                                           Tm, nrm);
   if (rk_eligible(k)) return rk_cg_update(ctx, dtype, N, k, X, P, R, Q, alpha, dinv, gamma, Tm, nrm);
@@ -452,6 +456,8 @@ void cg_update(bkts_ctx ctx, int dtype, int64_t N, int k, void* X, const void* P
 
 void cg_pupdate(bkts_ctx ctx, int dtype, int64_t N, int k, void* P, const void* R, const double* beta,
                 const double* dinv) {
+  if (wide_eligible(dtype, k))
+    return w_cg_pupdate(ctx, N, k, static_cast<float*>(P), static_cast<const float*>(R), beta, dinv);
   if (mf_eligible(k)) return mf_cg_pupdate(ctx, dtype, N, k, P, R, beta, dinv);
   if (rk_eligible(k)) return rk_cg_pupdate(ctx, dtype, N, k, P, R, beta, dinv);
   if (dtype == BKTS_F64)

@@ -15,6 +15,7 @@
 #include <cstring>
 
 #include "vecops.hpp"
+#include "wide.hpp"
 
 namespace bkts {
 
@@ -24,6 +25,14 @@ struct Small {
   double *G, *gamma, *T, *alpha, *beta, *nrm, *nrm0;
   int* ndefl;
 };
+
+// Gram matrices inside the inner iteration: FP32 blocks of 5 or more columns use the FP32 matrix
+// cores (per-tile FP32 sums, FP64 across tiles); everything else the exact-FP64 kernels.
+void inner_gram(bkts_ctx ctx, int dtype, int64_t N, int k, const void* X, const void* Y, double* G) {
+  if (wide_eligible(dtype, k))
+    return w_gram(ctx, N, k, static_cast<const float*>(X), static_cast<const float*>(Y), G);
+  gram(ctx, dtype, N, k, X, k, Y, k, G);
+}
 
 Small small_bufs(bkts_ctx ctx, const std::string& tag, int k) {
   const size_t kk = (size_t)k * k;
@@ -98,7 +107,7 @@ void block_cg(bkts_ctx ctx, const bkts_op_s& op, int dtype, int k, double a, dou
   if (st.converged) return;
 
   cg_pupdate(ctx, dtype, N, k, P, R, nullptr, dK);
-  gram(ctx, dtype, N, k, R, k, P, k, s.gamma);
+  inner_gram(ctx, dtype, N, k, R, P, s.gamma);
   // Convergence is read back one iteration late: the norms of iteration it are copied to pinned
   // memory behind an event while iteration it+1 is already enqueued, so the GPU never waits for
   // the host.  Stopping one iteration after the test passes only adds a valid CG step.
@@ -128,7 +137,7 @@ void block_cg(bkts_ctx ctx, const bkts_op_s& op, int dtype, int k, double a, dou
       rk_spmm_gram(ctx, op, dtype, k, a, P, b, Q, s.G);
     } else {
       spmm(ctx, op, dtype, k, 0.0, nullptr, k, a, P, k, b, Q, k);
-      gram(ctx, dtype, N, k, P, k, Q, k, s.G);
+      inner_gram(ctx, dtype, N, k, P, Q, s.G);
     }
     small_spd_solve(ctx, k, s.G, s.gamma, 1.0, eps, s.alpha, s.ndefl);
     cg_update(ctx, dtype, N, k, X, P, R, Q, s.alpha, dK, s.gamma, s.T, s.nrm);
@@ -149,7 +158,7 @@ void block_cg(bkts_ctx ctx, const bkts_op_s& op, int dtype, int k, double a, dou
     if (state == -1) {  // every search direction collapsed: restart from the preconditioned residual
       if (++restarts > 3) throw Error{BKTS_EBREAKDOWN, "block CG: search space collapsed repeatedly"};
       cg_pupdate(ctx, dtype, N, k, P, R, nullptr, dK);
-      gram(ctx, dtype, N, k, R, k, P, k, s.gamma);
+      inner_gram(ctx, dtype, N, k, R, P, s.gamma);
       continue;
     }
     restarts = 0;

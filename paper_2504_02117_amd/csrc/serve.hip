@@ -231,7 +231,7 @@ __global__ __launch_bounds__(256) void g_finalize_kernel(const GJob* __restrict_
   if (threadIdx.x == 0) *out = s[0];
 }
 
-__global__ __launch_bounds__(64) void g_solve_kernel(const GJob* __restrict__ jobs, const int* ids, int mode,
+__global__ __launch_bounds__(256) void g_solve_kernel(const GJob* __restrict__ jobs, const int* ids, int mode,
                                                      double eps) {
   __shared__ dev::SolveLds sm;
   const GJob& J = jobs[ids[blockIdx.x]];
@@ -252,6 +252,13 @@ __global__ void scales_kernel(int k, const double* nrm2, double* sc, double* sp)
 }  // namespace
 
 int gjob_slots(int64_t N, int kp, int64_t* tps) {
+  if (kp >= 16) {  // matrix-core kernels: 16-row tiles, about eight per workgroup
+    const int64_t t16 = (N + 15) / 16;
+    int64_t ns = (t16 + 7) / 8;
+    ns = ns < 1 ? 1 : (ns > 1024 ? 1024 : ns);
+    *tps = (t16 + ns - 1) / ns;
+    return (int)ns;
+  }
   const int64_t rt = 2048 / kp;
   const int64_t ntiles = (N + rt - 1) / rt;
   int64_t ns = ntiles < 512 ? ntiles : 512;
@@ -296,7 +303,7 @@ void g_finalize(bkts_ctx ctx, int mode, const GJob* jobs, GList l) {
 
 void g_solve(bkts_ctx ctx, int mode, double eps, const GJob* jobs, GList l) {
   if (l.n == 0) return;
-  launch(ctx, g_solve_kernel, dim3(l.n), dim3(64), 0, jobs, l.ids, mode, eps);
+  launch(ctx, g_solve_kernel, dim3(l.n), dim3(dev::kSolveThreads), 0, jobs, l.ids, mode, eps);
   BKTS_HIP(hipGetLastError());
 }
 

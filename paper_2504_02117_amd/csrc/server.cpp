@@ -19,6 +19,7 @@
 #include "serve.hpp"
 #include "timecoupling.hpp"
 #include "vecops.hpp"
+#include "wide.hpp"
 
 namespace bkts {
 bkts_op fv_assemble(bkts_ctx ctx, const bkts_grid* grid, const bkts_fv_coeffs* c, int format);
@@ -31,7 +32,8 @@ namespace {
 
 constexpr int kStatusStride = 4 * BKTS_MAX_K;  // doubles per slot: nrm64 | nrm | nrm0 | ndefl
 
-int kp_of(int k) { return k <= 1 ? 1 : k <= 2 ? 2 : k <= 4 ? 4 : k <= 8 ? 8 : k <= 16 ? 16 : 32; }
+// Padded width of a job: row-tile kernels up to 4 columns, the FP32 matrix-core kernels beyond.
+int kp_of(int k) { return k <= 1 ? 1 : k <= 2 ? 2 : k <= 4 ? 4 : wide_kp(k); }
 
 int64_t grid_cells(const bkts_grid& g) {
   int64_t n = 1;
@@ -431,16 +433,29 @@ void bkts_server_s::round() {
     const GJob* dj = table_dev.as<GJob>();
     const double eps = 1e-6;
     long nl = 0;
+    // widths 16 and 32 run on the FP32 matrix cores, narrower ones on row tiles
     for (int c = 0; c < 6; ++c)
-      if (has[c]) g_spmm_gram(ctx, classes[c], dj, cl[c]), ++nl;
+      if (has[c]) {
+        if (classes[c] >= 16) gw_spmm_gram(ctx, classes[c] / 16, dj, cl[c]);
+        else g_spmm_gram(ctx, classes[c], dj, cl[c]);
+        ++nl;
+      }
     g_finalize(ctx, 0, dj, lg);
     g_solve(ctx, 0, eps, dj, ls);
     for (int c = 0; c < 6; ++c)
-      if (has[c]) g_update(ctx, classes[c], dj, cl[c]), ++nl;
+      if (has[c]) {
+        if (classes[c] >= 16) gw_update(ctx, classes[c] / 16, dj, cl[c]);
+        else g_update(ctx, classes[c], dj, cl[c]);
+        ++nl;
+      }
     g_finalize(ctx, 1, dj, lu);
     g_solve(ctx, 1, eps, dj, ls);
     for (int c = 0; c < 6; ++c)
-      if (has[c]) g_pupdate(ctx, classes[c], dj, cl[c]), ++nl;
+      if (has[c]) {
+        if (classes[c] >= 16) gw_pupdate(ctx, classes[c] / 16, dj, cl[c]);
+        else g_pupdate(ctx, classes[c], dj, cl[c]);
+        ++nl;
+      }
     nl += 4;
     std::lock_guard<std::mutex> g(mu);
     grouped_launches += nl;

@@ -1,5 +1,5 @@
-// Truncated (deflating) Cholesky solve of a k x k Gram system on one workgroup, shared by the
-// block-CG solver and the grouped serving kernels.
+// Deflating solve of a k x k Gram system on one workgroup, shared by the block-CG solver and the
+// grouped serving kernels.
 #pragma once
 
 #include "devcommon.hpp"
@@ -9,74 +9,76 @@ namespace bkts {
 namespace dev {
 
 constexpr int KM = BKTS_MAX_K;
+constexpr int kSolveThreads = 256;
 
 struct SolveLds {
-  double L[KM][KM + 1];
-  double Y[KM][KM + 1];
-  double sc[KM];
+  double M[KM][2 * KM + 1];  // augmented [G | S], Jacobi scaled
+  double d[KM];
   int active[KM];
 };
 
-// out = sign * G^+ S for k x k row-major G, S (device or LDS), run by threads 0..63 of the block
-// (the others pass the barriers).  G^+ inverts the symmetric part of G restricted to the
-// directions that survive a Cholesky factorisation of the Jacobi-scaled matrix D^-1/2 G D^-1/2: a
-// pivot below `eps` (relative; the scaled matrix has unit diagonal) marks its direction as
-// numerically dependent on the earlier ones, and that row and column are dropped.
+// out = sign * G^+ S for k x k row-major G, S in device memory, run by all kSolveThreads threads
+// of the block.  G^+ inverts the symmetric part of G on the directions that survive symmetric
+// elimination of the Jacobi-scaled matrix D G D (D = diag(G)^-1/2, unit diagonal) in index order:
+// a pivot (the Schur-complement diagonal, i.e. the squared Cholesky pivot) below `eps` marks its
+// direction as numerically dependent on the earlier ones, and that row and column are dropped
+// (the corresponding rows of the result are zero).  Gauss-Jordan on [D G D | D S] keeps every
+// step a parallel update of the whole augmented matrix, with two barriers per pivot.
 __device__ inline void spd_solve_dev(int k, const double* Gin, const double* S, double sign, double eps, double* out,
-                              int* ndefl, SolveLds& sm) {
+                                     int* ndefl, SolveLds& sm) {
   const int t = threadIdx.x;
-  for (int e = t; e < k * k; e += blockDim.x) {
+  const int w2 = 2 * k;
+  for (int e = t; e < k * k; e += kSolveThreads) {
     const int i = e / k, j = e % k;
-    sm.L[i][j] = 0.5 * (Gin[i * k + j] + Gin[j * k + i]);
+    sm.M[i][j] = 0.5 * (Gin[i * k + j] + Gin[j * k + i]);
+    sm.M[i][k + j] = S[i * k + j];
   }
   __syncthreads();
   if (t < k) {
-    const double d = sm.L[t][t];
-    const bool ok = d > 0.0 && isfinite(d);
-    sm.sc[t] = ok ? rsqrt(d) : 0.0;
+    const double g = sm.M[t][t];
+    const bool ok = g > 0.0 && isfinite(g);
+    sm.d[t] = ok ? rsqrt(g) : 0.0;
     sm.active[t] = ok ? 1 : 0;
   }
   __syncthreads();
-  for (int e = t; e < k * k; e += blockDim.x) {
-    const int i = e / k, j = e % k;
-    sm.L[i][j] *= sm.sc[i] * sm.sc[j];
+  for (int e = t; e < k * w2; e += kSolveThreads) {
+    const int i = e / w2, c = e % w2;
+    sm.M[i][c] *= c < k ? sm.d[i] * sm.d[c] : sm.d[i];
   }
   __syncthreads();
-  for (int j = 0; j < k; ++j) {  // right-looking Cholesky of the lower triangle, with deflation
-    if (t == 0) {
-      const double p = sm.L[j][j];
-      if (!sm.active[j] || !(p > eps)) {
-        sm.active[j] = 0;
-        sm.L[j][j] = 1.0;
-      } else {
-        sm.L[j][j] = sqrt(p);
+  constexpr int EPT = (KM * 2 * KM + kSolveThreads - 1) / kSolveThreads;  // elements per thread
+  for (int j = 0; j < k; ++j) {
+    const double p = sm.M[j][j];
+    const bool keep = sm.active[j] && p > eps;
+    const double rp = keep ? 1.0 / p : 0.0;
+    double nv[EPT];
+#pragma unroll
+    for (int q = 0; q < EPT; ++q) {
+      const int e = t + q * kSolveThreads;
+      nv[q] = 0.0;
+      if (e < k * w2) {
+        const int i = e / w2, c = e % w2;
+        const double mic = sm.M[i][c];
+        if (!keep)
+          nv[q] = (i == j || c == j) ? 0.0 : mic;
+        else if (i == j)
+          nv[q] = mic * rp;
+        else
+          nv[q] = mic - sm.M[i][j] * (sm.M[j][c] * rp);
       }
     }
     __syncthreads();
-    const bool aj = sm.active[j];
-    for (int i = j + 1 + t; i < k; i += blockDim.x) sm.L[i][j] = aj ? sm.L[i][j] / sm.L[j][j] : 0.0;
-    __syncthreads();
-    if (aj) {
-      for (int e = t; e < k * k; e += blockDim.x) {
-        const int i = e / k, l = e % k;
-        if (i > j && l > j && l <= i) sm.L[i][l] -= sm.L[i][j] * sm.L[l][j];
-      }
+#pragma unroll
+    for (int q = 0; q < EPT; ++q) {
+      const int e = t + q * kSolveThreads;
+      if (e < k * w2) sm.M[e / w2][e % w2] = nv[q];
     }
+    if (t == 0 && !keep) sm.active[j] = 0;
     __syncthreads();
   }
-  if (t < k) {  // solve (L L^T) y = D^-1/2 S[:, c] for the column c = t
-    const int c = t;
-    for (int i = 0; i < k; ++i) {
-      double v = sm.active[i] ? sm.sc[i] * S[i * k + c] : 0.0;
-      for (int l = 0; l < i; ++l) v -= sm.L[i][l] * sm.Y[l][c];
-      sm.Y[i][c] = sm.active[i] ? v / sm.L[i][i] : 0.0;
-    }
-    for (int i = k - 1; i >= 0; --i) {
-      double v = sm.Y[i][c];
-      for (int l = i + 1; l < k; ++l) v -= sm.L[l][i] * sm.Y[l][c];
-      sm.Y[i][c] = sm.active[i] ? v / sm.L[i][i] : 0.0;
-    }
-    for (int i = 0; i < k; ++i) out[i * k + c] = sign * sm.sc[i] * sm.Y[i][c];
+  for (int e = t; e < k * k; e += kSolveThreads) {
+    const int i = e / k, c = e % k;
+    out[e] = sm.active[i] ? sign * sm.d[i] * sm.M[i][k + c] : 0.0;
   }
   if (t == 0 && ndefl) {
     int nd = 0;
