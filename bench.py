@@ -28,6 +28,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+TIMER_PERIOD = 8  # time every 8th launch of each kernel (keeps the event overhead off the loop)
 
 
 def parse():
@@ -43,6 +44,8 @@ def parse():
     p.add_argument("--no-plain", action="store_true")
     p.add_argument("--no-cpu", action="store_true")
     p.add_argument("--cpu-steps", type=int, default=1)
+    p.add_argument("--no-kernel-timers", action="store_true",
+                   help="time the block form without the in-library kernel timers (no roofline)")
     p.add_argument("--calibrate-copy", action="store_true",
                    help="first run 3 plain 256 MiB device copies (reference dispatches for HBM counters)")
     p.add_argument("--serve-requests", type=int, default=512,
@@ -92,7 +95,8 @@ def roofline_of(kt, cat, k, precision):
     return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_for(name, precision, k), "kernel": name,
             "category": cat, "algorithmic_bytes_per_launch": bpl, "avg_launch_us": v["avg_us"],
-            "launches": v["launches"], "share_of_kernel_time": v["share"]}
+            "timed_launches": v["launches"], "timer_period": TIMER_PERIOD,
+            "share_of_kernel_time": v["share"]}
 
 
 def traffic_for(kernel, precision, k):
@@ -135,7 +139,7 @@ def run_form(torch, bkts, ctx, op, y0, k, precision, inner_rtol, warmup, steps, 
         if warmup:
             bkts.bkts_stepper_advance(st, warmup, inner=inner, outer_rtol=1e-8, max_outer=400)
         hist = torch.empty((steps, N), dtype=torch.float64, device="cuda")
-        bkts.bkts_profile_enable(ctx, profile)
+        bkts.bkts_profile_enable(ctx, profile, period=TIMER_PERIOD)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         info = bkts.bkts_stepper_advance(st, steps, inner=inner, outer_rtol=1e-8, max_outer=400, y_hist=hist)
@@ -258,7 +262,8 @@ def main():
     _, nnz = bkts.bkts_op_info(op)
 
     log(f"block form k={a.k} {a.precision}: warmup {a.warmup}, timed {a.steps}")
-    blk = run_form(torch, bkts, ctx, op, y0, a.k, a.precision, a.inner_rtol, a.warmup, a.steps, True)
+    blk = run_form(torch, bkts, ctx, op, y0, a.k, a.precision, a.inner_rtol, a.warmup, a.steps,
+                   not a.no_kernel_timers)
     log(f"  {blk['value']:.4g} DOF*steps/s, outer={blk['info'].outer_iterations} "
         f"krylov={blk['info'].krylov_iterations}")
     result_hist = blk["hist"][-2:].double().cpu().numpy() if a.steps >= 2 else None

@@ -76,12 +76,15 @@ bkts_status bkts_ctx_synchronize(bkts_ctx ctx);
 const char* bkts_last_error(void);
 const char* bkts_version(void);
 
-/* Per-kernel device timers.  When enabled, every launch of the kernels below is
- * bracketed by HIP events on the context stream and its algorithmic bytes (the
- * traffic the kernel must move by its definition, e.g. for the block operator
- * nnz*(s+4) + 4(N+1) + 2*N*k*s with s the element size) are accumulated.
- * bkts_profile_enable(ctx, 1) resets the counters; bkts_profile_query
- * synchronises and returns the totals for one kernel id. */
+/* Per-kernel device timers.  When enabled, timed launches of the kernels below
+ * carry HIP events in their dispatch (the interval is the kernel's own
+ * execution), and their algorithmic bytes (the traffic the kernel must move by
+ * its definition, e.g. for the block operator nnz*(s+4) + 4(N+1) + 2*N*k*s with
+ * s the element size) are accumulated.  bkts_profile_enable(ctx, n) resets the
+ * counters and times every launch (n = 1) or every n-th launch of each kernel
+ * id (n > 1, to keep the event overhead off the host path); n = 0 disables.
+ * bkts_profile_query synchronises and returns the totals over the timed
+ * launches of one kernel id. */
 enum {
   BKTS_K_SPMM = 0,       /* block operator Y = aX + bKX                      */
   BKTS_K_GRAM = 1,       /* X^T Y                                             */

@@ -336,8 +336,9 @@ def bkts_advance(ctx, op, tc, y, n_steps, inner=None, outer_rtol=1e-8, max_outer
     return info
 
 
-def bkts_profile_enable(ctx, enable=True):
-    _check(_lib.bkts_profile_enable(ctx, 1 if enable else 0))
+def bkts_profile_enable(ctx, enable=True, period=1):
+    """Enable the per-kernel timers on every `period`-th launch of each kernel id (or disable)."""
+    _check(_lib.bkts_profile_enable(ctx, max(1, int(period)) if enable else 0))
 
 
 def bkts_profile_query(ctx, kernel):

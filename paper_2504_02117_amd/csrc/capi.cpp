@@ -293,7 +293,9 @@ bkts_status bkts_profile_enable(bkts_ctx ctx, int enable) {
   ctx->sync();
   ctx->prof.resolve();
   ctx->prof.reset();
+  BKTS_REQUIRE(enable >= 0, "enable must be >= 0");
   ctx->prof.enabled = enable != 0;
+  ctx->prof.period = enable > 1 ? enable : 1;
   BKTS_API_END
 }
 

@@ -75,6 +75,7 @@ void Profiler::resolve() {
 
 void Profiler::reset() {
   for (auto& a : acc) a = Acc{};
+  for (auto& s : seq) s = 0;
 }
 
 Profiler::~Profiler() {
@@ -88,6 +89,7 @@ Profiler::~Profiler() {
 ProfScope::ProfScope(bkts_ctx c, int k, double bytes) : ctx(c), kid(k) {
   if (!ctx->prof.enabled) return;
   Profiler& p = ctx->prof;
+  if (p.seq[k]++ % p.period != 0) return;  // not a sampled launch
   if (p.pending.size() > 8192 && p.open == 0) p.resolve();  // only when every event is recorded
   if (p.ext_a) {  // an enclosing scope has not launched its kernel: record its events as empty
     BKTS_HIP(hipEventRecord(p.ext_a, ctx->stream));
@@ -128,6 +130,15 @@ int blocks_per_cu(const void* kernel) {
 }
 
 }  // namespace bkts
+
+unsigned* bkts_ctx_s::tail_counter(int i) {
+  constexpr int kCounters = 16;
+  if (!tail_counters.p) {
+    tail_counters.alloc(sizeof(unsigned) * kCounters);
+    BKTS_HIP(hipMemsetAsync(tail_counters.p, 0, sizeof(unsigned) * kCounters, stream));
+  }
+  return tail_counters.as<unsigned>() + (i % kCounters);
+}
 
 double* bkts_ctx_s::host_stage(size_t count) {
   size_t bytes = count * sizeof(double);

@@ -86,6 +86,8 @@ struct Profiler {
     double bytes = 0.0;
   };
   bool enabled = false;
+  int period = 1;                      // time every period-th launch of each kernel id
+  int64_t seq[BKTS_K_COUNT] = {};      // launches seen per kernel id since enabling
   int open = 0;  // scopes whose end event is not recorded yet (they nest)
   // Events of the innermost scope waiting for its kernel: the next launch() carries them in its
   // dispatch packet, so their interval is that kernel's own execution (no queue gaps).
@@ -108,6 +110,8 @@ struct bkts_ctx_s {
   double* h_pinned = nullptr;  // pinned host staging for small read-backs
   size_t h_pinned_bytes = 0;
   bkts::Profiler prof;
+  bkts::DevBuf tail_counters;  // zero-initialised device words for fold+solve launches
+  unsigned* tail_counter(int i);
   double* host_stage(size_t count);  // pinned buffer of at least `count` doubles
   void sync();
 };
@@ -233,12 +237,29 @@ struct FoldSet {
 };
 void finalize_sets(bkts_ctx ctx, int nblocks, int k, const FoldSet* sets, int nsets);
 
+// Coefficient step after a block-CG kernel in ONE launch: fold the kernel's partials in a fixed
+// order (one workgroup per entry) and let the last workgroup solve the k x k system.  After the SpMM: G and alpha = G^+ gamma_in
+// (and the deflation count).  After the update: gamma, T, nrm and beta = -G^+ T.
+struct CgTail {
+  unsigned* counter = nullptr;  // device word, zero between launches
+  double eps = 0.0;
+  double* G = nullptr;
+  const double* gamma_in = nullptr;
+  double* alpha = nullptr;
+  int* ndefl = nullptr;
+  double* gamma = nullptr;
+  double* T = nullptr;
+  double* nrm = nullptr;
+  double* beta = nullptr;
+};
+
 // Row-per-thread block kernels for k in {1, 2, 4} (rowk.hip); contiguous blocks (ld = k).
 bool rk_eligible(int k);
 void rk_spmm_gram(bkts_ctx ctx, const bkts_op_s& op, int dtype, int k, double alpha, const void* P, double beta,
-                  void* Q, double* G);  // Q = alpha P + beta K P, G = P^T Q
+                  void* Q, double* G, const CgTail* tail = nullptr);  // Q = alpha P + beta K P, G = P^T Q
 void rk_cg_update(bkts_ctx ctx, int dtype, int64_t N, int k, void* X, const void* P, void* R, const void* Q,
-                  const double* alpha, const double* dinv, double* gamma, double* Tm, double* nrm);
+                  const double* alpha, const double* dinv, double* gamma, double* Tm, double* nrm,
+                  const CgTail* tail = nullptr);
 void rk_cg_pupdate(bkts_ctx ctx, int dtype, int64_t N, int k, void* P, const void* R, const double* beta,
                    const double* dinv);
 void rk_gram(bkts_ctx ctx, int dtype, int64_t N, int k, const void* X, const void* Y, double* G);

@@ -131,16 +131,39 @@ void block_cg(bkts_ctx ctx, const bkts_op_s& op, int dtype, int k, double a, dou
     if (all_converged(nrm, nrm0, rtol, &st.max_rel)) return 1;
     return nd >= k ? -1 : 0;
   };
+  // k <= 4: each fold of partials and its k x k solve share one launch (five launches per
+  // iteration instead of seven)
+  const bool fused = rk_eligible(k);
+  CgTail tail_sg, tail_up;
+  if (fused) {
+    tail_sg.counter = ctx->tail_counter(0);
+    tail_sg.eps = eps;
+    tail_sg.G = s.G;
+    tail_sg.gamma_in = s.gamma;
+    tail_sg.alpha = s.alpha;
+    tail_sg.ndefl = s.ndefl;
+    tail_up.counter = ctx->tail_counter(1);
+    tail_up.eps = eps;
+    tail_up.G = s.G;
+    tail_up.gamma = s.gamma;
+    tail_up.T = s.T;
+    tail_up.nrm = s.nrm;
+    tail_up.beta = s.beta;
+  }
   int restarts = 0;
   for (int it = 1; it <= maxit; ++it) {
-    if (rk_eligible(k)) {
-      rk_spmm_gram(ctx, op, dtype, k, a, P, b, Q, s.G);
+    if (fused) {
+      rk_spmm_gram(ctx, op, dtype, k, a, P, b, Q, s.G, &tail_sg);  // also alpha = G^+ gamma
     } else {
       spmm(ctx, op, dtype, k, 0.0, nullptr, k, a, P, k, b, Q, k);
       inner_gram(ctx, dtype, N, k, P, Q, s.G);
     }
-    small_spd_solve(ctx, k, s.G, s.gamma, 1.0, eps, s.alpha, s.ndefl);
-    cg_update(ctx, dtype, N, k, X, P, R, Q, s.alpha, dK, s.gamma, s.T, s.nrm);
+    if (fused) {
+      rk_cg_update(ctx, dtype, N, k, X, P, R, Q, s.alpha, dK, s.gamma, s.T, s.nrm, &tail_up);  // also beta
+    } else {
+      small_spd_solve(ctx, k, s.G, s.gamma, 1.0, eps, s.alpha, s.ndefl);
+      cg_update(ctx, dtype, N, k, X, P, R, Q, s.alpha, dK, s.gamma, s.T, s.nrm);
+    }
     {
       const int slot = it & 1;
       double* h = hbuf + slot * (k + 2);
@@ -162,7 +185,7 @@ void block_cg(bkts_ctx ctx, const bkts_op_s& op, int dtype, int k, double a, dou
       continue;
     }
     restarts = 0;
-    small_spd_solve(ctx, k, s.G, s.T, -1.0, eps, s.beta, nullptr);
+    if (!fused) small_spd_solve(ctx, k, s.G, s.T, -1.0, eps, s.beta, nullptr);
     cg_pupdate(ctx, dtype, N, k, P, R, s.beta, dK);
   }
   if (check(maxit) == 1) {

@@ -7,6 +7,7 @@
 // contiguous XCD-aware row range, and leaves one partial per Gram entry (fixed-order folding).
 #include "devcommon.hpp"
 #include "internal.hpp"
+#include "spd.hpp"
 
 namespace bkts {
 namespace {
@@ -299,6 +300,39 @@ __global__ __launch_bounds__(256) void rk_rmul_kernel(int64_t N, const T* __rest
   }
 }
 
+// Fold + solve in one launch with one workgroup per partial entry: workgroup e sums entry e over
+// the slots in a fixed order (as finalize), and the workgroup that finishes last (device-scope
+// counter) solves the k x k system from the folded values.  MODE 0 follows the SpMM-Gram kernel
+// (G, then alpha = G^+ gamma_in); MODE 1 follows the update kernel (gamma, T, nrm, then
+// beta = -G^+ T).
+template <int KP, int MODE>
+__global__ __launch_bounds__(256) void fold_solve_kernel(const double* __restrict__ partials, int64_t nslots,
+                                                         CgTail t) {
+  constexpr int KK = KP * KP;
+  __shared__ double s[256];
+  __shared__ dev::SolveLdsT<KP> sm;
+  const int e = blockIdx.x;
+  const double* p = partials + (int64_t)e * nslots;
+  double acc = 0.0;
+  for (int64_t j = threadIdx.x; j < nslots; j += 256) acc += p[j];
+  s[threadIdx.x] = acc;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (threadIdx.x < off) s[threadIdx.x] += s[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    double* out = MODE == 0 ? t.G + e : (e < KK ? t.gamma + e : (e < 2 * KK ? t.T + (e - KK) : t.nrm + (e - 2 * KK)));
+    *out = s[0];
+  }
+  if (!dev::last_workgroup(t.counter)) return;
+  if (MODE == 0)
+    dev::spd_solve_dev_t<KP>(KP, t.G, t.gamma_in, 1.0, t.eps, t.alpha, t.ndefl, sm);
+  else
+    dev::spd_solve_dev_t<KP>(KP, t.G, t.T, -1.0, t.eps, t.beta, nullptr, sm);
+  if (threadIdx.x == 0) atomicExch(t.counter, 0u);
+}
+
 // Persistent grid: the resident capacity of the chip for this kernel (occupancy x CUs), capped by
 // the number of 256-row chunks.
 template <typename K>
@@ -322,7 +356,7 @@ bool rk_eligible(int k) { return k == 1 || k == 2 || k == 4; }
 
 template <typename T, int KP>
 static void rk_spmm_gram_t(bkts_ctx ctx, const bkts_op_s& op, double alpha, const void* P, double beta, void* Q,
-                           double* G) {
+                           double* G, const CgTail* tail) {
   const bool sell = op.format == BKTS_FMT_SELL;
   RkSpmmArgs<T> a{};
   a.N = op.N;
@@ -354,21 +388,24 @@ static void rk_spmm_gram_t(bkts_ctx ctx, const bkts_op_s& op, double alpha, cons
   }
   BKTS_HIP(hipGetLastError());
   prof.end();
-  finalize_gram(ctx, a.partials, (int)nb, KP, KP, G);
+  if (!tail) return finalize_gram(ctx, a.partials, (int)nb, KP, KP, G);
+  ProfScope ps(ctx, BKTS_K_SMALL, 8.0 * KP * KP * nb);
+  launch(ctx, (fold_solve_kernel<KP, 0>), dim3(KP * KP), dim3(256), 0, (const double*)a.partials, nb, *tail);
+  BKTS_HIP(hipGetLastError());
 }
 
 void rk_spmm_gram(bkts_ctx ctx, const bkts_op_s& op, int dtype, int k, double alpha, const void* P, double beta,
-                  void* Q, double* G) {
+                  void* Q, double* G, const CgTail* tail) {
   if (dtype == BKTS_F64)
-    BKTS_RK_DISPATCH(k, (rk_spmm_gram_t<double, KP>(ctx, op, alpha, P, beta, Q, G)));
+    BKTS_RK_DISPATCH(k, (rk_spmm_gram_t<double, KP>(ctx, op, alpha, P, beta, Q, G, tail)));
   else
-    BKTS_RK_DISPATCH(k, (rk_spmm_gram_t<float, KP>(ctx, op, alpha, P, beta, Q, G)));
+    BKTS_RK_DISPATCH(k, (rk_spmm_gram_t<float, KP>(ctx, op, alpha, P, beta, Q, G, tail)));
 }
 
 template <typename T, int KP>
 static void rk_cg_update_t(bkts_ctx ctx, int64_t N, void* X, const void* P, void* R, const void* Q,
                            const double* alpha, const double* dinv,
-                           double* gamma, double* Tm, double* nrm) {
+                           double* gamma, double* Tm, double* nrm, const CgTail* tail) {
   constexpr int NA = 2 * KP * KP + KP;
   const int64_t nb = rk_grid(ctx, rk_cg_update_kernel<T, KP>, N);
   double* part = ctx->ws.get<double>("rk_upd_part", (size_t)NA * nb);
@@ -377,17 +414,24 @@ static void rk_cg_update_t(bkts_ctx ctx, int64_t N, void* X, const void* P, void
   launch(ctx, (rk_cg_update_kernel<T, KP>), dim3(nb), dim3(256), 0, a);
   BKTS_HIP(hipGetLastError());
   prof.end();
+  if (tail) {
+    ProfScope ps(ctx, BKTS_K_SMALL, 8.0 * NA * nb);
+    launch(ctx, (fold_solve_kernel<KP, 1>), dim3(NA), dim3(256), 0, (const double*)part, nb, *tail);
+    BKTS_HIP(hipGetLastError());
+    return;
+  }
   const FoldSet sets[3] = {{part, KP, 0, gamma}, {part + (size_t)KP * KP * nb, KP, 0, Tm},
                            {part + (size_t)2 * KP * KP * nb, KP, 1, nrm}};
   finalize_sets(ctx, (int)nb, KP, sets, 3);
 }
 
 void rk_cg_update(bkts_ctx ctx, int dtype, int64_t N, int k, void* X, const void* P, void* R, const void* Q,
-                  const double* alpha, const double* dinv, double* gamma, double* Tm, double* nrm) {
+                  const double* alpha, const double* dinv, double* gamma, double* Tm, double* nrm,
+                  const CgTail* tail) {
   if (dtype == BKTS_F64)
-    BKTS_RK_DISPATCH(k, (rk_cg_update_t<double, KP>(ctx, N, X, P, R, Q, alpha, dinv, gamma, Tm, nrm)));
+    BKTS_RK_DISPATCH(k, (rk_cg_update_t<double, KP>(ctx, N, X, P, R, Q, alpha, dinv, gamma, Tm, nrm, tail)));
   else
-    BKTS_RK_DISPATCH(k, (rk_cg_update_t<float, KP>(ctx, N, X, P, R, Q, alpha, dinv, gamma, Tm, nrm)));
+    BKTS_RK_DISPATCH(k, (rk_cg_update_t<float, KP>(ctx, N, X, P, R, Q, alpha, dinv, gamma, Tm, nrm, tail)));
 }
 
 template <typename T, int KP>

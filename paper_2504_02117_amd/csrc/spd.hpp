@@ -11,11 +11,13 @@ namespace dev {
 constexpr int KM = BKTS_MAX_K;
 constexpr int kSolveThreads = 256;
 
-struct SolveLds {
-  double M[KM][2 * KM + 1];  // augmented [G | S], Jacobi scaled
-  double d[KM];
-  int active[KM];
+template <int KMAX>
+struct SolveLdsT {
+  double M[KMAX][2 * KMAX + 1];  // augmented [G | S], Jacobi scaled
+  double d[KMAX];
+  int active[KMAX];
 };
+using SolveLds = SolveLdsT<KM>;
 
 // out = sign * G^+ S for k x k row-major G, S in device memory, run by all kSolveThreads threads
 // of the block.  G^+ inverts the symmetric part of G on the directions that survive symmetric
@@ -24,8 +26,9 @@ struct SolveLds {
 // direction as numerically dependent on the earlier ones, and that row and column are dropped
 // (the corresponding rows of the result are zero).  Gauss-Jordan on [D G D | D S] keeps every
 // step a parallel update of the whole augmented matrix, with two barriers per pivot.
-__device__ inline void spd_solve_dev(int k, const double* Gin, const double* S, double sign, double eps, double* out,
-                                     int* ndefl, SolveLds& sm) {
+template <int KMAX>
+__device__ inline void spd_solve_dev_t(int k, const double* Gin, const double* S, double sign, double eps, double* out,
+                                       int* ndefl, SolveLdsT<KMAX>& sm) {
   const int t = threadIdx.x;
   const int w2 = 2 * k;
   for (int e = t; e < k * k; e += kSolveThreads) {
@@ -46,7 +49,7 @@ __device__ inline void spd_solve_dev(int k, const double* Gin, const double* S, 
     sm.M[i][c] *= c < k ? sm.d[i] * sm.d[c] : sm.d[i];
   }
   __syncthreads();
-  constexpr int EPT = (KM * 2 * KM + kSolveThreads - 1) / kSolveThreads;  // elements per thread
+  constexpr int EPT = (KMAX * 2 * KMAX + kSolveThreads - 1) / kSolveThreads;  // elements per thread
   for (int j = 0; j < k; ++j) {
     const double p = sm.M[j][j];
     const bool keep = sm.active[j] && p > eps;
@@ -86,6 +89,53 @@ __device__ inline void spd_solve_dev(int k, const double* Gin, const double* S, 
     *ndefl = nd;
   }
   __syncthreads();
+}
+
+__device__ inline void spd_solve_dev(int k, const double* Gin, const double* S, double sign, double eps, double* out,
+                                     int* ndefl, SolveLds& sm) {
+  spd_solve_dev_t<KM>(k, Gin, S, sign, eps, out, ndefl, sm);
+}
+
+// Threads per entry for folding E partial entries with one 256-thread workgroup.
+constexpr int fold_tpe(int E) {
+  int g = 1;
+  while (2 * g * E <= kSolveThreads && g < kSolveThreads) g *= 2;
+  return g;
+}
+
+// out[e] = sum over s of partials[e * nslots + s] for e < E, in a fixed order (strided partial
+// sums per thread, then a fixed tree); all kSolveThreads threads, `red` holds kSolveThreads doubles.
+template <int E>
+__device__ inline void fold_slots(const double* partials, int64_t nslots, double* out, double* red) {
+  constexpr int G = fold_tpe(E);
+  constexpr int EPP = kSolveThreads / G;
+  const int t = threadIdx.x, j = t % G;
+  for (int e0 = 0; e0 < E; e0 += EPP) {
+    const int e = e0 + t / G;
+    double acc = 0.0;
+    if (e < E)
+      for (int64_t s = j; s < nslots; s += G) acc += partials[(int64_t)e * nslots + s];
+    red[t] = acc;
+    __syncthreads();
+    for (int off = G / 2; off > 0; off >>= 1) {
+      if (j < off) red[t] += red[t + off];
+      __syncthreads();
+    }
+    if (j == 0 && e < E) out[e] = red[t];
+    __syncthreads();
+  }
+}
+
+// True in the workgroup that finishes last among gridDim.x (device-scope counter, which the caller
+// resets).  Global writes made before the call by every workgroup are visible to the last one.
+__device__ inline bool last_workgroup(unsigned* counter) {
+  __shared__ int last;
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) last = atomicAdd(counter, 1u) == gridDim.x - 1 ? 1 : 0;
+  __syncthreads();
+  if (last) __threadfence();
+  return last != 0;
 }
 
 }  // namespace dev
