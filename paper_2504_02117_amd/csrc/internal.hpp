@@ -253,6 +253,9 @@ struct CgTail {
   double* beta = nullptr;
 };
 
+// fold.hip: mode 0 after a Gram kernel, mode 1 after an update kernel; kp in {1, 2, 4, 16, 32}.
+void fold_solve(bkts_ctx ctx, int mode, int kp, int k, const double* partials, int64_t nslots, const CgTail& t);
+
 // Row-per-thread block kernels for k in {1, 2, 4} (rowk.hip); contiguous blocks (ld = k).
 bool rk_eligible(int k);
 void rk_spmm_gram(bkts_ctx ctx, const bkts_op_s& op, int dtype, int k, double alpha, const void* P, double beta,

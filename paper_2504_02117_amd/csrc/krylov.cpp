@@ -133,6 +133,8 @@ void block_cg(bkts_ctx ctx, const bkts_op_s& op, int dtype, int k, double a, dou
   };
   // k <= 4: each fold of partials and its k x k solve share one launch (five launches per
   // iteration instead of seven)
+  // (for wider blocks the separate fold and solve launches measure faster: the fused form's
+  // k x k working set per workgroup costs more than the launch it saves)
   const bool fused = rk_eligible(k);
   CgTail tail_sg, tail_up;
   if (fused) {

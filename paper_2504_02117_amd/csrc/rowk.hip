@@ -300,39 +300,6 @@ __global__ __launch_bounds__(256) void rk_rmul_kernel(int64_t N, const T* __rest
   }
 }
 
-// Fold + solve in one launch with one workgroup per partial entry: workgroup e sums entry e over
-// the slots in a fixed order (as finalize), and the workgroup that finishes last (device-scope
-// counter) solves the k x k system from the folded values.  MODE 0 follows the SpMM-Gram kernel
-// (G, then alpha = G^+ gamma_in); MODE 1 follows the update kernel (gamma, T, nrm, then
-// beta = -G^+ T).
-template <int KP, int MODE>
-__global__ __launch_bounds__(256) void fold_solve_kernel(const double* __restrict__ partials, int64_t nslots,
-                                                         CgTail t) {
-  constexpr int KK = KP * KP;
-  __shared__ double s[256];
-  __shared__ dev::SolveLdsT<KP> sm;
-  const int e = blockIdx.x;
-  const double* p = partials + (int64_t)e * nslots;
-  double acc = 0.0;
-  for (int64_t j = threadIdx.x; j < nslots; j += 256) acc += p[j];
-  s[threadIdx.x] = acc;
-  __syncthreads();
-  for (int off = 128; off > 0; off >>= 1) {
-    if (threadIdx.x < off) s[threadIdx.x] += s[threadIdx.x + off];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-    double* out = MODE == 0 ? t.G + e : (e < KK ? t.gamma + e : (e < 2 * KK ? t.T + (e - KK) : t.nrm + (e - 2 * KK)));
-    *out = s[0];
-  }
-  if (!dev::last_workgroup(t.counter)) return;
-  if (MODE == 0)
-    dev::spd_solve_dev_t<KP>(KP, t.G, t.gamma_in, 1.0, t.eps, t.alpha, t.ndefl, sm);
-  else
-    dev::spd_solve_dev_t<KP>(KP, t.G, t.T, -1.0, t.eps, t.beta, nullptr, sm);
-  if (threadIdx.x == 0) atomicExch(t.counter, 0u);
-}
-
 // Persistent grid: the resident capacity of the chip for this kernel (occupancy x CUs), capped by
 // the number of 256-row chunks.
 template <typename K>
@@ -389,9 +356,7 @@ static void rk_spmm_gram_t(bkts_ctx ctx, const bkts_op_s& op, double alpha, cons
   BKTS_HIP(hipGetLastError());
   prof.end();
   if (!tail) return finalize_gram(ctx, a.partials, (int)nb, KP, KP, G);
-  ProfScope ps(ctx, BKTS_K_SMALL, 8.0 * KP * KP * nb);
-  launch(ctx, (fold_solve_kernel<KP, 0>), dim3(KP * KP), dim3(256), 0, (const double*)a.partials, nb, *tail);
-  BKTS_HIP(hipGetLastError());
+  fold_solve(ctx, 0, KP, KP, a.partials, nb, *tail);
 }
 
 void rk_spmm_gram(bkts_ctx ctx, const bkts_op_s& op, int dtype, int k, double alpha, const void* P, double beta,
@@ -415,9 +380,7 @@ static void rk_cg_update_t(bkts_ctx ctx, int64_t N, void* X, const void* P, void
   BKTS_HIP(hipGetLastError());
   prof.end();
   if (tail) {
-    ProfScope ps(ctx, BKTS_K_SMALL, 8.0 * NA * nb);
-    launch(ctx, (fold_solve_kernel<KP, 1>), dim3(NA), dim3(256), 0, (const double*)part, nb, *tail);
-    BKTS_HIP(hipGetLastError());
+    fold_solve(ctx, 1, KP, KP, part, nb, *tail);
     return;
   }
   const FoldSet sets[3] = {{part, KP, 0, gamma}, {part + (size_t)KP * KP * nb, KP, 0, Tm},

@@ -511,7 +511,8 @@ int wide_kp(int k) { return k <= 16 ? 16 : 32; }
   } while (0)
 
 void w_cg_update(bkts_ctx ctx, int64_t N, int k, float* X, const float* P, float* R, const float* Q,
-                 const double* alpha, const double* dinv, double* gamma, double* Tm, double* nrm) {
+                 const double* alpha, const double* dinv, double* gamma, double* Tm, double* nrm,
+                 const CgTail* tail) {
   const int KP = wide_kp(k);
   const int64_t nb = wide_blocks(ctx, k <= 16 ? (const void*)w_update_kernel<1> : (const void*)w_update_kernel<2>,
                                  (N + 15) / 16);
@@ -525,13 +526,14 @@ void w_cg_update(bkts_ctx ctx, int64_t N, int k, float* X, const float* P, float
   a.Q = const_cast<float*>(Q);
   a.coef = alpha;
   a.dinv = dinv;
-  a.pg = ctx->ws.get<double>("w_pg", np);
-  a.pt = ctx->ws.get<double>("w_pt", np);
-  a.pn = ctx->ws.get<double>("w_pn", (size_t)KP * nb);
+  a.pg = ctx->ws.get<double>("w_upd", 2 * np + (size_t)KP * nb);  // [gamma | T | nrm] entries
+  a.pt = a.pg + np;
+  a.pn = a.pt + np;
   ProfScope prof(ctx, BKTS_K_CG_UPDATE, 24.0 * N * k + (dinv ? 8.0 * N : 0.0));
   BKTS_WNB(k, launch(ctx, w_update_kernel<NB>, dim3(nb), dim3(256), 0, a));
   BKTS_HIP(hipGetLastError());
   prof.end();
+  if (tail) return fold_solve(ctx, 1, KP, k, a.pg, nb, *tail);
   const FoldSet sets[3] = {{a.pg, KP, 0, gamma}, {a.pt, KP, 0, Tm}, {a.pn, KP, 1, nrm}};
   finalize_sets(ctx, (int)nb, k, sets, 3);
 }
@@ -575,7 +577,7 @@ void w_spmm_gram(bkts_ctx ctx, const bkts_op_s& op, int k, double alpha, const f
   finalize_gram(ctx, a.pg, (int)nb, k, KP, G);
 }
 
-void w_gram(bkts_ctx ctx, int64_t N, int k, const float* X, const float* Y, double* G) {
+void w_gram(bkts_ctx ctx, int64_t N, int k, const float* X, const float* Y, double* G, const CgTail* tail) {
   const int KP = wide_kp(k);
   const int64_t nb =
       wide_blocks(ctx, k <= 16 ? (const void*)w_gram_kernel<1> : (const void*)w_gram_kernel<2>, (N + 15) / 16);
@@ -589,6 +591,7 @@ void w_gram(bkts_ctx ctx, int64_t N, int k, const float* X, const float* Y, doub
   BKTS_WNB(k, launch(ctx, w_gram_kernel<NB>, dim3(nb), dim3(256), 0, a));
   BKTS_HIP(hipGetLastError());
   prof.end();
+  if (tail) return fold_solve(ctx, 0, KP, k, a.pg, nb, *tail);
   finalize_gram(ctx, a.pg, (int)nb, k, KP, G);
 }
 

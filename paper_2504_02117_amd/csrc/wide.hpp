@@ -25,9 +25,11 @@ bool wide_eligible(int dtype, int k);
 int wide_kp(int k);
 
 void w_cg_update(bkts_ctx ctx, int64_t N, int k, float* X, const float* P, float* R, const float* Q,
-                 const double* alpha, const double* dinv, double* gamma, double* Tm, double* nrm);
+                 const double* alpha, const double* dinv, double* gamma, double* Tm, double* nrm,
+                 const CgTail* tail = nullptr);
 void w_cg_pupdate(bkts_ctx ctx, int64_t N, int k, float* P, const float* R, const double* beta, const double* dinv);
-void w_gram(bkts_ctx ctx, int64_t N, int k, const float* X, const float* Y, double* G);
+void w_gram(bkts_ctx ctx, int64_t N, int k, const float* X, const float* Y, double* G,
+            const CgTail* tail = nullptr);
 void w_spmm_gram(bkts_ctx ctx, const bkts_op_s& op, int k, double alpha, const float* P, double beta, float* Q,
                  double* G);
 
