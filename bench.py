@@ -39,22 +39,27 @@ def parse():
     p.add_argument("--n", type=int, default=128)
     p.add_argument("--k", type=int, default=4)
     p.add_argument("--precision", choices=["f32", "f64"], default="f32")
-    p.add_argument("--inner-rtol", type=float, default=1e-2)
+    p.add_argument("--inner-rtol", type=float, default=0.1,
+                   help="inner (FP32 block-CG) relative tolerance per outer iteration; the outer loop converges "
+                        "every accepted step to 1e-8 regardless")
     p.add_argument("--plain-steps", type=int, default=8)
     p.add_argument("--no-plain", action="store_true")
     p.add_argument("--no-cpu", action="store_true")
-    p.add_argument("--cpu-steps", type=int, default=1)
+    p.add_argument("--cpu-steps", type=int, default=3)
     p.add_argument("--no-kernel-timers", action="store_true",
                    help="time the block form without the in-library kernel timers (no roofline)")
     p.add_argument("--calibrate-copy", action="store_true",
                    help="first run 3 plain 256 MiB device copies (reference dispatches for HBM counters)")
-    p.add_argument("--serve-requests", type=int, default=512,
-                   help="serving leg: Poisson-arrival requests (0 = skip)")
+    p.add_argument("--serve-requests", type=int, default=128,
+                   help="serving leg: the first n requests of the seeded Poisson trace (0 = skip; the full "
+                        "trace is 512)")
     p.add_argument("--serve-rate", type=float, default=200.0, help="mean arrivals per second")
     p.add_argument("--serve-budget-gib", type=float, default=4.0)
     p.add_argument("--serve-slots", type=int, default=64)
-    p.add_argument("--sweep", type=str, default="1f32,4f64,8,16,32",
-                   help="comma list of extra block forms to time: <k>[f32|f64] (default precision: --precision)")
+    p.add_argument("--serve-inner-rtol", type=float, default=0.1)
+    p.add_argument("--sweep", type=str, default="1f32,4f64,4f32@0.01,8,16,32",
+                   help="comma list of extra block forms to time: <k>[f32|f64][@inner_rtol] (defaults: --precision, "
+                        "--inner-rtol)")
     return p.parse_args()
 
 
@@ -174,6 +179,8 @@ def run_serving(torch, bkts, ctx, a):
         kd = torch.from_numpy(inputs.lognormal_field(n, 0.0, 2.0, 8.0, 1000 + i)).cuda()
         out = torch.empty((n[0] * n[1], int(widths[i])), dtype=torch.float64, device="cuda")
         reqs.append((n, kd, out))
+        if (i + 1) % 128 == 0:
+            log(f"  built {i + 1}")
     torch.cuda.synchronize()
     srv = bkts.bkts_server_create(ctx, int(a.serve_budget_gib * (1 << 30)), a.serve_slots)
     results = {}
@@ -185,13 +192,18 @@ def run_serving(torch, bkts, ctx, a):
                 for r in bkts.bkts_server_poll(srv):
                     results[r.ticket] = r
                 time.sleep(min(5e-4, max(0.0, t0 + arrivals[i] - bkts.bkts_server_clock(srv))))
-            req = bkts.make_request(n, y0s[n], out, int(widths[i]), 1e-3, kappa=kd, rtol=1e-8, inner_rtol=1e-2,
-                                    tag=i)
+            req = bkts.make_request(n, y0s[n], out, int(widths[i]), 1e-3, kappa=kd, rtol=1e-8,
+                                    inner_rtol=a.serve_inner_rtol, tag=i)
             tickets[bkts.bkts_server_submit(srv, req)] = i
+        log(f"  all {m} submitted at t={bkts.bkts_server_clock(srv) - t0:.2f} s, {len(results)} done")
+        last = time.time()
         while len(results) < m:
             bkts.bkts_server_wait(srv, 1, 1.0)
             for r in bkts.bkts_server_poll(srv):
                 results[r.ticket] = r
+            if time.time() - last > 10.0:
+                last = time.time()
+                log(f"  {len(results)}/{m} done at t={bkts.bkts_server_clock(srv) - t0:.1f} s")
         st = bkts.bkts_server_stats_get(srv)
     finally:
         bkts.bkts_server_destroy(srv)
@@ -228,7 +240,7 @@ def run_serving(torch, bkts, ctx, a):
             "krylov_element_iterations": elem_it,
             "inner_stream_GBps": 44.0 * elem_it / makespan / 1e9,
             "hbm_budget_bytes": int(a.serve_budget_gib * (1 << 30)), "hbm_peak_reserved_bytes": st.bytes_peak,
-            "oracle_max_rel_err_sampled": max(errs) if errs else None,
+            "oracle_max_rel_err_sampled": max(errs) if errs else None, "inner_rtol": a.serve_inner_rtol,
             "workload": "2-D lognormal diffusion (log-std 2, corr. 8 cells, seed 1000+i), n in {64,128,256,512}, "
                         "k in {4,8,16,32}, implicit Euler tau=1e-3, one window of k steps per request, "
                         "FP32 block CG inside FP64 Newton to 1e-8, Poisson arrivals"}
@@ -279,16 +291,19 @@ def main():
 
     sweep = {}
     for item in [v.strip() for v in a.sweep.split(",") if v.strip()]:
-        prec = a.precision
+        prec, tol = a.precision, a.inner_rtol
+        if "@" in item:
+            item, t = item.split("@")
+            tol = float(t)
         if item.endswith("f32") or item.endswith("f64"):
             prec, item = item[-3:], item[:-3]
         ks = int(item)
-        r = run_form(torch, bkts, ctx, op, y0, ks, prec, a.inner_rtol, a.warmup, a.steps, True)
+        r = run_form(torch, bkts, ctx, op, y0, ks, prec, tol, a.warmup, a.steps, True)
         sp = r["kernels"].get("spmm", {})
         sv = 4 if prec == "f32" else 8
         bpl = nnz * (sv + 4) + 4 * (N + 1) + 2 * N * ks * sv
         dom = max(r["kernels"].items(), key=lambda kv: kv[1]["total_ms"])[0] if r["kernels"] else None
-        sweep[f"k={ks} {prec}"] = {
+        sweep[f"k={ks} {prec} inner={tol:g}"] = {
             "value": r["value"], "outer": r["info"].outer_iterations, "krylov": r["info"].krylov_iterations,
             "spmm_avg_us": sp.get("avg_us"),
             "spmm_GBps": (bpl / (sp["avg_us"] * 1e-6) / 1e9) if sp else None,
@@ -296,7 +311,7 @@ def main():
             "spmm_kernel": kernel_name("spmm", ks), "spmm_flop_per_byte": 2.0 * nnz * ks / bpl,
             "dominant_kernel": dom,
             "kernels": {kk: {"avg_us": vv["avg_us"], "GBps": vv["GBps"]} for kk, vv in r["kernels"].items()}}
-        log(f"  sweep k={ks} {prec}: {r['value']:.4g} DOF*steps/s (spmm {sp.get('avg_us', 0):.1f} us)")
+        log(f"  sweep k={ks} {prec} inner={tol:g}: {r['value']:.4g} DOF*steps/s (spmm {sp.get('avg_us', 0):.1f} us)")
 
     roof = spmm_roof = None
     if blk["kernels"]:

@@ -50,6 +50,13 @@ __device__ inline void spd_solve_dev_t(int k, const double* Gin, const double* S
   }
   __syncthreads();
   constexpr int EPT = (KMAX * 2 * KMAX + kSolveThreads - 1) / kSolveThreads;  // elements per thread
+  int ri[EPT], ci[EPT];  // this thread's elements of the augmented matrix (fixed for all pivots)
+#pragma unroll
+  for (int q = 0; q < EPT; ++q) {
+    const int e = t + q * kSolveThreads;
+    ri[q] = e < k * w2 ? e / w2 : -1;
+    ci[q] = e < k * w2 ? e % w2 : 0;
+  }
   for (int j = 0; j < k; ++j) {
     const double p = sm.M[j][j];
     const bool keep = sm.active[j] && p > eps;
@@ -57,10 +64,9 @@ __device__ inline void spd_solve_dev_t(int k, const double* Gin, const double* S
     double nv[EPT];
 #pragma unroll
     for (int q = 0; q < EPT; ++q) {
-      const int e = t + q * kSolveThreads;
+      const int i = ri[q], c = ci[q];
       nv[q] = 0.0;
-      if (e < k * w2) {
-        const int i = e / w2, c = e % w2;
+      if (i >= 0) {
         const double mic = sm.M[i][c];
         if (!keep)
           nv[q] = (i == j || c == j) ? 0.0 : mic;
@@ -72,10 +78,8 @@ __device__ inline void spd_solve_dev_t(int k, const double* Gin, const double* S
     }
     __syncthreads();
 #pragma unroll
-    for (int q = 0; q < EPT; ++q) {
-      const int e = t + q * kSolveThreads;
-      if (e < k * w2) sm.M[e / w2][e % w2] = nv[q];
-    }
+    for (int q = 0; q < EPT; ++q)
+      if (ri[q] >= 0) sm.M[ri[q]][ci[q]] = nv[q];
     if (t == 0 && !keep) sm.active[j] = 0;
     __syncthreads();
   }
@@ -126,17 +130,20 @@ __device__ inline void fold_slots(const double* partials, int64_t nslots, double
   }
 }
 
-// True in the workgroup that finishes last among gridDim.x (device-scope counter, which the caller
-// resets).  Global writes made before the call by every workgroup are visible to the last one.
-__device__ inline bool last_workgroup(unsigned* counter) {
+// True in the workgroup that finishes last among `expected` workgroups sharing a device-scope
+// counter (which the caller resets).  Global writes made before the call by every one of them are
+// visible to the last one.
+__device__ inline bool last_of(unsigned* counter, unsigned expected) {
   __shared__ int last;
   __threadfence();
   __syncthreads();
-  if (threadIdx.x == 0) last = atomicAdd(counter, 1u) == gridDim.x - 1 ? 1 : 0;
+  if (threadIdx.x == 0) last = atomicAdd(counter, 1u) == expected - 1 ? 1 : 0;
   __syncthreads();
   if (last) __threadfence();
   return last != 0;
 }
+
+__device__ inline bool last_workgroup(unsigned* counter) { return last_of(counter, gridDim.x); }
 
 }  // namespace dev
 }  // namespace bkts
