@@ -93,6 +93,40 @@ __global__ __launch_bounds__(256) void colnorm_kernel(int64_t N, int k, const T*
   dev::block_reduce_store<KP, 1>(acc, red, partials, gridDim.x, slot);
 }
 
+// Column-wise dot products of up to three pairs of contiguous blocks (ld = k), FP64 accumulation:
+// partial entry p*KP + c holds sum_r X_p[r][c] Y_p[r][c].
+struct DotPairs {
+  const void* x[3];
+  const void* y[3];
+};
+
+template <typename T, int KP, int NP>
+__global__ __launch_bounds__(256) void coldots_kernel(int64_t N, int k, DotPairs d, double* partials, int64_t tps) {
+  using G = TileGeom<KP>;
+  __shared__ double red[4 * NP * KP];
+  const int t = threadIdx.x, c = t % KP, r0 = t / KP;
+  const int64_t slot = dev::xcd_slot(blockIdx.x, gridDim.x);
+  const int64_t ntiles = (N + G::RT - 1) / G::RT;
+  double acc[NP];
+#pragma unroll
+  for (int p = 0; p < NP; ++p) acc[p] = 0.0;
+  const int64_t tend = (slot + 1) * tps < ntiles ? (slot + 1) * tps : ntiles;
+  for (int64_t tile = slot * tps; tile < tend; ++tile) {
+    const int64_t row0 = tile * G::RT;
+#pragma unroll
+    for (int i = 0; i < G::RPT; ++i) {
+      const int64_t gr = row0 + r0 + i * G::RS;
+      if (gr < N && c < k) {
+#pragma unroll
+        for (int p = 0; p < NP; ++p)
+          acc[p] = fma(dev::ld_d(static_cast<const T*>(d.x[p]) + gr * k + c),
+                       dev::ld_d(static_cast<const T*>(d.y[p]) + gr * k + c), acc[p]);
+      }
+    }
+  }
+  dev::block_reduce_store<KP, NP>(acc, red, partials, gridDim.x, slot);
+}
+
 // out[i] = sum over slots of partials[e(i)][slot], e(i) = (i / kout) * KP + i % kout for the
 // Gram layout (nrow = kout) or e(i) = i for vectors (nrow = 1).  One workgroup per output entry,
 // fixed summation order.
@@ -344,6 +378,22 @@ void launch_colnorm_t(bkts_ctx ctx, int dtype, int64_t N, int k, const void* X, 
   BKTS_HIP(hipGetLastError());
 }
 
+template <int KP, int NP>
+void launch_coldots_t(bkts_ctx ctx, int dtype, int64_t N, int k, const DotPairs& d, double* const* out) {
+  Slots s = make_slots<KP>(ctx, N);
+  double* part = ctx->ws.get<double>("dots_partials", (size_t)NP * KP * s.nslots);
+  ProfScope prof(ctx, BKTS_K_NORMS, 2.0 * NP * N * k * esize(dtype));
+  if (dtype == BKTS_F64)
+    launch(ctx, (coldots_kernel<double, KP, NP>), dim3(s.nslots), dim3(256), 0, N, k, d, part, s.tps);
+  else
+    launch(ctx, (coldots_kernel<float, KP, NP>), dim3(s.nslots), dim3(256), 0, N, k, d, part, s.tps);
+  BKTS_HIP(hipGetLastError());
+  prof.end();
+  FoldSet sets[3];
+  for (int p = 0; p < NP; ++p) sets[p] = FoldSet{part + (size_t)p * KP * s.nslots, KP, 1, out[p]};
+  finalize_sets(ctx, (int)s.nslots, k, sets, NP);
+}
+
 template <typename T, int KP>
 void launch_cg_update_t(bkts_ctx ctx, int64_t N, int k, void* X, const void* P, void* R, const void* Q,
                         const double* alpha, const double* dinv,
@@ -431,6 +481,19 @@ void gram(bkts_ctx ctx, int dtype, int64_t N, int k, const void* X, int ldx, con
   auto al16 = [](const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; };
   if (rk_eligible(k) && ldx == k && ldy == k && al16(X) && al16(Y)) return rk_gram(ctx, dtype, N, k, X, Y, G);
   BKTS_KP_DISPATCH(k, (launch_gram_t<KP>(ctx, dtype, N, k, X, ldx, Y, ldy, G)));
+}
+
+void col_dots(bkts_ctx ctx, int dtype, int64_t N, int k, int npairs, const void* const* X, const void* const* Y,
+              double* const* out) {
+  BKTS_REQUIRE(npairs >= 1 && npairs <= 3, "col_dots: 1..3 pairs");
+  DotPairs d{};
+  for (int p = 0; p < npairs; ++p) {
+    d.x[p] = X[p];
+    d.y[p] = Y[p];
+  }
+  if (npairs == 1) BKTS_KP_DISPATCH(k, (launch_coldots_t<KP, 1>(ctx, dtype, N, k, d, out)));
+  else if (npairs == 2) BKTS_KP_DISPATCH(k, (launch_coldots_t<KP, 2>(ctx, dtype, N, k, d, out)));
+  else BKTS_KP_DISPATCH(k, (launch_coldots_t<KP, 3>(ctx, dtype, N, k, d, out)));
 }
 
 void colnorms2(bkts_ctx ctx, int dtype, int64_t N, int k, const void* X, int ldx, double* out) {

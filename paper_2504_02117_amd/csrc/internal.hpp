@@ -286,6 +286,10 @@ void mf_rmul(bkts_ctx ctx, int dtype, int64_t N, int k, const void* X, const dou
 void gram(bkts_ctx ctx, int dtype, int64_t N, int k, const void* X, int ldx, const void* Y, int ldy,
           double* G);
 
+// Column-wise dot products of npairs (1..3) pairs of contiguous N x k blocks: out[p][j] =
+// sum_r X_p[r, j] Y_p[r, j] (FP64 accumulation, fixed-order reduction; out[p] device, k values).
+void col_dots(bkts_ctx ctx, int dtype, int64_t N, int k, int npairs, const void* const* X, const void* const* Y,
+              double* const* out);
 // Column sums of squares: out[j] = sum_r X[r, j]^2 (device, k)
 void colnorms2(bkts_ctx ctx, int dtype, int64_t N, int k, const void* X, int ldx, double* out);
 
@@ -319,6 +323,9 @@ void small_gemm(bkts_ctx ctx, int k, const double* A, const double* B, double al
 void small_lu_solve2(bkts_ctx ctx, int k, const double* M, const double* B1, double s1, double* X1, const double* B2,
                      double s2, double* X2, double eps);
 void small_omega(bkts_ctx ctx, int k, const double* TS, const double* TT, double* out);
+// out = diag(sign * a_j / b_j) as a k x k matrix, for device k-vectors a, b (0 where b_j is zero or
+// the ratio is not finite)
+void small_diag_ratio(bkts_ctx ctx, int k, const double* a, const double* b, double sign, double* out);
 int gmres_max_rows();
 void gmres_lsq(bkts_ctx ctx, int k, int nr, int nc, const double* H, int ldh, const double* S, double eps, double* Y,
                double* resn);

@@ -10,6 +10,7 @@ struct KrylovStats {
   int refinements = 0;
   int converged = 0;
   int deflations = 0;
+  int breakdown = 0;  // the method stopped early on a breakdown and returned its last iterate
   double max_rel = 0.0;
 };
 

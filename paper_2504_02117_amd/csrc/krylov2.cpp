@@ -154,8 +154,13 @@ void block_gmres(bkts_ctx ctx, const bkts_op_s& op, int dtype, int k, double a, 
   st.converged = 0;
 }
 
+// Vectorized BiCGStab: the k columns advance together through one block operator application per
+// half step (the matrix streams once for all of them), each column with its own scalars alpha_j,
+// omega_j, beta_j taken from the diagonals of the k x k products (the lane-wise form of a
+// vectorized solver).  Coupling the columns through k x k solves (the block form) needs a
+// well-conditioned residual block at every step, which FP32 windows of Algorithm 1 do not keep.
 void block_bicgstab(bkts_ctx ctx, const bkts_op_s& op, int dtype, int k, double a, double b, const void* B, void* X,
-                    bool x0_zero, bool jacobi, double rtol, int maxit, KrylovStats& st) {
+                   bool x0_zero, bool jacobi, double rtol, int maxit, KrylovStats& st) {
   const int64_t N = op.N;
   const size_t es = esize(dtype);
   const size_t blk = es * N * k;
@@ -170,11 +175,11 @@ void block_bicgstab(bkts_ctx ctx, const bkts_op_s& op, int dtype, int k, double 
   void* Sh = ctx->ws.get("bs_Sh_" + tag, blk);
   void* T = ctx->ws.get("bs_T_" + tag, blk);
   const size_t kk = (size_t)k * k;
-  double* sm = ctx->ws.get<double>("bs_small", 8 * kk + 2 * k + 2);
-  double *M1 = sm, *Mr = M1 + kk, *M3 = Mr + kk, *al = M3 + kk, *be = al + kk, *TS = be + kk, *TT = TS + kk;
-  double* om = TT + kk;
-  double* nrmd = om + 2;
-  const double lu_eps = dtype == BKTS_F64 ? 1e-14 : 1e-7;
+  // per-column dots (k each): m1 = rt.v, mr = rt.r, ts = t.s, tt = t.t, m3 = rt.t; diagonal
+  // coefficient matrices (k x k): alpha, beta, omega
+  double* sm = ctx->ws.get<double>("bs_small", 3 * kk + 6 * k);
+  double *al = sm, *be = al + kk, *W = be + kk;
+  double *m1 = W + kk, *mr = m1 + k, *ts = mr + k, *tt = ts + k, *m3 = tt + k, *nrmd = m3 + k;
   const double* dinv = nullptr;
   if (jacobi) {
     double* d = ctx->ws.get<double>("bs_dinv", N);
@@ -200,32 +205,46 @@ void block_bicgstab(bkts_ctx ctx, const bkts_op_s& op, int dtype, int k, double 
   for (int it = 1; it <= maxit; ++it) {
     scale_rows(ctx, dtype, N, k, dinv, P, Ph);
     spmm(ctx, op, dtype, k, 0.0, nullptr, k, a, Ph, k, b, V, k);  // V = A D^-1 P
-    gram(ctx, dtype, N, k, Rt, k, V, k, M1);
-    gram(ctx, dtype, N, k, Rt, k, R, k, Mr);
-    small_lu_solve2(ctx, k, M1, Mr, 1.0, al, nullptr, 0.0, nullptr, lu_eps);  // alpha = M1^-1 Rt^T R
+    {
+      const void* xs[2] = {Rt, Rt};
+      const void* ys[2] = {V, R};
+      double* os[2] = {m1, mr};
+      col_dots(ctx, dtype, N, k, 2, xs, ys, os);
+    }
+    small_diag_ratio(ctx, k, mr, m1, 1.0, al);  // alpha_j = (rt_j^T r_j) / (rt_j^T v_j)
     BKTS_HIP(hipMemcpyAsync(Sb, R, blk, hipMemcpyDeviceToDevice, ctx->stream));
     block_rmul(ctx, dtype, N, k, V, k, al, 1.0, -1.0, Sb, k);  // S = R - V alpha
     scale_rows(ctx, dtype, N, k, dinv, Sb, Sh);
     spmm(ctx, op, dtype, k, 0.0, nullptr, k, a, Sh, k, b, T, k);  // T = A D^-1 S
-    gram(ctx, dtype, N, k, T, k, Sb, k, TS);
-    gram(ctx, dtype, N, k, T, k, T, k, TT);
-    small_omega(ctx, k, TS, TT, om);
-    block_rmul(ctx, dtype, N, k, Ph, k, al, 1.0, 1.0, X, k);  // X += D^-1 P alpha
-    axpy_ds(ctx, dtype, N * k, om, 1.0, Sh, X);               //    + omega D^-1 S
+    {
+      const void* xs[3] = {T, T, Rt};
+      const void* ys[3] = {Sb, T, T};
+      double* os[3] = {ts, tt, m3};
+      col_dots(ctx, dtype, N, k, 3, xs, ys, os);
+    }
+    small_diag_ratio(ctx, k, ts, tt, 1.0, W);  // omega_j = (t_j^T s_j) / (t_j^T t_j)
     BKTS_HIP(hipMemcpyAsync(R, Sb, blk, hipMemcpyDeviceToDevice, ctx->stream));
-    axpy_ds(ctx, dtype, N * k, om, -1.0, T, R);  // R = S - omega T
+    block_rmul(ctx, dtype, N, k, T, k, W, 1.0, -1.0, R, k);  // R = S - T omega
     colnorms2(ctx, dtype, N, k, R, k, nrmd);
     read_host(ctx, nrmd, k, nrm);
+    bool finite = true;
+    for (double v : nrm) finite = finite && std::isfinite(v);
+    if (!finite) {  // breakdown: keep the last iterate (X is updated only after its residual is known)
+      st.breakdown = 1;
+      st.converged = 0;
+      return;
+    }
+    block_rmul(ctx, dtype, N, k, Ph, k, al, 1.0, 1.0, X, k);  // X += D^-1 P alpha
+    block_rmul(ctx, dtype, N, k, Sh, k, W, 1.0, 1.0, X, k);   //    + D^-1 S omega
     st.iterations = it;
     if (converged(nrm, nrm0, rtol, &st.max_rel, true)) {
       st.converged = 1;
       return;
     }
-    gram(ctx, dtype, N, k, Rt, k, T, k, M3);
-    small_lu_solve2(ctx, k, M1, M3, -1.0, be, nullptr, 0.0, nullptr, lu_eps);  // beta = -M1^-1 Rt^T T
-    axpy_ds(ctx, dtype, N * k, om, -1.0, V, P);                               // P - omega V
+    small_diag_ratio(ctx, k, m3, m1, -1.0, be);              // beta_j = -(rt_j^T t_j) / (rt_j^T v_j)
+    block_rmul(ctx, dtype, N, k, V, k, W, 1.0, -1.0, P, k);   // P - V omega
     BKTS_HIP(hipMemcpyAsync(Pn, R, blk, hipMemcpyDeviceToDevice, ctx->stream));
-    block_rmul(ctx, dtype, N, k, P, k, be, 1.0, 1.0, Pn, k);  // P = R + (P - omega V) beta
+    block_rmul(ctx, dtype, N, k, P, k, be, 1.0, 1.0, Pn, k);  // P = R + (P - V omega) beta
     std::swap(P, Pn);
   }
   st.converged = 0;

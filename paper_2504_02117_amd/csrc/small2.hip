@@ -176,6 +176,18 @@ __global__ void omega_kernel(int k, const double* TS, const double* TT, double* 
   out[0] = b > 0.0 ? a / b : 0.0;
 }
 
+__global__ void diag_ratio_kernel(int k, const double* a, const double* b, double sign, double* out) {
+  for (int e = threadIdx.x; e < k * k; e += blockDim.x) {
+    const int i = e / k, j = e % k;
+    double v = 0.0;
+    if (i == j) {
+      const double q = sign * a[i] / b[i];
+      v = (b[i] != 0.0 && isfinite(q)) ? q : 0.0;
+    }
+    out[e] = v;
+  }
+}
+
 constexpr int kLsqMax = 64;  // rows of the block Hessenberg system handled in LDS
 
 // Least squares min || [S; 0] - H Y ||_F for the block upper Hessenberg H with nr = (j+2)k rows and
@@ -287,6 +299,12 @@ void small_lu_solve2(bkts_ctx ctx, int k, const double* M, const double* B1, dou
 void small_omega(bkts_ctx ctx, int k, const double* TS, const double* TT, double* out) {
   ProfScope prof(ctx, BKTS_K_SMALL, 16.0 * k * k);
   launch(ctx, omega_kernel, dim3(1), dim3(64), 0, k, TS, TT, out);
+  BKTS_HIP(hipGetLastError());
+}
+
+void small_diag_ratio(bkts_ctx ctx, int k, const double* A, const double* B, double sign, double* out) {
+  ProfScope prof(ctx, BKTS_K_SMALL, 24.0 * k);
+  launch(ctx, diag_ratio_kernel, dim3(1), dim3(256), 0, k, A, B, sign, out);
   BKTS_HIP(hipGetLastError());
 }
 
