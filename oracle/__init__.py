@@ -22,6 +22,10 @@ method converges to, by the plain definitions:
                    or simple iterative per-stage solve (Sec. 2,
                    eq. stiffly-accurate-DIRK) -- the result the all-at-once
                    method must reproduce.
+* ``richards``     Richards' equation with the van Genuchten closure on an FV grid
+                   (Sec. 4.3, eq. RelationshipsThetaK), its exact Jacobian, the
+                   window residual with a split mass term and sequential implicit
+                   Euler with Newton and direct solves.
 * ``blockops``     plain definitions of the block kernels (block operator,
                    Gram matrices, block solves) used for kernel parity.
 
