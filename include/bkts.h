@@ -268,10 +268,12 @@ bkts_status bkts_nlop_create(bkts_ctx ctx, const bkts_grid* grid, const bkts_nl_
 void bkts_nlop_destroy(bkts_nlop nl);
 /* F[:, j] = f(Y[:, j]) for an N x k device block (row-major, leading dimensions ldy, ldf). */
 bkts_status bkts_nl_eval(bkts_ctx ctx, bkts_nlop nl, int k, const double* Y, int ldy, double* F, int ldf);
-/* Assemble J = alpha I + beta Df(u) on the stencil sparsity (u: device, N doubles) and return it as an
- * operator handle owned by `nl` (valid until the next call or bkts_nlop_destroy; do not destroy it). */
+/* Assemble J = alpha m'(u) + beta Df(u) on the stencil sparsity (m' = 1 for the diffusion-reaction
+ * operator; see Richards below) (u: device, N doubles) and return it as an operator handle owned
+ * by `nl` (valid until the next call or bkts_nlop_destroy; do not destroy it). */
 bkts_status bkts_nl_jacobian(bkts_ctx ctx, bkts_nlop nl, const double* u, double alpha, double beta, bkts_op* J);
-/* The nonlinear all-at-once residual R = Y A1^T + F(Y) A2^T - B0 (Sec. 2.2) for the window
+/* The nonlinear all-at-once residual R = m(Y) A1^T + F(Y) A2^T - B0 (Sec. 2.2; m = identity except
+ * for Richards' equation, where m = theta) for the window
  * matrices of `phase`; arguments as bkts_residual. */
 bkts_status bkts_nl_residual(bkts_ctx ctx, bkts_nlop nl, bkts_tc tc, int phase, const double* Y, int ldy,
                              const double* B0, int ldb0, int nb0, double* R, int ldr, double* col_norms2);
@@ -283,6 +285,32 @@ bkts_status bkts_nl_residual(bkts_ctx ctx, bkts_nlop nl, bkts_tc tc, int phase, 
  * Synchronises. */
 bkts_status bkts_newton_step(bkts_ctx ctx, bkts_nlop nl, bkts_tc tc, int phase, const double* B0, int ldb0, int nb0,
                              double* Y, double* col_norms2, const bkts_solve_opts* opts, bkts_solve_info* info);
+
+/* Richards' equation (Sec. 4.3): d/dt theta(psi) - div(K(psi) grad(psi + z)) = 0 for the pressure
+ * head psi on a cell-centred FV grid of the unit square/cube whose LAST axis is the height z, with
+ * the van Genuchten closure of eq. RelationshipsThetaK (theta = theta_r + (theta_s - theta_r) Se,
+ * Se = (1 + (alpha |psi|)^n)^(-m), m = 1 - 1/n, Se = 1 for psi >= 0; K = Ks s^(1/2)(1 - (1 -
+ * s^(1/m))^m)^2 with s = theta / theta_s as printed in the paper).  Faces: K_f = harmonic mean of
+ * Ks times the arithmetic mean of K/Ks; top face Dirichlet psi = top_value (half a cell away) or no
+ * flow; bottom face free drainage (unit head gradient, outflow Ks kr(psi)) or no flow; lateral faces
+ * no flow.  As an operator for the calls above: f(psi) = -div_h(K grad_h(psi + z)), the mass term
+ * is theta(psi) (Algorithm 1 uses theta(Y) A1^T + F(Y) A2^T - B0), and the Jacobian is
+ * alpha m'(psi) + beta Df(psi) with m' = theta' (Newton) or the constant lin_L > 0 (L-scheme). */
+enum { BKTS_RI_NO_FLOW = 0, BKTS_RI_DIRICHLET = 1, BKTS_RI_FREE_DRAINAGE = 2 };
+typedef struct bkts_richards_params {
+  double theta_r, theta_s, alpha, n;  /* van Genuchten parameters (n > 1) */
+  int top;                            /* BKTS_RI_DIRICHLET or BKTS_RI_NO_FLOW */
+  double top_value;                   /* psi on the top face when Dirichlet */
+  int bottom;                         /* BKTS_RI_FREE_DRAINAGE or BKTS_RI_NO_FLOW */
+  double lin_L;                       /* 0: Newton; > 0: L-scheme constant for theta' */
+} bkts_richards_params;
+/* ks: device, N saturated conductivities > 0 (copied).  Errors: NULL arguments, dim outside 1..3,
+ * n <= 1, alpha <= 0, theta_s <= theta_r < 0, an unknown top/bottom type, lin_L < 0. */
+bkts_status bkts_richards_create(bkts_ctx ctx, const bkts_grid* grid, const double* ks,
+                                 const bkts_richards_params* params, bkts_nlop* out);
+/* M[:, j] = m(Y[:, j]): psi -> theta(psi) for Richards, the identity for the diffusion-reaction
+ * operator (device, N x k row-major blocks). */
+bkts_status bkts_nl_mass(bkts_ctx ctx, bkts_nlop nl, int k, const double* Y, int ldy, double* M, int ldm);
 
 /* A persistent Algorithm 1 pipeline: the window of k stages and the history
  * of the front step survive between calls, so consecutive

@@ -26,6 +26,7 @@ BKTS_F64, BKTS_F32 = 0, 1
 BKTS_FMT_CSR, BKTS_FMT_SELL = 0, 1
 BKTS_BC_DIRICHLET, BKTS_BC_NEUMANN = 0, 1
 BKTS_IE, BKTS_THETA, BKTS_SDIRK2, BKTS_DIRK_CUSTOM = 0, 1, 2, 3
+BKTS_RI_NO_FLOW, BKTS_RI_DIRICHLET, BKTS_RI_FREE_DRAINAGE = 0, 1, 2
 BKTS_CG, BKTS_GMRES, BKTS_BICGSTAB = 0, 1, 2
 BKTS_PREC_NONE, BKTS_PREC_JACOBI = 0, 1
 BKTS_PRECISION_F64, BKTS_PRECISION_F32_REFINE = 0, 1
@@ -73,6 +74,11 @@ class bkts_run_info(C.Structure):
 class bkts_nl_coeffs(C.Structure):
     _fields_ = [("dcoef", C.c_double * 4), ("rcoef", C.c_double * 4), ("bc_type", C.c_int * 6),
                 ("bc_value", C.c_double * 6)]
+
+
+class bkts_richards_params(C.Structure):
+    _fields_ = [("theta_r", C.c_double), ("theta_s", C.c_double), ("alpha", C.c_double), ("n", C.c_double),
+                ("top", C.c_int), ("top_value", C.c_double), ("bottom", C.c_int), ("lin_L", C.c_double)]
 
 
 class bkts_request(C.Structure):
@@ -133,6 +139,8 @@ _SIGS = {
     "bkts_newton_step": (_I, [_P, _P, _P, _I, _P, _I, _I, _P, _P, C.POINTER(bkts_solve_opts),
                               C.POINTER(bkts_solve_info)]),
     "bkts_nl_stepper_create": (_I, [_P, _P, _P, _P, C.POINTER(_P)]),
+    "bkts_richards_create": (_I, [_P, C.POINTER(bkts_grid), _P, C.POINTER(bkts_richards_params), C.POINTER(_P)]),
+    "bkts_nl_mass": (_I, [_P, _P, _I, _P, _I, _P, _I]),
     "bkts_server_create": (_I, [_P, C.c_size_t, _I, C.POINTER(_P)]),
     "bkts_server_submit": (_I, [_P, C.POINTER(bkts_request), C.POINTER(C.c_uint64)]),
     "bkts_server_poll": (_I, [_P, C.POINTER(bkts_result), _I, C.POINTER(_I)]),
@@ -444,6 +452,23 @@ def bkts_nl_stepper_create(ctx, nl, tc, y0):
     out = C.c_void_p()
     _check(_lib.bkts_nl_stepper_create(ctx, nl, tc, _ptr(y0), C.byref(out)))
     return out.value
+
+
+def bkts_richards_create(ctx, n, ks, theta_r=0.05, theta_s=0.4, alpha=2.0, vg_n=2.0, top=BKTS_RI_DIRICHLET,
+                         top_value=0.0, bottom=BKTS_RI_FREE_DRAINAGE, lin_L=0.0):
+    """Richards operator on the grid ``n`` (last axis = height) with the float64 device tensor ``ks``
+    of saturated conductivities (copied)."""
+    p = bkts_richards_params(theta_r, theta_s, alpha, vg_n, int(top), top_value, int(bottom), lin_L)
+    g = _grid(n)
+    out = C.c_void_p()
+    _check(_lib.bkts_richards_create(ctx, C.byref(g), _ptr(ks), C.byref(p), C.byref(out)))
+    return out.value
+
+
+def bkts_nl_mass(ctx, nl, Y, M):
+    """M[:, j] = m(Y[:, j]) for (N, k) float64 device tensors."""
+    k = Y.shape[1]
+    _check(_lib.bkts_nl_mass(ctx, nl, k, _ptr(Y), Y.stride(0), _ptr(M), M.stride(0)))
 
 
 def bkts_server_create(ctx, hbm_budget_bytes, max_slots=64):

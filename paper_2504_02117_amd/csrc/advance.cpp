@@ -1,3 +1,4 @@
+#include <algorithm>
 // Algorithm 1 (Block Krylov Time Stepping with Pipelining) for the linear problem y' + K y = b.
 //
 // The window Y holds k consecutive implicit stages.  Each outer iteration forms the fused FP64
@@ -91,6 +92,42 @@ void bkts_stepper_s::eval_f(const double* x, int ldx, double* out, int ldo) {  /
   bkts::spmm(ctx, *op, BKTS_F64, 1, -1.0, bsrc, 1, 0.0, x, ldx, 1.0, out, ldo);
 }
 
+// Safeguard of the Newton form (not part of Algorithm 1): the later slots of the window are
+// updated with the front stage's Jacobian, and when the problem changes quickly over the window
+// (a wetting front in Richards' equation) their iterates can diverge even though the front stage
+// converges.  A later slot whose residual norm becomes non-finite or exceeds kGrowth times its norm
+// at stage entry is rolled back by its last update and takes no further update this stage; at the
+// shift it restarts from the converged front stage, the initial guess sequential stepping would
+// use.  The front stage is never touched, so the accepted steps are those of plain Newton.
+void bkts_stepper_s::guard_window(int it, int off, const std::vector<double>& hn, std::vector<double>& ref,
+                                  std::vector<char>& active, std::vector<char>& frozen) {
+  using namespace bkts;
+  constexpr double kGrowth = 10.0;
+  const int64_t N = op->N;
+  const int k = tc->k;
+  double* Yp = Y.as<double>();
+  double* Rp = R.as<double>();
+  double* Vp = V.as<double>();
+  for (int j = 0; j < k; ++j) {
+    if (j == off) continue;
+    const double r = std::sqrt(hn[j]);
+    if (it == 0) {
+      ref[j] = r;
+      if (std::isfinite(r)) continue;
+      copy_col(ctx, N, Yp, k, off, j);  // defensive: no finite iterate to roll back to
+    } else {
+      if (!active[j] || (std::isfinite(r) && r <= kGrowth * ref[j])) continue;
+      LinComb back;  // Y_j += V_j undoes the last update
+      back.add(1.0, Yp + j, k);
+      back.add(1.0, Vp + j, k);
+      lincomb(ctx, N, back, Yp + j, k);
+    }
+    active[j] = 0;
+    frozen[j] = 1;
+    copy_col(ctx, N, Rp, k, off, j);  // a finite right-hand side for the block solve
+  }
+}
+
 bkts_status bkts_stepper_s::advance(int n_steps, const bkts_solve_opts& inner, double outer_rtol, int max_outer,
                                     double* y_hist, bkts_step_cb cb, void* user, bkts_run_info* info) {
   using namespace bkts;
@@ -108,15 +145,25 @@ bkts_status bkts_stepper_s::advance(int n_steps, const bkts_solve_opts& inner, d
   double* nrmp = nrm.as<double>();
   bkts_run_info ri{};
   std::vector<double> hn;
+  // Newton form: per window slot, the residual norm at stage entry, whether the slot still takes
+  // updates this stage, and whether it was frozen this stage.
+  std::vector<double> ref(k, 0.0);
+  std::vector<char> active(k, 1), frozen(k, 0);
   bkts_status status = BKTS_OK;
   int done = 0;
   while (done < n_steps) {
     // B0 columns of the window: stages q = phase + i of the front step (Sec. 2.2)
     const int nb0 = std::min(mi - phase, k);
+    // m(y^n): identity, or theta(psi^n) for Richards' equation
+    const double* myp = yp;
+    if (nl && nl->nd.kind != 0) {
+      nl_mass(ctx, *nl, 1, yp, 1, tmp.as<double>(), 1);
+      myp = tmp.as<double>();
+    }
     for (int i = 0; i < nb0; ++i) {
       const int q = phase + i;
       LinComb lc;
-      lc.add(1.0 / tau, yp, 1);
+      lc.add(1.0 / tau, myp, 1);
       for (int j = 0; j < phase; ++j) lc.add(-tc->Ai[q * mi + j], fstp + j, mi);
       if (tc->explicit_first) lc.add(-tc->ae[q], fyn.as<double>(), 1);
       lincomb(ctx, N, lc, B0p + i, mi);
@@ -146,6 +193,7 @@ bkts_status bkts_stepper_s::advance(int n_steps, const bkts_solve_opts& inner, d
       read_vec(ctx, nrmp, k + 1, hn);
       const double rhs0 = std::sqrt(hn[k]);
       const double front = std::sqrt(hn[off]);
+      if (nl && k > 1) guard_window(it, off, hn, ref, active, frozen);
       ri.final_front_rel_residual = rhs0 > 0.0 ? front / rhs0 : front;
       if (!std::isfinite(front)) throw Error{BKTS_EBREAKDOWN, "non-finite residual in the time window"};
       if (front <= outer_rtol * rhs0) {
@@ -157,6 +205,8 @@ bkts_status bkts_stepper_s::advance(int n_steps, const bkts_solve_opts& inner, d
       if (nl) {  // Newton: J = I/tau + a_kk Df(front column), used for every column of the window
         nl_jacobian(ctx, *nl, Yp + off, k, 1.0 / tau, beta);
         solve(ctx, *nl->jac, 0.0, 1.0, k, Rp, Vp, true, inner, true, ks);
+        for (int j = 0; j < k; ++j)
+          if (!active[j]) lincomb(ctx, N, LinComb{}, Vp + j, k);  // frozen slots take no update
       } else {
         solve(ctx, *op, 1.0 / tau, beta, k, Rp, Vp, true, inner, true, ks);
       }
@@ -170,6 +220,13 @@ bkts_status bkts_stepper_s::advance(int n_steps, const bkts_solve_opts& inner, d
       set_last_error(fmt("front stage not converged after %d outer iterations (rel. residual %.3e)", max_outer,
                          ri.final_front_rel_residual));
       break;
+    }
+    // slots frozen during this stage restart from the converged front stage
+    if (nl) {
+      for (int j = 0; j < k; ++j)
+        if (frozen[j] && j != off) copy_col(ctx, N, Yp, k, off, j);
+      std::fill(frozen.begin(), frozen.end(), 0);
+      std::fill(active.begin(), active.end(), 1);
     }
     // accept the front stage
     if (phase == mi - 1) {

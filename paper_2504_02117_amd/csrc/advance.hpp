@@ -1,5 +1,7 @@
-// Algorithm 1, linear case (advance.cpp).
+// Algorithm 1, linear and Newton forms (advance.cpp).
 #pragma once
+
+#include <vector>
 
 #include "internal.hpp"
 
@@ -17,6 +19,8 @@ struct bkts_stepper_s {
   void eval_f(const double* x, int ldx, double* out, int ldo);
   bkts_status advance(int n_steps, const bkts_solve_opts& inner, double outer_rtol, int max_outer, double* y_hist,
                       bkts_step_cb cb, void* user, bkts_run_info* info);
+  void guard_window(int it, int off, const std::vector<double>& hn, std::vector<double>& ref,
+                    std::vector<char>& active, std::vector<char>& frozen);
 };
 
 namespace bkts {

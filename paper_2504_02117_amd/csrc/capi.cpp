@@ -359,6 +359,29 @@ bkts_status bkts_nlop_create(bkts_ctx ctx, const bkts_grid* grid, const bkts_nl_
   BKTS_API_END
 }
 
+bkts_status bkts_richards_create(bkts_ctx ctx, const bkts_grid* grid, const double* ks,
+                                 const bkts_richards_params* params, bkts_nlop* out) {
+  BKTS_API_BEGIN
+  check_ctx(ctx);
+  BKTS_REQUIRE(out, "out must not be NULL");
+  *out = nullptr;
+  set_device(ctx);
+  *out = bkts::richards_create(ctx, grid, ks, params);
+  BKTS_API_END
+}
+
+bkts_status bkts_nl_mass(bkts_ctx ctx, bkts_nlop nl, int k, const double* Y, int ldy, double* M, int ldm) {
+  BKTS_API_BEGIN
+  check_ctx(ctx);
+  BKTS_REQUIRE(nl && nl->ctx == ctx, "nl must belong to ctx");
+  check_k(k);
+  check_block(Y, k, ldy, "Y");
+  check_block(M, k, ldm, "M");
+  set_device(ctx);
+  bkts::nl_mass(ctx, *nl, k, Y, ldy, M, ldm);
+  BKTS_API_END
+}
+
 void bkts_nlop_destroy(bkts_nlop nl) {
   if (!nl) return;
   (void)hipSetDevice(nl->ctx->device);

@@ -142,12 +142,20 @@ struct bkts_op_s {
 namespace bkts {
 
 struct NlDev {
+  int kind;  // 0: diffusion-reaction (mass = identity), 1: Richards (mass = theta(psi))
   int dim;
   int n[3];
   double w[3];  // 1 / h_d^2
+  // diffusion-reaction
   double dc[4], rc[4];
   int bc_type[6];
   double bc_val[6];
+  // Richards: van Genuchten closure, saturated conductivity per cell, z = last axis
+  double tr, ts, alpha, vn, vm;
+  const double* ks;
+  int top_dirichlet, bottom_drain;
+  double top_g, top_kr, hz;
+  double lin_L;  // > 0: the mass derivative in the Jacobian is this constant (L-scheme)
 };
 
 }  // namespace bkts
@@ -157,6 +165,7 @@ struct bkts_nlop_s {
   bkts::NlDev nd{};
   int64_t N = 0;
   bkts_op jac = nullptr;  // stencil sparsity; values overwritten by bkts_nl_jacobian
+  bkts::DevBuf ks;        // Richards: own copy of the saturated conductivity
   ~bkts_nlop_s() { delete jac; }
 };
 
@@ -211,6 +220,9 @@ void op_refresh_values(bkts_op op);  // after CSR values changed: diag, SELL val
 bkts_nlop nlop_create(bkts_ctx ctx, const bkts_grid* grid, const bkts_nl_coeffs* c);
 // F[:, j] = f(Y[:, j]) for j < k
 void nl_eval(bkts_ctx ctx, const bkts_nlop_s& nl, int k, const double* Y, int ldy, double* F, int ldf);
+// Mass term of the semi-discrete problem, column-wise: M[:, j] = m(Y[:, j]) (identity or theta)
+void nl_mass(bkts_ctx ctx, const bkts_nlop_s& nl, int k, const double* Y, int ldy, double* M, int ldm);
+bkts_nlop richards_create(bkts_ctx ctx, const bkts_grid* grid, const double* ks, const bkts_richards_params* p);
 // nl.jac values = alpha I + beta Df(u) (u: column with stride ldu)
 void nl_jacobian(bkts_ctx ctx, bkts_nlop_s& nl, const double* u, int ldu, double alpha, double beta);
 // R = Y A1^T + F(Y) A2^T - B0 with column norms (A1, A2 device, row-major, physical order)

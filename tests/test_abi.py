@@ -112,3 +112,5 @@ def test_server_null_handles_rejected():
     assert lib.bkts_server_clock(None) == 0.0
     lib.bkts_server_destroy(None)
     assert lib.bkts_nlop_create(None, None, None, C.byref(out)) == bkts.BKTS_EINVAL
+    assert lib.bkts_richards_create(None, None, None, None, C.byref(out)) == bkts.BKTS_EINVAL
+    assert lib.bkts_nl_mass(None, None, 1, None, 1, None, 1) == bkts.BKTS_EINVAL
