@@ -62,6 +62,11 @@ def parse():
     p.add_argument("--nl-steps", type=int, default=8)
     p.add_argument("--nl-inner-rtol", type=float, default=0.1,
                    help="inner tolerance of the timed block form (the paper's 1e-5 is timed beside it)")
+    p.add_argument("--ri-n", type=int, default=96, help="Richards leg: grid n^3 (0 = skip)")
+    p.add_argument("--ri-k", type=int, default=16, help="Richards leg: window columns (implicit Euler steps)")
+    p.add_argument("--ri-steps", type=int, default=4)
+    p.add_argument("--ri-inner-rtol", type=float, default=1e-4,
+                   help="inner tolerance (looser tolerances let Newton diverge at 96^3, tau=1e-3)")
     p.add_argument("--sweep", type=str, default="1f32,4f64,4f32@0.01,8,16,32",
                    help="comma list of extra block forms to time: <k>[f32|f64][@inner_rtol] (defaults: --precision, "
                         "--inner-rtol)")
@@ -325,6 +330,94 @@ def run_nonlinear(torch, bkts, ctx, a):
             "kernels": {kk: {"avg_us": vv["avg_us"], "GBps": vv["GBps"]} for kk, vv in blk["kernels"].items()}}
 
 
+def run_richards(torch, bkts, ctx, a):
+    """Richards' equation (Sec. 4.3): van Genuchten closure (alpha=2, n=2, theta_r=0.05, theta_s=0.4),
+    lognormal Ks (log-std 1.5, corr. 8 cells), hydrostatic start psi0 = -z, Dirichlet psi = -0.3 on top,
+    free drainage below, implicit Euler tau = 1e-3, Newton to 1e-8."""
+    import numpy as np
+
+    from paper_2504_02117_amd import inputs
+
+    tau, g = 1e-3, -0.3
+
+    def setup(n, corr):
+        ks = torch.from_numpy(inputs.lognormal_field(n, 0.0, 1.5, corr, 1).ravel()).cuda()
+        z = (np.arange(n[2]) + 0.5) / n[2]
+        y0 = np.ascontiguousarray(np.broadcast_to(-z[:, None, None], inputs.field_shape(n)).ravel())
+        return ks, y0
+
+    def form(n, ks, y0, k, krylov, precision, steps, warmup, profile, hist=False):
+        nl = bkts.bkts_richards_create(ctx, n, ks, top=bkts.BKTS_RI_DIRICHLET, top_value=g,
+                                       bottom=bkts.BKTS_RI_FREE_DRAINAGE)
+        tc = bkts.bkts_tc_create(ctx, bkts.BKTS_IE, k, tau)
+        st = bkts.bkts_nl_stepper_create(ctx, nl, tc, torch.from_numpy(y0).cuda())
+        inner = bkts.solve_opts(krylov=krylov, precision=precision, rtol=a.ri_inner_rtol,
+                                inner_rtol=a.ri_inner_rtol, maxit=4000, restart=30)
+        N = n[0] * n[1] * n[2]
+        t_start = time.perf_counter()
+
+        def cb(step, t, y, user):
+            log(f"    step {step} ({time.perf_counter() - t_start:.1f} s)")
+        try:
+            if warmup:
+                bkts.bkts_stepper_advance(st, warmup, inner=inner, outer_rtol=1e-8, max_outer=60, cb=cb)
+            h = torch.empty((steps, N), dtype=torch.float64, device="cuda") if hist else None
+            bkts.bkts_profile_enable(ctx, profile, period=TIMER_PERIOD)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            info = bkts.bkts_stepper_advance(st, steps, inner=inner, outer_rtol=1e-8, max_outer=60, y_hist=h)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            kt = kernel_table(bkts, ctx) if profile else {}
+            bkts.bkts_profile_enable(ctx, False)
+            return dict(seconds=dt, info=info, kernels=kt, value=N * steps / dt, hist=h)
+        finally:
+            bkts.bkts_stepper_destroy(st)
+            bkts.bkts_tc_destroy(tc)
+            bkts.bkts_nlop_destroy(nl)
+
+    GM, BI = bkts.BKTS_GMRES, bkts.BKTS_BICGSTAB
+    F32, F64 = bkts.BKTS_PRECISION_F32_REFINE, bkts.BKTS_PRECISION_F64
+    n = (a.ri_n,) * 3
+    ks, y0 = setup(n, 8.0)
+    res = {}
+    for name, k, kry, prec in (("block_gmres", a.ri_k, GM, F32), ("block_bicgstab", a.ri_k, BI, F32),
+                               ("plain_gmres", 1, GM, F64), ("plain_bicgstab", 1, BI, F64)):
+        log(f"Richards leg {n}: {name} k={k}, inner {a.ri_inner_rtol:g}, {a.ri_steps} steps")
+        r = form(n, ks, y0, k, kry, prec, a.ri_steps, 1, name == "block_gmres")
+        log(f"  {r['value']:.4g} DOF*steps/s, outer={r['info'].outer_iterations} "
+            f"krylov={r['info'].krylov_iterations}")
+        res[name] = r
+    # parity of the block GMRES configuration on a 16 x 16 x 20 grid against sequential implicit Euler
+    from oracle import richards as ori
+    m = (16, 16, 20)
+    ks_m, y0_m = setup(m, 8.0 * 16 / 96)
+    chk = form(m, ks_m, y0_m, a.ri_k, GM, F32, 4, 0, False, hist=True)
+    ref = ori.Richards(m, ks_m.cpu().numpy(), ori.VanGenuchten(), top=("dirichlet", g), bottom="free_drainage")
+    ys, _ = ori.implicit_euler(ref, y0_m, tau, 4)
+    got = chk["hist"].cpu().numpy()
+    err = max(float(np.abs(got[s_] - ys[s_ + 1]).max() / np.abs(ys[s_ + 1]).max()) for s_ in range(4))
+    blk = res["block_gmres"]
+    roof = None
+    if blk["kernels"]:
+        dom = max((c for c in blk["kernels"] if c not in ("small", "other")),
+                  key=lambda c: blk["kernels"][c]["total_ms"])
+        roof = roofline_of(blk["kernels"], dom, a.ri_k, "f32")
+        roof["kernel"] = {"spmm": "spmm_ell_kernel", "residual": "nl_residual_kernel"}.get(dom, roof["kernel"])
+    best = max(res, key=lambda t: res[t]["value"])
+    return {"workload": f"Richards' equation {a.ri_n}^3 FV, van Genuchten alpha=2 n=2 theta_r=0.05 theta_s=0.4, "
+                        f"lognormal Ks (log-std 1.5, corr. 8 cells), psi0=-z, Dirichlet psi=-0.3 on top, free "
+                        f"drainage below, implicit Euler tau=1e-3, {a.ri_k} columns, Newton to 1e-8, block GMRES(30) "
+                        f"inner {a.ri_inner_rtol:g} in FP32 with FP64 residuals, Jacobi",
+            "value": blk["value"], "unit": "DOF*timesteps/s", "ms_per_step": 1e3 * blk["seconds"] / a.ri_steps,
+            "forms": {kk: {"value": v["value"], "outer_iterations": v["info"].outer_iterations,
+                           "krylov_iterations": v["info"].krylov_iterations} for kk, v in res.items()},
+            "fastest_form": best,
+            "speedup_vs_plain": blk["value"] / max(res["plain_gmres"]["value"], res["plain_bicgstab"]["value"]),
+            "oracle_max_rel_err_16x16x20": err, "roofline": roof,
+            "kernels": {kk: {"avg_us": vv["avg_us"], "GBps": vv["GBps"]} for kk, vv in blk["kernels"].items()}}
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -405,6 +498,11 @@ def main():
         nonlinear = run_nonlinear(torch, bkts, ctx, a)
         log(f"  nonlinear: oracle rel. error at 256^2 {nonlinear['oracle_max_rel_err_256']:.2e}")
 
+    richards = None
+    if a.ri_n > 0:
+        richards = run_richards(torch, bkts, ctx, a)
+        log(f"  Richards: oracle rel. error at 16x16x20 {richards['oracle_max_rel_err_16x16x20']:.2e}")
+
     serving = None
     if a.serve_requests > 0:
         serving = run_serving(torch, bkts, ctx, a)
@@ -456,6 +554,7 @@ def main():
         "kernels": blk["kernels"],
         "cpu_baseline": cpu,
         "nonlinear": nonlinear,
+        "richards": richards,
         "serving": serving,
     }
     print(json.dumps(out))
