@@ -338,9 +338,16 @@ void small_omega(bkts_ctx ctx, int k, const double* TS, const double* TT, double
 // out = diag(sign * a_j / b_j) as a k x k matrix, for device k-vectors a, b (0 where b_j is zero or
 // the ratio is not finite)
 void small_diag_ratio(bkts_ctx ctx, int k, const double* a, const double* b, double sign, double* out);
-int gmres_max_rows();
-void gmres_lsq(bkts_ctx ctx, int k, int nr, int nc, const double* H, int ldh, const double* S, double eps, double* Y,
-               double* resn);
+// Largest Hessenberg row count (m + 1)k that block GMRES may use for block width k.
+int gmres_max_rows(int k);
+// Incremental Householder QR of block column jb of the block Hessenberg matrix (rows (jb+2)k of H,
+// column-major with leading dimension ldh), with the triangular factor Rq, reflectors Vr (2k per
+// column), Br, and Gq = Q^T [S; 0] ((m+1)k x k row-major) kept between calls; resn = per-column
+// least-squares residual norms.
+void gmres_qr_step(bkts_ctx ctx, int k, int jb, const double* H, int ldh, const double* S, double* Rq, double* Vr,
+                   double* Br, double* Gq, double* resn);
+// Y (nc x k row-major) = R^-1 Gq over the first nc rows, dropping |R_ii| <= eps max|R_jj|.
+void gmres_backsolve(bkts_ctx ctx, int k, int nc, const double* Rq, int ldh, const double* Gq, double eps, double* Y);
 
 // k x k dense kernels on one workgroup (small.hip).
 // alpha = G^+ S with truncated Cholesky of the Jacobi-scaled G (threshold `eps`); writes

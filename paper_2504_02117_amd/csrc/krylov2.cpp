@@ -48,17 +48,23 @@ void block_gmres(bkts_ctx ctx, const bkts_op_s& op, int dtype, int k, double a, 
   const int64_t N = op.N;
   const size_t es = esize(dtype);
   const size_t blk = es * N * k;
-  int m = std::max(1, std::min(restart > 0 ? restart : 30, gmres_max_rows() / k - 1));
-  BKTS_REQUIRE(m >= 1, "block GMRES needs k <= %d", gmres_max_rows() / 2);
+  BKTS_REQUIRE(gmres_max_rows(k) / k >= 2, "block GMRES: block width %d too large", k);
+  const int m = std::max(1, std::min(restart > 0 ? restart : 30, gmres_max_rows(k) / k - 1));
   const std::string tag = dtype == BKTS_F64 ? "d" : "s";
   char* V = static_cast<char*>(ctx->ws.get("gm_V_" + tag, blk * (m + 1)));
   void* W = ctx->ws.get("gm_W_" + tag, blk);
   void* Z = ctx->ws.get("gm_Z_" + tag, blk);
   const int ldh = (m + 1) * k;
   const size_t kk = (size_t)k * k;
-  double* sm = ctx->ws.get<double>("gm_small", (size_t)ldh * m * k + 8 * kk + (size_t)m * k * k + 4 * k + 2);
+  const size_t hsz = (size_t)ldh * m * k;
+  double* sm = ctx->ws.get<double>("gm_small", 2 * hsz + (size_t)m * k * (2 * k + 1) + (size_t)ldh * k + 8 * kk +
+                                                   (size_t)m * k * k + 4 * k + 2);
   double* H = sm;
-  double* S = H + (size_t)ldh * m * k;
+  double* Rq = H + hsz;                   // triangular factor of H
+  double* Vr = Rq + hsz;                  // Householder vectors, 2k per column
+  double* Br = Vr + (size_t)m * k * 2 * k;
+  double* Gq = Br + (size_t)m * k;        // Q^T [S; 0]
+  double* S = Gq + (size_t)ldh * k;
   double* Gm = S + kk;
   double* Ri1 = Gm + kk;
   double* R1 = Ri1 + kk;
@@ -125,7 +131,7 @@ void block_gmres(bkts_ctx ctx, const bkts_op_s& op, int dtype, int k, double a, 
       }
       cholqr2(W, Vb(j + 1), Tm);  // W = V_{j+1} H_{j+1,j}
       hblock(ctx, k, Tm, H, ldh, (j + 1) * k, j * k, false);
-      gmres_lsq(ctx, k, (j + 2) * k, (j + 1) * k, H, ldh, S, lsq_eps, Y, resn);
+      gmres_qr_step(ctx, k, j, H, ldh, S, Rq, Vr, Br, Gq, resn);
       read_host(ctx, resn, k, res);
       ++total;
       jdone = j + 1;
@@ -135,6 +141,7 @@ void block_gmres(bkts_ctx ctx, const bkts_op_s& op, int dtype, int k, double a, 
         break;
       }
     }
+    gmres_backsolve(ctx, k, jdone * k, Rq, ldh, Gq, lsq_eps, Y);
     // X += D^-1 sum_i V_i Y_i
     BKTS_HIP(hipMemsetAsync(W, 0, blk, ctx->stream));
     for (int i = 0; i < jdone; ++i) block_rmul(ctx, dtype, N, k, Vb(i), k, Y + (size_t)i * kk, 1.0, 1.0, W, k);

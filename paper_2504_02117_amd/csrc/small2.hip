@@ -1,5 +1,7 @@
 // Single-workgroup k x k (and small block-Hessenberg) kernels for block GMRES and block BiCGStab.
 // Every coefficient stays on the device in FP64.
+#include <algorithm>
+
 #include "devcommon.hpp"
 #include "internal.hpp"
 
@@ -188,88 +190,149 @@ __global__ void diag_ratio_kernel(int k, const double* a, const double* b, doubl
   }
 }
 
-constexpr int kLsqMax = 64;  // rows of the block Hessenberg system handled in LDS
+// Block upper Hessenberg least squares of block GMRES, min || [S; 0] - H Y ||_F, by Householder QR
+// updated one block column per iteration.  H has block lower bandwidth k, so the reflector that
+// annihilates the sub-diagonal of column c = jb k + i spans rows c .. (jb + 2)k - 1 (2k - i rows).
+// State kept in device memory between calls: the triangular factor Rq (column-major, ldh), the
+// reflectors Vr (2k entries per column) with Br = 2 / v^T v (0 = identity), and Gq = Q^T [S; 0]
+// (row-major, k columns).  Columns of R whose diagonal is below eps * max|diag| are dropped by the
+// back substitution (their unknowns are set to zero), which covers directions deflated by CholQR.
+constexpr int kLsqRows = 512;        // rows of the Hessenberg system
+constexpr int kLsqLdsDoubles = 8000;  // dynamic LDS of one step: the new block column (jb + 2)k x k plus 2k x k rows of Gq
 
-// Least squares min || [S; 0] - H Y ||_F for the block upper Hessenberg H with nr = (j+2)k rows and
-// nc = (j+1)k columns (column-major in device memory with leading dimension ldh), by Householder
-// QR in LDS.  Writes Y (nc x k, row-major) and the per-column residual norms (k).  Columns of R
-// whose diagonal is below eps * max|diag| are dropped (their unknowns set to zero).
-__global__ __launch_bounds__(256) void gmres_lsq_kernel(int k, int nr, int nc, const double* __restrict__ H, int ldh,
-                                                        const double* __restrict__ S, double eps, double* Y,
-                                                        double* resn) {
-  __shared__ double A[kLsqMax][kLsqMax + 1];  // A[row][col]
-  __shared__ double Bm[kLsqMax][KM + 1];
-  __shared__ double v[kLsqMax];
-  __shared__ double red[256];
-  __shared__ double beta_s, rmax;
+// Threads per column: a power of two with tpc * k <= 256, at most one wavefront.
+__device__ __forceinline__ int lsq_tpc(int k) {
+  int t = 64;
+  while (t * k > 256 && t > 1) t >>= 1;
+  return t;
+}
+
+// Sum over the tpc consecutive lanes of a group (tpc divides the wavefront).
+__device__ __forceinline__ double group_sum(double v, int tpc) {
+  for (int off = tpc >> 1; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  return v;
+}
+
+// Block column jb: apply the earlier reflectors, compute k new ones, update Gq and the residual
+// norms ||rows (jb+1)k .. (jb+2)k-1 of Gq|| per right-hand side.  Row r of every column is touched
+// only by lane r % tpc of that column's group, so the reflector chain needs no barrier.
+__global__ __launch_bounds__(256) void gmres_qr_kernel(int k, int jb, const double* __restrict__ H, int ldh,
+                                                       const double* __restrict__ S, double* __restrict__ Rq,
+                                                       double* __restrict__ Vr, double* __restrict__ Br,
+                                                       double* __restrict__ Gq, double* __restrict__ resn) {
+  extern __shared__ double lds[];
+  __shared__ double vs[2 * KM];
+  __shared__ double bs;
+  const int nr = (jb + 2) * k, k2 = 2 * k, c0 = jb * k;
+  double* B = lds;            // nr x k: the new block column, B[r * k + i]
+  double* Gl = lds + nr * k;  // rows c0 .. c0 + 2k - 1 of Gq
   const int t = threadIdx.x;
-  for (int e = t; e < nr * nc; e += 256) {
-    const int r = e % nr, c = e / nr;
-    A[r][c] = H[(int64_t)c * ldh + r];
+  const int tpc = lsq_tpc(k);
+  const int col = t / tpc, lane = t % tpc;
+  const bool act = col < k;
+  for (int e = t; e < nr * k; e += blockDim.x) {
+    const int r = e / k, i = e % k;
+    B[e] = H[(int64_t)(c0 + i) * ldh + r];
   }
-  for (int e = t; e < nr * k; e += 256) {
-    const int r = e / k, c = e % k;
-    Bm[r][c] = r < k ? S[r * k + c] : 0.0;
+  for (int e = t; e < k2 * k; e += blockDim.x) {
+    const int r = e / k, i = e % k;
+    Gl[e] = r < k ? (jb == 0 ? S[r * k + i] : Gq[(int64_t)(c0 + r) * k + i]) : 0.0;
   }
   __syncthreads();
-  for (int j = 0; j < nc; ++j) {
-    // Householder vector of column j, rows j..nr-1
-    double s = 0.0;
-    for (int r = j + t; r < nr; r += 256) s += A[r][j] * A[r][j];
-    red[t] = s;
-    __syncthreads();
-    for (int off = 128; off > 0; off >>= 1) {
-      if (t < off) red[t] += red[t + off];
-      __syncthreads();
+  if (act) {
+    for (int c = 0; c < c0; ++c) {
+      const double beta = Br[c];
+      if (beta == 0.0) continue;
+      const int L = k2 - c % k;
+      const double* v = Vr + (int64_t)c * k2;
+      const int r0 = c + ((lane - c % tpc) % tpc + tpc) % tpc;
+      double d = 0.0;
+      for (int r = r0; r < c + L; r += tpc) d += v[r - c] * B[r * k + col];
+      d = beta * group_sum(d, tpc);
+      for (int r = r0; r < c + L; r += tpc) B[r * k + col] -= d * v[r - c];
     }
-    if (t == 0) {
-      const double nrm = sqrt(red[0]);
-      const double x0 = A[j][j];
+  }
+  __syncthreads();
+  for (int i = 0; i < k; ++i) {
+    const int c = c0 + i;
+    const int r0 = c + ((lane - c % tpc) % tpc + tpc) % tpc;
+    if (col == i) {
+      double ss = 0.0;
+      for (int r = r0; r < nr; r += tpc) ss += B[r * k + i] * B[r * k + i];
+      ss = group_sum(ss, tpc);
+      const double x0 = B[c * k + i];  // same value in every lane of the group
+      const double nrm = sqrt(ss);
       const double alpha = x0 >= 0.0 ? -nrm : nrm;
       const double v0 = x0 - alpha;
-      const double vn2 = red[0] - x0 * x0 + v0 * v0;
-      beta_s = vn2 > 0.0 ? 2.0 / vn2 : 0.0;
-      v[j] = v0;
-      A[j][j] = alpha;
+      const double vn2 = ss - x0 * x0 + v0 * v0;
+      const double beta = (nrm > 0.0 && vn2 > 0.0) ? 2.0 / vn2 : 0.0;
+      for (int r = r0; r < nr; r += tpc) vs[r - c] = r == c ? v0 : B[r * k + i];
+      if (lane == c % tpc && beta != 0.0) B[c * k + i] = alpha;
+      if (lane == 0) bs = beta;
     }
     __syncthreads();
-    for (int r = j + 1 + t; r < nr; r += 256) v[r] = A[r][j];
-    __syncthreads();
-    // apply to remaining columns of A and to Bm
-    const int ncols = (nc - j - 1) + k;
-    for (int cc = t; cc < ncols; cc += 256) {
-      const bool isA = cc < nc - j - 1;
-      const int col = isA ? j + 1 + cc : cc - (nc - j - 1);
-      double d = 0.0;
-      for (int r = j; r < nr; ++r) d += v[r] * (isA ? A[r][col] : Bm[r][col]);
-      d *= beta_s;
-      for (int r = j; r < nr; ++r) {
-        if (isA)
-          A[r][col] -= d * v[r];
-        else
-          Bm[r][col] -= d * v[r];
+    const double beta = bs;
+    if (act && beta != 0.0) {
+      if (col > i) {
+        double d = 0.0;
+        for (int r = r0; r < nr; r += tpc) d += vs[r - c] * B[r * k + col];
+        d = beta * group_sum(d, tpc);
+        for (int r = r0; r < nr; r += tpc) B[r * k + col] -= d * vs[r - c];
       }
+      // the same reflector on right-hand side `col`: local rows i .. 2k - 1 of Gl
+      const int g0 = i + ((lane - i % tpc) % tpc + tpc) % tpc;
+      double d = 0.0;
+      for (int r = g0; r < k2; r += tpc) d += vs[r - i] * Gl[r * k + col];
+      d = beta * group_sum(d, tpc);
+      for (int r = g0; r < k2; r += tpc) Gl[r * k + col] -= d * vs[r - i];
     }
-    __syncthreads();
-    for (int r = j + 1 + t; r < nr; r += 256) A[r][j] = 0.0;
+    if (t < k2) Vr[(int64_t)c * k2 + t] = t < k2 - i ? vs[t] : 0.0;
+    if (t == 0) Br[c] = beta;
     __syncthreads();
   }
-  if (t == 0) {
-    double m = 0.0;
-    for (int j = 0; j < nc; ++j) m = fmax(m, fabs(A[j][j]));
-    rmax = m;
+  for (int e = t; e < nr * k; e += blockDim.x) {
+    const int r = e / k, i = e % k;
+    Rq[(int64_t)(c0 + i) * ldh + r] = r <= c0 + i ? B[e] : 0.0;
   }
+  for (int e = t; e < k2 * k; e += blockDim.x) {
+    const int r = e / k, i = e % k;
+    Gq[(int64_t)(c0 + r) * k + i] = Gl[e];
+  }
+  if (t < k) {
+    double ss = 0.0;
+    for (int r = k; r < k2; ++r) ss += Gl[r * k + t] * Gl[r * k + t];
+    resn[t] = sqrt(ss);
+  }
+}
+
+// Y (nc x k, row-major) from R Y = Gq (first nc rows) by back substitution; lane r % tpc of each
+// right-hand side's group owns row r of Y and reads only the rows it wrote.
+__global__ __launch_bounds__(256) void gmres_backsolve_kernel(int k, int nc, const double* __restrict__ Rq, int ldh,
+                                                              const double* __restrict__ Gq, double eps,
+                                                              double* __restrict__ Y) {
+  __shared__ double red[256];
+  const int t = threadIdx.x;
+  double m = 0.0;
+  for (int i = t; i < nc; i += blockDim.x) m = fmax(m, fabs(Rq[(int64_t)i * ldh + i]));
+  red[t] = m;
   __syncthreads();
-  if (t < k) {  // back substitution for RHS column t
-    const int c = t;
-    for (int i = nc - 1; i >= 0; --i) {
-      double s = Bm[i][c];
-      for (int l = i + 1; l < nc; ++l) s -= A[i][l] * Y[l * k + c];
-      Y[i * k + c] = fabs(A[i][i]) > eps * rmax ? s / A[i][i] : 0.0;
+  for (int off = 128; off > 0; off >>= 1) {
+    if (t < off) red[t] = fmax(red[t], red[t + off]);
+    __syncthreads();
+  }
+  const double tol = eps * red[0];
+  const int tpc = lsq_tpc(k);
+  const int col = t / tpc, lane = t % tpc;
+  if (col >= k) return;
+  for (int i = nc - 1; i >= 0; --i) {
+    const int l0 = i + 1 + ((lane - (i + 1) % tpc) % tpc + tpc) % tpc;
+    double s = 0.0;
+    for (int l = l0; l < nc; l += tpc) s += Rq[(int64_t)l * ldh + i] * Y[(int64_t)l * k + col];
+    s = group_sum(s, tpc);
+    if (lane == i % tpc) {
+      const double rii = Rq[(int64_t)i * ldh + i];
+      Y[(int64_t)i * k + col] = fabs(rii) > tol ? (Gq[(int64_t)i * k + col] - s) / rii : 0.0;
     }
-    double rr = 0.0;
-    for (int r = nc; r < nr; ++r) rr += Bm[r][c] * Bm[r][c];
-    resn[c] = sqrt(rr);
   }
 }
 
@@ -308,13 +371,25 @@ void small_diag_ratio(bkts_ctx ctx, int k, const double* A, const double* B, dou
   BKTS_HIP(hipGetLastError());
 }
 
-int gmres_max_rows() { return kLsqMax; }
+int gmres_max_rows(int k) {
+  k = std::max(k, 1);
+  return std::min(kLsqRows, (kLsqLdsDoubles - 2 * k * k) / k);
+}
 
-void gmres_lsq(bkts_ctx ctx, int k, int nr, int nc, const double* H, int ldh, const double* S, double eps, double* Y,
-               double* resn) {
-  BKTS_REQUIRE(nr <= kLsqMax && nc < nr, "block Hessenberg system too large");
-  ProfScope prof(ctx, BKTS_K_SMALL, 8.0 * nr * nc);
-  launch(ctx, gmres_lsq_kernel, dim3(1), dim3(256), 0, k, nr, nc, H, ldh, S, eps, Y, resn);
+void gmres_qr_step(bkts_ctx ctx, int k, int jb, const double* H, int ldh, const double* S, double* Rq, double* Vr,
+                   double* Br, double* Gq, double* resn) {
+  const int nr = (jb + 2) * k;
+  BKTS_REQUIRE(k >= 1 && k <= KM && nr <= gmres_max_rows(k) && nr <= ldh, "block Hessenberg system too large");
+  const size_t lds = sizeof(double) * ((size_t)nr * k + 2 * (size_t)k * k);
+  ProfScope prof(ctx, BKTS_K_SMALL, 8.0 * ((double)nr * k * 3 + 2.0 * jb * k * 2 * k));
+  launch(ctx, gmres_qr_kernel, dim3(1), dim3(256), lds, k, jb, H, ldh, S, Rq, Vr, Br, Gq, resn);
+  BKTS_HIP(hipGetLastError());
+}
+
+void gmres_backsolve(bkts_ctx ctx, int k, int nc, const double* Rq, int ldh, const double* Gq, double eps, double* Y) {
+  BKTS_REQUIRE(nc >= 1 && nc <= ldh, "bad block Hessenberg size");
+  ProfScope prof(ctx, BKTS_K_SMALL, 8.0 * ((double)nc * nc / 2 + 2.0 * nc * k));
+  launch(ctx, gmres_backsolve_kernel, dim3(1), dim3(256), 0, k, nc, Rq, ldh, Gq, eps, Y);
   BKTS_HIP(hipGetLastError());
 }
 

@@ -337,6 +337,31 @@ def test_nonsymmetric_block_solve(env, krylov, k, precision):
         bkts.bkts_op_destroy(op)
 
 
+@pytest.mark.parametrize("k,restart", [(1, 2), (5, 3), (16, 30), (32, 30), (32, 1)])
+def test_block_gmres_restart_cycles(env, k, restart):
+    """Block GMRES through several restart cycles (short restarts; k = 32 caps the cycle at 4 block
+    iterations) on the upwind operator, with a rank-deficient right-hand side block."""
+    torch, bkts, ctx = env
+    n = (14, 9, 8)
+    say(f"block GMRES restart k={k} restart={restart}")
+    op, K, _ = fv_op(env, n, inputs.lognormal_field(n, 0.0, 1.0, 2.0, 6), velocity=(30.0, 10.0, -20.0))
+    try:
+        N = K.shape[0]
+        B = inputs.random_block(N, k, 51)
+        if k >= 3:
+            B[:, 2] = 2.0 * B[:, 0] - B[:, 1]
+        alpha, beta = 50.0, 1.0
+        Xd = torch.zeros((N, k), dtype=torch.float64, device="cuda")
+        opts = bkts.solve_opts(krylov=1, precision=0, rtol=1e-10, restart=restart, maxit=5000)
+        info = bkts.bkts_block_solve(ctx, op, alpha, beta, dev(torch, B), Xd, opts)
+        ref = blockops.block_solve(K, alpha, beta, B)
+        err = np.linalg.norm(Xd.cpu().numpy() - ref, axis=0) / np.linalg.norm(ref, axis=0)
+        say(f"  iterations={info.iterations} err={err.max():.2e}")
+        assert info.converged == 1 and err.max() < 1e-8
+    finally:
+        bkts.bkts_op_destroy(op)
+
+
 @pytest.mark.parametrize("krylov,method,name", [(1, 0, "ie"), (2, 0, "ie"), (1, 2, "sdirk2"), (2, 1, "theta")])
 @pytest.mark.parametrize("precision", [0, 1])
 def test_advance_convection_diffusion(env, krylov, method, name, precision):
