@@ -251,6 +251,31 @@ bkts_status bkts_advance(bkts_ctx ctx, bkts_op op, bkts_tc tc, double* y, int n_
                          const bkts_solve_opts* inner, double outer_rtol, int max_outer,
                          double* y_hist, bkts_step_cb cb, void* user, bkts_run_info* info);
 
+/* One window solved as a whole (linear problem; the outer acceleration the paper names as ongoing
+ * work in Sec. 4.1): M Y A1^T + K Y A2^T = b rs^T + B0 with the window matrices of `phase`
+ * (Sec. 2.1 eq. general-system-time-steps; rs = row sums of A2), B0 (device, N x nb0, leading
+ * dimension ldb0, nb0 <= min(k, 8); NULL = zero) in the first columns.
+ *   BKTS_WINDOW_FGMRES:    FGMRES(restart) whose vectors are whole N x k windows (Frobenius inner
+ *                          products), right-preconditioned by V -> J^-1 V column by column,
+ *                          J = I/tau + beta K, each application one block Krylov solve of the k
+ *                          columns with `inner` (eq. matrix-splitting as a preconditioner).
+ *   BKTS_WINDOW_SPLITTING: the plain fixed point of eq. matrix-fixed-point-equation,
+ *                          Y <- Y + J^-1 (F - L(Y)), for comparison.
+ * Y (device, N x k, ld = k) is the initial guess on entry and the solution on exit, to
+ * ||R(Y)||_F <= rtol ||F||_F.  At most `maxit` outer iterations; BKTS_ENOCONV (info filled) if the
+ * test is not met.  Synchronises. */
+enum { BKTS_WINDOW_FGMRES = 0, BKTS_WINDOW_SPLITTING = 1 };
+typedef struct bkts_window_info {
+  int iterations;            /* outer iterations */
+  int inner_iterations;      /* block Krylov iterations of all J^-1 applications */
+  int precond_applications;  /* J^-1 applications (block solves of k columns) */
+  int converged;
+  double rel_residual;       /* ||R(Y)||_F / ||F||_F on return */
+} bkts_window_info;
+bkts_status bkts_window_solve(bkts_ctx ctx, bkts_op op, bkts_tc tc, int phase, const double* B0, int ldb0, int nb0,
+                              double* Y, int method, const bkts_solve_opts* inner, double rtol, int restart,
+                              int maxit, bkts_window_info* info);
+
 /* ---------------------------------------------- nonlinear problems (Sec. 2.2) */
 
 /* M y' + f(y) = 0 with f(u) = -div_h(D(u) grad_h u) - r(u) on a cell-centred FV grid,

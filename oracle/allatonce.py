@@ -44,6 +44,16 @@ def solve_dense(M, K, A1, A2, B, B0):
     return unvec(np.linalg.solve(kron_operator(M, K, A1, A2), rhs), N)
 
 
+def solve_sparse(M, K, A1, A2, B, B0):
+    """The all-at-once system of eq. general-system-time-steps solved directly with a sparse LU of
+    ``A1 (x) M + A2 (x) K`` (moderate sizes); returns the N x k block Y."""
+    N = K.shape[0]
+    M = sp.csr_matrix(M) if sp.issparse(M) else sp.csr_matrix(np.asarray(M, dtype=np.float64))
+    Kop = sp.kron(sp.csr_matrix(A1), M) + sp.kron(sp.csr_matrix(A2), sp.csr_matrix(K))
+    rhs = vec(np.asarray(B) @ np.asarray(A2).T + np.asarray(B0))
+    return unvec(spla.spsolve(Kop.tocsc(), rhs), N)
+
+
 def residual_linear(M, K, A1, A2, Y, B, B0):
     """``R = M Y A1^T + (K Y - B) A2^T - B0`` (matrix form)."""
     return M @ Y @ A1.T + (K @ Y - B) @ A2.T - B0

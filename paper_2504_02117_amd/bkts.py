@@ -27,6 +27,7 @@ BKTS_FMT_CSR, BKTS_FMT_SELL = 0, 1
 BKTS_BC_DIRICHLET, BKTS_BC_NEUMANN = 0, 1
 BKTS_IE, BKTS_THETA, BKTS_SDIRK2, BKTS_DIRK_CUSTOM = 0, 1, 2, 3
 BKTS_RI_NO_FLOW, BKTS_RI_DIRICHLET, BKTS_RI_FREE_DRAINAGE = 0, 1, 2
+BKTS_WINDOW_FGMRES, BKTS_WINDOW_SPLITTING = 0, 1
 BKTS_CG, BKTS_GMRES, BKTS_BICGSTAB = 0, 1, 2
 BKTS_PREC_NONE, BKTS_PREC_JACOBI = 0, 1
 BKTS_PRECISION_F64, BKTS_PRECISION_F32_REFINE = 0, 1
@@ -69,6 +70,11 @@ class bkts_solve_info(C.Structure):
 class bkts_run_info(C.Structure):
     _fields_ = [("accepted_steps", C.c_int), ("outer_iterations", C.c_int), ("krylov_iterations", C.c_int),
                 ("refinements", C.c_int), ("final_front_rel_residual", C.c_double)]
+
+
+class bkts_window_info(C.Structure):
+    _fields_ = [("iterations", C.c_int), ("inner_iterations", C.c_int), ("precond_applications", C.c_int),
+                ("converged", C.c_int), ("rel_residual", C.c_double)]
 
 
 class bkts_nl_coeffs(C.Structure):
@@ -124,6 +130,8 @@ _SIGS = {
                               C.POINTER(bkts_solve_info)]),
     "bkts_advance": (_I, [_P, _P, _P, _P, _I, C.POINTER(bkts_solve_opts), _D, _I, _P, bkts_step_cb, _P,
                           C.POINTER(bkts_run_info)]),
+    "bkts_window_solve": (_I, [_P, _P, _P, _I, _P, _I, _I, _P, _I, C.POINTER(bkts_solve_opts), _D, _I, _I,
+                               C.POINTER(bkts_window_info)]),
     "bkts_profile_enable": (_I, [_P, _I]),
     "bkts_profile_query": (_I, [_P, _I, C.POINTER(_I64), C.POINTER(_D), C.POINTER(_D)]),
     "bkts_stepper_create": (_I, [_P, _P, _P, _P, C.POINTER(_P)]),
@@ -341,6 +349,21 @@ def bkts_advance(ctx, op, tc, y, n_steps, inner=None, outer_rtol=1e-8, max_outer
     cfun = bkts_step_cb(cb) if cb is not None else C.cast(None, bkts_step_cb)
     _check(_lib.bkts_advance(ctx, op, tc, _ptr(y), n_steps, C.byref(inner), outer_rtol, max_outer, _ptr(y_hist), cfun,
                              None, C.byref(info)))
+    return info
+
+
+def bkts_window_solve(ctx, op, tc, Y, B0=None, phase=0, method=BKTS_WINDOW_FGMRES, inner=None, rtol=1e-8,
+                      restart=30, maxit=200, raise_on_noconv=True):
+    """Solve the all-at-once window system for the (N, k) float64 device tensor Y in place (Y is the
+    initial guess); returns bkts_window_info."""
+    inner = inner or solve_opts(rtol=1e-2)
+    info = bkts_window_info()
+    nb0 = 0 if B0 is None else B0.shape[1]
+    ldb0 = 0 if B0 is None else B0.stride(0)
+    st = _lib.bkts_window_solve(ctx, op, tc, phase, _ptr(B0), ldb0, nb0, _ptr(Y), method, C.byref(inner), rtol,
+                                restart, maxit, C.byref(info))
+    if st != BKTS_OK and (raise_on_noconv or st != BKTS_ENOCONV):
+        _check(st)
     return info
 
 

@@ -2,6 +2,7 @@
 #include <cmath>
 #include <cstring>
 
+#include "accel.hpp"
 #include "advance.hpp"
 #include "internal.hpp"
 #include "krylov.hpp"
@@ -284,6 +285,41 @@ bkts_status bkts_advance(bkts_ctx ctx, bkts_op op, bkts_tc tc, double* y, int n_
   BKTS_REQUIRE(max_outer >= 1, "max_outer must be >= 1");
   set_device(ctx);
   return bkts::advance(ctx, op, tc, y, n_steps, *inner, outer_rtol, max_outer, y_hist, cb, user, info);
+  BKTS_API_END
+}
+
+bkts_status bkts_window_solve(bkts_ctx ctx, bkts_op op, bkts_tc tc, int phase, const double* B0, int ldb0, int nb0,
+                              double* Y, int method, const bkts_solve_opts* inner, double rtol, int restart,
+                              int maxit, bkts_window_info* info) {
+  BKTS_API_BEGIN
+  check_ctx(ctx);
+  BKTS_REQUIRE(op && op->ctx == ctx && tc, "op must belong to ctx and tc must not be NULL");
+  BKTS_REQUIRE(phase >= 0 && phase < tc->m_impl, "phase must be in 0..%d", tc->m_impl - 1);
+  BKTS_REQUIRE(Y, "Y must not be NULL");
+  BKTS_REQUIRE(method == BKTS_WINDOW_FGMRES || method == BKTS_WINDOW_SPLITTING, "unknown window method %d", method);
+  BKTS_REQUIRE(inner, "inner options must not be NULL");
+  BKTS_REQUIRE(inner->rtol > 0.0 && inner->rtol < 1.0, "inner rtol must be in (0, 1)");
+  BKTS_REQUIRE(rtol > 0.0 && rtol < 1.0, "rtol must be in (0, 1)");
+  BKTS_REQUIRE(restart >= 1 && maxit >= 1, "restart and maxit must be >= 1");
+  const int k = tc->k;
+  BKTS_REQUIRE(nb0 >= 0 && nb0 <= k && nb0 <= 8, "nb0 must be in 0..min(k, 8)");
+  if (B0 && nb0 > 0) BKTS_REQUIRE(ldb0 >= nb0, "ldb0 < nb0");
+  set_device(ctx);
+  bkts::WindowStats ws;
+  bkts::window_solve(ctx, *op, *tc, phase, B0, ldb0, nb0, Y, *inner, method, rtol, restart, maxit, ws);
+  ctx->sync();
+  if (info) {
+    info->iterations = ws.iterations;
+    info->inner_iterations = ws.inner_iterations;
+    info->precond_applications = ws.precond_applications;
+    info->converged = ws.converged;
+    info->rel_residual = ws.rel_residual;
+  }
+  if (!ws.converged) {
+    bkts::set_last_error(bkts::fmt("window not converged after %d iterations (rel. residual %.3e)", ws.iterations,
+                                   ws.rel_residual));
+    return BKTS_ENOCONV;
+  }
   BKTS_API_END
 }
 

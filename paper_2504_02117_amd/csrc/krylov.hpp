@@ -1,6 +1,8 @@
 // Block Krylov solvers (krylov.cpp).
 #pragma once
 
+#include <functional>
+
 #include "internal.hpp"
 
 namespace bkts {
@@ -21,6 +23,20 @@ void block_cg(bkts_ctx ctx, const bkts_op_s& op, int dtype, int k, double a, dou
 
 void block_gmres(bkts_ctx ctx, const bkts_op_s& op, int dtype, int k, double a, double b, const void* B, void* X,
                  bool x0_zero, bool jacobi, double rtol, int restart, int maxit, KrylovStats& st);
+
+// Block GMRES(m) on an operator given by callbacks, on contiguous N x k blocks of type dtype:
+// apply: out = A in; precond: out = P in (right preconditioner); residual: W = B - A X (when
+// x0_zero, also set X = 0).  flexible keeps P V_j for every j (FGMRES).  Workspace names start
+// with ws_prefix, so a preconditioner may itself run block GMRES under another prefix.
+struct GmresOps {
+  std::function<void(const void*, void*)> apply;
+  std::function<void(const void*, void*)> precond;
+  std::function<void(const void*, void*, bool, void*)> residual;
+  bool flexible = false;
+  const char* ws_prefix = "gm";
+};
+void gmres_core(bkts_ctx ctx, int dtype, int64_t N, int k, const GmresOps& ops, const void* B, void* X,
+                bool x0_zero, double rtol, int restart, int maxit, KrylovStats& st);
 void block_bicgstab(bkts_ctx ctx, const bkts_op_s& op, int dtype, int k, double a, double b, const void* B, void* X,
                     bool x0_zero, bool jacobi, double rtol, int maxit, KrylovStats& st);
 

@@ -5,7 +5,10 @@
 //
 // Block GMRES: block Arnoldi with classical block Gram-Schmidt applied twice and CholQR2 for the
 // new block (directions that CholQR finds dependent are dropped), then the small least-squares
-// problem min || [S;0] - Hbar Y || by Householder QR on one workgroup.
+// problem min || [S;0] - Hbar Y || by Householder reflectors updated one block column per iteration
+// on one workgroup.  The core takes the operator, the right preconditioner and the residual as
+// callbacks; with `flexible` it keeps every preconditioned direction (FGMRES), for preconditioners
+// that change from one application to the next (an inner Krylov solve).
 // Block BiCGStab (Guennouni-Jbilou-Sadok form): k x k alpha and beta from the shadow Gram
 // Rt^T V, a scalar omega = <T,S>_F / <T,T>_F.
 #include <algorithm>
@@ -43,22 +46,22 @@ bool converged(const std::vector<double>& nrm2, const std::vector<double>& nrm0,
 
 }  // namespace
 
-void block_gmres(bkts_ctx ctx, const bkts_op_s& op, int dtype, int k, double a, double b, const void* B, void* X,
-                 bool x0_zero, bool jacobi, double rtol, int restart, int maxit, KrylovStats& st) {
-  const int64_t N = op.N;
+void gmres_core(bkts_ctx ctx, int dtype, int64_t N, int k, const GmresOps& ops, const void* B, void* X,
+                bool x0_zero, double rtol, int restart, int maxit, KrylovStats& st) {
   const size_t es = esize(dtype);
   const size_t blk = es * N * k;
   BKTS_REQUIRE(gmres_max_rows(k) / k >= 2, "block GMRES: block width %d too large", k);
   const int m = std::max(1, std::min(restart > 0 ? restart : 30, gmres_max_rows(k) / k - 1));
-  const std::string tag = dtype == BKTS_F64 ? "d" : "s";
-  char* V = static_cast<char*>(ctx->ws.get("gm_V_" + tag, blk * (m + 1)));
-  void* W = ctx->ws.get("gm_W_" + tag, blk);
-  void* Z = ctx->ws.get("gm_Z_" + tag, blk);
+  const std::string pre = std::string(ops.ws_prefix) + (dtype == BKTS_F64 ? "_d" : "_s");
+  char* V = static_cast<char*>(ctx->ws.get(pre + "_V", blk * (m + 1)));
+  char* Zs = ops.flexible ? static_cast<char*>(ctx->ws.get(pre + "_Zs", blk * m)) : nullptr;
+  void* W = ctx->ws.get(pre + "_W", blk);
+  void* Z = ctx->ws.get(pre + "_Z", blk);
   const int ldh = (m + 1) * k;
   const size_t kk = (size_t)k * k;
   const size_t hsz = (size_t)ldh * m * k;
-  double* sm = ctx->ws.get<double>("gm_small", 2 * hsz + (size_t)m * k * (2 * k + 1) + (size_t)ldh * k + 8 * kk +
-                                                   (size_t)m * k * k + 4 * k + 2);
+  double* sm = ctx->ws.get<double>(pre + "_small", 2 * hsz + (size_t)m * k * (2 * k + 1) + (size_t)ldh * k + 8 * kk +
+                                                       (size_t)m * k * k + 4 * k + 2);
   double* H = sm;
   double* Rq = H + hsz;                   // triangular factor of H
   double* Vr = Rq + hsz;                  // Householder vectors, 2k per column
@@ -77,22 +80,8 @@ void block_gmres(bkts_ctx ctx, const bkts_op_s& op, int dtype, int k, double a, 
   double* nrmd = resn + k;
   const double eps = dtype == BKTS_F64 ? 1e-13 : 1e-6;
   const double lsq_eps = dtype == BKTS_F64 ? 1e-14 : 1e-7;
-  const double* dinv = nullptr;
-  if (jacobi) {
-    double* d = ctx->ws.get<double>("gm_dinv", N);
-    jacobi_inverse(ctx, op, a, b, d);
-    dinv = d;
-  }
   auto Vb = [&](int j) { return static_cast<void*>(V + blk * j); };
-  auto residual_into_W = [&]() {
-    if (x0_zero) {
-      BKTS_HIP(hipMemsetAsync(X, 0, blk, ctx->stream));
-      BKTS_HIP(hipMemcpyAsync(W, B, blk, hipMemcpyDeviceToDevice, ctx->stream));
-      x0_zero = false;
-    } else {
-      spmm(ctx, op, dtype, k, 1.0, B, k, -a, X, k, -b, W, k);
-    }
-  };
+  auto Zb = [&](int j) { return ops.flexible ? static_cast<void*>(Zs + blk * j) : Z; };
   // CholQR2 of the block `src` into `dst` (may alias): dst R = src, R = R2 R1 stored in Rout.
   auto cholqr2 = [&](void* src, void* dst, double* Rout) {
     gram(ctx, dtype, N, k, src, k, src, k, Gm);
@@ -104,7 +93,7 @@ void block_gmres(bkts_ctx ctx, const bkts_op_s& op, int dtype, int k, double a, 
     small_gemm(ctx, k, R2, R1, 1.0, Rout);
   };
 
-  residual_into_W();
+  ops.residual(B, X, x0_zero, W);
   colnorms2(ctx, dtype, N, k, W, k, nrmd);
   std::vector<double> nrm0, res;
   read_host(ctx, nrmd, k, nrm0);
@@ -116,13 +105,12 @@ void block_gmres(bkts_ctx ctx, const bkts_op_s& op, int dtype, int k, double a, 
   int total = 0;
   while (total < maxit) {
     cholqr2(W, Vb(0), S);  // R0 = V0 S
-    BKTS_HIP(hipMemsetAsync(H, 0, sizeof(double) * ldh * m * k, ctx->stream));
+    BKTS_HIP(hipMemsetAsync(H, 0, sizeof(double) * hsz, ctx->stream));
     int jdone = 0;
-    bool conv = false;
     for (int j = 0; j < m && total < maxit; ++j) {
-      scale_rows(ctx, dtype, N, k, dinv, Vb(j), Z);
-      spmm(ctx, op, dtype, k, 0.0, nullptr, k, a, Z, k, b, W, k);  // W = A D^-1 V_j
-      for (int pass = 0; pass < 2; ++pass) {                         // block CGS2
+      ops.precond(Vb(j), Zb(j));
+      ops.apply(Zb(j), W);  // W = A P V_j
+      for (int pass = 0; pass < 2; ++pass) {  // block CGS2
         for (int i = 0; i <= j; ++i) {
           gram(ctx, dtype, N, k, Vb(i), k, W, k, Hb);
           hblock(ctx, k, Hb, H, ldh, i * k, j * k, pass > 0);
@@ -136,19 +124,20 @@ void block_gmres(bkts_ctx ctx, const bkts_op_s& op, int dtype, int k, double a, 
       ++total;
       jdone = j + 1;
       st.iterations = total;
-      if (converged(res, nrm0, rtol, &st.max_rel, false)) {
-        conv = true;
-        break;
-      }
+      if (converged(res, nrm0, rtol, &st.max_rel, false)) break;
     }
     gmres_backsolve(ctx, k, jdone * k, Rq, ldh, Gq, lsq_eps, Y);
-    // X += D^-1 sum_i V_i Y_i
     BKTS_HIP(hipMemsetAsync(W, 0, blk, ctx->stream));
-    for (int i = 0; i < jdone; ++i) block_rmul(ctx, dtype, N, k, Vb(i), k, Y + (size_t)i * kk, 1.0, 1.0, W, k);
-    scale_rows(ctx, dtype, N, k, dinv, W, Z);
-    block_cast_scale(ctx, N, k, dtype, Z, k, dtype, X, k, nullptr, false, true);  // X += Z
+    if (ops.flexible) {  // X += sum_i (P V_i) Y_i
+      for (int i = 0; i < jdone; ++i) block_rmul(ctx, dtype, N, k, Zb(i), k, Y + (size_t)i * kk, 1.0, 1.0, W, k);
+      block_cast_scale(ctx, N, k, dtype, W, k, dtype, X, k, nullptr, false, true);
+    } else {  // X += P sum_i V_i Y_i
+      for (int i = 0; i < jdone; ++i) block_rmul(ctx, dtype, N, k, Vb(i), k, Y + (size_t)i * kk, 1.0, 1.0, W, k);
+      ops.precond(W, Z);
+      block_cast_scale(ctx, N, k, dtype, Z, k, dtype, X, k, nullptr, false, true);
+    }
     // true residual for the next cycle (and the final check)
-    residual_into_W();
+    ops.residual(B, X, false, W);
     colnorms2(ctx, dtype, N, k, W, k, nrmd);
     std::vector<double> nr;
     read_host(ctx, nrmd, k, nr);
@@ -156,9 +145,32 @@ void block_gmres(bkts_ctx ctx, const bkts_op_s& op, int dtype, int k, double a, 
       st.converged = 1;
       return;
     }
-    (void)conv;
   }
   st.converged = 0;
+}
+
+void block_gmres(bkts_ctx ctx, const bkts_op_s& op, int dtype, int k, double a, double b, const void* B, void* X,
+                 bool x0_zero, bool jacobi, double rtol, int restart, int maxit, KrylovStats& st) {
+  const int64_t N = op.N;
+  const size_t blk = esize(dtype) * N * k;
+  const double* dinv = nullptr;
+  if (jacobi) {
+    double* d = ctx->ws.get<double>("gm_dinv", N);
+    jacobi_inverse(ctx, op, a, b, d);
+    dinv = d;
+  }
+  GmresOps ops;
+  ops.apply = [&](const void* in, void* out) { spmm(ctx, op, dtype, k, 0.0, nullptr, k, a, in, k, b, out, k); };
+  ops.precond = [&](const void* in, void* out) { scale_rows(ctx, dtype, N, k, dinv, in, out); };
+  ops.residual = [&](const void* Bp, void* Xp, bool zero, void* Wp) {
+    if (zero) {
+      BKTS_HIP(hipMemsetAsync(Xp, 0, blk, ctx->stream));
+      BKTS_HIP(hipMemcpyAsync(Wp, Bp, blk, hipMemcpyDeviceToDevice, ctx->stream));
+    } else {
+      spmm(ctx, op, dtype, k, 1.0, Bp, k, -a, Xp, k, -b, Wp, k);  // W = B - A X
+    }
+  };
+  gmres_core(ctx, dtype, N, k, ops, B, X, x0_zero, rtol, restart, maxit, st);
 }
 
 // Vectorized BiCGStab: the k columns advance together through one block operator application per

@@ -1,0 +1,156 @@
+"""GPU parity of the accelerated window solve (FGMRES on the all-at-once operator with the J^-1
+block solve as right preconditioner, and the plain splitting iteration beside it) through the C
+ABI, against the oracle's sparse direct solve of the same window system (Sec. 2.1)."""
+import sys
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+from oracle import allatonce as aao
+from oracle import fv
+from oracle import timecoupling as otc
+from paper_2504_02117_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    from paper_2504_02117_amd import bkts
+    assert torch.cuda.is_available()
+    ctx = bkts.bkts_ctx_create(0, torch.cuda.current_stream())
+    yield torch, bkts, ctx
+    torch.cuda.synchronize()
+    bkts.bkts_ctx_destroy(ctx)
+
+
+def dev(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def problem(env, n, velocity, g, seed=3):
+    """Heterogeneous convection-diffusion with Dirichlet value g on every face (b != 0)."""
+    torch, bkts, ctx = env
+    kap = inputs.lognormal_field(n, 0.0, 1.0, 2.0, seed)
+    op = bkts.bkts_fv_assemble(ctx, n, kappa=dev(torch, kap), kappa_const=1.0, velocity=velocity,
+                               bc_type=[bkts.BKTS_BC_DIRICHLET] * 6, bc_value=[g] * 6, fmt=1)
+    K, b = fv.assemble_linear(n, kappa=kap, velocity=velocity[:len(n)], bc={"default": ("dirichlet", g)})
+    return op, K, b
+
+
+METHODS = {0: "fgmres", 1: "splitting"}
+
+
+@pytest.mark.parametrize("method", [0, 1])
+@pytest.mark.parametrize("k,krylov,precision", [(1, 1, 0), (4, 1, 1), (8, 2, 1), (16, 1, 1), (5, 2, 0)])
+def test_ie_window_matches_direct_solve(env, method, k, krylov, precision):
+    torch, bkts, ctx = env
+    n = (12, 10, 9)
+    tau = 2e-3
+    say(f"window IE {METHODS[method]} k={k} krylov={krylov} precision={precision}")
+    op, K, b = problem(env, n, (20.0, -10.0, 5.0), 0.4)
+    tc = bkts.bkts_tc_create(ctx, bkts.BKTS_IE, k, tau)
+    try:
+        N = K.shape[0]
+        y0 = inputs.smooth_random(n, 2)
+        A, _, c = otc.tableau("ie")
+        A1, A2, _ = otc.window_matrices(A, c, k, 0, tau)
+        B = np.tile(b[:, None], (1, k))
+        B0 = otc.window_b0(A, c, k, 0, tau, y0, K @ y0 - b, [])
+        want = aao.solve_sparse(sp.identity(N), K, A1, A2, B, B0)
+        Yd = dev(torch, np.tile(y0[:, None], (1, k)))
+        inner = bkts.solve_opts(krylov=krylov, precision=precision, rtol=1e-2, inner_rtol=1e-2, maxit=2000)
+        info = bkts.bkts_window_solve(ctx, op, tc, Yd, B0=dev(torch, B0[:, :1]), method=method, inner=inner,
+                                      rtol=1e-11, restart=20, maxit=400)
+        got = Yd.cpu().numpy()
+        err = np.abs(got - want).max() / np.abs(want).max()
+        say(f"  iterations={info.iterations} precond={info.precond_applications} inner={info.inner_iterations} "
+            f"rel_res={info.rel_residual:.2e} err={err:.2e}")
+        assert info.converged == 1 and info.rel_residual <= 1e-11
+        assert err < 1e-8  # the time-stepping parity bar
+        # the oracle's residual of the returned window is at the rounding level of its evaluation
+        R = aao.residual_linear(sp.identity(N), K, A1, A2, got, B, B0)
+        F = B @ A2.T + B0
+        assert np.linalg.norm(R) / np.linalg.norm(F) < 1e-9
+    finally:
+        bkts.bkts_tc_destroy(tc)
+        bkts.bkts_op_destroy(op)
+
+
+@pytest.mark.parametrize("phase", [0, 1])
+@pytest.mark.parametrize("k", [3, 6])
+def test_sdirk2_window_with_b0(env, phase, k):
+    """Pipelined SDIRK2 windows (front at stage `phase`) with their B0 columns."""
+    torch, bkts, ctx = env
+    n = (16, 14)
+    tau = 5e-3
+    say(f"window SDIRK2 phase={phase} k={k}")
+    op, K, b = problem(env, n, (3.0, 1.0, 0.0), -0.2, seed=4)
+    tc = bkts.bkts_tc_create(ctx, bkts.BKTS_SDIRK2, k, tau)
+    try:
+        N = K.shape[0]
+        A, _, c = otc.tableau("sdirk2")
+        A1, A2, _ = otc.window_matrices(A, c, k, phase, tau)
+        yn = inputs.smooth_random(n, 5)
+        fst = [K @ (0.9 * yn) - b]
+        B = np.tile(b[:, None], (1, k))
+        B0 = otc.window_b0(A, c, k, phase, tau, yn, K @ yn - b, fst[:phase])
+        nb0 = min(2 - phase, k)
+        want = aao.solve_sparse(sp.identity(N), K, A1, A2, B, B0)
+        Yd = dev(torch, np.tile(yn[:, None], (1, k)))
+        inner = bkts.solve_opts(krylov=bkts.BKTS_GMRES, precision=1, rtol=1e-3, inner_rtol=1e-3)
+        info = bkts.bkts_window_solve(ctx, op, tc, Yd, B0=dev(torch, B0[:, :nb0]), phase=phase, inner=inner,
+                                      rtol=1e-11, restart=10, maxit=200)
+        err = np.abs(Yd.cpu().numpy() - want).max() / np.abs(want).max()
+        say(f"  iterations={info.iterations} precond={info.precond_applications} err={err:.2e}")
+        assert info.converged == 1 and err < 1e-8
+    finally:
+        bkts.bkts_tc_destroy(tc)
+        bkts.bkts_op_destroy(op)
+
+
+def test_zero_right_hand_side_gives_zero(env):
+    torch, bkts, ctx = env
+    op, _, _ = problem(env, (6, 5), (0.0, 0.0, 0.0), 0.0)
+    tc = bkts.bkts_tc_create(ctx, bkts.BKTS_IE, 4, 1e-2)
+    try:
+        Yd = torch.full((30, 4), 3.0, dtype=torch.float64, device="cuda")
+        info = bkts.bkts_window_solve(ctx, op, tc, Yd, B0=None)
+        assert info.converged == 1 and info.iterations == 0
+        assert torch.count_nonzero(Yd).item() == 0
+    finally:
+        bkts.bkts_tc_destroy(tc)
+        bkts.bkts_op_destroy(op)
+
+
+def test_iteration_limit_and_errors(env):
+    torch, bkts, ctx = env
+    n = (10, 9)
+    op, K, b = problem(env, n, (5.0, 0.0, 0.0), 1.0)
+    tc = bkts.bkts_tc_create(ctx, bkts.BKTS_IE, 8, 5e-2)
+    try:
+        N = K.shape[0]
+        y0 = np.zeros(N)
+        B0 = dev(torch, y0[:, None] / 5e-2)
+        Yd = torch.zeros((N, 8), dtype=torch.float64, device="cuda")
+        inner = bkts.solve_opts(krylov=bkts.BKTS_GMRES, rtol=0.5)
+        info = bkts.bkts_window_solve(ctx, op, tc, Yd, B0=B0, method=bkts.BKTS_WINDOW_SPLITTING, inner=inner,
+                                      rtol=1e-12, maxit=1, raise_on_noconv=False)
+        assert info.converged == 0 and info.iterations == 1 and 0 < info.rel_residual < 1
+        with pytest.raises(bkts.BktsError) as e:
+            bkts.bkts_window_solve(ctx, op, tc, Yd, B0=B0, method=bkts.BKTS_WINDOW_SPLITTING, inner=inner,
+                                   rtol=1e-12, maxit=1)
+        assert e.value.status == bkts.BKTS_ENOCONV
+        for kw in (dict(method=7), dict(rtol=0.0), dict(restart=0), dict(phase=1)):
+            with pytest.raises(bkts.BktsError):
+                bkts.bkts_window_solve(ctx, op, tc, Yd, B0=B0, **kw)
+    finally:
+        bkts.bkts_tc_destroy(tc)
+        bkts.bkts_op_destroy(op)

@@ -51,6 +51,27 @@ def test_allatonce_equals_sequential(method, theta, s):
     np.testing.assert_allclose(Y[:, -1], ys[-1], rtol=1e-12, atol=1e-12)
 
 
+@pytest.mark.parametrize("method,theta", [("ie", 1.0), ("sdirk2", 0.5)])
+@pytest.mark.parametrize("s", [1, 3])
+def test_sparse_allatonce_solve_equals_sequential(method, theta, s):
+    """The sparse direct solve of the window system reproduces sequential stepping."""
+    n = (6, 5, 4)
+    kap = inputs.lognormal_field(n, 0.0, 1.0, 1.5, 12)
+    K, b = fv.assemble_linear(n, kappa=kap, velocity=(0.5, 0.0, -1.0), bc={"default": ("dirichlet", 0.3)})
+    N = K.shape[0]
+    tau = 0.02
+    y0 = inputs.smooth_random(n, 8)
+    A, _, c = tc.tableau(method, theta)
+    A1, A2 = tc.time_stepping_matrices(A, c, s, tau)
+    k = A1.shape[0]
+    B = np.tile(b[:, None], (1, k))
+    B0 = tc.window_b0(A, c, k, 0, tau, y0, K @ y0 - b, [])
+    Y = aao.solve_sparse(sp.identity(N), K, A1, A2, B, B0)
+    _, st = stepping.dirk_linear(K, b, y0, tau, method, s, theta=theta)
+    seq = np.column_stack([v for step in st for v in step])
+    np.testing.assert_allclose(Y, seq, rtol=1e-11, atol=1e-11)
+
+
 @pytest.mark.parametrize("method", ["ie", "theta", "sdirk2"])
 @pytest.mark.parametrize("k", [1, 3, 4])
 def test_pipelined_window_residual_vanishes(method, k):
