@@ -33,10 +33,10 @@ void window_solve(bkts_ctx ctx, const bkts_op_s& op, const bkts_tc_s& tc, int ph
   BKTS_HIP(hipMemsetAsync(matsL + 2 * k * k, 0, sizeof(double) * k, ctx->stream));
   double* nrm = ctx->ws.get<double>("acc_nrm", k);
   double* W0 = ctx->ws.get<double>("acc_w0", n);
+  double* Z = ctx->ws.get<double>("acc_z", n);  // zero input for ||F||, then the splitting's correction
   int cols[8];
   for (int i = 0; i < 8; ++i) cols[i] = i;
   const int nb = B0 ? nb0 : 0;
-  std::vector<double> h;
   auto fro2 = [&]() {  // sum of the k column norms^2 of the last residual launch
     double* hs = ctx->host_stage(k);
     BKTS_HIP(hipMemcpyAsync(hs, nrm, sizeof(double) * k, hipMemcpyDeviceToHost, ctx->stream));
@@ -50,16 +50,16 @@ void window_solve(bkts_ctx ctx, const bkts_op_s& op, const bkts_tc_s& tc, int ph
     residual(ctx, op, k, X, k, mats, mats + k * k, mats + 2 * k * k, B0, ldb0, nb, cols, W, k, nrm);
     axpby(ctx, n, 0.0, W, -1.0, W);
   };
-  auto precond = [&](const double* V, double* Z) {
+  auto precond = [&](const double* V, double* PV) {
     KrylovStats s;
-    solve(ctx, op, 1.0 / tau, beta, k, V, Z, true, inner, true, s);
+    solve(ctx, op, 1.0 / tau, beta, k, V, PV, true, inner, true, s);
     out.inner_iterations += s.iterations;
     ++out.precond_applications;
   };
   out = WindowStats{};
-  // ||F|| from the residual at zero
-  BKTS_HIP(hipMemsetAsync(W0, 0, sizeof(double) * n, ctx->stream));
-  residual(ctx, op, k, W0, k, mats, mats + k * k, mats + 2 * k * k, B0, ldb0, nb, cols, W0, k, nrm);
+  // ||F|| from the residual at zero (input and output must not alias: the stencil reads neighbours)
+  BKTS_HIP(hipMemsetAsync(Z, 0, sizeof(double) * n, ctx->stream));
+  residual(ctx, op, k, Z, k, mats, mats + k * k, mats + 2 * k * k, B0, ldb0, nb, cols, W0, k, nrm);
   const double fnorm = std::sqrt(fro2());
   if (!(fnorm > 0.0)) {  // zero right-hand side: the solution is zero
     BKTS_HIP(hipMemsetAsync(Y, 0, sizeof(double) * n, ctx->stream));
@@ -71,7 +71,6 @@ void window_solve(bkts_ctx ctx, const bkts_op_s& op, const bkts_tc_s& tc, int ph
   double r = std::sqrt(fro2());
   if (!std::isfinite(r)) throw Error{BKTS_EBREAKDOWN, "non-finite window residual"};
   if (method == BKTS_WINDOW_SPLITTING) {
-    double* Z = ctx->ws.get<double>("acc_z", n);
     while (r > rtol * fnorm && out.iterations < maxit) {
       precond(W0, Z);
       axpby(ctx, n, 1.0, Z, 1.0, Y);
