@@ -154,3 +154,36 @@ def test_iteration_limit_and_errors(env):
     finally:
         bkts.bkts_tc_destroy(tc)
         bkts.bkts_op_destroy(op)
+
+
+_LARGE = {}
+
+
+@pytest.mark.parametrize("method", [0, 1])
+def test_ie_window_on_a_larger_grid(env, method):
+    """A 28^3 window (many workgroups per launch) against sequential implicit Euler with direct
+    solves: guards the right-hand-side norm, whose input must not alias its output."""
+    torch, bkts, ctx = env
+    from oracle import stepping
+    n = (28, 28, 28)
+    k, tau = 4, 1e-3
+    say(f"window IE 28^3 {METHODS[method]}")
+    op, K, b = problem(env, n, (0.0, 0.0, 0.0), 0.0, seed=9)
+    tc = bkts.bkts_tc_create(ctx, bkts.BKTS_IE, k, tau)
+    try:
+        N = K.shape[0]
+        y0 = inputs.sin_product(n)
+        if "ys" not in _LARGE:  # the direct oracle solves take seconds; share them between methods
+            _LARGE["ys"] = stepping.dirk_linear(K, b, y0, tau, "ie", k)[0]
+        ys = _LARGE["ys"]
+        Yd = dev(torch, np.tile(y0[:, None], (1, k)))
+        inner = bkts.solve_opts(krylov=bkts.BKTS_CG, precision=1, rtol=0.1, inner_rtol=0.1)
+        info = bkts.bkts_window_solve(ctx, op, tc, Yd, B0=dev(torch, y0[:, None] / tau), method=method, inner=inner,
+                                      rtol=1e-10, restart=30, maxit=200)
+        got = Yd.cpu().numpy()
+        err = max(np.linalg.norm(got[:, j] - ys[j + 1]) / np.linalg.norm(ys[j + 1]) for j in range(k))
+        say(f"  iterations={info.iterations} rel_res={info.rel_residual:.2e} err={err:.2e}")
+        assert info.converged == 1 and info.iterations >= 2 and err < 1e-8
+    finally:
+        bkts.bkts_tc_destroy(tc)
+        bkts.bkts_op_destroy(op)
