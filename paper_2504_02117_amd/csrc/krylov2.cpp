@@ -187,7 +187,6 @@ void block_bicgstab(bkts_ctx ctx, const bkts_op_s& op, int dtype, int k, double 
   void* R = ctx->ws.get("bs_R_" + tag, blk);
   void* Rt = ctx->ws.get("bs_Rt_" + tag, blk);
   void* P = ctx->ws.get("bs_P_" + tag, blk);
-  void* Pn = ctx->ws.get("bs_Pn_" + tag, blk);
   void* Ph = ctx->ws.get("bs_Ph_" + tag, blk);
   void* V = ctx->ws.get("bs_V_" + tag, blk);
   void* Sb = ctx->ws.get("bs_S_" + tag, blk);
@@ -221,8 +220,8 @@ void block_bicgstab(bkts_ctx ctx, const bkts_op_s& op, int dtype, int k, double 
     st.converged = 1;
     return;
   }
+  scale_rows(ctx, dtype, N, k, dinv, P, Ph);
   for (int it = 1; it <= maxit; ++it) {
-    scale_rows(ctx, dtype, N, k, dinv, P, Ph);
     spmm(ctx, op, dtype, k, 0.0, nullptr, k, a, Ph, k, b, V, k);  // V = A D^-1 P
     {
       const void* xs[2] = {Rt, Rt};
@@ -230,10 +229,8 @@ void block_bicgstab(bkts_ctx ctx, const bkts_op_s& op, int dtype, int k, double 
       double* os[2] = {m1, mr};
       col_dots(ctx, dtype, N, k, 2, xs, ys, os);
     }
-    small_diag_ratio(ctx, k, mr, m1, 1.0, al);  // alpha_j = (rt_j^T r_j) / (rt_j^T v_j)
-    BKTS_HIP(hipMemcpyAsync(Sb, R, blk, hipMemcpyDeviceToDevice, ctx->stream));
-    block_rmul(ctx, dtype, N, k, V, k, al, 1.0, -1.0, Sb, k);  // S = R - V alpha
-    scale_rows(ctx, dtype, N, k, dinv, Sb, Sh);
+    small_diag_ratio(ctx, k, mr, m1, 1.0, al);           // alpha_j = (rt_j^T r_j) / (rt_j^T v_j)
+    bicg_s_step(ctx, dtype, N, k, R, V, al, dinv, Sb, Sh);  // S = R - V alpha, Sh = D^-1 S
     spmm(ctx, op, dtype, k, 0.0, nullptr, k, a, Sh, k, b, T, k);  // T = A D^-1 S
     {
       const void* xs[3] = {T, T, Rt};
@@ -242,8 +239,7 @@ void block_bicgstab(bkts_ctx ctx, const bkts_op_s& op, int dtype, int k, double 
       col_dots(ctx, dtype, N, k, 3, xs, ys, os);
     }
     small_diag_ratio(ctx, k, ts, tt, 1.0, W);  // omega_j = (t_j^T s_j) / (t_j^T t_j)
-    BKTS_HIP(hipMemcpyAsync(R, Sb, blk, hipMemcpyDeviceToDevice, ctx->stream));
-    block_rmul(ctx, dtype, N, k, T, k, W, 1.0, -1.0, R, k);  // R = S - T omega
+    bicg_r_step(ctx, dtype, N, k, Sb, T, W, R);  // R = S - T omega
     colnorms2(ctx, dtype, N, k, R, k, nrmd);
     read_host(ctx, nrmd, k, nrm);
     bool finite = true;
@@ -253,18 +249,14 @@ void block_bicgstab(bkts_ctx ctx, const bkts_op_s& op, int dtype, int k, double 
       st.converged = 0;
       return;
     }
-    block_rmul(ctx, dtype, N, k, Ph, k, al, 1.0, 1.0, X, k);  // X += D^-1 P alpha
-    block_rmul(ctx, dtype, N, k, Sh, k, W, 1.0, 1.0, X, k);   //    + D^-1 S omega
+    bicg_x_step(ctx, dtype, N, k, Ph, Sh, al, W, X);  // X += D^-1 P alpha + D^-1 S omega
     st.iterations = it;
     if (converged(nrm, nrm0, rtol, &st.max_rel, true)) {
       st.converged = 1;
       return;
     }
-    small_diag_ratio(ctx, k, m3, m1, -1.0, be);              // beta_j = -(rt_j^T t_j) / (rt_j^T v_j)
-    block_rmul(ctx, dtype, N, k, V, k, W, 1.0, -1.0, P, k);   // P - V omega
-    BKTS_HIP(hipMemcpyAsync(Pn, R, blk, hipMemcpyDeviceToDevice, ctx->stream));
-    block_rmul(ctx, dtype, N, k, P, k, be, 1.0, 1.0, Pn, k);  // P = R + (P - V omega) beta
-    std::swap(P, Pn);
+    small_diag_ratio(ctx, k, m3, m1, -1.0, be);  // beta_j = -(rt_j^T t_j) / (rt_j^T v_j)
+    bicg_p_step(ctx, dtype, N, k, R, V, W, be, dinv, P, Ph);  // P = R + (P - V omega) beta, Ph = D^-1 P
   }
   st.converged = 0;
 }

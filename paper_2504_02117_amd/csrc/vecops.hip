@@ -44,10 +44,24 @@ __global__ void jacobi_inverse_kernel(int64_t N, const double* diag, double a, d
 
 template <typename T>
 __global__ void scale_rows_kernel(int64_t N, int k, const double* dinv, const T* X, T* Y) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= N * k) return;
-  const double d = dinv ? dinv[i / k] : 1.0;
-  Y[i] = (T)(d * (double)X[i]);
+  // 4 elements 256 apart per thread (contiguous per wavefront); one 64-bit division for the first
+  // element's row, the others advance by (256 / k, 256 % k)
+  const int64_t n = N * k;
+  const int64_t i0 = (int64_t)blockIdx.x * 1024 + threadIdx.x;
+  int64_t r = i0 / k;
+  int c = (int)(i0 - r * k);
+  const int dq = 256 / k, dm = 256 % k;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int64_t i = i0 + (int64_t)e * 256;
+    if (i < n) Y[i] = (T)((dinv ? dinv[r] : 1.0) * (double)X[i]);
+    r += dq;
+    c += dm;
+    if (c >= k) {
+      c -= k;
+      ++r;
+    }
+  }
 }
 
 // Y += sign * s[0] * X with the scalar read from device memory
@@ -111,10 +125,10 @@ void scale_rows(bkts_ctx ctx, int dtype, int64_t N, int k, const double* dinv, c
   if (N * k == 0) return;
   ProfScope prof(ctx, BKTS_K_OTHER, 2.0 * N * k * esize(dtype) + 8.0 * N);
   if (dtype == BKTS_F64)
-    launch(ctx, scale_rows_kernel<double>, grid1(N * k), dim3(256), 0, N, k, dinv,
+    launch(ctx, scale_rows_kernel<double>, grid1((N * k + 3) / 4), dim3(256), 0, N, k, dinv,
                        static_cast<const double*>(X), static_cast<double*>(Y));
   else
-    launch(ctx, scale_rows_kernel<float>, grid1(N * k), dim3(256), 0, N, k, dinv,
+    launch(ctx, scale_rows_kernel<float>, grid1((N * k + 3) / 4), dim3(256), 0, N, k, dinv,
                        static_cast<const float*>(X), static_cast<float*>(Y));
   BKTS_HIP(hipGetLastError());
 }

@@ -29,6 +29,19 @@ void axpby(bkts_ctx ctx, int64_t n, double a, const double* x, double b, double*
 void scale_rows(bkts_ctx ctx, int dtype, int64_t N, int k, const double* dinv, const void* X, void* Y);
 // Y += sign * s[0] * X (n elements; s is a device scalar)
 void axpy_ds(bkts_ctx ctx, int dtype, int64_t n, const double* s, double sign, const void* X, void* Y);
+// Fused per-column steps of the vectorized BiCGStab (bicg.hip); alpha, omega, beta are diagonal
+// k x k device matrices, dinv may be null (no preconditioner).
+// S = R - V alpha, Sh = D^-1 S
+void bicg_s_step(bkts_ctx ctx, int dtype, int64_t N, int k, const void* R, const void* V, const double* al,
+                 const double* dinv, void* S, void* Sh);
+// R = S - T omega
+void bicg_r_step(bkts_ctx ctx, int dtype, int64_t N, int k, const void* S, const void* Tv, const double* om, void* R);
+// X += Ph alpha + Sh omega
+void bicg_x_step(bkts_ctx ctx, int dtype, int64_t N, int k, const void* Ph, const void* Sh, const double* al,
+                 const double* om, void* X);
+// P = R + (P - V omega) beta, Ph = D^-1 P
+void bicg_p_step(bkts_ctx ctx, int dtype, int64_t N, int k, const void* R, const void* V, const double* om,
+                 const double* be, const double* dinv, void* P, void* Ph);
 // store (or add) a k x k row-major block into a column-major matrix at (r0, c0)
 void hblock(bkts_ctx ctx, int k, const double* M, double* H, int ldh, int r0, int c0, bool accumulate);
 
