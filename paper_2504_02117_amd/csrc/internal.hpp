@@ -283,6 +283,26 @@ void rk_rmul(bkts_ctx ctx, int dtype, int64_t N, int k, const void* X, const dou
 
 // MFMA-based block kernels for 8 <= k <= 32 (mfma.hip); contiguous blocks (ld = k) unless noted.
 bool mf_eligible(int k);
+// Block Gram-Schmidt against nblk <= mf_mgs_max_blocks(k) blocks V_i = V0 + i * vstride (elements):
+// mf_mgram writes per-slot partials of every V_i^T W (nslots_out slots; the partial buffer holds
+// nblk * KP^2 * mf_mgram_slots() doubles, KP = 16 or 32); mf_mgs_finalize sums them into C (nblk
+// row-major k x k blocks) and stores or adds them into H at (r0 + i k, c0) (KP = 1 for k = 1, the
+// mdot partials); mf_mrmul applies W -= sum_i V_i C_i.
+int mf_mgs_max_blocks(int k);
+int64_t mf_mgram_slots(bkts_ctx ctx, int dtype, int64_t N, int k);
+void mf_mgram(bkts_ctx ctx, int dtype, int64_t N, int k, int nblk, const void* V0, int64_t vstride, const void* W,
+              double* partials_out, int* nslots_out);
+void mf_mgs_finalize(bkts_ctx ctx, const double* partials, int nslots, int k, int nblk, double* C, double* H, int ldh,
+                     int r0, int c0, bool accumulate);
+void mf_mrmul(bkts_ctx ctx, int dtype, int64_t N, int k, int nblk, const void* V0, int64_t vstride, const double* C,
+              void* W);
+// The same for single columns (k = 1, any length n): nblk <= mdot_max_blocks() dot products
+// (partials: nblk * mdot_slots() doubles; finalize with mf_mgs_finalize and k = 1) and the update.
+int mdot_max_blocks();
+int64_t mdot_slots(bkts_ctx ctx, int64_t n);
+void mdot(bkts_ctx ctx, int dtype, int64_t n, int nblk, const void* V0, int64_t vstride, const void* W,
+          double* partials_out, int* nslots_out);
+void maxpy(bkts_ctx ctx, int dtype, int64_t n, int nblk, const void* V0, int64_t vstride, const double* C, void* W);
 void mf_gram(bkts_ctx ctx, int dtype, int64_t N, int k, const void* X, int ldx, const void* Y, int ldy, double* G);
 void mf_spmm_gram(bkts_ctx ctx, const bkts_op_s& op, int dtype, int k, double alpha, const void* P, double beta,
                   void* Q, double* G);  // Q = alpha P + beta K P, G = P^T Q

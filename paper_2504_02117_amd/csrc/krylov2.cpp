@@ -93,6 +93,45 @@ void gmres_core(bkts_ctx ctx, int dtype, int64_t N, int k, const GmresOps& ops, 
     small_gemm(ctx, k, R2, R1, 1.0, Rout);
   };
 
+  // W -= sum_{i<=j} V_i (V_i^T W), the coefficients stored into (or, on the second pass, added to)
+  // block column j of H.  Widths with multi-block kernels (k = 1, or 8..32 on the matrix cores) take
+  // every projection from one pass over W and the update from another (classical Gram-Schmidt);
+  // other widths project block by block.
+  const bool mgs_mf = mf_eligible(k), mgs_dot = k == 1;
+  const int mgs_max = mgs_mf ? mf_mgs_max_blocks(k) : mgs_dot ? mdot_max_blocks() : 1;
+  const int KPm = mgs_dot ? 1 : (k <= 16 ? 16 : 32);
+  const int64_t mslots = mgs_mf ? mf_mgram_slots(ctx, dtype, N, k) : mgs_dot ? mdot_slots(ctx, N) : 1;
+  double* Cb = (mgs_mf || mgs_dot) ? ctx->ws.get<double>(pre + "_Cb", (size_t)(m + 1) * kk) : nullptr;
+  double* mpart = (mgs_mf || mgs_dot)
+                      ? ctx->ws.get<double>(pre + "_mpart", (size_t)mgs_max * KPm * KPm * mslots) : nullptr;
+  const int64_t vstride = (int64_t)N * k;  // elements between consecutive basis blocks
+  auto project = [&](int j, bool second) {
+    if (!(mgs_mf || mgs_dot)) {
+      for (int i = 0; i <= j; ++i) {
+        gram(ctx, dtype, N, k, Vb(i), k, W, k, Hb);
+        hblock(ctx, k, Hb, H, ldh, i * k, j * k, second);
+        block_rmul(ctx, dtype, N, k, Vb(i), k, Hb, 1.0, -1.0, W, k);
+      }
+      return;
+    }
+    for (int i0 = 0; i0 <= j; i0 += mgs_max) {
+      const int nb = std::min(mgs_max, j + 1 - i0);
+      int ns = 0;
+      if (mgs_mf)
+        mf_mgram(ctx, dtype, N, k, nb, Vb(i0), vstride, W, mpart, &ns);
+      else
+        mdot(ctx, dtype, N, nb, Vb(i0), vstride, W, mpart, &ns);
+      mf_mgs_finalize(ctx, mpart, ns, k, nb, Cb + (size_t)i0 * kk, H, ldh, i0 * k, j * k, second);
+    }
+    for (int i0 = 0; i0 <= j; i0 += mgs_max) {
+      const int nb = std::min(mgs_max, j + 1 - i0);
+      if (mgs_mf)
+        mf_mrmul(ctx, dtype, N, k, nb, Vb(i0), vstride, Cb + (size_t)i0 * kk, W);
+      else
+        maxpy(ctx, dtype, N, nb, Vb(i0), vstride, Cb + (size_t)i0 * kk, W);
+    }
+  };
+
   ops.residual(B, X, x0_zero, W);
   colnorms2(ctx, dtype, N, k, W, k, nrmd);
   std::vector<double> nrm0, res;
@@ -110,13 +149,7 @@ void gmres_core(bkts_ctx ctx, int dtype, int64_t N, int k, const GmresOps& ops, 
     for (int j = 0; j < m && total < maxit; ++j) {
       ops.precond(Vb(j), Zb(j));
       ops.apply(Zb(j), W);  // W = A P V_j
-      for (int pass = 0; pass < 2; ++pass) {  // block CGS2
-        for (int i = 0; i <= j; ++i) {
-          gram(ctx, dtype, N, k, Vb(i), k, W, k, Hb);
-          hblock(ctx, k, Hb, H, ldh, i * k, j * k, pass > 0);
-          block_rmul(ctx, dtype, N, k, Vb(i), k, Hb, 1.0, -1.0, W, k);
-        }
-      }
+      for (int pass = 0; pass < 2; ++pass) project(j, pass > 0);  // block Gram-Schmidt, twice
       cholqr2(W, Vb(j + 1), Tm);  // W = V_{j+1} H_{j+1,j}
       hblock(ctx, k, Tm, H, ldh, (j + 1) * k, j * k, false);
       gmres_qr_step(ctx, k, j, H, ldh, S, Rq, Vr, Br, Gq, resn);

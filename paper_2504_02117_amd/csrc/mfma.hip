@@ -17,6 +17,8 @@
 // Every wave owns a contiguous range of 16-row tiles (workgroups remapped per XCD); the k x k
 // accumulators of the 4 waves of a workgroup are folded in a fixed order into one partial per
 // workgroup, which finalize_partials() sums in a fixed order (bitwise reproducible).
+#include <algorithm>
+
 #include "devcommon.hpp"
 #include "internal.hpp"
 
@@ -459,6 +461,184 @@ __global__ __launch_bounds__(256) void mf_rmul_kernel(int64_t N, int k, const T*
   }
 }
 
+// ----------------------------------------------------------------------------- block Gram-Schmidt
+// Projection of W against nblk blocks V_i = V0 + i * vstride (block GMRES): G_i = V_i^T W for all i
+// in one pass that reads W once, and W -= sum_i V_i C_i in one pass that reads and writes W once.
+// MB blocks at most per launch (register budget: MB * NB^2 accumulators).
+
+template <int NB>
+constexpr int mgs_max_blocks() { return NB == 1 ? 4 : 2; }
+
+template <typename T, int NB>
+__global__ __launch_bounds__(256) void mf_mgram_kernel(int64_t N, int k, int nblk, const T* __restrict__ V0,
+                                                       int64_t vstride, const T* __restrict__ W,
+                                                       double* partials) {
+  constexpr int MB = mgs_max_blocks<NB>();
+  constexpr int KP = 16 * NB;
+  __shared__ __align__(16) double red[4 * KP * KP];
+  const int l = threadIdx.x & 63, g = l >> 4, c = l & 15;
+  d4 acc[MB][NB][NB];
+#pragma unroll
+  for (int b = 0; b < MB; ++b)
+#pragma unroll
+    for (int i = 0; i < NB; ++i)
+#pragma unroll
+      for (int j = 0; j < NB; ++j) acc[b][i][j] = zero4();
+  const WaveRange wr = wave_range((N + 3) / 4);
+  for (int64_t q = wr.begin; q < wr.end; ++q) {
+    const int64_t r = 4 * q + g;
+    double y[NB], x[MB][NB];
+#pragma unroll
+    for (int cb = 0; cb < NB; ++cb) {
+      const int col = 16 * cb + c;
+      y[cb] = ldz(W + r * k + col, r < N && col < k);
+#pragma unroll
+      for (int b = 0; b < MB; ++b) x[b][cb] = (b < nblk) ? ldz(V0 + b * vstride + r * k + col, r < N && col < k) : 0.0;
+    }
+#pragma unroll
+    for (int b = 0; b < MB; ++b)
+      if (b < nblk) {
+#pragma unroll
+        for (int ia = 0; ia < NB; ++ia)
+#pragma unroll
+          for (int jb = 0; jb < NB; ++jb) acc[b][ia][jb] = mfma(x[b][ia], y[jb], acc[b][ia][jb]);
+      }
+  }
+#pragma unroll
+  for (int b = 0; b < MB; ++b)
+    if (b < nblk) fold_kxk<NB>(acc[b], red, partials + (int64_t)b * KP * KP * gridDim.x);
+}
+
+// W -= sum_b V_b C_b, C_b = C + b * k * k (row-major k x k, FP64).  The coefficient blocks are
+// staged once per workgroup in LDS (negated, zero padded); the A operand of each basis tile is read
+// straight from device memory in the transposed order it needs (lane l: row l % 16, columns
+// 4kb + l / 16, all within the tile's contiguous rows), and all basis tiles of a W tile are loaded
+// before the first matrix-core instruction.
+template <typename T, int NB>
+__global__ __launch_bounds__(256) void mf_mrmul_kernel(int64_t N, int k, int nblk, const T* __restrict__ V0,
+                                                       int64_t vstride, const double* C, T* W) {
+  constexpr int MB = mgs_max_blocks<NB>();
+  constexpr int KP = 16 * NB;
+  __shared__ double Cs[MB * KP * KP];
+  for (int e = threadIdx.x; e < MB * KP * KP; e += 256) {
+    const int b = e / (KP * KP), rc = e % (KP * KP), r = rc / KP, c = rc % KP;
+    Cs[e] = (b < nblk && r < k && c < k) ? -C[(int64_t)b * k * k + r * k + c] : 0.0;
+  }
+  __syncthreads();
+  const int l = threadIdx.x & 63, g = l >> 4, c = l & 15;
+  const WaveRange wr = wave_range((N + 15) / 16);
+  for (int64_t t = wr.begin; t < wr.end; ++t) {
+    const int64_t row0 = 16 * t;
+    double yd[NB][4];
+    load_tile<T, NB>(W, N, k, row0, yd, nullptr);
+    double xa[MB][4 * NB];
+    const int64_t ra = row0 + (l & 15);
+#pragma unroll
+    for (int b = 0; b < MB; ++b)
+#pragma unroll
+      for (int kb = 0; kb < 4 * NB; ++kb) {
+        const int col = 4 * kb + (l >> 4);
+        xa[b][kb] = (b < nblk) ? ldz(V0 + b * vstride + ra * k + col, ra < N && col < k) : 0.0;
+      }
+#pragma unroll
+    for (int b = 0; b < MB; ++b) {
+      if (b < nblk) {
+        double bf[4 * NB][NB];
+#pragma unroll
+        for (int kb = 0; kb < 4 * NB; ++kb)
+#pragma unroll
+          for (int cb = 0; cb < NB; ++cb) bf[kb][cb] = Cs[b * KP * KP + (4 * kb + g) * KP + 16 * cb + c];
+        d4 yn[NB];
+        tile_rmul<NB>(xa[b], bf, yd, yn);
+#pragma unroll
+        for (int cb = 0; cb < NB; ++cb)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) yd[cb][v] = yn[cb][v];
+      }
+    }
+    d4 out[NB];
+#pragma unroll
+    for (int cb = 0; cb < NB; ++cb) out[cb] = d4{yd[cb][0], yd[cb][1], yd[cb][2], yd[cb][3]};
+    store_tile<T, NB>(W, N, k, row0, out);
+  }
+}
+
+// Single-column blocks (k = 1): the projection of w against nblk <= kMdotMax vectors is nblk dot
+// products in one pass over w, and w -= sum_b c_b v_b one pass that reads and writes w once.
+constexpr int kMdotMax = 16;
+
+template <typename T>
+__global__ __launch_bounds__(256) void mdot_kernel(int64_t n, int nblk, const T* __restrict__ V0, int64_t vstride,
+                                                   const T* __restrict__ W, double* partials) {
+  __shared__ double red[4 * kMdotMax];
+  double acc[kMdotMax];
+#pragma unroll
+  for (int b = 0; b < kMdotMax; ++b) acc[b] = 0.0;
+  const int64_t slot = dev::xcd_slot(blockIdx.x, gridDim.x);
+  const int64_t per = (n + gridDim.x - 1) / gridDim.x;
+  const int64_t lo = slot * per, hi = lo + per < n ? lo + per : n;
+  for (int64_t i = lo + threadIdx.x; i < hi; i += 256) {
+    const double w = (double)W[i];
+#pragma unroll
+    for (int b = 0; b < kMdotMax; ++b)
+      if (b < nblk) acc[b] = fma((double)V0[b * vstride + i], w, acc[b]);
+  }
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int b = 0; b < kMdotMax; ++b) {
+    double v = acc[b];
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    if (lane == 0) red[wv * kMdotMax + b] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < nblk) {
+    const int b = threadIdx.x;
+    partials[(int64_t)b * gridDim.x + slot] =
+        ((red[b] + red[kMdotMax + b]) + red[2 * kMdotMax + b]) + red[3 * kMdotMax + b];
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void maxpy_kernel(int64_t n, int nblk, const T* __restrict__ V0, int64_t vstride,
+                                                    const double* __restrict__ C, T* __restrict__ W) {
+  __shared__ double cs[kMdotMax];
+  if (threadIdx.x < nblk) cs[threadIdx.x] = C[threadIdx.x];
+  __syncthreads();
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  double w = (double)W[i];
+#pragma unroll
+  for (int b = 0; b < kMdotMax; ++b)
+    if (b < nblk) w = fma(-cs[b], (double)V0[b * vstride + i], w);
+  W[i] = (T)w;
+}
+
+// One workgroup per entry (b, a, c) of the nblk projection blocks: sum the slots in a fixed order,
+// store C_b[a][c] and add it into the block Hessenberg matrix H (column-major, ldh) at row
+// r0 + b k + a, column c0 + c.
+__global__ __launch_bounds__(256) void mgs_finalize_kernel(const double* partials, int64_t nslots, int k, int KP,
+                                                           double* C, double* H, int ldh, int r0, int c0,
+                                                           int accumulate) {
+  __shared__ double sred[256];
+  const int idx = blockIdx.x;
+  const int b = idx / (k * k), a = (idx / k) % k, cc = idx % k;
+  const double* p = partials + ((int64_t)b * KP * KP + (int64_t)a * KP + cc) * nslots;
+  double acc = 0.0;
+  for (int64_t j = threadIdx.x; j < nslots; j += 256) acc += p[j];
+  sred[threadIdx.x] = acc;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (threadIdx.x < off) sred[threadIdx.x] += sred[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double v = sred[0];
+    C[idx] = v;
+    double* h = H + (int64_t)(c0 + cc) * ldh + r0 + b * k + a;
+    *h = accumulate ? *h + v : v;
+  }
+}
+
 // Persistent grid: the chip's resident capacity for the kernel, capped so that every wave owns at
 // least ~4 work units.
 int64_t mf_blocks(bkts_ctx ctx, const void* kernel, int64_t units) {
@@ -603,6 +783,92 @@ void mf_rmul(bkts_ctx ctx, int dtype, int64_t N, int k, const void* X, const dou
   else
     BKTS_NB_DISPATCH(k, launch(ctx, (mf_rmul_kernel<float, NB>), dim3(nb), dim3(256), 0, N, k,
                                             static_cast<const float*>(X), C, c0, c1, static_cast<float*>(Y)));
+  BKTS_HIP(hipGetLastError());
+}
+
+int mf_mgs_max_blocks(int k) { return k <= 16 ? mgs_max_blocks<1>() : mgs_max_blocks<2>(); }
+
+void mf_mgram(bkts_ctx ctx, int dtype, int64_t N, int k, int nblk, const void* V0, int64_t vstride, const void* W,
+              double* partials_out, int* nslots_out) {
+  const int64_t nb = mf_blocks(ctx, dtype == BKTS_F64 ? (k <= 16 ? (const void*)mf_mgram_kernel<double, 1> : (const void*)mf_mgram_kernel<double, 2>)
+                                                     : (k <= 16 ? (const void*)mf_mgram_kernel<float, 1> : (const void*)mf_mgram_kernel<float, 2>),
+                                (N + 3) / 4);
+  BKTS_REQUIRE(nblk >= 1 && nblk <= mf_mgs_max_blocks(k), "mf_mgram: bad block count %d", nblk);
+  ProfScope prof(ctx, BKTS_K_GRAM, (1.0 + nblk) * N * k * esize(dtype));
+  if (dtype == BKTS_F64)
+    BKTS_NB_DISPATCH(k, launch(ctx, (mf_mgram_kernel<double, NB>), dim3(nb), dim3(256), 0, N, k, nblk,
+                               static_cast<const double*>(V0), vstride, static_cast<const double*>(W), partials_out));
+  else
+    BKTS_NB_DISPATCH(k, launch(ctx, (mf_mgram_kernel<float, NB>), dim3(nb), dim3(256), 0, N, k, nblk,
+                               static_cast<const float*>(V0), vstride, static_cast<const float*>(W), partials_out));
+  BKTS_HIP(hipGetLastError());
+  *nslots_out = (int)nb;
+}
+
+int64_t mf_mgram_slots(bkts_ctx ctx, int dtype, int64_t N, int k) {
+  return mf_blocks(ctx, dtype == BKTS_F64 ? (k <= 16 ? (const void*)mf_mgram_kernel<double, 1> : (const void*)mf_mgram_kernel<double, 2>)
+                                         : (k <= 16 ? (const void*)mf_mgram_kernel<float, 1> : (const void*)mf_mgram_kernel<float, 2>),
+                   (N + 3) / 4);
+}
+
+void mf_mrmul(bkts_ctx ctx, int dtype, int64_t N, int k, int nblk, const void* V0, int64_t vstride, const double* C,
+              void* W) {
+  const int64_t nb = mf_blocks(ctx, dtype == BKTS_F64 ? (k <= 16 ? (const void*)mf_mrmul_kernel<double, 1> : (const void*)mf_mrmul_kernel<double, 2>)
+                                                     : (k <= 16 ? (const void*)mf_mrmul_kernel<float, 1> : (const void*)mf_mrmul_kernel<float, 2>),
+                                (N + 15) / 16);
+  BKTS_REQUIRE(nblk >= 1 && nblk <= mf_mgs_max_blocks(k), "mf_mrmul: bad block count %d", nblk);
+  ProfScope prof(ctx, BKTS_K_OTHER, (2.0 + nblk) * N * k * esize(dtype));
+  if (dtype == BKTS_F64)
+    BKTS_NB_DISPATCH(k, launch(ctx, (mf_mrmul_kernel<double, NB>), dim3(nb), dim3(256), 0, N, k, nblk,
+                               static_cast<const double*>(V0), vstride, C, static_cast<double*>(W)));
+  else
+    BKTS_NB_DISPATCH(k, launch(ctx, (mf_mrmul_kernel<float, NB>), dim3(nb), dim3(256), 0, N, k, nblk,
+                               static_cast<const float*>(V0), vstride, C, static_cast<float*>(W)));
+  BKTS_HIP(hipGetLastError());
+}
+
+void mf_mgs_finalize(bkts_ctx ctx, const double* partials, int nslots, int k, int nblk, double* C, double* H, int ldh,
+                     int r0, int c0, bool accumulate) {
+  const int KP = k == 1 ? 1 : k <= 16 ? 16 : 32;
+  ProfScope prof(ctx, BKTS_K_SMALL, 8.0 * nblk * KP * KP * nslots);
+  launch(ctx, mgs_finalize_kernel, dim3(nblk * k * k), dim3(256), 0, partials, (int64_t)nslots, k, KP, C, H, ldh, r0,
+         c0, accumulate ? 1 : 0);
+  BKTS_HIP(hipGetLastError());
+}
+
+int mdot_max_blocks() { return kMdotMax; }
+
+int64_t mdot_slots(bkts_ctx ctx, int64_t n) {
+  const int64_t cap = 4 * (int64_t)ctx->num_cu;
+  const int64_t want = (n + 4095) / 4096;
+  return std::max<int64_t>(1, std::min(cap, want));
+}
+
+void mdot(bkts_ctx ctx, int dtype, int64_t n, int nblk, const void* V0, int64_t vstride, const void* W,
+          double* partials_out, int* nslots_out) {
+  BKTS_REQUIRE(nblk >= 1 && nblk <= kMdotMax, "mdot: bad block count %d", nblk);
+  const int64_t ns = mdot_slots(ctx, n);
+  ProfScope prof(ctx, BKTS_K_GRAM, (1.0 + nblk) * n * esize(dtype));
+  if (dtype == BKTS_F64)
+    launch(ctx, mdot_kernel<double>, dim3(ns), dim3(256), 0, n, nblk, static_cast<const double*>(V0), vstride,
+           static_cast<const double*>(W), partials_out);
+  else
+    launch(ctx, mdot_kernel<float>, dim3(ns), dim3(256), 0, n, nblk, static_cast<const float*>(V0), vstride,
+           static_cast<const float*>(W), partials_out);
+  BKTS_HIP(hipGetLastError());
+  *nslots_out = (int)ns;
+}
+
+void maxpy(bkts_ctx ctx, int dtype, int64_t n, int nblk, const void* V0, int64_t vstride, const double* C, void* W) {
+  BKTS_REQUIRE(nblk >= 1 && nblk <= kMdotMax, "maxpy: bad block count %d", nblk);
+  ProfScope prof(ctx, BKTS_K_OTHER, (2.0 + nblk) * n * esize(dtype));
+  const dim3 grid((unsigned)((n + 255) / 256));
+  if (dtype == BKTS_F64)
+    launch(ctx, maxpy_kernel<double>, grid, dim3(256), 0, n, nblk, static_cast<const double*>(V0), vstride, C,
+           static_cast<double*>(W));
+  else
+    launch(ctx, maxpy_kernel<float>, grid, dim3(256), 0, n, nblk, static_cast<const float*>(V0), vstride, C,
+           static_cast<float*>(W));
   BKTS_HIP(hipGetLastError());
 }
 

@@ -406,6 +406,7 @@ bkts_nlop richards_create(bkts_ctx ctx, const bkts_grid* grid, const double* ks,
     g.lin_L = p->lin_L;
     nl->ks.alloc(sizeof(double) * nl->N);
     BKTS_HIP(hipMemcpyAsync(nl->ks.p, ks, sizeof(double) * nl->N, hipMemcpyDeviceToDevice, ctx->stream));
+    ctx->sync();  // the caller may release ks on return
     g.ks = nl->ks.as<double>();
     bkts_fv_coeffs lc{};
     lc.kappa_const = 1.0;
