@@ -317,7 +317,8 @@ def run_nonlinear(torch, bkts, ctx, a):
         dom = max((c for c in blk["kernels"] if c not in ("small", "other")),
                   key=lambda c: blk["kernels"][c]["total_ms"])
         roof = roofline_of(blk["kernels"], dom, a.nl_k, "f32")
-        roof["kernel"] = {"spmm": "spmm_ell_kernel", "residual": "nl_residual_kernel"}.get(dom, roof["kernel"])
+        roof["kernel"] = {"spmm": "spmm_ell_kernel", "residual": "nl_residual_kernel",
+                          "norms": "coldots_kernel (BiCGStab column dots) and colnorm_kernel"}.get(dom, roof["kernel"])
     return {"workload": f"nonlinear diffusion-reaction {a.nl_n}^2 FV, D(u)=1+u^2, r(u)=-u^3, zero flux, SDIRK2 "
                         f"tau=1e-4, {a.nl_k} columns ({a.nl_k // 2} steps x 2 stages), Newton to 1e-8, per-column "
                         f"(vectorized) BiCGStab inner {a.nl_inner_rtol:g} in FP32, Jacobi, seeded smooth u0 in [0,1]",
@@ -448,7 +449,8 @@ def run_richards(torch, bkts, ctx, a):
         dom = max((c for c in blk["kernels"] if c not in ("small", "other")),
                   key=lambda c: blk["kernels"][c]["total_ms"])
         roof = roofline_of(blk["kernels"], dom, a.ri_k, "f32")
-        roof["kernel"] = {"spmm": "spmm_ell_kernel", "residual": "nl_residual_kernel"}.get(dom, roof["kernel"])
+        roof["kernel"] = {"spmm": "spmm_ell_kernel", "residual": "nl_residual_kernel",
+                          "gram": "mf_mgram_kernel and mf_gram_kernel (block Gram-Schmidt)"}.get(dom, roof["kernel"])
     best = max(res, key=lambda t: res[t]["value"])
     return {"workload": f"Richards' equation {a.ri_n}^3 FV, van Genuchten alpha=2 n=2 theta_r=0.05 theta_s=0.4, "
                         f"lognormal Ks (log-std 1.5, corr. 8 cells), psi0=-z, Dirichlet psi=-0.3 on top, free "
