@@ -71,6 +71,9 @@ def parse():
                    help="window-solve leg: comma list of window widths solved whole by FGMRES on the all-at-once "
                         "operator and by the plain splitting iteration (empty = skip)")
     p.add_argument("--accel-inner-rtol", type=float, default=0.1)
+    p.add_argument("--spmm-ks", type=str, default="1,4,8,16,32",
+                   help="block-operator sweep widths ('' = skip)")
+    p.add_argument("--spmm-reps", type=int, default=30)
     p.add_argument("--sweep", type=str, default="1f32,4f64,4f32@0.01,8,16,32",
                    help="comma list of extra block forms to time: <k>[f32|f64][@inner_rtol] (defaults: --precision, "
                         "--inner-rtol)")
@@ -97,7 +100,7 @@ def kernel_table(bkts, ctx):
 def kernel_name(cat, k):
     """The kernel behind a profiling category in the block-CG inner solve at width k."""
     row = k in (1, 2, 4)  # one thread per row; wider blocks use column tiles (MFMA for the updates)
-    return {"spmm": "rk_spmm_gram_kernel" if row else "spmm_ell_kernel",
+    return {"spmm": "rk_spmm_gram_kernel" if row else spmm_kernel_name(k, "f32"),
             "cg_update": "rk_cg_update_kernel" if row else "mf_cg_update_kernel",
             "cg_pupdate": "rk_cg_pupdate_kernel" if row else "mf_cg_pupdate_kernel",
             "gram": "rk_gram_kernel" if row else "mf_gram_kernel",
@@ -135,6 +138,55 @@ def traffic_for(kernel, precision, k):
         return e["hbm_bytes_per_launch"]
     except (OSError, ValueError, KeyError):
         return None
+
+
+def spmm_kernel_name(k, precision):
+    """Kernel that bkts_spmm launches on a uniform-width SELL operator at width k."""
+    kp = 1
+    while kp < k:
+        kp *= 2
+    sv = 4 if precision == "f32" else 8
+    return "spmm_coop_kernel" if kp * sv >= 64 else "spmm_ell_kernel"
+
+
+def run_spmm_sweep(torch, bkts, ctx, a, kd, n):
+    """Block operator alone at every width, FP64 and FP32, on the 128^3 lognormal operator.
+
+    Three assembled copies of the operator and three (X, Y) pairs are used in rotation so that the
+    working set of consecutive launches exceeds the 256 MiB Infinity Cache (each launch reads cold
+    data). Time per launch comes from the library's in-dispatch event timers."""
+    N = n[0] * n[1] * n[2]
+    ops = [bkts.bkts_fv_assemble(ctx, n, kappa=kd, fmt=bkts.BKTS_FMT_SELL) for _ in range(3)]
+    _, nnz = bkts.bkts_op_info(ops[0])
+    out = {}
+    for prec, dt, sv in (("f64", torch.float64, 8), ("f32", torch.float32, 4)):
+        for k in [int(v) for v in a.spmm_ks.split(",") if v.strip()]:
+            gen = torch.Generator(device="cuda").manual_seed(k)
+            Xs = [torch.randn((N, k), dtype=dt, device="cuda", generator=gen) for _ in range(3)]
+            Ys = [torch.empty_like(x) for x in Xs]
+            for i in range(3):
+                bkts.bkts_spmm(ctx, ops[i], Xs[i], Ys[i], alpha=1e3, beta=1.0)
+            torch.cuda.synchronize()
+            bkts.bkts_profile_enable(ctx, True, 1)
+            for i in range(a.spmm_reps):
+                j = i % 3
+                bkts.bkts_spmm(ctx, ops[j], Xs[j], Ys[j], alpha=1e3, beta=1.0)
+            torch.cuda.synchronize()
+            cnt, ms, by = bkts.bkts_profile_query(ctx, "spmm")
+            bkts.bkts_profile_enable(ctx, False)
+            us = 1e3 * ms / cnt
+            bpl = by / cnt
+            gbs = bpl / (us * 1e-6) / 1e9
+            out[f"{prec} k={k}"] = {"avg_us": us, "GBps": gbs, "frac": gbs / HBM_PEAK_GBS,
+                                    "algorithmic_bytes_per_launch": bpl, "flop_per_byte": 2.0 * nnz * k / bpl,
+                                    "kernel": spmm_kernel_name(k, prec), "launches": cnt}
+            log(f"  spmm {prec} k={k:2d}: {us:7.1f} us  {gbs:6.0f} GB/s  frac {gbs / HBM_PEAK_GBS:.3f}  "
+                f"AI {2.0 * nnz * k / bpl:.3f} flop/B")
+            del Xs, Ys
+    for o in ops:
+        bkts.bkts_op_destroy(o)
+    torch.cuda.synchronize()
+    return out
 
 
 def calibrate_copy(torch):
@@ -317,7 +369,7 @@ def run_nonlinear(torch, bkts, ctx, a):
         dom = max((c for c in blk["kernels"] if c not in ("small", "other")),
                   key=lambda c: blk["kernels"][c]["total_ms"])
         roof = roofline_of(blk["kernels"], dom, a.nl_k, "f32")
-        roof["kernel"] = {"spmm": "spmm_ell_kernel", "residual": "nl_residual_kernel",
+        roof["kernel"] = {"spmm": spmm_kernel_name(a.nl_k, "f32"), "residual": "nl_residual_kernel",
                           "norms": "coldots_kernel (BiCGStab column dots) and colnorm_kernel"}.get(dom, roof["kernel"])
     return {"workload": f"nonlinear diffusion-reaction {a.nl_n}^2 FV, D(u)=1+u^2, r(u)=-u^3, zero flux, SDIRK2 "
                         f"tau=1e-4, {a.nl_k} columns ({a.nl_k // 2} steps x 2 stages), Newton to 1e-8, per-column "
@@ -449,7 +501,7 @@ def run_richards(torch, bkts, ctx, a):
         dom = max((c for c in blk["kernels"] if c not in ("small", "other")),
                   key=lambda c: blk["kernels"][c]["total_ms"])
         roof = roofline_of(blk["kernels"], dom, a.ri_k, "f32")
-        roof["kernel"] = {"spmm": "spmm_ell_kernel", "residual": "nl_residual_kernel",
+        roof["kernel"] = {"spmm": spmm_kernel_name(a.ri_k, "f32"), "residual": "nl_residual_kernel",
                           "gram": "mf_mgram_kernel and mf_gram_kernel (block Gram-Schmidt)"}.get(dom, roof["kernel"])
     best = max(res, key=lambda t: res[t]["value"])
     return {"workload": f"Richards' equation {a.ri_n}^3 FV, van Genuchten alpha=2 n=2 theta_r=0.05 theta_s=0.4, "
@@ -540,6 +592,11 @@ def main():
         if "spmm" in blk["kernels"]:
             spmm_roof = roofline_of(blk["kernels"], "spmm", a.k, a.precision)
 
+    spmm_sweep = None
+    if a.spmm_ks.strip():
+        log(f"block-operator sweep: k in {a.spmm_ks}, FP64 and FP32, 3 rotating copies")
+        spmm_sweep = run_spmm_sweep(torch, bkts, ctx, a, kd, n)
+
     accel, accel_keep = None, None
     if a.accel.strip():
         log(f"window-solve leg (outer acceleration): k in {a.accel}")
@@ -610,6 +667,7 @@ def main():
         "sweep": sweep or None,
         "roofline": roof,
         "spmm_roofline": spmm_roof,
+        "spmm_sweep": spmm_sweep,
         "kernels": blk["kernels"],
         "cpu_baseline": cpu,
         "window_acceleration": accel,

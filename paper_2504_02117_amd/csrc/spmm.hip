@@ -58,6 +58,26 @@ __device__ __forceinline__ void vstore(T* p, const Vec<T, V>& r) {
   }
 }
 
+// Streaming store of the output rows: Y is not re-read by this kernel, so its lines are marked
+// non-temporal and do not displace the X rows that later stencil neighbours read from L2.
+template <typename T, int V>
+__device__ __forceinline__ void vstore_nt(T* p, const Vec<T, V>& r) {
+  if constexpr (sizeof(T) * V == 16) {
+    if constexpr (sizeof(T) == 8) {
+      typedef double d2 __attribute__((ext_vector_type(2)));
+      const d2 q = {r.v[0], r.v[1]};
+      __builtin_nontemporal_store(q, reinterpret_cast<d2*>(p));
+    } else {
+      typedef float f4 __attribute__((ext_vector_type(4)));
+      const f4 q = {r.v[0], r.v[1], r.v[2], r.v[3]};
+      __builtin_nontemporal_store(q, reinterpret_cast<f4*>(p));
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < V; ++i) __builtin_nontemporal_store(r.v[i], p + i);
+  }
+}
+
 template <typename T>
 struct SpmmArgs {
   int64_t N;
@@ -162,7 +182,7 @@ __global__ __launch_bounds__(256) void spmm_kernel(SpmmArgs<T> a) {
 // all G rows are in flight before their dependent X-row loads, which are again all in flight
 // before the first FMA.  Branch-free: padding entries and rows past N read a valid row with a
 // zero weight.
-template <typename T, int KP, int VEC, int G>
+template <typename T, int KP, int VEC, int G, bool NTS>
 __global__ __launch_bounds__(256) void spmm_ell_kernel(SpmmArgs<T> a) {
   constexpr int LPR = KP / VEC;
   constexpr int RPB = dev::kThreads / LPR;
@@ -218,16 +238,100 @@ __global__ __launch_bounds__(256) void spmm_ell_kernel(SpmmArgs<T> a) {
 #pragma unroll
       for (int i = 0; i < VEC; ++i) out.v[i] = fma(a.cb, br.v[i], out.v[i]);
     }
-    vstore<T, VEC>(a.Y + r[g] * a.ldy + c0, out);
+    if constexpr (NTS)
+      vstore_nt<T, VEC>(a.Y + r[g] * a.ldy + c0, out);
+    else
+      vstore<T, VEC>(a.Y + r[g] * a.ldy + c0, out);
   }
+}
+
+// Uniform-width SELL with cooperative matrix loads, for wide rows (LPR = KP/VEC >= 2 lanes per
+// row): lane l of a row's lane group loads entries l, l+LPR, ... of that row, and the entries are
+// then broadcast inside the group with cross-lane shuffles.  One wave instruction thus fetches
+// LPR entries of every row instead of one, which cuts the matrix-load instructions by LPR (the
+// X-row gathers and the output store are as in the ELL kernel).  All lanes take part in the
+// shuffles, so lanes past k (or rows past N) stay alive and only skip their X loads and stores.
+template <typename T, int KP, int VEC>
+__global__ __launch_bounds__(256) void spmm_coop_kernel(SpmmArgs<T> a) {
+  constexpr int LPR = KP / VEC;
+  constexpr int RPB = dev::kThreads / LPR;
+  constexpr int NE = (kUnroll + LPR - 1) / LPR;  // entries per lane (W <= kUnroll)
+  const int t = threadIdx.x;
+  const int l = t % LPR, c0 = l * VEC;
+  const int gb = (t & 63) & ~(LPR - 1);           // first lane of this row's group in the wave
+  int64_t tile;
+  if (a.strip > 0) {
+    const int64_t b = blockIdx.x, x = b % dev::kXcd, i = b / dev::kXcd;
+    tile = ((i / a.strip) * dev::kXcd + x) * a.strip + i % a.strip;
+  } else {
+    tile = dev::xcd_slot(blockIdx.x, gridDim.x);
+  }
+  const int W = a.uw;
+  const int64_t nslot_rows = ((a.N + a.C - 1) / a.C) * a.C;
+  const int64_t r = tile * RPB + t / LPR;
+  const int64_t rs = r < nslot_rows ? r : nslot_rows - 1;
+  const int64_t s = rs / a.C;
+  const int64_t base = s * a.C * W + (rs - s * a.C);
+  const int32_t self = (int32_t)(rs < a.N ? rs : a.N - 1);
+  T vo[NE];
+  int32_t co[NE];
+#pragma unroll
+  for (int e = 0; e < NE; ++e) {
+    const int u = l + e * LPR;
+    if (u < W) {
+      vo[e] = __builtin_nontemporal_load(a.val + base + (int64_t)u * a.C);
+      co[e] = __builtin_nontemporal_load(a.col + base + (int64_t)u * a.C);
+    } else {
+      vo[e] = T(0);
+      co[e] = self;
+    }
+  }
+  const bool active = c0 < a.k && r < a.N;
+  Vec<T, VEC> acc;
+#pragma unroll
+  for (int i = 0; i < VEC; ++i) acc.v[i] = T(0);
+  T v[kUnroll];
+  Vec<T, VEC> x[kUnroll];
+#pragma unroll
+  for (int u = 0; u < kUnroll; ++u) {
+    if (u < W) {  // uniform over the launch
+      v[u] = __shfl(vo[u / LPR], gb + u % LPR, 64);
+      const int32_t cu = __shfl(co[u / LPR], gb + u % LPR, 64);
+      if (active) x[u] = vload<T, VEC>(a.X + (int64_t)cu * a.ldx + c0);
+    }
+  }
+  if (!active) return;
+#pragma unroll
+  for (int u = 0; u < kUnroll; ++u) {
+    if (u < W) {
+#pragma unroll
+      for (int i = 0; i < VEC; ++i) acc.v[i] = fma(v[u], x[u].v[i], acc.v[i]);
+    }
+  }
+  const Vec<T, VEC> xr = vload<T, VEC>(a.X + r * a.ldx + c0);
+  Vec<T, VEC> out;
+#pragma unroll
+  for (int i = 0; i < VEC; ++i) out.v[i] = a.beta * acc.v[i] + a.alpha * xr.v[i];
+  if (a.B) {
+    const Vec<T, VEC> br = vload<T, VEC>(a.B + r * a.ldb + c0);
+#pragma unroll
+    for (int i = 0; i < VEC; ++i) out.v[i] = fma(a.cb, br.v[i], out.v[i]);
+  }
+  vstore_nt<T, VEC>(a.Y + r * a.ldy + c0, out);
 }
 
 template <typename T, int KP, int VEC>
 void launch_fmt(bkts_ctx ctx, const bkts_op_s& op, const SpmmArgs<T>& a) {
   constexpr int LPR = KP / VEC;
-  constexpr int G = sizeof(T) == 8 ? 1 : 2;  // rows per thread on the uniform-width path (FP64: registers)
+  // Uniform-width path, measured on the 128^3 7-point operator with cold inputs: rows of >= 16
+  // bytes split over >= 2 lanes (FP64 k >= 8, FP32 k >= 16) take the cooperative-load kernel;
+  // narrower rows the ELL kernel, with streaming stores from 8 columns on.  Two rows per thread
+  // pay off only for narrow FP32 rows (FP64: registers).
+  constexpr bool COOP = LPR >= 2 && KP * sizeof(T) >= 64;
+  constexpr bool NTS = KP >= 8;
+  constexpr int G = (sizeof(T) == 8 || KP >= 8) ? 1 : 2;
   const bool ell = op.format == BKTS_FMT_SELL && op.sell_uniform_w > 0 && op.sell_uniform_w <= kUnroll;
-  const int RPB = dev::kThreads / LPR * (ell ? G : 1);
+  const int RPB = dev::kThreads / LPR * (ell && !COOP ? G : 1);
   const int64_t ntiles = (a.N + RPB - 1) / RPB;
   int64_t nb = ntiles;
   SpmmArgs<T> aa = a;
@@ -237,8 +341,10 @@ void launch_fmt(bkts_ctx ctx, const bkts_op_s& op, const SpmmArgs<T>& a) {
     const int64_t per = dev::kXcd * aa.strip;
     nb = (ntiles + per - 1) / per * per;  // whole rounds of 8 strips; blocks past the end exit
   }
-  if (ell)
-    launch(ctx, (spmm_ell_kernel<T, KP, VEC, G>), dim3(nb), dim3(dev::kThreads), 0, aa);
+  if (ell && COOP)
+    launch(ctx, (spmm_coop_kernel<T, KP, VEC>), dim3(nb), dim3(dev::kThreads), 0, aa);
+  else if (ell)
+    launch(ctx, (spmm_ell_kernel<T, KP, VEC, G, NTS>), dim3(nb), dim3(dev::kThreads), 0, aa);
   else if (op.format == BKTS_FMT_SELL)
     launch(ctx, (spmm_kernel<T, KP, VEC, true>), dim3(nb), dim3(dev::kThreads), 0, aa);
   else

@@ -267,6 +267,43 @@ def test_advance_matches_sequential_oracle(env, method, name, theta, k, precisio
         bkts.bkts_op_destroy(op)
 
 
+@pytest.mark.parametrize("strided", [False, True])
+@pytest.mark.parametrize("k", [2, 5, 8, 12, 16, 32])
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_spmm_fv_uniform_width(env, dtype, k, strided):
+    """Stencil operators store a uniform-width SELL; wide rows take the cooperative-load kernel
+    (entries loaded by one lane each, then shuffled to the row's lanes) and narrow rows the ELL
+    kernel. Ragged N (not a multiple of the 64-row slice), k below its padded width, and leading
+    dimensions that rule out 16-byte vector access."""
+    torch, bkts, ctx = env
+    n = (20, 19, 18)
+    say(f"spmm fv uniform k={k} {dtype} strided={strided}")
+    op, K, _ = fv_op(env, n, inputs.lognormal_field(n, 0, 2.0, 3.0, 2))
+    try:
+        N = K.shape[0]
+        X = inputs.random_block(N, k, 11)
+        tdt = torch.float64 if dtype == "f64" else torch.float32
+        pad = 3 if strided else 0
+        Xbig = torch.zeros((N, k + pad), dtype=tdt, device="cuda")
+        Xbig[:, :k] = dev(torch, X, tdt)
+        Ybig = torch.full((N, k + pad), 7.0, dtype=tdt, device="cuda")
+        bkts.bkts_spmm(ctx, op, Xbig[:, :k], Ybig[:, :k], alpha=-2.5, beta=1.0)
+        if dtype == "f64":
+            ref = blockops.block_operator(K, X, -2.5, 1.0)
+            tol = 1e-13
+        else:
+            Kf = sp.csr_matrix((K.data.astype(np.float32).astype(np.float64), K.indices, K.indptr), shape=K.shape)
+            ref = blockops.block_operator(Kf, X.astype(np.float32).astype(np.float64), -2.5, 1.0)
+            tol = 2e-6
+        got = Ybig.double().cpu().numpy()
+        scale = abs(K).sum(1).A.ravel()[:, None] * abs(X).max() + 2.5 * abs(X).max()
+        assert (abs(got[:, :k] - ref) / scale).max() < tol
+        if pad:
+            assert (got[:, k:] == 7.0).all()  # padding columns untouched
+    finally:
+        bkts.bkts_op_destroy(op)
+
+
 def test_full_size_128cubed_sampled(env):
     """The 128^3 lognormal (sigma=2, correlation 8 cells) operator at full size: sampled SpMM rows at
     k = 16 against the oracle's rows one by one, and two accepted IE steps of the block method
