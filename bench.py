@@ -57,6 +57,8 @@ def parse():
     p.add_argument("--serve-budget-gib", type=float, default=4.0)
     p.add_argument("--serve-slots", type=int, default=64)
     p.add_argument("--serve-inner-rtol", type=float, default=0.1)
+    p.add_argument("--no-serve-plain", dest="serve_plain", action="store_false",
+                   help="skip the plain FP64 one-at-a-time replay of the serving trace")
     p.add_argument("--nl-n", type=int, default=1024, help="nonlinear leg: grid n x n (0 = skip)")
     p.add_argument("--nl-k", type=int, default=16, help="nonlinear leg: window columns (8 steps x 2 stages)")
     p.add_argument("--nl-steps", type=int, default=8)
@@ -287,6 +289,7 @@ def run_serving(torch, bkts, ctx, a):
         elem_it += float(r.krylov_iterations) * sizes[i] ** 2 * widths[i]
         outer_tot += r.outer_iterations
     makespan = t_end - t0
+    fifo = run_serving_plain(torch, bkts, ctx, reqs, arrivals, widths, sizes, y0s) if a.serve_plain else None
     # oracle check of the smallest requests of the trace
     from oracle import fv, stepping
     errs = []
@@ -307,9 +310,50 @@ def run_serving(torch, bkts, ctx, a):
             "inner_stream_GBps": 44.0 * elem_it / makespan / 1e9,
             "hbm_budget_bytes": int(a.serve_budget_gib * (1 << 30)), "hbm_peak_reserved_bytes": st.bytes_peak,
             "oracle_max_rel_err_sampled": max(errs) if errs else None, "inner_rtol": a.serve_inner_rtol,
+            "plain_fifo": fifo,
+            "speedup_vs_plain_fifo": (fifo["makespan_s"] / makespan) if fifo else None,
             "workload": "2-D lognormal diffusion (log-std 2, corr. 8 cells, seed 1000+i), n in {64,128,256,512}, "
                         "k in {4,8,16,32}, implicit Euler tau=1e-3, one window of k steps per request, "
                         "FP32 block CG inside FP64 Newton to 1e-8, Poisson arrivals"}
+
+
+def run_serving_plain(torch, bkts, ctx, reqs, arrivals, widths, sizes, y0s):
+    """The same trace served one request at a time in arrival order by plain FP64 k = 1 stepping (CG +
+    Jacobi, inner = outer = 1e-8): each request's operator is assembled when it starts, and its k steps
+    are taken one after another.  Arrivals are replayed on the same clock as the served form."""
+    import numpy as np
+    log(f"serving baseline: plain FP64 k=1 stepping, one request at a time in arrival order")
+    inner = bkts.solve_opts(precision=bkts.BKTS_PRECISION_F64, rtol=1e-8, inner_rtol=1e-8, maxit=100000)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lat, done, its = [], 0.0, 0
+    for i, (n, kd, out) in enumerate(reqs):
+        now = time.perf_counter() - t0
+        if now < arrivals[i]:
+            time.sleep(arrivals[i] - now)
+        k = int(widths[i])
+        op = bkts.bkts_fv_assemble(ctx, n, kappa=kd, fmt=bkts.BKTS_FMT_SELL)
+        tc = bkts.bkts_tc_create(ctx, bkts.BKTS_IE, 1, 1e-3)
+        st = bkts.bkts_stepper_create(ctx, op, tc, y0s[n])
+        hist = torch.empty((k, n[0] * n[1]), dtype=torch.float64, device="cuda")
+        try:
+            info = bkts.bkts_stepper_advance(st, k, inner=inner, outer_rtol=1e-8, max_outer=400, y_hist=hist)
+            its += info.krylov_iterations
+            torch.empty_like(out).copy_(hist.t())  # the result in the served layout (N x k)
+            torch.cuda.synchronize()
+        finally:
+            bkts.bkts_stepper_destroy(st)
+            bkts.bkts_tc_destroy(tc)
+            bkts.bkts_op_destroy(op)
+        done = time.perf_counter() - t0
+        lat.append(done - arrivals[i])
+    work = float(np.sum(np.asarray(sizes, dtype=np.float64) ** 2 * widths))
+    log(f"  plain FIFO: makespan {done:.2f} s, {work / done:.4g} DOF*steps/s, p50 "
+        f"{1e3 * np.percentile(lat, 50):.0f} ms, p99 {1e3 * np.percentile(lat, 99):.0f} ms")
+    return {"makespan_s": done, "throughput_dof_timesteps_per_s": work / done,
+            "latency_p50_ms": 1e3 * float(np.percentile(lat, 50)),
+            "latency_p99_ms": 1e3 * float(np.percentile(lat, 99)), "krylov_iterations": its,
+            "config": "FP64 k=1 CG + Jacobi, inner = outer = 1e-8, one request at a time, operator assembled per request"}
 
 
 def run_nonlinear(torch, bkts, ctx, a):
