@@ -11,6 +11,10 @@ Algorithm 1 only changes how that solution is reached.  Stage ``i`` of step
 with ``f(y) = K y - b`` (linear) or a nonlinear ``f`` (Sec. 2.2).  An explicit
 first stage is ``y_1 = y^n``.  Each implicit stage is solved by a direct sparse
 LU (default) or by a Jacobi-preconditioned Krylov method from scipy.
+
+``rk_linear`` covers fully implicit tableaux (the remark on fully implicit
+Runge-Kutta methods after Algorithm 1) by solving the coupled stages of a step
+together.
 """
 from __future__ import annotations
 
@@ -73,6 +77,39 @@ def dirk_linear(K, b, y0, tau, method, n_steps, theta=0.5, M=None, solver="direc
             yq = linear_solve(J, rhs, x0=(st[-1] if st else y), kind=solver, rtol=rtol)
             st.append(yq)
             fst.append(K @ yq - b)
+        y = st[-1].copy()
+        ys.append(y.copy())
+        stages_all.append(st)
+    return ys, stages_all
+
+
+def rk_linear(K, b, y0, tau, method, n_steps, M=None):
+    """Step ``M y' + K y = b`` with any stiffly accurate Runge-Kutta tableau, one step at a time.
+
+    All ``m`` stages of a step are solved together: with ``f(y) = K y - b`` the stage equations
+    ``(1/tau) M (y_i - y^n) + sum_j a_ij f(y_j) = 0`` (Sec. 2 with the sum over every stage, which
+    is the fully implicit case of the remark after Algorithm 1) are, stacked stage by stage,
+
+        (I_m (x) M/tau + A (x) K) [y_1; ...; y_m] = 1 (x) M y^n / tau + (A 1) (x) b,
+
+    solved by one sparse LU of the ``mN x mN`` matrix.  ``y^{n+1} = y_m``.  An explicit first
+    stage (a zero first row) is kept as an ordinary stage, whose equation then gives ``y_1 = y^n``.
+    Returns ``(ys, stages)`` like ``dirk_linear``.
+    """
+    A, _, _ = tableau(method)
+    m = A.shape[0]
+    N = K.shape[0]
+    M = _mass(M, N)
+    Mt = sp.csr_matrix(M) / tau
+    big = (sp.kron(sp.identity(m), Mt) + sp.kron(sp.csr_matrix(A), sp.csr_matrix(K))).tocsc()
+    lu = spla.splu(big)
+    rowsum = A.sum(axis=1)
+    y = np.asarray(y0, dtype=np.float64).copy()
+    ys, stages_all = [y.copy()], []
+    for _ in range(n_steps):
+        rhs = np.concatenate([Mt @ y + rowsum[i] * b for i in range(m)])
+        Ys = lu.solve(rhs)
+        st = [Ys[i * N:(i + 1) * N].copy() for i in range(m)]
         y = st[-1].copy()
         ys.append(y.copy())
         stages_all.append(st)

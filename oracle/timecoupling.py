@@ -37,6 +37,9 @@ def tableau(name: str, theta: float = 0.5):
       an explicit first stage (Sec. 2.1, Example 1).
     * ``"sdirk2"``: the 2-stage L-stable SDIRK with ``gamma = 1 - 1/sqrt(2)``
       (the paper does not print its second-order DIRK; this is the reading).
+    * ``"radau2"``: the 2-stage Radau IIA collocation method (order 3, stiffly
+      accurate, L-stable), a fully implicit scheme for the remark on fully
+      implicit Runge-Kutta methods that follows Algorithm 1.
     """
     name = name.lower()
     if name == "ie":
@@ -52,9 +55,27 @@ def tableau(name: str, theta: float = 0.5):
         A = np.array([[g, 0.0], [1.0 - g, g]])
         b = np.array([1.0 - g, g])
         c = np.array([g, 1.0])
+    elif name == "radau2":
+        A = np.array([[5.0 / 12.0, -1.0 / 12.0], [0.75, 0.25]])
+        b = np.array([0.75, 0.25])
+        c = np.array([1.0 / 3.0, 1.0])
     else:
         raise ValueError(f"unknown method {name!r}")
     return A, b, c
+
+
+def is_fully_implicit(A) -> bool:
+    """True when some stage couples to a later one (an entry above the diagonal)."""
+    return bool(np.any(np.triu(np.asarray(A, dtype=np.float64), 1)))
+
+
+def averaged_beta(A) -> float:
+    """Splitting coefficient of a fully implicit tableau: the remark on fully implicit Runge-Kutta
+    methods (after Algorithm 1) replaces the stage-wise Jacobian by an averaged one.  Reading: a
+    single ``J = M/tau + beta K`` for every stage with ``beta = |det A|^(1/m)``, the geometric mean
+    of the moduli of A's eigenvalues (sqrt(1/6) for 2-stage Radau IIA)."""
+    A = np.asarray(A, dtype=np.float64)
+    return float(abs(np.linalg.det(A)) ** (1.0 / A.shape[0]))
 
 
 def is_stiffly_accurate(A, b) -> bool:
