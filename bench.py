@@ -73,6 +73,10 @@ def parse():
                    help="window-solve leg: comma list of window widths solved whole by FGMRES on the all-at-once "
                         "operator and by the plain splitting iteration (empty = skip)")
     p.add_argument("--accel-inner-rtol", type=float, default=0.1)
+    p.add_argument("--firk-ks", type=str, default="2,4,8",
+                   help="Radau IIA leg: window widths (2 columns per step) of the pipelined form ('' = skip)")
+    p.add_argument("--firk-steps", type=int, default=4)
+    p.add_argument("--firk-inner-rtol", type=float, default=0.1)
     p.add_argument("--spmm-ks", type=str, default="1,4,8,16,32",
                    help="block-operator sweep widths ('' = skip)")
     p.add_argument("--spmm-reps", type=int, default=30)
@@ -472,6 +476,97 @@ def run_accel(torch, bkts, ctx, a, op, u0):
             "unit": "DOF*timesteps/s", "forms": out}, keep
 
 
+def run_firk(torch, bkts, ctx, a, op, u0, kd, n):
+    """2-stage Radau IIA on the 128^3 operator (fully implicit; averaged splitting coefficient).
+
+    Forms, each advancing the same number of steps from u0 to a 1e-8 residual per accepted step:
+    Algorithm 1 accepting whole steps with windows of 1, 2 and 4 steps (2, 4, 8 columns), and
+    sequential stepping in which every step's 2-column window is solved by FGMRES on the
+    all-at-once operator (right-preconditioned by the block J^-1 solve) or by the plain splitting."""
+    import numpy as np
+    tau, steps = 1e-3, a.firk_steps
+    N = u0.shape[0]
+    prec = bkts.BKTS_PRECISION_F32_REFINE
+    inner = bkts.solve_opts(krylov=bkts.BKTS_CG, precision=prec, rtol=a.firk_inner_rtol,
+                            inner_rtol=a.firk_inner_rtol, maxit=100000)
+    forms = {}
+    for kk in [int(v) for v in a.firk_ks.split(",") if v.strip()]:
+        tc = bkts.bkts_tc_create(ctx, bkts.BKTS_RADAU2, kk, tau)
+        st = bkts.bkts_stepper_create(ctx, op, tc, u0)
+        try:
+            bkts.bkts_stepper_advance(st, 1, inner=inner, outer_rtol=1e-8, max_outer=1000)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            info = bkts.bkts_stepper_advance(st, steps, inner=inner, outer_rtol=1e-8, max_outer=1000)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+        finally:
+            bkts.bkts_stepper_destroy(st)
+            bkts.bkts_tc_destroy(tc)
+        forms[f"pipelined k={kk} ({kk // 2} steps)"] = {
+            "value": N * steps / dt, "outer_iterations": info.outer_iterations,
+            "krylov_iterations": info.krylov_iterations}
+        log(f"  Radau IIA pipelined k={kk}: {N * steps / dt:.4g} DOF*steps/s, outer {info.outer_iterations}, "
+            f"krylov {info.krylov_iterations}")
+    tc = bkts.bkts_tc_create(ctx, bkts.BKTS_RADAU2, 2, tau)
+    try:
+        for name, method in (("fgmres", bkts.BKTS_WINDOW_FGMRES), ("splitting", bkts.BKTS_WINDOW_SPLITTING)):
+            y = u0.clone()
+            its = pre = inn = 0
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                B0 = (y / tau).reshape(N, 1).repeat(1, 2).contiguous()
+                Y = y.reshape(N, 1).repeat(1, 2).contiguous()
+                info = bkts.bkts_window_solve(ctx, op, tc, Y, B0=B0, method=method, inner=inner, rtol=1e-8,
+                                              restart=30, maxit=1000)
+                its += info.iterations
+                pre += info.precond_applications
+                inn += info.inner_iterations
+                y = Y[:, 1].contiguous()
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            forms[f"sequential window {name}"] = {"value": N * steps / dt, "outer_iterations": its,
+                                                  "precond_applications": pre, "krylov_iterations": inn}
+            log(f"  Radau IIA sequential {name}: {N * steps / dt:.4g} DOF*steps/s, {its} its, {pre} J-solves")
+    finally:
+        bkts.bkts_tc_destroy(tc)
+    # oracle check on a small grid: pipelined k=4 against sequential coupled-stage stepping
+    from oracle import fv, stepping
+    m = (16, 16, 16)
+    kap = inputs_lognormal(m)
+    K, b = fv.assemble_linear(m, kappa=kap)
+    y0 = u0_small(m)
+    op_s = bkts.bkts_fv_assemble(ctx, m, kappa=torch.from_numpy(kap).cuda(), fmt=bkts.BKTS_FMT_SELL)
+    tc = bkts.bkts_tc_create(ctx, bkts.BKTS_RADAU2, 4, tau)
+    try:
+        hist = torch.empty((4, y0.shape[0]), dtype=torch.float64, device="cuda")
+        bkts.bkts_advance(ctx, op_s, tc, torch.from_numpy(y0).cuda(), 4, inner=inner, outer_rtol=1e-8,
+                          max_outer=1000, y_hist=hist)
+        ys, _ = stepping.rk_linear(K, b, y0, tau, "radau2", 4)
+        got = hist.cpu().numpy()
+        err = max(np.linalg.norm(got[s] - ys[s + 1]) / np.linalg.norm(ys[s + 1]) for s in range(4))
+    finally:
+        bkts.bkts_tc_destroy(tc)
+        bkts.bkts_op_destroy(op_s)
+    best = max(forms, key=lambda f: forms[f]["value"])
+    return {"workload": f"heterogeneous diffusion {a.n}^3 (the headline operator), 2-stage Radau IIA tau=1e-3, "
+                        f"{steps} steps to a 1e-8 residual per accepted step, averaged splitting coefficient "
+                        f"|det A|^(1/2), J^-1 = FP32 block CG + Jacobi at inner rtol {a.firk_inner_rtol}",
+            "unit": "DOF*timesteps/s", "forms": forms, "best": best,
+            "oracle_max_rel_err_16cubed": err}
+
+
+def inputs_lognormal(m):
+    from paper_2504_02117_amd import inputs
+    return inputs.lognormal_field(m, 0.0, 2.0, 8.0 * m[0] / 128.0, 0)
+
+
+def u0_small(m):
+    from paper_2504_02117_amd import inputs
+    return inputs.sin_product(m)
+
+
 def run_richards(torch, bkts, ctx, a):
     """Richards' equation (Sec. 4.3): van Genuchten closure (alpha=2, n=2, theta_r=0.05, theta_s=0.4),
     lognormal Ks (log-std 1.5, corr. 8 cells), hydrostatic start psi0 = -z, Dirichlet psi = -0.3 on top,
@@ -646,6 +741,12 @@ def main():
         log(f"window-solve leg (outer acceleration): k in {a.accel}")
         accel, accel_keep = run_accel(torch, bkts, ctx, a, op, y0)
 
+    firk = None
+    if a.firk_ks.strip():
+        log(f"fully implicit leg (Radau IIA): windows {a.firk_ks}")
+        firk = run_firk(torch, bkts, ctx, a, op, y0, kd, n)
+        log(f"  Radau IIA: oracle rel. error at 16^3 {firk['oracle_max_rel_err_16cubed']:.2e}")
+
     nonlinear = None
     if a.nl_n > 0:
         nonlinear = run_nonlinear(torch, bkts, ctx, a)
@@ -715,6 +816,7 @@ def main():
         "kernels": blk["kernels"],
         "cpu_baseline": cpu,
         "window_acceleration": accel,
+        "fully_implicit": firk,
         "nonlinear": nonlinear,
         "richards": richards,
         "serving": serving,

@@ -154,28 +154,37 @@ bkts_status bkts_gram(bkts_ctx ctx, int dtype, int64_t N, int k, const void* X, 
 
 /* ------------------------------------------------------------ time coupling */
 
-enum { BKTS_IE = 0, BKTS_THETA = 1, BKTS_SDIRK2 = 2, BKTS_DIRK_CUSTOM = 3 };
+enum { BKTS_IE = 0, BKTS_THETA = 1, BKTS_SDIRK2 = 2, BKTS_DIRK_CUSTOM = 3, BKTS_RADAU2 = 4 };
 
 typedef struct bkts_tc_desc {
-  int method;        /* BKTS_IE, BKTS_THETA, BKTS_SDIRK2 or BKTS_DIRK_CUSTOM */
+  int method;        /* BKTS_IE, BKTS_THETA, BKTS_SDIRK2, BKTS_RADAU2 or BKTS_DIRK_CUSTOM */
   double theta;      /* BKTS_THETA only */
   int stages;        /* BKTS_DIRK_CUSTOM: number of stages m (<= 8) */
-  const double* A;   /* BKTS_DIRK_CUSTOM: host, m x m row-major, lower triangular, stiffly accurate */
+  const double* A;   /* BKTS_DIRK_CUSTOM: host, m x m row-major, stiffly accurate (b = last row);
+                        lower triangular (DIRK) or full (fully implicit) */
   const double* c;   /* BKTS_DIRK_CUSTOM: host, m */
   int k;             /* block width: number of stage columns in one window (1..BKTS_MAX_K) */
   double tau;        /* time step */
 } bkts_tc_desc;
 
-/* Build the time coupling of a stiffly accurate DIRK method (Sec. 2, eq.
+/* Build the time coupling of a stiffly accurate Runge-Kutta method (Sec. 2, eq.
  * stiffly-accurate-DIRK; b = last row of A).  A first stage with a zero row
  * is eliminated (Sec. 2.1).  The theta method is the 2-stage scheme
  * [[0,0],[1-theta,theta]]; SDIRK2 is the L-stable 2-stage SDIRK with
- * gamma = 1 - 1/sqrt(2).  The time coupling is a host object: `ctx` may be
- * NULL, and a tc can be used with any context. */
+ * gamma = 1 - 1/sqrt(2); RADAU2 is the 2-stage Radau IIA method
+ * [[5/12,-1/12],[3/4,1/4]], c = (1/3, 1).
+ * Fully implicit tableaux (an entry above the diagonal of the implicit part; the
+ * remark on fully implicit Runge-Kutta methods after Algorithm 1): A2 holds full
+ * m x m diagonal blocks, k must be a multiple of m, windows start at stage 0
+ * (phase 0 only), Algorithm 1 accepts a whole step at a time, and the splitting
+ * uses one averaged coefficient beta = |det A|^(1/m) for every stage.  BKTS_EINVAL
+ * for a singular fully implicit A or such a k.  The time coupling is a host
+ * object: `ctx` may be NULL, and a tc can be used with any context. */
 bkts_status bkts_tc_create(bkts_ctx ctx, const bkts_tc_desc* desc, bkts_tc* out);
 /* Window matrices of eq. time-stepping-matrices-multiple-parallel-time-steps
  * taken from diagonal index `phase` (Sec. 2.2, pipelining): A1, A2 (HOST,
- * k x k row-major) and beta = A2[0][0] (eq. matrix-splitting).  `phase` is the
+ * k x k row-major) and beta = A2[0][0] (eq. matrix-splitting; the averaged
+ * coefficient for a fully implicit tableau).  `phase` is the
  * implicit-stage index of the front column within its step (0 <= phase < m_impl).
  * Any output may be NULL. */
 bkts_status bkts_tc_get(bkts_tc tc, int phase, double* A1, double* A2, double* beta, int* k, int* m_impl);
@@ -243,7 +252,9 @@ typedef void (*bkts_step_cb)(int step, double t, const double* y_device, void* u
  * problem y' + K y = b: a window of k stage columns is iterated with
  * Y <- Y - J^{-1} R(Y), J = I/tau + beta K, until the front column's residual
  * satisfies ||R_0|| <= outer_rtol * ||rhs_0||; the front stage is then
- * accepted and the window shifted (shift(Y_1..Y_k) = (Y_2..Y_k, Y_k)).
+ * accepted and the window shifted (shift(Y_1..Y_k) = (Y_2..Y_k, Y_k)).  For a
+ * fully implicit tableau the m columns of the front step must all pass the test
+ * and are accepted and shifted out together.
  * `y` (device, N) holds y^0 on entry and y^{n_steps} on exit.  `y_hist`
  * (device, n_steps x N, may be NULL) receives every accepted y^n.  `cb` may
  * be NULL.  Synchronises. */
@@ -344,7 +355,8 @@ bkts_status bkts_nl_mass(bkts_ctx ctx, bkts_nlop nl, int k, const double* Y, int
 typedef struct bkts_stepper_s* bkts_stepper;
 bkts_status bkts_stepper_create(bkts_ctx ctx, bkts_op op, bkts_tc tc, const double* y0, bkts_stepper* out);
 /* The nonlinear pipeline (Algorithm 1 with Newton: the Jacobian at the front column is rebuilt
- * every outer iteration and used for all columns). */
+ * every outer iteration and used for all columns).  DIRK tableaux only: BKTS_EINVAL for a fully
+ * implicit one. */
 bkts_status bkts_nl_stepper_create(bkts_ctx ctx, bkts_nlop nl, bkts_tc tc, const double* y0, bkts_stepper* out);
 bkts_status bkts_stepper_advance(bkts_stepper st, int n_steps, const bkts_solve_opts* inner, double outer_rtol,
                                  int max_outer, double* y_hist, bkts_step_cb cb, void* user, bkts_run_info* info);

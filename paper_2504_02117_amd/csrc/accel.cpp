@@ -24,7 +24,7 @@ void window_solve(bkts_ctx ctx, const bkts_op_s& op, const bkts_tc_s& tc, int ph
   const int k = tc.k;
   const int64_t n = N * k;
   const double tau = tc.tau;
-  const double beta = tc.A2[phase][0];
+  const double beta = tc_beta(tc, phase);
   const size_t nm = 2 * (size_t)k * k + k;
   double* mats = ctx->ws.get<double>("acc_mats", 2 * nm);  // window matrices, then a copy with zero row sums
   double* matsL = mats + nm;

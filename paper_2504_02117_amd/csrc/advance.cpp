@@ -179,7 +179,10 @@ bkts_status bkts_stepper_s::advance(int n_steps, const bkts_solve_opts& inner, d
       colnorms2(ctx, BKTS_F64, N, 1, tmp.as<double>(), 1, nrmp + k);
     }
     upload_window(ctx, *tc, phase, off, mats.as<double>(), nullptr, nullptr);
-    const double beta = tc->A2[phase][0];
+    const double beta = tc_beta(*tc, phase);
+    // columns accepted together: the front stage, or every stage of the front step when the
+    // tableau is fully implicit (its first stage couples to the later ones of the same step)
+    const int nacc = tc->fully_implicit ? mi : 1;
     bool front_ok = false;
     for (int it = 0;; ++it) {
       if (nl) {
@@ -192,7 +195,9 @@ bkts_status bkts_stepper_s::advance(int n_steps, const bkts_solve_opts& inner, d
       }
       read_vec(ctx, nrmp, k + 1, hn);
       const double rhs0 = std::sqrt(hn[k]);
-      const double front = std::sqrt(hn[off]);
+      double front2 = 0.0;
+      for (int i = 0; i < nacc; ++i) front2 = std::max(front2, hn[(off + i) % k]);
+      const double front = std::sqrt(front2);
       if (nl && k > 1) guard_window(it, off, hn, ref, active, frozen);
       ri.final_front_rel_residual = rhs0 > 0.0 ? front / rhs0 : front;
       if (!std::isfinite(front)) throw Error{BKTS_EBREAKDOWN, "non-finite residual in the time window"};
@@ -228,9 +233,9 @@ bkts_status bkts_stepper_s::advance(int n_steps, const bkts_solve_opts& inner, d
       std::fill(frozen.begin(), frozen.end(), 0);
       std::fill(active.begin(), active.end(), 1);
     }
-    // accept the front stage
-    if (phase == mi - 1) {
-      extract_col(ctx, N, Yp, k, off, yp);
+    // accept the front stage (the whole front step for a fully implicit tableau)
+    if (tc->fully_implicit || phase == mi - 1) {
+      extract_col(ctx, N, Yp, k, (off + nacc - 1) % k, yp);
       ++done;
       ++accepted;
       if (y_hist)
@@ -246,8 +251,10 @@ bkts_status bkts_stepper_s::advance(int n_steps, const bkts_solve_opts& inner, d
       eval_f(Yp + off, k, fstp + phase, mi);
       ++phase;
     }
-    copy_col(ctx, N, Yp, k, (off + k - 1) % k, off);  // shift: duplicate the last column
-    off = (off + 1) % k;
+    for (int i = 0; i < nacc; ++i) {  // shift: duplicate the last column
+      copy_col(ctx, N, Yp, k, (off + k - 1) % k, off);
+      off = (off + 1) % k;
+    }
   }
   ctx->sync();
   ri.accepted_steps = done;

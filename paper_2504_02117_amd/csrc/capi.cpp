@@ -189,7 +189,7 @@ bkts_status bkts_tc_get(bkts_tc tc, int phase, double* A1, double* A2, double* b
   const size_t kk = (size_t)tc->k * tc->k;
   if (A1) std::memcpy(A1, tc->A1[phase].data(), sizeof(double) * kk);
   if (A2) std::memcpy(A2, tc->A2[phase].data(), sizeof(double) * kk);
-  if (beta) *beta = tc->A2[phase][0];
+  if (beta) *beta = tc_beta(*tc, phase);
   if (k) *k = tc->k;
   if (m_impl) *m_impl = tc->m_impl;
   BKTS_API_END
@@ -203,6 +203,7 @@ bkts_status bkts_residual(bkts_ctx ctx, bkts_op op, bkts_tc tc, int phase, const
   check_ctx(ctx);
   BKTS_REQUIRE(op && op->ctx == ctx && tc, "op must belong to ctx and tc must not be NULL");
   BKTS_REQUIRE(phase >= 0 && phase < tc->m_impl, "phase must be in 0..%d", tc->m_impl - 1);
+  BKTS_REQUIRE(!tc->fully_implicit || phase == 0, "a fully implicit tableau's windows start at stage 0 (whole steps)");
   const int k = tc->k;
   check_block(Y, k, ldy, "Y");
   check_block(R, k, ldr, "R");
@@ -295,6 +296,7 @@ bkts_status bkts_window_solve(bkts_ctx ctx, bkts_op op, bkts_tc tc, int phase, c
   check_ctx(ctx);
   BKTS_REQUIRE(op && op->ctx == ctx && tc, "op must belong to ctx and tc must not be NULL");
   BKTS_REQUIRE(phase >= 0 && phase < tc->m_impl, "phase must be in 0..%d", tc->m_impl - 1);
+  BKTS_REQUIRE(!tc->fully_implicit || phase == 0, "a fully implicit tableau's windows start at stage 0 (whole steps)");
   BKTS_REQUIRE(Y, "Y must not be NULL");
   BKTS_REQUIRE(method == BKTS_WINDOW_FGMRES || method == BKTS_WINDOW_SPLITTING, "unknown window method %d", method);
   BKTS_REQUIRE(inner, "inner options must not be NULL");
@@ -455,6 +457,7 @@ bkts_status bkts_nl_residual(bkts_ctx ctx, bkts_nlop nl, bkts_tc tc, int phase, 
   check_ctx(ctx);
   BKTS_REQUIRE(nl && nl->ctx == ctx && tc, "nl must belong to ctx and tc must not be NULL");
   BKTS_REQUIRE(phase >= 0 && phase < tc->m_impl, "phase must be in 0..%d", tc->m_impl - 1);
+  BKTS_REQUIRE(!tc->fully_implicit || phase == 0, "a fully implicit tableau's windows start at stage 0 (whole steps)");
   const int k = tc->k;
   check_block(Y, k, ldy, "Y");
   check_block(R, k, ldr, "R");
@@ -481,6 +484,7 @@ bkts_status bkts_newton_step(bkts_ctx ctx, bkts_nlop nl, bkts_tc tc, int phase, 
   check_ctx(ctx);
   BKTS_REQUIRE(nl && nl->ctx == ctx && tc, "nl must belong to ctx and tc must not be NULL");
   BKTS_REQUIRE(phase >= 0 && phase < tc->m_impl, "phase must be in 0..%d", tc->m_impl - 1);
+  BKTS_REQUIRE(!tc->fully_implicit || phase == 0, "a fully implicit tableau's windows start at stage 0 (whole steps)");
   BKTS_REQUIRE(Y && opts, "Y and opts must not be NULL");
   BKTS_REQUIRE(opts->rtol > 0.0 && opts->rtol < 1.0, "rtol must be in (0, 1)");
   const int k = tc->k;
@@ -497,7 +501,7 @@ bkts_status bkts_newton_step(bkts_ctx ctx, bkts_nlop nl, bkts_tc tc, int phase, 
   for (int i = 0; i < 8; ++i) cols[i] = i;
   bkts::nl_residual(ctx, *nl, k, Y, k, mats, mats + k * k, B0, ldb0, B0 ? nb0 : 0, cols, R, k, nrm);
   if (col_norms2) BKTS_HIP(hipMemcpyAsync(col_norms2, nrm, sizeof(double) * k, hipMemcpyDeviceToHost, ctx->stream));
-  bkts::nl_jacobian(ctx, *nl, Y, k, 1.0 / tc->tau, tc->A2[phase][0]);
+  bkts::nl_jacobian(ctx, *nl, Y, k, 1.0 / tc->tau, tc_beta(*tc, phase));
   bkts::KrylovStats st;
   bkts::solve(ctx, *nl->jac, 0.0, 1.0, k, R, V, true, *opts, false, st);
   bkts::axpby(ctx, N * k, -1.0, V, 1.0, Y);
@@ -519,6 +523,7 @@ bkts_status bkts_nl_stepper_create(bkts_ctx ctx, bkts_nlop nl, bkts_tc tc, const
   *out = nullptr;
   BKTS_REQUIRE(nl && nl->ctx == ctx && tc, "nl must belong to ctx and tc must not be NULL");
   BKTS_REQUIRE(y0, "y0 must not be NULL");
+  BKTS_REQUIRE(!tc->fully_implicit, "the Newton stepper takes DIRK tableaux (lower triangular A)");
   set_device(ctx);
   *out = new bkts_stepper_s(ctx, nl->jac, tc, y0, nl);
   BKTS_API_END

@@ -67,6 +67,14 @@ struct Workspace {
 
 inline size_t esize(int dtype) { return dtype == BKTS_F32 ? 4 : 8; }
 
+// Pivot floor of the deflating k x k Gram solve in block CG (Jacobi-scaled, so a pivot is the squared
+// sine of the angle between a direction and the span of the earlier ones).  FP32 Gram matrices
+// carry relative noise near 1e-6 (FP32 products summed over 16-row tiles), so an FP32 pivot below
+// 1e-4 is not resolved and keeping it multiplies that noise by its inverse; the stage residuals of
+// a fully implicit tableau are that close to parallel.  FP64 Gram matrices resolve pivots far
+// below 1e-13.
+inline double cg_pivot_floor(int dtype) { return dtype == BKTS_F64 ? 1e-13 : 1e-4; }
+
 // Resident workgroups per CU of a kernel with 256-thread workgroups (cached per kernel).
 int blocks_per_cu(const void* kernel);
 
@@ -180,7 +188,15 @@ struct bkts_tc_s {
   std::vector<double> ci;
   // window matrices for each phase, row-major k x k
   std::vector<std::vector<double>> A1, A2;
+  // fully implicit tableau (an implicit stage couples to a later one): windows hold whole steps,
+  // the front is always stage 0, and the splitting uses the averaged coefficient beta_avg
+  int fully_implicit = 0;
+  double beta_avg = 0.0;
 };
+
+// Splitting coefficient beta of J = M/tau + beta K for a window whose front is implicit stage
+// `phase`: the front stage's diagonal entry, or the averaged coefficient of a fully implicit tableau.
+inline double tc_beta(const bkts_tc_s& t, int phase) { return t.fully_implicit ? t.beta_avg : t.A2[phase][0]; }
 
 namespace bkts {
 

@@ -85,7 +85,7 @@ void block_cg(bkts_ctx ctx, const bkts_op_s& op, int dtype, int k, double a, dou
   void* P = ctx->ws.get("cg_P_" + tag, es * N * k);
   void* Q = ctx->ws.get("cg_Q_" + tag, es * N * k);
   Small s = small_bufs(ctx, "cg" + tag, k);
-  const double eps = dtype == BKTS_F64 ? 1e-13 : 1e-6;
+  const double eps = cg_pivot_floor(dtype);
   const double* dK = nullptr;  // inverse Jacobi diagonal of a I + b K, computed once per solve
   if (jacobi) {
     double* d = ctx->ws.get<double>("cg_dinv", N);

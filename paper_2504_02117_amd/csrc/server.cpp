@@ -431,7 +431,7 @@ void bkts_server_s::round() {
     BKTS_REQUIRE(used <= table_bytes, "serving table overflow");
     BKTS_HIP(hipMemcpyAsync(table_dev.p, table_host, used, hipMemcpyHostToDevice, ctx->stream));
     const GJob* dj = table_dev.as<GJob>();
-    const double eps = 1e-6;
+    const double eps = cg_pivot_floor(BKTS_F32);
     long nl = 0;
     // widths 16 and 32 run on the FP32 matrix cores, narrower ones on row tiles
     for (int c = 0; c < 6; ++c)

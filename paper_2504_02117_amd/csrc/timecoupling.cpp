@@ -1,7 +1,9 @@
-// Time coupling of a stiffly accurate DIRK method (Sec. 2, eq. stiffly-accurate-DIRK; Sec. 2.1):
-// tableau, elimination of an explicit first stage, and the k x k window matrices A1, A2 of
+// Time coupling of a stiffly accurate Runge-Kutta method (Sec. 2, eq. stiffly-accurate-DIRK; Sec.
+// 2.1): tableau, elimination of an explicit first stage, and the k x k window matrices A1, A2 of
 // eq. time-stepping-matrices-multiple-parallel-time-steps taken from the diagonal position of the
-// window's front stage (Sec. 2.2, pipelining).
+// window's front stage (Sec. 2.2, pipelining).  Fully implicit tableaux (the remark on fully
+// implicit Runge-Kutta methods after Algorithm 1) give full diagonal blocks in A2; their windows
+// hold whole steps and their splitting uses one averaged coefficient for every stage.
 #include <cmath>
 
 #include "internal.hpp"
@@ -24,6 +26,26 @@ static void coupling_entry(const bkts_tc_s& tc, int qi, int qj, double& a1, doub
     a1 += -1.0 / tc.tau;
     if (tc.explicit_first) a2 += tc.ae[li];
   }
+}
+
+// |det A|^(1/m) of an m x m row-major matrix (Gaussian elimination with partial pivoting): the
+// geometric mean of the moduli of A's eigenvalues.
+static double geometric_mean_modulus(std::vector<double> a, int m) {
+  double logdet = 0.0;
+  for (int c = 0; c < m; ++c) {
+    int p = c;
+    for (int r = c + 1; r < m; ++r)
+      if (std::fabs(a[r * m + c]) > std::fabs(a[p * m + c])) p = r;
+    if (a[p * m + c] == 0.0) return 0.0;
+    if (p != c)
+      for (int j = 0; j < m; ++j) std::swap(a[p * m + j], a[c * m + j]);
+    logdet += std::log(std::fabs(a[c * m + c]));
+    for (int r = c + 1; r < m; ++r) {
+      const double f = a[r * m + c] / a[c * m + c];
+      for (int j = c; j < m; ++j) a[r * m + j] -= f * a[c * m + j];
+    }
+  }
+  return std::exp(logdet / m);
 }
 
 bkts_tc tc_create(bkts_ctx ctx, const bkts_tc_desc* d) {
@@ -51,13 +73,17 @@ bkts_tc tc_create(bkts_ctx ctx, const bkts_tc_desc* d) {
       c = {g, 1.0};
       break;
     }
+    case BKTS_RADAU2:  // 2-stage Radau IIA: order 3, stiffly accurate, L-stable, fully implicit
+      m = 2;
+      A = {5.0 / 12.0, -1.0 / 12.0, 0.75, 0.25};
+      c = {1.0 / 3.0, 1.0};
+      break;
     case BKTS_DIRK_CUSTOM:
       BKTS_REQUIRE(d->stages >= 1 && d->stages <= 8 && d->A && d->c, "custom tableau needs 1..8 stages, A and c");
       m = d->stages;
       A.assign(d->A, d->A + m * m);
       c.assign(d->c, d->c + m);
-      for (int i = 0; i < m; ++i)
-        for (int j = i + 1; j < m; ++j) BKTS_REQUIRE(A[i * m + j] == 0.0, "tableau must be lower triangular");
+      for (double v : A) BKTS_REQUIRE(std::isfinite(v), "tableau entries must be finite");
       break;
     default:
       throw Error{BKTS_EINVAL, fmt("unknown method %d", d->method)};
@@ -81,10 +107,21 @@ bkts_tc tc_create(bkts_ctx ctx, const bkts_tc_desc* d) {
     if (expl) t->ae[i] = A[(i + off) * m];
     t->ci[i] = c[i + off];
   }
-  for (int i = 0; i < mi; ++i) {
-    if (!(t->Ai[i * mi + i] > 0.0)) {
+  for (int i = 0; i < mi; ++i)
+    for (int j = i + 1; j < mi; ++j) t->fully_implicit |= t->Ai[i * mi + j] != 0.0 ? 1 : 0;
+  if (t->fully_implicit) {
+    t->beta_avg = geometric_mean_modulus(t->Ai, mi);
+    if (!(t->beta_avg > 0.0) || d->k % mi != 0) {
       delete t;
-      throw Error{BKTS_EINVAL, "implicit stages need a positive diagonal entry"};
+      throw Error{BKTS_EINVAL, fmt("a fully implicit tableau needs a nonsingular A and k a multiple of its %d "
+                                   "implicit stages (got k=%d)", mi, d->k)};
+    }
+  } else {
+    for (int i = 0; i < mi; ++i) {
+      if (!(t->Ai[i * mi + i] > 0.0)) {
+        delete t;
+        throw Error{BKTS_EINVAL, "implicit stages need a positive diagonal entry"};
+      }
     }
   }
   const int k = d->k;

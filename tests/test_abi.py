@@ -82,9 +82,11 @@ def test_custom_tableau_and_validation():
         with pytest.raises(bkts.BktsError) as e:
             bkts.bkts_tc_create(None, bkts.BKTS_IE, kw["k"], kw["tau"])
         assert e.value.status == bkts.BKTS_EINVAL
-    with pytest.raises(bkts.BktsError):  # upper-triangular entry
-        bkts.bkts_tc_create(None, bkts.BKTS_DIRK_CUSTOM, 2, 0.1, A=np.array([[1.0, 0.5], [0.0, 1.0]]),
-                            c=np.array([1.0, 1.0]))
+    with pytest.raises(bkts.BktsError):  # fully implicit but singular: no averaged coefficient
+        bkts.bkts_tc_create(None, bkts.BKTS_DIRK_CUSTOM, 2, 0.1, A=np.array([[1.0, 0.5], [2.0, 1.0]]),
+                            c=np.array([1.5, 3.0]))
+    with pytest.raises(bkts.BktsError):  # fully implicit: k must hold whole steps
+        bkts.bkts_tc_create(None, bkts.BKTS_RADAU2, 3, 0.1)
     with pytest.raises(bkts.BktsError):
         bkts.bkts_tc_get(tc := bkts.bkts_tc_create(None, bkts.BKTS_IE, 2, 0.1), 1)
     bkts.bkts_tc_destroy(tc)
@@ -114,3 +116,23 @@ def test_server_null_handles_rejected():
     assert lib.bkts_nlop_create(None, None, None, C.byref(out)) == bkts.BKTS_EINVAL
     assert lib.bkts_richards_create(None, None, None, None, C.byref(out)) == bkts.BKTS_EINVAL
     assert lib.bkts_nl_mass(None, None, 1, None, 1, None, 1) == bkts.BKTS_EINVAL
+
+
+@pytest.mark.parametrize("k", [2, 4, 6])
+def test_fully_implicit_time_coupling_matches_oracle(k):
+    """2-stage Radau IIA (named and as a custom full tableau): full diagonal blocks in A2, the
+    averaged splitting coefficient, and whole-step windows."""
+    from paper_2504_02117_amd import bkts
+    tau = 0.2
+    A, _, c = otc.tableau("radau2")
+    oA1, oA2, _ = otc.window_matrices(A, c, k, 0, tau)
+    for tc in (bkts.bkts_tc_create(None, bkts.BKTS_RADAU2, k, tau),
+               bkts.bkts_tc_create(None, bkts.BKTS_DIRK_CUSTOM, k, tau, A=A, c=c)):
+        try:
+            A1, A2, beta, mi = bkts.bkts_tc_get(tc, 0)
+            assert mi == 2
+            np.testing.assert_allclose(A1, oA1, rtol=0, atol=1e-15)
+            np.testing.assert_allclose(A2, oA2, rtol=0, atol=1e-15)
+            assert beta == pytest.approx(otc.averaged_beta(A), rel=1e-14)
+        finally:
+            bkts.bkts_tc_destroy(tc)
