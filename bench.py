@@ -42,6 +42,10 @@ def parse():
     p.add_argument("--inner-rtol", type=float, default=0.1,
                    help="inner (FP32 block-CG) relative tolerance per outer iteration; the outer loop converges "
                         "every accepted step to 1e-8 regardless")
+    p.add_argument("--format", choices=["stencil", "sell"], default="stencil",
+                   help="storage of the 128^3 operator: the index-free stencil form (diagonal + one array per "
+                        "neighbour offset) or SELL-C; the other format's block and plain forms are timed beside it")
+    p.add_argument("--no-format-compare", dest="format_compare", action="store_false")
     p.add_argument("--plain-steps", type=int, default=8)
     p.add_argument("--no-plain", action="store_true")
     p.add_argument("--no-cpu", action="store_true")
@@ -103,10 +107,14 @@ def kernel_table(bkts, ctx):
     return out
 
 
-def kernel_name(cat, k):
+def kernel_name(cat, k, fmt="sell"):
     """The kernel behind a profiling category in the block-CG inner solve at width k."""
     row = k in (1, 2, 4)  # one thread per row; wider blocks use column tiles (MFMA for the updates)
-    return {"spmm": "rk_spmm_gram_kernel" if row else spmm_kernel_name(k, "f32"),
+    if fmt == "stencil":
+        spmm = "rk_st_spmm_gram_kernel" if row else "st_spmm_kernel"
+    else:
+        spmm = "rk_spmm_gram_kernel" if row else spmm_kernel_name(k, "f32")
+    return {"spmm": spmm,
             "cg_update": "rk_cg_update_kernel" if row else "mf_cg_update_kernel",
             "cg_pupdate": "rk_cg_pupdate_kernel" if row else "mf_cg_pupdate_kernel",
             "gram": "rk_gram_kernel" if row else "mf_gram_kernel",
@@ -114,12 +122,12 @@ def kernel_name(cat, k):
             "small": "finalize / k x k kernels", "other": "vector kernels"}.get(cat, cat)
 
 
-def roofline_of(kt, cat, k, precision):
+def roofline_of(kt, cat, k, precision, fmt="sell"):
     """HBM roofline of one profiling category: algorithmic bytes per launch / average launch time."""
     v = kt[cat]
     bpl = v["bytes_per_launch"]
     achieved = bpl / (v["avg_us"] * 1e-6) / 1e9
-    name = kernel_name(cat, k)
+    name = kernel_name(cat, k, fmt)
     return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_for(name, precision, k), "kernel": name,
             "category": cat, "algorithmic_bytes_per_launch": bpl, "avg_launch_us": v["avg_us"],
@@ -146,8 +154,10 @@ def traffic_for(kernel, precision, k):
         return None
 
 
-def spmm_kernel_name(k, precision):
-    """Kernel that bkts_spmm launches on a uniform-width SELL operator at width k."""
+def spmm_kernel_name(k, precision, fmt="sell"):
+    """Kernel that bkts_spmm launches on a uniform-width SELL operator (or the stencil form) at width k."""
+    if fmt == "stencil":
+        return "st_spmm_kernel"
     kp = 1
     while kp < k:
         kp *= 2
@@ -162,7 +172,14 @@ def run_spmm_sweep(torch, bkts, ctx, a, kd, n):
     working set of consecutive launches exceeds the 256 MiB Infinity Cache (each launch reads cold
     data). Time per launch comes from the library's in-dispatch event timers."""
     N = n[0] * n[1] * n[2]
-    ops = [bkts.bkts_fv_assemble(ctx, n, kappa=kd, fmt=bkts.BKTS_FMT_SELL) for _ in range(3)]
+    out = {}
+    for fmt, code in (("sell", bkts.BKTS_FMT_SELL), ("stencil", bkts.BKTS_FMT_STENCIL)):
+        out.update(spmm_sweep_format(torch, bkts, ctx, a, kd, n, N, fmt, code))
+    return out
+
+
+def spmm_sweep_format(torch, bkts, ctx, a, kd, n, N, fmt, code):
+    ops = [bkts.bkts_fv_assemble(ctx, n, kappa=kd, fmt=code) for _ in range(3)]
     _, nnz = bkts.bkts_op_info(ops[0])
     out = {}
     for prec, dt, sv in (("f64", torch.float64, 8), ("f32", torch.float32, 4)):
@@ -183,10 +200,11 @@ def run_spmm_sweep(torch, bkts, ctx, a, kd, n):
             us = 1e3 * ms / cnt
             bpl = by / cnt
             gbs = bpl / (us * 1e-6) / 1e9
-            out[f"{prec} k={k}"] = {"avg_us": us, "GBps": gbs, "frac": gbs / HBM_PEAK_GBS,
-                                    "algorithmic_bytes_per_launch": bpl, "flop_per_byte": 2.0 * nnz * k / bpl,
-                                    "kernel": spmm_kernel_name(k, prec), "launches": cnt}
-            log(f"  spmm {prec} k={k:2d}: {us:7.1f} us  {gbs:6.0f} GB/s  frac {gbs / HBM_PEAK_GBS:.3f}  "
+            key = f"{prec} k={k}" if fmt == "sell" else f"{fmt} {prec} k={k}"
+            out[key] = {"avg_us": us, "GBps": gbs, "frac": gbs / HBM_PEAK_GBS,
+                        "algorithmic_bytes_per_launch": bpl, "flop_per_byte": 2.0 * nnz * k / bpl,
+                        "kernel": spmm_kernel_name(k, prec, fmt), "format": fmt, "launches": cnt}
+            log(f"  spmm {fmt:7s} {prec} k={k:2d}: {us:7.1f} us  {gbs:6.0f} GB/s  frac {gbs / HBM_PEAK_GBS:.3f}  "
                 f"AI {2.0 * nnz * k / bpl:.3f} flop/B")
             del Xs, Ys
     for o in ops:
@@ -679,7 +697,8 @@ def main():
     y0 = torch.from_numpy(u0).cuda()
     torch.cuda.synchronize()
     t = time.perf_counter()
-    op = bkts.bkts_fv_assemble(ctx, n, kappa=kd, fmt=bkts.BKTS_FMT_SELL)
+    fcode = {"stencil": bkts.BKTS_FMT_STENCIL, "sell": bkts.BKTS_FMT_SELL}
+    op = bkts.bkts_fv_assemble(ctx, n, kappa=kd, fmt=fcode[a.format])
     setup_s = time.perf_counter() - t
     _, nnz = bkts.bkts_op_info(op)
 
@@ -711,14 +730,14 @@ def main():
         r = run_form(torch, bkts, ctx, op, y0, ks, prec, tol, a.warmup, a.steps, True)
         sp = r["kernels"].get("spmm", {})
         sv = 4 if prec == "f32" else 8
-        bpl = nnz * (sv + 4) + 4 * (N + 1) + 2 * N * ks * sv
+        bpl = (4 * N * sv if a.format == "stencil" else nnz * (sv + 4) + 4 * (N + 1)) + 2 * N * ks * sv
         dom = max(r["kernels"].items(), key=lambda kv: kv[1]["total_ms"])[0] if r["kernels"] else None
         sweep[f"k={ks} {prec} inner={tol:g}"] = {
             "value": r["value"], "outer": r["info"].outer_iterations, "krylov": r["info"].krylov_iterations,
             "spmm_avg_us": sp.get("avg_us"),
             "spmm_GBps": (bpl / (sp["avg_us"] * 1e-6) / 1e9) if sp else None,
             "spmm_frac": (bpl / (sp["avg_us"] * 1e-6) / 1e9 / HBM_PEAK_GBS) if sp else None,
-            "spmm_kernel": kernel_name("spmm", ks), "spmm_flop_per_byte": 2.0 * nnz * ks / bpl,
+            "spmm_kernel": kernel_name("spmm", ks, a.format), "spmm_flop_per_byte": 2.0 * nnz * ks / bpl,
             "dominant_kernel": dom,
             "kernels": {kk: {"avg_us": vv["avg_us"], "GBps": vv["GBps"]} for kk, vv in r["kernels"].items()}}
         log(f"  sweep k={ks} {prec} inner={tol:g}: {r['value']:.4g} DOF*steps/s (spmm {sp.get('avg_us', 0):.1f} us)")
@@ -727,9 +746,27 @@ def main():
     if blk["kernels"]:
         dom = max((c for c in blk["kernels"] if c not in ("small", "other")),
                   key=lambda c: blk["kernels"][c]["total_ms"])
-        roof = roofline_of(blk["kernels"], dom, a.k, a.precision)
+        roof = roofline_of(blk["kernels"], dom, a.k, a.precision, a.format)
         if "spmm" in blk["kernels"]:
-            spmm_roof = roofline_of(blk["kernels"], "spmm", a.k, a.precision)
+            spmm_roof = roofline_of(blk["kernels"], "spmm", a.k, a.precision, a.format)
+
+    formats = None
+    if a.format_compare:
+        other = "sell" if a.format == "stencil" else "stencil"
+        log(f"{other} operator: block form k={a.k} {a.precision} and plain k=1 f64 beside the {a.format} ones")
+        op2 = bkts.bkts_fv_assemble(ctx, n, kappa=kd, fmt=fcode[other])
+        try:
+            b2 = run_form(torch, bkts, ctx, op2, y0, a.k, a.precision, a.inner_rtol, a.warmup, a.steps, True)
+            p2 = None if a.no_plain else run_form(torch, bkts, ctx, op2, y0, 1, "f64", 1e-8, 1, a.plain_steps, False)
+        finally:
+            bkts.bkts_op_destroy(op2)
+        sp2 = b2["kernels"].get("spmm", {})
+        formats = {a.format: {"block": blk["value"], "plain": plain["value"] if plain else None,
+                              "spmm_avg_us": blk["kernels"].get("spmm", {}).get("avg_us")},
+                   other: {"block": b2["value"], "plain": p2["value"] if p2 else None,
+                           "spmm_avg_us": sp2.get("avg_us"), "krylov_iterations": b2["info"].krylov_iterations}}
+        log(f"  {other}: block {b2['value']:.4g}" + (f", plain {p2['value']:.4g}" if p2 else "") +
+            f" DOF*steps/s (spmm {sp2.get('avg_us', 0):.1f} us)")
 
     spmm_sweep = None
     if a.spmm_ks.strip():
@@ -802,14 +839,16 @@ def main():
         "vs_baseline": None, "dtype": "f32 inner / f64 outer" if a.precision == "f32" else "f64",
         "data": "synthetic (seeded lognormal field, sin-product initial state)",
         "config": {"workload": f"heterogeneous diffusion {a.n}^3 FV 7-point, lognormal kappa (log-std 2, corr. 8 "
-                               f"cells), implicit Euler tau=1e-3, block width k={a.k}, "
+                               f"cells), implicit Euler tau=1e-3, block width k={a.k}, {a.format} operator, "
                                f"{'FP32-inner + FP64 refinement' if a.precision == 'f32' else 'FP64'} to 1e-8",
-                   "N": N, "nnz": nnz, "k": a.k, "inner_rtol": a.inner_rtol, "setup_s": setup_s},
+                   "N": N, "nnz": nnz, "k": a.k, "inner_rtol": a.inner_rtol, "format": a.format,
+                   "setup_s": setup_s},
         "outer_iterations": blk["info"].outer_iterations, "krylov_iterations": blk["info"].krylov_iterations,
         "oracle_rel_residual_last_step": err,
         "plain": plain,
         "speedup_vs_plain": (blk["value"] / plain["value"]) if plain else None,
         "sweep": sweep or None,
+        "formats": formats,
         "roofline": roof,
         "spmm_roofline": spmm_roof,
         "spmm_sweep": spmm_sweep,

@@ -61,7 +61,7 @@ typedef struct bkts_server_s* bkts_server;
 /* element types of block vectors */
 enum { BKTS_F64 = 0, BKTS_F32 = 1 };
 /* sparse storage formats of an operator */
-enum { BKTS_FMT_CSR = 0, BKTS_FMT_SELL = 1 };
+enum { BKTS_FMT_CSR = 0, BKTS_FMT_SELL = 1, BKTS_FMT_STENCIL = 2 };
 
 /* ------------------------------------------------------------------ context */
 
@@ -125,7 +125,15 @@ typedef struct bkts_fv_coeffs {
  * mean 2 kP kQ / (kP + kQ) / h^2, Dirichlet faces 2 kP / h^2 with b += 2 kP g / h^2,
  * convection is first-order upwind (boundary inflow moves w g / h into b).
  * Runs on the device from the device array `kappa`.  `format` selects the
- * storage used by the block operator (CSR is always kept for export). */
+ * storage used by the block operator (CSR is always kept for export):
+ * BKTS_FMT_CSR, BKTS_FMT_SELL (SELL-C, C = 64), or BKTS_FMT_STENCIL, the
+ * block operator of Sec. 3 without its column-index stream: with rows numbered
+ * as above, every off-diagonal entry sits at an offset s in {1, n0, n0*n1}, and
+ * a symmetric K is stored as its diagonal plus one array per offset,
+ * o_s[r] = K[r][r+s] = K[r+s][r] ((1 + dim) N values against nnz values and
+ * nnz indices).  SELL is kept beside it for the fused residual.  The stencil
+ * format needs a symmetric operator: BKTS_EINVAL when a velocity is nonzero
+ * (upwind convection).  bkts_op_create_csr rejects it (no grid). */
 bkts_status bkts_fv_assemble(bkts_ctx ctx, const bkts_grid* grid, const bkts_fv_coeffs* coeffs,
                              int format, bkts_op* out);
 

@@ -23,7 +23,7 @@ _lib = C.CDLL(LIB_PATH, mode=C.RTLD_GLOBAL)
 BKTS_MAX_K = 32
 BKTS_OK, BKTS_EINVAL, BKTS_ENOMEM, BKTS_EDEVICE, BKTS_EBREAKDOWN, BKTS_ENOCONV, BKTS_EBUSY = 0, -1, -2, -3, -4, -5, -6
 BKTS_F64, BKTS_F32 = 0, 1
-BKTS_FMT_CSR, BKTS_FMT_SELL = 0, 1
+BKTS_FMT_CSR, BKTS_FMT_SELL, BKTS_FMT_STENCIL = 0, 1, 2
 BKTS_BC_DIRICHLET, BKTS_BC_NEUMANN = 0, 1
 BKTS_IE, BKTS_THETA, BKTS_SDIRK2, BKTS_DIRK_CUSTOM, BKTS_RADAU2 = 0, 1, 2, 3, 4
 BKTS_RI_NO_FLOW, BKTS_RI_DIRICHLET, BKTS_RI_FREE_DRAINAGE = 0, 1, 2

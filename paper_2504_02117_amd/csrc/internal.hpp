@@ -144,6 +144,12 @@ struct bkts_op_s {
   // that XCD's L2.  0 = unknown.
   int64_t strip_period = 0;
   bkts::DevBuf sell_ptr, sell_w, sell_col, sell_val, sell_val32;
+  // Index-free stencil form (BKTS_FMT_STENCIL; stencil.hip): st_na > 0 distinct neighbour offsets
+  // st_off[a] in rows; st_coef holds (1 + st_na) arrays of N: the diagonal, then o_a[r] = K[r, r + s_a].
+  // When present, the block operator uses it instead of CSR/SELL.
+  int st_na = 0;
+  int64_t st_off[3] = {0, 0, 0};
+  bkts::DevBuf st_coef, st_coef32;
 };
 
 // Nonlinear FV operator (nonlinear.hip).
@@ -231,6 +237,11 @@ void op_build_sell(bkts_op op);
 void jacobi_inverse(bkts_ctx ctx, const bkts_op_s& op, double a, double b, double* dinv);
 void op_finish(bkts_op op);  // diag, fp32 copies, SELL if requested
 void op_refresh_values(bkts_op op);  // after CSR values changed: diag, SELL values, FP32 copies
+// Index-free stencil form from the CSR (stencil.hip); BKTS_EINVAL unless K is a symmetric operator
+// whose entries all lie at the grid-neighbour offsets.
+void op_build_stencil(bkts_op op);
+void spmm_stencil(bkts_ctx ctx, const bkts_op_s& op, int dtype, int k, double cb, const void* B, int ldb,
+                  double alpha, const void* X, int ldx, double beta, void* Y, int ldy);
 
 // ---- nonlinear operator (nonlinear.hip)
 bkts_nlop nlop_create(bkts_ctx ctx, const bkts_grid* grid, const bkts_nl_coeffs* c);

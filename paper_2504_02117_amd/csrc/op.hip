@@ -331,7 +331,8 @@ void op_finish(bkts_op op) {
 bkts_op fv_assemble(bkts_ctx ctx, const bkts_grid* grid, const bkts_fv_coeffs* c, int format) {
   BKTS_REQUIRE(grid && c, "grid and coeffs must not be NULL");
   BKTS_REQUIRE(grid->dim >= 1 && grid->dim <= 3, "grid dim must be 1, 2 or 3 (got %d)", grid->dim);
-  BKTS_REQUIRE(format == BKTS_FMT_CSR || format == BKTS_FMT_SELL, "unknown format %d", format);
+  BKTS_REQUIRE(format == BKTS_FMT_CSR || format == BKTS_FMT_SELL || format == BKTS_FMT_STENCIL,
+               "unknown format %d", format);
   GridDev g{};
   g.dim = grid->dim;
   int64_t N = 1;
@@ -361,7 +362,7 @@ bkts_op fv_assemble(bkts_ctx ctx, const bkts_grid* grid, const bkts_fv_coeffs* c
   try {
     op->ctx = ctx;
     op->N = N;
-    op->format = format;
+    op->format = format == BKTS_FMT_STENCIL ? BKTS_FMT_SELL : format;  // SELL serves the other kernels
     op->grid = *grid;
     DevBuf len, rp64;
     len.alloc(sizeof(int64_t) * N);
@@ -382,6 +383,7 @@ bkts_op fv_assemble(bkts_ctx ctx, const bkts_grid* grid, const bkts_fv_coeffs* c
     op->b_nonzero = nz;
     op->strip_period = grid->dim == 3 ? (int64_t)g.n[0] * g.n[1] : grid->dim == 2 ? g.n[0] : 0;
     op_finish(op);
+    if (format == BKTS_FMT_STENCIL) op_build_stencil(op);
   } catch (...) {
     delete op;
     throw;
@@ -398,6 +400,7 @@ bkts_op op_from_csr(bkts_ctx ctx, int64_t N, int64_t nnz, const int32_t* rowptr,
                     const double* val, int format) {
   BKTS_REQUIRE(N >= 1 && nnz >= 0, "N must be >= 1 and nnz >= 0");
   BKTS_REQUIRE(rowptr && (nnz == 0 || (col && val)), "CSR pointers must not be NULL");
+  BKTS_REQUIRE(format != BKTS_FMT_STENCIL, "the stencil format needs the grid of bkts_fv_assemble");
   BKTS_REQUIRE(format == BKTS_FMT_CSR || format == BKTS_FMT_SELL, "unknown format %d", format);
   BKTS_REQUIRE(nnz < ((int64_t)1 << 31) && N < ((int64_t)1 << 31), "CSR too large for int32 indices");
   // validate the row pointer on the host (one copy of N+1 ints): monotone, starts at 0, ends at nnz

@@ -166,6 +166,78 @@ __global__ __launch_bounds__(256) void rk_spmm_gram_kernel(RkSpmmArgs<T> a) {
   fold_block<KP * KP>(g, red, a.partials);
 }
 
+// Stencil form (symmetric 5/7-point operator on a structured grid): no column-index stream;
+// coef holds d and the na off-diagonal arrays o_a (entry K[r, r + s_a]), each of length N.
+template <typename T>
+struct RkStArgs {
+  int64_t N;
+  int na;
+  int64_t s[3];
+  const T* coef;
+  double alpha, beta;
+  const T* P;
+  T* Q;
+  double* partials;
+};
+
+template <typename T, int KP>
+__global__ __launch_bounds__(256) void rk_st_spmm_gram_kernel(RkStArgs<T> a) {
+  __shared__ double red[4 * KP * KP];
+  double g[KP * KP];
+#pragma unroll
+  for (int e = 0; e < KP * KP; ++e) g[e] = 0.0;
+  const int64_t N = a.N;
+  const RowRange rr = block_rows(N);
+  for (int64_t r = rr.begin + threadIdx.x; r < rr.end; r += dev::kThreads) {
+    const T dg = __builtin_nontemporal_load(a.coef + r);
+    T up[3], lo[3];
+    Row<T, KP> xu[3], xl[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      up[q] = lo[q] = T(0);
+      if (q < a.na) {
+        const int64_t s = a.s[q];
+        const T* oq = a.coef + (1 + q) * N;
+        if (r + s < N) {
+          up[q] = oq[r];
+          xu[q] = ld_row<T, KP>(a.P + (r + s) * KP, KP);
+        }
+        if (r - s >= 0) {
+          lo[q] = oq[r - s];
+          xl[q] = ld_row<T, KP>(a.P + (r - s) * KP, KP);
+        }
+      }
+    }
+    const Row<T, KP> p = ld_row<T, KP>(a.P + r * KP, KP);
+    T acc[KP];
+#pragma unroll
+    for (int j = 0; j < KP; ++j) acc[j] = dg * p.v[j];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      if (q < a.na) {
+        const int64_t s = a.s[q];
+        if (r - s >= 0) {
+#pragma unroll
+          for (int j = 0; j < KP; ++j) acc[j] = fma(lo[q], xl[q].v[j], acc[j]);
+        }
+        if (r + s < N) {
+#pragma unroll
+          for (int j = 0; j < KP; ++j) acc[j] = fma(up[q], xu[q].v[j], acc[j]);
+        }
+      }
+    }
+    Row<T, KP> qv;
+#pragma unroll
+    for (int j = 0; j < KP; ++j) qv.v[j] = (T)a.beta * acc[j] + (T)a.alpha * p.v[j];
+    st_row<T, KP>(a.Q + r * KP, qv);
+#pragma unroll
+    for (int i = 0; i < KP; ++i)
+#pragma unroll
+      for (int j = 0; j < KP; ++j) g[i * KP + j] = fma((double)p.v[i], (double)qv.v[j], g[i * KP + j]);
+  }
+  fold_block<KP * KP>(g, red, a.partials);
+}
+
 struct RkUpdArgs {
   int64_t N;
   void* X;
@@ -322,8 +394,35 @@ bool rk_eligible(int k) { return k == 1 || k == 2 || k == 4; }
   } while (0)
 
 template <typename T, int KP>
+static void rk_st_spmm_gram_t(bkts_ctx ctx, const bkts_op_s& op, double alpha, const void* P, double beta, void* Q,
+                              double* G, const CgTail* tail) {
+  RkStArgs<T> a{};
+  a.N = op.N;
+  a.na = op.st_na;
+  for (int q = 0; q < 3; ++q) a.s[q] = op.st_off[q];
+  if constexpr (sizeof(T) == 8)
+    a.coef = op.st_coef.as<double>();
+  else
+    a.coef = op.st_coef32.as<float>();
+  a.alpha = alpha;
+  a.beta = beta;
+  a.P = static_cast<const T*>(P);
+  a.Q = static_cast<T*>(Q);
+  const double sv = sizeof(T);
+  ProfScope prof(ctx, BKTS_K_SPMM, (1.0 + op.st_na) * op.N * sv + 2.0 * op.N * KP * sv);
+  const int64_t nb = rk_grid(ctx, rk_st_spmm_gram_kernel<T, KP>, op.N);
+  a.partials = ctx->ws.get<double>("rk_sg_part", (size_t)KP * KP * nb);
+  launch(ctx, (rk_st_spmm_gram_kernel<T, KP>), dim3(nb), dim3(256), 0, a);
+  BKTS_HIP(hipGetLastError());
+  prof.end();
+  if (!tail) return finalize_gram(ctx, a.partials, (int)nb, KP, KP, G);
+  fold_solve(ctx, 0, KP, KP, a.partials, nb, *tail);
+}
+
+template <typename T, int KP>
 static void rk_spmm_gram_t(bkts_ctx ctx, const bkts_op_s& op, double alpha, const void* P, double beta, void* Q,
                            double* G, const CgTail* tail) {
+  if (op.st_na > 0) return rk_st_spmm_gram_t<T, KP>(ctx, op, alpha, P, beta, Q, G, tail);
   const bool sell = op.format == BKTS_FMT_SELL;
   RkSpmmArgs<T> a{};
   a.N = op.N;

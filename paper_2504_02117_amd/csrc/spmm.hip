@@ -417,6 +417,7 @@ void spmm_t(bkts_ctx ctx, const bkts_op_s& op, int k, double cb, const void* B, 
 void spmm(bkts_ctx ctx, const bkts_op_s& op, int dtype, int k, double cb, const void* B, int ldb, double alpha,
           const void* X, int ldx, double beta, void* Y, int ldy) {
   if (op.N == 0) return;
+  if (op.st_na > 0) return spmm_stencil(ctx, op, dtype, k, cb, B, ldb, alpha, X, ldx, beta, Y, ldy);
   if (dtype == BKTS_F64)
     spmm_t<double>(ctx, op, k, cb, B, ldb, alpha, X, ldx, beta, Y, ldy);
   else

@@ -1,0 +1,321 @@
+// Index-free stencil form of the block operator (the BOP of Sec. 3 without its column-index
+// stream) for symmetric 5/7-point operators on a structured grid, as produced by the cell-centred
+// FV assembly without convection (Sec. 4.1).
+//
+// Rows are numbered ix + nx*iy + nx*ny*iz, so every off-diagonal entry sits at a fixed offset s_a
+// in {1, nx, nx*ny}.  For a symmetric K the entry K[r, r + s_a] equals K[r + s_a, r], and one array
+// per offset holds it once:  o_a[r] = K[r, r + s_a] (zero where r + s_a is not a neighbour: the
+// + faces on the domain boundary).  With d[r] = K[r, r]
+//
+//   (K x)[r] = d[r] x[r] + sum_a ( o_a[r] x[r + s_a] + o_a[r - s_a] x[r - s_a] ).
+//
+// A neighbour index that wraps to the next grid line or plane meets a zero coefficient (o_a of a
+// cell on the + boundary); only indices outside [0, N) are skipped.  The matrix stream drops from
+// nnz * (value + index) bytes to (1 + dim) * N values: 4N against 14N words for the 7-point
+// operator.  The arrays are extracted from the assembled CSR, which stays the operator's
+// definition, and every entry is checked: an operator with an entry off the three offsets or a
+// non-symmetric pair (convection) is rejected.
+#include "devcommon.hpp"
+#include "internal.hpp"
+
+namespace bkts {
+namespace {
+
+struct StOff {
+  int na;
+  int64_t s[3];
+};
+
+// First offset index a with s_a == d (duplicated offsets, as for nx == 1, count once), or -1.
+__device__ __forceinline__ int offset_index(const StOff& o, int64_t d) {
+  for (int a = 0; a < o.na; ++a)
+    if (o.s[a] == d) return a;
+  return -1;
+}
+
+// d[r] and o_a[r] from the forward entries of row r; flags an entry at any other offset.
+__global__ void st_fill(int64_t N, const int32_t* rowptr, const int32_t* col, const double* val, StOff o,
+                        double* coef, int* bad) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= N) return;
+  for (int32_t e = rowptr[r]; e < rowptr[r + 1]; ++e) {
+    const int64_t c = col[e];
+    const double v = val[e];
+    if (c == r) {
+      coef[r] += v;
+      continue;
+    }
+    const int a = offset_index(o, c - r);
+    if (a >= 0) {
+      coef[(1 + a) * N + r] += v;
+    } else if (offset_index(o, r - c) < 0 && v != 0.0) {
+      atomicOr(bad, 1);
+    }
+  }
+}
+
+// Every backward entry K[r, r - s_a] must equal the forward one stored by row r - s_a (and be
+// absent exactly when that one is zero).
+__global__ void st_check(int64_t N, const int32_t* rowptr, const int32_t* col, const double* val, StOff o,
+                         const double* coef, int* bad) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= N) return;
+  for (int a = 0; a < o.na; ++a) {
+    const int64_t c = r - o.s[a];
+    double found = 0.0;
+    for (int32_t e = rowptr[r]; e < rowptr[r + 1]; ++e)
+      if (col[e] == c) found += val[e];
+    const double want = c >= 0 ? coef[(1 + a) * N + c] : 0.0;
+    if (found != want) atomicOr(bad, 2);
+  }
+}
+
+__global__ void st_to_f32(int64_t n, const double* in, float* out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = (float)in[i];
+}
+
+template <typename T, int V>
+struct SVec {
+  T v[V];
+};
+
+template <typename T, int V>
+__device__ __forceinline__ SVec<T, V> sload(const T* p) {
+  SVec<T, V> r;
+  if constexpr (sizeof(T) * V == 16 && sizeof(T) == 8) {
+    const double2 q = *reinterpret_cast<const double2*>(p);
+    r.v[0] = q.x;
+    r.v[1] = q.y;
+  } else if constexpr (sizeof(T) * V == 16) {
+    const float4 q = *reinterpret_cast<const float4*>(p);
+    r.v[0] = q.x;
+    r.v[1] = q.y;
+    r.v[2] = q.z;
+    r.v[3] = q.w;
+  } else {
+#pragma unroll
+    for (int i = 0; i < V; ++i) r.v[i] = p[i];
+  }
+  return r;
+}
+
+template <typename T, int V>
+__device__ __forceinline__ void sstore(T* p, const SVec<T, V>& r, bool nt) {
+  if constexpr (sizeof(T) * V == 16) {
+    typedef T vt __attribute__((ext_vector_type(V)));
+    vt q;
+#pragma unroll
+    for (int i = 0; i < V; ++i) q[i] = r.v[i];
+    if (nt)
+      __builtin_nontemporal_store(q, reinterpret_cast<vt*>(p));
+    else
+      *reinterpret_cast<vt*>(p) = q;
+  } else {
+#pragma unroll
+    for (int i = 0; i < V; ++i) p[i] = r.v[i];
+  }
+}
+
+template <typename T>
+struct StArgs {
+  int64_t N;
+  int k;
+  StOff o;
+  const T* coef;  // (1 + na) arrays of N: d, o_0, ..., o_{na-1}
+  int64_t strip;  // > 0: XCD-strip schedule with this many blocks per strip
+  T cb, alpha, beta;
+  const T* B;
+  int ldb;
+  const T* X;
+  int ldx;
+  T* Y;
+  int ldy;
+};
+
+// Y = cb B + alpha X + beta K X.  Each row is handled by LPR = KP/VEC lanes, each owning VEC
+// consecutive columns (16-byte accesses when the block allows).  The diagonal stream is read
+// non-temporally (single use); the o_a arrays are read twice (at r and at r - s_a, one line, one
+// grid line or one plane later), so they stay cached for the second read.
+template <typename T, int KP, int VEC>
+__global__ __launch_bounds__(256) void st_spmm_kernel(StArgs<T> a) {
+  constexpr int LPR = KP / VEC;
+  constexpr int RPB = dev::kThreads / LPR;
+  const int t = threadIdx.x;
+  const int c0 = (t % LPR) * VEC;
+  int64_t tile;
+  if (a.strip > 0) {
+    const int64_t b = blockIdx.x, x = b % dev::kXcd, i = b / dev::kXcd;
+    tile = ((i / a.strip) * dev::kXcd + x) * a.strip + i % a.strip;
+  } else {
+    tile = dev::xcd_slot(blockIdx.x, gridDim.x);
+  }
+  const int64_t r = tile * RPB + t / LPR;
+  if (r >= a.N || c0 >= a.k) return;
+  const int64_t N = a.N;
+  const T dg = __builtin_nontemporal_load(a.coef + r);
+  T up[3], lo[3];
+  SVec<T, VEC> xu[3], xl[3];
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    up[q] = lo[q] = T(0);
+    if (q < a.o.na) {
+      const int64_t s = a.o.s[q];
+      const T* oq = a.coef + (1 + q) * N;
+      if (r + s < N) {
+        up[q] = oq[r];
+        xu[q] = sload<T, VEC>(a.X + (r + s) * a.ldx + c0);
+      }
+      if (r - s >= 0) {
+        lo[q] = oq[r - s];
+        xl[q] = sload<T, VEC>(a.X + (r - s) * a.ldx + c0);
+      }
+    }
+  }
+  const SVec<T, VEC> xr = sload<T, VEC>(a.X + r * a.ldx + c0);
+  SVec<T, VEC> acc;
+#pragma unroll
+  for (int i = 0; i < VEC; ++i) acc.v[i] = dg * xr.v[i];
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    if (q < a.o.na) {
+      const int64_t s = a.o.s[q];
+      if (r - s >= 0) {
+#pragma unroll
+        for (int i = 0; i < VEC; ++i) acc.v[i] = fma(lo[q], xl[q].v[i], acc.v[i]);
+      }
+      if (r + s < N) {
+#pragma unroll
+        for (int i = 0; i < VEC; ++i) acc.v[i] = fma(up[q], xu[q].v[i], acc.v[i]);
+      }
+    }
+  }
+  SVec<T, VEC> out;
+#pragma unroll
+  for (int i = 0; i < VEC; ++i) out.v[i] = a.beta * acc.v[i] + a.alpha * xr.v[i];
+  if (a.B) {
+    const SVec<T, VEC> br = sload<T, VEC>(a.B + r * a.ldb + c0);
+#pragma unroll
+    for (int i = 0; i < VEC; ++i) out.v[i] = fma(a.cb, br.v[i], out.v[i]);
+  }
+  sstore<T, VEC>(a.Y + r * a.ldy + c0, out, KP >= 8);
+}
+
+template <typename T, int KP, int VEC>
+void st_launch(bkts_ctx ctx, const bkts_op_s& op, const StArgs<T>& a0) {
+  constexpr int LPR = KP / VEC;
+  constexpr int RPB = dev::kThreads / LPR;
+  StArgs<T> a = a0;
+  const int64_t ntiles = (a.N + RPB - 1) / RPB;
+  int64_t nb = ntiles;
+  a.strip = 0;
+  if (op.strip_period >= (int64_t)dev::kXcd * RPB) {
+    a.strip = op.strip_period / dev::kXcd / RPB;
+    const int64_t per = dev::kXcd * a.strip;
+    nb = (ntiles + per - 1) / per * per;  // whole rounds of 8 strips; blocks past the end exit
+  }
+  launch(ctx, (st_spmm_kernel<T, KP, VEC>), dim3(nb), dim3(dev::kThreads), 0, a);
+}
+
+template <typename T, int KP>
+void st_launch_kp(bkts_ctx ctx, const bkts_op_s& op, const StArgs<T>& a, bool vec_ok) {
+  constexpr int VMAX = 16 / sizeof(T);
+  if constexpr (KP >= VMAX) {
+    if (vec_ok) return st_launch<T, KP, VMAX>(ctx, op, a);
+  }
+  st_launch<T, KP, 1>(ctx, op, a);
+}
+
+template <typename T>
+void st_spmm_t(bkts_ctx ctx, const bkts_op_s& op, int k, double cb, const void* B, int ldb, double alpha,
+               const void* X, int ldx, double beta, void* Y, int ldy) {
+  StArgs<T> a{};
+  a.N = op.N;
+  a.k = k;
+  a.o.na = op.st_na;
+  for (int q = 0; q < 3; ++q) a.o.s[q] = op.st_off[q];
+  if constexpr (sizeof(T) == 8)
+    a.coef = op.st_coef.as<double>();
+  else
+    a.coef = op.st_coef32.as<float>();
+  a.cb = (T)cb;
+  a.alpha = (T)alpha;
+  a.beta = (T)beta;
+  a.B = static_cast<const T*>(B);
+  a.ldb = ldb;
+  a.X = static_cast<const T*>(X);
+  a.ldx = ldx;
+  a.Y = static_cast<T*>(Y);
+  a.ldy = ldy;
+  int kp = 1;
+  while (kp < k) kp <<= 1;
+  constexpr int VMAX = 16 / sizeof(T);
+  const double sv = sizeof(T);
+  ProfScope prof(ctx, BKTS_K_SPMM, (1.0 + op.st_na) * op.N * sv + (2.0 + (B ? 1.0 : 0.0)) * op.N * k * sv);
+  auto aligned = [](const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; };
+  const bool vec_ok = k == kp && ldx % VMAX == 0 && ldy % VMAX == 0 && aligned(X) && aligned(Y) &&
+                      (!B || (ldb % VMAX == 0 && aligned(B)));
+  switch (kp) {
+    case 1: st_launch_kp<T, 1>(ctx, op, a, vec_ok); break;
+    case 2: st_launch_kp<T, 2>(ctx, op, a, vec_ok); break;
+    case 4: st_launch_kp<T, 4>(ctx, op, a, vec_ok); break;
+    case 8: st_launch_kp<T, 8>(ctx, op, a, vec_ok); break;
+    case 16: st_launch_kp<T, 16>(ctx, op, a, vec_ok); break;
+    case 32: st_launch_kp<T, 32>(ctx, op, a, vec_ok); break;
+    default: throw Error{BKTS_EINVAL, fmt("k=%d exceeds BKTS_MAX_K", k)};
+  }
+  BKTS_HIP(hipGetLastError());
+}
+
+}  // namespace
+
+void op_build_stencil(bkts_op op) {
+  bkts_ctx ctx = op->ctx;
+  const bkts_grid& g = op->grid;
+  BKTS_REQUIRE(g.dim >= 1 && g.dim <= 3, "the stencil form needs a structured grid");
+  const int64_t N = op->N;
+  StOff o{};
+  int64_t stride = 1;
+  for (int d = 0; d < g.dim; ++d) {
+    bool dup = false;
+    for (int q = 0; q < o.na; ++q) dup |= o.s[q] == stride;
+    if (!dup && stride < N) o.s[o.na++] = stride;
+    stride *= g.n[d];
+  }
+  op->st_na = 0;
+  op->st_coef.alloc(sizeof(double) * (1 + o.na) * N);
+  op->st_coef32.alloc(sizeof(float) * (1 + o.na) * N);
+  int* bad = ctx->ws.get<int>("st_bad", 1);
+  BKTS_HIP(hipMemsetAsync(op->st_coef.p, 0, sizeof(double) * (1 + o.na) * N, ctx->stream));
+  BKTS_HIP(hipMemsetAsync(bad, 0, sizeof(int), ctx->stream));
+  const dim3 grid((unsigned)((N + 255) / 256));
+  launch(ctx, st_fill, grid, dim3(256), 0, N, op->rowptr.as<int32_t>(), op->col.as<int32_t>(),
+         op->val.as<double>(), o, op->st_coef.as<double>(), bad);
+  launch(ctx, st_check, grid, dim3(256), 0, N, op->rowptr.as<int32_t>(), op->col.as<int32_t>(),
+         op->val.as<double>(), o, op->st_coef.as<double>(), bad);
+  const int64_t n = (1 + o.na) * N;
+  launch(ctx, st_to_f32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, n, op->st_coef.as<double>(),
+         op->st_coef32.as<float>());
+  BKTS_HIP(hipGetLastError());
+  int hbad = 0;
+  BKTS_HIP(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+  ctx->sync();
+  if (hbad) {
+    op->st_coef.release();
+    op->st_coef32.release();
+    throw Error{BKTS_EINVAL, hbad & 1 ? "stencil format: an entry lies off the grid-neighbour offsets"
+                                      : "stencil format needs a symmetric operator (no convection)"};
+  }
+  op->st_na = o.na;
+  for (int q = 0; q < 3; ++q) op->st_off[q] = q < o.na ? o.s[q] : 0;
+}
+
+void spmm_stencil(bkts_ctx ctx, const bkts_op_s& op, int dtype, int k, double cb, const void* B, int ldb,
+                  double alpha, const void* X, int ldx, double beta, void* Y, int ldy) {
+  if (dtype == BKTS_F64)
+    st_spmm_t<double>(ctx, op, k, cb, B, ldb, alpha, X, ldx, beta, Y, ldy);
+  else
+    st_spmm_t<float>(ctx, op, k, cb, B, ldb, alpha, X, ldx, beta, Y, ldy);
+}
+
+}  // namespace bkts
