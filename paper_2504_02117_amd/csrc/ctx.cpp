@@ -147,7 +147,8 @@ double* bkts_ctx_s::host_stage(size_t count) {
     h_pinned = nullptr;
     h_pinned_bytes = 0;
     size_t want = bytes < 65536 ? 65536 : bytes;
-    BKTS_HIP(hipHostMalloc(reinterpret_cast<void**>(&h_pinned), want, hipHostMallocDefault));
+    // coherent: kernels may write results straight into it (the fused block-CG tail does)
+    BKTS_HIP(hipHostMalloc(reinterpret_cast<void**>(&h_pinned), want, hipHostMallocCoherent));
     h_pinned_bytes = want;
   }
   return h_pinned;

@@ -2,7 +2,8 @@
 // fixed order (as the plain fold), and the workgroup that finishes last (device-scope counter)
 // solves the k x k system from the folded values.  MODE 0 follows a Gram kernel (G, then
 // alpha = G^+ gamma_in); MODE 1 follows a block-CG update kernel whose partials are laid out
-// [gamma (KP^2) | T (KP^2) | nrm (KP)] (gamma, T, nrm, then beta = -G^+ T).  Entries are
+// [gamma (KP^2) | T (KP^2) | nrm (KP)] (gamma, T, nrm, then beta = -G^+ T, and optionally the norms
+// and the deflation count of the preceding alpha solve written to pinned host memory).  Entries are
 // a*KP + b; rows or columns >= k are padding and are dropped.
 #include "devcommon.hpp"
 #include "internal.hpp"
@@ -36,10 +37,15 @@ __global__ __launch_bounds__(256) void fold_solve_kernel(const double* __restric
     }
   }
   if (!dev::last_workgroup(t.counter)) return;
-  if (MODE == 0)
+  if (MODE == 0) {
     dev::spd_solve_dev_t<KP>(k, t.G, t.gamma_in, 1.0, t.eps, t.alpha, t.ndefl, sm);
-  else
+  } else {
     dev::spd_solve_dev_t<KP>(k, t.G, t.T, -1.0, t.eps, t.beta, nullptr, sm);
+    if (t.host) {
+      if (threadIdx.x < k) t.host[threadIdx.x] = t.nrm[threadIdx.x];
+      if (threadIdx.x == 0) *reinterpret_cast<int*>(t.host + k) = t.ndefl ? *t.ndefl : 0;
+    }
+  }
   if (threadIdx.x == 0) atomicExch(t.counter, 0u);
 }
 

@@ -290,6 +290,9 @@ struct CgTail {
   double* T = nullptr;
   double* nrm = nullptr;
   double* beta = nullptr;
+  // mode 1, optional: device-visible pinned host memory that the solving workgroup fills with
+  // nrm[0..k) followed by *ndefl (as an int), so the host reads the norms without a copy launch
+  double* host = nullptr;
 };
 
 // fold.hip: mode 0 after a Gram kernel, mode 1 after an update kernel; kp in {1, 2, 4, 16, 32}.

@@ -151,7 +151,11 @@ void block_cg(bkts_ctx ctx, const bkts_op_s& op, int dtype, int k, double a, dou
     tail_up.T = s.T;
     tail_up.nrm = s.nrm;
     tail_up.beta = s.beta;
+    tail_up.ndefl = s.ndefl;  // read only: copied to the host next to the norms
   }
+  // the fused tail writes the norms straight into the pinned staging buffer (no copy launch)
+  double* hbuf_dev = nullptr;
+  if (fused) BKTS_HIP(hipHostGetDevicePointer(reinterpret_cast<void**>(&hbuf_dev), hbuf, 0));
   int restarts = 0;
   for (int it = 1; it <= maxit; ++it) {
     if (fused) {
@@ -160,18 +164,17 @@ void block_cg(bkts_ctx ctx, const bkts_op_s& op, int dtype, int k, double a, dou
       spmm(ctx, op, dtype, k, 0.0, nullptr, k, a, P, k, b, Q, k);
       inner_gram(ctx, dtype, N, k, P, Q, s.G);
     }
+    const int slot = it & 1;
     if (fused) {
+      tail_up.host = hbuf_dev + slot * (k + 2);
       rk_cg_update(ctx, dtype, N, k, X, P, R, Q, s.alpha, dK, s.gamma, s.T, s.nrm, &tail_up);  // also beta
     } else {
       small_spd_solve(ctx, k, s.G, s.gamma, 1.0, eps, s.alpha, s.ndefl);
       cg_update(ctx, dtype, N, k, X, P, R, Q, s.alpha, dK, s.gamma, s.T, s.nrm);
+      BKTS_HIP(hipMemcpyAsync(hbuf + slot * (k + 2), s.nrm, sizeof(double) * (k + 1), hipMemcpyDeviceToHost,
+                              ctx->stream));
     }
-    {
-      const int slot = it & 1;
-      double* h = hbuf + slot * (k + 2);
-      BKTS_HIP(hipMemcpyAsync(h, s.nrm, sizeof(double) * (k + 1), hipMemcpyDeviceToHost, ctx->stream));
-      BKTS_HIP(hipEventRecord(ev[slot], ctx->stream));
-    }
+    BKTS_HIP(hipEventRecord(ev[slot], ctx->stream));
     int state = 0;
     if (it > 1) state = check(it - 1);
     if (state == 1) {

@@ -22,6 +22,10 @@ struct ResArgs {
   const int64_t* sptr;
   const int32_t* sw;
   int C;
+  int uw;                 // uniform SELL width (0: per-slice widths)
+  int na;                 // stencil form: number of neighbour offsets (0: none)
+  int64_t soff[3];
+  const double* coef;     // stencil form: diagonal, then one array per offset
   const double* Y;
   int ldy;
   const double* A1;    // row-major k x k (physical column order)
@@ -42,7 +46,65 @@ constexpr int res_lds() {
   return (2 * TileGeom<KP>::LDS_DOUBLES > 4 * KP) ? 2 * TileGeom<KP>::LDS_DOUBLES : 4 * KP;
 }
 
-template <int KP, bool SELL>
+// (K Y)[gr, c] for FMT 0 (CSR), 1 (SELL-C) and 2 (stencil form).  Every load of the row is issued
+// before the first FMA: the stencil form's addresses are known up front, and a uniform-width SELL
+// row issues its (at most 8) value/index loads, then its Y loads.
+template <int FMT>
+__device__ __forceinline__ double row_ky(const ResArgs& a, int64_t gr, int c) {
+  double ky = 0.0;
+  if constexpr (FMT == 2) {
+    double up[3], lo[3], yu[3], yl[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      up[q] = lo[q] = yu[q] = yl[q] = 0.0;
+      if (q < a.na) {
+        const int64_t s = a.soff[q];
+        const double* oq = a.coef + (1 + q) * a.N;
+        if (gr + s < a.N) {
+          up[q] = oq[gr];
+          yu[q] = a.Y[(gr + s) * a.ldy + c];
+        }
+        if (gr - s >= 0) {
+          lo[q] = oq[gr - s];
+          yl[q] = a.Y[(gr - s) * a.ldy + c];
+        }
+      }
+    }
+    ky = a.coef[gr] * a.Y[gr * a.ldy + c];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) ky = fma(up[q], yu[q], fma(lo[q], yl[q], ky));
+  } else if constexpr (FMT == 1) {
+    const int64_t sl = gr / a.C;
+    if (a.uw > 0 && a.uw <= 8) {
+      const int64_t base = sl * a.C * a.uw + (gr - sl * a.C);
+      double v[8], y[8];
+      int32_t ci[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        v[u] = u < a.uw ? a.val[base + (int64_t)u * a.C] : 0.0;
+        ci[u] = u < a.uw ? a.col[base + (int64_t)u * a.C] : (int32_t)gr;
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) y[u] = a.Y[(int64_t)ci[u] * a.ldy + c];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) ky = fma(v[u], y[u], ky);
+    } else {
+      const int64_t base = a.sptr[sl] + (gr - sl * a.C);
+      const int64_t len = a.sw[sl];
+      for (int64_t j = 0; j < len; ++j) {
+        const int64_t e = base + j * a.C;
+        ky = fma(a.val[e], a.Y[(int64_t)a.col[e] * a.ldy + c], ky);
+      }
+    }
+  } else {
+    const int64_t base = a.rowptr[gr];
+    const int64_t len = a.rowptr[gr + 1] - base;
+    for (int64_t j = 0; j < len; ++j) ky = fma(a.val[base + j], a.Y[(int64_t)a.col[base + j] * a.ldy + c], ky);
+  }
+  return ky;
+}
+
+template <int KP, int FMT>
 __global__ __launch_bounds__(256) void residual_kernel(ResArgs a) {
   using G = TileGeom<KP>;
   __shared__ __align__(16) double lds[res_lds<KP>()];
@@ -73,21 +135,7 @@ __global__ __launch_bounds__(256) void residual_kernel(ResArgs a) {
       double yv = 0.0, ky = 0.0;
       if (gr < a.N && cok) {
         yv = a.Y[gr * a.ldy + c];
-        int64_t base, stride, len;
-        if constexpr (SELL) {
-          const int64_t s = gr / a.C;
-          base = a.sptr[s] + (gr - s * a.C);
-          stride = a.C;
-          len = a.sw[s];
-        } else {
-          base = a.rowptr[gr];
-          stride = 1;
-          len = a.rowptr[gr + 1] - base;
-        }
-        for (int64_t j = 0; j < len; ++j) {
-          const int64_t e = base + j * stride;
-          ky = fma(a.val[e], a.Y[(int64_t)a.col[e] * a.ldy + c], ky);
-        }
+        ky = row_ky<FMT>(a, gr, c);
       }
       Yl[row * G::LDL + c] = yv;
       KYl[row * G::LDL + c] = ky;
@@ -114,17 +162,19 @@ template <int KP>
 void launch_res(bkts_ctx ctx, const bkts_op_s& op, ResArgs a, double* nrm) {
   using G = TileGeom<KP>;
   const int64_t ntiles = (a.N + G::RT - 1) / G::RT;
-  const int64_t cap = 2 * (int64_t)ctx->num_cu;
+  const int64_t cap = 3 * (int64_t)ctx->num_cu;  // the LDS tile pair admits 3 workgroups per CU at k = 4
   int64_t ns = ntiles < cap ? ntiles : cap;
   if (ns < 1) ns = 1;
   a.tps = (ntiles + ns - 1) / ns;
   a.partials = ctx->ws.get<double>("res_partials", (size_t)KP * ns);
-  ProfScope prof(ctx, BKTS_K_RESIDUAL,
-                 op.nnz * 12.0 + 4.0 * (op.N + 1) + 16.0 * op.N * a.k + (a.b ? 8.0 * op.N : 0.0) + 8.0 * op.N * a.nb0);
-  if (op.format == BKTS_FMT_SELL)
-    launch(ctx, (residual_kernel<KP, true>), dim3(ns), dim3(256), 0, a);
+  const double mat = op.st_na > 0 ? 8.0 * (1 + op.st_na) * op.N : op.nnz * 12.0 + 4.0 * (op.N + 1);
+  ProfScope prof(ctx, BKTS_K_RESIDUAL, mat + 16.0 * op.N * a.k + (a.b ? 8.0 * op.N : 0.0) + 8.0 * op.N * a.nb0);
+  if (op.st_na > 0)
+    launch(ctx, (residual_kernel<KP, 2>), dim3(ns), dim3(256), 0, a);
+  else if (op.format == BKTS_FMT_SELL)
+    launch(ctx, (residual_kernel<KP, 1>), dim3(ns), dim3(256), 0, a);
   else
-    launch(ctx, (residual_kernel<KP, false>), dim3(ns), dim3(256), 0, a);
+    launch(ctx, (residual_kernel<KP, 0>), dim3(ns), dim3(256), 0, a);
   BKTS_HIP(hipGetLastError());
   prof.end();
   finalize_partials(ctx, a.partials, (int)ns, a.k, nrm);
@@ -146,6 +196,10 @@ void residual(bkts_ctx ctx, const bkts_op_s& op, int k, const double* Y, int ldy
   a.sptr = op.sell_ptr.as<int64_t>();
   a.sw = op.sell_w.as<int32_t>();
   a.C = op.sell_C;
+  a.uw = op.sell_uniform_w;
+  a.na = op.st_na;
+  for (int q = 0; q < 3; ++q) a.soff[q] = op.st_off[q];
+  a.coef = op.st_coef.as<double>();
   a.Y = Y;
   a.ldy = ldy;
   a.A1 = A1t;

@@ -134,10 +134,11 @@ struct StArgs {
 };
 
 // Y = cb B + alpha X + beta K X.  Each row is handled by LPR = KP/VEC lanes, each owning VEC
-// consecutive columns (16-byte accesses when the block allows).  The diagonal stream is read
-// non-temporally (single use); the o_a arrays are read twice (at r and at r - s_a, one line, one
-// grid line or one plane later), so they stay cached for the second read.
-template <typename T, int KP, int VEC>
+// consecutive columns (16-byte accesses when the block allows); a thread carries G rows RPB apart,
+// whose loads are all issued before the first FMA.  The diagonal stream is read non-temporally
+// (single use); the o_a arrays are read twice (at r and at r - s_a, one line, one grid line or one
+// plane later), so they stay cached for the second read.
+template <typename T, int KP, int VEC, int G>
 __global__ __launch_bounds__(256) void st_spmm_kernel(StArgs<T> a) {
   constexpr int LPR = KP / VEC;
   constexpr int RPB = dev::kThreads / LPR;
@@ -150,61 +151,72 @@ __global__ __launch_bounds__(256) void st_spmm_kernel(StArgs<T> a) {
   } else {
     tile = dev::xcd_slot(blockIdx.x, gridDim.x);
   }
-  const int64_t r = tile * RPB + t / LPR;
-  if (r >= a.N || c0 >= a.k) return;
+  if (c0 >= a.k) return;
   const int64_t N = a.N;
-  const T dg = __builtin_nontemporal_load(a.coef + r);
-  T up[3], lo[3];
-  SVec<T, VEC> xu[3], xl[3];
+  int64_t r[G];
+  T dg[G], up[G][3], lo[G][3];
+  SVec<T, VEC> xr[G], xu[G][3], xl[G][3];
 #pragma unroll
-  for (int q = 0; q < 3; ++q) {
-    up[q] = lo[q] = T(0);
-    if (q < a.o.na) {
-      const int64_t s = a.o.s[q];
-      const T* oq = a.coef + (1 + q) * N;
-      if (r + s < N) {
-        up[q] = oq[r];
-        xu[q] = sload<T, VEC>(a.X + (r + s) * a.ldx + c0);
-      }
-      if (r - s >= 0) {
-        lo[q] = oq[r - s];
-        xl[q] = sload<T, VEC>(a.X + (r - s) * a.ldx + c0);
-      }
-    }
-  }
-  const SVec<T, VEC> xr = sload<T, VEC>(a.X + r * a.ldx + c0);
-  SVec<T, VEC> acc;
+  for (int g = 0; g < G; ++g) {
+    r[g] = (tile * G + g) * RPB + t / LPR;
+    const bool ok = r[g] < N;
+    dg[g] = ok ? __builtin_nontemporal_load(a.coef + r[g]) : T(0);
+    if (ok) xr[g] = sload<T, VEC>(a.X + r[g] * a.ldx + c0);
 #pragma unroll
-  for (int i = 0; i < VEC; ++i) acc.v[i] = dg * xr.v[i];
-#pragma unroll
-  for (int q = 0; q < 3; ++q) {
-    if (q < a.o.na) {
-      const int64_t s = a.o.s[q];
-      if (r - s >= 0) {
-#pragma unroll
-        for (int i = 0; i < VEC; ++i) acc.v[i] = fma(lo[q], xl[q].v[i], acc.v[i]);
-      }
-      if (r + s < N) {
-#pragma unroll
-        for (int i = 0; i < VEC; ++i) acc.v[i] = fma(up[q], xu[q].v[i], acc.v[i]);
+    for (int q = 0; q < 3; ++q) {
+      up[g][q] = lo[g][q] = T(0);
+      if (ok && q < a.o.na) {
+        const int64_t s = a.o.s[q];
+        const T* oq = a.coef + (1 + q) * N;
+        if (r[g] + s < N) {
+          up[g][q] = oq[r[g]];
+          xu[g][q] = sload<T, VEC>(a.X + (r[g] + s) * a.ldx + c0);
+        }
+        if (r[g] - s >= 0) {
+          lo[g][q] = oq[r[g] - s];
+          xl[g][q] = sload<T, VEC>(a.X + (r[g] - s) * a.ldx + c0);
+        }
       }
     }
   }
-  SVec<T, VEC> out;
 #pragma unroll
-  for (int i = 0; i < VEC; ++i) out.v[i] = a.beta * acc.v[i] + a.alpha * xr.v[i];
-  if (a.B) {
-    const SVec<T, VEC> br = sload<T, VEC>(a.B + r * a.ldb + c0);
+  for (int g = 0; g < G; ++g) {
+    if (r[g] >= N) continue;
+    SVec<T, VEC> acc;
 #pragma unroll
-    for (int i = 0; i < VEC; ++i) out.v[i] = fma(a.cb, br.v[i], out.v[i]);
+    for (int i = 0; i < VEC; ++i) acc.v[i] = dg[g] * xr[g].v[i];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      if (q < a.o.na) {
+        const int64_t s = a.o.s[q];
+        if (r[g] - s >= 0) {
+#pragma unroll
+          for (int i = 0; i < VEC; ++i) acc.v[i] = fma(lo[g][q], xl[g][q].v[i], acc.v[i]);
+        }
+        if (r[g] + s < N) {
+#pragma unroll
+          for (int i = 0; i < VEC; ++i) acc.v[i] = fma(up[g][q], xu[g][q].v[i], acc.v[i]);
+        }
+      }
+    }
+    SVec<T, VEC> out;
+#pragma unroll
+    for (int i = 0; i < VEC; ++i) out.v[i] = a.beta * acc.v[i] + a.alpha * xr[g].v[i];
+    if (a.B) {
+      const SVec<T, VEC> br = sload<T, VEC>(a.B + r[g] * a.ldb + c0);
+#pragma unroll
+      for (int i = 0; i < VEC; ++i) out.v[i] = fma(a.cb, br.v[i], out.v[i]);
+    }
+    sstore<T, VEC>(a.Y + r[g] * a.ldy + c0, out, KP >= 8);
   }
-  sstore<T, VEC>(a.Y + r * a.ldy + c0, out, KP >= 8);
 }
 
 template <typename T, int KP, int VEC>
 void st_launch(bkts_ctx ctx, const bkts_op_s& op, const StArgs<T>& a0) {
   constexpr int LPR = KP / VEC;
-  constexpr int RPB = dev::kThreads / LPR;
+  // rows per thread: narrow rows carry several rows per thread (more loads in flight per wave)
+  constexpr int G = KP * sizeof(T) <= 16 ? 2 : 1;
+  constexpr int RPB = dev::kThreads / LPR * G;
   StArgs<T> a = a0;
   const int64_t ntiles = (a.N + RPB - 1) / RPB;
   int64_t nb = ntiles;
@@ -214,7 +226,7 @@ void st_launch(bkts_ctx ctx, const bkts_op_s& op, const StArgs<T>& a0) {
     const int64_t per = dev::kXcd * a.strip;
     nb = (ntiles + per - 1) / per * per;  // whole rounds of 8 strips; blocks past the end exit
   }
-  launch(ctx, (st_spmm_kernel<T, KP, VEC>), dim3(nb), dim3(dev::kThreads), 0, a);
+  launch(ctx, (st_spmm_kernel<T, KP, VEC, G>), dim3(nb), dim3(dev::kThreads), 0, a);
 }
 
 template <typename T, int KP>
