@@ -262,7 +262,8 @@ struct RkUpdArgs {
   double* partials;  // [gamma (KP^2) | T (KP^2) | nrm (KP)] entries
 };
 
-// X += P alpha; R -= Q alpha; Z = D^-1 R; gamma = R^T Z; T = Q^T Z; nrm = diag(R^T R)
+// X += P alpha; R -= Q alpha; Z = D^-1 R; gamma = R^T Z; T = Q^T Z; nrm = diag(R^T R).  Two rows per
+// thread per step, with the loads of both issued before the arithmetic.
 template <typename T, int KP>
 __global__ __launch_bounds__(256) void rk_cg_update_kernel(RkUpdArgs a) {
   constexpr int NA = 2 * KP * KP + KP;
@@ -278,37 +279,53 @@ __global__ __launch_bounds__(256) void rk_cg_update_kernel(RkUpdArgs a) {
   T* X = static_cast<T*>(a.X);
   T* R = static_cast<T*>(a.R);
   const RowRange rr = block_rows(a.N);
-  for (int64_t r = rr.begin + threadIdx.x; r < rr.end; r += dev::kThreads) {
-    const Row<T, KP> p = ld_row<T, KP>(P + r * KP, KP);
-    const Row<T, KP> q = ld_row<T, KP>(Q + r * KP, KP);
-    Row<T, KP> x = ld_row<T, KP>(X + r * KP, KP);
-    Row<T, KP> rv = ld_row<T, KP>(R + r * KP, KP);
-    const double dv = a.dinv ? a.dinv[r] : 1.0;
-    double z[KP], rn[KP];
+  constexpr int GR = 2;  // rows per thread per step (256 apart), all loads issued first
+  for (int64_t r0 = rr.begin + threadIdx.x; r0 < rr.end; r0 += GR * dev::kThreads) {
+    Row<T, KP> p[GR], q[GR], x[GR], rv[GR];
+    double dv[GR];
+    bool ok[GR];
 #pragma unroll
-    for (int c = 0; c < KP; ++c) {
-      double xs = (double)x.v[c], rs = (double)rv.v[c];
-#pragma unroll
-      for (int j = 0; j < KP; ++j) {
-        xs = fma((double)p.v[j], al[j * KP + c], xs);
-        rs = fma(-(double)q.v[j], al[j * KP + c], rs);
+    for (int h = 0; h < GR; ++h) {
+      const int64_t r = r0 + h * dev::kThreads;
+      ok[h] = r < rr.end;
+      if (ok[h]) {
+        p[h] = ld_row<T, KP>(P + r * KP, KP);
+        q[h] = ld_row<T, KP>(Q + r * KP, KP);
+        x[h] = ld_row<T, KP>(X + r * KP, KP);
+        rv[h] = ld_row<T, KP>(R + r * KP, KP);
       }
-      x.v[c] = (T)xs;
-      rv.v[c] = (T)rs;
-      rn[c] = (double)rv.v[c];
-      z[c] = rn[c] * dv;
+      dv[h] = (ok[h] && a.dinv) ? a.dinv[r] : 1.0;
     }
-    st_row<T, KP>(X + r * KP, x);
-    st_row<T, KP>(R + r * KP, rv);
 #pragma unroll
-    for (int i = 0; i < KP; ++i)
+    for (int h = 0; h < GR; ++h) {
+      if (!ok[h]) continue;
+      const int64_t r = r0 + h * dev::kThreads;
+      double z[KP], rn[KP];
 #pragma unroll
-      for (int j = 0; j < KP; ++j) {
-        acc[i * KP + j] = fma(rn[i], z[j], acc[i * KP + j]);
-        acc[KP * KP + i * KP + j] = fma((double)q.v[i], z[j], acc[KP * KP + i * KP + j]);
+      for (int c = 0; c < KP; ++c) {
+        double xs = (double)x[h].v[c], rs = (double)rv[h].v[c];
+#pragma unroll
+        for (int j = 0; j < KP; ++j) {
+          xs = fma((double)p[h].v[j], al[j * KP + c], xs);
+          rs = fma(-(double)q[h].v[j], al[j * KP + c], rs);
+        }
+        x[h].v[c] = (T)xs;
+        rv[h].v[c] = (T)rs;
+        rn[c] = (double)rv[h].v[c];
+        z[c] = rn[c] * dv[h];
       }
+      st_row<T, KP>(X + r * KP, x[h]);
+      st_row<T, KP>(R + r * KP, rv[h]);
 #pragma unroll
-    for (int c = 0; c < KP; ++c) acc[2 * KP * KP + c] = fma(rn[c], rn[c], acc[2 * KP * KP + c]);
+      for (int i = 0; i < KP; ++i)
+#pragma unroll
+        for (int j = 0; j < KP; ++j) {
+          acc[i * KP + j] = fma(rn[i], z[j], acc[i * KP + j]);
+          acc[KP * KP + i * KP + j] = fma((double)q[h].v[i], z[j], acc[KP * KP + i * KP + j]);
+        }
+#pragma unroll
+      for (int c = 0; c < KP; ++c) acc[2 * KP * KP + c] = fma(rn[c], rn[c], acc[2 * KP * KP + c]);
+    }
   }
   fold_block<NA>(acc, red, a.partials);
 }
