@@ -46,6 +46,8 @@ def parse():
                    help="storage of the 128^3 operator: the index-free stencil form (diagonal + one array per "
                         "neighbour offset) or SELL-C; the other format's block and plain forms are timed beside it")
     p.add_argument("--no-format-compare", dest="format_compare", action="store_false")
+    p.add_argument("--precond", choices=["jacobi", "mg"], default="jacobi",
+                   help="preconditioner of the inner block CG of the headline forms (mg needs the stencil format)")
     p.add_argument("--plain-steps", type=int, default=8)
     p.add_argument("--no-plain", action="store_true")
     p.add_argument("--no-cpu", action="store_true")
@@ -223,12 +225,13 @@ def calibrate_copy(torch):
     del a, b
 
 
-def run_form(torch, bkts, ctx, op, y0, k, precision, inner_rtol, warmup, steps, profile):
+def run_form(torch, bkts, ctx, op, y0, k, precision, inner_rtol, warmup, steps, profile, precond="jacobi"):
     """Time `steps` accepted steps of a persistent stepper after `warmup` untimed ones."""
     tc = bkts.bkts_tc_create(ctx, bkts.BKTS_IE, k, 1e-3)
     st = bkts.bkts_stepper_create(ctx, op, tc, y0)
     prec = bkts.BKTS_PRECISION_F32_REFINE if precision == "f32" else bkts.BKTS_PRECISION_F64
-    inner = bkts.solve_opts(precision=prec, rtol=inner_rtol, inner_rtol=inner_rtol, maxit=100000)
+    pc = bkts.BKTS_PREC_MG if precond == "mg" else bkts.BKTS_PREC_JACOBI
+    inner = bkts.solve_opts(precond=pc, precision=prec, rtol=inner_rtol, inner_rtol=inner_rtol, maxit=100000)
     N = y0.numel()
     try:
         if warmup:
@@ -704,7 +707,7 @@ def main():
 
     log(f"block form k={a.k} {a.precision}: warmup {a.warmup}, timed {a.steps}")
     blk = run_form(torch, bkts, ctx, op, y0, a.k, a.precision, a.inner_rtol, a.warmup, a.steps,
-                   not a.no_kernel_timers)
+                   not a.no_kernel_timers, a.precond)
     log(f"  {blk['value']:.4g} DOF*steps/s, outer={blk['info'].outer_iterations} "
         f"krylov={blk['info'].krylov_iterations}")
     result_hist = blk["hist"][-2:].double().cpu().numpy() if a.steps >= 2 else None
@@ -712,7 +715,7 @@ def main():
     plain = None
     if not a.no_plain:
         log(f"plain form k=1 f64: timed {a.plain_steps}")
-        pl = run_form(torch, bkts, ctx, op, y0, 1, "f64", 1e-8, 1, a.plain_steps, False)
+        pl = run_form(torch, bkts, ctx, op, y0, 1, "f64", 1e-8, 1, a.plain_steps, False, a.precond)
         plain = {"value": pl["value"], "ms_per_step": 1e3 * pl["seconds"] / a.plain_steps,
                  "krylov_iterations_per_step": pl["info"].krylov_iterations / a.plain_steps,
                  "config": "k=1, FP64 block CG (= CG) + Jacobi, inner = outer = 1e-8"}
@@ -727,7 +730,7 @@ def main():
         if item.endswith("f32") or item.endswith("f64"):
             prec, item = item[-3:], item[:-3]
         ks = int(item)
-        r = run_form(torch, bkts, ctx, op, y0, ks, prec, tol, a.warmup, a.steps, True)
+        r = run_form(torch, bkts, ctx, op, y0, ks, prec, tol, a.warmup, a.steps, True, a.precond)
         sp = r["kernels"].get("spmm", {})
         sv = 4 if prec == "f32" else 8
         bpl = (4 * N * sv if a.format == "stencil" else nnz * (sv + 4) + 4 * (N + 1)) + 2 * N * ks * sv

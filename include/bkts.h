@@ -211,12 +211,16 @@ bkts_status bkts_residual(bkts_ctx ctx, bkts_op op, bkts_tc tc, int phase, const
 /* ------------------------------------------------------------- block solve */
 
 enum { BKTS_CG = 0, BKTS_GMRES = 1, BKTS_BICGSTAB = 2 };
-enum { BKTS_PREC_NONE = 0, BKTS_PREC_JACOBI = 1 };
+/* BKTS_PREC_MG: one symmetric geometric multigrid V-cycle per iteration (Galerkin 2x2x2
+ * aggregation of the stencil form, damped Jacobi smoothing); block CG only, and the operator must
+ * carry the stencil form (BKTS_FMT_STENCIL), else BKTS_EINVAL.  The paper preconditions its inner
+ * solves with AMG (Sec. 4.1). */
+enum { BKTS_PREC_NONE = 0, BKTS_PREC_JACOBI = 1, BKTS_PREC_MG = 2 };
 enum { BKTS_PRECISION_F64 = 0, BKTS_PRECISION_F32_REFINE = 1 };
 
 typedef struct bkts_solve_opts {
   int krylov;        /* BKTS_CG (SPD operators), BKTS_GMRES, BKTS_BICGSTAB */
-  int precond;       /* BKTS_PREC_NONE or BKTS_PREC_JACOBI */
+  int precond;       /* BKTS_PREC_NONE, BKTS_PREC_JACOBI or BKTS_PREC_MG */
   int precision;     /* BKTS_PRECISION_F64, or FP32 Krylov iterations inside an FP64
                         iterative-refinement loop (residuals in FP64) */
   double rtol;       /* per column: stop when ||r_j|| <= rtol * ||b_j - A x0_j|| for every j */

@@ -29,7 +29,7 @@ BKTS_IE, BKTS_THETA, BKTS_SDIRK2, BKTS_DIRK_CUSTOM, BKTS_RADAU2 = 0, 1, 2, 3, 4
 BKTS_RI_NO_FLOW, BKTS_RI_DIRICHLET, BKTS_RI_FREE_DRAINAGE = 0, 1, 2
 BKTS_WINDOW_FGMRES, BKTS_WINDOW_SPLITTING = 0, 1
 BKTS_CG, BKTS_GMRES, BKTS_BICGSTAB = 0, 1, 2
-BKTS_PREC_NONE, BKTS_PREC_JACOBI = 0, 1
+BKTS_PREC_NONE, BKTS_PREC_JACOBI, BKTS_PREC_MG = 0, 1, 2
 BKTS_PRECISION_F64, BKTS_PRECISION_F32_REFINE = 0, 1
 KERNELS = ("spmm", "gram", "norms", "cg_update", "cg_pupdate", "residual", "small", "cast", "other")
 

@@ -9,6 +9,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <map>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -124,6 +125,11 @@ struct bkts_ctx_s {
   void sync();
 };
 
+namespace bkts {
+struct MgHier;  // multigrid hierarchy of an operator (mg.hip)
+void mg_hier_delete(MgHier* h);
+}  // namespace bkts
+
 struct bkts_op_s {
   bkts_ctx ctx = nullptr;
   int64_t N = 0, nnz = 0;
@@ -150,6 +156,8 @@ struct bkts_op_s {
   int st_na = 0;
   int64_t st_off[3] = {0, 0, 0};
   bkts::DevBuf st_coef, st_coef32;
+  // Galerkin multigrid hierarchy of K and the mass (built on first use by a multigrid solve)
+  mutable std::shared_ptr<bkts::MgHier> mg;
 };
 
 // Nonlinear FV operator (nonlinear.hip).
@@ -242,6 +250,9 @@ void op_refresh_values(bkts_op op);  // after CSR values changed: diag, SELL val
 void op_build_stencil(bkts_op op);
 void spmm_stencil(bkts_ctx ctx, const bkts_op_s& op, int dtype, int k, double cb, const void* B, int ldb,
                   double alpha, const void* X, int ldx, double beta, void* Y, int ldy);
+// Z = V-cycle(F) for a I + b K (mg.hip): symmetric geometric multigrid on the stencil form, N x k
+// contiguous blocks of type dtype.  BKTS_EINVAL without the stencil form.
+void mg_vcycle(bkts_ctx ctx, const bkts_op_s& op, int dtype, int k, double a, double b, const void* F, void* Z);
 
 // ---- nonlinear operator (nonlinear.hip)
 bkts_nlop nlop_create(bkts_ctx ctx, const bkts_grid* grid, const bkts_nl_coeffs* c);

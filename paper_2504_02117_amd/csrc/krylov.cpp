@@ -200,6 +200,69 @@ void block_cg(bkts_ctx ctx, const bkts_op_s& op, int dtype, int k, double a, dou
   st.converged = 0;
 }
 
+// Block CG preconditioned by the multigrid V-cycle (mg.hip).  Z = M^-1 R is a block of its own, so
+// gamma = R^T Z and T = Q^T Z are separate Gram passes (the Jacobi form folds them into the update);
+// the deflating k x k solves and the restart on a collapsed search space are those of block_cg.
+void block_pcg_mg(bkts_ctx ctx, const bkts_op_s& op, int dtype, int k, double a, double b, const void* B, void* X,
+                  bool x0_zero, double rtol, int maxit, KrylovStats& st) {
+  const int64_t N = op.N;
+  const size_t es = esize(dtype);
+  const std::string tag = dtype == BKTS_F64 ? "d" : "s";
+  void* R = ctx->ws.get("mgcg_R_" + tag, es * N * k);
+  void* P = ctx->ws.get("mgcg_P_" + tag, es * N * k);
+  void* Q = ctx->ws.get("mgcg_Q_" + tag, es * N * k);
+  void* Z = ctx->ws.get("mgcg_Z_" + tag, es * N * k);
+  Small s = small_bufs(ctx, "mgcg" + tag, k);
+  const double eps = cg_pivot_floor(dtype);
+  if (x0_zero) {
+    BKTS_HIP(hipMemsetAsync(X, 0, es * N * k, ctx->stream));
+    BKTS_HIP(hipMemcpyAsync(R, B, es * N * k, hipMemcpyDeviceToDevice, ctx->stream));
+  } else {
+    spmm(ctx, op, dtype, k, 1.0, B, k, -a, X, k, -b, R, k);
+  }
+  colnorms2(ctx, dtype, N, k, R, k, s.nrm0);
+  std::vector<double> nrm0, nrm;
+  read_norms(ctx, s.nrm0, k, nrm0);
+  st.iterations = 0;
+  st.deflations = 0;
+  st.converged = all_converged(nrm0, nrm0, rtol, &st.max_rel) ? 1 : 0;
+  if (st.converged) return;
+  auto precondition = [&]() {  // Z = M^-1 R, P = Z, gamma = R^T Z
+    mg_vcycle(ctx, op, dtype, k, a, b, R, Z);
+    cg_pupdate(ctx, dtype, N, k, P, Z, nullptr, nullptr);
+    inner_gram(ctx, dtype, N, k, R, Z, s.gamma);
+  };
+  precondition();
+  int restarts = 0;
+  for (int it = 1; it <= maxit; ++it) {
+    spmm(ctx, op, dtype, k, 0.0, nullptr, k, a, P, k, b, Q, k);
+    inner_gram(ctx, dtype, N, k, P, Q, s.G);
+    small_spd_solve(ctx, k, s.G, s.gamma, 1.0, eps, s.alpha, s.ndefl);
+    // X += P alpha, R -= Q alpha and the norms of R (its gamma and T outputs are recomputed below)
+    cg_update(ctx, dtype, N, k, X, P, R, Q, s.alpha, nullptr, s.T, s.beta, s.nrm);
+    int nd = 0;
+    read_norms(ctx, s.nrm, k, nrm, s.ndefl, &nd);
+    st.iterations = it;
+    st.deflations = std::max(st.deflations, nd);
+    if (all_converged(nrm, nrm0, rtol, &st.max_rel)) {
+      st.converged = 1;
+      return;
+    }
+    if (nd >= k) {  // every search direction collapsed: restart from the preconditioned residual
+      if (++restarts > 3) throw Error{BKTS_EBREAKDOWN, "block CG: search space collapsed repeatedly"};
+      precondition();
+      continue;
+    }
+    restarts = 0;
+    mg_vcycle(ctx, op, dtype, k, a, b, R, Z);
+    inner_gram(ctx, dtype, N, k, R, Z, s.gamma);
+    inner_gram(ctx, dtype, N, k, Q, Z, s.T);
+    small_spd_solve(ctx, k, s.G, s.T, -1.0, eps, s.beta, nullptr);
+    cg_pupdate(ctx, dtype, N, k, P, Z, s.beta, nullptr);
+  }
+  st.converged = 0;
+}
+
 // One FP32 block CG solve of (a I + b K) V = R64 for FP64 blocks: R64 is scaled per column to
 // unit norm, cast to FP32, solved to `rtol`, and the FP32 correction is scaled back and added to
 // V64 (which need not be zero).
@@ -207,8 +270,15 @@ void block_cg(bkts_ctx ctx, const bkts_op_s& op, int dtype, int k, double a, dou
 static void krylov_run(bkts_ctx ctx, const bkts_op_s& op, const bkts_solve_opts& o, int dtype, int k, double a,
                        double b, const void* B, void* X, bool x0_zero, double rtol, int maxit, KrylovStats& st) {
   const bool jacobi = o.precond == BKTS_PREC_JACOBI;
+  BKTS_REQUIRE(o.precond >= BKTS_PREC_NONE && o.precond <= BKTS_PREC_MG, "unknown preconditioner %d", o.precond);
+  BKTS_REQUIRE(o.precond != BKTS_PREC_MG || o.krylov == BKTS_CG, "multigrid preconditions block CG only");
   switch (o.krylov) {
-    case BKTS_CG: block_cg(ctx, op, dtype, k, a, b, B, X, x0_zero, jacobi, rtol, maxit, st); break;
+    case BKTS_CG:
+      if (o.precond == BKTS_PREC_MG)
+        block_pcg_mg(ctx, op, dtype, k, a, b, B, X, x0_zero, rtol, maxit, st);
+      else
+        block_cg(ctx, op, dtype, k, a, b, B, X, x0_zero, jacobi, rtol, maxit, st);
+      break;
     case BKTS_GMRES: block_gmres(ctx, op, dtype, k, a, b, B, X, x0_zero, jacobi, rtol, o.restart, maxit, st); break;
     case BKTS_BICGSTAB: block_bicgstab(ctx, op, dtype, k, a, b, B, X, x0_zero, jacobi, rtol, maxit, st); break;
     default: throw Error{BKTS_EINVAL, fmt("unknown Krylov method %d", o.krylov)};
