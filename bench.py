@@ -46,7 +46,7 @@ def parse():
                    help="storage of the 128^3 operator: the index-free stencil form (diagonal + one array per "
                         "neighbour offset) or SELL-C; the other format's block and plain forms are timed beside it")
     p.add_argument("--no-format-compare", dest="format_compare", action="store_false")
-    p.add_argument("--precond", choices=["jacobi", "mg"], default="jacobi",
+    p.add_argument("--precond", choices=["jacobi", "mg"], default="mg",
                    help="preconditioner of the inner block CG of the headline forms (mg needs the stencil format)")
     p.add_argument("--plain-steps", type=int, default=8)
     p.add_argument("--no-plain", action="store_true")
@@ -121,7 +121,8 @@ def kernel_name(cat, k, fmt="sell"):
             "cg_pupdate": "rk_cg_pupdate_kernel" if row else "mf_cg_pupdate_kernel",
             "gram": "rk_gram_kernel" if row else "mf_gram_kernel",
             "residual": "residual_kernel", "norms": "colnorm_kernel", "cast": "cast_scale_kernel",
-            "small": "finalize / k x k kernels", "other": "vector kernels"}.get(cat, cat)
+            "small": "finalize / k x k kernels", "other": "vector kernels",
+            "mg_restrict": "mg_restrict_kernel", "mg_prolong": "mg_prolong_kernel"}.get(cat, cat)
 
 
 def roofline_of(kt, cat, k, precision, fmt="sell"):
@@ -467,6 +468,7 @@ def run_accel(torch, bkts, ctx, a, op, u0):
         tc = bkts.bkts_tc_create(ctx, bkts.BKTS_IE, kk, tau)
         B0 = (u0 / tau).reshape(N, 1).contiguous()
         inner = bkts.solve_opts(krylov=bkts.BKTS_CG, precision=bkts.BKTS_PRECISION_F32_REFINE,
+                                precond=bkts.BKTS_PREC_MG if a.precond == "mg" else bkts.BKTS_PREC_JACOBI,
                                 rtol=a.accel_inner_rtol, inner_rtol=a.accel_inner_rtol, maxit=4000)
         try:
             row = {}
@@ -492,7 +494,7 @@ def run_accel(torch, bkts, ctx, a, op, u0):
         finally:
             bkts.bkts_tc_destroy(tc)
     return {"workload": f"heterogeneous diffusion {a.n}^3 (the headline operator), one implicit-Euler window of k "
-                        f"steps from u0 solved whole to ||R||_F <= 1e-8 ||F||_F; J^-1 = FP32 block CG + Jacobi "
+                        f"steps from u0 solved whole to ||R||_F <= 1e-8 ||F||_F; J^-1 = FP32 block CG + {a.precond} "
                         f"at inner rtol {a.accel_inner_rtol:g}; FGMRES restart 30",
             "unit": "DOF*timesteps/s", "forms": out}, keep
 
@@ -509,6 +511,7 @@ def run_firk(torch, bkts, ctx, a, op, u0, kd, n):
     N = u0.shape[0]
     prec = bkts.BKTS_PRECISION_F32_REFINE
     inner = bkts.solve_opts(krylov=bkts.BKTS_CG, precision=prec, rtol=a.firk_inner_rtol,
+                            precond=bkts.BKTS_PREC_MG if a.precond == "mg" else bkts.BKTS_PREC_JACOBI,
                             inner_rtol=a.firk_inner_rtol, maxit=100000)
     forms = {}
     for kk in [int(v) for v in a.firk_ks.split(",") if v.strip()]:
@@ -558,7 +561,7 @@ def run_firk(torch, bkts, ctx, a, op, u0, kd, n):
     kap = inputs_lognormal(m)
     K, b = fv.assemble_linear(m, kappa=kap)
     y0 = u0_small(m)
-    op_s = bkts.bkts_fv_assemble(ctx, m, kappa=torch.from_numpy(kap).cuda(), fmt=bkts.BKTS_FMT_SELL)
+    op_s = bkts.bkts_fv_assemble(ctx, m, kappa=torch.from_numpy(kap).cuda(), fmt=bkts.BKTS_FMT_STENCIL)
     tc = bkts.bkts_tc_create(ctx, bkts.BKTS_RADAU2, 4, tau)
     try:
         hist = torch.empty((4, y0.shape[0]), dtype=torch.float64, device="cuda")
@@ -573,7 +576,7 @@ def run_firk(torch, bkts, ctx, a, op, u0, kd, n):
     best = max(forms, key=lambda f: forms[f]["value"])
     return {"workload": f"heterogeneous diffusion {a.n}^3 (the headline operator), 2-stage Radau IIA tau=1e-3, "
                         f"{steps} steps to a 1e-8 residual per accepted step, averaged splitting coefficient "
-                        f"|det A|^(1/2), J^-1 = FP32 block CG + Jacobi at inner rtol {a.firk_inner_rtol}",
+                        f"|det A|^(1/2), J^-1 = FP32 block CG + {a.precond} at inner rtol {a.firk_inner_rtol}",
             "unit": "DOF*timesteps/s", "forms": forms, "best": best,
             "oracle_max_rel_err_16cubed": err}
 
@@ -718,7 +721,7 @@ def main():
         pl = run_form(torch, bkts, ctx, op, y0, 1, "f64", 1e-8, 1, a.plain_steps, False, a.precond)
         plain = {"value": pl["value"], "ms_per_step": 1e3 * pl["seconds"] / a.plain_steps,
                  "krylov_iterations_per_step": pl["info"].krylov_iterations / a.plain_steps,
-                 "config": "k=1, FP64 block CG (= CG) + Jacobi, inner = outer = 1e-8"}
+                 "config": f"k=1, FP64 block CG (= CG) + {a.precond}, inner = outer = 1e-8"}
         log(f"  {pl['value']:.4g} DOF*steps/s")
 
     sweep = {}
@@ -755,21 +758,27 @@ def main():
 
     formats = None
     if a.format_compare:
-        other = "sell" if a.format == "stencil" else "stencil"
-        log(f"{other} operator: block form k={a.k} {a.precision} and plain k=1 f64 beside the {a.format} ones")
-        op2 = bkts.bkts_fv_assemble(ctx, n, kappa=kd, fmt=fcode[other])
-        try:
-            b2 = run_form(torch, bkts, ctx, op2, y0, a.k, a.precision, a.inner_rtol, a.warmup, a.steps, True)
-            p2 = None if a.no_plain else run_form(torch, bkts, ctx, op2, y0, 1, "f64", 1e-8, 1, a.plain_steps, False)
-        finally:
-            bkts.bkts_op_destroy(op2)
-        sp2 = b2["kernels"].get("spmm", {})
-        formats = {a.format: {"block": blk["value"], "plain": plain["value"] if plain else None,
-                              "spmm_avg_us": blk["kernels"].get("spmm", {}).get("avg_us")},
-                   other: {"block": b2["value"], "plain": p2["value"] if p2 else None,
-                           "spmm_avg_us": sp2.get("avg_us"), "krylov_iterations": b2["info"].krylov_iterations}}
-        log(f"  {other}: block {b2['value']:.4g}" + (f", plain {p2['value']:.4g}" if p2 else "") +
-            f" DOF*steps/s (spmm {sp2.get('avg_us', 0):.1f} us)")
+        # the headline's block and plain forms with the other operator storage and preconditioner
+        formats = {f"{a.format}+{a.precond}": {"block": blk["value"], "plain": plain["value"] if plain else None,
+                                              "krylov_iterations": blk["info"].krylov_iterations,
+                                              "spmm_avg_us": blk["kernels"].get("spmm", {}).get("avg_us")}}
+        for fmt, pc in (("stencil", "jacobi"), ("sell", "jacobi"), ("stencil", "mg")):
+            key = f"{fmt}+{pc}"
+            if key in formats:
+                continue
+            log(f"{key}: block form k={a.k} {a.precision} and plain k=1 f64 beside the headline's")
+            op2 = bkts.bkts_fv_assemble(ctx, n, kappa=kd, fmt=fcode[fmt])
+            try:
+                b2 = run_form(torch, bkts, ctx, op2, y0, a.k, a.precision, a.inner_rtol, a.warmup, a.steps, True, pc)
+                p2 = None if a.no_plain else run_form(torch, bkts, ctx, op2, y0, 1, "f64", 1e-8, 1, a.plain_steps,
+                                                      False, pc)
+            finally:
+                bkts.bkts_op_destroy(op2)
+            sp2 = b2["kernels"].get("spmm", {})
+            formats[key] = {"block": b2["value"], "plain": p2["value"] if p2 else None,
+                            "krylov_iterations": b2["info"].krylov_iterations, "spmm_avg_us": sp2.get("avg_us")}
+            log(f"  {key}: block {b2['value']:.4g}" + (f", plain {p2['value']:.4g}" if p2 else "") +
+                f" DOF*steps/s, krylov {b2['info'].krylov_iterations} (spmm {sp2.get('avg_us', 0):.1f} us)")
 
     spmm_sweep = None
     if a.spmm_ks.strip():
@@ -843,8 +852,10 @@ def main():
         "data": "synthetic (seeded lognormal field, sin-product initial state)",
         "config": {"workload": f"heterogeneous diffusion {a.n}^3 FV 7-point, lognormal kappa (log-std 2, corr. 8 "
                                f"cells), implicit Euler tau=1e-3, block width k={a.k}, {a.format} operator, "
+                               f"block CG + {'multigrid V-cycle' if a.precond == 'mg' else 'Jacobi'}, "
                                f"{'FP32-inner + FP64 refinement' if a.precision == 'f32' else 'FP64'} to 1e-8",
                    "N": N, "nnz": nnz, "k": a.k, "inner_rtol": a.inner_rtol, "format": a.format,
+                   "precond": a.precond,
                    "setup_s": setup_s},
         "outer_iterations": blk["info"].outer_iterations, "krylov_iterations": blk["info"].krylov_iterations,
         "oracle_rel_residual_last_step": err,

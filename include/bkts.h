@@ -95,7 +95,9 @@ enum {
   BKTS_K_SMALL = 6,      /* k x k device kernels and partial-sum folding      */
   BKTS_K_CAST = 7,       /* precision casts / strided copies                  */
   BKTS_K_OTHER = 8,      /* vector helpers of the time-stepping loop          */
-  BKTS_K_COUNT = 9
+  BKTS_K_MG_RESTRICT = 9,  /* multigrid: smoothed residual restricted (all levels) */
+  BKTS_K_MG_PROLONG = 10,  /* multigrid: prolongation and post-sweep (all levels)  */
+  BKTS_K_COUNT = 11
 };
 bkts_status bkts_profile_enable(bkts_ctx ctx, int enable);
 bkts_status bkts_profile_query(bkts_ctx ctx, int kernel, int64_t* launches, double* total_ms,

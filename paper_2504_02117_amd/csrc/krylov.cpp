@@ -233,22 +233,52 @@ void block_pcg_mg(bkts_ctx ctx, const bkts_op_s& op, int dtype, int k, double a,
     inner_gram(ctx, dtype, N, k, R, Z, s.gamma);
   };
   precondition();
+  // Convergence is read one iteration late, as in block_cg: the norms of iteration it are copied to
+  // pinned memory behind an event while iteration it+1 is enqueued.
+  double* hbuf = ctx->host_stage(2 * (k + 2));
+  ctx->sync();
+  hipEvent_t ev[2];
+  BKTS_HIP(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
+  BKTS_HIP(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
+  struct EvGuard {
+    hipEvent_t* e;
+    ~EvGuard() { (void)hipEventDestroy(e[0]); (void)hipEventDestroy(e[1]); }
+  } guard{ev};
+  auto check = [&](int it) -> int {  // 1 = converged, -1 = all directions deflated, 0 = continue
+    const int slot = it & 1;
+    BKTS_HIP(hipEventSynchronize(ev[slot]));
+    double* h = hbuf + slot * (k + 2);
+    nrm.assign(h, h + k);
+    const int nd = *reinterpret_cast<int*>(h + k);
+    st.iterations = it;
+    st.deflations = std::max(st.deflations, nd);
+    if (all_converged(nrm, nrm0, rtol, &st.max_rel)) return 1;
+    return nd >= k ? -1 : 0;
+  };
+  const bool rowk = rk_eligible(k);
   int restarts = 0;
   for (int it = 1; it <= maxit; ++it) {
-    spmm(ctx, op, dtype, k, 0.0, nullptr, k, a, P, k, b, Q, k);
-    inner_gram(ctx, dtype, N, k, P, Q, s.G);
+    if (rowk) {  // Q = a P + b K P with G = P^T Q folded from the same pass
+      rk_spmm_gram(ctx, op, dtype, k, a, P, b, Q, s.G, nullptr);
+    } else {
+      spmm(ctx, op, dtype, k, 0.0, nullptr, k, a, P, k, b, Q, k);
+      inner_gram(ctx, dtype, N, k, P, Q, s.G);
+    }
     small_spd_solve(ctx, k, s.G, s.gamma, 1.0, eps, s.alpha, s.ndefl);
     // X += P alpha, R -= Q alpha and the norms of R (its gamma and T outputs are recomputed below)
     cg_update(ctx, dtype, N, k, X, P, R, Q, s.alpha, nullptr, s.T, s.beta, s.nrm);
-    int nd = 0;
-    read_norms(ctx, s.nrm, k, nrm, s.ndefl, &nd);
-    st.iterations = it;
-    st.deflations = std::max(st.deflations, nd);
-    if (all_converged(nrm, nrm0, rtol, &st.max_rel)) {
+    const int slot = it & 1;
+    BKTS_HIP(hipMemcpyAsync(hbuf + slot * (k + 2), s.nrm, sizeof(double) * (k + 1), hipMemcpyDeviceToHost,
+                            ctx->stream));
+    BKTS_HIP(hipEventRecord(ev[slot], ctx->stream));
+    const int state = it > 1 ? check(it - 1) : 0;
+    if (state == 1) {
+      ctx->sync();  // iteration `it` is in flight; it only improves X
+      st.iterations = it;
       st.converged = 1;
       return;
     }
-    if (nd >= k) {  // every search direction collapsed: restart from the preconditioned residual
+    if (state == -1) {  // every search direction collapsed: restart from the preconditioned residual
       if (++restarts > 3) throw Error{BKTS_EBREAKDOWN, "block CG: search space collapsed repeatedly"};
       precondition();
       continue;
@@ -259,6 +289,10 @@ void block_pcg_mg(bkts_ctx ctx, const bkts_op_s& op, int dtype, int k, double a,
     inner_gram(ctx, dtype, N, k, Q, Z, s.T);
     small_spd_solve(ctx, k, s.G, s.T, -1.0, eps, s.beta, nullptr);
     cg_pupdate(ctx, dtype, N, k, P, Z, s.beta, nullptr);
+  }
+  if (check(maxit) == 1) {
+    st.converged = 1;
+    return;
   }
   st.converged = 0;
 }

@@ -29,10 +29,12 @@ struct MgLevel {
   int n[3];
   int64_t N;
   DevBuf c64, c32;  // 5 arrays of N: dK, m, o_x, o_y, o_z  (o_d[r] = K[r, r + s_d], 0 past the + face)
+  DevBuf di64, di32;  // 1 / (a m + b dK) for the (a, b) of the last V-cycle
 };
 
 struct MgHier {
   std::vector<MgLevel> lv;
+  double a = 0.0, b = 0.0;  // the pair the inverse diagonals hold (0, 0: none yet)
 };
 
 namespace {
@@ -111,6 +113,15 @@ __global__ void mg_coarsen(Geo f, Geo c, const double* cf, double* cc) {
   for (int d = 0; d < 3; ++d) cc[(2 + d) * c.N + R] = o[d];
 }
 
+// di = 1 / (a m + b dK) on one level, FP64 and FP32.
+__global__ void mg_dinv(int64_t N, const double* c, double a, double b, double* d64, float* d32) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= N) return;
+  const double v = 1.0 / (a * c[N + r] + b * c[r]);
+  d64[r] = v;
+  d32[r] = (float)v;
+}
+
 __global__ void mg_to_f32(int64_t n, const double* in, float* out) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) out[i] = (float)in[i];
@@ -119,7 +130,8 @@ __global__ void mg_to_f32(int64_t n, const double* in, float* out) {
 template <typename T>
 struct LvArgs {
   Geo g;
-  const T* c;  // 5 arrays of N
+  const T* c;   // 5 arrays of N
+  const T* di;  // inverse diagonal of A on this level
   T a, b, w;
   int k;
 };
@@ -132,7 +144,7 @@ __device__ __forceinline__ T diagA(const LvArgs<T>& L, int64_t r) {
 // Damped Jacobi from zero: x[r] = w f[r] / dA[r], for the CW columns starting at c0.
 template <typename T, int CW>
 __device__ __forceinline__ void pre_x(const LvArgs<T>& L, const T* f, int64_t r, int c0, T (&x)[CW]) {
-  const T s = L.w / diagA(L, r);
+  const T s = L.w * L.di[r];
 #pragma unroll
   for (int j = 0; j < CW; ++j) x[j] = s * f[r * L.k + c0 + j];
 }
@@ -169,39 +181,46 @@ __device__ __forceinline__ void apply_row(const LvArgs<T>& L, int64_t r, int ix,
   }
 }
 
-// fc = P^T (f - A x) with x = w D^-1 f, one thread per coarse cell.
+// fc = P^T (f - A x) with x = w D^-1 f.  A workgroup covers a strip of 32 coarse cells along x: its
+// 256 threads are the 64 x 2 x 2 fine cells of those aggregates (consecutive threads on consecutive
+// cells of one grid line), each forms its own residual, and the 8 residuals of an aggregate are
+// summed through LDS in a fixed order.  Grid: (ceil(ncx / 32), ncy, ncz).
 template <typename T, int CW>
 __global__ __launch_bounds__(256) void mg_restrict_kernel(LvArgs<T> L, Geo c, const T* __restrict__ f,
                                                           T* __restrict__ fc) {
-  const int64_t R = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (R >= c.N) return;
-  int X, Y, Z;
-  coords(c, R, X, Y, Z);
+  __shared__ T red[CW][256];
+  const int t = threadIdx.x;
+  const int x = t & 63, y = (t >> 6) & 1, z = t >> 7;
+  const int X0 = blockIdx.x * 32, Y = blockIdx.y, Z = blockIdx.z;
   const Geo& g = L.g;
+  const int ix = 2 * X0 + x, iy = 2 * Y + y, iz = 2 * Z + z;
+  const bool in = ix < g.nx && iy < g.ny && iz < g.nz;
+  const int64_t i = in ? ix + g.sy * iy + g.sz * iz : 0;
   for (int c0 = 0; c0 < L.k; c0 += CW) {
-    T acc[CW];
+    T v[CW];
 #pragma unroll
-    for (int j = 0; j < CW; ++j) acc[j] = T(0);
-    for (int dz = 0; dz < 2; ++dz) {
-      const int iz = 2 * Z + dz;
-      if (iz >= g.nz) continue;
-      for (int dy = 0; dy < 2; ++dy) {
-        const int iy = 2 * Y + dy;
-        if (iy >= g.ny) continue;
-        for (int dx = 0; dx < 2; ++dx) {
-          const int ix = 2 * X + dx;
-          if (ix >= g.nx) continue;
-          const int64_t i = ix + g.sy * iy + g.sz * iz;
-          T xi[CW], ax[CW];
-          pre_x<T, CW>(L, f, i, c0, xi);
-          apply_row<T, CW>(L, i, ix, iy, iz, xi, [&](int64_t q, T(&y)[CW]) { pre_x<T, CW>(L, f, q, c0, y); }, ax);
+    for (int j = 0; j < CW; ++j) v[j] = T(0);
+    if (in) {
+      T xi[CW], ax[CW];
+      pre_x<T, CW>(L, f, i, c0, xi);
+      apply_row<T, CW>(L, i, ix, iy, iz, xi, [&](int64_t q, T(&yq)[CW]) { pre_x<T, CW>(L, f, q, c0, yq); }, ax);
 #pragma unroll
-          for (int j = 0; j < CW; ++j) acc[j] += f[i * L.k + c0 + j] - ax[j];
-        }
-      }
+      for (int j = 0; j < CW; ++j) v[j] = f[i * L.k + c0 + j] - ax[j];
     }
 #pragma unroll
-    for (int j = 0; j < CW; ++j) fc[R * L.k + c0 + j] = acc[j];
+    for (int j = 0; j < CW; ++j) red[j][t] = v[j];
+    __syncthreads();
+    if (t < 32 && X0 + t < c.nx) {
+      const int64_t R = (X0 + t) + c.sy * Y + c.sz * Z;
+#pragma unroll
+      for (int j = 0; j < CW; ++j) {
+        T sum = T(0);
+#pragma unroll
+        for (int q = 0; q < 8; ++q) sum += red[j][(2 * t + (q & 1)) + 64 * ((q >> 1) & 1) + 128 * (q >> 2)];
+        fc[R * L.k + c0 + j] = sum;
+      }
+    }
+    __syncthreads();
   }
 }
 
@@ -229,7 +248,7 @@ __global__ __launch_bounds__(256) void mg_prolong_kernel(LvArgs<T> L, Geo c, con
                        ycell(q, qx, qy, qz, c0, y);
                      },
                      ay);
-    const T s = L.w / diagA(L, r);
+    const T s = L.w * L.di[r];
 #pragma unroll
     for (int j = 0; j < CW; ++j) z[r * L.k + c0 + j] = yr[j] + s * (f[r * L.k + c0 + j] - ay[j]);
   }
@@ -242,7 +261,7 @@ __global__ __launch_bounds__(256) void mg_coarse_kernel(LvArgs<T> L, const T* __
   const int64_t n = L.g.N * L.k;
   for (int64_t e = threadIdx.x; e < n; e += blockDim.x) {
     const int64_t r = e / L.k;
-    xs[0][e] = L.w * f[e] / diagA(L, r);
+    xs[0][e] = L.w * f[e] * L.di[r];
   }
   __syncthreads();
   int cur = 0;
@@ -254,7 +273,7 @@ __global__ __launch_bounds__(256) void mg_coarse_kernel(LvArgs<T> L, const T* __
       coords(L.g, r, ix, iy, iz);
       T yr[1] = {xs[cur][e]}, ay[1];
       apply_row<T, 1>(L, r, ix, iy, iz, yr, [&](int64_t q, T(&y)[1]) { y[0] = xs[cur][q * L.k + col]; }, ay);
-      xs[cur ^ 1][e] = yr[0] + L.w * (f[e] - ay[0]) / diagA(L, r);
+      xs[cur ^ 1][e] = yr[0] + L.w * (f[e] - ay[0]) * L.di[r];
     }
     __syncthreads();
     cur ^= 1;
@@ -268,10 +287,13 @@ template <typename T>
 LvArgs<T> lv_args(const MgLevel& l, int k, double a, double b) {
   LvArgs<T> L;
   L.g = geo_of(l);
-  if constexpr (sizeof(T) == 8)
+  if constexpr (sizeof(T) == 8) {
     L.c = l.c64.as<double>();
-  else
+    L.di = l.di64.as<double>();
+  } else {
     L.c = l.c32.as<float>();
+    L.di = l.di32.as<float>();
+  }
   L.a = (T)a;
   L.b = (T)b;
   L.w = (T)kOmega;
@@ -283,7 +305,9 @@ template <typename T>
 void vcycle(bkts_ctx ctx, const MgHier& h, int lvl, int k, double a, double b, const T* f, T* z) {
   const MgLevel& l = h.lv[lvl];
   const LvArgs<T> L = lv_args<T>(l, k, a, b);
+  const double sv = sizeof(T);
   if (lvl + 1 == (int)h.lv.size()) {
+    ProfScope prof(ctx, BKTS_K_SMALL, sv * (2.0 * l.N * k + 5.0 * l.N));
     launch(ctx, (mg_coarse_kernel<T>), dim3(1), dim3(256), 0, L, f, z);
     return;
   }
@@ -293,14 +317,20 @@ void vcycle(bkts_ctx ctx, const MgHier& h, int lvl, int k, double a, double b, c
   T* fc = ctx->ws.get<T>("mg_f" + tag, (size_t)lc.N * k);
   T* xc = ctx->ws.get<T>("mg_x" + tag, (size_t)lc.N * k);
   const int cw = chunk_width(k);
-  const dim3 gr((unsigned)((lc.N + 255) / 256)), gp((unsigned)((l.N + 255) / 256));
-  if (cw == 4)
-    launch(ctx, (mg_restrict_kernel<T, 4>), gr, dim3(256), 0, L, gc, f, fc);
-  else if (cw == 2)
-    launch(ctx, (mg_restrict_kernel<T, 2>), gr, dim3(256), 0, L, gc, f, fc);
-  else
-    launch(ctx, (mg_restrict_kernel<T, 1>), gr, dim3(256), 0, L, gc, f, fc);
+  const dim3 gr((unsigned)((lc.n[0] + 31) / 32), (unsigned)lc.n[1], (unsigned)lc.n[2]);
+  const dim3 gp((unsigned)((l.N + 255) / 256));
+  {  // algorithmic bytes: f and the 5 coefficient arrays of this level read, the coarse f written
+    ProfScope prof(ctx, BKTS_K_MG_RESTRICT, sv * (1.0 * l.N * k + 5.0 * l.N + 1.0 * lc.N * k));
+    if (cw == 4)
+      launch(ctx, (mg_restrict_kernel<T, 4>), gr, dim3(256), 0, L, gc, f, fc);
+    else if (cw == 2)
+      launch(ctx, (mg_restrict_kernel<T, 2>), gr, dim3(256), 0, L, gc, f, fc);
+    else
+      launch(ctx, (mg_restrict_kernel<T, 1>), gr, dim3(256), 0, L, gc, f, fc);
+  }
   vcycle<T>(ctx, h, lvl + 1, k, a, b, fc, xc);
+  // algorithmic bytes: f, the coarse x and the 5 coefficient arrays read, z written
+  ProfScope prof(ctx, BKTS_K_MG_PROLONG, sv * (2.0 * l.N * k + 5.0 * l.N + 1.0 * lc.N * k));
   if (cw == 4)
     launch(ctx, (mg_prolong_kernel<T, 4>), gp, dim3(256), 0, L, gc, f, (const T*)xc, z);
   else if (cw == 2)
@@ -338,6 +368,7 @@ static MgHier* mg_build(bkts_op op) {
     const MgLevel& f = h->lv.back();
     MgLevel c;
     for (int d = 0; d < 3; ++d) c.n[d] = (f.n[d] + 1) / 2;
+    BKTS_REQUIRE(c.n[1] <= 65535 && c.n[2] <= 65535, "multigrid: grid too tall for the restriction launch");
     c.N = (int64_t)c.n[0] * c.n[1] * c.n[2];
     c.c64.alloc(sizeof(double) * 5 * c.N);
     c.c32.alloc(sizeof(float) * 5 * c.N);
@@ -345,9 +376,12 @@ static MgHier* mg_build(bkts_op op) {
            f.c64.as<double>(), c.c64.as<double>());
     h->lv.push_back(std::move(c));
   }
-  for (auto& l : h->lv)
+  for (auto& l : h->lv) {
     launch(ctx, mg_to_f32, dim3((unsigned)((5 * l.N + 255) / 256)), dim3(256), 0, 5 * l.N, l.c64.as<double>(),
            l.c32.as<float>());
+    l.di64.alloc(sizeof(double) * l.N);
+    l.di32.alloc(sizeof(float) * l.N);
+  }
   BKTS_HIP(hipGetLastError());
   ctx->sync();
   BKTS_REQUIRE(h->lv.back().N <= kCoarsestMax, "multigrid: coarsest level too large");
@@ -357,6 +391,14 @@ static MgHier* mg_build(bkts_op op) {
 void mg_vcycle(bkts_ctx ctx, const bkts_op_s& op, int dtype, int k, double a, double b, const void* F, void* Z) {
   BKTS_REQUIRE(k >= 1 && k <= BKTS_MAX_K, "k out of range");
   if (!op.mg) op.mg.reset(mg_build(const_cast<bkts_op>(&op)), mg_hier_delete);
+  MgHier& h = *op.mg;
+  if (h.a != a || h.b != b) {  // inverse diagonals of every level for this (a, b)
+    for (auto& l : h.lv)
+      launch(ctx, mg_dinv, dim3((unsigned)((l.N + 255) / 256)), dim3(256), 0, l.N, l.c64.as<double>(), a, b,
+             l.di64.as<double>(), l.di32.as<float>());
+    h.a = a;
+    h.b = b;
+  }
   if (dtype == BKTS_F64)
     vcycle<double>(ctx, *op.mg, 0, k, a, b, static_cast<const double*>(F), static_cast<double*>(Z));
   else
