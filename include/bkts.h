@@ -95,9 +95,10 @@ enum {
   BKTS_K_SMALL = 6,      /* k x k device kernels and partial-sum folding      */
   BKTS_K_CAST = 7,       /* precision casts / strided copies                  */
   BKTS_K_OTHER = 8,      /* vector helpers of the time-stepping loop          */
-  BKTS_K_MG_RESTRICT = 9,  /* multigrid: smoothed residual restricted (all levels) */
-  BKTS_K_MG_PROLONG = 10,  /* multigrid: prolongation and post-sweep (all levels)  */
-  BKTS_K_COUNT = 11
+  BKTS_K_MG_RESTRICT = 9,  /* multigrid, finest level: smoothed residual restricted */
+  BKTS_K_MG_PROLONG = 10,  /* multigrid, finest level: prolongation and post-sweep  */
+  BKTS_K_MG_COARSE = 11,   /* multigrid: every coarser level and the coarsest solve */
+  BKTS_K_COUNT = 12
 };
 bkts_status bkts_profile_enable(bkts_ctx ctx, int enable);
 bkts_status bkts_profile_query(bkts_ctx ctx, int kernel, int64_t* launches, double* total_ms,

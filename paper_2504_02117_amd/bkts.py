@@ -32,7 +32,7 @@ BKTS_CG, BKTS_GMRES, BKTS_BICGSTAB = 0, 1, 2
 BKTS_PREC_NONE, BKTS_PREC_JACOBI, BKTS_PREC_MG = 0, 1, 2
 BKTS_PRECISION_F64, BKTS_PRECISION_F32_REFINE = 0, 1
 KERNELS = ("spmm", "gram", "norms", "cg_update", "cg_pupdate", "residual", "small", "cast", "other", "mg_restrict",
-           "mg_prolong")
+           "mg_prolong", "mg_coarse")
 
 _STATUS_NAMES = {0: "BKTS_OK", -1: "BKTS_EINVAL", -2: "BKTS_ENOMEM", -3: "BKTS_EDEVICE",
                  -4: "BKTS_EBREAKDOWN", -5: "BKTS_ENOCONV", -6: "BKTS_EBUSY"}

@@ -319,6 +319,9 @@ void rk_cg_update(bkts_ctx ctx, int dtype, int64_t N, int k, void* X, const void
 void rk_cg_pupdate(bkts_ctx ctx, int dtype, int64_t N, int k, void* P, const void* R, const double* beta,
                    const double* dinv);
 void rk_gram(bkts_ctx ctx, int dtype, int64_t N, int k, const void* X, const void* Y, double* G);
+// G1 = X1^T Y and G2 = X2^T Y in one pass (k in {1, 2, 4}, contiguous blocks)
+void rk_gram2(bkts_ctx ctx, int dtype, int64_t N, int k, const void* X1, const void* X2, const void* Y, double* G1,
+              double* G2);
 void rk_rmul(bkts_ctx ctx, int dtype, int64_t N, int k, const void* X, const double* C, double c0, double c1,
              void* Y);
 

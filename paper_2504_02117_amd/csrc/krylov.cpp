@@ -285,8 +285,12 @@ void block_pcg_mg(bkts_ctx ctx, const bkts_op_s& op, int dtype, int k, double a,
     }
     restarts = 0;
     mg_vcycle(ctx, op, dtype, k, a, b, R, Z);
-    inner_gram(ctx, dtype, N, k, R, Z, s.gamma);
-    inner_gram(ctx, dtype, N, k, Q, Z, s.T);
+    if (rowk) {
+      rk_gram2(ctx, dtype, N, k, R, Q, Z, s.gamma, s.T);  // gamma = R^T Z and T = Q^T Z in one pass
+    } else {
+      inner_gram(ctx, dtype, N, k, R, Z, s.gamma);
+      inner_gram(ctx, dtype, N, k, Q, Z, s.T);
+    }
     small_spd_solve(ctx, k, s.G, s.T, -1.0, eps, s.beta, nullptr);
     cg_pupdate(ctx, dtype, N, k, P, Z, s.beta, nullptr);
   }

@@ -136,11 +136,6 @@ struct LvArgs {
   int k;
 };
 
-template <typename T>
-__device__ __forceinline__ T diagA(const LvArgs<T>& L, int64_t r) {
-  return L.a * L.c[L.g.N + r] + L.b * L.c[r];
-}
-
 // Damped Jacobi from zero: x[r] = w f[r] / dA[r], for the CW columns starting at c0.
 template <typename T, int CW>
 __device__ __forceinline__ void pre_x(const LvArgs<T>& L, const T* f, int64_t r, int c0, T (&x)[CW]) {
@@ -155,7 +150,7 @@ __device__ __forceinline__ void apply_row(const LvArgs<T>& L, int64_t r, int ix,
                                           Y ycell, T (&out)[CW]) {
   const Geo& g = L.g;
   const int64_t N = g.N;
-  const T dA = diagA(L, r);
+  const T dA = T(1) / L.di[r];  // the diagonal from its cached inverse: no dK or mass read
 #pragma unroll
   for (int j = 0; j < CW; ++j) out[j] = dA * yr[j];
   const int pos[3] = {ix, iy, iz};
@@ -307,7 +302,7 @@ void vcycle(bkts_ctx ctx, const MgHier& h, int lvl, int k, double a, double b, c
   const LvArgs<T> L = lv_args<T>(l, k, a, b);
   const double sv = sizeof(T);
   if (lvl + 1 == (int)h.lv.size()) {
-    ProfScope prof(ctx, BKTS_K_SMALL, sv * (2.0 * l.N * k + 5.0 * l.N));
+    ProfScope prof(ctx, BKTS_K_MG_COARSE, sv * (2.0 * l.N * k + 4.0 * l.N));
     launch(ctx, (mg_coarse_kernel<T>), dim3(1), dim3(256), 0, L, f, z);
     return;
   }
@@ -319,8 +314,9 @@ void vcycle(bkts_ctx ctx, const MgHier& h, int lvl, int k, double a, double b, c
   const int cw = chunk_width(k);
   const dim3 gr((unsigned)((lc.n[0] + 31) / 32), (unsigned)lc.n[1], (unsigned)lc.n[2]);
   const dim3 gp((unsigned)((l.N + 255) / 256));
-  {  // algorithmic bytes: f and the 5 coefficient arrays of this level read, the coarse f written
-    ProfScope prof(ctx, BKTS_K_MG_RESTRICT, sv * (1.0 * l.N * k + 5.0 * l.N + 1.0 * lc.N * k));
+  {  // algorithmic bytes: f, the inverse diagonal and the 3 coupling arrays read, the coarse f written
+    ProfScope prof(ctx, lvl == 0 ? BKTS_K_MG_RESTRICT : BKTS_K_MG_COARSE,
+                   sv * (1.0 * l.N * k + 4.0 * l.N + 1.0 * lc.N * k));
     if (cw == 4)
       launch(ctx, (mg_restrict_kernel<T, 4>), gr, dim3(256), 0, L, gc, f, fc);
     else if (cw == 2)
@@ -329,8 +325,9 @@ void vcycle(bkts_ctx ctx, const MgHier& h, int lvl, int k, double a, double b, c
       launch(ctx, (mg_restrict_kernel<T, 1>), gr, dim3(256), 0, L, gc, f, fc);
   }
   vcycle<T>(ctx, h, lvl + 1, k, a, b, fc, xc);
-  // algorithmic bytes: f, the coarse x and the 5 coefficient arrays read, z written
-  ProfScope prof(ctx, BKTS_K_MG_PROLONG, sv * (2.0 * l.N * k + 5.0 * l.N + 1.0 * lc.N * k));
+  // algorithmic bytes: f, the coarse x, the inverse diagonal and the 3 coupling arrays read, z written
+  ProfScope prof(ctx, lvl == 0 ? BKTS_K_MG_PROLONG : BKTS_K_MG_COARSE,
+                 sv * (2.0 * l.N * k + 4.0 * l.N + 1.0 * lc.N * k));
   if (cw == 4)
     launch(ctx, (mg_prolong_kernel<T, 4>), gp, dim3(256), 0, L, gc, f, (const T*)xc, z);
   else if (cw == 2)

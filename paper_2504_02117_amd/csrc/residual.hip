@@ -158,6 +158,90 @@ __global__ __launch_bounds__(256) void residual_kernel(ResArgs a) {
   dev::block_reduce_store<KP, 1>(nacc, lds, a.partials, gridDim.x, slot);
 }
 
+// Stencil form, k <= 4: one thread per row holds the whole row of Y, of K Y and of R in registers
+// (no LDS staging); A1 and A2 sit in registers; the column norms are folded per workgroup.
+template <int KP>
+__global__ __launch_bounds__(256) void st_residual_row_kernel(ResArgs a) {
+  __shared__ double red[4 * KP];
+  double a1[KP][KP], a2[KP][KP], rs[KP];
+  int b0[KP];
+#pragma unroll
+  for (int c = 0; c < KP; ++c) {
+#pragma unroll
+    for (int j = 0; j < KP; ++j) {
+      a1[c][j] = a.A1[c * KP + j];
+      a2[c][j] = a.A2[c * KP + j];
+    }
+    rs[c] = a.b ? a.rs[c] : 0.0;
+    b0[c] = -1;
+    for (int j = 0; j < a.nb0; ++j)
+      if (a.b0col[j] == c) b0[c] = j;
+  }
+  double nacc[KP];
+#pragma unroll
+  for (int c = 0; c < KP; ++c) nacc[c] = 0.0;
+  const int64_t N = a.N;
+  for (int64_t r = (int64_t)blockIdx.x * dev::kThreads + threadIdx.x; r < N; r += (int64_t)gridDim.x * dev::kThreads) {
+    double y[KP], up[3], lo[3], yu[3][KP], yl[3][KP];
+#pragma unroll
+    for (int j = 0; j < KP; ++j) y[j] = a.Y[r * a.ldy + j];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      up[q] = lo[q] = 0.0;
+#pragma unroll
+      for (int j = 0; j < KP; ++j) yu[q][j] = yl[q][j] = 0.0;
+      if (q < a.na) {
+        const int64_t s = a.soff[q];
+        const double* oq = a.coef + (1 + q) * N;
+        if (r + s < N) {
+          up[q] = oq[r];
+#pragma unroll
+          for (int j = 0; j < KP; ++j) yu[q][j] = a.Y[(r + s) * a.ldy + j];
+        }
+        if (r - s >= 0) {
+          lo[q] = oq[r - s];
+#pragma unroll
+          for (int j = 0; j < KP; ++j) yl[q][j] = a.Y[(r - s) * a.ldy + j];
+        }
+      }
+    }
+    const double dg = a.coef[r];
+    double ky[KP];
+#pragma unroll
+    for (int j = 0; j < KP; ++j) {
+      double v = dg * y[j];
+#pragma unroll
+      for (int q = 0; q < 3; ++q) v = fma(up[q], yu[q][j], fma(lo[q], yl[q][j], v));
+      ky[j] = v;
+    }
+    const double bv = a.b ? a.b[r] : 0.0;
+#pragma unroll
+    for (int c = 0; c < KP; ++c) {
+      double v = 0.0;
+#pragma unroll
+      for (int j = 0; j < KP; ++j) v = fma(y[j], a1[c][j], fma(ky[j], a2[c][j], v));
+      if (a.b) v -= bv * rs[c];
+      if (b0[c] >= 0) v -= a.B0[r * a.ldb0 + b0[c]];
+      a.R[r * a.ldr + c] = v;
+      nacc[c] = fma(v, v, nacc[c]);
+    }
+  }
+  // fixed-order fold: lanes of a wavefront, then the 4 wavefronts
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1)
+#pragma unroll
+    for (int c = 0; c < KP; ++c) nacc[c] += __shfl_xor(nacc[c], off);
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  if (l == 0) {
+#pragma unroll
+    for (int c = 0; c < KP; ++c) red[w * KP + c] = nacc[c];
+  }
+  __syncthreads();
+  if (threadIdx.x < KP)
+    a.partials[(int64_t)threadIdx.x * gridDim.x + blockIdx.x] =
+        ((red[threadIdx.x] + red[KP + threadIdx.x]) + red[2 * KP + threadIdx.x]) + red[3 * KP + threadIdx.x];
+}
+
 template <int KP>
 void launch_res(bkts_ctx ctx, const bkts_op_s& op, ResArgs a, double* nrm) {
   using G = TileGeom<KP>;
@@ -169,7 +253,15 @@ void launch_res(bkts_ctx ctx, const bkts_op_s& op, ResArgs a, double* nrm) {
   a.partials = ctx->ws.get<double>("res_partials", (size_t)KP * ns);
   const double mat = op.st_na > 0 ? 8.0 * (1 + op.st_na) * op.N : op.nnz * 12.0 + 4.0 * (op.N + 1);
   ProfScope prof(ctx, BKTS_K_RESIDUAL, mat + 16.0 * op.N * a.k + (a.b ? 8.0 * op.N : 0.0) + 8.0 * op.N * a.nb0);
-  if (op.st_na > 0)
+  if (op.st_na > 0 && KP <= 4 && a.k == KP) {
+    int64_t nr = (a.N + 255) / 256;
+    const int64_t rcap = 4 * (int64_t)ctx->num_cu;
+    if (nr > rcap) nr = rcap;
+    if (nr < 1) nr = 1;
+    a.partials = ctx->ws.get<double>("res_partials", (size_t)KP * nr);
+    launch(ctx, (st_residual_row_kernel<KP>), dim3(nr), dim3(256), 0, a);
+    ns = nr;
+  } else if (op.st_na > 0)
     launch(ctx, (residual_kernel<KP, 2>), dim3(ns), dim3(256), 0, a);
   else if (op.format == BKTS_FMT_SELL)
     launch(ctx, (residual_kernel<KP, 1>), dim3(ns), dim3(256), 0, a);

@@ -379,6 +379,45 @@ __global__ __launch_bounds__(256) void rk_gram_kernel(int64_t N, const T* __rest
   fold_block<KP * KP>(g, red, partials);
 }
 
+// G1 = X1^T Y and G2 = X2^T Y in one pass over the three blocks (two rows per thread per step)
+template <typename T, int KP>
+__global__ __launch_bounds__(256) void rk_gram2_kernel(int64_t N, const T* __restrict__ X1, const T* __restrict__ X2,
+                                                       const T* __restrict__ Y, double* partials) {
+  constexpr int NA = 2 * KP * KP;
+  constexpr int GR = 2;
+  __shared__ double red[4 * NA];
+  double g[NA];
+#pragma unroll
+  for (int e = 0; e < NA; ++e) g[e] = 0.0;
+  const RowRange rr = block_rows(N);
+  for (int64_t r0 = rr.begin + threadIdx.x; r0 < rr.end; r0 += GR * dev::kThreads) {
+    Row<T, KP> a[GR], b[GR], y[GR];
+    bool ok[GR];
+#pragma unroll
+    for (int h = 0; h < GR; ++h) {
+      const int64_t r = r0 + h * dev::kThreads;
+      ok[h] = r < rr.end;
+      if (ok[h]) {
+        a[h] = ld_row<T, KP>(X1 + r * KP, KP);
+        b[h] = ld_row<T, KP>(X2 + r * KP, KP);
+        y[h] = ld_row<T, KP>(Y + r * KP, KP);
+      }
+    }
+#pragma unroll
+    for (int h = 0; h < GR; ++h) {
+      if (!ok[h]) continue;
+#pragma unroll
+      for (int i = 0; i < KP; ++i)
+#pragma unroll
+        for (int j = 0; j < KP; ++j) {
+          g[i * KP + j] = fma((double)a[h].v[i], (double)y[h].v[j], g[i * KP + j]);
+          g[KP * KP + i * KP + j] = fma((double)b[h].v[i], (double)y[h].v[j], g[KP * KP + i * KP + j]);
+        }
+    }
+  }
+  fold_block<NA>(g, red, partials);
+}
+
 // Y = c0 Y + c1 X C (contiguous blocks)
 template <typename T, int KP>
 __global__ __launch_bounds__(256) void rk_rmul_kernel(int64_t N, const T* __restrict__ X, const double* Cm, double c0,
@@ -553,6 +592,28 @@ static void rk_gram_t(bkts_ctx ctx, int64_t N, const void* X, const void* Y, dou
   BKTS_HIP(hipGetLastError());
   prof.end();
   finalize_gram(ctx, part, (int)nb, KP, KP, G);
+}
+
+template <typename T, int KP>
+static void rk_gram2_t(bkts_ctx ctx, int64_t N, const void* X1, const void* X2, const void* Y, double* G1,
+                       double* G2) {
+  const int64_t nb = rk_grid(ctx, rk_gram2_kernel<T, KP>, N);
+  double* part = ctx->ws.get<double>("rk_gram2_part", (size_t)2 * KP * KP * nb);
+  ProfScope prof(ctx, BKTS_K_GRAM, 3.0 * N * KP * sizeof(T));
+  launch(ctx, (rk_gram2_kernel<T, KP>), dim3(nb), dim3(256), 0, N, static_cast<const T*>(X1),
+         static_cast<const T*>(X2), static_cast<const T*>(Y), part);
+  BKTS_HIP(hipGetLastError());
+  prof.end();
+  const FoldSet sets[2] = {{part, KP, 0, G1}, {part + (size_t)KP * KP * nb, KP, 0, G2}};
+  finalize_sets(ctx, (int)nb, KP, sets, 2);
+}
+
+void rk_gram2(bkts_ctx ctx, int dtype, int64_t N, int k, const void* X1, const void* X2, const void* Y, double* G1,
+              double* G2) {
+  if (dtype == BKTS_F64)
+    BKTS_RK_DISPATCH(k, (rk_gram2_t<double, KP>(ctx, N, X1, X2, Y, G1, G2)));
+  else
+    BKTS_RK_DISPATCH(k, (rk_gram2_t<float, KP>(ctx, N, X1, X2, Y, G1, G2)));
 }
 
 void rk_gram(bkts_ctx ctx, int dtype, int64_t N, int k, const void* X, const void* Y, double* G) {

@@ -234,3 +234,42 @@ def test_stencil_full_size_128cubed_sampled(env):
             del Xd, Yd
     finally:
         bkts.bkts_op_destroy(op)
+
+
+@pytest.mark.parametrize("method,name", [(0, "ie"), (2, "sdirk2"), (4, "radau2")])
+@pytest.mark.parametrize("k", [1, 2, 4, 6])
+def test_stencil_residual_matches_oracle(env, method, name, k):
+    """The fused all-at-once residual on the stencil form (row-per-thread kernel for k <= 4, the tiled
+    kernel above), with a nonzero source and B0 columns, every phase, against the oracle."""
+    from oracle import allatonce as aao
+    from oracle import timecoupling as otc
+    torch, bkts, ctx = env
+    if name == "radau2" and k % 2:
+        pytest.skip("Radau IIA windows hold whole steps")
+    n = (11, 9, 7)
+    op, K, b = stencil_op(env, n, inputs.lognormal_field(n, 0.0, 1.0, 2.0, 2), {(0, 0): ("dirichlet", 1.0)})
+    tau = 0.01
+    tc = bkts.bkts_tc_create(ctx, method, k, tau)
+    try:
+        N = K.shape[0]
+        A, _, c = otc.tableau(name)
+        mi = otc.implicit_part(A, c)[0].shape[0]
+        phases = [0] if name == "radau2" else range(mi)
+        for phase in phases:
+            Y = inputs.random_block(N, k, 20 + phase)
+            nb0 = min(mi - phase, k)
+            B0 = inputs.random_block(N, nb0, 30 + phase)
+            R = torch.empty((N, k), dtype=torch.float64, device="cuda")
+            norms = bkts.bkts_residual(ctx, op, tc, torch.from_numpy(Y).cuda(), R, B0=torch.from_numpy(B0).cuda(),
+                                       phase=phase)
+            A1, A2, _ = otc.window_matrices(A, c, k, phase, tau)
+            B0full = np.zeros((N, k))
+            B0full[:, :nb0] = B0
+            ref = aao.residual_linear(sp.identity(N), K, A1, A2, Y, np.tile(b[:, None], (1, k)), B0full)
+            got = R.cpu().numpy()
+            scale = (abs(K).sum(1).A.ravel()[:, None] + 2 / tau) * 4
+            assert (abs(got - ref) / scale).max() < 1e-13
+            np.testing.assert_allclose(norms, (ref ** 2).sum(0), rtol=1e-11)
+    finally:
+        bkts.bkts_tc_destroy(tc)
+        bkts.bkts_op_destroy(op)
