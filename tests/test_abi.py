@@ -136,3 +136,22 @@ def test_fully_implicit_time_coupling_matches_oracle(k):
             assert beta == pytest.approx(otc.averaged_beta(A), rel=1e-14)
         finally:
             bkts.bkts_tc_destroy(tc)
+
+
+def test_binding_constants_match_header():
+    """Every enum constant the binding names has the header's value, and the profiling categories
+    cover every kernel id the header declares."""
+    import re
+    from pathlib import Path
+    from paper_2504_02117_amd import bkts
+    hdr = (Path(__file__).resolve().parents[1] / "include" / "bkts.h").read_text()
+    vals = {m.group(1): int(m.group(2)) for m in re.finditer(r"\b(BKTS_[A-Z0-9_]+)\s*=\s*(-?\d+)", hdr)}
+    checked = 0
+    for name, v in vars(bkts).items():
+        if name.startswith("BKTS_") and isinstance(v, int) and name in vals:
+            assert v == vals[name], name
+            checked += 1
+    assert checked >= 20
+    for name in ("BKTS_FMT_STENCIL", "BKTS_PREC_MG", "BKTS_RADAU2"):
+        assert getattr(bkts, name) == vals[name]
+    assert len(bkts.KERNELS) == vals["BKTS_K_COUNT"]
