@@ -134,9 +134,12 @@ typedef struct bkts_fv_coeffs {
  * as above, every off-diagonal entry sits at an offset s in {1, n0, n0*n1}, and
  * a symmetric K is stored as its diagonal plus one array per offset,
  * o_s[r] = K[r][r+s] = K[r+s][r] ((1 + dim) N values against nnz values and
- * nnz indices).  SELL is kept beside it for the fused residual.  The stencil
- * format needs a symmetric operator: BKTS_EINVAL when a velocity is nonzero
- * (upwind convection).  bkts_op_create_csr rejects it (no grid). */
+ * nnz indices).  The block operator, the fused SpMM + Gram of block CG and the
+ * fused residual read it; CSR and SELL are kept beside it for export and for
+ * the kernels without a stencil variant.  The stencil format needs a symmetric
+ * operator: BKTS_EINVAL when a velocity is nonzero (upwind convection).
+ * bkts_op_create_csr rejects it (no grid).  It is also what the multigrid
+ * preconditioner (BKTS_PREC_MG) is built from. */
 bkts_status bkts_fv_assemble(bkts_ctx ctx, const bkts_grid* grid, const bkts_fv_coeffs* coeffs,
                              int format, bkts_op* out);
 
