@@ -160,6 +160,18 @@ void bkts_op_destroy(bkts_op op);
 bkts_status bkts_spmm(bkts_ctx ctx, bkts_op op, int dtype, int k, double alpha, double beta,
                       const void* X, int ldx, void* Y, int ldy);
 
+/* One multigrid V-cycle Z = B F for A = a I + b K, the preconditioner BKTS_PREC_MG
+ * applies in every block-CG iteration (Sec. 4.1 preconditions the inner solves
+ * with AMG; this is a geometric counterpart).  Galerkin 2x2x2 aggregation of the
+ * stencil form of K (and of the identity mass), one damped Jacobi sweep (w = 0.8)
+ * before the restriction and one after the prolongation, 24 sweeps on the coarsest
+ * level (at most 64 cells).  B is symmetric positive definite.  F, Z: device N x k
+ * blocks of type `dtype`, contiguous (ldf = ldz = k), not overlapping.  The op must
+ * carry the stencil form (BKTS_FMT_STENCIL), else BKTS_EINVAL; the hierarchy is
+ * built on first use and kept with the op. */
+bkts_status bkts_mg_apply(bkts_ctx ctx, bkts_op op, int dtype, int k, double a, double b, const void* F,
+                          int ldf, void* Z, int ldz);
+
 /* Gram matrix G = X^T Y (k x k, row-major, FP64, DEVICE pointer) of two N x k
  * blocks of type `dtype`, accumulated in FP64 in a fixed order (bitwise
  * reproducible). */

@@ -123,6 +123,7 @@ _SIGS = {
     "bkts_op_destroy": (None, [_P]),
     "bkts_spmm": (_I, [_P, _P, _I, _I, _D, _D, _P, _I, _P, _I]),
     "bkts_gram": (_I, [_P, _I, _I64, _I, _P, _I, _P, _I, _P]),
+    "bkts_mg_apply": (_I, [_P, _P, _I, _I, _D, _D, _P, _I, _P, _I]),
     "bkts_tc_create": (_I, [_P, C.POINTER(bkts_tc_desc), C.POINTER(_P)]),
     "bkts_tc_get": (_I, [_P, _I, _P, _P, C.POINTER(_D), C.POINTER(_I), C.POINTER(_I)]),
     "bkts_tc_destroy": (None, [_P]),
@@ -276,6 +277,12 @@ def bkts_gram(ctx, X, Y, G):
     """G (k x k float64 device tensor) = X^T Y."""
     N, k = X.shape
     _check(_lib.bkts_gram(ctx, _dtype_code(X), N, k, _ptr(X), X.stride(0), _ptr(Y), Y.stride(0), _ptr(G)))
+
+
+def bkts_mg_apply(ctx, op, F, Z, a, b):
+    """Z = one multigrid V-cycle applied to F (contiguous N x k device tensors) for a I + b K."""
+    N, k = F.shape
+    _check(_lib.bkts_mg_apply(ctx, op, _dtype_code(F), k, a, b, _ptr(F), F.stride(0), _ptr(Z), Z.stride(0)))
 
 
 def bkts_tc_create(ctx, method, k, tau, theta=0.5, A=None, c=None):

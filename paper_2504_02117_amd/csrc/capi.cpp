@@ -159,6 +159,25 @@ bkts_status bkts_spmm(bkts_ctx ctx, bkts_op op, int dtype, int k, double alpha, 
   BKTS_API_END
 }
 
+bkts_status bkts_mg_apply(bkts_ctx ctx, bkts_op op, int dtype, int k, double a, double b, const void* F, int ldf,
+                          void* Z, int ldz) {
+  BKTS_API_BEGIN
+  check_ctx(ctx);
+  BKTS_REQUIRE(op && op->ctx == ctx, "op must belong to ctx");
+  BKTS_REQUIRE(dtype == BKTS_F64 || dtype == BKTS_F32, "dtype must be BKTS_F64 or BKTS_F32");
+  check_k(k);
+  BKTS_REQUIRE(F && Z, "F and Z must not be NULL");
+  BKTS_REQUIRE(ldf == k && ldz == k, "F and Z must be contiguous (ld == k)");
+  const size_t bytes = (size_t)op->N * k * (dtype == BKTS_F64 ? 8 : 4);
+  const char* f = static_cast<const char*>(F);
+  const char* z = static_cast<const char*>(Z);
+  BKTS_REQUIRE(f + bytes <= z || z + bytes <= f, "F and Z must not overlap");
+  BKTS_REQUIRE(std::isfinite(a) && std::isfinite(b) && a >= 0.0 && b > 0.0, "need a >= 0 and b > 0");
+  set_device(ctx);
+  if (op->N > 0) bkts::mg_vcycle(ctx, *op, dtype, k, a, b, F, Z);
+  BKTS_API_END
+}
+
 bkts_status bkts_gram(bkts_ctx ctx, int dtype, int64_t N, int k, const void* X, int ldx, const void* Y, int ldy,
                       double* G) {
   BKTS_API_BEGIN
