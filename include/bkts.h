@@ -164,7 +164,7 @@ bkts_status bkts_spmm(bkts_ctx ctx, bkts_op op, int dtype, int k, double alpha, 
  * applies in every block-CG iteration (Sec. 4.1 preconditions the inner solves
  * with AMG; this is a geometric counterpart).  Galerkin 2x2x2 aggregation of the
  * stencil form of K (and of the identity mass), one damped Jacobi sweep (w = 0.8)
- * before the restriction and one after the prolongation, 24 sweeps on the coarsest
+ * before the restriction and one after the prolongation, 12 sweeps on the coarsest
  * level (at most 64 cells).  B is symmetric positive definite.  F, Z: device N x k
  * blocks of type `dtype`, contiguous (ldf = ldz = k), not overlapping.  The op must
  * carry the stencil form (BKTS_FMT_STENCIL), else BKTS_EINVAL; the hierarchy is

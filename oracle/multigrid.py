@@ -10,7 +10,7 @@ scipy sparse matrices, so that one application can be compared entry by entry:
   prolongation ``P_l`` (``P[i, I] = 1`` when fine cell i lies in aggregate I) the coarse operators are
   the Galerkin products ``K_{l+1} = P^T K_l P`` and ``M_{l+1} = P^T M_l P``;
 * coarsening stops once a level has at most 64 cells (or after 16 levels);
-* ``V(l, f)``: on the coarsest level, 24 damped Jacobi sweeps from zero; otherwise
+* ``V(l, f)``: on the coarsest level, 12 damped Jacobi sweeps from zero; otherwise
   ``x = w D^-1 f``, ``x_c = V(l+1, P^T (f - A x))``, ``z = x + P x_c``, ``z += w D^-1 (f - A z)``,
   with ``D = diag(A_l)`` and ``w = 0.8``.
 
@@ -25,7 +25,7 @@ import scipy.sparse as sp
 
 OMEGA = 0.8
 COARSEST_MAX = 64
-COARSE_SWEEPS = 24
+COARSE_SWEEPS = 12
 MAX_LEVELS = 16
 
 

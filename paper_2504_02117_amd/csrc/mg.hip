@@ -40,7 +40,7 @@ struct MgHier {
 namespace {
 
 constexpr int kCoarsestMax = 64;  // cells of the coarsest level
-constexpr int kCoarseSweeps = 24;
+constexpr int kCoarseSweeps = 12;
 constexpr double kOmega = 0.8;
 
 struct Geo {
