@@ -256,20 +256,22 @@ void block_pcg_mg(bkts_ctx ctx, const bkts_op_s& op, int dtype, int k, double a,
     return nd >= k ? -1 : 0;
   };
   const bool rowk = rk_eligible(k);
+  // the norms and the deflation count are written straight into the pinned buffer (no copy launch)
+  double* hbuf_dev = nullptr;
+  BKTS_HIP(hipHostGetDevicePointer(reinterpret_cast<void**>(&hbuf_dev), hbuf, 0));
   int restarts = 0;
   for (int it = 1; it <= maxit; ++it) {
+    const int slot = it & 1;
+    double* hn = hbuf_dev + slot * (k + 2);
     if (rowk) {  // Q = a P + b K P with G = P^T Q folded from the same pass
       rk_spmm_gram(ctx, op, dtype, k, a, P, b, Q, s.G, nullptr);
     } else {
       spmm(ctx, op, dtype, k, 0.0, nullptr, k, a, P, k, b, Q, k);
       inner_gram(ctx, dtype, N, k, P, Q, s.G);
     }
-    small_spd_solve(ctx, k, s.G, s.gamma, 1.0, eps, s.alpha, s.ndefl);
+    small_spd_solve(ctx, k, s.G, s.gamma, 1.0, eps, s.alpha, reinterpret_cast<int*>(hn + k));
     // X += P alpha, R -= Q alpha and the norms of R (its gamma and T outputs are recomputed below)
-    cg_update(ctx, dtype, N, k, X, P, R, Q, s.alpha, nullptr, s.T, s.beta, s.nrm);
-    const int slot = it & 1;
-    BKTS_HIP(hipMemcpyAsync(hbuf + slot * (k + 2), s.nrm, sizeof(double) * (k + 1), hipMemcpyDeviceToHost,
-                            ctx->stream));
+    cg_update(ctx, dtype, N, k, X, P, R, Q, s.alpha, nullptr, s.T, s.beta, hn);
     BKTS_HIP(hipEventRecord(ev[slot], ctx->stream));
     const int state = it > 1 ? check(it - 1) : 0;
     if (state == 1) {
