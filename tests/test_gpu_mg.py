@@ -208,3 +208,30 @@ def test_mg_apply_rejections(env):
         assert e.value.status == bkts.BKTS_EINVAL
     finally:
         bkts.bkts_op_destroy(op)
+
+
+def test_mg_apply_full_size_128cubed(env):
+    """The headline operator at full size (128^3, lognormal log-std 2, correlation 8 cells) in the launch
+    configuration the benchmark times (FP32, k = 4, a = 1/tau, b = 1): one V-cycle against the
+    oracle's cycle, every entry."""
+    import time
+    from oracle import multigrid as omg
+    torch, bkts, ctx = env
+    n = (128, 128, 128)
+    say("mg apply full size 128^3")
+    kap = inputs.lognormal_field(n, 0.0, 2.0, 8.0, 0)
+    op = bkts.bkts_fv_assemble(ctx, n, kappa=dev(torch, kap), fmt=bkts.BKTS_FMT_STENCIL)
+    try:
+        K, _ = fv.assemble_linear(n, kappa=kap)
+        N, k = K.shape[0], 4
+        F = inputs.random_block(N, k, 77).astype(np.float32)
+        Fd = torch.from_numpy(F).cuda()
+        Zd = torch.empty_like(Fd)
+        bkts.bkts_mg_apply(ctx, op, Fd, Zd, 1e3, 1.0)
+        t = time.perf_counter()
+        want = omg.vcycle(omg.hierarchy(K, n), 1e3, 1.0, F.astype(np.float64))
+        say(f"  oracle cycle {time.perf_counter() - t:.1f} s")
+        got = Zd.double().cpu().numpy()
+        assert np.abs(got - want).max() / np.abs(want).max() < 2e-5
+    finally:
+        bkts.bkts_op_destroy(op)
