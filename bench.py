@@ -7,13 +7,18 @@ with tau = 1e-3 from u0 = sin(pi x) sin(pi y) sin(pi z).  All inputs are seeded 
 
 A "step" is one accepted time step of Algorithm 1 (residual, block solves, shift), each step
 converged to a front-column relative residual of 1e-8.  The block form uses k time columns
-with FP32 block-CG inner solves (Jacobi) inside the FP64 outer refinement; the plain form is the
-same library at k = 1 in FP64 (inner = outer = 1e-8, i.e. one solve per step).
+with FP32 block-CG inner solves (multigrid V-cycle preconditioner on the stencil form of the
+operator) inside the FP64 outer refinement; the plain form is the same library at k = 1 in FP64
+(inner = outer = 1e-8, i.e. one solve per step) with the same operator and preconditioner.
 
-Prints ONE JSON line.  `value` = DOF * accepted steps / second of the block form, inputs resident
-in HBM before the timed region; `roofline` is the block operator (SpMM) kernel of the inner
-solves, its average launch time measured with HIP events inside the library over the timed
-region; `cpu_baseline` is the FP64 CPU oracle stepping a bounded sample of the same workload.
+Prints ONE compact JSON line on stdout (the full record, with every leg and sweep, goes to
+--full-out).  `value` = DOF * accepted steps / second of the block form, the median of --repeats
+timed runs (each a fresh stepper: warmup steps, then the timed steps), inputs resident in HBM
+before the timed region; `roofline` is the kernel category with the largest share of kernel time
+in the median run, its average launch time measured with HIP events inside the library over the
+timed region; `oracle_rel_error` is the error of the headline configuration's first steps against
+the FP64 oracle's sequential steps; `cpu_baseline` is the oracle stepping a bounded sample of the
+same workload on the host (plain C on every core, and the scipy form on one core beside it).
 """
 from __future__ import annotations
 
@@ -36,6 +41,12 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=16)
     p.add_argument("--warmup", type=int, default=16)
+    p.add_argument("--repeats", type=int, default=5,
+                   help="timed runs of the headline (fresh stepper, warmup + timed steps each); value = median")
+    p.add_argument("--err-steps", type=int, default=3,
+                   help="untimed headline steps from u0 checked against the oracle (0 = skip)")
+    p.add_argument("--full-out", default="gpurun_out/bench_full.json",
+                   help="where the full JSON record goes (the stdout line is the compact summary)")
     p.add_argument("--n", type=int, default=128)
     p.add_argument("--k", type=int, default=4)
     p.add_argument("--precision", choices=["f32", "f64"], default="f32")
@@ -682,6 +693,126 @@ def run_richards(torch, bkts, ctx, a):
             "kernels": {kk: {"avg_us": vv["avg_us"], "GBps": vv["GBps"]} for kk, vv in blk["kernels"].items()}}
 
 
+def headline_error(torch, bkts, ctx, op, y0, a, K, b, u0):
+    """Relative 2-norm error of the headline configuration's first accepted steps against the oracle.
+
+    An untimed run of the same stepper (k, precision, inner tolerance, preconditioner, outer 1e-8)
+    from u0, against the oracle's sequential implicit Euler (plain C Jacobi-PCG to a 1e-12 residual,
+    every host core)."""
+    import numpy as np
+
+    from oracle import cstep
+    steps = a.err_steps
+    r = run_form(torch, bkts, ctx, op, y0, a.k, a.precision, a.inner_rtol, 0, steps, False, a.precond)
+    got = r["hist"].cpu().numpy()
+    t = time.perf_counter()
+    ys, its, used = cstep.ie_steps(K, b, u0, 1e-3, steps, rtol=1e-12)
+    log(f"  oracle reference: {steps} steps to 1e-12 on {used} threads in {time.perf_counter() - t:.1f} s")
+    errs = [float(np.linalg.norm(got[s] - ys[s + 1]) / np.linalg.norm(ys[s + 1])) for s in range(steps)]
+    return {"max": max(errs), "per_step": errs, "steps": steps,
+            "reference": "oracle sequential implicit Euler, Jacobi-PCG to a 1e-12 relative residual (plain C)"}
+
+
+def cpu_baselines(a, K, b, u0, N):
+    """The oracle timed on the host: the plain C form on every core (the reported value) and the
+    scipy form on one core, each stepping a bounded sample of the headline workload to 1e-8."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle import cstep, stepping
+    steps = a.cpu_steps
+    log(f"oracle time stepping on the host: {steps} IE steps to 1e-8, C on all cores, then scipy on one")
+    t = time.perf_counter()
+    _, its, used = cstep.ie_steps(K, b, u0, 1e-3, steps, rtol=1e-8)
+    cs = time.perf_counter() - t
+    with threadpool_limits(1):
+        t = time.perf_counter()
+        stepping.dirk_linear(K, b, u0, 1e-3, "ie", steps, solver="cg", rtol=1e-8)
+        ps = time.perf_counter() - t
+    log(f"  C on {used} threads: {N * steps / cs:.4g} DOF*steps/s; scipy on 1 core: {N * steps / ps:.4g}")
+    return {"value": N * steps / cs, "unit": "DOF*timesteps/s", "cores": used, "kind": "oracle",
+            "sample": f"{steps} implicit-Euler steps of the 128^3 workload, Jacobi-PCG to a 1e-8 relative "
+                      f"residual per step, {cs:.1f} s (plain C oracle, OpenMP, {used} threads)",
+            "one_core": {"value": N * steps / ps, "cores": 1, "seconds": ps,
+                         "sample": f"the same {steps} steps with the scipy oracle (Jacobi-CG), BLAS limited to 1"},
+            "cg_iterations": its, "cpu_model": _cpu_model(), "nproc": os.cpu_count()}
+
+
+def pick_roofline(kt, k, precision, fmt):
+    """Roofline of the category with the largest share of kernel time (no exclusions), plus the
+    categories made of small latency-bound launches, reported by their launch counts."""
+    if not kt:
+        return None, None
+    dom = max(kt, key=lambda c: kt[c]["total_ms"])
+    roof = roofline_of(kt, dom, k, precision, fmt)
+    lat = {c: {"launches": kt[c]["launches"], "avg_us": kt[c]["avg_us"], "share": kt[c]["share"]}
+           for c in ("mg_coarse", "small") if c in kt}
+    return roof, lat
+
+
+def _r(x, d=4):
+    """Round floats for the compact line."""
+    if isinstance(x, float):
+        return float(f"{x:.{d}g}")
+    if isinstance(x, dict):
+        return {kk: _r(v, d) for kk, v in x.items()}
+    if isinstance(x, list):
+        return [_r(v, d) for v in x]
+    return x
+
+
+def compact_line(out, full_path):
+    """The one JSON line the driver reads: the contract's fields plus the headline's roofline, the
+    CPU baseline, the error against the oracle and one figure per leg; the full record is written
+    to `full_path`."""
+    roof = out["roofline"]
+    keep_roof = None if roof is None else {kk: roof[kk] for kk in (
+        "bound", "achieved", "peak", "unit", "frac", "traffic", "kernel", "category", "avg_launch_us",
+        "algorithmic_bytes_per_launch", "share_of_kernel_time")}
+    sw = out.get("spmm_sweep") or {}
+    spmm = {kk: {"us": v["avg_us"], "frac": v["frac"], "kernel": v["kernel"]} for kk, v in sw.items()
+            if kk.endswith("k=16") or kk.endswith("k=4")}
+    cpu = out["cpu_baseline"]
+    legs = {}
+    if out.get("nonlinear"):
+        nl = out["nonlinear"]
+        legs["nonlinear_1024sq_k16"] = {"value": nl["value"], "k4": nl["k4"]["value"], "plain": nl["plain"]["value"],
+                                        "oracle_err_256sq": nl["oracle_max_rel_err_256"]}
+    if out.get("richards"):
+        ri = out["richards"]
+        legs["richards_96cubed_k16"] = {f: v["value"] for f, v in ri["forms"].items()}
+        legs["richards_96cubed_k16"]["oracle_err_16x16x20"] = ri["oracle_max_rel_err_16x16x20"]
+    if out.get("fully_implicit"):
+        fi = out["fully_implicit"]
+        legs["radau2_128cubed"] = {"best": fi["best"], "value": fi["forms"][fi["best"]]["value"],
+                                   "oracle_err_16cubed": fi["oracle_max_rel_err_16cubed"]}
+    if out.get("window_acceleration"):
+        wa = out["window_acceleration"]["forms"]
+        legs["window_solve_128cubed"] = {kk: {"fgmres": v["fgmres"]["value"], "splitting": v["splitting"]["value"]}
+                                         for kk, v in wa.items()}
+    if out.get("serving"):
+        sv = out["serving"]
+        legs["serving"] = {"requests": sv["requests"], "throughput": sv["throughput_dof_timesteps_per_s"],
+                           "p50_ms": sv["latency_p50_ms"], "p99_ms": sv["latency_p99_ms"],
+                           "failed": sv["failed"], "oracle_err_sampled": sv["oracle_max_rel_err_sampled"],
+                           "fifo_plain": None if not sv["plain_fifo"] else {
+                               "throughput": sv["plain_fifo"]["throughput_dof_timesteps_per_s"],
+                               "p50_ms": sv["plain_fifo"]["latency_p50_ms"],
+                               "p99_ms": sv["plain_fifo"]["latency_p99_ms"]}}
+    line = {kk: out[kk] for kk in ("metric", "value", "unit", "n_gpus", "steps", "warmup", "ms_per_step",
+                                   "higher_is_better", "scaling", "vs_baseline", "dtype", "data")}
+    line["config"] = {kk: out["config"][kk] for kk in ("workload", "N", "k", "format", "precond", "inner_rtol")}
+    line.update({
+        "runs": out["runs"], "plain": out["plain"] and {"value": out["plain"]["value"],
+                                                      "ms_per_step": out["plain"]["ms_per_step"]},
+        "speedup_vs_plain": out["speedup_vs_plain"], "oracle_rel_error": out["oracle_rel_error"] and {
+            "max": out["oracle_rel_error"]["max"], "steps": out["oracle_rel_error"]["steps"]},
+        "roofline": keep_roof, "latency_bound": out["latency_bound"], "spmm_roofline": spmm or None,
+        "cpu_baseline": cpu and {kk: cpu[kk] for kk in ("value", "unit", "cores", "kind", "sample")} | {
+            "one_core": cpu["one_core"]["value"], "cpu_model": cpu["cpu_model"]},
+        "legs": legs or None, "full_record": os.path.relpath(full_path, ROOT)})
+    return json.dumps(_r(line), separators=(",", ":"))
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -710,12 +841,24 @@ def main():
     setup_s = time.perf_counter() - t
     _, nnz = bkts.bkts_op_info(op)
 
-    log(f"block form k={a.k} {a.precision}: warmup {a.warmup}, timed {a.steps}")
-    blk = run_form(torch, bkts, ctx, op, y0, a.k, a.precision, a.inner_rtol, a.warmup, a.steps,
-                   not a.no_kernel_timers, a.precond)
-    log(f"  {blk['value']:.4g} DOF*steps/s, outer={blk['info'].outer_iterations} "
-        f"krylov={blk['info'].krylov_iterations}")
-    result_hist = blk["hist"][-2:].double().cpu().numpy() if a.steps >= 2 else None
+    log(f"block form k={a.k} {a.precision}: {a.repeats} runs of warmup {a.warmup} + timed {a.steps}")
+    runs = []
+    for i in range(a.repeats):
+        r = run_form(torch, bkts, ctx, op, y0, a.k, a.precision, a.inner_rtol, a.warmup, a.steps,
+                     not a.no_kernel_timers, a.precond)
+        log(f"  run {i + 1}: {r['value']:.4g} DOF*steps/s, outer={r['info'].outer_iterations} "
+            f"krylov={r['info'].krylov_iterations}")
+        if runs:
+            r["hist"] = None
+        runs.append(r)
+    order = sorted(range(len(runs)), key=lambda i: runs[i]["value"])
+    blk = runs[order[len(runs) // 2]]
+    first_hist = runs[0]["hist"]
+    result_hist = first_hist[-2:].double().cpu().numpy() if a.steps >= 2 else None
+    del first_hist
+    for r in runs:
+        r["hist"] = None
+    torch.cuda.synchronize()
 
     plain = None
     if not a.no_plain:
@@ -736,6 +879,7 @@ def main():
             prec, item = item[-3:], item[:-3]
         ks = int(item)
         r = run_form(torch, bkts, ctx, op, y0, ks, prec, tol, a.warmup, a.steps, True, a.precond)
+        r["hist"] = None
         sp = r["kernels"].get("spmm", {})
         sv = 4 if prec == "f32" else 8
         bpl = (4 * N * sv if a.format == "stencil" else nnz * (sv + 4) + 4 * (N + 1)) + 2 * N * ks * sv
@@ -750,13 +894,8 @@ def main():
             "kernels": {kk: {"avg_us": vv["avg_us"], "GBps": vv["GBps"]} for kk, vv in r["kernels"].items()}}
         log(f"  sweep k={ks} {prec} inner={tol:g}: {r['value']:.4g} DOF*steps/s (spmm {sp.get('avg_us', 0):.1f} us)")
 
-    roof = spmm_roof = None
-    if blk["kernels"]:
-        dom = max((c for c in blk["kernels"] if c not in ("small", "other", "mg_coarse")),
-                  key=lambda c: blk["kernels"][c]["total_ms"])
-        roof = roofline_of(blk["kernels"], dom, a.k, a.precision, a.format)
-        if "spmm" in blk["kernels"]:
-            spmm_roof = roofline_of(blk["kernels"], "spmm", a.k, a.precision, a.format)
+    roof, lat = pick_roofline(blk["kernels"], a.k, a.precision, a.format)
+    spmm_roof = roofline_of(blk["kernels"], "spmm", a.k, a.precision, a.format) if "spmm" in blk["kernels"] else None
 
     formats = None
     if a.format_compare:
@@ -772,6 +911,7 @@ def main():
             op2 = bkts.bkts_fv_assemble(ctx, n, kappa=kd, fmt=fcode[fmt])
             try:
                 b2 = run_form(torch, bkts, ctx, op2, y0, a.k, a.precision, a.inner_rtol, a.warmup, a.steps, True, pc)
+                b2["hist"] = None
                 p2 = None if a.no_plain else run_form(torch, bkts, ctx, op2, y0, 1, "f64", 1e-8, 1, a.plain_steps,
                                                       False, pc)
             finally:
@@ -817,8 +957,9 @@ def main():
 
     cpu = None
     err = None
-    if not a.no_cpu or result_hist is not None or accel_keep is not None:
-        from oracle import fv, stepping
+    oerr = None
+    if not a.no_cpu or result_hist is not None or accel_keep is not None or a.err_steps > 0:
+        from oracle import fv
         log("oracle assembly (CPU)")
         K, b = fv.assemble_linear(n, kappa=kap)
         if accel_keep is not None:
@@ -829,23 +970,19 @@ def main():
                                                               np.linalg.norm(u0 / 1e-3))
             log(f"  window k={kk}: oracle rel. residual {accel['oracle_rel_residual_first_window']:.2e}")
         if result_hist is not None:
-            # FP64 oracle residual of the last accepted step of the timed block run
+            # FP64 oracle residual of the last accepted step of the first timed block run
             import scipy.sparse as sp
             J = (sp.identity(N) / 1e-3 + K).tocsr()
             r = J @ result_hist[1] - result_hist[0] / 1e-3 - b
             err = float(np.linalg.norm(r) / np.linalg.norm(result_hist[0] / 1e-3 + b))
+        if a.err_steps > 0:
+            log(f"error against the oracle: {a.err_steps} untimed steps of the headline configuration from u0")
+            oerr = headline_error(torch, bkts, ctx, op, y0, a, K, b, u0)
+            log(f"  relative errors {['%.2e' % e for e in oerr['per_step']]}")
         if not a.no_cpu:
-            from threadpoolctl import threadpool_limits
-            log(f"oracle time stepping on the host: {a.cpu_steps} IE step(s), Jacobi-CG to 1e-8")
-            with threadpool_limits(1):
-                t = time.perf_counter()
-                stepping.dirk_linear(K, b, u0, 1e-3, "ie", a.cpu_steps, solver="cg", rtol=1e-8)
-                cs = time.perf_counter() - t
-            cpu = {"value": N * a.cpu_steps / cs, "unit": "DOF*timesteps/s", "cores": 1, "kind": "oracle",
-                   "sample": f"{a.cpu_steps} implicit-Euler step(s) of the same 128^3 workload, scipy Jacobi-CG "
-                             f"to a 1e-8 relative residual, {cs:.1f} s, 1 thread (BLAS limited to 1)",
-                   "cpu_model": _cpu_model(), "nproc": os.cpu_count()}
+            cpu = cpu_baselines(a, K, b, u0, N)
 
+    vals = [r["value"] for r in runs]
     out = {
         "metric": "DOF·timesteps/s to 1e-8 residual (block vs plain); SpMM HBM GB/s; p50/p99",
         "value": blk["value"], "unit": "DOF*timesteps/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
@@ -859,13 +996,16 @@ def main():
                    "N": N, "nnz": nnz, "k": a.k, "inner_rtol": a.inner_rtol, "format": a.format,
                    "precond": a.precond,
                    "setup_s": setup_s},
+        "runs": vals, "value_is": f"median of {len(vals)} runs of {a.steps} timed steps",
         "outer_iterations": blk["info"].outer_iterations, "krylov_iterations": blk["info"].krylov_iterations,
+        "oracle_rel_error": oerr,
         "oracle_rel_residual_last_step": err,
         "plain": plain,
         "speedup_vs_plain": (blk["value"] / plain["value"]) if plain else None,
         "sweep": sweep or None,
         "formats": formats,
         "roofline": roof,
+        "latency_bound": lat,
         "spmm_roofline": spmm_roof,
         "spmm_sweep": spmm_sweep,
         "kernels": blk["kernels"],
@@ -876,10 +1016,18 @@ def main():
         "richards": richards,
         "serving": serving,
     }
-    print(json.dumps(out))
+    full_path = a.full_out if os.path.isabs(a.full_out) else os.path.join(ROOT, a.full_out)
+    try:
+        os.makedirs(os.path.dirname(full_path), exist_ok=True)
+        with open(full_path, "w") as f:
+            json.dump(out, f, indent=1)
+    except OSError as e:
+        log(f"could not write the full record to {full_path}: {e}")
+    log(f"full record: {full_path}")
     bkts.bkts_op_destroy(op)
     torch.cuda.synchronize()
     bkts.bkts_ctx_destroy(ctx)
+    print(compact_line(out, full_path), flush=True)
 
 
 def _cpu_model():

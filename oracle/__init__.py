@@ -26,6 +26,11 @@ method converges to, by the plain definitions:
                    (Sec. 4.3, eq. RelationshipsThetaK), its exact Jacobian, the
                    window residual with a split mass term and sequential implicit
                    Euler with Newton and direct solves.
+* ``cstep``        the same sequential implicit Euler with Jacobi-PCG in plain C
+                   (``seqstep.c``, OpenMP), for full-size checks and the
+                   all-core CPU baseline.
+* ``multigrid``    the geometric V-cycle that defines this library's own
+                   multigrid preconditioner (the paper uses AMG without details).
 * ``blockops``     plain definitions of the block kernels (block operator,
                    Gram matrices, block solves) used for kernel parity.
 
