@@ -166,7 +166,8 @@ bkts_status bkts_spmm(bkts_ctx ctx, bkts_op op, int dtype, int k, double alpha, 
  * stencil form of K (and of the identity mass), one damped Jacobi sweep (w = 0.8)
  * before the restriction and one after the prolongation, 12 sweeps on the coarsest
  * level (at most 64 cells).  B is symmetric positive definite.  F, Z: device N x k
- * blocks of type `dtype`, contiguous (ldf = ldz = k), not overlapping.  The op must
+ * blocks of type `dtype`, contiguous (ldf = ldz = k), 16-byte aligned, not
+ * overlapping (else BKTS_EINVAL).  The op must
  * carry the stencil form (BKTS_FMT_STENCIL), else BKTS_EINVAL; the hierarchy is
  * built on first use and kept with the op. */
 bkts_status bkts_mg_apply(bkts_ctx ctx, bkts_op op, int dtype, int k, double a, double b, const void* F,

@@ -172,6 +172,8 @@ bkts_status bkts_mg_apply(bkts_ctx ctx, bkts_op op, int dtype, int k, double a, 
   const char* f = static_cast<const char*>(F);
   const char* z = static_cast<const char*>(Z);
   BKTS_REQUIRE(f + bytes <= z || z + bytes <= f, "F and Z must not overlap");
+  BKTS_REQUIRE(reinterpret_cast<uintptr_t>(F) % 16 == 0 && reinterpret_cast<uintptr_t>(Z) % 16 == 0,
+               "F and Z must be 16-byte aligned");
   BKTS_REQUIRE(std::isfinite(a) && std::isfinite(b) && a >= 0.0 && b > 0.0, "need a >= 0 and b > 0");
   set_device(ctx);
   if (op->N > 0) bkts::mg_vcycle(ctx, *op, dtype, k, a, b, F, Z);

@@ -250,9 +250,23 @@ void op_refresh_values(bkts_op op);  // after CSR values changed: diag, SELL val
 void op_build_stencil(bkts_op op);
 void spmm_stencil(bkts_ctx ctx, const bkts_op_s& op, int dtype, int k, double cb, const void* B, int ldb,
                   double alpha, const void* X, int ldx, double beta, void* Y, int ldy);
+// Block-CG reductions folded into the finest prolongation of a V-cycle Z = V(R) (k in {1, 2, 4}):
+// in: Q (N x k, contiguous, the V-cycle's dtype); out: partials of gamma = R^T Z, T = Q^T Z and
+// nrm = diag(R^T R), laid out [gamma (k*k) | T (k*k) | nrm (k)] x nslots (workspace owned by the
+// context).  nslots == 0 on return: the hierarchy is too small for a separate finest prolongation and
+// nothing was reduced.
+struct MgFuse {
+  const void* Q = nullptr;
+  double* partials = nullptr;
+  int64_t nslots = 0;
+};
 // Z = V-cycle(F) for a I + b K (mg.hip): symmetric geometric multigrid on the stencil form, N x k
 // contiguous blocks of type dtype.  BKTS_EINVAL without the stencil form.
-void mg_vcycle(bkts_ctx ctx, const bkts_op_s& op, int dtype, int k, double a, double b, const void* F, void* Z);
+void mg_vcycle(bkts_ctx ctx, const bkts_op_s& op, int dtype, int k, double a, double b, const void* F, void* Z,
+               MgFuse* fuse = nullptr);
+// Whether a V-cycle of width k on this operator has a separate finest prolongation that can fold the
+// block-CG reductions (builds the hierarchy on first use).
+bool mg_fusable(bkts_ctx ctx, const bkts_op_s& op, int k);
 
 // ---- nonlinear operator (nonlinear.hip)
 bkts_nlop nlop_create(bkts_ctx ctx, const bkts_grid* grid, const bkts_nl_coeffs* c);
@@ -318,6 +332,9 @@ void rk_cg_update(bkts_ctx ctx, int dtype, int64_t N, int k, void* X, const void
                   const CgTail* tail = nullptr);
 void rk_cg_pupdate(bkts_ctx ctx, int dtype, int64_t N, int k, void* P, const void* R, const double* beta,
                    const double* dinv);
+// X += P alpha, R -= Q alpha with no reductions (the multigrid prolongation folds them instead)
+void rk_cg_xr_update(bkts_ctx ctx, int dtype, int64_t N, int k, void* X, const void* P, void* R, const void* Q,
+                     const double* alpha);
 void rk_gram(bkts_ctx ctx, int dtype, int64_t N, int k, const void* X, const void* Y, double* G);
 // G1 = X1^T Y and G2 = X2^T Y in one pass (k in {1, 2, 4}, contiguous blocks)
 void rk_gram2(bkts_ctx ctx, int dtype, int64_t N, int k, const void* X1, const void* X2, const void* Y, double* G1,

@@ -256,6 +256,28 @@ void block_pcg_mg(bkts_ctx ctx, const bkts_op_s& op, int dtype, int k, double a,
     return nd >= k ? -1 : 0;
   };
   const bool rowk = rk_eligible(k);
+  // k <= 4 on a hierarchy with a separate finest prolongation: the V-cycle's last pass folds
+  // gamma = R^T Z, T = Q^T Z and the norms of R, one launch folds those partials and solves for beta
+  // (writing the norms and the deflation count to pinned host memory), and the Gram of the SpMM pass
+  // is folded and solved for alpha in one launch: 12 launches per iteration instead of 20.
+  const bool fused = rowk && mg_fusable(ctx, op, k);
+  CgTail tail_sg, tail_up;
+  if (fused) {
+    tail_sg.counter = ctx->tail_counter(0);
+    tail_sg.eps = eps;
+    tail_sg.G = s.G;
+    tail_sg.gamma_in = s.gamma;
+    tail_sg.alpha = s.alpha;
+    tail_sg.ndefl = s.ndefl;
+    tail_up.counter = ctx->tail_counter(1);
+    tail_up.eps = eps;
+    tail_up.G = s.G;
+    tail_up.gamma = s.gamma;
+    tail_up.T = s.T;
+    tail_up.nrm = s.nrm;
+    tail_up.beta = s.beta;
+    tail_up.ndefl = s.ndefl;  // read only: copied to the host next to the norms
+  }
   // the norms and the deflation count are written straight into the pinned buffer (no copy launch)
   double* hbuf_dev = nullptr;
   BKTS_HIP(hipHostGetDevicePointer(reinterpret_cast<void**>(&hbuf_dev), hbuf, 0));
@@ -263,16 +285,23 @@ void block_pcg_mg(bkts_ctx ctx, const bkts_op_s& op, int dtype, int k, double a,
   for (int it = 1; it <= maxit; ++it) {
     const int slot = it & 1;
     double* hn = hbuf_dev + slot * (k + 2);
-    if (rowk) {  // Q = a P + b K P with G = P^T Q folded from the same pass
-      rk_spmm_gram(ctx, op, dtype, k, a, P, b, Q, s.G, nullptr);
+    if (fused) {
+      rk_spmm_gram(ctx, op, dtype, k, a, P, b, Q, s.G, &tail_sg);  // also alpha = G^+ gamma
+      rk_cg_xr_update(ctx, dtype, N, k, X, P, R, Q, s.alpha);
     } else {
-      spmm(ctx, op, dtype, k, 0.0, nullptr, k, a, P, k, b, Q, k);
-      inner_gram(ctx, dtype, N, k, P, Q, s.G);
+      if (rowk) {  // Q = a P + b K P with G = P^T Q folded from the same pass
+        rk_spmm_gram(ctx, op, dtype, k, a, P, b, Q, s.G, nullptr);
+      } else {
+        spmm(ctx, op, dtype, k, 0.0, nullptr, k, a, P, k, b, Q, k);
+        inner_gram(ctx, dtype, N, k, P, Q, s.G);
+      }
+      small_spd_solve(ctx, k, s.G, s.gamma, 1.0, eps, s.alpha, reinterpret_cast<int*>(hn + k));
+      // X += P alpha, R -= Q alpha and the norms of R (its gamma and T outputs are recomputed below)
+      cg_update(ctx, dtype, N, k, X, P, R, Q, s.alpha, nullptr, s.T, s.beta, hn);
+      BKTS_HIP(hipEventRecord(ev[slot], ctx->stream));
     }
-    small_spd_solve(ctx, k, s.G, s.gamma, 1.0, eps, s.alpha, reinterpret_cast<int*>(hn + k));
-    // X += P alpha, R -= Q alpha and the norms of R (its gamma and T outputs are recomputed below)
-    cg_update(ctx, dtype, N, k, X, P, R, Q, s.alpha, nullptr, s.T, s.beta, hn);
-    BKTS_HIP(hipEventRecord(ev[slot], ctx->stream));
+    // the norms of iteration it-1 (in the fused form they come after its V-cycle, which the GPU
+    // finished before starting this iteration's SpMM)
     const int state = it > 1 ? check(it - 1) : 0;
     if (state == 1) {
       ctx->sync();  // iteration `it` is in flight; it only improves X
@@ -283,17 +312,35 @@ void block_pcg_mg(bkts_ctx ctx, const bkts_op_s& op, int dtype, int k, double a,
     if (state == -1) {  // every search direction collapsed: restart from the preconditioned residual
       if (++restarts > 3) throw Error{BKTS_EBREAKDOWN, "block CG: search space collapsed repeatedly"};
       precondition();
+      if (fused) {  // this iteration's norms, for the check of the next one
+        colnorms2(ctx, dtype, N, k, R, k, s.nrm);
+        BKTS_HIP(hipMemcpyAsync(hbuf + slot * (k + 2), s.nrm, sizeof(double) * k, hipMemcpyDeviceToHost,
+                                ctx->stream));
+        BKTS_HIP(hipMemcpyAsync(reinterpret_cast<int*>(hbuf + slot * (k + 2) + k), s.ndefl, sizeof(int),
+                                hipMemcpyDeviceToHost, ctx->stream));
+        BKTS_HIP(hipEventRecord(ev[slot], ctx->stream));
+      }
       continue;
     }
     restarts = 0;
-    mg_vcycle(ctx, op, dtype, k, a, b, R, Z);
-    if (rowk) {
-      rk_gram2(ctx, dtype, N, k, R, Q, Z, s.gamma, s.T);  // gamma = R^T Z and T = Q^T Z in one pass
+    if (fused) {
+      MgFuse fu;
+      fu.Q = Q;
+      mg_vcycle(ctx, op, dtype, k, a, b, R, Z, &fu);
+      BKTS_REQUIRE(fu.nslots > 0, "multigrid: the fused reductions were not produced");
+      tail_up.host = hn;
+      fold_solve(ctx, 1, k, k, fu.partials, fu.nslots, tail_up);  // gamma, T, nrm, then beta = -G^+ T
+      BKTS_HIP(hipEventRecord(ev[slot], ctx->stream));
     } else {
-      inner_gram(ctx, dtype, N, k, R, Z, s.gamma);
-      inner_gram(ctx, dtype, N, k, Q, Z, s.T);
+      mg_vcycle(ctx, op, dtype, k, a, b, R, Z);
+      if (rowk) {
+        rk_gram2(ctx, dtype, N, k, R, Q, Z, s.gamma, s.T);  // gamma = R^T Z and T = Q^T Z in one pass
+      } else {
+        inner_gram(ctx, dtype, N, k, R, Z, s.gamma);
+        inner_gram(ctx, dtype, N, k, Q, Z, s.T);
+      }
+      small_spd_solve(ctx, k, s.G, s.T, -1.0, eps, s.beta, nullptr);
     }
-    small_spd_solve(ctx, k, s.G, s.T, -1.0, eps, s.beta, nullptr);
     cg_pupdate(ctx, dtype, N, k, P, Z, s.beta, nullptr);
   }
   if (check(maxit) == 1) {

@@ -16,7 +16,16 @@
 //   x_{l+1} = V-cycle(l + 1, f_{l+1})
 //   z = x + P x_{l+1};  z += w D^-1 (f - A z)   (prolongation and post-sweep, one pass)
 // with the pre-smoothed x recomputed wherever it is needed instead of stored, and on the coarsest
-// level (at most 64 cells) a fixed number of damped Jacobi sweeps in one workgroup.
+// level (at most 64 cells) a fixed number of damped Jacobi sweeps.
+//
+// Launch structure.  The large levels run one multi-workgroup launch per restriction and per
+// prolongation, each workgroup on a contiguous range of the grid that belongs to one XCD (so the
+// neighbour lines and planes that a cell's stencil re-reads sit in that XCD's L2).  Every level
+// whose block has at most kTailElems entries, down to the coarsest solve and back up, runs in ONE
+// single-workgroup launch (the tail): its passes are separated by workgroup barriers instead of
+// kernel boundaries, and the coarsest level's coefficients and iterate live in LDS.  The finest
+// prolongation can also fold the block-CG reductions that follow the preconditioner
+// (gamma = R^T Z, T = Q^T Z and the column norms of R), since it already holds R and Z per row.
 #include <memory>
 #include <vector>
 
@@ -42,6 +51,9 @@ namespace {
 constexpr int kCoarsestMax = 64;  // cells of the coarsest level
 constexpr int kCoarseSweeps = 12;
 constexpr double kOmega = 0.8;
+constexpr int kMaxLevels = 16;
+constexpr int64_t kTailElems = 2048;  // levels with N_l * k <= this run inside the tail launch
+constexpr int kTailThreads = 512;
 
 struct Geo {
   int nx, ny, nz;
@@ -136,57 +148,147 @@ struct LvArgs {
   int k;
 };
 
+// CW consecutive values of one row as one vector access (one address per lane instead of CW; a row
+// chunk starts at a multiple of CW elements and the blocks are 16-byte aligned).
+template <typename T, int CW>
+__device__ __forceinline__ void ld_cw(const T* p, T (&v)[CW]) {
+  if constexpr (CW == 4 && sizeof(T) == 4) {
+    const float4 q = *reinterpret_cast<const float4*>(p);
+    v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
+  } else if constexpr (CW == 2 && sizeof(T) == 4) {
+    const float2 q = *reinterpret_cast<const float2*>(p);
+    v[0] = q.x; v[1] = q.y;
+  } else if constexpr (CW == 4 && sizeof(T) == 8) {
+    const double2 a = *reinterpret_cast<const double2*>(p);
+    const double2 b = *reinterpret_cast<const double2*>(p + 2);
+    v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y;
+  } else if constexpr (CW == 2 && sizeof(T) == 8) {
+    const double2 a = *reinterpret_cast<const double2*>(p);
+    v[0] = a.x; v[1] = a.y;
+  } else {
+#pragma unroll
+    for (int j = 0; j < CW; ++j) v[j] = p[j];
+  }
+}
+
+template <typename T, int CW>
+__device__ __forceinline__ void st_cw(T* p, const T (&v)[CW]) {
+  if constexpr (CW == 4 && sizeof(T) == 4) {
+    *reinterpret_cast<float4*>(p) = float4{v[0], v[1], v[2], v[3]};
+  } else if constexpr (CW == 2 && sizeof(T) == 4) {
+    *reinterpret_cast<float2*>(p) = float2{v[0], v[1]};
+  } else if constexpr (CW == 4 && sizeof(T) == 8) {
+    *reinterpret_cast<double2*>(p) = double2{v[0], v[1]};
+    *reinterpret_cast<double2*>(p + 2) = double2{v[2], v[3]};
+  } else if constexpr (CW == 2 && sizeof(T) == 8) {
+    *reinterpret_cast<double2*>(p) = double2{v[0], v[1]};
+  } else {
+#pragma unroll
+    for (int j = 0; j < CW; ++j) p[j] = v[j];
+  }
+}
+
 // Damped Jacobi from zero: x[r] = w f[r] / dA[r], for the CW columns starting at c0.
 template <typename T, int CW>
 __device__ __forceinline__ void pre_x(const LvArgs<T>& L, const T* f, int64_t r, int c0, T (&x)[CW]) {
   const T s = L.w * L.di[r];
+  T fv[CW];
+  ld_cw<T, CW>(f + r * L.k + c0, fv);
 #pragma unroll
-  for (int j = 0; j < CW; ++j) x[j] = s * f[r * L.k + c0 + j];
+  for (int j = 0; j < CW; ++j) x[j] = s * fv[j];
 }
 
-// (A y)[r] for the CW columns at c0, where y at any cell q is produced by ycell(q, out[CW]).
+// (A y)[r] for the CW columns at c0, where y at cell q = (qx, qy, qz) is produced by
+// ycell(q, qx, qy, qz, out[CW]).  Neighbours in the order +x, -x, +y, -y, +z, -z.  Branch-free: an
+// absent neighbour (grid boundary) is read at the cell itself with a zero coefficient, so the loads
+// of all six neighbours are in flight together.
 template <typename T, int CW, typename Y>
 __device__ __forceinline__ void apply_row(const LvArgs<T>& L, int64_t r, int ix, int iy, int iz, const T (&yr)[CW],
                                           Y ycell, T (&out)[CW]) {
   const Geo& g = L.g;
   const int64_t N = g.N;
-  const T dA = T(1) / L.di[r];  // the diagonal from its cached inverse: no dK or mass read
-#pragma unroll
-  for (int j = 0; j < CW; ++j) out[j] = dA * yr[j];
   const int pos[3] = {ix, iy, iz};
   const int len[3] = {g.nx, g.ny, g.nz};
   const int64_t st[3] = {g.sx, g.sy, g.sz};
+  T cf[6];
+  T y[6][CW];
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
     const T* od = L.c + (2 + d) * N;
-    if (pos[d] + 1 < len[d]) {
-      const T cu = L.b * od[r];
-      T y[CW];
-      ycell(r + st[d], y);
-#pragma unroll
-      for (int j = 0; j < CW; ++j) out[j] = fma(cu, y[j], out[j]);
-    }
-    if (pos[d] > 0) {
-      const T cl = L.b * od[r - st[d]];
-      T y[CW];
-      ycell(r - st[d], y);
-#pragma unroll
-      for (int j = 0; j < CW; ++j) out[j] = fma(cl, y[j], out[j]);
-    }
+    const bool up = pos[d] + 1 < len[d], lo = pos[d] > 0;
+    const int64_t ql = lo ? r - st[d] : r;
+    // both couplings read unconditionally (a select on the loaded value would become a branch)
+    cf[2 * d] = L.b * od[r] * T(up ? 1 : 0);
+    cf[2 * d + 1] = L.b * od[ql] * T(lo ? 1 : 0);
+    const int du = up ? 1 : 0, dl = lo ? 1 : 0;
+    ycell(up ? r + st[d] : r, ix + (d == 0 ? du : 0), iy + (d == 1 ? du : 0), iz + (d == 2 ? du : 0), y[2 * d]);
+    ycell(ql, ix - (d == 0 ? dl : 0), iy - (d == 1 ? dl : 0), iz - (d == 2 ? dl : 0), y[2 * d + 1]);
   }
+  const T dA = T(1) / L.di[r];  // the diagonal from its cached inverse: no dK or mass read
+#pragma unroll
+  for (int j = 0; j < CW; ++j) out[j] = dA * yr[j];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+#pragma unroll
+    for (int j = 0; j < CW; ++j) out[j] = fma(cf[2 * d], y[2 * d][j], out[j]);
+#pragma unroll
+    for (int j = 0; j < CW; ++j) out[j] = fma(cf[2 * d + 1], y[2 * d + 1][j], out[j]);
+  }
+}
+
+// r = f - A x at fine cell i with x = w D^-1 f (the pre-smoothed iterate, recomputed from f).
+template <typename T, int CW>
+__device__ __forceinline__ void smoothed_residual(const LvArgs<T>& L, const T* f, int64_t i, int ix, int iy, int iz,
+                                                  int c0, T (&v)[CW]) {
+  T fi[CW], xi[CW], ax[CW];
+  ld_cw<T, CW>(f + i * L.k + c0, fi);
+  const T s = L.w * L.di[i];
+#pragma unroll
+  for (int j = 0; j < CW; ++j) xi[j] = s * fi[j];
+  apply_row<T, CW>(L, i, ix, iy, iz, xi,
+                   [&](int64_t q, int, int, int, T(&yq)[CW]) { pre_x<T, CW>(L, f, q, c0, yq); }, ax);
+#pragma unroll
+  for (int j = 0; j < CW; ++j) v[j] = fi[j] - ax[j];
+}
+
+// z = y + w D^-1 (f - A y) at fine cell r with y = w D^-1 f + P xc (coarse level c); also returns the
+// row's f values.
+template <typename T, int CW>
+__device__ __forceinline__ void prolong_row(const LvArgs<T>& L, const Geo& c, const T* f, const T* xc, int64_t r,
+                                            int ix, int iy, int iz, int c0, T (&zr)[CW], T (&fr)[CW]) {
+  auto ycell = [&](int64_t q, int qx, int qy, int qz, T(&y)[CW]) {
+    pre_x<T, CW>(L, f, q, c0, y);
+    const int64_t P = (qx >> 1) + c.sy * (qy >> 1) + c.sz * (qz >> 1);
+    T xv[CW];
+    ld_cw<T, CW>(xc + P * L.k + c0, xv);
+#pragma unroll
+    for (int j = 0; j < CW; ++j) y[j] += xv[j];
+  };
+  T xv[CW], yr[CW], ay[CW];
+  ld_cw<T, CW>(f + r * L.k + c0, fr);
+  const T s = L.w * L.di[r];
+  ld_cw<T, CW>(xc + ((ix >> 1) + c.sy * (iy >> 1) + c.sz * (iz >> 1)) * L.k + c0, xv);
+#pragma unroll
+  for (int j = 0; j < CW; ++j) yr[j] = s * fr[j] + xv[j];
+  apply_row<T, CW>(L, r, ix, iy, iz, yr, ycell, ay);
+#pragma unroll
+  for (int j = 0; j < CW; ++j) zr[j] = yr[j] + s * (fr[j] - ay[j]);
 }
 
 // fc = P^T (f - A x) with x = w D^-1 f.  A workgroup covers a strip of 32 coarse cells along x: its
 // 256 threads are the 64 x 2 x 2 fine cells of those aggregates (consecutive threads on consecutive
 // cells of one grid line), each forms its own residual, and the 8 residuals of an aggregate are
-// summed through LDS in a fixed order.  Grid: (ceil(ncx / 32), ncy, ncz).
+// summed through LDS in a fixed order.  One-dimensional grid of gx * ncy * ncz strips, x fastest,
+// remapped so that each XCD takes one contiguous range of strips.
 template <typename T, int CW>
-__global__ __launch_bounds__(256) void mg_restrict_kernel(LvArgs<T> L, Geo c, const T* __restrict__ f,
+__global__ __launch_bounds__(256) void mg_restrict_kernel(LvArgs<T> L, Geo c, int gx, const T* __restrict__ f,
                                                           T* __restrict__ fc) {
   __shared__ T red[CW][256];
   const int t = threadIdx.x;
   const int x = t & 63, y = (t >> 6) & 1, z = t >> 7;
-  const int X0 = blockIdx.x * 32, Y = blockIdx.y, Z = blockIdx.z;
+  const int64_t unit = dev::xcd_slot(blockIdx.x, gridDim.x);
+  const int64_t yz = unit / gx;
+  const int X0 = (int)(unit - yz * gx) * 32, Y = (int)(yz % c.ny), Z = (int)(yz / c.ny);
   const Geo& g = L.g;
   const int ix = 2 * X0 + x, iy = 2 * Y + y, iz = 2 * Z + z;
   const bool in = ix < g.nx && iy < g.ny && iz < g.nz;
@@ -195,13 +297,7 @@ __global__ __launch_bounds__(256) void mg_restrict_kernel(LvArgs<T> L, Geo c, co
     T v[CW];
 #pragma unroll
     for (int j = 0; j < CW; ++j) v[j] = T(0);
-    if (in) {
-      T xi[CW], ax[CW];
-      pre_x<T, CW>(L, f, i, c0, xi);
-      apply_row<T, CW>(L, i, ix, iy, iz, xi, [&](int64_t q, T(&yq)[CW]) { pre_x<T, CW>(L, f, q, c0, yq); }, ax);
-#pragma unroll
-      for (int j = 0; j < CW; ++j) v[j] = f[i * L.k + c0 + j] - ax[j];
-    }
+    if (in) smoothed_residual<T, CW>(L, f, i, ix, iy, iz, c0, v);
 #pragma unroll
     for (int j = 0; j < CW; ++j) red[j][t] = v[j];
     __syncthreads();
@@ -219,61 +315,210 @@ __global__ __launch_bounds__(256) void mg_restrict_kernel(LvArgs<T> L, Geo c, co
   }
 }
 
-// z = y + w D^-1 (f - A y) with y = w D^-1 f + P xc, one thread per fine cell.
-template <typename T, int CW>
+// z = y + w D^-1 (f - A y) with y = w D^-1 f + P xc.  Persistent: each workgroup walks one contiguous
+// XCD-aware range of rows, one row per thread per step.  With GRAM (CW == k, k in {1, 2, 4}) the
+// workgroup also accumulates gamma = f^T z, T = Q^T z and nrm = diag(f^T f) in FP64 and stores one
+// partial per entry, laid out [gamma (k*k) | T (k*k) | nrm (k)] x gridDim.x (fixed-order folding).
+template <typename T, int CW, bool GRAM>
 __global__ __launch_bounds__(256) void mg_prolong_kernel(LvArgs<T> L, Geo c, const T* __restrict__ f,
-                                                         const T* __restrict__ xc, T* __restrict__ z) {
-  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= L.g.N) return;
-  int ix, iy, iz;
-  coords(L.g, r, ix, iy, iz);
-  auto ycell = [&](int64_t q, int qx, int qy, int qz, int c0, T(&y)[CW]) {
-    pre_x<T, CW>(L, f, q, c0, y);
-    const int64_t P = (qx >> 1) + c.sy * (qy >> 1) + c.sz * (qz >> 1);
+                                                         const T* __restrict__ xc, T* __restrict__ z,
+                                                         const T* __restrict__ Qm, double* partials) {
+  constexpr int NA = GRAM ? 2 * CW * CW + CW : 1;
+  double acc[NA];
 #pragma unroll
-    for (int j = 0; j < CW; ++j) y[j] += xc[P * L.k + c0 + j];
-  };
-  for (int c0 = 0; c0 < L.k; c0 += CW) {
-    T yr[CW], ay[CW];
-    ycell(r, ix, iy, iz, c0, yr);
-    apply_row<T, CW>(L, r, ix, iy, iz, yr,
-                     [&](int64_t q, T(&y)[CW]) {
-                       int qx, qy, qz;
-                       coords(L.g, q, qx, qy, qz);
-                       ycell(q, qx, qy, qz, c0, y);
-                     },
-                     ay);
-    const T s = L.w * L.di[r];
+  for (int e = 0; e < NA; ++e) acc[e] = 0.0;
+  const int64_t N = L.g.N;
+  const int64_t slot = dev::xcd_slot(blockIdx.x, gridDim.x);
+  const int64_t chunks = (N + 255) / 256;
+  const int64_t per = (chunks + gridDim.x - 1) / gridDim.x;
+  const int64_t end = (slot + 1) * per * 256 < N ? (slot + 1) * per * 256 : N;
+  for (int64_t r = slot * per * 256 + threadIdx.x; r < end; r += 256) {
+    int ix, iy, iz;
+    coords(L.g, r, ix, iy, iz);
+    const int kc = GRAM ? CW : L.k;  // with the reductions the row is one chunk
+    for (int c0 = 0; c0 < kc; c0 += CW) {
+      T zr[CW], fr[CW];
+      prolong_row<T, CW>(L, c, f, xc, r, ix, iy, iz, c0, zr, fr);
+      st_cw<T, CW>(z + r * L.k + c0, zr);
+      if constexpr (GRAM) {
+        T q[CW];
+        ld_cw<T, CW>(Qm + r * CW, q);
 #pragma unroll
-    for (int j = 0; j < CW; ++j) z[r * L.k + c0 + j] = yr[j] + s * (f[r * L.k + c0 + j] - ay[j]);
+        for (int i = 0; i < CW; ++i) {
+#pragma unroll
+          for (int j = 0; j < CW; ++j) {
+            acc[i * CW + j] = fma((double)fr[i], (double)zr[j], acc[i * CW + j]);
+            acc[CW * CW + i * CW + j] = fma((double)q[i], (double)zr[j], acc[CW * CW + i * CW + j]);
+          }
+          acc[2 * CW * CW + i] = fma((double)fr[i], (double)fr[i], acc[2 * CW * CW + i]);
+        }
+      }
+    }
+  }
+  if constexpr (GRAM) {
+    __shared__ double red[4 * NA];
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1)
+#pragma unroll
+      for (int e = 0; e < NA; ++e) acc[e] += __shfl_xor(acc[e], off);
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (lane == 0) {
+#pragma unroll
+      for (int e = 0; e < NA; ++e) red[w * NA + e] = acc[e];
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < NA; e += 256)
+      partials[(int64_t)e * gridDim.x + slot] = ((red[e] + red[NA + e]) + red[2 * NA + e]) + red[3 * NA + e];
   }
 }
 
-// Coarsest level: kCoarseSweeps damped Jacobi sweeps from zero in one workgroup (x in LDS).
+// The levels of the tail, finest first: the coefficients, the inverse diagonal, the right-hand side
+// f and the output z (also the scratch of the level's residuals while restricting).
 template <typename T>
-__global__ __launch_bounds__(256) void mg_coarse_kernel(LvArgs<T> L, const T* __restrict__ f, T* __restrict__ z) {
+struct TailLv {
+  Geo g;
+  const T* c;
+  const T* di;
+  T* f;
+  T* z;
+};
+
+template <typename T>
+struct TailArgs {
+  TailLv<T> lv[kMaxLevels];
+  int nl;  // levels in the tail; the last is the coarsest
+  int k;
+  T a, b, w;
+};
+
+template <typename T>
+__device__ __forceinline__ LvArgs<T> tail_lv(const TailArgs<T>& A, int l) {
+  LvArgs<T> L;
+  L.g = A.lv[l].g;
+  L.c = A.lv[l].c;
+  L.di = A.lv[l].di;
+  L.a = A.a;
+  L.b = A.b;
+  L.w = A.w;
+  L.k = A.k;
+  return L;
+}
+
+// The tail of the V-cycle in one workgroup: for every tail level but the coarsest, the smoothed
+// residual of each cell (into the level's z buffer) and then the aggregate sums into the next
+// level's f; on the coarsest level kCoarseSweeps damped Jacobi sweeps with the coefficients and the
+// iterate in LDS; then the prolongations and post-sweeps back up to the first tail level.  Each pass
+// ends with a workgroup barrier, which also orders the global-memory hand-over between passes (all
+// waves share one CU).  Sums over an aggregate run over its children in the same fixed order as the
+// multi-workgroup restriction.
+template <typename T, int CW>
+__global__ __launch_bounds__(kTailThreads) void mg_tail_kernel(TailArgs<T> A) {
   __shared__ T xs[2][kCoarsestMax * BKTS_MAX_K];
-  const int64_t n = L.g.N * L.k;
-  for (int64_t e = threadIdx.x; e < n; e += blockDim.x) {
-    const int64_t r = e / L.k;
-    xs[0][e] = L.w * f[e] * L.di[r];
-  }
-  __syncthreads();
-  int cur = 0;
-  for (int it = 1; it < kCoarseSweeps; ++it) {
-    for (int64_t e = threadIdx.x; e < n; e += blockDim.x) {
-      const int64_t r = e / L.k;
-      const int col = (int)(e - r * L.k);
+  __shared__ T cs[6 * kCoarsestMax];  // the coarsest level's 5 coefficient arrays and its inverse diagonal
+  const int t = threadIdx.x;
+  const int k = A.k;
+  const int nch = k / CW;
+  for (int l = 0; l + 1 < A.nl; ++l) {
+    const LvArgs<T> L = tail_lv(A, l);
+    const T* f = A.lv[l].f;
+    T* s = A.lv[l].z;
+    const int64_t n = L.g.N * nch;
+    for (int64_t e = t; e < n; e += kTailThreads) {
+      const int64_t i = e / nch;
+      const int c0 = (int)(e - i * nch) * CW;
       int ix, iy, iz;
-      coords(L.g, r, ix, iy, iz);
-      T yr[1] = {xs[cur][e]}, ay[1];
-      apply_row<T, 1>(L, r, ix, iy, iz, yr, [&](int64_t q, T(&y)[1]) { y[0] = xs[cur][q * L.k + col]; }, ay);
-      xs[cur ^ 1][e] = yr[0] + L.w * (f[e] - ay[0]) * L.di[r];
+      coords(L.g, i, ix, iy, iz);
+      T v[CW];
+      smoothed_residual<T, CW>(L, f, i, ix, iy, iz, c0, v);
+      st_cw<T, CW>(s + i * k + c0, v);
     }
     __syncthreads();
-    cur ^= 1;
+    const Geo g = L.g, gc = A.lv[l + 1].g;
+    T* fc = A.lv[l + 1].f;
+    const int64_t nc = gc.N * nch;
+    for (int64_t e = t; e < nc; e += kTailThreads) {
+      const int64_t R = e / nch;
+      const int c0 = (int)(e - R * nch) * CW;
+      int X, Y, Z;
+      coords(gc, R, X, Y, Z);
+      T sum[CW];
+#pragma unroll
+      for (int j = 0; j < CW; ++j) sum[j] = T(0);
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int ix = 2 * X + (q & 1), iy = 2 * Y + ((q >> 1) & 1), iz = 2 * Z + (q >> 2);
+        if (ix < g.nx && iy < g.ny && iz < g.nz) {
+          T v[CW];
+          ld_cw<T, CW>(s + (ix + g.sy * iy + g.sz * iz) * k + c0, v);
+#pragma unroll
+          for (int j = 0; j < CW; ++j) sum[j] += v[j];
+        }
+      }
+      st_cw<T, CW>(fc + R * k + c0, sum);
+    }
+    __syncthreads();
   }
-  for (int64_t e = threadIdx.x; e < n; e += blockDim.x) z[e] = xs[cur][e];
+  {  // coarsest level
+    const int l = A.nl - 1;
+    LvArgs<T> L = tail_lv(A, l);
+    const int64_t N = L.g.N;
+    for (int64_t e = t; e < 5 * N; e += kTailThreads) cs[e] = L.c[e];
+    for (int64_t e = t; e < N; e += kTailThreads) cs[5 * N + e] = L.di[e];
+    __syncthreads();
+    L.c = cs;
+    L.di = cs + 5 * N;
+    const T* f = A.lv[l].f;
+    const int64_t n = N * k;
+    for (int64_t e = t; e < n; e += kTailThreads) {
+      const int64_t r = e / k;
+      xs[0][e] = L.w * f[e] * L.di[r];
+    }
+    __syncthreads();
+    int cur = 0;
+    for (int it = 1; it < kCoarseSweeps; ++it) {
+      for (int64_t e = t; e < n; e += kTailThreads) {
+        const int64_t r = e / k;
+        const int col = (int)(e - r * k);
+        int ix, iy, iz;
+        coords(L.g, r, ix, iy, iz);
+        T yr[1] = {xs[cur][e]}, ay[1];
+        apply_row<T, 1>(L, r, ix, iy, iz, yr,
+                        [&](int64_t q, int, int, int, T(&y)[1]) { y[0] = xs[cur][q * k + col]; }, ay);
+        xs[cur ^ 1][e] = yr[0] + L.w * (f[e] - ay[0]) * L.di[r];
+      }
+      __syncthreads();
+      cur ^= 1;
+    }
+    T* z = A.lv[l].z;
+    for (int64_t e = t; e < n; e += kTailThreads) z[e] = xs[cur][e];
+    __syncthreads();
+  }
+  for (int l = A.nl - 2; l >= 0; --l) {
+    const LvArgs<T> L = tail_lv(A, l);
+    const Geo gc = A.lv[l + 1].g;
+    const T* f = A.lv[l].f;
+    const T* xc = A.lv[l + 1].z;
+    T* z = A.lv[l].z;
+    const int64_t n = L.g.N * nch;
+    for (int64_t e = t; e < n; e += kTailThreads) {
+      const int64_t i = e / nch;
+      const int c0 = (int)(e - i * nch) * CW;
+      int ix, iy, iz;
+      coords(L.g, i, ix, iy, iz);
+      T zr[CW], fr[CW];
+      prolong_row<T, CW>(L, gc, f, xc, i, ix, iy, iz, c0, zr, fr);
+      st_cw<T, CW>(z + i * k + c0, zr);
+    }
+    __syncthreads();
+  }
+}
+
+// First level of the tail for block width k.
+int tail_start(const MgHier& h, int k) {
+  const int nl = (int)h.lv.size();
+  int t0 = 0;
+  while (t0 + 1 < nl && h.lv[t0].N * k > kTailElems) ++t0;
+  return t0;
 }
 
 int chunk_width(int k) { return k % 4 == 0 ? 4 : (k % 2 == 0 ? 2 : 1); }
@@ -296,44 +541,128 @@ LvArgs<T> lv_args(const MgLevel& l, int k, double a, double b) {
   return L;
 }
 
+// Persistent grid of the prolongation: the resident capacity of the chip, capped by the row chunks.
+template <typename K>
+int64_t prolong_grid(bkts_ctx ctx, K kernel, int64_t N) {
+  int64_t nb = (int64_t)blocks_per_cu(reinterpret_cast<const void*>(kernel)) * ctx->num_cu;
+  const int64_t chunks = (N + 255) / 256;
+  if (nb > chunks) nb = chunks;
+  return nb < 1 ? 1 : nb;
+}
+
+template <typename T, int CW, bool GRAM>
+void launch_prolong(bkts_ctx ctx, const LvArgs<T>& L, const Geo& gc, const T* f, const T* xc, T* z, const T* Q,
+                    double* partials, int64_t nb) {
+  launch(ctx, (mg_prolong_kernel<T, CW, GRAM>), dim3((unsigned)nb), dim3(256), 0, L, gc, f, xc, z, Q, partials);
+}
+
+template <typename T, int CW, bool GRAM>
+void prolong_level(bkts_ctx ctx, const LvArgs<T>& L, const Geo& gc, const T* f, const T* xc, T* z) {
+  const int64_t nb = prolong_grid(ctx, mg_prolong_kernel<T, CW, GRAM>, L.g.N);
+  launch_prolong<T, CW, GRAM>(ctx, L, gc, f, xc, z, nullptr, nullptr, nb);
+}
+
+// Finest prolongation with the fused reductions: partials of NA = 2k^2 + k entries per workgroup.
+template <typename T, int CW>
+void prolong_fused(bkts_ctx ctx, const LvArgs<T>& L, const Geo& gc, const T* f, const T* xc, T* z, MgFuse* fuse,
+                   const std::string& tag) {
+  const int64_t nb = prolong_grid(ctx, mg_prolong_kernel<T, CW, true>, L.g.N);
+  double* part = ctx->ws.get<double>("mg_fuse_part" + tag, (size_t)(2 * CW * CW + CW) * nb);
+  launch_prolong<T, CW, true>(ctx, L, gc, f, xc, z, static_cast<const T*>(fuse->Q), part, nb);
+  fuse->partials = part;
+  fuse->nslots = nb;
+}
+
 template <typename T>
-void vcycle(bkts_ctx ctx, const MgHier& h, int lvl, int k, double a, double b, const T* f, T* z) {
-  const MgLevel& l = h.lv[lvl];
-  const LvArgs<T> L = lv_args<T>(l, k, a, b);
+void vcycle(bkts_ctx ctx, MgHier& h, int k, double a, double b, const T* f, T* z, MgFuse* fuse) {
+  const int nl = (int)h.lv.size();
   const double sv = sizeof(T);
-  if (lvl + 1 == (int)h.lv.size()) {
-    ProfScope prof(ctx, BKTS_K_MG_COARSE, sv * (2.0 * l.N * k + 4.0 * l.N));
-    launch(ctx, (mg_coarse_kernel<T>), dim3(1), dim3(256), 0, L, f, z);
-    return;
+  const std::string tag = sizeof(T) == 8 ? "d" : "s";
+  // per-level right-hand sides and iterates: the caller's F and Z on level 0, workspace below
+  std::vector<T*> fb(nl), zb(nl);
+  fb[0] = const_cast<T*>(f);
+  zb[0] = z;
+  for (int l = 1; l < nl; ++l) {
+    fb[l] = ctx->ws.get<T>("mg_f" + std::to_string(l) + tag, (size_t)h.lv[l].N * k);
+    zb[l] = ctx->ws.get<T>("mg_x" + std::to_string(l) + tag, (size_t)h.lv[l].N * k);
   }
-  const MgLevel& lc = h.lv[lvl + 1];
-  const Geo gc = geo_of(lc);
-  const std::string tag = std::to_string(lvl + 1) + (sizeof(T) == 8 ? "d" : "s");
-  T* fc = ctx->ws.get<T>("mg_f" + tag, (size_t)lc.N * k);
-  T* xc = ctx->ws.get<T>("mg_x" + tag, (size_t)lc.N * k);
+  const int t0 = tail_start(h, k);
   const int cw = chunk_width(k);
-  const dim3 gr((unsigned)((lc.n[0] + 31) / 32), (unsigned)lc.n[1], (unsigned)lc.n[2]);
-  const dim3 gp((unsigned)((l.N + 255) / 256));
-  {  // algorithmic bytes: f, the inverse diagonal and the 3 coupling arrays read, the coarse f written
-    ProfScope prof(ctx, lvl == 0 ? BKTS_K_MG_RESTRICT : BKTS_K_MG_COARSE,
-                   sv * (1.0 * l.N * k + 4.0 * l.N + 1.0 * lc.N * k));
+  for (int l = 0; l < t0; ++l) {
+    const MgLevel& lf = h.lv[l];
+    const MgLevel& lc = h.lv[l + 1];
+    const LvArgs<T> L = lv_args<T>(lf, k, a, b);
+    const Geo gc = geo_of(lc);
+    const int gx = (lc.n[0] + 31) / 32;
+    const int64_t nbr = (int64_t)gx * lc.n[1] * lc.n[2];
+    BKTS_REQUIRE(nbr < ((int64_t)1 << 31), "multigrid: grid too large for the restriction launch");
+    // algorithmic bytes: f, the inverse diagonal and the 3 coupling arrays read, the coarse f written
+    ProfScope prof(ctx, l == 0 ? BKTS_K_MG_RESTRICT : BKTS_K_MG_COARSE,
+                   sv * (1.0 * lf.N * k + 4.0 * lf.N + 1.0 * lc.N * k));
+    const dim3 gr((unsigned)nbr);
     if (cw == 4)
-      launch(ctx, (mg_restrict_kernel<T, 4>), gr, dim3(256), 0, L, gc, f, fc);
+      launch(ctx, (mg_restrict_kernel<T, 4>), gr, dim3(256), 0, L, gc, gx, (const T*)fb[l], fb[l + 1]);
     else if (cw == 2)
-      launch(ctx, (mg_restrict_kernel<T, 2>), gr, dim3(256), 0, L, gc, f, fc);
+      launch(ctx, (mg_restrict_kernel<T, 2>), gr, dim3(256), 0, L, gc, gx, (const T*)fb[l], fb[l + 1]);
     else
-      launch(ctx, (mg_restrict_kernel<T, 1>), gr, dim3(256), 0, L, gc, f, fc);
+      launch(ctx, (mg_restrict_kernel<T, 1>), gr, dim3(256), 0, L, gc, gx, (const T*)fb[l], fb[l + 1]);
   }
-  vcycle<T>(ctx, h, lvl + 1, k, a, b, fc, xc);
-  // algorithmic bytes: f, the coarse x, the inverse diagonal and the 3 coupling arrays read, z written
-  ProfScope prof(ctx, lvl == 0 ? BKTS_K_MG_PROLONG : BKTS_K_MG_COARSE,
-                 sv * (2.0 * l.N * k + 4.0 * l.N + 1.0 * lc.N * k));
-  if (cw == 4)
-    launch(ctx, (mg_prolong_kernel<T, 4>), gp, dim3(256), 0, L, gc, f, (const T*)xc, z);
-  else if (cw == 2)
-    launch(ctx, (mg_prolong_kernel<T, 2>), gp, dim3(256), 0, L, gc, f, (const T*)xc, z);
-  else
-    launch(ctx, (mg_prolong_kernel<T, 1>), gp, dim3(256), 0, L, gc, f, (const T*)xc, z);
+  {
+    TailArgs<T> A{};
+    A.nl = nl - t0;
+    A.k = k;
+    A.a = (T)a;
+    A.b = (T)b;
+    A.w = (T)kOmega;
+    double bytes = 0.0;
+    for (int l = t0; l < nl; ++l) {
+      const LvArgs<T> L = lv_args<T>(h.lv[l], k, a, b);
+      TailLv<T>& tl = A.lv[l - t0];
+      tl.g = L.g;
+      tl.c = L.c;
+      tl.di = L.di;
+      tl.f = fb[l];
+      tl.z = zb[l];
+      bytes += sv * (2.0 * h.lv[l].N * k + 4.0 * h.lv[l].N);
+    }
+    ProfScope prof(ctx, BKTS_K_MG_COARSE, bytes);
+    if (cw == 4)
+      launch(ctx, (mg_tail_kernel<T, 4>), dim3(1), dim3(kTailThreads), 0, A);
+    else if (cw == 2)
+      launch(ctx, (mg_tail_kernel<T, 2>), dim3(1), dim3(kTailThreads), 0, A);
+    else
+      launch(ctx, (mg_tail_kernel<T, 1>), dim3(1), dim3(kTailThreads), 0, A);
+  }
+  const bool gram = fuse && t0 >= 1 && (k == 1 || k == 2 || k == 4);
+  if (fuse) fuse->nslots = 0;
+  for (int l = t0 - 1; l >= 0; --l) {
+    const MgLevel& lf = h.lv[l];
+    const MgLevel& lc = h.lv[l + 1];
+    const LvArgs<T> L = lv_args<T>(lf, k, a, b);
+    const Geo gc = geo_of(lc);
+    const T* fl = fb[l];
+    const T* xc = zb[l + 1];
+    T* zl = zb[l];
+    // algorithmic bytes: f, the coarse x, the inverse diagonal and the 3 coupling arrays read, z
+    // written (and Q read when the reductions are fused)
+    const bool g = gram && l == 0;
+    ProfScope prof(ctx, l == 0 ? BKTS_K_MG_PROLONG : BKTS_K_MG_COARSE,
+                   sv * ((g ? 3.0 : 2.0) * lf.N * k + 4.0 * lf.N + 1.0 * lc.N * k));
+    if (g) {
+      if (k == 4)
+        prolong_fused<T, 4>(ctx, L, gc, fl, xc, zl, fuse, tag);
+      else if (k == 2)
+        prolong_fused<T, 2>(ctx, L, gc, fl, xc, zl, fuse, tag);
+      else
+        prolong_fused<T, 1>(ctx, L, gc, fl, xc, zl, fuse, tag);
+    } else if (cw == 4) {
+      prolong_level<T, 4, false>(ctx, L, gc, fl, xc, zl);
+    } else if (cw == 2) {
+      prolong_level<T, 2, false>(ctx, L, gc, fl, xc, zl);
+    } else {
+      prolong_level<T, 1, false>(ctx, L, gc, fl, xc, zl);
+    }
+  }
 }
 
 }  // namespace
@@ -361,11 +690,10 @@ static MgHier* mg_build(bkts_op op) {
   launch(ctx, mg_level0, dim3((unsigned)((l0.N + 255) / 256)), dim3(256), 0, l0.N, op->st_na,
          op->st_coef.as<double>(), sel[0], sel[1], sel[2], l0.c64.as<double>());
   h->lv.push_back(std::move(l0));
-  while (h->lv.back().N > kCoarsestMax && h->lv.size() < 16) {
+  while (h->lv.back().N > kCoarsestMax && (int)h->lv.size() < kMaxLevels) {
     const MgLevel& f = h->lv.back();
     MgLevel c;
     for (int d = 0; d < 3; ++d) c.n[d] = (f.n[d] + 1) / 2;
-    BKTS_REQUIRE(c.n[1] <= 65535 && c.n[2] <= 65535, "multigrid: grid too tall for the restriction launch");
     c.N = (int64_t)c.n[0] * c.n[1] * c.n[2];
     c.c64.alloc(sizeof(double) * 5 * c.N);
     c.c32.alloc(sizeof(float) * 5 * c.N);
@@ -385,7 +713,15 @@ static MgHier* mg_build(bkts_op op) {
   return h.release();
 }
 
-void mg_vcycle(bkts_ctx ctx, const bkts_op_s& op, int dtype, int k, double a, double b, const void* F, void* Z) {
+bool mg_fusable(bkts_ctx ctx, const bkts_op_s& op, int k) {
+  (void)ctx;
+  if (!(k == 1 || k == 2 || k == 4)) return false;
+  if (!op.mg) op.mg.reset(mg_build(const_cast<bkts_op>(&op)), mg_hier_delete);
+  return tail_start(*op.mg, k) >= 1;
+}
+
+void mg_vcycle(bkts_ctx ctx, const bkts_op_s& op, int dtype, int k, double a, double b, const void* F, void* Z,
+               MgFuse* fuse) {
   BKTS_REQUIRE(k >= 1 && k <= BKTS_MAX_K, "k out of range");
   if (!op.mg) op.mg.reset(mg_build(const_cast<bkts_op>(&op)), mg_hier_delete);
   MgHier& h = *op.mg;
@@ -397,9 +733,9 @@ void mg_vcycle(bkts_ctx ctx, const bkts_op_s& op, int dtype, int k, double a, do
     h.b = b;
   }
   if (dtype == BKTS_F64)
-    vcycle<double>(ctx, *op.mg, 0, k, a, b, static_cast<const double*>(F), static_cast<double*>(Z));
+    vcycle<double>(ctx, h, k, a, b, static_cast<const double*>(F), static_cast<double*>(Z), fuse);
   else
-    vcycle<float>(ctx, *op.mg, 0, k, a, b, static_cast<const float*>(F), static_cast<float*>(Z));
+    vcycle<float>(ctx, h, k, a, b, static_cast<const float*>(F), static_cast<float*>(Z), fuse);
   BKTS_HIP(hipGetLastError());
 }
 

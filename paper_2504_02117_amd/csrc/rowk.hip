@@ -330,6 +330,52 @@ __global__ __launch_bounds__(256) void rk_cg_update_kernel(RkUpdArgs a) {
   fold_block<NA>(acc, red, a.partials);
 }
 
+// X += P alpha; R -= Q alpha and nothing else (the reductions that follow come from another pass).
+// Two rows per thread per step, loads of both issued first.
+template <typename T, int KP>
+__global__ __launch_bounds__(256) void rk_cg_xr_kernel(int64_t N, T* __restrict__ X, const T* __restrict__ P,
+                                                       T* __restrict__ R, const T* __restrict__ Q,
+                                                       const double* alpha) {
+  double al[KP * KP];
+#pragma unroll
+  for (int e = 0; e < KP * KP; ++e) al[e] = alpha[e];
+  const RowRange rr = block_rows(N);
+  constexpr int GR = 2;
+  for (int64_t r0 = rr.begin + threadIdx.x; r0 < rr.end; r0 += GR * dev::kThreads) {
+    Row<T, KP> p[GR], q[GR], x[GR], rv[GR];
+    bool ok[GR];
+#pragma unroll
+    for (int h = 0; h < GR; ++h) {
+      const int64_t r = r0 + h * dev::kThreads;
+      ok[h] = r < rr.end;
+      if (ok[h]) {
+        p[h] = ld_row<T, KP>(P + r * KP, KP);
+        q[h] = ld_row<T, KP>(Q + r * KP, KP);
+        x[h] = ld_row<T, KP>(X + r * KP, KP);
+        rv[h] = ld_row<T, KP>(R + r * KP, KP);
+      }
+    }
+#pragma unroll
+    for (int h = 0; h < GR; ++h) {
+      if (!ok[h]) continue;
+      const int64_t r = r0 + h * dev::kThreads;
+#pragma unroll
+      for (int c = 0; c < KP; ++c) {
+        double xs = (double)x[h].v[c], rs = (double)rv[h].v[c];
+#pragma unroll
+        for (int j = 0; j < KP; ++j) {
+          xs = fma((double)p[h].v[j], al[j * KP + c], xs);
+          rs = fma(-(double)q[h].v[j], al[j * KP + c], rs);
+        }
+        x[h].v[c] = (T)xs;
+        rv[h].v[c] = (T)rs;
+      }
+      st_row<T, KP>(X + r * KP, x[h]);
+      st_row<T, KP>(R + r * KP, rv[h]);
+    }
+  }
+}
+
 // P = D^-1 R + P beta   (beta == nullptr: P = D^-1 R)
 template <typename T, int KP>
 __global__ __launch_bounds__(256) void rk_cg_pupdate_kernel(int64_t N, T* __restrict__ P, const T* __restrict__ R,
@@ -563,6 +609,23 @@ void rk_cg_update(bkts_ctx ctx, int dtype, int64_t N, int k, void* X, const void
     BKTS_RK_DISPATCH(k, (rk_cg_update_t<double, KP>(ctx, N, X, P, R, Q, alpha, dinv, gamma, Tm, nrm, tail)));
   else
     BKTS_RK_DISPATCH(k, (rk_cg_update_t<float, KP>(ctx, N, X, P, R, Q, alpha, dinv, gamma, Tm, nrm, tail)));
+}
+
+template <typename T, int KP>
+static void rk_cg_xr_t(bkts_ctx ctx, int64_t N, void* X, const void* P, void* R, const void* Q, const double* alpha) {
+  const int64_t nb = rk_grid(ctx, rk_cg_xr_kernel<T, KP>, N);
+  ProfScope prof(ctx, BKTS_K_CG_UPDATE, 6.0 * N * KP * sizeof(T));
+  launch(ctx, (rk_cg_xr_kernel<T, KP>), dim3(nb), dim3(256), 0, N, static_cast<T*>(X), static_cast<const T*>(P),
+         static_cast<T*>(R), static_cast<const T*>(Q), alpha);
+  BKTS_HIP(hipGetLastError());
+}
+
+void rk_cg_xr_update(bkts_ctx ctx, int dtype, int64_t N, int k, void* X, const void* P, void* R, const void* Q,
+                     const double* alpha) {
+  if (dtype == BKTS_F64)
+    BKTS_RK_DISPATCH(k, (rk_cg_xr_t<double, KP>(ctx, N, X, P, R, Q, alpha)));
+  else
+    BKTS_RK_DISPATCH(k, (rk_cg_xr_t<float, KP>(ctx, N, X, P, R, Q, alpha)));
 }
 
 template <typename T, int KP>

@@ -57,6 +57,10 @@ GRIDS = [
     ((1, 7, 9), {}),
     ((9, 5, 1), {}),
     ((3, 3, 3), {}),  # a single level: the coarsest solve alone
+    # large enough (N k > 16384 for every k here) for multi-workgroup restriction and prolongation
+    # above the single-workgroup tail, and for the block-CG reductions folded into the finest one
+    ((37, 29, 23), {(1, 0): ("dirichlet", 0.5), (0, 1): ("neumann",)}),
+    ((181, 150), {(0, 0): ("neumann",)}),
 ]
 
 
@@ -163,7 +167,7 @@ def test_mg_rejections(env):
         bkts.bkts_op_destroy(op_sell)
 
 
-@pytest.mark.parametrize("gi", [0, 1, 2, 3, 5])
+@pytest.mark.parametrize("gi", [0, 1, 2, 3, 5, 6, 7])
 @pytest.mark.parametrize("k", [1, 3, 4])
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 def test_mg_apply_matches_oracle_vcycle(env, gi, k, dtype):
