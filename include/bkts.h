@@ -179,6 +179,19 @@ bkts_status bkts_mg_apply(bkts_ctx ctx, bkts_op op, int dtype, int k, double a, 
 bkts_status bkts_gram(bkts_ctx ctx, int dtype, int64_t N, int k, const void* X, int ldx,
                       const void* Y, int ldy, double* G);
 
+/* Allocation-free variant of bkts_gram, for callers that cannot allocate device
+ * memory: code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  Same arguments, checks and result as bkts_gram (FP64 accumulation in a
+ * fixed order; the fold may differ from bkts_gram's in the last bits).  The
+ * per-workgroup partials live in a fixed 4 MiB device array of the library (one
+ * copy per GPU, held until the process ends; its address is recorded when a
+ * context is created on that GPU), and the number of partials is capped to fit it,
+ * so every N is accepted; a fit failure would return BKTS_EINVAL.  The call
+ * enqueues two kernels on the ctx stream and calls no allocator.  Calls that
+ * overlap on one GPU (other contexts or streams) share the array and race. */
+bkts_status bkts_gram_noalloc(bkts_ctx ctx, int dtype, int64_t N, int k, const void* X, int ldx,
+                              const void* Y, int ldy, double* G);
+
 /* ------------------------------------------------------------ time coupling */
 
 enum { BKTS_IE = 0, BKTS_THETA = 1, BKTS_SDIRK2 = 2, BKTS_DIRK_CUSTOM = 3, BKTS_RADAU2 = 4 };

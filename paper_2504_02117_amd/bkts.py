@@ -123,6 +123,7 @@ _SIGS = {
     "bkts_op_destroy": (None, [_P]),
     "bkts_spmm": (_I, [_P, _P, _I, _I, _D, _D, _P, _I, _P, _I]),
     "bkts_gram": (_I, [_P, _I, _I64, _I, _P, _I, _P, _I, _P]),
+    "bkts_gram_noalloc": (_I, [_P, _I, _I64, _I, _P, _I, _P, _I, _P]),
     "bkts_mg_apply": (_I, [_P, _P, _I, _I, _D, _D, _P, _I, _P, _I]),
     "bkts_tc_create": (_I, [_P, C.POINTER(bkts_tc_desc), C.POINTER(_P)]),
     "bkts_tc_get": (_I, [_P, _I, _P, _P, C.POINTER(_D), C.POINTER(_I), C.POINTER(_I)]),
@@ -277,6 +278,12 @@ def bkts_gram(ctx, X, Y, G):
     """G (k x k float64 device tensor) = X^T Y."""
     N, k = X.shape
     _check(_lib.bkts_gram(ctx, _dtype_code(X), N, k, _ptr(X), X.stride(0), _ptr(Y), Y.stride(0), _ptr(G)))
+
+
+def bkts_gram_noalloc(ctx, X, Y, G):
+    """G (k x k float64 device tensor) = X^T Y, partials in the library's fixed scratch array."""
+    N, k = X.shape
+    _check(_lib.bkts_gram_noalloc(ctx, _dtype_code(X), N, k, _ptr(X), X.stride(0), _ptr(Y), Y.stride(0), _ptr(G)))
 
 
 def bkts_mg_apply(ctx, op, F, Z, a, b):

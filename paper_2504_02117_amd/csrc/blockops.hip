@@ -8,6 +8,9 @@
 // matrices and for Gram accumulation).  Each persistent workgroup walks one contiguous range of
 // tiles (XCD-aware) and leaves one partial k x k result; finalize_partials() folds the partials in
 // a fixed order, so results are bitwise reproducible.
+#include <map>
+#include <mutex>
+
 #include "devcommon.hpp"
 #include "internal.hpp"
 #include "wide.hpp"
@@ -481,6 +484,66 @@ void gram(bkts_ctx ctx, int dtype, int64_t N, int k, const void* X, int ldx, con
   auto al16 = [](const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; };
   if (rk_eligible(k) && ldx == k && ldy == k && al16(X) && al16(Y)) return rk_gram(ctx, dtype, N, k, X, Y, G);
   BKTS_KP_DISPATCH(k, (launch_gram_t<KP>(ctx, dtype, N, k, X, ldx, Y, ldy, G)));
+}
+
+// ---------------------------------------------------------------- allocation-free Gram
+// bkts_gram_noalloc keeps its per-workgroup partials in this fixed array instead of the context's
+// workspace.  Each GPU holds its own copy until the process ends; host code never passes the array's
+// name to a kernel (on the host it is only a stand-in) but the address hipGetSymbolAddress returned
+// for the device, recorded once per device when a context is created on it.  Every workgroup writes
+// all of its partials before the fold reads them, so nothing needs clearing between calls; calls
+// that overlap on one GPU share the array and race.
+constexpr size_t kScratchDoubles = 512 * 1024;  // 4 MiB
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+namespace {
+std::mutex g_scratch_mu;
+std::map<int, double*> g_scratch_addr;  // device ordinal -> that device's copy of `scratch`
+
+double* scratch_of(int device) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  auto it = g_scratch_addr.find(device);
+  BKTS_REQUIRE(it != g_scratch_addr.end(), "no scratch address recorded for device %d", device);
+  return it->second;
+}
+
+template <int KP>
+void gram_noalloc_t(bkts_ctx ctx, int dtype, int64_t N, int k, const void* X, int ldx, const void* Y, int ldy,
+                    double* G) {
+  double* part = scratch_of(ctx->device);
+  Slots s = make_slots<KP>(ctx, N);
+  const int64_t cap = (int64_t)(kScratchDoubles / (KP * KP));  // slots whose partials fit the array
+  if (s.nslots > cap) {
+    s.tps = (s.ntiles + cap - 1) / cap;
+    s.nslots = (s.ntiles + s.tps - 1) / s.tps;
+  }
+  BKTS_REQUIRE((size_t)KP * KP * s.nslots <= kScratchDoubles,
+               "bkts_gram_noalloc: %lld partials exceed the %zu-entry scratch array",
+               (long long)(KP * KP * s.nslots), kScratchDoubles);
+  if (dtype == BKTS_F64)
+    launch(ctx, (gram_kernel<double, KP>), dim3(s.nslots), dim3(256), 0, N, k, static_cast<const double*>(X), ldx,
+           static_cast<const double*>(Y), ldy, part, s.tps);
+  else
+    launch(ctx, (gram_kernel<float, KP>), dim3(s.nslots), dim3(256), 0, N, k, static_cast<const float*>(X), ldx,
+           static_cast<const float*>(Y), ldy, part, s.tps);
+  BKTS_HIP(hipGetLastError());
+  launch(ctx, finalize_kernel, dim3(k * k), dim3(256), 0, (const double*)part, s.nslots, k, KP, 0, G);
+  BKTS_HIP(hipGetLastError());
+}
+}  // namespace
+
+void scratch_init(int device) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_addr.count(device)) return;
+  void* p = nullptr;
+  BKTS_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+  BKTS_REQUIRE(p, "hipGetSymbolAddress returned no address for the scratch array on device %d", device);
+  g_scratch_addr[device] = static_cast<double*>(p);
+}
+
+void gram_noalloc(bkts_ctx ctx, int dtype, int64_t N, int k, const void* X, int ldx, const void* Y, int ldy,
+                  double* G) {
+  BKTS_KP_DISPATCH(k, (gram_noalloc_t<KP>(ctx, dtype, N, k, X, ldx, Y, ldy, G)));
 }
 
 void col_dots(bkts_ctx ctx, int dtype, int64_t N, int k, int npairs, const void* const* X, const void* const* Y,

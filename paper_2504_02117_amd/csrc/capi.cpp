@@ -71,6 +71,12 @@ bkts_status bkts_ctx_create(int device, void* hip_stream, bkts_ctx* out) {
   int ncu = 0;
   if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && ncu > 0)
     c->num_cu = ncu;
+  try {
+    bkts::scratch_init(device);  // this device's address of the allocation-free entry point's array
+  } catch (...) {
+    delete c;
+    throw;
+  }
   *out = c;
   BKTS_API_END
 }
@@ -192,6 +198,21 @@ bkts_status bkts_gram(bkts_ctx ctx, int dtype, int64_t N, int k, const void* X, 
   BKTS_REQUIRE(G, "G must not be NULL");
   set_device(ctx);
   bkts::gram(ctx, dtype, N, k, X, ldx, Y, ldy, G);
+  BKTS_API_END
+}
+
+bkts_status bkts_gram_noalloc(bkts_ctx ctx, int dtype, int64_t N, int k, const void* X, int ldx, const void* Y,
+                              int ldy, double* G) {
+  BKTS_API_BEGIN
+  check_ctx(ctx);
+  BKTS_REQUIRE(dtype == BKTS_F64 || dtype == BKTS_F32, "dtype must be BKTS_F64 or BKTS_F32");
+  BKTS_REQUIRE(N >= 0, "N must be >= 0");
+  check_k(k);
+  check_block(X, k, ldx, "X");
+  check_block(Y, k, ldy, "Y");
+  BKTS_REQUIRE(G, "G must not be NULL");
+  set_device(ctx);
+  bkts::gram_noalloc(ctx, dtype, N, k, X, ldx, Y, ldy, G);
   BKTS_API_END
 }
 

@@ -287,6 +287,12 @@ void nl_residual(bkts_ctx ctx, const bkts_nlop_s& nl, int k, const double* Y, in
 void spmm(bkts_ctx ctx, const bkts_op_s& op, int dtype, int k, double cb, const void* B, int ldb,
           double alpha, const void* X, int ldx, double beta, void* Y, int ldy);
 
+// G = X^T Y with the partials in the library's fixed per-device scratch array (no allocation);
+// scratch_init(device) records that device's address of the array (device current, once).
+void gram_noalloc(bkts_ctx ctx, int dtype, int64_t N, int k, const void* X, int ldx, const void* Y, int ldy,
+                  double* G);
+void scratch_init(int device);
+
 // Reductions produce per-block partials that finalize_partials() folds, in a fixed order.
 int reduce_blocks(bkts_ctx ctx, int64_t N, int k);
 void finalize_partials(bkts_ctx ctx, const double* partials, int nblocks, int nentries, double* out);
