@@ -121,6 +121,7 @@ struct bkts_ctx_s {
   bkts::Profiler prof;
   bkts::DevBuf tail_counters;  // zero-initialised device words for fold+solve launches
   unsigned* tail_counter(int i);
+
   double* host_stage(size_t count);  // pinned buffer of at least `count` doubles
   void sync();
 };
@@ -341,6 +342,12 @@ void rk_cg_pupdate(bkts_ctx ctx, int dtype, int64_t N, int k, void* P, const voi
 // X += P alpha, R -= Q alpha with no reductions (the multigrid prolongation folds them instead)
 void rk_cg_xr_update(bkts_ctx ctx, int dtype, int64_t N, int k, void* X, const void* P, void* R, const void* Q,
                      const double* alpha);
+// The two halves on their own: R -= Q alpha, and X += P alpha
+void rk_cg_r_update(bkts_ctx ctx, int dtype, int64_t N, int k, void* R, const void* Q, const double* alpha);
+void rk_cg_x_update(bkts_ctx ctx, int dtype, int64_t N, int k, void* X, const void* P, const double* alpha);
+// X += P alpha and P = Z + P beta in one pass (both read the old P)
+void rk_cg_xp_update(bkts_ctx ctx, int dtype, int64_t N, int k, void* X, void* P, const void* Z, const double* alpha,
+                     const double* beta);
 void rk_gram(bkts_ctx ctx, int dtype, int64_t N, int k, const void* X, const void* Y, double* G);
 // G1 = X1^T Y and G2 = X2^T Y in one pass (k in {1, 2, 4}, contiguous blocks)
 void rk_gram2(bkts_ctx ctx, int dtype, int64_t N, int k, const void* X1, const void* X2, const void* Y, double* G1,

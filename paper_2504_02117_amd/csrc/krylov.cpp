@@ -259,7 +259,9 @@ void block_pcg_mg(bkts_ctx ctx, const bkts_op_s& op, int dtype, int k, double a,
   // k <= 4 on a hierarchy with a separate finest prolongation: the V-cycle's last pass folds
   // gamma = R^T Z, T = Q^T Z and the norms of R, one launch folds those partials and solves for beta
   // (writing the norms and the deflation count to pinned host memory), and the Gram of the SpMM pass
-  // is folded and solved for alpha in one launch: 12 launches per iteration instead of 20.
+  // is folded and solved for alpha in one launch: 12 launches per iteration instead of 20.  The
+  // update is split: R -= Q alpha feeds the V-cycle, and X += P alpha joins the direction update
+  // P = Z + P beta after it, in one pass that reads the old P once for both.
   const bool fused = rowk && mg_fusable(ctx, op, k);
   CgTail tail_sg, tail_up;
   if (fused) {
@@ -287,7 +289,7 @@ void block_pcg_mg(bkts_ctx ctx, const bkts_op_s& op, int dtype, int k, double a,
     double* hn = hbuf_dev + slot * (k + 2);
     if (fused) {
       rk_spmm_gram(ctx, op, dtype, k, a, P, b, Q, s.G, &tail_sg);  // also alpha = G^+ gamma
-      rk_cg_xr_update(ctx, dtype, N, k, X, P, R, Q, s.alpha);
+      rk_cg_r_update(ctx, dtype, N, k, R, Q, s.alpha);
     } else {
       if (rowk) {  // Q = a P + b K P with G = P^T Q folded from the same pass
         rk_spmm_gram(ctx, op, dtype, k, a, P, b, Q, s.G, nullptr);
@@ -303,6 +305,8 @@ void block_pcg_mg(bkts_ctx ctx, const bkts_op_s& op, int dtype, int k, double a,
     // the norms of iteration it-1 (in the fused form they come after its V-cycle, which the GPU
     // finished before starting this iteration's SpMM)
     const int state = it > 1 ? check(it - 1) : 0;
+    // this iteration's X += P alpha on its own when no direction update follows
+    if (fused && state != 0) rk_cg_x_update(ctx, dtype, N, k, X, P, s.alpha);
     if (state == 1) {
       ctx->sync();  // iteration `it` is in flight; it only improves X
       st.iterations = it;
@@ -331,6 +335,8 @@ void block_pcg_mg(bkts_ctx ctx, const bkts_op_s& op, int dtype, int k, double a,
       tail_up.host = hn;
       fold_solve(ctx, 1, k, k, fu.partials, fu.nslots, tail_up);  // gamma, T, nrm, then beta = -G^+ T
       BKTS_HIP(hipEventRecord(ev[slot], ctx->stream));
+      rk_cg_xp_update(ctx, dtype, N, k, X, P, Z, s.alpha, s.beta);  // X += P alpha; P = Z + P beta
+      continue;
     } else {
       mg_vcycle(ctx, op, dtype, k, a, b, R, Z);
       if (rowk) {

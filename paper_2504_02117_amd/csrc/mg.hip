@@ -23,7 +23,8 @@
 // neighbour lines and planes that a cell's stencil re-reads sit in that XCD's L2).  Every level
 // whose block has at most kTailElems entries, down to the coarsest solve and back up, runs in ONE
 // single-workgroup launch (the tail): its passes are separated by workgroup barriers instead of
-// kernel boundaries, and the coarsest level's coefficients and iterate live in LDS.  The finest
+// kernel boundaries; on the coarsest level the iterate lives in LDS and each thread keeps its
+// elements' couplings in registers across the sweeps.  The finest
 // prolongation can also fold the block-CG reductions that follow the preconditioner
 // (gamma = R^T Z, T = Q^T Z and the column norms of R), since it already holds R and Z per row.
 #include <memory>
@@ -414,7 +415,6 @@ __device__ __forceinline__ LvArgs<T> tail_lv(const TailArgs<T>& A, int l) {
 template <typename T, int CW>
 __global__ __launch_bounds__(kTailThreads) void mg_tail_kernel(TailArgs<T> A) {
   __shared__ T xs[2][kCoarsestMax * BKTS_MAX_K];
-  __shared__ T cs[6 * kCoarsestMax];  // the coarsest level's 5 coefficient arrays and its inverse diagonal
   const int t = threadIdx.x;
   const int k = A.k;
   const int nch = k / CW;
@@ -458,39 +458,61 @@ __global__ __launch_bounds__(kTailThreads) void mg_tail_kernel(TailArgs<T> A) {
     }
     __syncthreads();
   }
-  {  // coarsest level
+  {  // coarsest level: each thread keeps its elements' neighbour indices and coefficients in
+     // registers for all sweeps, and only the iterate moves through LDS
+    constexpr int kCE = (kCoarsestMax * BKTS_MAX_K + kTailThreads - 1) / kTailThreads;
     const int l = A.nl - 1;
-    LvArgs<T> L = tail_lv(A, l);
-    const int64_t N = L.g.N;
-    for (int64_t e = t; e < 5 * N; e += kTailThreads) cs[e] = L.c[e];
-    for (int64_t e = t; e < N; e += kTailThreads) cs[5 * N + e] = L.di[e];
-    __syncthreads();
-    L.c = cs;
-    L.di = cs + 5 * N;
+    const LvArgs<T> L = tail_lv(A, l);
+    const Geo& g = L.g;
+    const int n = (int)(g.N * k);
     const T* f = A.lv[l].f;
-    const int64_t n = N * k;
-    for (int64_t e = t; e < n; e += kTailThreads) {
-      const int64_t r = e / k;
-      xs[0][e] = L.w * f[e] * L.di[r];
+    int nb[kCE][6];
+    T cf[kCE][6], fv[kCE], dA[kCE], di[kCE];
+#pragma unroll
+    for (int i = 0; i < kCE; ++i) {
+      const int e = t + i * kTailThreads;
+      if (e < n) {
+        const int r = e / k, col = e - r * k;
+        int ix, iy, iz;
+        coords(g, r, ix, iy, iz);
+        const int pos[3] = {ix, iy, iz};
+        const int len[3] = {g.nx, g.ny, g.nz};
+        const int st[3] = {1, g.nx, g.nx * g.ny};
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {  // same neighbour order and zero-coefficient rule as apply_row
+          const T* od = L.c + (2 + d) * g.N;
+          const bool up = pos[d] + 1 < len[d], lo = pos[d] > 0;
+          const int ql = lo ? r - st[d] : r;
+          nb[i][2 * d] = (up ? r + st[d] : r) * k + col;
+          nb[i][2 * d + 1] = ql * k + col;
+          cf[i][2 * d] = L.b * od[r] * T(up ? 1 : 0);
+          cf[i][2 * d + 1] = L.b * od[ql] * T(lo ? 1 : 0);
+        }
+        di[i] = L.di[r];
+        dA[i] = T(1) / di[i];
+        fv[i] = f[e];
+        xs[0][e] = L.w * fv[i] * di[i];
+      }
     }
     __syncthreads();
     int cur = 0;
     for (int it = 1; it < kCoarseSweeps; ++it) {
-      for (int64_t e = t; e < n; e += kTailThreads) {
-        const int64_t r = e / k;
-        const int col = (int)(e - r * k);
-        int ix, iy, iz;
-        coords(L.g, r, ix, iy, iz);
-        T yr[1] = {xs[cur][e]}, ay[1];
-        apply_row<T, 1>(L, r, ix, iy, iz, yr,
-                        [&](int64_t q, int, int, int, T(&y)[1]) { y[0] = xs[cur][q * k + col]; }, ay);
-        xs[cur ^ 1][e] = yr[0] + L.w * (f[e] - ay[0]) * L.di[r];
+#pragma unroll
+      for (int i = 0; i < kCE; ++i) {
+        const int e = t + i * kTailThreads;
+        if (e < n) {
+          const T yr = xs[cur][e];
+          T ay = dA[i] * yr;
+#pragma unroll
+          for (int q = 0; q < 6; ++q) ay = fma(cf[i][q], xs[cur][nb[i][q]], ay);
+          xs[cur ^ 1][e] = yr + L.w * (fv[i] - ay) * di[i];
+        }
       }
       __syncthreads();
       cur ^= 1;
     }
     T* z = A.lv[l].z;
-    for (int64_t e = t; e < n; e += kTailThreads) z[e] = xs[cur][e];
+    for (int e = t; e < n; e += kTailThreads) z[e] = xs[cur][e];
     __syncthreads();
   }
   for (int l = A.nl - 2; l >= 0; --l) {

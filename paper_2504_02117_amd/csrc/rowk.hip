@@ -330,12 +330,13 @@ __global__ __launch_bounds__(256) void rk_cg_update_kernel(RkUpdArgs a) {
   fold_block<NA>(acc, red, a.partials);
 }
 
-// X += P alpha; R -= Q alpha and nothing else (the reductions that follow come from another pass).
-// Two rows per thread per step, loads of both issued first.
-template <typename T, int KP>
+// X += P alpha (MODE 0, 2) and R -= Q alpha (MODE 0, 1), and nothing else (the reductions that
+// follow come from another pass).  Two rows per thread per step, loads of both issued first.
+template <typename T, int KP, int MODE>
 __global__ __launch_bounds__(256) void rk_cg_xr_kernel(int64_t N, T* __restrict__ X, const T* __restrict__ P,
                                                        T* __restrict__ R, const T* __restrict__ Q,
                                                        const double* alpha) {
+  constexpr bool DX = MODE != 1, DR = MODE != 2;
   double al[KP * KP];
 #pragma unroll
   for (int e = 0; e < KP * KP; ++e) al[e] = alpha[e];
@@ -349,10 +350,14 @@ __global__ __launch_bounds__(256) void rk_cg_xr_kernel(int64_t N, T* __restrict_
       const int64_t r = r0 + h * dev::kThreads;
       ok[h] = r < rr.end;
       if (ok[h]) {
-        p[h] = ld_row<T, KP>(P + r * KP, KP);
-        q[h] = ld_row<T, KP>(Q + r * KP, KP);
-        x[h] = ld_row<T, KP>(X + r * KP, KP);
-        rv[h] = ld_row<T, KP>(R + r * KP, KP);
+        if (DX) {
+          p[h] = ld_row<T, KP>(P + r * KP, KP);
+          x[h] = ld_row<T, KP>(X + r * KP, KP);
+        }
+        if (DR) {
+          q[h] = ld_row<T, KP>(Q + r * KP, KP);
+          rv[h] = ld_row<T, KP>(R + r * KP, KP);
+        }
       }
     }
 #pragma unroll
@@ -361,18 +366,54 @@ __global__ __launch_bounds__(256) void rk_cg_xr_kernel(int64_t N, T* __restrict_
       const int64_t r = r0 + h * dev::kThreads;
 #pragma unroll
       for (int c = 0; c < KP; ++c) {
-        double xs = (double)x[h].v[c], rs = (double)rv[h].v[c];
+        if (DX) {
+          double xs = (double)x[h].v[c];
 #pragma unroll
-        for (int j = 0; j < KP; ++j) {
-          xs = fma((double)p[h].v[j], al[j * KP + c], xs);
-          rs = fma(-(double)q[h].v[j], al[j * KP + c], rs);
+          for (int j = 0; j < KP; ++j) xs = fma((double)p[h].v[j], al[j * KP + c], xs);
+          x[h].v[c] = (T)xs;
         }
-        x[h].v[c] = (T)xs;
-        rv[h].v[c] = (T)rs;
+        if (DR) {
+          double rs = (double)rv[h].v[c];
+#pragma unroll
+          for (int j = 0; j < KP; ++j) rs = fma(-(double)q[h].v[j], al[j * KP + c], rs);
+          rv[h].v[c] = (T)rs;
+        }
       }
-      st_row<T, KP>(X + r * KP, x[h]);
-      st_row<T, KP>(R + r * KP, rv[h]);
+      if (DX) st_row<T, KP>(X + r * KP, x[h]);
+      if (DR) st_row<T, KP>(R + r * KP, rv[h]);
     }
+  }
+}
+
+// X += P alpha and P = Z + P beta from the same read of the old P (one row per thread per step).
+template <typename T, int KP>
+__global__ __launch_bounds__(256) void rk_cg_xp_kernel(int64_t N, T* __restrict__ X, T* __restrict__ P,
+                                                       const T* __restrict__ Z, const double* alpha,
+                                                       const double* beta) {
+  double al[KP * KP], be[KP * KP];
+#pragma unroll
+  for (int e = 0; e < KP * KP; ++e) {
+    al[e] = alpha[e];
+    be[e] = beta[e];
+  }
+  const RowRange rr = block_rows(N);
+  for (int64_t r = rr.begin + threadIdx.x; r < rr.end; r += dev::kThreads) {
+    const Row<T, KP> p = ld_row<T, KP>(P + r * KP, KP);
+    Row<T, KP> x = ld_row<T, KP>(X + r * KP, KP);
+    Row<T, KP> z = ld_row<T, KP>(Z + r * KP, KP);
+#pragma unroll
+    for (int c = 0; c < KP; ++c) {
+      double xs = (double)x.v[c], ps = (double)z.v[c];
+#pragma unroll
+      for (int j = 0; j < KP; ++j) {
+        xs = fma((double)p.v[j], al[j * KP + c], xs);
+        ps = fma((double)p.v[j], be[j * KP + c], ps);
+      }
+      x.v[c] = (T)xs;
+      z.v[c] = (T)ps;
+    }
+    st_row<T, KP>(X + r * KP, x);
+    st_row<T, KP>(P + r * KP, z);
   }
 }
 
@@ -611,21 +652,53 @@ void rk_cg_update(bkts_ctx ctx, int dtype, int64_t N, int k, void* X, const void
     BKTS_RK_DISPATCH(k, (rk_cg_update_t<float, KP>(ctx, N, X, P, R, Q, alpha, dinv, gamma, Tm, nrm, tail)));
 }
 
-template <typename T, int KP>
+template <typename T, int KP, int MODE>
 static void rk_cg_xr_t(bkts_ctx ctx, int64_t N, void* X, const void* P, void* R, const void* Q, const double* alpha) {
-  const int64_t nb = rk_grid(ctx, rk_cg_xr_kernel<T, KP>, N);
-  ProfScope prof(ctx, BKTS_K_CG_UPDATE, 6.0 * N * KP * sizeof(T));
-  launch(ctx, (rk_cg_xr_kernel<T, KP>), dim3(nb), dim3(256), 0, N, static_cast<T*>(X), static_cast<const T*>(P),
-         static_cast<T*>(R), static_cast<const T*>(Q), alpha);
+  const int64_t nb = rk_grid(ctx, rk_cg_xr_kernel<T, KP, MODE>, N);
+  ProfScope prof(ctx, BKTS_K_CG_UPDATE, (MODE == 0 ? 6.0 : 3.0) * N * KP * sizeof(T));
+  launch(ctx, (rk_cg_xr_kernel<T, KP, MODE>), dim3(nb), dim3(256), 0, N, static_cast<T*>(X),
+         static_cast<const T*>(P), static_cast<T*>(R), static_cast<const T*>(Q), alpha);
   BKTS_HIP(hipGetLastError());
 }
 
 void rk_cg_xr_update(bkts_ctx ctx, int dtype, int64_t N, int k, void* X, const void* P, void* R, const void* Q,
                      const double* alpha) {
   if (dtype == BKTS_F64)
-    BKTS_RK_DISPATCH(k, (rk_cg_xr_t<double, KP>(ctx, N, X, P, R, Q, alpha)));
+    BKTS_RK_DISPATCH(k, (rk_cg_xr_t<double, KP, 0>(ctx, N, X, P, R, Q, alpha)));
   else
-    BKTS_RK_DISPATCH(k, (rk_cg_xr_t<float, KP>(ctx, N, X, P, R, Q, alpha)));
+    BKTS_RK_DISPATCH(k, (rk_cg_xr_t<float, KP, 0>(ctx, N, X, P, R, Q, alpha)));
+}
+
+void rk_cg_r_update(bkts_ctx ctx, int dtype, int64_t N, int k, void* R, const void* Q, const double* alpha) {
+  if (dtype == BKTS_F64)
+    BKTS_RK_DISPATCH(k, (rk_cg_xr_t<double, KP, 1>(ctx, N, nullptr, nullptr, R, Q, alpha)));
+  else
+    BKTS_RK_DISPATCH(k, (rk_cg_xr_t<float, KP, 1>(ctx, N, nullptr, nullptr, R, Q, alpha)));
+}
+
+void rk_cg_x_update(bkts_ctx ctx, int dtype, int64_t N, int k, void* X, const void* P, const double* alpha) {
+  if (dtype == BKTS_F64)
+    BKTS_RK_DISPATCH(k, (rk_cg_xr_t<double, KP, 2>(ctx, N, X, P, nullptr, nullptr, alpha)));
+  else
+    BKTS_RK_DISPATCH(k, (rk_cg_xr_t<float, KP, 2>(ctx, N, X, P, nullptr, nullptr, alpha)));
+}
+
+template <typename T, int KP>
+static void rk_cg_xp_t(bkts_ctx ctx, int64_t N, void* X, void* P, const void* Z, const double* alpha,
+                       const double* beta) {
+  const int64_t nb = rk_grid(ctx, rk_cg_xp_kernel<T, KP>, N);
+  ProfScope prof(ctx, BKTS_K_CG_PUPDATE, 5.0 * N * KP * sizeof(T));
+  launch(ctx, (rk_cg_xp_kernel<T, KP>), dim3(nb), dim3(256), 0, N, static_cast<T*>(X), static_cast<T*>(P),
+         static_cast<const T*>(Z), alpha, beta);
+  BKTS_HIP(hipGetLastError());
+}
+
+void rk_cg_xp_update(bkts_ctx ctx, int dtype, int64_t N, int k, void* X, void* P, const void* Z, const double* alpha,
+                     const double* beta) {
+  if (dtype == BKTS_F64)
+    BKTS_RK_DISPATCH(k, (rk_cg_xp_t<double, KP>(ctx, N, X, P, Z, alpha, beta)));
+  else
+    BKTS_RK_DISPATCH(k, (rk_cg_xp_t<float, KP>(ctx, N, X, P, Z, alpha, beta)));
 }
 
 template <typename T, int KP>
