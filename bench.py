@@ -25,6 +25,7 @@ from __future__ import annotations
 import argparse
 import hashlib
 import json
+import statistics
 import os
 import sys
 import time
@@ -108,12 +109,18 @@ def log(msg):
 
 
 def kernel_table(bkts, ctx):
+    """Per-category launch duration from the library's in-dispatch event timers.  The duration of a
+    category is the median of its timed launches (the mean is kept as mean_us): a short kernel's
+    event interval now and then takes in a stall of the queue ahead of it, which the median ignores
+    and the mean does not."""
     out = {}
     for name in bkts.KERNELS:
         n, ms, by = bkts.bkts_profile_query(ctx, name)
         if n:
-            out[name] = {"launches": n, "avg_us": 1e3 * ms / n, "total_ms": ms, "bytes_per_launch": by / n,
-                         "GBps": (by / 1e9) / (ms / 1e3) if ms > 0 else None}
+            med_ms = statistics.median(bkts.bkts_profile_samples(ctx, name))
+            tot = med_ms * n
+            out[name] = {"launches": n, "avg_us": 1e3 * med_ms, "mean_us": 1e3 * ms / n, "total_ms": tot,
+                         "bytes_per_launch": by / n, "GBps": (by / n / 1e9) / (med_ms / 1e3) if med_ms > 0 else None}
     tot = sum(v["total_ms"] for v in out.values())
     for v in out.values():
         v["share"] = v["total_ms"] / tot if tot > 0 else None
@@ -171,13 +178,14 @@ def traffic_for(kernel, precision, k):
 
 
 def spmm_kernel_name(k, precision, fmt="sell"):
-    """Kernel that bkts_spmm launches on a uniform-width SELL operator (or the stencil form) at width k."""
-    if fmt == "stencil":
-        return "st_spmm_kernel"
+    """Kernel that bkts_spmm launches on a uniform-width SELL operator (or the stencil form of a 3-D
+    grid) at width k, for contiguous blocks."""
     kp = 1
     while kp < k:
         kp *= 2
     sv = 4 if precision == "f32" else 8
+    if fmt == "stencil":
+        return "st_tile_kernel" if k == kp and 64 <= kp * sv <= 256 else "st_spmm_kernel"
     return "spmm_coop_kernel" if kp * sv >= 64 else "spmm_ell_kernel"
 
 

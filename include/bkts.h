@@ -103,6 +103,13 @@ enum {
 bkts_status bkts_profile_enable(bkts_ctx ctx, int enable);
 bkts_status bkts_profile_query(bkts_ctx ctx, int kernel, int64_t* launches, double* total_ms,
                                double* algorithmic_bytes);
+/* The individual durations (ms) of the timed launches of one kernel id since
+ * profiling was enabled, in launch order: copies min(total, max) of them into ms
+ * and stores the total count in *n (max = 0 and ms = NULL query the count).  A
+ * robust statistic (the median) of these is what a benchmark should report for
+ * short kernels, whose event intervals occasionally include queue stalls.
+ * Synchronises the ctx stream. */
+bkts_status bkts_profile_samples(bkts_ctx ctx, int kernel, float* ms, int max, int* n);
 
 /* ---------------------------------------------------------------- operators */
 

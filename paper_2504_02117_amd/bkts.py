@@ -137,6 +137,7 @@ _SIGS = {
                                C.POINTER(bkts_window_info)]),
     "bkts_profile_enable": (_I, [_P, _I]),
     "bkts_profile_query": (_I, [_P, _I, C.POINTER(_I64), C.POINTER(_D), C.POINTER(_D)]),
+    "bkts_profile_samples": (_I, [_P, _I, _P, _I, C.POINTER(_I)]),
     "bkts_stepper_create": (_I, [_P, _P, _P, _P, C.POINTER(_P)]),
     "bkts_stepper_advance": (_I, [_P, _I, C.POINTER(bkts_solve_opts), _D, _I, _P, bkts_step_cb, _P,
                                   C.POINTER(bkts_run_info)]),
@@ -393,6 +394,16 @@ def bkts_profile_query(ctx, kernel):
     n, ms, by = C.c_int64(), C.c_double(), C.c_double()
     _check(_lib.bkts_profile_query(ctx, kid, C.byref(n), C.byref(ms), C.byref(by)))
     return n.value, ms.value, by.value
+
+
+def bkts_profile_samples(ctx, kernel):
+    """The individual timed durations (ms) of kernel id or name, in launch order."""
+    kid = KERNELS.index(kernel) if isinstance(kernel, str) else int(kernel)
+    n = C.c_int()
+    _check(_lib.bkts_profile_samples(ctx, kid, None, 0, C.byref(n)))
+    buf = (C.c_float * max(1, n.value))()
+    _check(_lib.bkts_profile_samples(ctx, kid, buf, n.value, C.byref(n)))
+    return list(buf)[:n.value]
 
 
 def bkts_stepper_create(ctx, op, tc, y0):

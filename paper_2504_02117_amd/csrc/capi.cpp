@@ -4,6 +4,8 @@
 
 #include "accel.hpp"
 #include "advance.hpp"
+#include <algorithm>
+
 #include "internal.hpp"
 #include "krylov.hpp"
 #include "server.hpp"
@@ -389,6 +391,20 @@ bkts_status bkts_profile_query(bkts_ctx ctx, int kernel, int64_t* launches, doub
   if (launches) *launches = a.launches;
   if (total_ms) *total_ms = a.ms;
   if (bytes) *bytes = a.bytes;
+  BKTS_API_END
+}
+
+bkts_status bkts_profile_samples(bkts_ctx ctx, int kernel, float* ms, int max, int* n) {
+  BKTS_API_BEGIN
+  check_ctx(ctx);
+  BKTS_REQUIRE(kernel >= 0 && kernel < BKTS_K_COUNT, "kernel id out of range");
+  BKTS_REQUIRE(n && (ms || max == 0) && max >= 0, "need n, and ms unless max == 0");
+  ctx->sync();
+  ctx->prof.resolve();
+  const auto& v = ctx->prof.acc[kernel].samples;
+  const int m = (int)std::min<size_t>(v.size(), (size_t)max);
+  for (int i = 0; i < m; ++i) ms[i] = v[i];
+  *n = (int)v.size();
   BKTS_API_END
 }
 

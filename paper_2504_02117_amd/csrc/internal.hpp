@@ -93,6 +93,7 @@ struct Profiler {
     int64_t launches = 0;
     double ms = 0.0;
     double bytes = 0.0;
+    std::vector<float> samples;  // each timed launch's duration (ms), in launch order
   };
   bool enabled = false;
   int period = 1;                      // time every period-th launch of each kernel id

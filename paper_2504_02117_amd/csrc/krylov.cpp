@@ -238,8 +238,11 @@ void block_pcg_mg(bkts_ctx ctx, const bkts_op_s& op, int dtype, int k, double a,
   double* hbuf = ctx->host_stage(2 * (k + 2));
   ctx->sync();
   hipEvent_t ev[2];
-  BKTS_HIP(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
-  BKTS_HIP(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
+  // The kernels write the norms and the deflation count straight into coherent pinned memory, so the
+  // events that pace the host need no system-scope fence (which would write back the whole L2 once
+  // per iteration).
+  BKTS_HIP(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming | hipEventDisableSystemFence));
+  BKTS_HIP(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming | hipEventDisableSystemFence));
   struct EvGuard {
     hipEvent_t* e;
     ~EvGuard() { (void)hipEventDestroy(e[0]); (void)hipEventDestroy(e[1]); }
@@ -316,13 +319,14 @@ void block_pcg_mg(bkts_ctx ctx, const bkts_op_s& op, int dtype, int k, double a,
     if (state == -1) {  // every search direction collapsed: restart from the preconditioned residual
       if (++restarts > 3) throw Error{BKTS_EBREAKDOWN, "block CG: search space collapsed repeatedly"};
       precondition();
-      if (fused) {  // this iteration's norms, for the check of the next one
+      if (fused) {  // this iteration's norms, for the check of the next one (copied, then a full sync)
         colnorms2(ctx, dtype, N, k, R, k, s.nrm);
         BKTS_HIP(hipMemcpyAsync(hbuf + slot * (k + 2), s.nrm, sizeof(double) * k, hipMemcpyDeviceToHost,
                                 ctx->stream));
         BKTS_HIP(hipMemcpyAsync(reinterpret_cast<int*>(hbuf + slot * (k + 2) + k), s.ndefl, sizeof(int),
                                 hipMemcpyDeviceToHost, ctx->stream));
         BKTS_HIP(hipEventRecord(ev[slot], ctx->stream));
+        ctx->sync();
       }
       continue;
     }

@@ -211,6 +211,182 @@ __global__ __launch_bounds__(256) void st_spmm_kernel(StArgs<T> a) {
   }
 }
 
+// Wide rows on a 3-D grid (rows of 64 bytes or more: the SpMM is bound by gathering each row's six
+// neighbours, not by HBM): a workgroup owns a TX x TY tile of grid columns and marches through a
+// range of z-planes.  Three plane slots of (TX+2) x (TY+2) rows (the tile and its one-cell halo) rotate
+// in LDS: each step loads plane z+1 once (coalesced 16-byte chunks, zeros outside the grid), stages
+// the seven coefficients of plane z's tile rows once per row, and then every output chunk reads its
+// row and its six neighbours from LDS.  Arithmetic order and the zero-coefficient rule are those of
+// st_spmm_kernel (d x, then the lower and upper neighbour along x, y, z).  One-dimensional grid of
+// tiles x z-chunks, remapped so that each XCD takes one contiguous range (neighbouring tiles, whose
+// halos overlap, share that XCD's L2).
+template <typename T>
+struct StTileArgs {
+  StArgs<T> s;
+  int nx, ny, nz;
+  int tiles_x, tiles_y, zlen;
+};
+
+template <typename T, int KP, int TX, int TY>
+__global__ __launch_bounds__(256) void st_tile_kernel(StTileArgs<T> a) {
+  constexpr int VEC = 16 / sizeof(T);
+  constexpr int LPR = KP / VEC;  // 16-byte chunks per row
+  constexpr int HX = TX + 2, HY = TY + 2, HP = HX * HY, TR = TX * TY;
+  constexpr int PL = (HP * LPR + 255) / 256;  // plane chunks per thread
+  constexpr int CL = (TR * 7 + 255) / 256;    // coefficients per thread
+  typedef T vt __attribute__((ext_vector_type(VEC)));
+  __shared__ vt xs[3][HP * LPR];
+  __shared__ T cs[TR * 7];
+  const int t = threadIdx.x;
+  const int nx = a.nx, ny = a.ny, nz = a.nz;
+  const int64_t plane = (int64_t)nx * ny, N = a.s.N;
+  const int64_t ntile = (int64_t)a.tiles_x * a.tiles_y;
+  const int64_t unit = dev::xcd_slot(blockIdx.x, gridDim.x);
+  const int zc = (int)(unit / ntile), tile = (int)(unit - (int64_t)zc * ntile);
+  const int tx0 = (tile % a.tiles_x) * TX, ty0 = (tile / a.tiles_x) * TY;
+  const int z0 = zc * a.zlen;
+  const int z1 = z0 + a.zlen < nz ? z0 + a.zlen : nz;
+  const T* X = a.s.X;
+  const int ldx = a.s.ldx;
+  // All loads of a plane are issued before any of them is used: out-of-grid chunks read row 0 and
+  // are replaced by zeros afterwards.
+  auto fetch_plane = [&](int z, vt (&v)[PL]) {
+#pragma unroll
+    for (int i = 0; i < PL; ++i) {
+      const int e = t + i * 256;
+      const int row = e / LPR, c = e - row * LPR;
+      const int hy = row / HX, hx = row - hy * HX;
+      const int ix = tx0 - 1 + hx, iy = ty0 - 1 + hy;
+      const bool ok = e < HP * LPR && z >= 0 && z < nz && ix >= 0 && ix < nx && iy >= 0 && iy < ny;
+      const int64_t off = ok ? ((int64_t)z * plane + (int64_t)iy * nx + ix) * ldx + c * VEC : 0;
+      v[i] = *reinterpret_cast<const vt*>(X + off);
+      if (!ok) v[i] = (vt)(T(0));
+    }
+  };
+  auto store_plane = [&](int slot, const vt (&v)[PL]) {
+#pragma unroll
+    for (int i = 0; i < PL; ++i) {
+      const int e = t + i * 256;
+      if (e < HP * LPR) xs[slot][e] = v[i];
+    }
+  };
+  // coefficient q of a tile row: d; then the lower and the upper coupling along x, y, z (a lower
+  // coupling across the grid boundary is zero)
+  auto fetch_coef = [&](int z, T (&v)[CL]) {
+#pragma unroll
+    for (int i = 0; i < CL; ++i) {
+      const int e = t + i * 256;
+      const int row = e / 7, q = e - row * 7;
+      const int ly = row / TX, lx = row - ly * TX;
+      const int ix = tx0 + lx, iy = ty0 + ly;
+      const int axis = (q + 1) >> 1;
+      const bool lower = (q & 1) != 0;
+      const int64_t st = axis == 1 ? 1 : (axis == 2 ? (int64_t)nx : plane);
+      const bool inside = axis == 1 ? ix > 0 : (axis == 2 ? iy > 0 : z > 0);
+      const bool ok = e < TR * 7 && z < nz && ix < nx && iy < ny && (!lower || inside);
+      const int64_t r = (int64_t)z * plane + (int64_t)iy * nx + ix;
+      const int64_t off = ok ? axis * N + r - (lower ? st : 0) : 0;
+      v[i] = a.s.coef[off];
+      if (!ok) v[i] = T(0);
+    }
+  };
+  auto store_coef = [&](const T (&v)[CL]) {
+#pragma unroll
+    for (int i = 0; i < CL; ++i) {
+      const int e = t + i * 256;
+      if (e < TR * 7) cs[e] = v[i];
+    }
+  };
+  if (z0 >= z1) return;
+  // planes z-1, z, z+1 sit in the LDS slots while plane z+2 is in flight in registers and plane z+3
+  // is being requested: two planes of loads in flight per workgroup
+  vt pv[2][PL];
+  T cv[2][CL];
+  fetch_plane(z0 - 1, pv[0]);
+  store_plane((z0 + 2) % 3, pv[0]);
+  fetch_plane(z0, pv[0]);
+  store_plane(z0 % 3, pv[0]);
+  fetch_plane(z0 + 1, pv[0]);
+  store_plane((z0 + 1) % 3, pv[0]);
+  fetch_coef(z0, cv[0]);
+  store_coef(cv[0]);
+  if (z0 + 1 < z1) {
+    fetch_plane(z0 + 2, pv[0]);
+    fetch_coef(z0 + 1, cv[0]);
+  }
+  __syncthreads();
+  for (int z = z0; z < z1; ++z) {
+    const int b = (z - z0) & 1;
+    if (z + 2 < z1) {
+      fetch_plane(z + 3, pv[b ^ 1]);
+      fetch_coef(z + 2, cv[b ^ 1]);
+    }
+    const vt* P0 = xs[z % 3];
+    const vt* Pm = xs[(z + 2) % 3];
+    const vt* Pp = xs[(z + 1) % 3];
+    for (int e = t; e < TR * LPR; e += 256) {
+      const int row = e / LPR, c = e - row * LPR;
+      const int ly = row / TX, lx = row - ly * TX;
+      const int ix = tx0 + lx, iy = ty0 + ly;
+      if (ix >= nx || iy >= ny) continue;
+      const int h = ((ly + 1) * HX + lx + 1) * LPR + c;
+      const vt xc = P0[h];
+      const T* cf = cs + row * 7;
+      vt acc = cf[0] * xc;
+      acc = __builtin_elementwise_fma((vt)cf[1], P0[h - LPR], acc);
+      acc = __builtin_elementwise_fma((vt)cf[2], P0[h + LPR], acc);
+      acc = __builtin_elementwise_fma((vt)cf[3], P0[h - HX * LPR], acc);
+      acc = __builtin_elementwise_fma((vt)cf[4], P0[h + HX * LPR], acc);
+      acc = __builtin_elementwise_fma((vt)cf[5], Pm[h], acc);
+      acc = __builtin_elementwise_fma((vt)cf[6], Pp[h], acc);
+      const int64_t r = (int64_t)z * plane + (int64_t)iy * nx + ix;
+      vt out = a.s.beta * acc + a.s.alpha * xc;
+      if (a.s.B) {
+        const vt br = *reinterpret_cast<const vt*>(a.s.B + r * a.s.ldb + c * VEC);
+        out = __builtin_elementwise_fma((vt)a.s.cb, br, out);
+      }
+      __builtin_nontemporal_store(out, reinterpret_cast<vt*>(a.s.Y + r * a.s.ldy + c * VEC));
+    }
+    __syncthreads();  // slot (z-1) % 3 and the coefficients are free
+    if (z + 1 < z1) {
+      store_plane((z + 2) % 3, pv[b]);
+      store_coef(cv[b]);
+    }
+    __syncthreads();
+  }
+}
+
+template <typename T, int KP, int TX, int TY>
+void st_tile_launch(bkts_ctx ctx, const bkts_op_s& op, const StArgs<T>& s, int rounds) {
+  StTileArgs<T> a;
+  a.s = s;
+  a.nx = op.grid.n[0];
+  a.ny = op.grid.n[1];
+  a.nz = op.grid.n[2];
+  a.tiles_x = (a.nx + TX - 1) / TX;
+  a.tiles_y = (a.ny + TY - 1) / TY;
+  const int64_t ntile = (int64_t)a.tiles_x * a.tiles_y;
+  // `rounds` rounds of resident workgroups (LDS bounds the occupancy); each z-chunk costs two extra
+  // plane loads
+  const int64_t resident =
+      (int64_t)blocks_per_cu(reinterpret_cast<const void*>(st_tile_kernel<T, KP, TX, TY>)) * ctx->num_cu;
+  int64_t nzc = (rounds * resident + ntile / 2) / ntile;
+  if (nzc > a.nz) nzc = a.nz;
+  if (nzc < 1) nzc = 1;
+  a.zlen = (int)((a.nz + nzc - 1) / nzc);
+  nzc = (a.nz + a.zlen - 1) / a.zlen;
+  launch(ctx, (st_tile_kernel<T, KP, TX, TY>), dim3((unsigned)(ntile * nzc)), dim3(dev::kThreads), 0, a);
+}
+
+// Whether the tiled kernel serves this call: a 3-D grid with all three offsets, full-width 16-byte
+// aligned blocks (vec_ok) and rows of 64 to 256 bytes.
+template <typename T>
+bool st_tile_fits(const bkts_op_s& op, int kp, bool vec_ok) {
+  const int rowb = kp * (int)sizeof(T);
+  return vec_ok && op.grid.dim == 3 && op.st_na == 3 && op.grid.n[0] >= 2 && op.grid.n[1] >= 2 &&
+         op.grid.n[2] >= 2 && rowb >= 64 && rowb <= 256;
+}
+
 template <typename T, int KP, int VEC>
 void st_launch(bkts_ctx ctx, const bkts_op_s& op, const StArgs<T>& a0) {
   constexpr int LPR = KP / VEC;
@@ -267,6 +443,20 @@ void st_spmm_t(bkts_ctx ctx, const bkts_op_s& op, int k, double cb, const void* 
   auto aligned = [](const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; };
   const bool vec_ok = k == kp && ldx % VMAX == 0 && ldy % VMAX == 0 && aligned(X) && aligned(Y) &&
                       (!B || (ldb % VMAX == 0 && aligned(B)));
+  if (st_tile_fits<T>(op, kp, vec_ok)) {
+    // tile shapes from a sweep on the 128^3 operator: the smaller the LDS footprint, the more
+    // workgroups per CU keep loads in flight, which beats the larger halo share of a small tile
+    if constexpr (sizeof(T) == 8) {
+      if (kp == 8) st_tile_launch<T, 8, 16, 8>(ctx, op, a, 1);
+      else if (kp == 16) st_tile_launch<T, 16, 8, 4>(ctx, op, a, 1);
+      else st_tile_launch<T, 32, 8, 4>(ctx, op, a, 2);
+    } else {
+      if (kp == 16) st_tile_launch<T, 16, 16, 8>(ctx, op, a, 1);
+      else st_tile_launch<T, 32, 8, 4>(ctx, op, a, 1);
+    }
+    BKTS_HIP(hipGetLastError());
+    return;
+  }
   switch (kp) {
     case 1: st_launch_kp<T, 1>(ctx, op, a, vec_ok); break;
     case 2: st_launch_kp<T, 2>(ctx, op, a, vec_ok); break;

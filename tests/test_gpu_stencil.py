@@ -93,6 +93,37 @@ def test_stencil_spmm_matches_oracle(env, gi, k, dtype):
         bkts.bkts_op_destroy(op)
 
 
+@pytest.mark.parametrize("k", [8, 16, 32])
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_stencil_spmm_tiled_ragged(env, k, dtype):
+    """Wide rows on a 3-D grid whose sizes are not multiples of the x-y tile, with several z-planes
+    per workgroup and a shorter last z-chunk (71 planes), against the oracle's operator."""
+    torch, bkts, ctx = env
+    n = (45, 37, 71)
+    say(f"stencil spmm tiled n={n} k={k} {dtype}")
+    kap = inputs.lognormal_field(n, 0.0, 1.5, 3.0, 7)
+    op, K, _ = stencil_op(env, n, kap, {(0, 1): ("dirichlet", 2.0), (1, 0): ("neumann",)})
+    try:
+        N = K.shape[0]
+        X = inputs.random_block(N, k, 5 + k)
+        tdt = torch.float64 if dtype == "f64" else torch.float32
+        Xd = dev(torch, X, tdt)
+        Yd = torch.full((N, k), 7.0, dtype=tdt, device="cuda")
+        bkts.bkts_spmm(ctx, op, Xd, Yd, alpha=0.75, beta=-1.5)
+        if dtype == "f64":
+            ref = blockops.block_operator(K, X, 0.75, -1.5)
+            tol = 1e-13
+        else:
+            Kf = sp.csr_matrix((K.data.astype(np.float32).astype(np.float64), K.indices, K.indptr), shape=K.shape)
+            ref = blockops.block_operator(Kf, X.astype(np.float32).astype(np.float64), 0.75, -1.5)
+            tol = 2e-6
+        got = Yd.double().cpu().numpy()
+        scale = abs(K).sum(1).A.ravel()[:, None] * abs(X).max() + 1.5 * abs(X).max()
+        assert (abs(got - ref) / scale).max() < tol
+    finally:
+        bkts.bkts_op_destroy(op)
+
+
 @pytest.mark.parametrize("k", [3, 16])
 def test_stencil_spmm_strided_and_source(env, k):
     """Leading dimensions that rule out 16-byte access, and the operator inside the refinement
