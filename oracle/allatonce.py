@@ -76,3 +76,21 @@ def splitting_sweep(M, K, A1, A2, tau, beta, Y, B, B0):
     J = sp.csc_matrix(M / tau + beta * K)
     lu = spla.splu(J)
     return np.column_stack([lu.solve(rhs[:, j]) for j in range(k)])
+
+
+def splitting_sweep_diag(M, K, A1, A2, Y, B, B0):
+    """One sweep of the splitting that keeps every column's own diagonal coefficients (the remark
+    after eq. matrix-fixed-point-equation: with M a scaled identity the left-hand side
+    ``D (x) M + beta I (x) K``, D diagonal, still admits vectorized block Krylov solves).  Column j:
+
+    ``(A1_jj M + A2_jj K) y_j_new = [-M Y (A1 - diag A1)^T - K Y (A2 - diag A2)^T + B A2^T + B0]_j``
+
+    with an exact (direct) solve per column.  For a DIRK window the off-diagonal parts are strictly
+    lower triangular, so k sweeps reach the all-at-once solution whatever the diagonal."""
+    k = Y.shape[1]
+    d1, d2 = np.diag(A1), np.diag(A2)
+    rhs = -(M @ Y @ (A1 - np.diag(d1)).T) - K @ Y @ (A2 - np.diag(d2)).T + B @ A2.T + B0
+    out = np.empty_like(rhs)
+    for j in range(k):
+        out[:, j] = spla.spsolve(sp.csc_matrix(d1[j] * M + d2[j] * K), rhs[:, j])
+    return out

@@ -22,7 +22,7 @@ import numpy as np
 import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 
-from .timecoupling import implicit_part, tableau
+from .timecoupling import implicit_part, resolve
 
 
 def linear_solve(A, rhs, x0=None, kind="direct", rtol=1e-13):
@@ -55,10 +55,11 @@ def _mass(M, N):
 def dirk_linear(K, b, y0, tau, method, n_steps, theta=0.5, M=None, solver="direct", rtol=1e-13):
     """Step ``M y' + K y = b`` (constant ``b``) ``n_steps`` times.
 
+    ``method`` is a method name or a custom stiffly accurate ``(A, c)`` (``timecoupling.resolve``).
     Returns ``(ys, stages)``: ``ys[n]`` is ``y^n`` (``ys[0] = y0``) and
     ``stages[n]`` the list of implicit-stage vectors of step ``n``.
     """
-    A, _, c = tableau(method, theta)
+    A, _, c = resolve(method, theta)
     Ai, ae, _, _ = implicit_part(A, c)
     mi = Ai.shape[0]
     N = K.shape[0]
@@ -96,7 +97,7 @@ def rk_linear(K, b, y0, tau, method, n_steps, M=None):
     stage (a zero first row) is kept as an ordinary stage, whose equation then gives ``y_1 = y^n``.
     Returns ``(ys, stages)`` like ``dirk_linear``.
     """
-    A, _, _ = tableau(method)
+    A, _, _ = resolve(method)
     m = A.shape[0]
     N = K.shape[0]
     M = _mass(M, N)
@@ -124,7 +125,7 @@ def dirk_nonlinear(fop, y0, tau, method, n_steps, theta=0.5, M=None, solver="dir
     ``||G(y)|| <= newton_rtol * ||M y^n / tau||`` with ``G`` the stage residual.
     Returns ``(ys, stages, newton_iterations_per_step)``.
     """
-    A, _, c = tableau(method, theta)
+    A, _, c = resolve(method, theta)
     Ai, ae, _, _ = implicit_part(A, c)
     mi = Ai.shape[0]
     y = np.asarray(y0, dtype=np.float64).copy()

@@ -64,6 +64,34 @@ def tableau(name: str, theta: float = 0.5):
     return A, b, c
 
 
+def custom_tableau(A, c, tol: float = 1e-12):
+    """Tableau ``(A, b, c)`` of a user-given stiffly accurate method: ``b`` is the last row of ``A``
+    (Sec. 2, eq. stiffly-accurate-DIRK: the step result is the last stage).  The stage times must be
+    the row sums ``c_i = sum_j a_ij`` and the last one must be 1 (so that ``sum_i b_i = 1``);
+    otherwise the tableau does not define a consistent stiffly accurate method and ``ValueError`` is
+    raised."""
+    A = np.array(A, dtype=np.float64)
+    c = np.array(c, dtype=np.float64)
+    m = A.shape[0]
+    if A.shape != (m, m) or c.shape != (m,) or m < 1:
+        raise ValueError("A must be m x m and c of length m")
+    if not (np.all(np.isfinite(A)) and np.all(np.isfinite(c))):
+        raise ValueError("tableau entries must be finite")
+    if np.any(np.abs(A.sum(axis=1) - c) > tol * np.maximum(1.0, np.abs(c))):
+        raise ValueError("stage times must be the row sums of A")
+    if abs(c[-1] - 1.0) > tol:
+        raise ValueError("a stiffly accurate method ends at c_m = 1")
+    return A, A[-1].copy(), c
+
+
+def resolve(method, theta: float = 0.5):
+    """``(A, b, c)`` for a method name (see ``tableau``) or a custom ``(A, c)`` pair."""
+    if isinstance(method, str):
+        return tableau(method, theta)
+    A, c = method
+    return custom_tableau(A, c)
+
+
 def is_fully_implicit(A) -> bool:
     """True when some stage couples to a later one (an entry above the diagonal)."""
     return bool(np.any(np.triu(np.asarray(A, dtype=np.float64), 1)))
