@@ -209,7 +209,8 @@ typedef struct bkts_tc_desc {
   int stages;        /* BKTS_DIRK_CUSTOM: number of stages m (<= 8) */
   const double* A;   /* BKTS_DIRK_CUSTOM: host, m x m row-major, stiffly accurate (b = last row);
                         lower triangular (DIRK) or full (fully implicit) */
-  const double* c;   /* BKTS_DIRK_CUSTOM: host, m */
+  const double* c;   /* BKTS_DIRK_CUSTOM: host, m; must be the row sums of A with c_m = 1
+                        (a consistent stiffly accurate method), else BKTS_EINVAL */
   int k;             /* block width: number of stage columns in one window (1..BKTS_MAX_K) */
   double tau;        /* time step */
 } bkts_tc_desc;
@@ -305,7 +306,12 @@ typedef void (*bkts_step_cb)(int step, double t, const double* y_device, void* u
  * satisfies ||R_0|| <= outer_rtol * ||rhs_0||; the front stage is then
  * accepted and the window shifted (shift(Y_1..Y_k) = (Y_2..Y_k, Y_k)).  For a
  * fully implicit tableau the m columns of the front step must all pass the test
- * and are accepted and shifted out together.
+ * and are accepted and shifted out together.  For a DIRK tableau whose implicit
+ * diagonal entries differ (a custom tableau), inner->krylov = BKTS_BICGSTAB (a
+ * column-wise method) keeps each column's own block J_j = I/tau + A2_jj K: the
+ * D (x) M + beta I (x) K form of the remark after eq. matrix-fixed-point-equation,
+ * whose splitting is exact after k sweeps; block CG and GMRES use beta = A2_00
+ * for every column.
  * `y` (device, N) holds y^0 on entry and y^{n_steps} on exit.  `y_hist`
  * (device, n_steps x N, may be NULL) receives every accepted y^n.  `cb` may
  * be NULL.  Synchronises. */

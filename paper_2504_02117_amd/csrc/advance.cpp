@@ -180,6 +180,20 @@ bkts_status bkts_stepper_s::advance(int n_steps, const bkts_solve_opts& inner, d
     }
     upload_window(ctx, *tc, phase, off, mats.as<double>(), nullptr, nullptr);
     const double beta = tc_beta(*tc, phase);
+    // A DIRK window whose diagonal coefficients differ (a custom tableau with distinct a_ii): with a
+    // column-wise inner method, each column keeps its own diagonal block M/tau + A2_jj K, the
+    // D (x) M + beta I (x) K form of the remark after eq. matrix-fixed-point-equation, instead of
+    // moving (A2_jj - beta) K to the right-hand side.
+    ColOp cop;
+    bool col_ops = false;
+    if (!nl && !tc->fully_implicit && inner.krylov == BKTS_BICGSTAB) {
+      for (int i = 0; i < k; ++i) {
+        const int p = (off + i) % k;  // physical column of window slot i
+        cop.a[p] = tc->A1[phase][i * k + i];
+        cop.b[p] = tc->A2[phase][i * k + i];
+        col_ops = col_ops || cop.b[p] != beta || cop.a[p] != 1.0 / tau;
+      }
+    }
     // columns accepted together: the front stage, or every stage of the front step when the
     // tableau is fully implicit (its first stage couples to the later ones of the same step)
     const int nacc = tc->fully_implicit ? mi : 1;
@@ -213,7 +227,7 @@ bkts_status bkts_stepper_s::advance(int n_steps, const bkts_solve_opts& inner, d
         for (int j = 0; j < k; ++j)
           if (!active[j]) lincomb(ctx, N, LinComb{}, Vp + j, k);  // frozen slots take no update
       } else {
-        solve(ctx, *op, 1.0 / tau, beta, k, Rp, Vp, true, inner, true, ks);
+        solve(ctx, *op, 1.0 / tau, beta, k, Rp, Vp, true, inner, true, ks, col_ops ? &cop : nullptr);
       }
       ri.krylov_iterations += ks.iterations;
       ri.refinements += ks.refinements;

@@ -8,6 +8,7 @@
 // Arithmetic in FP64, stored in the block type.  Each thread handles 4 elements 256 apart.
 #include "devcommon.hpp"
 #include "internal.hpp"
+#include "vecops.hpp"
 
 namespace bkts {
 namespace {
@@ -114,6 +115,25 @@ __global__ __launch_bounds__(256) void bicg_p_kernel(int64_t n, int k, const T* 
 
 dim3 grid_ept(int64_t n) { return dim3((unsigned)((n + 256 * kEPT - 1) / (256 * kEPT))); }
 
+struct ColCoef {
+  double a[BKTS_MAX_K], b[BKTS_MAX_K];
+};
+
+template <typename T>
+__global__ __launch_bounds__(256) void col_affine_kernel(int64_t n, int k, const T* __restrict__ B,
+                                                         const T* __restrict__ X, T* __restrict__ Y, ColCoef cc) {
+  const int64_t i0 = (int64_t)blockIdx.x * (256 * kEPT) + threadIdx.x;
+  RowCol rc(i0, k);
+#pragma unroll
+  for (int e = 0; e < kEPT; ++e, rc.step(k)) {
+    const int64_t i = i0 + (int64_t)e * 256;
+    if (i < n) {
+      const double y = cc.b[rc.c] * (double)Y[i] + cc.a[rc.c] * (double)X[i];
+      Y[i] = (T)(B ? (double)B[i] - y : y);
+    }
+  }
+}
+
 }  // namespace
 
 void bicg_s_step(bkts_ctx ctx, int dtype, int64_t N, int k, const void* R, const void* V, const double* al,
@@ -168,6 +188,26 @@ void bicg_p_step(bkts_ctx ctx, int dtype, int64_t N, int k, const void* R, const
   else
     launch(ctx, bicg_p_kernel<float>, grid_ept(n), dim3(256), 0, n, k, static_cast<const float*>(R),
            static_cast<const float*>(V), om, be, dinv, static_cast<float*>(P), static_cast<float*>(Ph));
+  BKTS_HIP(hipGetLastError());
+}
+
+void col_affine(bkts_ctx ctx, int dtype, int64_t N, int k, const void* B, const void* X, void* Y, const double* a,
+                const double* b) {
+  BKTS_REQUIRE(k >= 1 && k <= BKTS_MAX_K, "k out of range");
+  ColCoef cc{};
+  for (int j = 0; j < k; ++j) {
+    cc.a[j] = a[j];
+    cc.b[j] = b[j];
+  }
+  const int64_t n = N * k;
+  const dim3 grid((unsigned)((n + 256 * kEPT - 1) / (256 * kEPT)));
+  ProfScope prof(ctx, BKTS_K_OTHER, (B ? 4.0 : 3.0) * n * esize(dtype));
+  if (dtype == BKTS_F64)
+    launch(ctx, (col_affine_kernel<double>), grid, dim3(256), 0, n, k, static_cast<const double*>(B),
+           static_cast<const double*>(X), static_cast<double*>(Y), cc);
+  else
+    launch(ctx, (col_affine_kernel<float>), grid, dim3(256), 0, n, k, static_cast<const float*>(B),
+           static_cast<const float*>(X), static_cast<float*>(Y), cc);
   BKTS_HIP(hipGetLastError());
 }
 

@@ -365,8 +365,10 @@ void block_pcg_mg(bkts_ctx ctx, const bkts_op_s& op, int dtype, int k, double a,
 // V64 (which need not be zero).
 // Dispatch on the Krylov method of the options.
 static void krylov_run(bkts_ctx ctx, const bkts_op_s& op, const bkts_solve_opts& o, int dtype, int k, double a,
-                       double b, const void* B, void* X, bool x0_zero, double rtol, int maxit, KrylovStats& st) {
+                       double b, const void* B, void* X, bool x0_zero, double rtol, int maxit, KrylovStats& st,
+                       const ColOp* cop = nullptr) {
   const bool jacobi = o.precond == BKTS_PREC_JACOBI;
+  BKTS_REQUIRE(!cop || o.krylov == BKTS_BICGSTAB, "per-column operators need the vectorized BiCGStab");
   BKTS_REQUIRE(o.precond >= BKTS_PREC_NONE && o.precond <= BKTS_PREC_MG, "unknown preconditioner %d", o.precond);
   BKTS_REQUIRE(o.precond != BKTS_PREC_MG || o.krylov == BKTS_CG, "multigrid preconditions block CG only");
   switch (o.krylov) {
@@ -377,13 +379,14 @@ static void krylov_run(bkts_ctx ctx, const bkts_op_s& op, const bkts_solve_opts&
         block_cg(ctx, op, dtype, k, a, b, B, X, x0_zero, jacobi, rtol, maxit, st);
       break;
     case BKTS_GMRES: block_gmres(ctx, op, dtype, k, a, b, B, X, x0_zero, jacobi, rtol, o.restart, maxit, st); break;
-    case BKTS_BICGSTAB: block_bicgstab(ctx, op, dtype, k, a, b, B, X, x0_zero, jacobi, rtol, maxit, st); break;
+    case BKTS_BICGSTAB: block_bicgstab(ctx, op, dtype, k, a, b, B, X, x0_zero, jacobi, rtol, maxit, st, cop); break;
     default: throw Error{BKTS_EINVAL, fmt("unknown Krylov method %d", o.krylov)};
   }
 }
 
 void f32_correction(bkts_ctx ctx, const bkts_op_s& op, const bkts_solve_opts& o, int k, double a, double b,
-                    const double* R64, const double* nrm2, double* V64, double rtol, int maxit, KrylovStats& st) {
+                    const double* R64, const double* nrm2, double* V64, double rtol, int maxit, KrylovStats& st,
+                    const ColOp* cop = nullptr) {
   const int64_t N = op.N;
   double* scale = ctx->ws.get<double>("f32_scale", k);
   std::vector<double> hs(k);
@@ -393,20 +396,21 @@ void f32_correction(bkts_ctx ctx, const bkts_op_s& op, const bkts_solve_opts& o,
   float* V32 = ctx->ws.get<float>("f32_V", (size_t)N * k);
   block_cast_scale(ctx, N, k, BKTS_F64, R64, k, BKTS_F32, R32, k, scale, true, false);
   BKTS_HIP(hipMemsetAsync(V32, 0, sizeof(float) * N * k, ctx->stream));
-  krylov_run(ctx, op, o, BKTS_F32, k, a, b, R32, V32, true, rtol, maxit, st);
+  krylov_run(ctx, op, o, BKTS_F32, k, a, b, R32, V32, true, rtol, maxit, st, cop);
   block_cast_scale(ctx, N, k, BKTS_F32, V32, k, BKTS_F64, V64, k, scale, false, true);
   ctx->sync();  // hs must outlive the async upload
 }
 
 void solve(bkts_ctx ctx, const bkts_op_s& op, double a, double b, int k, const double* B, double* X, bool x0_zero,
-           const bkts_solve_opts& o, bool single_f32_pass, KrylovStats& st) {
+           const bkts_solve_opts& o, bool single_f32_pass, KrylovStats& st, const ColOp* cop) {
   const int maxit = o.maxit > 0 ? o.maxit : 10000;
   if (o.precision == BKTS_PRECISION_F64) {
-    krylov_run(ctx, op, o, BKTS_F64, k, a, b, B, X, x0_zero, o.rtol, maxit, st);
+    krylov_run(ctx, op, o, BKTS_F64, k, a, b, B, X, x0_zero, o.rtol, maxit, st, cop);
     st.refinements = 0;
     return;
   }
   BKTS_REQUIRE(o.precision == BKTS_PRECISION_F32_REFINE, "unknown precision %d", o.precision);
+  BKTS_REQUIRE(!cop || single_f32_pass, "per-column operators: FP64, or one FP32 pass inside the caller's loop");
   const int64_t N = op.N;
   const double inner = o.inner_rtol > 0.0 ? o.inner_rtol : 1e-4;
   double* n2 = ctx->ws.get<double>("ref_n2", k);
@@ -418,7 +422,7 @@ void solve(bkts_ctx ctx, const bkts_op_s& op, double a, double b, int k, const d
     std::vector<double> nb;
     read_norms(ctx, n2, k, nb);
     st = KrylovStats{};
-    f32_correction(ctx, op, o, k, a, b, B, nb.data(), X, std::max(o.rtol, inner), maxit, st);
+    f32_correction(ctx, op, o, k, a, b, B, nb.data(), X, std::max(o.rtol, inner), maxit, st, cop);
     st.refinements = 1;
     return;
   }

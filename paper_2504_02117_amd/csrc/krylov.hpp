@@ -7,6 +7,16 @@
 
 namespace bkts {
 
+// A different operator per column: column j of the block solves (a[j] I + b[j] K) x_j = r_j.  This
+// is the left-hand side D (x) M + beta I (x) K of the remark after eq. matrix-fixed-point-equation
+// (M the identity, D diagonal), after each column is divided by its own beta: the columns' Krylov
+// spaces are those of K, so the column-wise (vectorized) methods solve every column with its own
+// shift.  Entries in the physical column order of the block.
+struct ColOp {
+  double a[BKTS_MAX_K];
+  double b[BKTS_MAX_K];
+};
+
 struct KrylovStats {
   int iterations = 0;
   int refinements = 0;
@@ -37,13 +47,17 @@ struct GmresOps {
 };
 void gmres_core(bkts_ctx ctx, int dtype, int64_t N, int k, const GmresOps& ops, const void* B, void* X,
                 bool x0_zero, double rtol, int restart, int maxit, KrylovStats& st);
+// cop != nullptr: column j's operator is cop->a[j] I + cop->b[j] K (the Jacobi scaling stays that
+// of a I + b K)
 void block_bicgstab(bkts_ctx ctx, const bkts_op_s& op, int dtype, int k, double a, double b, const void* B, void* X,
-                    bool x0_zero, bool jacobi, double rtol, int maxit, KrylovStats& st);
+                    bool x0_zero, bool jacobi, double rtol, int maxit, KrylovStats& st, const ColOp* cop = nullptr);
 
 // FP64 solve entry: F64 block CG, or FP32 block CG inside FP64 iterative refinement.  With
 // single_f32_pass the refinement loop makes one FP32 correction (the caller's own outer loop
 // computes FP64 residuals).
+// With cop (vectorized BiCGStab only, one FP32 pass or FP64): the per-column operators of ColOp;
+// (a, b) then only set the Jacobi scaling.
 void solve(bkts_ctx ctx, const bkts_op_s& op, double a, double b, int k, const double* B, double* X, bool x0_zero,
-           const bkts_solve_opts& o, bool single_f32_pass, KrylovStats& st);
+           const bkts_solve_opts& o, bool single_f32_pass, KrylovStats& st, const ColOp* cop = nullptr);
 
 }  // namespace bkts

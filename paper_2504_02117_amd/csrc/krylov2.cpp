@@ -212,7 +212,7 @@ void block_gmres(bkts_ctx ctx, const bkts_op_s& op, int dtype, int k, double a, 
 // vectorized solver).  Coupling the columns through k x k solves (the block form) needs a
 // well-conditioned residual block at every step, which FP32 windows of Algorithm 1 do not keep.
 void block_bicgstab(bkts_ctx ctx, const bkts_op_s& op, int dtype, int k, double a, double b, const void* B, void* X,
-                   bool x0_zero, bool jacobi, double rtol, int maxit, KrylovStats& st) {
+                   bool x0_zero, bool jacobi, double rtol, int maxit, KrylovStats& st, const ColOp* cop) {
   const int64_t N = op.N;
   const size_t es = esize(dtype);
   const size_t blk = es * N * k;
@@ -237,11 +237,20 @@ void block_bicgstab(bkts_ctx ctx, const bkts_op_s& op, int dtype, int k, double 
     jacobi_inverse(ctx, op, a, b, d);
     dinv = d;
   }
+  // out = A in, column by column: one SpMM for K in, then each column's own a_j, b_j
+  auto apply = [&](const void* in, void* out) {
+    if (!cop) return spmm(ctx, op, dtype, k, 0.0, nullptr, k, a, in, k, b, out, k);
+    spmm(ctx, op, dtype, k, 0.0, nullptr, k, 0.0, in, k, 1.0, out, k);
+    col_affine(ctx, dtype, N, k, nullptr, in, out, cop->a, cop->b);
+  };
   if (x0_zero) {
     BKTS_HIP(hipMemsetAsync(X, 0, blk, ctx->stream));
     BKTS_HIP(hipMemcpyAsync(R, B, blk, hipMemcpyDeviceToDevice, ctx->stream));
-  } else {
+  } else if (!cop) {
     spmm(ctx, op, dtype, k, 1.0, B, k, -a, X, k, -b, R, k);
+  } else {  // R = B - (a_j X_j + b_j K X_j)
+    spmm(ctx, op, dtype, k, 0.0, nullptr, k, 0.0, X, k, 1.0, R, k);
+    col_affine(ctx, dtype, N, k, B, X, R, cop->a, cop->b);
   }
   BKTS_HIP(hipMemcpyAsync(Rt, R, blk, hipMemcpyDeviceToDevice, ctx->stream));
   BKTS_HIP(hipMemcpyAsync(P, R, blk, hipMemcpyDeviceToDevice, ctx->stream));
@@ -255,7 +264,7 @@ void block_bicgstab(bkts_ctx ctx, const bkts_op_s& op, int dtype, int k, double 
   }
   scale_rows(ctx, dtype, N, k, dinv, P, Ph);
   for (int it = 1; it <= maxit; ++it) {
-    spmm(ctx, op, dtype, k, 0.0, nullptr, k, a, Ph, k, b, V, k);  // V = A D^-1 P
+    apply(Ph, V);  // V = A D^-1 P
     {
       const void* xs[2] = {Rt, Rt};
       const void* ys[2] = {V, R};
@@ -264,7 +273,7 @@ void block_bicgstab(bkts_ctx ctx, const bkts_op_s& op, int dtype, int k, double 
     }
     small_diag_ratio(ctx, k, mr, m1, 1.0, al);           // alpha_j = (rt_j^T r_j) / (rt_j^T v_j)
     bicg_s_step(ctx, dtype, N, k, R, V, al, dinv, Sb, Sh);  // S = R - V alpha, Sh = D^-1 S
-    spmm(ctx, op, dtype, k, 0.0, nullptr, k, a, Sh, k, b, T, k);  // T = A D^-1 S
+    apply(Sh, T);  // T = A D^-1 S
     {
       const void* xs[3] = {T, T, Rt};
       const void* ys[3] = {Sb, T, T};

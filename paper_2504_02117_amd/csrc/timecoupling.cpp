@@ -4,6 +4,7 @@
 // window's front stage (Sec. 2.2, pipelining).  Fully implicit tableaux (the remark on fully
 // implicit Runge-Kutta methods after Algorithm 1) give full diagonal blocks in A2; their windows
 // hold whole steps and their splitting uses one averaged coefficient for every stage.
+#include <algorithm>
 #include <cmath>
 
 #include "internal.hpp"
@@ -84,6 +85,15 @@ bkts_tc tc_create(bkts_ctx ctx, const bkts_tc_desc* d) {
       A.assign(d->A, d->A + m * m);
       c.assign(d->c, d->c + m);
       for (double v : A) BKTS_REQUIRE(std::isfinite(v), "tableau entries must be finite");
+      // a consistent stiffly accurate method: stage times are the row sums of A, and the last
+      // stage (the step result, b = last row) ends the step, c_m = 1
+      for (int i = 0; i < m; ++i) {
+        double rs = 0.0;
+        for (int j = 0; j < m; ++j) rs += A[i * m + j];
+        BKTS_REQUIRE(std::isfinite(c[i]) && std::fabs(rs - c[i]) <= 1e-12 * std::max(1.0, std::fabs(c[i])),
+                     "custom tableau: c_%d = %g is not the row sum %g of A", i + 1, c[i], rs);
+      }
+      BKTS_REQUIRE(std::fabs(c[m - 1] - 1.0) <= 1e-12, "custom tableau: a stiffly accurate method needs c_m = 1");
       break;
     default:
       throw Error{BKTS_EINVAL, fmt("unknown method %d", d->method)};

@@ -27,6 +27,10 @@ void lincomb(bkts_ctx ctx, int64_t N, const LinComb& lc, double* out, int ldo);
 void axpby(bkts_ctx ctx, int64_t n, double a, const double* x, double b, double* y);  // y = a x + b y
 // Y = diag(dinv) X for N x k contiguous blocks of type dtype (dinv null: copy)
 void scale_rows(bkts_ctx ctx, int dtype, int64_t N, int k, const double* dinv, const void* X, void* Y);
+// Per-column affine step of a column-wise operator (contiguous N x k blocks of type dtype):
+// Y_j = b[j] Y_j + a[j] X_j, and then Y_j = B_j - Y_j when B is given.  a, b: host arrays of k.
+void col_affine(bkts_ctx ctx, int dtype, int64_t N, int k, const void* B, const void* X, void* Y, const double* a,
+                const double* b);
 // Y += sign * s[0] * X (n elements; s is a device scalar)
 void axpy_ds(bkts_ctx ctx, int dtype, int64_t n, const double* s, double sign, const void* X, void* Y);
 // Fused per-column steps of the vectorized BiCGStab (bicg.hip); alpha, omega, beta are diagonal

@@ -87,6 +87,11 @@ def test_custom_tableau_and_validation():
                             c=np.array([1.5, 3.0]))
     with pytest.raises(bkts.BktsError):  # fully implicit: k must hold whole steps
         bkts.bkts_tc_create(None, bkts.BKTS_RADAU2, 3, 0.1)
+    for A_bad, c_bad in (([[0.5, 0.0], [0.5, 0.5]], [0.4, 1.0]),      # c is not the row sums of A
+                         ([[0.5, 0.0], [0.25, 0.5]], [0.5, 0.75])):   # the last stage does not end at 1
+        with pytest.raises(bkts.BktsError) as e:
+            bkts.bkts_tc_create(None, bkts.BKTS_DIRK_CUSTOM, 2, 0.1, A=np.array(A_bad), c=np.array(c_bad))
+        assert e.value.status == bkts.BKTS_EINVAL
     with pytest.raises(bkts.BktsError):
         bkts.bkts_tc_get(tc := bkts.bkts_tc_create(None, bkts.BKTS_IE, 2, 0.1), 1)
     bkts.bkts_tc_destroy(tc)
