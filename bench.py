@@ -68,9 +68,10 @@ def parse():
                    help="time the block form without the in-library kernel timers (no roofline)")
     p.add_argument("--calibrate-copy", action="store_true",
                    help="first run 3 plain 256 MiB device copies (reference dispatches for HBM counters)")
-    p.add_argument("--serve-requests", type=int, default=128,
-                   help="serving leg: the first n requests of the seeded Poisson trace (0 = skip; the full "
-                        "trace is 512)")
+    p.add_argument("--serve-requests", type=int, default=512,
+                   help="requests in the serving trace (0 = skip the serving leg)")
+    p.add_argument("--serve-mode", type=int, default=1, choices=[0, 1],
+                   help="0: grouped window splitting (Jacobi); 1: pipelined Algorithm 1 with multigrid on lanes")
     p.add_argument("--serve-rate", type=float, default=200.0, help="mean arrivals per second")
     p.add_argument("--serve-budget-gib", type=float, default=4.0)
     p.add_argument("--serve-slots", type=int, default=64)
@@ -308,7 +309,7 @@ def run_serving(torch, bkts, ctx, a):
                     results[r.ticket] = r
                 time.sleep(min(5e-4, max(0.0, t0 + arrivals[i] - bkts.bkts_server_clock(srv))))
             req = bkts.make_request(n, y0s[n], out, int(widths[i]), 1e-3, kappa=kd, rtol=1e-8,
-                                    inner_rtol=a.serve_inner_rtol, tag=i)
+                                    inner_rtol=a.serve_inner_rtol, tag=i, mode=a.serve_mode)
             tickets[bkts.bkts_server_submit(srv, req)] = i
         log(f"  all {m} submitted at t={bkts.bkts_server_clock(srv) - t0:.2f} s, {len(results)} done")
         last = time.time()
@@ -359,18 +360,24 @@ def run_serving(torch, bkts, ctx, a):
             "oracle_max_rel_err_sampled": max(errs) if errs else None, "inner_rtol": a.serve_inner_rtol,
             "plain_fifo": fifo,
             "speedup_vs_plain_fifo": (fifo["makespan_s"] / makespan) if fifo else None,
+            "mode": a.serve_mode,
             "workload": "2-D lognormal diffusion (log-std 2, corr. 8 cells, seed 1000+i), n in {64,128,256,512}, "
-                        "k in {4,8,16,32}, implicit Euler tau=1e-3, one window of k steps per request, "
-                        "FP32 block CG inside FP64 Newton to 1e-8, Poisson arrivals"}
+                        "k in {4,8,16,32}, implicit Euler tau=1e-3, k steps per request, Poisson arrivals; "
+                        + ("pipelined Algorithm 1 (window min(k,4)), FP32 multigrid block CG inside FP64 to 1e-8 "
+                           "per step, on worker lanes" if a.serve_mode == 1 else
+                           "one window of k steps by grouped splitting, FP32 Jacobi block CG inside FP64 "
+                           "Newton to 1e-8")}
 
 
 def run_serving_plain(torch, bkts, ctx, reqs, arrivals, widths, sizes, y0s):
-    """The same trace served one request at a time in arrival order by plain FP64 k = 1 stepping (CG +
-    Jacobi, inner = outer = 1e-8): each request's operator is assembled when it starts, and its k steps
-    are taken one after another.  Arrivals are replayed on the same clock as the served form."""
+    """The same trace served one request at a time in arrival order by plain FP64 k = 1 stepping (CG
+    preconditioned by the same multigrid V-cycle on the stencil form, inner = outer = 1e-8): each
+    request's operator is assembled when it starts, and its k steps are taken one after another.
+    Arrivals are replayed on the same clock as the served form."""
     import numpy as np
     log(f"serving baseline: plain FP64 k=1 stepping, one request at a time in arrival order")
-    inner = bkts.solve_opts(precision=bkts.BKTS_PRECISION_F64, rtol=1e-8, inner_rtol=1e-8, maxit=100000)
+    inner = bkts.solve_opts(precond=bkts.BKTS_PREC_MG, precision=bkts.BKTS_PRECISION_F64, rtol=1e-8,
+                            inner_rtol=1e-8, maxit=100000)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     lat, done, its = [], 0.0, 0
@@ -379,7 +386,7 @@ def run_serving_plain(torch, bkts, ctx, reqs, arrivals, widths, sizes, y0s):
         if now < arrivals[i]:
             time.sleep(arrivals[i] - now)
         k = int(widths[i])
-        op = bkts.bkts_fv_assemble(ctx, n, kappa=kd, fmt=bkts.BKTS_FMT_SELL)
+        op = bkts.bkts_fv_assemble(ctx, n, kappa=kd, fmt=bkts.BKTS_FMT_STENCIL)
         tc = bkts.bkts_tc_create(ctx, bkts.BKTS_IE, 1, 1e-3)
         st = bkts.bkts_stepper_create(ctx, op, tc, y0s[n])
         hist = torch.empty((k, n[0] * n[1]), dtype=torch.float64, device="cuda")
@@ -400,7 +407,8 @@ def run_serving_plain(torch, bkts, ctx, reqs, arrivals, widths, sizes, y0s):
     return {"makespan_s": done, "throughput_dof_timesteps_per_s": work / done,
             "latency_p50_ms": 1e3 * float(np.percentile(lat, 50)),
             "latency_p99_ms": 1e3 * float(np.percentile(lat, 99)), "krylov_iterations": its,
-            "config": "FP64 k=1 CG + Jacobi, inner = outer = 1e-8, one request at a time, operator assembled per request"}
+            "config": "FP64 k=1 CG + multigrid (stencil form), inner = outer = 1e-8, one request at a time, "
+                      "operator assembled per request"}
 
 
 def run_nonlinear(torch, bkts, ctx, a):
@@ -799,7 +807,8 @@ def compact_line(out, full_path):
                                          for kk, v in wa.items()}
     if out.get("serving"):
         sv = out["serving"]
-        legs["serving"] = {"requests": sv["requests"], "throughput": sv["throughput_dof_timesteps_per_s"],
+        legs["serving"] = {"requests": sv["requests"], "mode": sv.get("mode"),
+                           "throughput": sv["throughput_dof_timesteps_per_s"],
                            "p50_ms": sv["latency_p50_ms"], "p99_ms": sv["latency_p99_ms"],
                            "failed": sv["failed"], "oracle_err_sampled": sv["oracle_max_rel_err_sampled"],
                            "fifo_plain": None if not sv["plain_fifo"] else {

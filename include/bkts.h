@@ -432,12 +432,20 @@ void bkts_stepper_destroy(bkts_stepper st);
  * each round runs one grouped launch per block-CG kernel and block-width class over every solve
  * inside its inner iteration, so requests that arrive while others run share those launches.
  *
- * A request assembles the FV operator of its grid and coefficient field and solves the
- * all-at-once system of one window of k implicit stages from y0 (Sec. 2.1, eq.
- * general-system-time-steps; for implicit Euler, k time steps) by the Newton/splitting iteration
- * (eq. matrix-fixed-point-equation) until max_j ||R_j|| <= rtol ||rhs_0|| for every column j
- * (rhs_0 = front column of B A2^T + B0).  Each correction is an FP32 block-CG solve (Jacobi) of
- * the column-scaled FP64 residual to inner_rtol; residuals and updates are FP64.
+ * A request assembles the FV operator of its grid and coefficient field and advances y0 by k
+ * implicit stages (for implicit Euler, k time steps), in one of two modes:
+ *  - mode 0 (grouped window splitting): the all-at-once system of one window of k stages (Sec.
+ *    2.1, eq. general-system-time-steps) by the Newton/splitting iteration (eq.
+ *    matrix-fixed-point-equation) until max_j ||R_j|| <= rtol ||rhs_0|| for every column j
+ *    (rhs_0 = front column of B A2^T + B0).  Each correction is an FP32 block-CG solve (Jacobi)
+ *    of the column-scaled FP64 residual to inner_rtol, grouped with the other mode-0 requests;
+ *    residuals and updates are FP64.
+ *  - mode 1 (pipelined, implicit Euler only): Algorithm 1 with a window of `window` columns
+ *    (0: min(k, 4)), each front column accepted as soon as ||R_0|| <= rtol ||rhs_0|| (Sec. 2.2),
+ *    on the index-free stencil form of the operator with FP32 block CG preconditioned by the
+ *    geometric multigrid V-cycle (inner_rtol) inside the FP64 outer iteration.  Mode-1 requests
+ *    run on a few worker lanes, each with its own stream, beside the grouped rounds.
+ * Both modes share the arrival-order admission and the HBM budget.
  *
  * A request's result does not depend on the other requests in flight: every job keeps its own
  * launch geometry and reduction order. */
@@ -457,16 +465,18 @@ typedef struct bkts_request {
   double tau;
   double rtol;           /* outer tolerance, (0, 1) */
   double inner_rtol;     /* FP32 block-CG per-column relative tolerance, (0, 1) */
-  int max_outer;         /* 0: 200 */
+  int max_outer;         /* 0: 200 (mode 1: per accepted step) */
   int max_inner;         /* per correction; 0: 2000 */
   uint64_t tag;          /* returned in the result */
+  int mode;              /* 0: grouped window splitting; 1: pipelined Algorithm 1 with multigrid */
+  int window;            /* mode 1: window width in columns, 0 = min(k, 4) */
 } bkts_request;
 
 typedef struct bkts_result {
   uint64_t ticket, tag;
   int status;            /* BKTS_OK, BKTS_ENOCONV, BKTS_EBREAKDOWN, or the setup error */
   int outer_iterations, krylov_iterations;
-  double rel_residual;   /* max_j ||R_j|| / ||rhs_0|| at exit */
+  double rel_residual;   /* max_j ||R_j|| / ||rhs_0|| at exit (mode 1: the last front column's) */
   double t_submit, t_admit, t_done;  /* seconds on the server clock (bkts_server_clock) */
   size_t footprint_bytes;            /* HBM reserved for the request while it ran */
 } bkts_result;

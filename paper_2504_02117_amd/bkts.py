@@ -92,7 +92,8 @@ class bkts_request(C.Structure):
     _fields_ = [("grid", bkts_grid), ("kappa", C.c_void_p), ("kappa_const", C.c_double), ("bc_type", C.c_int * 6),
                 ("bc_value", C.c_double * 6), ("y0", C.c_void_p), ("y_out", C.c_void_p), ("method", C.c_int),
                 ("theta", C.c_double), ("k", C.c_int), ("tau", C.c_double), ("rtol", C.c_double),
-                ("inner_rtol", C.c_double), ("max_outer", C.c_int), ("max_inner", C.c_int), ("tag", C.c_uint64)]
+                ("inner_rtol", C.c_double), ("max_outer", C.c_int), ("max_inner", C.c_int), ("tag", C.c_uint64),
+                ("mode", C.c_int), ("window", C.c_int)]
 
 
 class bkts_result(C.Structure):
@@ -527,8 +528,10 @@ def bkts_server_create(ctx, hbm_budget_bytes, max_slots=64):
 
 
 def make_request(n, y0, y_out, k, tau, kappa=None, kappa_const=1.0, method=BKTS_IE, theta=0.5, rtol=1e-8,
-                 inner_rtol=1e-2, bc_type=None, bc_value=None, max_outer=0, max_inner=0, tag=0):
-    """A serving request; device buffers are torch tensors (y_out: (N, k) float64)."""
+                 inner_rtol=1e-2, bc_type=None, bc_value=None, max_outer=0, max_inner=0, tag=0, mode=0, window=0):
+    """A serving request; device buffers are torch tensors (y_out: (N, k) float64).  mode 0: grouped
+    window splitting; mode 1: pipelined Algorithm 1 with multigrid (implicit Euler), window columns
+    (0: min(k, 4))."""
     r = bkts_request()
     r.grid = _grid(n)
     r.kappa = _ptr(kappa)
@@ -539,6 +542,7 @@ def make_request(n, y0, y_out, k, tau, kappa=None, kappa_const=1.0, method=BKTS_
     r.y0, r.y_out = _ptr(y0), _ptr(y_out)
     r.method, r.theta, r.k, r.tau = method, theta, k, tau
     r.rtol, r.inner_rtol, r.max_outer, r.max_inner, r.tag = rtol, inner_rtol, max_outer, max_inner, tag
+    r.mode, r.window = mode, window
     return r
 
 

@@ -5,10 +5,13 @@
 // launch per block-CG kernel and block-width class for every job inside its inner solve, then one
 // read-back of all jobs' norms.  Requests that arrive while others run join at the next round.
 //
-// Each request solves the all-at-once system of one window of k columns (Sec. 2.1, eq.
+// A mode-0 request solves the all-at-once system of one window of k columns (Sec. 2.1, eq.
 // general-system-time-steps) by the Newton/splitting iteration of eq. matrix-fixed-point-equation,
 // until every column meets the tolerance; the inner solves are FP32 block CG with Jacobi, the
-// residual and the update are FP64.
+// residual and the update are FP64.  A mode-1 request runs the pipelined Algorithm 1 (its front
+// column accepted as soon as it converges) with multigrid-preconditioned block CG on a lane of its
+// own: kLanes threads, each with a context and stream, take mode-1 requests from the same
+// arrival-order queue under the same HBM budget.
 #include "server.hpp"
 
 #include <algorithm>
@@ -60,6 +63,26 @@ size_t bkts_server_s::footprint(const bkts_request& r) {
   return b;
 }
 
+// Mode 1: the operator (CSR with its FP32 values, the stencil form in FP64 and FP32), the
+// multigrid hierarchy (five coefficient arrays and an inverse diagonal in both precisions, about
+// 8/7 of the fine level in total), the pipeline window (Y, R, V and the stage history), the FP32
+// block-CG blocks (R, P, Q, Z, the scaled residual and correction), the multigrid level buffers,
+// the accepted steps (k x N) and small buffers.
+size_t bkts_server_s::footprint_pipelined(const bkts_request& r) {
+  const int64_t N = grid_cells(r.grid);
+  const int64_t nnz = (2 * r.grid.dim + 1) * N;
+  const int w = r.window > 0 ? r.window : std::min(r.k, 4);
+  size_t b = 0;
+  b += 4 * (N + 1) + nnz * (4 + 8 + 4) + 16 * N + 16 * (N + 1);  // CSR, diagonal, b, assembly scratch
+  b += (size_t)(1 + r.grid.dim) * N * (8 + 4);                    // stencil form
+  b += (size_t)(N * 8 / 7 + 64) * 6 * (8 + 4);                     // multigrid hierarchy
+  b += (size_t)N * w * 8 * 3 + (size_t)N * 8 * 6;                  // window, residual, correction, history
+  b += (size_t)N * w * 4 * 6 + (size_t)(N * 8 / 7 + 64) * w * 4 * 2;  // FP32 block CG, level buffers
+  b += (size_t)N * r.k * 8 + (size_t)N * 8;                        // accepted steps, y
+  b += (size_t)1 << 20;                                            // k x k buffers and partials
+  return b;
+}
+
 bkts_server_s::bkts_server_s(int device, size_t budget_, int max_slots_)
     : budget(budget_), max_slots(max_slots_), t0(std::chrono::steady_clock::now()) {
   BKTS_HIP(hipSetDevice(device));
@@ -78,7 +101,16 @@ bkts_server_s::bkts_server_s(int device, size_t budget_, int max_slots_)
   table_bytes = sizeof(GJob) * max_slots + sizeof(int) * 16 * (max_slots + 1) * 4;
   table_dev.alloc(table_bytes);
   BKTS_HIP(hipHostMalloc(&table_host, table_bytes, hipHostMallocDefault));
+  for (Lane& L : lanes) {
+    hipStream_t ls = nullptr;
+    BKTS_HIP(hipStreamCreateWithFlags(&ls, hipStreamNonBlocking));  // default priority
+    L.ctx = new bkts_ctx_s();
+    L.ctx->device = device;
+    L.ctx->stream = ls;
+    L.ctx->num_cu = ctx->num_cu;
+  }
   worker = std::thread([this] { run(); });
+  for (int l = 0; l < kLanes; ++l) lanes[l].th = std::thread([this, l] { lane_run(l); });
 }
 
 bkts_server_s::~bkts_server_s() {
@@ -88,6 +120,17 @@ bkts_server_s::~bkts_server_s() {
   }
   cv.notify_all();
   if (worker.joinable()) worker.join();
+  for (Lane& L : lanes)
+    if (L.th.joinable()) L.th.join();
+  for (Lane& L : lanes) {
+    if (!L.ctx) continue;
+    (void)hipStreamSynchronize(L.ctx->stream);
+    L.ctx->ws.bufs.clear();
+    if (L.ctx->h_pinned) (void)hipHostFree(L.ctx->h_pinned);
+    (void)hipStreamDestroy(L.ctx->stream);
+    delete L.ctx;
+    L.ctx = nullptr;
+  }
   (void)hipSetDevice(ctx->device);
   (void)hipStreamSynchronize(ctx->stream);
   for (auto& j : jobs) j.reset();
@@ -115,8 +158,11 @@ uint64_t bkts_server_s::submit(const bkts_request& r) {
   BKTS_REQUIRE(r.y0 && r.y_out, "request y0 and y_out must not be NULL");
   BKTS_REQUIRE(r.method == BKTS_IE || r.method == BKTS_THETA || r.method == BKTS_SDIRK2,
                "request method must be BKTS_IE, BKTS_THETA or BKTS_SDIRK2");
+  BKTS_REQUIRE(r.mode == 0 || r.mode == 1, "request mode must be 0 (grouped) or 1 (pipelined)");
+  BKTS_REQUIRE(r.mode == 0 || r.method == BKTS_IE, "pipelined (mode 1) requests take implicit Euler");
+  BKTS_REQUIRE(r.window >= 0 && r.window <= r.k, "request window must be in 0..k");
   BKTS_REQUIRE(grid_cells(r.grid) < (int64_t)1 << 30, "request grid too large");
-  const size_t fp = footprint(r);
+  const size_t fp = r.mode == 1 ? footprint_pipelined(r) : footprint(r);
   if (fp > budget)
     throw Error{BKTS_ENOMEM, fmt("request needs %.1f MB, more than the server budget of %.1f MB", fp / 1e6,
                                  budget / 1e6)};
@@ -181,6 +227,24 @@ void bkts_server_s::run() {
         while (!queue.empty() && !stop) {
           const Pending& h = queue.front();
           if (in_use + h.footprint > budget) break;
+          if (h.req.mode == 1) {  // a pipelined request goes to a free lane
+            int lane = -1;
+            for (int l = 0; l < kLanes; ++l)
+              if (!lanes[l].busy) {
+                lane = l;
+                break;
+              }
+            if (lane < 0) break;
+            in_use += h.footprint;
+            peak = std::max(peak, in_use);
+            ++n_active;
+            max_active = std::max(max_active, n_active);
+            lanes[lane].busy = true;
+            lanes[lane].p = h;
+            queue.pop_front();
+            cv.notify_all();
+            continue;
+          }
           int slot = -1;
           for (int s = 0; s < max_slots; ++s)
             if (!jobs[s] && std::find_if(admit.begin(), admit.end(), [&](auto& a) { return a.first == s; }) ==
@@ -197,7 +261,12 @@ void bkts_server_s::run() {
         if (stop) queue.clear();
       }
       for (auto& a : admit) setup(a.first, a.second);
-      if (n_active_now() > 0) round();
+      if (n_active_now() > 0) {
+        round();
+      } else {  // only lanes are busy, or the queue head waits for memory: sleep until something changes
+        std::unique_lock<std::mutex> g(mu);
+        if (!stop) cv.wait_for(g, std::chrono::milliseconds(2));
+      }
     }
   } catch (const Error& e) {
     std::lock_guard<std::mutex> g(mu);
@@ -210,6 +279,118 @@ void bkts_server_s::run() {
     fatal_msg = e.what();
     cv_done.notify_all();
   }
+}
+
+void bkts_server_s::lane_run(int l) {
+  Lane& L = lanes[l];
+  (void)hipSetDevice(L.ctx->device);
+  for (;;) {
+    Pending p;
+    {
+      std::unique_lock<std::mutex> g(mu);
+      cv.wait(g, [&] { return (L.busy && L.p.ticket != 0) || (stop && !L.busy) || fatal; });
+      if (!L.busy || fatal) {
+        if (fatal && L.busy) L.busy = false;
+        if (stop || fatal) return;
+        continue;
+      }
+      p = L.p;
+    }
+    bkts_result res{};
+    bool device_error = false;
+    std::string msg;
+    try {
+      res = lane_solve(L, p);
+    } catch (const Error& e) {
+      device_error = e.status == BKTS_EDEVICE;
+      msg = e.msg;
+      res.ticket = p.ticket;
+      res.tag = p.req.tag;
+      res.status = e.status;
+      res.t_submit = p.t_submit;
+      res.t_done = now();
+      res.footprint_bytes = p.footprint;
+    }
+    std::lock_guard<std::mutex> g(mu);
+    in_use -= p.footprint;
+    --n_active;
+    L.busy = false;
+    L.p = Pending{};
+    if (device_error) {
+      fatal = true;
+      fatal_msg = msg;
+    } else {
+      done.push_back(res);
+    }
+    cv_done.notify_all();
+    cv.notify_all();
+  }
+}
+
+// Mode 1: the pipelined Algorithm 1 (implicit Euler, window of `window` columns) with FP32 block CG
+// preconditioned by the multigrid V-cycle on the stencil form, then the k accepted steps written as
+// the columns of y_out.  The lane's workspace is released afterwards, with the request's footprint.
+bkts_result bkts_server_s::lane_solve(Lane& L, const Pending& p) {
+  bkts_ctx c = L.ctx;
+  const bkts_request& r = p.req;
+  bkts_result res{};
+  res.ticket = p.ticket;
+  res.tag = r.tag;
+  res.t_submit = p.t_submit;
+  res.t_admit = now();
+  res.footprint_bytes = p.footprint;
+  struct Cleanup {
+    bkts_ctx c;
+    ~Cleanup() {
+      (void)hipStreamSynchronize(c->stream);
+      c->ws.bufs.clear();
+    }
+  } cleanup{c};
+  bkts_fv_coeffs co{};
+  co.kappa = r.kappa;
+  co.kappa_const = r.kappa_const;
+  for (int f = 0; f < 6; ++f) {
+    co.bc_type[f] = r.bc_type[f];
+    co.bc_value[f] = r.bc_value[f];
+  }
+  try {
+    std::unique_ptr<bkts_op_s, OpDel> op(fv_assemble(c, &r.grid, &co, BKTS_FMT_STENCIL));
+    bkts_tc_desc d{};
+    d.method = BKTS_IE;
+    d.k = r.window > 0 ? r.window : std::min(r.k, 4);
+    d.tau = r.tau;
+    std::unique_ptr<bkts_tc_s, TcDel> tc(tc_create(c, &d));
+    const int64_t N = op->N;
+    double* y = c->ws.get<double>("lane_y", N);
+    double* hist = c->ws.get<double>("lane_hist", (size_t)N * r.k);
+    BKTS_HIP(hipMemcpyAsync(y, r.y0, sizeof(double) * N, hipMemcpyDeviceToDevice, c->stream));
+    bkts_solve_opts in{};
+    in.krylov = BKTS_CG;
+    in.precond = BKTS_PREC_MG;
+    in.precision = BKTS_PRECISION_F32_REFINE;
+    in.rtol = r.inner_rtol;
+    in.inner_rtol = r.inner_rtol;
+    in.maxit = r.max_inner > 0 ? r.max_inner : 100000;
+    in.restart = 30;
+    bkts_run_info ri{};
+    const bkts_status st = advance(c, op.get(), tc.get(), y, r.k, in, r.rtol, r.max_outer > 0 ? r.max_outer : 200,
+                                   hist, nullptr, nullptr, &ri);
+    for (int j = 0; j < r.k && j < ri.accepted_steps; ++j) {  // step j + 1 into column j of y_out
+      LinComb lc;
+      lc.add(1.0, hist + (size_t)j * N, 1);
+      lincomb(c, N, lc, r.y_out + j, r.k);
+    }
+    c->sync();
+    res.status = st;
+    res.outer_iterations = ri.outer_iterations;
+    res.krylov_iterations = ri.krylov_iterations;
+    res.rel_residual = ri.final_front_rel_residual;
+  } catch (const Error& e) {
+    if (e.status == BKTS_EDEVICE) throw;
+    res.status = e.status;
+  }
+  res.t_done = now();
+  return res;
 }
 
 int bkts_server_s::n_active_now() {

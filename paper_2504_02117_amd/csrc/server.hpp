@@ -43,6 +43,15 @@ struct bkts_server_s {
     int outer = 0, inner_it = 0, krylov = 0, final_status = BKTS_OK;
   };
 
+  // A worker lane for mode-1 (pipelined) requests: its own thread, context and stream.
+  struct Lane {
+    bkts_ctx ctx = nullptr;
+    std::thread th;
+    bool busy = false;  // a request is assigned (guarded by mu)
+    Pending p;
+  };
+  static constexpr int kLanes = 4;
+
   bkts_ctx ctx = nullptr;  // the server's own context and stream
   size_t budget;
   int max_slots;
@@ -61,6 +70,7 @@ struct bkts_server_s {
 
   // worker-only state
   std::vector<std::unique_ptr<Job>> jobs;  // one per slot
+  Lane lanes[kLanes];
   bkts::DevBuf status_dev, table_dev;
   double* status_host = nullptr;
   void* table_host = nullptr;
@@ -70,6 +80,7 @@ struct bkts_server_s {
   bkts_server_s(int device, size_t budget, int max_slots);
   ~bkts_server_s();
   static size_t footprint(const bkts_request& r);
+  static size_t footprint_pipelined(const bkts_request& r);
   double now() const;
   uint64_t submit(const bkts_request& r);
   int poll(bkts_result* out, int max);
@@ -78,6 +89,8 @@ struct bkts_server_s {
 
  private:
   void run();
+  void lane_run(int l);
+  bkts_result lane_solve(Lane& L, const Pending& p);
   int n_active_now();
   void setup(int slot, const Pending& p);
   void round();

@@ -1,6 +1,7 @@
 """GPU tests of the serving loop: every request's window against the oracle's sequential stepping,
 bitwise equality of a request alone and inside a mix of other requests, HBM-budgeted admission
-and continuous batching (requests admitted while others run)."""
+and continuous batching (requests admitted while others run), for grouped window-splitting
+requests (mode 0) and pipelined multigrid requests on worker lanes (mode 1)."""
 import sys
 import time
 
@@ -34,8 +35,9 @@ def env():
 class Req:
     """One synthetic request: 2-D lognormal diffusion (seed = tag), y0 = sin-product."""
 
-    def __init__(self, torch, n, k, tag, method="ie", tau=1e-3, sigma=1.0):
+    def __init__(self, torch, n, k, tag, method="ie", tau=1e-3, sigma=1.0, mode=0, window=0):
         self.n, self.k, self.tag, self.method, self.tau = n, k, tag, method, tau
+        self.mode, self.window = mode, window
         self.kappa = inputs.lognormal_field(n, 0.0, sigma, 4.0, tag)
         self.y0 = inputs.sin_product(n)
         self.N = int(np.prod(n))
@@ -45,7 +47,8 @@ class Req:
 
     def request(self, bkts, rtol=1e-12, inner_rtol=1e-3):
         return bkts.make_request(self.n, self.y0d, self.out, self.k, self.tau, kappa=self.kd,
-                                 method=METHODS[self.method], rtol=rtol, inner_rtol=inner_rtol, tag=self.tag)
+                                 method=METHODS[self.method], rtol=rtol, inner_rtol=inner_rtol, tag=self.tag,
+                                 mode=self.mode, window=self.window)
 
     def oracle_columns(self):
         """Window columns by sequential stepping: every implicit stage in order."""
@@ -78,15 +81,18 @@ def check_against_oracle(r, res):
         assert rel < 1e-8, (r.n, r.k, r.method, j, rel)
 
 
-@pytest.mark.parametrize("n,k,method", [((16, 16), 4, "ie"), ((24, 20), 1, "ie"), ((33, 31), 8, "ie"),
-                                        ((20, 18), 3, "sdirk2"), ((18, 18), 16, "ie"), ((12, 10), 32, "ie"),
-                                        ((21, 19), 5, "theta"), ((40, 8), 2, "sdirk2")])
-def test_request_matches_oracle(env, n, k, method):
+@pytest.mark.parametrize("n,k,method,mode,window", [
+    ((16, 16), 4, "ie", 0, 0), ((24, 20), 1, "ie", 0, 0), ((33, 31), 8, "ie", 0, 0),
+    ((20, 18), 3, "sdirk2", 0, 0), ((18, 18), 16, "ie", 0, 0), ((12, 10), 32, "ie", 0, 0),
+    ((21, 19), 5, "theta", 0, 0), ((40, 8), 2, "sdirk2", 0, 0),
+    ((16, 16), 4, "ie", 1, 0), ((24, 20), 1, "ie", 1, 0), ((33, 31), 8, "ie", 1, 0), ((70, 66), 16, "ie", 1, 0),
+    ((12, 10), 32, "ie", 1, 0), ((45, 43), 7, "ie", 1, 2), ((30, 28), 5, "ie", 1, 5)])
+def test_request_matches_oracle(env, n, k, method, mode, window):
     torch, bkts, ctx = env
-    say(f"serving single n={n} k={k} {method}")
+    say(f"serving single n={n} k={k} {method} mode={mode} window={window}")
     srv = bkts.bkts_server_create(ctx, 1 << 30, 8)
     try:
-        r = Req(torch, n, k, 7, method=method)
+        r = Req(torch, n, k, 7, method=method, mode=mode, window=window)
         torch.cuda.synchronize()
         res = run_all(bkts, srv, [r])[r]
         check_against_oracle(r, res)
@@ -95,13 +101,14 @@ def test_request_matches_oracle(env, n, k, method):
         bkts.bkts_server_destroy(srv)
 
 
-def test_alone_equals_mix_and_batching(env):
-    """The same request alone and among 11 others of mixed sizes and widths: bitwise equal
+@pytest.mark.parametrize("probe_mode", [0, 1])
+def test_alone_equals_mix_and_batching(env, probe_mode):
+    """The same request alone and among 11 others of mixed sizes, widths and modes: bitwise equal
     outputs, each within 1e-8 of the oracle; later requests join while earlier ones run."""
     torch, bkts, ctx = env
-    say("serving alone vs mix")
+    say(f"serving alone vs mix, probe mode {probe_mode}")
     probe_shape = ((48, 40), 8)
-    alone = Req(torch, probe_shape[0], probe_shape[1], 3)
+    alone = Req(torch, probe_shape[0], probe_shape[1], 3, mode=probe_mode)
     torch.cuda.synchronize()
     srv = bkts.bkts_server_create(ctx, 1 << 30, 4)
     try:
@@ -115,8 +122,8 @@ def test_alone_equals_mix_and_batching(env):
     for i in range(11):
         n = int(rng.choice([16, 24, 32, 64]))
         k = int(rng.choice([1, 4, 8, 16, 32]))
-        mix.append(Req(torch, (n, n), k, 100 + i))
-    probe = Req(torch, probe_shape[0], probe_shape[1], 3)
+        mix.append(Req(torch, (n, n), k, 100 + i, mode=i % 2))
+    probe = Req(torch, probe_shape[0], probe_shape[1], 3, mode=probe_mode)
     torch.cuda.synchronize()
     srv = bkts.bkts_server_create(ctx, 1 << 30, 6)
     try:
@@ -149,10 +156,11 @@ def test_alone_equals_mix_and_batching(env):
     say(f"  rounds={st.rounds} launches={st.grouped_launches} max_active={st.max_active}")
 
 
-def test_admission_respects_budget(env):
+@pytest.mark.parametrize("mode", [0, 1])
+def test_admission_respects_budget(env, mode):
     torch, bkts, ctx = env
-    say("serving budget")
-    reqs = [Req(torch, (64, 64), 16, 200 + i) for i in range(4)]
+    say(f"serving budget, mode {mode}")
+    reqs = [Req(torch, (64, 64), 16, 200 + i, mode=mode) for i in range(4)]
     torch.cuda.synchronize()
     fp = None
     srv = bkts.bkts_server_create(ctx, 1 << 40, 8)
@@ -183,6 +191,17 @@ def test_submit_errors(env):
         assert e.value.status == bkts.BKTS_ENOMEM
         bad = r.request(bkts)
         bad.k = 33
+        with pytest.raises(bkts.BktsError) as e:
+            bkts.bkts_server_submit(srv, bad)
+        assert e.value.status == bkts.BKTS_EINVAL
+        small = Req(torch, (8, 8), 4, 2)
+        for field, value in (("mode", 2), ("window", 5), ("window", -1)):
+            bad = small.request(bkts)
+            setattr(bad, field, value)
+            with pytest.raises(bkts.BktsError) as e:
+                bkts.bkts_server_submit(srv, bad)
+            assert e.value.status == bkts.BKTS_EINVAL, (field, value)
+        bad = Req(torch, (8, 8), 4, 2, method="sdirk2", mode=1).request(bkts)  # pipelined: implicit Euler only
         with pytest.raises(bkts.BktsError) as e:
             bkts.bkts_server_submit(srv, bad)
         assert e.value.status == bkts.BKTS_EINVAL
