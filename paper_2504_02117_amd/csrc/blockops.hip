@@ -130,6 +130,58 @@ __global__ __launch_bounds__(256) void coldots_kernel(int64_t N, int k, DotPairs
   dev::block_reduce_store<KP, NP>(acc, red, partials, gridDim.x, slot);
 }
 
+// Column-wise dot products for full-width, 16-byte aligned contiguous blocks (k == KP, rows of
+// 16 bytes or more): each lane owns VEC = 16 / sizeof(T) consecutive columns of a row and loads them
+// as one 16-byte vector, LPR = KP / VEC lanes share a row, and persistent workgroups (the resident
+// capacity of the chip) walk contiguous XCD-aware row ranges.  FP64 accumulation; lanes with the
+// same columns are summed by shuffles in a fixed order, then the four waves through LDS.  Same
+// partial layout as coldots_kernel (entry p*KP + c).
+template <typename T, int KP, int NP>
+__global__ __launch_bounds__(256) void coldots_vec_kernel(int64_t N, DotPairs d, double* partials) {
+  constexpr int VEC = 16 / sizeof(T);
+  constexpr int LPR = KP / VEC;
+  constexpr int RPW = 256 / LPR;  // rows per workgroup step
+  typedef T vt __attribute__((ext_vector_type(VEC)));
+  __shared__ double red[4][NP * KP];
+  const int t = threadIdx.x, l = t % LPR;
+  const int64_t slot = dev::xcd_slot(blockIdx.x, gridDim.x);
+  const int64_t per = (N + gridDim.x - 1) / gridDim.x;
+  const int64_t r_begin = slot * per, r_end = r_begin + per < N ? r_begin + per : N;
+  double acc[NP][VEC];
+#pragma unroll
+  for (int p = 0; p < NP; ++p)
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) acc[p][v] = 0.0;
+  for (int64_t r = r_begin + t / LPR; r < r_end; r += RPW) {
+    vt x[NP], y[NP];
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+      x[p] = *reinterpret_cast<const vt*>(static_cast<const T*>(d.x[p]) + r * KP + l * VEC);
+      y[p] = *reinterpret_cast<const vt*>(static_cast<const T*>(d.y[p]) + r * KP + l * VEC);
+    }
+#pragma unroll
+    for (int p = 0; p < NP; ++p)
+#pragma unroll
+      for (int v = 0; v < VEC; ++v) acc[p][v] = fma((double)x[p][v], (double)y[p][v], acc[p][v]);
+  }
+#pragma unroll
+  for (int off = LPR; off < 64; off <<= 1)
+#pragma unroll
+    for (int p = 0; p < NP; ++p)
+#pragma unroll
+      for (int v = 0; v < VEC; ++v) acc[p][v] += __shfl_xor(acc[p][v], off);
+  const int w = t >> 6, lane = t & 63;
+  if (lane < LPR) {
+#pragma unroll
+    for (int p = 0; p < NP; ++p)
+#pragma unroll
+      for (int v = 0; v < VEC; ++v) red[w][p * KP + lane * VEC + v] = acc[p][v];
+  }
+  __syncthreads();
+  for (int e = t; e < NP * KP; e += 256)
+    partials[(int64_t)e * gridDim.x + slot] = ((red[0][e] + red[1][e]) + red[2][e]) + red[3][e];
+}
+
 // out[i] = sum over slots of partials[e(i)][slot], e(i) = (i / kout) * KP + i % kout for the
 // Gram layout (nrow = kout) or e(i) = i for vectors (nrow = 1).  One workgroup per output entry,
 // fixed summation order.
@@ -381,8 +433,35 @@ void launch_colnorm_t(bkts_ctx ctx, int dtype, int64_t N, int k, const void* X, 
   BKTS_HIP(hipGetLastError());
 }
 
+template <typename T, int KP, int NP>
+void launch_coldots_vec(bkts_ctx ctx, int64_t N, int k, const DotPairs& d, double* const* out) {
+  static_assert(KP * sizeof(T) >= 16, "rows of 16 bytes or more");
+  int64_t nb = (int64_t)blocks_per_cu(reinterpret_cast<const void*>(coldots_vec_kernel<T, KP, NP>)) * ctx->num_cu;
+  constexpr int64_t rows_per_step = 256 / (KP / (16 / (int)sizeof(T)));
+  const int64_t steps = (N + rows_per_step - 1) / rows_per_step;
+  if (nb > steps) nb = steps;
+  if (nb < 1) nb = 1;
+  double* part = ctx->ws.get<double>("dots_partials", (size_t)NP * KP * nb);
+  ProfScope prof(ctx, BKTS_K_NORMS, 2.0 * NP * N * k * sizeof(T));
+  launch(ctx, (coldots_vec_kernel<T, KP, NP>), dim3((unsigned)nb), dim3(256), 0, N, d, part);
+  BKTS_HIP(hipGetLastError());
+  prof.end();
+  FoldSet sets[3];
+  for (int p = 0; p < NP; ++p) sets[p] = FoldSet{part + (size_t)p * KP * nb, KP, 1, out[p]};
+  finalize_sets(ctx, (int)nb, k, sets, NP);
+}
+
 template <int KP, int NP>
 void launch_coldots_t(bkts_ctx ctx, int dtype, int64_t N, int k, const DotPairs& d, double* const* out) {
+  auto al16 = [](const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; };
+  bool vec = k == KP;
+  for (int p = 0; p < NP; ++p) vec = vec && al16(d.x[p]) && al16(d.y[p]);
+  if (vec && dtype == BKTS_F64) {
+    if constexpr (KP >= 2) return launch_coldots_vec<double, KP, NP>(ctx, N, k, d, out);
+  }
+  if (vec && dtype == BKTS_F32) {
+    if constexpr (KP >= 4) return launch_coldots_vec<float, KP, NP>(ctx, N, k, d, out);
+  }
   Slots s = make_slots<KP>(ctx, N);
   double* part = ctx->ws.get<double>("dots_partials", (size_t)NP * KP * s.nslots);
   ProfScope prof(ctx, BKTS_K_NORMS, 2.0 * NP * N * k * esize(dtype));
@@ -560,6 +639,13 @@ void col_dots(bkts_ctx ctx, int dtype, int64_t N, int k, int npairs, const void*
 }
 
 void colnorms2(bkts_ctx ctx, int dtype, int64_t N, int k, const void* X, int ldx, double* out) {
+  // a full-width contiguous block of 16-byte rows: the vectorized column-dot pass of X with itself
+  if (ldx == k && (reinterpret_cast<uintptr_t>(X) & 15) == 0 && (k & (k - 1)) == 0 &&
+      k * (int)esize(dtype) >= 16) {
+    const void* xs[1] = {X};
+    double* os[1] = {out};
+    return col_dots(ctx, dtype, N, k, 1, xs, xs, os);
+  }
   BKTS_KP_DISPATCH(k, (launch_colnorm_t<KP>(ctx, dtype, N, k, X, ldx, out)));
 }
 

@@ -23,13 +23,15 @@ using dev::TileGeom;
 __device__ __forceinline__ double poly(const double (&c)[4], double u) { return ((c[3] * u + c[2]) * u + c[1]) * u + c[0]; }
 __device__ __forceinline__ double dpoly(const double (&c)[4], double u) { return (3.0 * c[3] * u + 2.0 * c[2]) * u + c[1]; }
 
+// Grid coordinates of cell r (32-bit arithmetic: operators are created with N < 2^31).
 __device__ __forceinline__ void coords(const NlDev& g, int64_t r, int (&i)[3]) {
-  int64_t q = r;
+  uint32_t q = (uint32_t)r;
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
     if (d < g.dim) {
-      i[d] = (int)(q % g.n[d]);
-      q /= g.n[d];
+      const uint32_t q2 = q / (uint32_t)g.n[d];
+      i[d] = (int)(q - q2 * (uint32_t)g.n[d]);
+      q = q2;
     } else {
       i[d] = 0;
     }
@@ -67,6 +69,15 @@ __device__ __forceinline__ double vg_dkr(const NlDev& g, double psi) {
   return (0.5 / sqrt(s) * gg * gg + sqrt(s) * 2.0 * gg * dg) * ds;
 }
 
+// theta(psi) and kr(psi) together: one saturation evaluation serves both (same operations as
+// vg_theta and vg_kr, so the same values)
+__device__ __forceinline__ void vg_theta_kr(const NlDev& g, double psi, double& theta, double& kr) {
+  theta = vg_theta(g, psi);
+  const double s = theta / g.ts;
+  const double gg = 1.0 - pow(1.0 - pow(s, 1.0 / g.vm), g.vm);
+  kr = sqrt(s) * gg * gg;
+}
+
 __device__ __forceinline__ double mass_at(const NlDev& g, double u) { return g.kind == 1 ? vg_theta(g, u) : u; }
 
 __device__ __forceinline__ double harm(double a, double b) { return a + b > 0.0 ? 2.0 * a * b / (a + b) : 0.0; }
@@ -96,6 +107,47 @@ __device__ double ri_f_at(const NlDev& g, const double* u, int ld, int64_t r) {
     }
   }
   return f;
+}
+
+// Richards f(psi)_r as ri_f_at, with kr read from kr[q * ldk] (evaluated once per cell beforehand)
+// instead of evaluated at the cell and at each neighbour.
+__device__ double ri_f_cached(const NlDev& g, const double* u, int ld, const double* kr, int ldk, int64_t r) {
+  int i[3];
+  coords(g, r, i);
+  const int zd = g.dim - 1;
+  const double up = u[r * ld], krp = kr[r * ldk], ksp = g.ks[r];
+  const double zp = (i[zd] + 0.5) * g.hz, Hp = up + zp;
+  double f = 0.0;
+  int64_t st = 1;
+  for (int d = 0; d < g.dim; ++d) {
+    for (int side = 0; side < 2; ++side) {
+      const bool interior = side == 0 ? i[d] > 0 : i[d] < g.n[d] - 1;
+      if (interior) {
+        const int64_t q = side == 0 ? r - st : r + st;
+        const double uq = u[q * ld];
+        const double Hq = uq + (d == zd ? zp + (side == 0 ? -g.hz : g.hz) : zp);
+        f += harm(ksp, g.ks[q]) * g.w[d] * 0.5 * (krp + kr[q * ldk]) * (Hp - Hq);
+      } else if (d == zd && side == 1 && g.top_dirichlet) {
+        f += 2.0 * ksp * 0.5 * (krp + g.top_kr) * (Hp - (g.top_g + 1.0)) * g.w[d];
+      } else if (d == zd && side == 0 && g.bottom_drain) {
+        f += ksp * krp / g.hz;
+      }
+    }
+    st *= g.n[d];
+  }
+  return f;
+}
+
+// theta and kr of every entry of the first k columns of Y, into TH and KR (N x k, contiguous)
+__global__ void ri_cache_kernel(NlDev g, int64_t N, int k, const double* Y, int ldy, double* TH, double* KR) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N * k) return;
+  const int64_t r = i / k;
+  const int c = (int)(i - r * k);
+  double th, kr;
+  vg_theta_kr(g, Y[r * ldy + c], th, kr);
+  TH[i] = th;
+  KR[i] = kr;
 }
 
 // f(u)_r for the column of u with stride ld (u[q * ld])
@@ -240,6 +292,8 @@ struct NlResArgs {
   int ldr;
   double* partials;
   int64_t tps;
+  const double* th;  // Richards: theta and kr of every entry (N x k), or null
+  const double* kr;
 };
 
 template <int KP>
@@ -274,8 +328,13 @@ __global__ __launch_bounds__(256) void nl_residual_kernel(NlResArgs a) {
       const int row = r0 + i * G::RS;
       const int64_t gr = row0 + row;
       const bool ok = gr < a.N && cok;
-      Yl[row * G::LDL + c] = ok ? mass_at(a.g, a.Y[gr * a.ldy + c]) : 0.0;
-      Fl[row * G::LDL + c] = ok ? f_at(a.g, a.Y + c, a.ldy, gr) : 0.0;
+      if (a.kr) {
+        Yl[row * G::LDL + c] = ok ? a.th[gr * a.k + c] : 0.0;
+        Fl[row * G::LDL + c] = ok ? ri_f_cached(a.g, a.Y + c, a.ldy, a.kr + c, a.k, gr) : 0.0;
+      } else {
+        Yl[row * G::LDL + c] = ok ? mass_at(a.g, a.Y[gr * a.ldy + c]) : 0.0;
+        Fl[row * G::LDL + c] = ok ? f_at(a.g, a.Y + c, a.ldy, gr) : 0.0;
+      }
     }
     __syncthreads();
 #pragma unroll
@@ -330,6 +389,7 @@ bkts_nlop nlop_create(bkts_ctx ctx, const bkts_grid* grid, const bkts_nl_coeffs*
       g.w[d] = (double)g.n[d] * g.n[d];
       nl->N *= g.n[d];
     }
+    BKTS_REQUIRE(nl->N < ((int64_t)1 << 31), "grid too large (N >= 2^31)");
     for (int i = 0; i < 4; ++i) {
       g.dc[i] = c->dcoef[i];
       g.rc[i] = c->rcoef[i];
@@ -388,6 +448,7 @@ bkts_nlop richards_create(bkts_ctx ctx, const bkts_grid* grid, const double* ks,
       g.w[d] = (double)g.n[d] * g.n[d];
       nl->N *= g.n[d];
     }
+    BKTS_REQUIRE(nl->N < ((int64_t)1 << 31), "grid too large (N >= 2^31)");
     g.tr = p->theta_r;
     g.ts = p->theta_s;
     g.alpha = p->alpha;
@@ -448,6 +509,16 @@ void nl_residual(bkts_ctx ctx, const bkts_nlop_s& nl, int k, const double* Y, in
   for (int j = 0; j < 8; ++j) a.b0col[j] = j < a.nb0 ? b0_to_col[j] : -1;
   a.R = R;
   a.ldr = ldr;
+  if (nl.nd.kind == 1) {  // Richards: theta and kr once per entry, then the flux pass reads them
+    double* th = ctx->ws.get<double>("ri_theta", (size_t)nl.N * k);
+    double* kr = ctx->ws.get<double>("ri_kr", (size_t)nl.N * k);
+    const int64_t n = nl.N * k;
+    ProfScope prof(ctx, BKTS_K_OTHER, 24.0 * n);
+    launch(ctx, ri_cache_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, nl.nd, nl.N, k, Y, ldy, th, kr);
+    BKTS_HIP(hipGetLastError());
+    a.th = th;
+    a.kr = kr;
+  }
   switch (k <= 1 ? 1 : k <= 2 ? 2 : k <= 4 ? 4 : k <= 8 ? 8 : k <= 16 ? 16 : 32) {
     case 1: launch_nlres<1>(ctx, a, nrm); break;
     case 2: launch_nlres<2>(ctx, a, nrm); break;
