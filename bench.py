@@ -128,9 +128,13 @@ def kernel_table(bkts, ctx):
     return out
 
 
-def kernel_name(cat, k, fmt="sell"):
+def kernel_name(cat, k, fmt="sell", precond="jacobi"):
     """The kernel behind a profiling category in the block-CG inner solve at width k."""
     row = k in (1, 2, 4)  # one thread per row; wider blocks use column tiles (MFMA for the updates)
+    if row and fmt == "stencil" and precond == "mg":  # V-cycle fused into the iteration
+        fused = {"cg_update": "rk_cg_xr_kernel", "cg_pupdate": "rk_cg_xp_kernel"}
+        if cat in fused:
+            return fused[cat]
     if fmt == "stencil":
         spmm = "rk_st_spmm_gram_kernel" if row else "st_spmm_kernel"
     else:
@@ -146,12 +150,12 @@ def kernel_name(cat, k, fmt="sell"):
             "mg_coarse": "multigrid kernels of the coarser levels"}.get(cat, cat)
 
 
-def roofline_of(kt, cat, k, precision, fmt="sell"):
+def roofline_of(kt, cat, k, precision, fmt="sell", precond="jacobi"):
     """HBM roofline of one profiling category: algorithmic bytes per launch / average launch time."""
     v = kt[cat]
     bpl = v["bytes_per_launch"]
     achieved = bpl / (v["avg_us"] * 1e-6) / 1e9
-    name = kernel_name(cat, k, fmt)
+    name = kernel_name(cat, k, fmt, precond)
     return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_for(name, precision, k), "kernel": name,
             "category": cat, "algorithmic_bytes_per_launch": bpl, "avg_launch_us": v["avg_us"],
@@ -197,10 +201,33 @@ def run_spmm_sweep(torch, bkts, ctx, a, kd, n):
     working set of consecutive launches exceeds the 256 MiB Infinity Cache (each launch reads cold
     data). Time per launch comes from the library's in-dispatch event timers."""
     N = n[0] * n[1] * n[2]
-    out = {}
+    out = {"copy": stream_copy_rate(torch)}
     for fmt, code in (("sell", bkts.BKTS_FMT_SELL), ("stencil", bkts.BKTS_FMT_STENCIL)):
         out.update(spmm_sweep_format(torch, bkts, ctx, a, kd, n, N, fmt, code))
     return out
+
+
+def stream_copy_rate(torch, mib=256, reps=12):
+    """Practical streaming ceiling: device-to-device copies of `mib` MiB in rotation over three buffer
+    pairs (cold in the Infinity Cache), read + write bytes over the median copy time."""
+    n = (mib << 20) // 8
+    src = [torch.full((n,), 1.0, dtype=torch.float64, device="cuda") for _ in range(3)]
+    dst = [torch.empty_like(x) for x in src]
+    times = []
+    for i in range(reps + 3):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        dst[i % 3].copy_(src[i % 3])
+        e1.record()
+        e1.synchronize()
+        if i >= 3:
+            times.append(e0.elapsed_time(e1))
+    del src, dst
+    ms = statistics.median(times)
+    gbs = 2.0 * (mib << 20) / (ms * 1e-3) / 1e9
+    log(f"  copy {mib} MiB: {1e3 * ms:.1f} us  {gbs:.0f} GB/s  frac {gbs / HBM_PEAK_GBS:.3f}")
+    return {"avg_us": 1e3 * ms, "GBps": gbs, "frac": gbs / HBM_PEAK_GBS, "bytes_per_copy": 2.0 * (mib << 20),
+            "kernel": "device-to-device copy (torch copy_)"}
 
 
 def spmm_sweep_format(torch, bkts, ctx, a, kd, n, N, fmt, code):
@@ -228,7 +255,8 @@ def spmm_sweep_format(torch, bkts, ctx, a, kd, n, N, fmt, code):
             key = f"{prec} k={k}" if fmt == "sell" else f"{fmt} {prec} k={k}"
             out[key] = {"avg_us": us, "GBps": gbs, "frac": gbs / HBM_PEAK_GBS,
                         "algorithmic_bytes_per_launch": bpl, "flop_per_byte": 2.0 * nnz * k / bpl,
-                        "kernel": spmm_kernel_name(k, prec, fmt), "format": fmt, "launches": cnt}
+                        "kernel": spmm_kernel_name(k, prec, fmt), "format": fmt, "launches": cnt,
+                        "traffic": traffic_for(spmm_kernel_name(k, prec, fmt), prec, k)}
             log(f"  spmm {fmt:7s} {prec} k={k:2d}: {us:7.1f} us  {gbs:6.0f} GB/s  frac {gbs / HBM_PEAK_GBS:.3f}  "
                 f"AI {2.0 * nnz * k / bpl:.3f} flop/B")
             del Xs, Ys
@@ -753,13 +781,13 @@ def cpu_baselines(a, K, b, u0, N):
             "cg_iterations": its, "cpu_model": _cpu_model(), "nproc": os.cpu_count()}
 
 
-def pick_roofline(kt, k, precision, fmt):
+def pick_roofline(kt, k, precision, fmt, precond="jacobi"):
     """Roofline of the category with the largest share of kernel time (no exclusions), plus the
     categories made of small latency-bound launches, reported by their launch counts."""
     if not kt:
         return None, None
     dom = max(kt, key=lambda c: kt[c]["total_ms"])
-    roof = roofline_of(kt, dom, k, precision, fmt)
+    roof = roofline_of(kt, dom, k, precision, fmt, precond)
     lat = {c: {"launches": kt[c]["launches"], "avg_us": kt[c]["avg_us"], "share": kt[c]["share"]}
            for c in ("mg_coarse", "small") if c in kt}
     return roof, lat
@@ -785,8 +813,11 @@ def compact_line(out, full_path):
         "bound", "achieved", "peak", "unit", "frac", "traffic", "kernel", "category", "avg_launch_us",
         "algorithmic_bytes_per_launch", "share_of_kernel_time")}
     sw = out.get("spmm_sweep") or {}
-    spmm = {kk: {"us": v["avg_us"], "frac": v["frac"], "kernel": v["kernel"]} for kk, v in sw.items()
+    spmm = {kk: {"us": v["avg_us"], "frac": v["frac"], "kernel": v["kernel"], "traffic": v.get("traffic")}
+            for kk, v in sw.items()
             if kk.endswith("k=16") or kk.endswith("k=4")}
+    if "copy" in sw:
+        spmm["copy_256MiB"] = {"us": sw["copy"]["avg_us"], "frac": sw["copy"]["frac"]}
     cpu = out["cpu_baseline"]
     legs = {}
     if out.get("nonlinear"):
@@ -911,7 +942,7 @@ def main():
             "kernels": {kk: {"avg_us": vv["avg_us"], "GBps": vv["GBps"]} for kk, vv in r["kernels"].items()}}
         log(f"  sweep k={ks} {prec} inner={tol:g}: {r['value']:.4g} DOF*steps/s (spmm {sp.get('avg_us', 0):.1f} us)")
 
-    roof, lat = pick_roofline(blk["kernels"], a.k, a.precision, a.format)
+    roof, lat = pick_roofline(blk["kernels"], a.k, a.precision, a.format, a.precond)
     spmm_roof = roofline_of(blk["kernels"], "spmm", a.k, a.precision, a.format) if "spmm" in blk["kernels"] else None
 
     formats = None
