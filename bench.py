@@ -700,6 +700,7 @@ def run_richards(torch, bkts, ctx, a):
     ks, y0 = setup(n, 8.0)
     res = {}
     for name, k, kry, prec in (("block_gmres", a.ri_k, GM, F32), ("block_bicgstab", a.ri_k, BI, F32),
+                               ("block_bicgstab_k4", 4, BI, F32),  # the width the paper finds best
                                ("plain_gmres", 1, GM, F64), ("plain_bicgstab", 1, BI, F64)):
         log(f"Richards leg {n}: {name} k={k}, inner {a.ri_inner_rtol:g}, {a.ri_steps} steps")
         r = form(n, ks, y0, k, kry, prec, a.ri_steps, 1, name == "block_gmres")

@@ -177,6 +177,8 @@ struct NlDev {
   // Richards: van Genuchten closure, saturated conductivity per cell, z = last axis
   double tr, ts, alpha, vn, vm;
   const double* ks;
+  const double* tf;  // per cell, 4 values: harm(Ks_P, Ks_Q) / h_d^2 of the face to the next cell Q along
+                     // x, y, z (0 where there is none), then Ks_P
   int top_dirichlet, bottom_drain;
   double top_g, top_kr, hz;
   double lin_L;  // > 0: the mass derivative in the Jacobian is this constant (L-scheme)
@@ -190,6 +192,7 @@ struct bkts_nlop_s {
   int64_t N = 0;
   bkts_op jac = nullptr;  // stencil sparsity; values overwritten by bkts_nl_jacobian
   bkts::DevBuf ks;        // Richards: own copy of the saturated conductivity
+  bkts::DevBuf tf;        // Richards: face transmissibilities and Ks per cell (NlDev::tf)
   ~bkts_nlop_s() { delete jac; }
 };
 

@@ -38,67 +38,130 @@ __device__ __forceinline__ void coords(const NlDev& g, int64_t r, int (&i)[3]) {
   }
 }
 
-__device__ __forceinline__ int64_t stride_of(const NlDev& g, int d) {
-  int64_t s = 1;
-  for (int e = 0; e < d; ++e) s *= g.n[e];
-  return s;
+// ---- van Genuchten closure (eq. RelationshipsThetaK), s = theta / theta_s as printed.
+// With a = -alpha psi (psi < 0), t = a^n, S_e = (1 + t)^(-m), m = 1 - 1/n, w = 1 - s^(1/m), g = 1 - w^m:
+//   theta = theta_r + (theta_s - theta_r) S_e,        kr = s^(1/2) g^2,
+//   dS_e/dpsi = alpha m n a^(n-1) (1 + t)^(-m-1) = alpha m n (t / a) S_e / (1 + t),
+//   dkr/dpsi = (s^(-1/2) g^2 / 2 + 2 s^(1/2) g w^(m-1) s^(1/m-1)) ds/dpsi,  w^(m-1) s^(1/m-1) = (w^m / w)(s^(1/m) / s).
+// Every power goes through one logarithm and one exponential, and the derivatives reuse the powers
+// of the values. For n = 2 (m = 1/2, 1/m = 2) the powers are products and square roots.
+struct VgVals {
+  double theta, kr, dtheta, dkr;
+};
+
+__device__ __forceinline__ double vg_se_t(const NlDev& g, double a, double& t) {
+  if (g.vn == 2.0) {
+    t = a * a;
+    return 1.0 / sqrt(1.0 + t);
+  }
+  t = exp(g.vn * log(a));
+  return exp(-g.vm * log1p(t));
 }
 
-// ---- van Genuchten closure (eq. RelationshipsThetaK), s = theta / theta_s as printed
-__device__ __forceinline__ double vg_se(const NlDev& g, double psi) {
-  return psi < 0.0 ? pow(1.0 + pow(-g.alpha * psi, g.vn), -g.vm) : 1.0;
-}
-__device__ __forceinline__ double vg_dse(const NlDev& g, double psi) {
-  if (!(psi < 0.0)) return 0.0;
+template <bool DERIV>
+__device__ __forceinline__ VgVals vg_eval(const NlDev& g, double psi) {
+  VgVals v;
+  if (!(psi < 0.0)) {  // saturated: S_e = 1, s = 1, w = 0
+    v.theta = g.ts;
+    v.kr = 1.0;
+    v.dtheta = 0.0;
+    v.dkr = 0.0;
+    return v;
+  }
   const double a = -g.alpha * psi;
-  return g.vm * g.vn * g.alpha * pow(a, g.vn - 1.0) * pow(1.0 + pow(a, g.vn), -g.vm - 1.0);
-}
-__device__ __forceinline__ double vg_theta(const NlDev& g, double psi) { return g.tr + (g.ts - g.tr) * vg_se(g, psi); }
-__device__ __forceinline__ double vg_dtheta(const NlDev& g, double psi) { return (g.ts - g.tr) * vg_dse(g, psi); }
-__device__ __forceinline__ double vg_kr(const NlDev& g, double psi) {
-  const double s = vg_theta(g, psi) / g.ts;
-  const double gg = 1.0 - pow(1.0 - pow(s, 1.0 / g.vm), g.vm);
-  return sqrt(s) * gg * gg;
-}
-__device__ __forceinline__ double vg_dkr(const NlDev& g, double psi) {
-  const double s = vg_theta(g, psi) / g.ts;
-  const double ds = vg_dtheta(g, psi) / g.ts;
-  const double w = 1.0 - pow(s, 1.0 / g.vm);
-  const double gg = 1.0 - pow(w, g.vm);
-  const double dg = w > 0.0 ? pow(w, g.vm - 1.0) * pow(s, 1.0 / g.vm - 1.0) : 0.0;
-  return (0.5 / sqrt(s) * gg * gg + sqrt(s) * 2.0 * gg * dg) * ds;
-}
-
-// theta(psi) and kr(psi) together: one saturation evaluation serves both (same operations as
-// vg_theta and vg_kr, so the same values)
-__device__ __forceinline__ void vg_theta_kr(const NlDev& g, double psi, double& theta, double& kr) {
-  theta = vg_theta(g, psi);
-  const double s = theta / g.ts;
-  const double gg = 1.0 - pow(1.0 - pow(s, 1.0 / g.vm), g.vm);
-  kr = sqrt(s) * gg * gg;
+  double t;
+  const double se = vg_se_t(g, a, t);
+  v.theta = g.tr + (g.ts - g.tr) * se;
+  const double s = v.theta / g.ts;
+  const bool two = g.vn == 2.0;
+  const double s1m = two ? s * s : exp(log(s) / g.vm);  // s^(1/m)
+  const double w = 1.0 - s1m;
+  const double wm = w > 0.0 ? (two ? sqrt(w) : exp(g.vm * log(w))) : 0.0;  // w^m
+  const double gg = 1.0 - wm, rs = sqrt(s);
+  v.kr = rs * gg * gg;
+  v.dtheta = 0.0;
+  v.dkr = 0.0;
+  if (DERIV) {
+    const double an1 = two ? a : (a > 0.0 ? t / a : 0.0);  // a^(n-1)
+    v.dtheta = (g.ts - g.tr) * g.alpha * g.vm * g.vn * an1 * se / (1.0 + t);
+    const double ds = v.dtheta / g.ts;
+    const double dg = w > 0.0 ? (wm / w) * (s1m / s) : 0.0;
+    v.dkr = (0.5 / rs * gg * gg + rs * 2.0 * gg * dg) * ds;
+  }
+  return v;
 }
 
+__device__ __forceinline__ double vg_theta(const NlDev& g, double psi) {
+  if (!(psi < 0.0)) return g.ts;
+  double t;
+  return g.tr + (g.ts - g.tr) * vg_se_t(g, -g.alpha * psi, t);
+}
+__device__ __forceinline__ double vg_kr(const NlDev& g, double psi) { return vg_eval<false>(g, psi).kr; }
 __device__ __forceinline__ double mass_at(const NlDev& g, double u) { return g.kind == 1 ? vg_theta(g, u) : u; }
 
 __device__ __forceinline__ double harm(double a, double b) { return a + b > 0.0 ? 2.0 * a * b / (a + b) : 0.0; }
 
-// Richards f(psi)_r for the column of u with stride ld
-__device__ double ri_f_at(const NlDev& g, const double* u, int ld, int64_t r) {
+// The six face neighbours of cell r: their rows (the cell itself for a face on the border or beyond
+// the grid's dimension) and whether the face is interior.
+struct Faces {
   int i[3];
-  coords(g, r, i);
+  int64_t q[6];
+  bool in[6];
+};
+
+__device__ __forceinline__ Faces faces_of(const NlDev& g, int64_t r) {
+  Faces F;
+  coords(g, r, F.i);
+  int64_t st = 1;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    F.in[2 * d] = d < g.dim && F.i[d] > 0;
+    F.in[2 * d + 1] = d < g.dim && F.i[d] < g.n[d] - 1;
+    F.q[2 * d] = F.in[2 * d] ? r - st : r;
+    F.q[2 * d + 1] = F.in[2 * d + 1] ? r + st : r;
+    st *= g.n[d];
+  }
+  return F;
+}
+
+// Richards f(psi)_r for the column of u with stride ld, kr of cell q from kr_at(q). Every neighbour
+// value is loaded before any is used (border faces load the cell itself and add nothing), so the
+// loads of one cell are in flight together; faces are summed in axis order, low side first.
+// The transmissibility harm(Ks_P, Ks_Q) / h_d^2 of every face of cell r (the low face along d is the
+// high face of the neighbour below), and Ks_r.
+__device__ __forceinline__ double face_t(const NlDev& g, int64_t r, const Faces& F, double (&T)[6]) {
+  const double2 a = *reinterpret_cast<const double2*>(g.tf + 4 * r);
+  const double2 b = *reinterpret_cast<const double2*>(g.tf + 4 * r + 2);
+  T[1] = a.x;
+  T[3] = a.y;
+  T[5] = b.x;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) T[2 * d] = g.tf[4 * F.q[2 * d] + d];
+  return b.y;
+}
+
+template <class KrAt>
+__device__ __forceinline__ double ri_flux(const NlDev& g, const double* u, int ld, int64_t r, KrAt kr_at) {
+  const Faces F = faces_of(g, r);
+  const double up = u[r * ld], krp = kr_at(r);
+  double uq[6], kq[6], T[6];
+#pragma unroll
+  for (int e = 0; e < 6; ++e) {
+    uq[e] = u[F.q[e] * ld];
+    kq[e] = kr_at(F.q[e]);
+  }
+  const double ksp = face_t(g, r, F, T);
   const int zd = g.dim - 1;
-  const double up = u[r * ld], krp = vg_kr(g, up), ksp = g.ks[r];
-  const double zp = (i[zd] + 0.5) * g.hz, Hp = up + zp;
+  const double zp = (F.i[zd] + 0.5) * g.hz, Hp = up + zp;
   double f = 0.0;
-  for (int d = 0; d < g.dim; ++d) {
-    const int64_t st = stride_of(g, d);
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+#pragma unroll
     for (int side = 0; side < 2; ++side) {
-      const bool interior = side == 0 ? i[d] > 0 : i[d] < g.n[d] - 1;
-      if (interior) {
-        const int64_t q = side == 0 ? r - st : r + st;
-        const double uq = u[q * ld];
-        const double Hq = uq + (d == zd ? zp + (side == 0 ? -g.hz : g.hz) : zp);
-        f += harm(ksp, g.ks[q]) * g.w[d] * 0.5 * (krp + vg_kr(g, uq)) * (Hp - Hq);
+      const int e = 2 * d + side;
+      if (F.in[e]) {
+        const double Hq = uq[e] + (d == zd ? zp + (side == 0 ? -g.hz : g.hz) : zp);
+        f += T[e] * 0.5 * (krp + kq[e]) * (Hp - Hq);
       } else if (d == zd && side == 1 && g.top_dirichlet) {
         f += 2.0 * ksp * 0.5 * (krp + g.top_kr) * (Hp - (g.top_g + 1.0)) * g.w[d];
       } else if (d == zd && side == 0 && g.bottom_drain) {
@@ -109,31 +172,27 @@ __device__ double ri_f_at(const NlDev& g, const double* u, int ld, int64_t r) {
   return f;
 }
 
-// Richards f(psi)_r as ri_f_at, with kr read from kr[q * ldk] (evaluated once per cell beforehand)
-// instead of evaluated at the cell and at each neighbour.
-__device__ double ri_f_cached(const NlDev& g, const double* u, int ld, const double* kr, int ldk, int64_t r) {
-  int i[3];
-  coords(g, r, i);
-  const int zd = g.dim - 1;
-  const double up = u[r * ld], krp = kr[r * ldk], ksp = g.ks[r];
-  const double zp = (i[zd] + 0.5) * g.hz, Hp = up + zp;
-  double f = 0.0;
-  int64_t st = 1;
-  for (int d = 0; d < g.dim; ++d) {
+// Diffusion-reaction f(u)_r for the column of u with stride ld, loads first as in ri_flux.
+__device__ __forceinline__ double dr_flux(const NlDev& g, const double* u, int ld, int64_t r) {
+  const Faces F = faces_of(g, r);
+  const double up = u[r * ld];
+  double uq[6];
+#pragma unroll
+  for (int e = 0; e < 6; ++e) uq[e] = u[F.q[e] * ld];
+  const double Dp = poly(g.dc, up);
+  double f = -poly(g.rc, up);
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+#pragma unroll
     for (int side = 0; side < 2; ++side) {
-      const bool interior = side == 0 ? i[d] > 0 : i[d] < g.n[d] - 1;
-      if (interior) {
-        const int64_t q = side == 0 ? r - st : r + st;
-        const double uq = u[q * ld];
-        const double Hq = uq + (d == zd ? zp + (side == 0 ? -g.hz : g.hz) : zp);
-        f += harm(ksp, g.ks[q]) * g.w[d] * 0.5 * (krp + kr[q * ldk]) * (Hp - Hq);
-      } else if (d == zd && side == 1 && g.top_dirichlet) {
-        f += 2.0 * ksp * 0.5 * (krp + g.top_kr) * (Hp - (g.top_g + 1.0)) * g.w[d];
-      } else if (d == zd && side == 0 && g.bottom_drain) {
-        f += ksp * krp / g.hz;
+      const int e = 2 * d + side;
+      if (F.in[e]) {
+        f += 0.5 * (Dp + poly(g.dc, uq[e])) * (up - uq[e]) * g.w[d];
+      } else if (d < g.dim && g.bc_type[e] == BKTS_BC_DIRICHLET) {
+        const double gv = g.bc_val[e];
+        f += 0.5 * (Dp + poly(g.dc, gv)) * (up - gv) * 2.0 * g.w[d];
       }
     }
-    st *= g.n[d];
   }
   return f;
 }
@@ -144,34 +203,26 @@ __global__ void ri_cache_kernel(NlDev g, int64_t N, int k, const double* Y, int 
   if (i >= N * k) return;
   const int64_t r = i / k;
   const int c = (int)(i - r * k);
-  double th, kr;
-  vg_theta_kr(g, Y[r * ldy + c], th, kr);
-  TH[i] = th;
-  KR[i] = kr;
+  const VgVals v = vg_eval<false>(g, Y[r * ldy + c]);
+  TH[i] = v.theta;
+  KR[i] = v.kr;
+}
+
+// Per cell r: harm(Ks_r, Ks_q) / h_d^2 for the next cell q along x, y, z (0 where there is none), Ks_r.
+__global__ void ri_faces_kernel(NlDev g, int64_t N, const double* ks, double* tf) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= N) return;
+  const Faces F = faces_of(g, r);
+  const double kp = ks[r];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) tf[4 * r + d] = F.in[2 * d + 1] ? harm(kp, ks[F.q[2 * d + 1]]) * g.w[d] : 0.0;
+  tf[4 * r + 3] = kp;
 }
 
 // f(u)_r for the column of u with stride ld (u[q * ld])
 __device__ double f_at(const NlDev& g, const double* u, int ld, int64_t r) {
-  if (g.kind == 1) return ri_f_at(g, u, ld, r);
-  int i[3];
-  coords(g, r, i);
-  const double up = u[r * ld];
-  const double Dp = poly(g.dc, up);
-  double f = -poly(g.rc, up);
-  for (int d = 0; d < g.dim; ++d) {
-    const int64_t st = stride_of(g, d);
-    for (int side = 0; side < 2; ++side) {
-      const bool interior = side == 0 ? i[d] > 0 : i[d] < g.n[d] - 1;
-      if (interior) {
-        const double uq = u[(side == 0 ? r - st : r + st) * ld];
-        f += 0.5 * (Dp + poly(g.dc, uq)) * (up - uq) * g.w[d];
-      } else if (g.bc_type[2 * d + side] == BKTS_BC_DIRICHLET) {
-        const double gv = g.bc_val[2 * d + side];
-        f += 0.5 * (Dp + poly(g.dc, gv)) * (up - gv) * 2.0 * g.w[d];
-      }
-    }
-  }
-  return f;
+  if (g.kind == 1) return ri_flux(g, u, ld, r, [&](int64_t q) { return vg_kr(g, u[q * ld]); });
+  return dr_flux(g, u, ld, r);
 }
 
 __global__ void nl_eval_kernel(NlDev g, int64_t N, int k, const double* Y, int ldy, double* F, int ldf) {
@@ -190,30 +241,33 @@ __global__ void nl_mass_kernel(NlDev g, int64_t N, int k, const double* Y, int l
   M[r * ldm + c] = mass_at(g, Y[r * ldy + c]);
 }
 
-// Row r of the Richards Jacobian alpha m'(u) + beta Df(u) (m' = theta' or lin_L).
-__device__ void ri_jac_row(const NlDev& g, const double* u, int ldu, int64_t r, double alpha, double beta,
-                           double& diag, double (&off)[6], bool (&has)[6]) {
-  int i[3];
-  coords(g, r, i);
+// Row r of the Richards Jacobian alpha m'(u) + beta Df(u) (m' = theta' or lin_L): the diagonal and
+// the off-diagonal entry of every face (interior faces only carry one).
+__device__ __forceinline__ void ri_jac_row(const NlDev& g, const double* u, int ldu, int64_t r, const Faces& F,
+                                           double alpha, double beta, double& diag, double (&off)[6]) {
+  const double up = u[r * ldu];
+  double uq[6], T[6];
+#pragma unroll
+  for (int e = 0; e < 6; ++e) uq[e] = u[F.q[e] * ldu];
+  const double ksp = face_t(g, r, F, T);
+  const VgVals vp = vg_eval<true>(g, up);
+  const double krp = vp.kr, dkrp = vp.dkr;
   const int zd = g.dim - 1;
-  const double up = u[r * ldu], krp = vg_kr(g, up), dkrp = vg_dkr(g, up), ksp = g.ks[r];
-  const double zp = (i[zd] + 0.5) * g.hz, Hp = up + zp;
+  const double zp = (F.i[zd] + 0.5) * g.hz, Hp = up + zp;
   double dd = 0.0;
-  for (int f = 0; f < 6; ++f) has[f] = false;
-  for (int d = 0; d < g.dim; ++d) {
-    const int64_t st = stride_of(g, d);
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+#pragma unroll
     for (int side = 0; side < 2; ++side) {
-      const int f = 2 * d + side;
-      const bool interior = side == 0 ? i[d] > 0 : i[d] < g.n[d] - 1;
-      if (interior) {
-        const int64_t q = side == 0 ? r - st : r + st;
-        const double uq = u[q * ldu];
-        const double Hq = uq + (d == zd ? zp + (side == 0 ? -g.hz : g.hz) : zp);
-        const double wk = harm(ksp, g.ks[q]) * g.w[d];
-        const double m = 0.5 * (krp + vg_kr(g, uq)), dH = Hp - Hq;
+      const int e = 2 * d + side;
+      off[e] = 0.0;
+      if (F.in[e]) {
+        const VgVals vq = vg_eval<true>(g, uq[e]);
+        const double Hq = uq[e] + (d == zd ? zp + (side == 0 ? -g.hz : g.hz) : zp);
+        const double wk = T[e];
+        const double m = 0.5 * (krp + vq.kr), dH = Hp - Hq;
         dd += wk * (m + 0.5 * dkrp * dH);
-        off[f] = beta * wk * (-m + 0.5 * vg_dkr(g, uq) * dH);
-        has[f] = true;
+        off[e] = beta * wk * (-m + 0.5 * vq.dkr * dH);
       } else if (d == zd && side == 1 && g.top_dirichlet) {
         dd += 2.0 * ksp * (0.5 * (krp + g.top_kr) + 0.5 * dkrp * (Hp - (g.top_g + 1.0))) * g.w[d];
       } else if (d == zd && side == 0 && g.bottom_drain) {
@@ -221,8 +275,37 @@ __device__ void ri_jac_row(const NlDev& g, const double* u, int ldu, int64_t r, 
       }
     }
   }
-  const double mp = g.lin_L > 0.0 ? g.lin_L : vg_dtheta(g, up);
+  const double mp = g.lin_L > 0.0 ? g.lin_L : vp.dtheta;
   diag = alpha * mp + beta * dd;
+}
+
+// Row r of the diffusion-reaction Jacobian alpha I + beta Df(u).
+__device__ __forceinline__ void dr_jac_row(const NlDev& g, const double* u, int ldu, int64_t r, const Faces& F,
+                                           double alpha, double beta, double& diag, double (&off)[6]) {
+  const double up = u[r * ldu];
+  double uq[6];
+#pragma unroll
+  for (int e = 0; e < 6; ++e) uq[e] = u[F.q[e] * ldu];
+  const double Dp = poly(g.dc, up), dDp = dpoly(g.dc, up);
+  double dd = -dpoly(g.rc, up);
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+#pragma unroll
+    for (int side = 0; side < 2; ++side) {
+      const int e = 2 * d + side;
+      off[e] = 0.0;
+      if (F.in[e]) {
+        const double Dq = poly(g.dc, uq[e]), dDq = dpoly(g.dc, uq[e]);
+        const double Df = 0.5 * (Dp + Dq), diff = up - uq[e];
+        dd += (Df + 0.5 * dDp * diff) * g.w[d];
+        off[e] = beta * ((-Df + 0.5 * dDq * diff) * g.w[d]);
+      } else if (d < g.dim && g.bc_type[e] == BKTS_BC_DIRICHLET) {
+        const double gv = g.bc_val[e];
+        dd += (0.5 * (Dp + poly(g.dc, gv)) + 0.5 * dDp * (up - gv)) * 2.0 * g.w[d];
+      }
+    }
+  }
+  diag = alpha + beta * dd;
 }
 
 // Row r of J = alpha m'(u) + beta Df(u), written in the stencil's sorted column order
@@ -231,50 +314,18 @@ __global__ void nl_jac_kernel(NlDev g, int64_t N, const double* u, int ldu, doub
                               const int32_t* rowptr, double* val) {
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= N) return;
-  if (g.kind == 1) {
-    double diag, off[6];
-    bool has[6];
-    ri_jac_row(g, u, ldu, r, alpha, beta, diag, off, has);
-    int64_t p = rowptr[r];
-    for (int d = g.dim - 1; d >= 0; --d)
-      if (has[2 * d]) val[p++] = off[2 * d];
-    val[p++] = diag;
-    for (int d = 0; d < g.dim; ++d)
-      if (has[2 * d + 1]) val[p++] = off[2 * d + 1];
-    return;
-  }
-  int i[3];
-  coords(g, r, i);
-  const double up = u[r * ldu];
-  const double Dp = poly(g.dc, up), dDp = dpoly(g.dc, up);
-  double diag = -dpoly(g.rc, up);
-  double off[6];
-  bool has[6];
-  for (int f = 0; f < 6; ++f) has[f] = false;
-  for (int d = 0; d < g.dim; ++d) {
-    const int64_t st = stride_of(g, d);
-    for (int side = 0; side < 2; ++side) {
-      const int f = 2 * d + side;
-      const bool interior = side == 0 ? i[d] > 0 : i[d] < g.n[d] - 1;
-      if (interior) {
-        const double uq = u[(side == 0 ? r - st : r + st) * ldu];
-        const double Dq = poly(g.dc, uq), dDq = dpoly(g.dc, uq);
-        const double Df = 0.5 * (Dp + Dq), diff = up - uq;
-        diag += (Df + 0.5 * dDp * diff) * g.w[d];
-        off[f] = (-Df + 0.5 * dDq * diff) * g.w[d];
-        has[f] = true;
-      } else if (g.bc_type[f] == BKTS_BC_DIRICHLET) {
-        const double gv = g.bc_val[f];
-        diag += (0.5 * (Dp + poly(g.dc, gv)) + 0.5 * dDp * (up - gv)) * 2.0 * g.w[d];
-      }
-    }
-  }
+  const Faces F = faces_of(g, r);
+  double diag, off[6];
+  if (g.kind == 1)
+    ri_jac_row(g, u, ldu, r, F, alpha, beta, diag, off);
+  else
+    dr_jac_row(g, u, ldu, r, F, alpha, beta, diag, off);
   int64_t p = rowptr[r];
   for (int d = g.dim - 1; d >= 0; --d)
-    if (has[2 * d]) val[p++] = beta * off[2 * d];
-  val[p++] = alpha + beta * diag;
+    if (F.in[2 * d]) val[p++] = off[2 * d];
+  val[p++] = diag;
   for (int d = 0; d < g.dim; ++d)
-    if (has[2 * d + 1]) val[p++] = beta * off[2 * d + 1];
+    if (F.in[2 * d + 1]) val[p++] = off[2 * d + 1];
 }
 
 struct NlResArgs {
@@ -296,57 +347,70 @@ struct NlResArgs {
   const double* kr;
 };
 
+// Tiles of the window residual: 256 / KP rows, one per thread and column; m(Y) and F(Y) of the tile
+// staged in LDS for the right-multiplications by A1^T and A2^T, whose transposes sit in LDS too.
 template <int KP>
-constexpr int nlres_lds() {
-  return (2 * TileGeom<KP>::LDS_DOUBLES > 4 * KP) ? 2 * TileGeom<KP>::LDS_DOUBLES : 4 * KP;
-}
+struct NlResGeom {
+  static constexpr int RT = 256 / KP;
+  static constexpr int LDL = TileGeom<KP>::LDL;
+  static constexpr int TILE = 2 * RT * LDL;
+  static constexpr int LDS = TILE + 2 * KP * KP;
+};
 
-template <int KP>
+// KIND 0: diffusion-reaction (m = identity); KIND 1: Richards (theta and kr read from the cache).
+template <int KP, int KIND>
 __global__ __launch_bounds__(256) void nl_residual_kernel(NlResArgs a) {
-  using G = TileGeom<KP>;
-  __shared__ __align__(16) double lds[nlres_lds<KP>()];
-  double* Yl = lds;
-  double* Fl = lds + G::LDS_DOUBLES;
-  const int t = threadIdx.x, c = t % KP, r0 = t / KP;
+  using G = NlResGeom<KP>;
+  static_assert(G::TILE >= 4 * KP, "the block reduction reuses the tile");
+  __shared__ __align__(16) double lds[G::LDS];
+  double* Ml = lds;
+  double* Fl = lds + G::RT * G::LDL;
+  double* At1 = lds + G::TILE;  // At1[j * KP + c] = A1[c][j]
+  double* At2 = At1 + KP * KP;
+  const int t = threadIdx.x, c = t % KP, row = t / KP;
+  for (int e = t; e < KP * KP; e += 256) {
+    const int j = e / KP, cc = e % KP;
+    const bool in = cc < a.k && j < a.k;
+    At1[e] = in ? a.A1[cc * a.k + j] : 0.0;
+    At2[e] = in ? a.A2[cc * a.k + j] : 0.0;
+  }
   const int64_t slot = dev::xcd_slot(blockIdx.x, gridDim.x);
   const int64_t ntiles = (a.N + G::RT - 1) / G::RT;
   const bool cok = c < a.k;
-  double a1[KP], a2[KP];
-#pragma unroll
-  for (int j = 0; j < KP; ++j) {
-    a1[j] = (cok && j < a.k) ? a.A1[c * a.k + j] : 0.0;
-    a2[j] = (cok && j < a.k) ? a.A2[c * a.k + j] : 0.0;
-  }
+  const int cc = cok ? c : 0;  // padding columns read column 0 and discard it
   int b0j = -1;
   for (int j = 0; j < a.nb0; ++j)
     if (a.b0col[j] == c) b0j = j;
   double nacc[1] = {0.0};
   const int64_t tend = (slot + 1) * a.tps < ntiles ? (slot + 1) * a.tps : ntiles;
   for (int64_t tile = slot * a.tps; tile < tend; ++tile) {
-    const int64_t row0 = tile * G::RT;
-    for (int i = 0; i < G::RPT; ++i) {
-      const int row = r0 + i * G::RS;
-      const int64_t gr = row0 + row;
-      const bool ok = gr < a.N && cok;
-      if (a.kr) {
-        Yl[row * G::LDL + c] = ok ? a.th[gr * a.k + c] : 0.0;
-        Fl[row * G::LDL + c] = ok ? ri_f_cached(a.g, a.Y + c, a.ldy, a.kr + c, a.k, gr) : 0.0;
-      } else {
-        Yl[row * G::LDL + c] = ok ? mass_at(a.g, a.Y[gr * a.ldy + c]) : 0.0;
-        Fl[row * G::LDL + c] = ok ? f_at(a.g, a.Y + c, a.ldy, gr) : 0.0;
-      }
+    const int64_t gr = tile * G::RT + row;
+    const bool ok = gr < a.N && cok;
+    const int64_t rr = gr < a.N ? gr : 0;  // rows past the end evaluate row 0 and discard it
+    double mv, fv;
+    if constexpr (KIND == 1) {
+      const double* kr = a.kr + cc;
+      mv = a.th[rr * a.k + cc];
+      fv = ri_flux(a.g, a.Y + cc, a.ldy, rr, [&](int64_t q) { return kr[q * a.k]; });
+    } else {
+      mv = a.Y[rr * a.ldy + cc];
+      fv = dr_flux(a.g, a.Y + cc, a.ldy, rr);
     }
+    Ml[row * G::LDL + c] = ok ? mv : 0.0;
+    Fl[row * G::LDL + c] = ok ? fv : 0.0;
     __syncthreads();
-#pragma unroll
-    for (int i = 0; i < G::RPT; ++i) {
-      const int row = r0 + i * G::RS;
-      const int64_t gr = row0 + row;
-      if (gr < a.N && cok) {
-        double r = dev::lds_row_dot<KP>(Yl, row, a1) + dev::lds_row_dot<KP>(Fl, row, a2);
-        if (b0j >= 0) r -= a.B0[gr * a.ldb0 + b0j];
-        a.R[gr * a.ldr + c] = r;
-        nacc[0] = fma(r, r, nacc[0]);
-      }
+    if (ok) {
+      const double* pm = Ml + row * G::LDL;
+      const double* pf = Fl + row * G::LDL;
+      double s1 = 0.0, s2 = 0.0;
+#pragma unroll 4
+      for (int j = 0; j < KP; ++j) s1 = fma(pm[j], At1[j * KP + c], s1);
+#pragma unroll 4
+      for (int j = 0; j < KP; ++j) s2 = fma(pf[j], At2[j * KP + c], s2);
+      double r = s1 + s2;
+      if (b0j >= 0) r -= a.B0[gr * a.ldb0 + b0j];
+      a.R[gr * a.ldr + c] = r;
+      nacc[0] = fma(r, r, nacc[0]);
     }
     __syncthreads();
   }
@@ -355,15 +419,18 @@ __global__ __launch_bounds__(256) void nl_residual_kernel(NlResArgs a) {
 
 template <int KP>
 void launch_nlres(bkts_ctx ctx, NlResArgs a, double* nrm) {
-  using G = TileGeom<KP>;
+  using G = NlResGeom<KP>;
   const int64_t ntiles = (a.N + G::RT - 1) / G::RT;
-  const int64_t cap = 2 * (int64_t)ctx->num_cu;
+  const int64_t cap = 8 * (int64_t)ctx->num_cu;  // latency-bound gathers: many workgroups in flight
   int64_t ns = ntiles < cap ? ntiles : cap;
   if (ns < 1) ns = 1;
   a.tps = (ntiles + ns - 1) / ns;
   a.partials = ctx->ws.get<double>("nlres_partials", (size_t)KP * ns);
   ProfScope prof(ctx, BKTS_K_RESIDUAL, 16.0 * a.N * a.k + 8.0 * a.N * a.nb0);
-  launch(ctx, (nl_residual_kernel<KP>), dim3(ns), dim3(256), 0, a);
+  if (a.g.kind == 1)
+    launch(ctx, (nl_residual_kernel<KP, 1>), dim3(ns), dim3(256), 0, a);
+  else
+    launch(ctx, (nl_residual_kernel<KP, 0>), dim3(ns), dim3(256), 0, a);
   BKTS_HIP(hipGetLastError());
   prof.end();
   finalize_partials(ctx, a.partials, (int)ns, a.k, nrm);
@@ -467,8 +534,12 @@ bkts_nlop richards_create(bkts_ctx ctx, const bkts_grid* grid, const double* ks,
     g.lin_L = p->lin_L;
     nl->ks.alloc(sizeof(double) * nl->N);
     BKTS_HIP(hipMemcpyAsync(nl->ks.p, ks, sizeof(double) * nl->N, hipMemcpyDeviceToDevice, ctx->stream));
-    ctx->sync();  // the caller may release ks on return
     g.ks = nl->ks.as<double>();
+    nl->tf.alloc(sizeof(double) * 4 * nl->N);
+    g.tf = nl->tf.as<double>();
+    launch(ctx, ri_faces_kernel, dim3((unsigned)((nl->N + 255) / 256)), dim3(256), 0, g, nl->N, g.ks, nl->tf.as<double>());
+    BKTS_HIP(hipGetLastError());
+    ctx->sync();  // the caller may release ks on return, and other streams may use the operator
     bkts_fv_coeffs lc{};
     lc.kappa_const = 1.0;
     for (int f = 0; f < 6; ++f) lc.bc_type[f] = BKTS_BC_NEUMANN;

@@ -15,6 +15,8 @@ from paper_2504_02117_amd import inputs
 pytestmark = pytest.mark.gpu
 
 VG = dict(theta_r=0.05, theta_s=0.4, alpha=2.0, n=2.0)
+# the library takes n = 2 (m = 1/2) through square roots and other n through logarithms and exponentials
+CLOSURES = {"n2": VG, "n1.6": dict(theta_r=0.02, theta_s=0.45, alpha=3.5, n=1.6)}
 
 
 def say(msg):
@@ -44,15 +46,15 @@ def ks_field(n, seed=5):
     return inputs.lognormal_field(n, 0.0, 1.5, corr, seed).ravel()
 
 
-def make(env, n, top=("dirichlet", 0.0), bottom="free_drainage", lin_L=0.0, seed=5):
+def make(env, n, top=("dirichlet", 0.0), bottom="free_drainage", lin_L=0.0, seed=5, vg=VG):
     torch, bkts, ctx = env
     ks = ks_field(n, seed)
     btop = bkts.BKTS_RI_DIRICHLET if top[0] == "dirichlet" else bkts.BKTS_RI_NO_FLOW
     bbot = bkts.BKTS_RI_FREE_DRAINAGE if bottom == "free_drainage" else bkts.BKTS_RI_NO_FLOW
-    nl = bkts.bkts_richards_create(ctx, n, dev(torch, ks), vg_n=VG["n"], alpha=VG["alpha"], theta_r=VG["theta_r"],
-                                   theta_s=VG["theta_s"], top=btop, top_value=top[1] if len(top) > 1 else 0.0,
+    nl = bkts.bkts_richards_create(ctx, n, dev(torch, ks), vg_n=vg["n"], alpha=vg["alpha"], theta_r=vg["theta_r"],
+                                   theta_s=vg["theta_s"], top=btop, top_value=top[1] if len(top) > 1 else 0.0,
                                    bottom=bbot, lin_L=lin_L)
-    ref = ri.Richards(n, ks, ri.VanGenuchten(**VG), top=top, bottom=bottom)
+    ref = ri.Richards(n, ks, ri.VanGenuchten(**vg), top=top, bottom=bottom)
     return nl, ref
 
 
@@ -76,12 +78,14 @@ def _psi(ref, k, seed):
     return np.column_stack(cols)
 
 
+@pytest.mark.parametrize("closure", sorted(CLOSURES))
 @pytest.mark.parametrize("ci", range(len(CASES)))
-def test_mass_and_flux_match_oracle(env, ci):
+def test_mass_and_flux_match_oracle(env, ci, closure):
     torch, bkts, ctx = env
     c = CASES[ci]
-    say(f"richards mass/flux {c}")
-    nl, ref = make(env, c["n"], c.get("top", ("dirichlet", 0.0)), c.get("bottom", "free_drainage"))
+    say(f"richards mass/flux {c} {closure}")
+    nl, ref = make(env, c["n"], c.get("top", ("dirichlet", 0.0)), c.get("bottom", "free_drainage"),
+                   vg=CLOSURES[closure])
     try:
         k = 5
         Y = _psi(ref, k, 31)
@@ -108,13 +112,15 @@ def test_mass_and_flux_match_oracle(env, ci):
         bkts.bkts_nlop_destroy(nl)
 
 
+@pytest.mark.parametrize("closure", sorted(CLOSURES))
 @pytest.mark.parametrize("ci", range(len(CASES)))
 @pytest.mark.parametrize("lin_L", [0.0, 0.045])
-def test_jacobian_matches_oracle(env, ci, lin_L):
+def test_jacobian_matches_oracle(env, ci, lin_L, closure):
     torch, bkts, ctx = env
     c = CASES[ci]
-    say(f"richards jacobian {c} L={lin_L}")
-    nl, ref = make(env, c["n"], c.get("top", ("dirichlet", 0.0)), c.get("bottom", "free_drainage"), lin_L=lin_L)
+    say(f"richards jacobian {c} L={lin_L} {closure}")
+    nl, ref = make(env, c["n"], c.get("top", ("dirichlet", 0.0)), c.get("bottom", "free_drainage"), lin_L=lin_L,
+                   vg=CLOSURES[closure])
     try:
         u = _psi(ref, 1, 3)[:, 0]
         N = u.shape[0]
@@ -131,13 +137,15 @@ def test_jacobian_matches_oracle(env, ci, lin_L):
         bkts.bkts_nlop_destroy(nl)
 
 
-@pytest.mark.parametrize("k", [1, 4, 16])
-def test_window_residual_matches_oracle(env, k):
+@pytest.mark.parametrize("closure", sorted(CLOSURES))
+@pytest.mark.parametrize("k", [1, 4, 5, 16, 32])
+def test_window_residual_matches_oracle(env, k, closure):
+    """Ragged tiles (5670 rows) and padded column groups (k = 5)."""
     torch, bkts, ctx = env
     n = (21, 18, 15)
     tau = 2e-3
-    say(f"richards residual k={k}")
-    nl, ref = make(env, n)
+    say(f"richards residual k={k} {closure}")
+    nl, ref = make(env, n, vg=CLOSURES[closure])
     tc = bkts.bkts_tc_create(ctx, bkts.BKTS_IE, k, tau)
     try:
         A, _, c = otc.tableau("ie")
@@ -163,6 +171,7 @@ def test_window_residual_matches_oracle(env, k):
     (4, 2, 1, 0.0),    # BiCGStab
     (8, 1, 0, 0.0),    # FP64 inner
     (4, 1, 1, 0.3),    # L-scheme linearisation (L above the Lipschitz constant of theta): same fixed point
+    (4, 2, 1, "n1.6"),  # the closure evaluated through logarithms and exponentials
 ])
 def test_stepper_matches_sequential_implicit_euler(env, k, krylov, precision, lin_L):
     """Infiltration into a column at hydrostatic rest (psi0 = -z) through a Dirichlet top at
@@ -171,7 +180,10 @@ def test_stepper_matches_sequential_implicit_euler(env, k, krylov, precision, li
     n = (10, 9, 14)
     steps, tau = 8, 1e-3
     say(f"richards stepper k={k} krylov={krylov} precision={precision} L={lin_L}")
-    nl, ref = make(env, n, lin_L=lin_L)
+    vg = VG
+    if isinstance(lin_L, str):
+        vg, lin_L = CLOSURES[lin_L], 0.0
+    nl, ref = make(env, n, lin_L=lin_L, vg=vg)
     tc = bkts.bkts_tc_create(ctx, bkts.BKTS_IE, k, tau)
     st = None
     try:
