@@ -226,13 +226,16 @@ bkts_status bkts_stepper_s::advance(int n_steps, const bkts_solve_opts& inner, d
         solve(ctx, *nl->jac, 0.0, 1.0, k, Rp, Vp, true, inner, true, ks);
         for (int j = 0; j < k; ++j)
           if (!active[j]) lincomb(ctx, N, LinComb{}, Vp + j, k);  // frozen slots take no update
+      } else if (inner.precision == BKTS_PRECISION_F32_REFINE) {
+        // Y <- Y - J^-1 R in one FP32 pass, scaled by the residual kernel's column norms
+        correct_f32(ctx, *op, 1.0 / tau, beta, k, Rp, nrmp, hn.data(), -1.0, Yp, inner, ks, col_ops ? &cop : nullptr);
       } else {
         solve(ctx, *op, 1.0 / tau, beta, k, Rp, Vp, true, inner, true, ks, col_ops ? &cop : nullptr);
       }
       ri.krylov_iterations += ks.iterations;
       ri.refinements += ks.refinements;
       ++ri.outer_iterations;
-      axpby(ctx, N * k, -1.0, Vp, 1.0, Yp);  // Y <- Y - V
+      if (nl || inner.precision != BKTS_PRECISION_F32_REFINE) axpby(ctx, N * k, -1.0, Vp, 1.0, Yp);  // Y <- Y - V
     }
     if (!front_ok) {
       status = BKTS_ENOCONV;

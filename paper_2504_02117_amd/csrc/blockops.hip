@@ -385,15 +385,21 @@ __global__ __launch_bounds__(256) void rmul_kernel(int64_t N, int k, const T* __
 
 // ---------------------------------------------------------------- casts / elementwise
 
+// dst = coef * src * diag(s) (+ dst with accumulate), s inverted on request; with norm2 the scale of
+// column c is sqrt(s[c]) (1 where s[c] is 0), so squared column norms scale without a host round trip.
 template <typename S, typename D>
 __global__ void cast_scale_kernel(int64_t N, int k, const S* src, int lds_, D* dst, int ldd, const double* s,
-                                  int invert, int accumulate) {
+                                  int invert, int accumulate, int norm2, double coef) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= N * k) return;
   const int64_t r = i / k;
   const int c = (int)(i % k);
   double v = (double)src[r * lds_ + c];
-  if (s) v = invert ? v / s[c] : v * s[c];
+  if (s) {
+    const double sc = norm2 ? (s[c] > 0.0 ? sqrt(s[c]) : 1.0) : s[c];
+    v = invert ? v / sc : v * sc;
+  }
+  if (coef != 1.0) v = coef * v;
   if (accumulate) v += (double)dst[r * ldd + c];
   dst[r * ldd + c] = (D)v;
 }
@@ -689,23 +695,24 @@ void block_rmul(bkts_ctx ctx, int dtype, int64_t N, int k, const void* X, int ld
 }
 
 void block_cast_scale(bkts_ctx ctx, int64_t N, int k, int src_t, const void* src, int lds_, int dst_t, void* dst,
-                      int ldd, const double* s, bool invert_s, bool accumulate) {
+                      int ldd, const double* s, bool invert_s, bool accumulate, bool norm2, double coef) {
   const int64_t n = N * k;
   if (n == 0) return;
   dim3 g((n + 255) / 256), b(256);
   ProfScope prof(ctx, BKTS_K_CAST, (double)n * (esize(src_t) + esize(dst_t) * (accumulate ? 2 : 1)));
+  const int iv = invert_s, ac = accumulate, n2 = norm2;
   if (src_t == BKTS_F64 && dst_t == BKTS_F32)
-    launch(ctx, (cast_scale_kernel<double, float>), g, b, 0, N, k, static_cast<const double*>(src),
-                       lds_, static_cast<float*>(dst), ldd, s, (int)invert_s, (int)accumulate);
+    launch(ctx, (cast_scale_kernel<double, float>), g, b, 0, N, k, static_cast<const double*>(src), lds_,
+           static_cast<float*>(dst), ldd, s, iv, ac, n2, coef);
   else if (src_t == BKTS_F32 && dst_t == BKTS_F64)
-    launch(ctx, (cast_scale_kernel<float, double>), g, b, 0, N, k, static_cast<const float*>(src),
-                       lds_, static_cast<double*>(dst), ldd, s, (int)invert_s, (int)accumulate);
+    launch(ctx, (cast_scale_kernel<float, double>), g, b, 0, N, k, static_cast<const float*>(src), lds_,
+           static_cast<double*>(dst), ldd, s, iv, ac, n2, coef);
   else if (src_t == BKTS_F64 && dst_t == BKTS_F64)
-    launch(ctx, (cast_scale_kernel<double, double>), g, b, 0, N, k, static_cast<const double*>(src),
-                       lds_, static_cast<double*>(dst), ldd, s, (int)invert_s, (int)accumulate);
+    launch(ctx, (cast_scale_kernel<double, double>), g, b, 0, N, k, static_cast<const double*>(src), lds_,
+           static_cast<double*>(dst), ldd, s, iv, ac, n2, coef);
   else
-    launch(ctx, (cast_scale_kernel<float, float>), g, b, 0, N, k, static_cast<const float*>(src),
-                       lds_, static_cast<float*>(dst), ldd, s, (int)invert_s, (int)accumulate);
+    launch(ctx, (cast_scale_kernel<float, float>), g, b, 0, N, k, static_cast<const float*>(src), lds_,
+           static_cast<float*>(dst), ldd, s, iv, ac, n2, coef);
   BKTS_HIP(hipGetLastError());
 }
 

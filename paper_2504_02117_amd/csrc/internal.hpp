@@ -417,9 +417,12 @@ void cg_pupdate(bkts_ctx ctx, int dtype, int64_t N, int k, void* P, const void* 
 void block_rmul(bkts_ctx ctx, int dtype, int64_t N, int k, const void* X, int ldx, const double* C,
                 double c0, double c1, void* Y, int ldy);
 
-// Scaled casts: dst = src * diag(s) (s device, k; null = ones), between F64 and F32 blocks.
+// Scaled casts: dst = coef * src * diag(s) (s device, k; null = ones), between F64 and F32 blocks;
+// invert_s divides by s; norm2: s holds squared column norms and column c scales by sqrt(s[c]) (1
+// for a zero column); accumulate adds into dst.
 void block_cast_scale(bkts_ctx ctx, int64_t N, int k, int src_t, const void* src, int lds, int dst_t,
-                      void* dst, int ldd, const double* s, bool invert_s, bool accumulate);
+                      void* dst, int ldd, const double* s, bool invert_s, bool accumulate, bool norm2 = false,
+                      double coef = 1.0);
 
 // All-at-once residual (fused).  A1t, A2t: device k x k transposed window matrices (A^T, row-major).
 // b0cols: host list of (b0 column index -> R column index).

@@ -204,11 +204,13 @@ void block_cg(bkts_ctx ctx, const bkts_op_s& op, int dtype, int k, double a, dou
 // gamma = R^T Z and T = Q^T Z are separate Gram passes (the Jacobi form folds them into the update);
 // the deflating k x k solves and the restart on a collapsed search space are those of block_cg.
 void block_pcg_mg(bkts_ctx ctx, const bkts_op_s& op, int dtype, int k, double a, double b, const void* B, void* X,
-                  bool x0_zero, double rtol, int maxit, KrylovStats& st) {
+                  bool x0_zero, double rtol, int maxit, KrylovStats& st, const SolveHints* hints) {
   const int64_t N = op.N;
   const size_t es = esize(dtype);
   const std::string tag = dtype == BKTS_F64 ? "d" : "s";
-  void* R = ctx->ws.get("mgcg_R_" + tag, es * N * k);
+  // with a zero initial guess and a scratch right-hand side, B itself becomes the residual block
+  const bool take_b = x0_zero && hints && hints->b_scratch;
+  void* R = take_b ? const_cast<void*>(B) : ctx->ws.get("mgcg_R_" + tag, es * N * k);
   void* P = ctx->ws.get("mgcg_P_" + tag, es * N * k);
   void* Q = ctx->ws.get("mgcg_Q_" + tag, es * N * k);
   void* Z = ctx->ws.get("mgcg_Z_" + tag, es * N * k);
@@ -216,21 +218,24 @@ void block_pcg_mg(bkts_ctx ctx, const bkts_op_s& op, int dtype, int k, double a,
   const double eps = cg_pivot_floor(dtype);
   if (x0_zero) {
     BKTS_HIP(hipMemsetAsync(X, 0, es * N * k, ctx->stream));
-    BKTS_HIP(hipMemcpyAsync(R, B, es * N * k, hipMemcpyDeviceToDevice, ctx->stream));
+    if (!take_b) BKTS_HIP(hipMemcpyAsync(R, B, es * N * k, hipMemcpyDeviceToDevice, ctx->stream));
   } else {
     spmm(ctx, op, dtype, k, 1.0, B, k, -a, X, k, -b, R, k);
   }
-  colnorms2(ctx, dtype, N, k, R, k, s.nrm0);
   std::vector<double> nrm0, nrm;
-  read_norms(ctx, s.nrm0, k, nrm0);
+  if (x0_zero && hints && hints->nrm0) {  // the caller knows the squared column norms of B
+    nrm0.assign(hints->nrm0, hints->nrm0 + k);
+  } else {
+    colnorms2(ctx, dtype, N, k, R, k, s.nrm0);
+    read_norms(ctx, s.nrm0, k, nrm0);
+  }
   st.iterations = 0;
   st.deflations = 0;
   st.converged = all_converged(nrm0, nrm0, rtol, &st.max_rel) ? 1 : 0;
   if (st.converged) return;
-  auto precondition = [&]() {  // Z = M^-1 R, P = Z, gamma = R^T Z
-    mg_vcycle(ctx, op, dtype, k, a, b, R, Z);
-    cg_pupdate(ctx, dtype, N, k, P, Z, nullptr, nullptr);
-    inner_gram(ctx, dtype, N, k, R, Z, s.gamma);
+  auto precondition = [&]() {  // P = Z = M^-1 R (the cycle writes the first direction directly), gamma = R^T P
+    mg_vcycle(ctx, op, dtype, k, a, b, R, P);
+    inner_gram(ctx, dtype, N, k, R, P, s.gamma);
   };
   precondition();
   // Convergence is read one iteration late, as in block_cg: the norms of iteration it are copied to
@@ -366,7 +371,7 @@ void block_pcg_mg(bkts_ctx ctx, const bkts_op_s& op, int dtype, int k, double a,
 // Dispatch on the Krylov method of the options.
 static void krylov_run(bkts_ctx ctx, const bkts_op_s& op, const bkts_solve_opts& o, int dtype, int k, double a,
                        double b, const void* B, void* X, bool x0_zero, double rtol, int maxit, KrylovStats& st,
-                       const ColOp* cop = nullptr) {
+                       const ColOp* cop = nullptr, const SolveHints* hints = nullptr) {
   const bool jacobi = o.precond == BKTS_PREC_JACOBI;
   BKTS_REQUIRE(!cop || o.krylov == BKTS_BICGSTAB, "per-column operators need the vectorized BiCGStab");
   BKTS_REQUIRE(o.precond >= BKTS_PREC_NONE && o.precond <= BKTS_PREC_MG, "unknown preconditioner %d", o.precond);
@@ -374,7 +379,7 @@ static void krylov_run(bkts_ctx ctx, const bkts_op_s& op, const bkts_solve_opts&
   switch (o.krylov) {
     case BKTS_CG:
       if (o.precond == BKTS_PREC_MG)
-        block_pcg_mg(ctx, op, dtype, k, a, b, B, X, x0_zero, rtol, maxit, st);
+        block_pcg_mg(ctx, op, dtype, k, a, b, B, X, x0_zero, rtol, maxit, st, hints);
       else
         block_cg(ctx, op, dtype, k, a, b, B, X, x0_zero, jacobi, rtol, maxit, st);
       break;
@@ -385,20 +390,31 @@ static void krylov_run(bkts_ctx ctx, const bkts_op_s& op, const bkts_solve_opts&
 }
 
 void f32_correction(bkts_ctx ctx, const bkts_op_s& op, const bkts_solve_opts& o, int k, double a, double b,
-                    const double* R64, const double* nrm2, double* V64, double rtol, int maxit, KrylovStats& st,
-                    const ColOp* cop = nullptr) {
+                    const double* R64, const double* n2_dev, const double* n2_host, double* V64, double coef,
+                    double rtol, int maxit, KrylovStats& st, const ColOp* cop = nullptr) {
   const int64_t N = op.N;
-  double* scale = ctx->ws.get<double>("f32_scale", k);
-  std::vector<double> hs(k);
-  for (int j = 0; j < k; ++j) hs[j] = nrm2[j] > 0.0 ? std::sqrt(nrm2[j]) : 1.0;
-  BKTS_HIP(hipMemcpyAsync(scale, hs.data(), sizeof(double) * k, hipMemcpyHostToDevice, ctx->stream));
   float* R32 = ctx->ws.get<float>("f32_R", (size_t)N * k);
   float* V32 = ctx->ws.get<float>("f32_V", (size_t)N * k);
-  block_cast_scale(ctx, N, k, BKTS_F64, R64, k, BKTS_F32, R32, k, scale, true, false);
-  BKTS_HIP(hipMemsetAsync(V32, 0, sizeof(float) * N * k, ctx->stream));
-  krylov_run(ctx, op, o, BKTS_F32, k, a, b, R32, V32, true, rtol, maxit, st, cop);
-  block_cast_scale(ctx, N, k, BKTS_F32, V32, k, BKTS_F64, V64, k, scale, false, true);
-  ctx->sync();  // hs must outlive the async upload
+  // column j scaled by 1 / ||R64_j|| (1 for a zero column), so the FP32 block has unit columns
+  block_cast_scale(ctx, N, k, BKTS_F64, R64, k, BKTS_F32, R32, k, n2_dev, true, false, true);
+  SolveHints h;
+  h.b_scratch = true;  // R32 is this pass's own: the solver may take it as its residual block
+  std::vector<double> n0(k);
+  for (int j = 0; j < k; ++j) n0[j] = n2_host[j] > 0.0 ? 1.0 : 0.0;
+  h.nrm0 = n0.data();
+  krylov_run(ctx, op, o, BKTS_F32, k, a, b, R32, V32, true, rtol, maxit, st, cop, &h);
+  block_cast_scale(ctx, N, k, BKTS_F32, V32, k, BKTS_F64, V64, k, n2_dev, false, true, true, coef);
+}
+
+void correct_f32(bkts_ctx ctx, const bkts_op_s& op, double a, double b, int k, const double* R, const double* rn2_dev,
+                 const double* rn2_host, double coef, double* Y, const bkts_solve_opts& o, KrylovStats& st,
+                 const ColOp* cop) {
+  BKTS_REQUIRE(o.precision == BKTS_PRECISION_F32_REFINE, "correct_f32 needs FP32 inner solves");
+  const int maxit = o.maxit > 0 ? o.maxit : 10000;
+  const double inner = o.inner_rtol > 0.0 ? o.inner_rtol : 1e-4;
+  st = KrylovStats{};
+  f32_correction(ctx, op, o, k, a, b, R, rn2_dev, rn2_host, Y, coef, std::max(o.rtol, inner), maxit, st, cop);
+  st.refinements = 1;
 }
 
 void solve(bkts_ctx ctx, const bkts_op_s& op, double a, double b, int k, const double* B, double* X, bool x0_zero,
@@ -422,7 +438,7 @@ void solve(bkts_ctx ctx, const bkts_op_s& op, double a, double b, int k, const d
     std::vector<double> nb;
     read_norms(ctx, n2, k, nb);
     st = KrylovStats{};
-    f32_correction(ctx, op, o, k, a, b, B, nb.data(), X, std::max(o.rtol, inner), maxit, st, cop);
+    f32_correction(ctx, op, o, k, a, b, B, n2, nb.data(), X, 1.0, std::max(o.rtol, inner), maxit, st, cop);
     st.refinements = 1;
     return;
   }
@@ -445,7 +461,7 @@ void solve(bkts_ctx ctx, const bkts_op_s& op, double a, double b, int k, const d
       return;
     }
     KrylovStats in;
-    f32_correction(ctx, op, o, k, a, b, R64, nrm.data(), X, inner, maxit - total, in);
+    f32_correction(ctx, op, o, k, a, b, R64, n2, nrm.data(), X, 1.0, inner, maxit - total, in);
     total += in.iterations;
     st.iterations = total;
     st.refinements = ref + 1;

@@ -52,6 +52,21 @@ void gmres_core(bkts_ctx ctx, int dtype, int64_t N, int k, const GmresOps& ops, 
 void block_bicgstab(bkts_ctx ctx, const bkts_op_s& op, int dtype, int k, double a, double b, const void* B, void* X,
                     bool x0_zero, bool jacobi, double rtol, int maxit, KrylovStats& st, const ColOp* cop = nullptr);
 
+// What a caller already knows about a solve's right-hand side: its squared column norms (host; only
+// with a zero initial guess), and that it is scratch the solver may overwrite.
+struct SolveHints {
+  const double* nrm0 = nullptr;
+  bool b_scratch = false;
+};
+
+// One FP32 correction inside a caller's FP64 outer loop: Y += coef * (a M + b K)^-1 R, where the
+// caller's residual kernel already produced R's squared column norms (on the device and the host).
+// R is scaled to unit columns in FP32, solved to the options' inner tolerance, and the correction is
+// scaled back and accumulated into Y in the same pass (no FP64 correction block).
+void correct_f32(bkts_ctx ctx, const bkts_op_s& op, double a, double b, int k, const double* R, const double* rn2_dev,
+                 const double* rn2_host, double coef, double* Y, const bkts_solve_opts& o, KrylovStats& st,
+                 const ColOp* cop = nullptr);
+
 // FP64 solve entry: F64 block CG, or FP32 block CG inside FP64 iterative refinement.  With
 // single_f32_pass the refinement loop makes one FP32 correction (the caller's own outer loop
 // computes FP64 residuals).
