@@ -254,21 +254,34 @@ __device__ __forceinline__ void smoothed_residual(const LvArgs<T>& L, const T* f
 
 // z = y + w D^-1 (f - A y) at fine cell r with y = w D^-1 f + P xc (coarse level c); also returns the
 // row's f values.
+// A cell's six neighbours lie in at most four aggregates: its own, and along each axis the one on
+// the side where the cell is the outer child. Those four coarse values are loaded once and each
+// neighbour takes its aggregate's.
 template <typename T, int CW>
 __device__ __forceinline__ void prolong_row(const LvArgs<T>& L, const Geo& c, const T* f, const T* xc, int64_t r,
                                             int ix, int iy, int iz, int c0, T (&zr)[CW], T (&fr)[CW]) {
+  const int pos[3] = {ix, iy, iz};
+  const int len[3] = {L.g.nx, L.g.ny, L.g.nz};
+  const int64_t cst[3] = {1, c.sy, c.sz};
+  const int64_t P0 = (ix >> 1) + c.sy * (iy >> 1) + c.sz * (iz >> 1);
+  T xv[CW], xo[3][CW];
+  ld_cw<T, CW>(xc + P0 * L.k + c0, xv);
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const bool odd = pos[d] & 1;
+    const int po = odd ? pos[d] + 1 : pos[d] - 1;  // the neighbour outside the own aggregate
+    const int64_t Po = (po >= 0 && po < len[d]) ? (odd ? P0 + cst[d] : P0 - cst[d]) : P0;
+    ld_cw<T, CW>(xc + Po * L.k + c0, xo[d]);
+  }
   auto ycell = [&](int64_t q, int qx, int qy, int qz, T(&y)[CW]) {
     pre_x<T, CW>(L, f, q, c0, y);
-    const int64_t P = (qx >> 1) + c.sy * (qy >> 1) + c.sz * (qz >> 1);
-    T xv[CW];
-    ld_cw<T, CW>(xc + P * L.k + c0, xv);
+    const bool ox = (qx >> 1) != (ix >> 1), oy = (qy >> 1) != (iy >> 1), oz = (qz >> 1) != (iz >> 1);
 #pragma unroll
-    for (int j = 0; j < CW; ++j) y[j] += xv[j];
+    for (int j = 0; j < CW; ++j) y[j] += ox ? xo[0][j] : (oy ? xo[1][j] : (oz ? xo[2][j] : xv[j]));
   };
-  T xv[CW], yr[CW], ay[CW];
+  T yr[CW], ay[CW];
   ld_cw<T, CW>(f + r * L.k + c0, fr);
   const T s = L.w * L.di[r];
-  ld_cw<T, CW>(xc + ((ix >> 1) + c.sy * (iy >> 1) + c.sz * (iz >> 1)) * L.k + c0, xv);
 #pragma unroll
   for (int j = 0; j < CW; ++j) yr[j] = s * fr[j] + xv[j];
   apply_row<T, CW>(L, r, ix, iy, iz, yr, ycell, ay);
