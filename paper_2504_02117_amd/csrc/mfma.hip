@@ -33,6 +33,13 @@ __device__ __forceinline__ d4 mfma(double a, double b, d4 c) {
 
 __device__ __forceinline__ d4 zero4() { return d4{0.0, 0.0, 0.0, 0.0}; }
 
+// FP32 matrix cores (v_mfma_f32_16x16x4f32): same A and B layouts as the FP64 instruction; its D
+// layout differs: lane l, register v holds D[4 (l / 16) + v][l % 16].
+typedef float f4m __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ f4m mfma32(float a, float b, f4m c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
 template <int NB>
 struct MGeom {
   static constexpr int KP = 16 * NB;
@@ -74,6 +81,27 @@ __device__ void fold_kxk(d4 (&acc)[NB][NB], double* red, double* partials) {
     for (int jb = 0; jb < NB; ++jb)
 #pragma unroll
       for (int v = 0; v < 4; ++v) red[w * KP * KP + (16 * ia + 4 * v + g) * KP + 16 * jb + c] = acc[ia][jb][v];
+  __syncthreads();
+  const int64_t slot = dev::xcd_slot(blockIdx.x, gridDim.x);
+  for (int e = threadIdx.x; e < KP * KP; e += dev::kThreads) {
+    const double s = ((red[e] + red[KP * KP + e]) + red[2 * KP * KP + e]) + red[3 * KP * KP + e];
+    partials[(int64_t)e * gridDim.x + slot] = s;
+  }
+  __syncthreads();
+}
+
+// fold_kxk for accumulators in the FP32 D layout (register v of lane l is row 4 (l / 16) + v).
+template <int NB>
+__device__ void fold_kxk32(d4 (&acc)[NB][NB], double* red, double* partials) {
+  constexpr int KP = 16 * NB;
+  const int l = threadIdx.x & 63, w = threadIdx.x >> 6, g = l >> 4, c = l & 15;
+  __syncthreads();
+#pragma unroll
+  for (int ia = 0; ia < NB; ++ia)
+#pragma unroll
+    for (int jb = 0; jb < NB; ++jb)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) red[w * KP * KP + (16 * ia + 4 * g + v) * KP + 16 * jb + c] = acc[ia][jb][v];
   __syncthreads();
   const int64_t slot = dev::xcd_slot(blockIdx.x, gridDim.x);
   for (int e = threadIdx.x; e < KP * KP; e += dev::kThreads) {
@@ -485,28 +513,84 @@ __global__ __launch_bounds__(256) void mf_mgram_kernel(int64_t N, int k, int nbl
 #pragma unroll
       for (int j = 0; j < NB; ++j) acc[b][i][j] = zero4();
   const WaveRange wr = wave_range((N + 3) / 4);
-  for (int64_t q = wr.begin; q < wr.end; ++q) {
-    const int64_t r = 4 * q + g;
-    double y[NB], x[MB][NB];
+  // Every load of a step precedes its first matrix-core instruction. Rows past N and columns past k
+  // are read at a valid element and multiplied by zero, so no load sits behind a branch.
+  if constexpr (sizeof(T) == 4) {
+    // FP32 blocks: FP32 matrix-core sums over one 16-row tile (4 quads), added in FP64 across tiles;
+    // the FP64 accumulators keep the FP32 D layout.
+    for (int64_t t = wr.begin; t < wr.end; t += 4) {
+      float y[4][NB], x[4][MB][NB];
 #pragma unroll
-    for (int cb = 0; cb < NB; ++cb) {
-      const int col = 16 * cb + c;
-      y[cb] = ldz(W + r * k + col, r < N && col < k);
+      for (int u = 0; u < 4; ++u) {
+        const int64_t r = 4 * (t + u) + g;
+        const bool rok = t + u < wr.end && r < N;
+        const int64_t rr = rok ? r : (4 * t + g < N ? 4 * t + g : N - 1);
 #pragma unroll
-      for (int b = 0; b < MB; ++b) x[b][cb] = (b < nblk) ? ldz(V0 + b * vstride + r * k + col, r < N && col < k) : 0.0;
-    }
+        for (int cb = 0; cb < NB; ++cb) {
+          const int col = 16 * cb + c;
+          const int cc = col < k ? col : k - 1;
+          const float m = (rok && col < k) ? 1.0f : 0.0f;
+          y[u][cb] = m * static_cast<float>(W[rr * k + cc]);
 #pragma unroll
-    for (int b = 0; b < MB; ++b)
-      if (b < nblk) {
-#pragma unroll
-        for (int ia = 0; ia < NB; ++ia)
-#pragma unroll
-          for (int jb = 0; jb < NB; ++jb) acc[b][ia][jb] = mfma(x[b][ia], y[jb], acc[b][ia][jb]);
+          for (int b = 0; b < MB; ++b)
+            x[u][b][cb] = (b < nblk) ? m * static_cast<float>(V0[b * vstride + rr * k + cc]) : 0.0f;
+        }
       }
+#pragma unroll
+      for (int b = 0; b < MB; ++b)
+        if (b < nblk) {
+#pragma unroll
+          for (int ia = 0; ia < NB; ++ia)
+#pragma unroll
+            for (int jb = 0; jb < NB; ++jb) {
+              f4m p = f4m{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+              for (int u = 0; u < 4; ++u) p = mfma32(x[u][b][ia], y[u][jb], p);
+#pragma unroll
+              for (int v = 0; v < 4; ++v) acc[b][ia][jb][v] += static_cast<double>(p[v]);
+            }
+        }
+    }
+  } else {
+    constexpr int U = 2;  // quads per step
+    for (int64_t q0 = wr.begin; q0 < wr.end; q0 += U) {
+      double y[U][NB], x[U][MB][NB];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int64_t r = 4 * (q0 + u) + g;
+        const bool rok = q0 + u < wr.end && r < N;
+        const int64_t rr = rok ? r : (4 * q0 + g < N ? 4 * q0 + g : N - 1);
+#pragma unroll
+        for (int cb = 0; cb < NB; ++cb) {
+          const int col = 16 * cb + c;
+          const int cc = col < k ? col : k - 1;
+          const double m = (rok && col < k) ? 1.0 : 0.0;
+          y[u][cb] = m * static_cast<double>(W[rr * k + cc]);
+#pragma unroll
+          for (int b = 0; b < MB; ++b)
+            x[u][b][cb] = (b < nblk) ? m * static_cast<double>(V0[b * vstride + rr * k + cc]) : 0.0;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int b = 0; b < MB; ++b)
+          if (b < nblk) {
+#pragma unroll
+            for (int ia = 0; ia < NB; ++ia)
+#pragma unroll
+              for (int jb = 0; jb < NB; ++jb) acc[b][ia][jb] = mfma(x[u][b][ia], y[u][jb], acc[b][ia][jb]);
+          }
+    }
   }
 #pragma unroll
   for (int b = 0; b < MB; ++b)
-    if (b < nblk) fold_kxk<NB>(acc[b], red, partials + (int64_t)b * KP * KP * gridDim.x);
+    if (b < nblk) {
+      if constexpr (sizeof(T) == 4)
+        fold_kxk32<NB>(acc[b], red, partials + (int64_t)b * KP * KP * gridDim.x);
+      else
+        fold_kxk<NB>(acc[b], red, partials + (int64_t)b * KP * KP * gridDim.x);
+    }
 }
 
 // W -= sum_b V_b C_b, C_b = C + b * k * k (row-major k x k, FP64).  The coefficient blocks are
