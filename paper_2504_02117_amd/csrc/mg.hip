@@ -331,16 +331,20 @@ __global__ __launch_bounds__(256) void mg_restrict_kernel(LvArgs<T> L, Geo c, in
 
 // z = y + w D^-1 (f - A y) with y = w D^-1 f + P xc.  Persistent: each workgroup walks one contiguous
 // XCD-aware range of rows, one row per thread per step.  With GRAM (CW == k, k in {1, 2, 4}) the
-// workgroup also accumulates gamma = f^T z, T = Q^T z and nrm = diag(f^T f) in FP64 and stores one
-// partial per entry, laid out [gamma (k*k) | T (k*k) | nrm (k)] x gridDim.x (fixed-order folding).
+// workgroup also accumulates gamma = f^T z, T = Q^T z and nrm = diag(f^T f) (per thread in the
+// block's precision, then in FP64) and stores one partial per entry, laid out
+// [gamma (k*k) | T (k*k) | nrm (k)] x gridDim.x (fixed-order folding).
 template <typename T, int CW, bool GRAM>
 __global__ __launch_bounds__(256) void mg_prolong_kernel(LvArgs<T> L, Geo c, const T* __restrict__ f,
                                                          const T* __restrict__ xc, T* __restrict__ z,
                                                          const T* __restrict__ Qm, double* partials) {
   constexpr int NA = GRAM ? 2 * CW * CW + CW : 1;
-  double acc[NA];
+  // a thread's rows are summed in the block's own precision (FP32 blocks: about 16 rows per thread,
+  // which keeps the accumulators in half the registers), the threads and workgroups in FP64
+  using A = T;
+  A acc[NA];
 #pragma unroll
-  for (int e = 0; e < NA; ++e) acc[e] = 0.0;
+  for (int e = 0; e < NA; ++e) acc[e] = A(0);
   const int64_t N = L.g.N;
   const int64_t slot = dev::xcd_slot(blockIdx.x, gridDim.x);
   const int64_t chunks = (N + 255) / 256;
@@ -361,24 +365,27 @@ __global__ __launch_bounds__(256) void mg_prolong_kernel(LvArgs<T> L, Geo c, con
         for (int i = 0; i < CW; ++i) {
 #pragma unroll
           for (int j = 0; j < CW; ++j) {
-            acc[i * CW + j] = fma((double)fr[i], (double)zr[j], acc[i * CW + j]);
-            acc[CW * CW + i * CW + j] = fma((double)q[i], (double)zr[j], acc[CW * CW + i * CW + j]);
+            acc[i * CW + j] = fma(fr[i], zr[j], acc[i * CW + j]);
+            acc[CW * CW + i * CW + j] = fma(q[i], zr[j], acc[CW * CW + i * CW + j]);
           }
-          acc[2 * CW * CW + i] = fma((double)fr[i], (double)fr[i], acc[2 * CW * CW + i]);
+          acc[2 * CW * CW + i] = fma(fr[i], fr[i], acc[2 * CW * CW + i]);
         }
       }
     }
   }
   if constexpr (GRAM) {
     __shared__ double red[4 * NA];
+    double sum[NA];
+#pragma unroll
+    for (int e = 0; e < NA; ++e) sum[e] = (double)acc[e];
 #pragma unroll
     for (int off = 1; off < 64; off <<= 1)
 #pragma unroll
-      for (int e = 0; e < NA; ++e) acc[e] += __shfl_xor(acc[e], off);
+      for (int e = 0; e < NA; ++e) sum[e] += __shfl_xor(sum[e], off);
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     if (lane == 0) {
 #pragma unroll
-      for (int e = 0; e < NA; ++e) red[w * NA + e] = acc[e];
+      for (int e = 0; e < NA; ++e) red[w * NA + e] = sum[e];
     }
     __syncthreads();
     for (int e = threadIdx.x; e < NA; e += 256)
