@@ -20,6 +20,33 @@ __device__ __forceinline__ int64_t xcd_slot(int64_t b, int64_t nb) {
   return x * q + (x < rem ? x : rem) + i;
 }
 
+// The 256-row chunks a workgroup of a persistent grid walks: the chunks are split into kXcd
+// contiguous slabs, one per XCD (workgroup b runs on XCD b % kXcd), and the workgroups of an XCD
+// step through its slab together (chunk j, j + W, j + 2W, ... for W workgroups per XCD), so each XCD
+// works on one contiguous window at a time and the neighbour planes of its rows stay in its L2.
+// Grids that are not a multiple of kXcd take one contiguous range per workgroup instead.
+struct ChunkWalk {
+  int64_t first, end, step;
+};
+__device__ __forceinline__ ChunkWalk xcd_chunks(int64_t chunks) {
+  ChunkWalk w;
+  if (gridDim.x % kXcd == 0) {
+    const int64_t nw = gridDim.x / kXcd, x = blockIdx.x % kXcd, j = blockIdx.x / kXcd;
+    const int64_t per = (chunks + kXcd - 1) / kXcd;
+    const int64_t hi = (x + 1) * per < chunks ? (x + 1) * per : chunks;
+    w.first = x * per + j;
+    w.end = hi;
+    w.step = nw;
+  } else {
+    const int64_t slot = xcd_slot(blockIdx.x, gridDim.x);
+    const int64_t per = (chunks + gridDim.x - 1) / gridDim.x;
+    w.first = slot * per;
+    w.end = (slot + 1) * per < chunks ? (slot + 1) * per : chunks;
+    w.step = 1;
+  }
+  return w;
+}
+
 // Row tiles of a block vector with padded width KP (power of two, 1..32).  A tile holds
 // RT = 2048/KP rows.  Thread t owns column c = t % KP of rows t/KP + i*RS (RS = 256/KP),
 // i = 0..7, both for its global loads and for its outputs, so loads are coalesced and each

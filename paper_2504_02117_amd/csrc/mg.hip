@@ -347,10 +347,10 @@ __global__ __launch_bounds__(256) void mg_prolong_kernel(LvArgs<T> L, Geo c, con
   for (int e = 0; e < NA; ++e) acc[e] = A(0);
   const int64_t N = L.g.N;
   const int64_t slot = dev::xcd_slot(blockIdx.x, gridDim.x);
-  const int64_t chunks = (N + 255) / 256;
-  const int64_t per = (chunks + gridDim.x - 1) / gridDim.x;
-  const int64_t end = (slot + 1) * per * 256 < N ? (slot + 1) * per * 256 : N;
-  for (int64_t r = slot * per * 256 + threadIdx.x; r < end; r += 256) {
+  const dev::ChunkWalk walk = dev::xcd_chunks((N + 255) / 256);
+  for (int64_t ch = walk.first; ch < walk.end; ch += walk.step) {
+    const int64_t r = ch * 256 + threadIdx.x;
+    if (r >= N) continue;  // the last chunk's tail
     int ix, iy, iz;
     coords(L.g, r, ix, iy, iz);
     const int kc = GRAM ? CW : L.k;  // with the reductions the row is one chunk
@@ -583,12 +583,14 @@ LvArgs<T> lv_args(const MgLevel& l, int k, double a, double b) {
   return L;
 }
 
-// Persistent grid of the prolongation: the resident capacity of the chip, capped by the row chunks.
+// Persistent grid of the prolongation: the resident capacity of the chip, capped by the row chunks,
+// in whole rounds over the XCDs when it has at least one.
 template <typename K>
 int64_t prolong_grid(bkts_ctx ctx, K kernel, int64_t N) {
   int64_t nb = (int64_t)blocks_per_cu(reinterpret_cast<const void*>(kernel)) * ctx->num_cu;
   const int64_t chunks = (N + 255) / 256;
   if (nb > chunks) nb = chunks;
+  if (nb >= dev::kXcd) nb -= nb % dev::kXcd;
   return nb < 1 ? 1 : nb;
 }
 
