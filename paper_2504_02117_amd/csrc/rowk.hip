@@ -189,8 +189,12 @@ __global__ __launch_bounds__(256) void rk_st_spmm_gram_kernel(RkStArgs<T> a) {
 #pragma unroll
   for (int e = 0; e < KP * KP; ++e) g[e] = 0.0;
   const int64_t N = a.N;
-  const RowRange rr = block_rows(N);
-  for (int64_t r0 = rr.begin + threadIdx.x; r0 < rr.end; r0 += G * dev::kThreads) {
+  // units of G chunks walked per XCD slab (the neighbour planes stay in the XCD's L2); every load of
+  // a unit is issued before the arithmetic: rows past N read row N - 1, a neighbour past either end
+  // reads the row itself, and both come with zero weights
+  const dev::ChunkWalk walk = dev::xcd_chunks((N + G * dev::kThreads - 1) / (G * dev::kThreads));
+  for (int64_t u = walk.first; u < walk.end; u += walk.step) {
+    const int64_t r0 = u * (G * dev::kThreads) + threadIdx.x;
     int64_t r[G];
     bool ok[G];
     T dg[G], up[G][3], lo[G][3];
@@ -198,24 +202,21 @@ __global__ __launch_bounds__(256) void rk_st_spmm_gram_kernel(RkStArgs<T> a) {
 #pragma unroll
     for (int h = 0; h < G; ++h) {
       r[h] = r0 + h * dev::kThreads;
-      ok[h] = r[h] < rr.end;
-      dg[h] = ok[h] ? __builtin_nontemporal_load(a.coef + r[h]) : T(0);
-      if (ok[h]) p[h] = ld_row<T, KP>(a.P + r[h] * KP, KP);
+      ok[h] = r[h] < N;
+      const int64_t rr = ok[h] ? r[h] : N - 1;
+      dg[h] = __builtin_nontemporal_load(a.coef + rr) * T(ok[h] ? 1 : 0);
+      p[h] = ld_row<T, KP>(a.P + rr * KP, KP);
 #pragma unroll
       for (int q = 0; q < 3; ++q) {
-        up[h][q] = lo[h][q] = T(0);
-        if (ok[h] && q < a.na) {
-          const int64_t s = a.s[q];
-          const T* oq = a.coef + (1 + q) * N;
-          if (r[h] + s < N) {
-            up[h][q] = oq[r[h]];
-            xu[h][q] = ld_row<T, KP>(a.P + (r[h] + s) * KP, KP);
-          }
-          if (r[h] - s >= 0) {
-            lo[h][q] = oq[r[h] - s];
-            xl[h][q] = ld_row<T, KP>(a.P + (r[h] - s) * KP, KP);
-          }
-        }
+        const bool has = q < a.na;
+        const int64_t s = has ? a.s[q] : 0;
+        const bool uo = has && rr + s < N, lk = has && rr - s >= 0;
+        const int64_t ru = uo ? rr + s : rr, rl = lk ? rr - s : rr;
+        const T* oq = a.coef + (1 + (has ? q : 0)) * N;
+        up[h][q] = oq[rr] * T(uo ? 1 : 0);
+        lo[h][q] = oq[rl] * T(lk ? 1 : 0);
+        xu[h][q] = ld_row<T, KP>(a.P + ru * KP, KP);
+        xl[h][q] = ld_row<T, KP>(a.P + rl * KP, KP);
       }
     }
 #pragma unroll
@@ -226,17 +227,10 @@ __global__ __launch_bounds__(256) void rk_st_spmm_gram_kernel(RkStArgs<T> a) {
       for (int j = 0; j < KP; ++j) acc[j] = dg[h] * p[h].v[j];
 #pragma unroll
       for (int q = 0; q < 3; ++q) {
-        if (q < a.na) {
-          const int64_t s = a.s[q];
-          if (r[h] - s >= 0) {
 #pragma unroll
-            for (int j = 0; j < KP; ++j) acc[j] = fma(lo[h][q], xl[h][q].v[j], acc[j]);
-          }
-          if (r[h] + s < N) {
+        for (int j = 0; j < KP; ++j) acc[j] = fma(lo[h][q], xl[h][q].v[j], acc[j]);
 #pragma unroll
-            for (int j = 0; j < KP; ++j) acc[j] = fma(up[h][q], xu[h][q].v[j], acc[j]);
-          }
-        }
+        for (int j = 0; j < KP; ++j) acc[j] = fma(up[h][q], xu[h][q].v[j], acc[j]);
       }
       Row<T, KP> qv;
 #pragma unroll
@@ -535,6 +529,7 @@ int64_t rk_grid(bkts_ctx ctx, K kernel, int64_t N) {
   int64_t nb = (int64_t)blocks_per_cu(reinterpret_cast<const void*>(kernel)) * ctx->num_cu;
   const int64_t chunks = (N + 255) / 256;
   if (nb > chunks) nb = chunks;
+  if (nb >= dev::kXcd) nb -= nb % dev::kXcd;  // whole rounds over the XCDs
   return nb < 1 ? 1 : nb;
 }
 
