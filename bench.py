@@ -703,7 +703,7 @@ def run_richards(torch, bkts, ctx, a):
                                ("block_bicgstab_k4", 4, BI, F32),  # the width the paper finds best
                                ("plain_gmres", 1, GM, F64), ("plain_bicgstab", 1, BI, F64)):
         log(f"Richards leg {n}: {name} k={k}, inner {a.ri_inner_rtol:g}, {a.ri_steps} steps")
-        r = form(n, ks, y0, k, kry, prec, a.ri_steps, 1, name == "block_gmres")
+        r = form(n, ks, y0, k, kry, prec, a.ri_steps, 1, True)
         log(f"  {r['value']:.4g} DOF*steps/s, outer={r['info'].outer_iterations} "
             f"krylov={r['info'].krylov_iterations}")
         res[name] = r
@@ -731,7 +731,9 @@ def run_richards(torch, bkts, ctx, a):
                         f"inner {a.ri_inner_rtol:g} in FP32 with FP64 residuals, Jacobi",
             "value": blk["value"], "unit": "DOF*timesteps/s", "ms_per_step": 1e3 * blk["seconds"] / a.ri_steps,
             "forms": {kk: {"value": v["value"], "outer_iterations": v["info"].outer_iterations,
-                           "krylov_iterations": v["info"].krylov_iterations} for kk, v in res.items()},
+                           "krylov_iterations": v["info"].krylov_iterations,
+                           "kernels": {c: {"avg_us": x["avg_us"], "launches": x["launches"], "share": x["share"]}
+                                       for c, x in v["kernels"].items()}} for kk, v in res.items()},
             "fastest_form": best,
             "speedup_vs_plain": blk["value"] / max(res["plain_gmres"]["value"], res["plain_bicgstab"]["value"]),
             "oracle_max_rel_err_16x16x20": err, "roofline": roof,

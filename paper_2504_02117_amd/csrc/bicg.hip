@@ -78,19 +78,29 @@ __global__ __launch_bounds__(256) void bicg_r_kernel(int64_t n, int k, const T* 
   }
 }
 
+// With nrm (the squared column norms of the residual this step produced), a column whose norm is
+// not finite keeps its iterate.
 template <typename T>
 __global__ __launch_bounds__(256) void bicg_x_kernel(int64_t n, int k, const T* __restrict__ Ph,
                                                      const T* __restrict__ Sh, const double* al, const double* om,
-                                                     T* __restrict__ X) {
+                                                     const double* nrm, T* __restrict__ X) {
   __shared__ double sa[BKTS_MAX_K], so[BKTS_MAX_K];
+  __shared__ int live[BKTS_MAX_K];
+  if (threadIdx.x < k) live[threadIdx.x] = nrm ? (int)isfinite(nrm[threadIdx.x]) : 1;
   load_diags(k, al, om, nullptr, sa, so, nullptr);
   const int64_t i0 = (int64_t)blockIdx.x * (256 * kEPT) + threadIdx.x;
   RowCol rc(i0, k);
 #pragma unroll
   for (int e = 0; e < kEPT; ++e, rc.step(k)) {
     const int64_t i = i0 + (int64_t)e * 256;
-    if (i < n) X[i] = (T)((double)X[i] + sa[rc.c] * (double)Ph[i] + so[rc.c] * (double)Sh[i]);
+    if (i < n && live[rc.c]) X[i] = (T)((double)X[i] + sa[rc.c] * (double)Ph[i] + so[rc.c] * (double)Sh[i]);
   }
+}
+
+// n values from device memory to host memory mapped into the device (coherent pinned memory)
+__global__ void publish_kernel(const double* src, int n, double* dst) {
+  const int i = threadIdx.x;
+  if (i < n) dst[i] = src[i];
 }
 
 template <typename T>
@@ -164,16 +174,22 @@ void bicg_r_step(bkts_ctx ctx, int dtype, int64_t N, int k, const void* S, const
 }
 
 void bicg_x_step(bkts_ctx ctx, int dtype, int64_t N, int k, const void* Ph, const void* Sh, const double* al,
-                 const double* om, void* X) {
+                 const double* om, const double* nrm, void* X) {
   const int64_t n = N * k;
   if (n == 0) return;
   ProfScope prof(ctx, BKTS_K_OTHER, 4.0 * n * esize(dtype));
   if (dtype == BKTS_F64)
     launch(ctx, bicg_x_kernel<double>, grid_ept(n), dim3(256), 0, n, k, static_cast<const double*>(Ph),
-           static_cast<const double*>(Sh), al, om, static_cast<double*>(X));
+           static_cast<const double*>(Sh), al, om, nrm, static_cast<double*>(X));
   else
     launch(ctx, bicg_x_kernel<float>, grid_ept(n), dim3(256), 0, n, k, static_cast<const float*>(Ph),
-           static_cast<const float*>(Sh), al, om, static_cast<float*>(X));
+           static_cast<const float*>(Sh), al, om, nrm, static_cast<float*>(X));
+  BKTS_HIP(hipGetLastError());
+}
+
+void publish(bkts_ctx ctx, const double* src, int n, double* dst_mapped) {
+  BKTS_REQUIRE(n >= 1 && n <= 256, "publish: 1..256 values");
+  launch(ctx, publish_kernel, dim3(1), dim3(256), 0, src, n, dst_mapped);
   BKTS_HIP(hipGetLastError());
 }
 

@@ -263,6 +263,36 @@ void block_bicgstab(bkts_ctx ctx, const bkts_op_s& op, int dtype, int k, double 
     return;
   }
   scale_rows(ctx, dtype, N, k, dinv, P, Ph);
+  // Convergence is read one iteration late: the norms of iteration it land in pinned host memory
+  // behind an event, and the host reads them after it has enqueued the residual half of iteration
+  // it + 1, before that iteration's X update, so the iterates are those of a synchronous check.
+  // The X update skips every column whose new residual norm is not finite (a breakdown keeps the
+  // last finite iterate).
+  double* hbuf = ctx->host_stage(2 * k);
+  ctx->sync();
+  double* hbuf_dev = nullptr;
+  BKTS_HIP(hipHostGetDevicePointer(reinterpret_cast<void**>(&hbuf_dev), hbuf, 0));
+  hipEvent_t ev[2];
+  BKTS_HIP(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming | hipEventDisableSystemFence));
+  BKTS_HIP(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming | hipEventDisableSystemFence));
+  struct EvGuard {
+    hipEvent_t* e;
+    ~EvGuard() { (void)hipEventDestroy(e[0]); (void)hipEventDestroy(e[1]); }
+  } guard{ev};
+  auto check = [&](int it) -> int {  // 1 = converged, -1 = breakdown, 0 = continue
+    BKTS_HIP(hipEventSynchronize(ev[it & 1]));
+    const double* h = hbuf + (it & 1) * k;
+    nrm.assign(h, h + k);
+    for (double v : nrm)
+      if (!std::isfinite(v)) return -1;
+    st.iterations = it;
+    return converged(nrm, nrm0, rtol, &st.max_rel, true) ? 1 : 0;
+  };
+  auto finish = [&](int state) {
+    ctx->sync();  // the residual half of the next iteration is in flight; it does not touch X
+    st.breakdown = state == -1 ? 1 : 0;
+    st.converged = state == 1 ? 1 : 0;
+  };
   for (int it = 1; it <= maxit; ++it) {
     apply(Ph, V);  // V = A D^-1 P
     {
@@ -283,24 +313,20 @@ void block_bicgstab(bkts_ctx ctx, const bkts_op_s& op, int dtype, int k, double 
     small_diag_ratio(ctx, k, ts, tt, 1.0, W);  // omega_j = (t_j^T s_j) / (t_j^T t_j)
     bicg_r_step(ctx, dtype, N, k, Sb, T, W, R);  // R = S - T omega
     colnorms2(ctx, dtype, N, k, R, k, nrmd);
-    read_host(ctx, nrmd, k, nrm);
-    bool finite = true;
-    for (double v : nrm) finite = finite && std::isfinite(v);
-    if (!finite) {  // breakdown: keep the last iterate (X is updated only after its residual is known)
-      st.breakdown = 1;
-      st.converged = 0;
-      return;
+    publish(ctx, nrmd, k, hbuf_dev + (it & 1) * k);
+    BKTS_HIP(hipEventRecord(ev[it & 1], ctx->stream));
+    if (it > 1) {  // iteration it - 1 is complete: stop there if it converged or broke down
+      const int state = check(it - 1);
+      if (state != 0) {
+        finish(state);  // this iteration's residual work is dropped, X is that of it - 1
+        return;
+      }
     }
-    bicg_x_step(ctx, dtype, N, k, Ph, Sh, al, W, X);  // X += D^-1 P alpha + D^-1 S omega
-    st.iterations = it;
-    if (converged(nrm, nrm0, rtol, &st.max_rel, true)) {
-      st.converged = 1;
-      return;
-    }
+    bicg_x_step(ctx, dtype, N, k, Ph, Sh, al, W, nrmd, X);  // X += D^-1 P alpha + D^-1 S omega
     small_diag_ratio(ctx, k, m3, m1, -1.0, be);  // beta_j = -(rt_j^T t_j) / (rt_j^T v_j)
     bicg_p_step(ctx, dtype, N, k, R, V, W, be, dinv, P, Ph);  // P = R + (P - V omega) beta, Ph = D^-1 P
   }
-  st.converged = 0;
+  finish(maxit >= 1 ? check(maxit) : 0);
 }
 
 }  // namespace bkts

@@ -40,9 +40,13 @@ void bicg_s_step(bkts_ctx ctx, int dtype, int64_t N, int k, const void* R, const
                  const double* dinv, void* S, void* Sh);
 // R = S - T omega
 void bicg_r_step(bkts_ctx ctx, int dtype, int64_t N, int k, const void* S, const void* Tv, const double* om, void* R);
-// X += Ph alpha + Sh omega
+// X += Ph alpha + Sh omega, except in the columns whose squared residual norm nrm[j] is not finite
+// (nrm may be null)
 void bicg_x_step(bkts_ctx ctx, int dtype, int64_t N, int k, const void* Ph, const void* Sh, const double* al,
-                 const double* om, void* X);
+                 const double* om, const double* nrm, void* X);
+// Copy n <= 256 device values into coherent pinned host memory through its device mapping (one
+// kernel store per value, so the host may read them after an event without a system fence).
+void publish(bkts_ctx ctx, const double* src, int n, double* dst_mapped);
 // P = R + (P - V omega) beta, Ph = D^-1 P
 void bicg_p_step(bkts_ctx ctx, int dtype, int64_t N, int k, const void* R, const void* V, const double* om,
                  const double* be, const double* dinv, void* P, void* Ph);
