@@ -444,7 +444,7 @@ void bkts_stepper_destroy(bkts_stepper st);
  *    (0: min(k, 4)), each front column accepted as soon as ||R_0|| <= rtol ||rhs_0|| (Sec. 2.2),
  *    on the index-free stencil form of the operator with FP32 block CG preconditioned by the
  *    geometric multigrid V-cycle (inner_rtol) inside the FP64 outer iteration.  Mode-1 requests
- *    run on a few worker lanes, each with its own stream, beside the grouped rounds.
+ *    run on min(16, max_slots) worker lanes, each with its own stream, beside the grouped rounds.
  * Both modes share the arrival-order admission and the HBM budget.
  *
  * A request's result does not depend on the other requests in flight: every job keeps its own
@@ -488,7 +488,8 @@ typedef struct bkts_server_stats {
 } bkts_server_stats;
 
 /* Start a server on ctx's device.  hbm_budget_bytes bounds the sum of the admitted requests'
- * footprints; max_slots (1..256) bounds how many run at once. */
+ * footprints; max_slots (1..256) bounds how many mode-0 requests run at once, and min(16,
+ * max_slots) how many mode-1 requests do. */
 bkts_status bkts_server_create(bkts_ctx ctx, size_t hbm_budget_bytes, int max_slots, bkts_server* out);
 /* Queue a request (non-blocking; thread-safe).  kappa, y0 and y_out must stay valid, and y0 and
  * kappa must already hold their values (the server's stream does not wait for the caller's),

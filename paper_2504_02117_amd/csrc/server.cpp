@@ -10,7 +10,7 @@
 // until every column meets the tolerance; the inner solves are FP32 block CG with Jacobi, the
 // residual and the update are FP64.  A mode-1 request runs the pipelined Algorithm 1 (its front
 // column accepted as soon as it converges) with multigrid-preconditioned block CG on a lane of its
-// own: kLanes threads, each with a context and stream, take mode-1 requests from the same
+// own: up to kLanes threads, each with a context and stream, take mode-1 requests from the same
 // arrival-order queue under the same HBM budget.
 #include "server.hpp"
 
@@ -101,7 +101,9 @@ bkts_server_s::bkts_server_s(int device, size_t budget_, int max_slots_)
   table_bytes = sizeof(GJob) * max_slots + sizeof(int) * 16 * (max_slots + 1) * 4;
   table_dev.alloc(table_bytes);
   BKTS_HIP(hipHostMalloc(&table_host, table_bytes, hipHostMallocDefault));
-  for (Lane& L : lanes) {
+  nlanes = std::min(kLanes, max_slots);
+  for (int l = 0; l < nlanes; ++l) {
+    Lane& L = lanes[l];
     hipStream_t ls = nullptr;
     BKTS_HIP(hipStreamCreateWithFlags(&ls, hipStreamNonBlocking));  // default priority
     L.ctx = new bkts_ctx_s();
@@ -110,7 +112,7 @@ bkts_server_s::bkts_server_s(int device, size_t budget_, int max_slots_)
     L.ctx->num_cu = ctx->num_cu;
   }
   worker = std::thread([this] { run(); });
-  for (int l = 0; l < kLanes; ++l) lanes[l].th = std::thread([this, l] { lane_run(l); });
+  for (int l = 0; l < nlanes; ++l) lanes[l].th = std::thread([this, l] { lane_run(l); });
 }
 
 bkts_server_s::~bkts_server_s() {
@@ -229,7 +231,7 @@ void bkts_server_s::run() {
           if (in_use + h.footprint > budget) break;
           if (h.req.mode == 1) {  // a pipelined request goes to a free lane
             int lane = -1;
-            for (int l = 0; l < kLanes; ++l)
+            for (int l = 0; l < nlanes; ++l)
               if (!lanes[l].busy) {
                 lane = l;
                 break;

@@ -50,7 +50,8 @@ struct bkts_server_s {
     bool busy = false;  // a request is assigned (guarded by mu)
     Pending p;
   };
-  static constexpr int kLanes = 4;
+  static constexpr int kLanes = 16;  // at most; a server has min(kLanes, max_slots)
+  int nlanes = 0;
 
   bkts_ctx ctx = nullptr;  // the server's own context and stream
   size_t budget;
