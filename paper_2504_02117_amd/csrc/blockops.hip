@@ -700,6 +700,8 @@ void block_cast_scale(bkts_ctx ctx, int64_t N, int k, int src_t, const void* src
   if (n == 0) return;
   dim3 g((n + 255) / 256), b(256);
   ProfScope prof(ctx, BKTS_K_CAST, (double)n * (esize(src_t) + esize(dst_t) * (accumulate ? 2 : 1)));
+  if (lds_ == k && ldd == k && rk_cast(ctx, N, k, src_t, src, dst_t, dst, s, invert_s, accumulate, norm2, coef))
+    return;
   const int iv = invert_s, ac = accumulate, n2 = norm2;
   if (src_t == BKTS_F64 && dst_t == BKTS_F32)
     launch(ctx, (cast_scale_kernel<double, float>), g, b, 0, N, k, static_cast<const double*>(src), lds_,

@@ -417,6 +417,11 @@ void cg_pupdate(bkts_ctx ctx, int dtype, int64_t N, int k, void* P, const void* 
 void block_rmul(bkts_ctx ctx, int dtype, int64_t N, int k, const void* X, int ldx, const double* C,
                 double c0, double c1, void* Y, int ldy);
 
+// block_cast_scale between FP64 and FP32 for contiguous 16-byte aligned blocks of k in {1, 2, 4}
+// columns, one row per thread; returns false (and does nothing) for any other shape.
+bool rk_cast(bkts_ctx ctx, int64_t N, int k, int src_t, const void* src, int dst_t, void* dst, const double* s,
+             bool invert, bool accumulate, bool norm2, double coef);
+
 // Scaled casts: dst = coef * src * diag(s) (s device, k; null = ones), between F64 and F32 blocks;
 // invert_s divides by s; norm2: s holds squared column norms and column c scales by sqrt(s[c]) (1
 // for a zero column); accumulate adds into dst.

@@ -533,6 +533,31 @@ int64_t rk_grid(bkts_ctx ctx, K kernel, int64_t N) {
   return nb < 1 ? 1 : nb;
 }
 
+// dst = coef * src * diag(s) (+ dst with accumulate) for contiguous rows of KP <= 4 columns, one row
+// per thread with vector loads; the column scales as in block_cast_scale (s inverted on request, or
+// the square roots of squared norms, 1 for a zero column).
+template <typename S, typename D, int KP>
+__global__ __launch_bounds__(256) void rk_cast_kernel(int64_t N, const S* __restrict__ src, D* dst, const double* s,
+                                                      int invert, int accumulate, int norm2, double coef) {
+  const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (r >= N) return;
+  double sc[KP];
+#pragma unroll
+  for (int c = 0; c < KP; ++c) sc[c] = s ? (norm2 ? (s[c] > 0.0 ? sqrt(s[c]) : 1.0) : s[c]) : 1.0;
+  const Row<S, KP> x = ld_row<S, KP>(src + r * KP, KP);
+  Row<D, KP> y;
+  if (accumulate) y = ld_row<D, KP>(dst + r * KP, KP);
+#pragma unroll
+  for (int c = 0; c < KP; ++c) {
+    double v = (double)x.v[c];
+    if (s) v = invert ? v / sc[c] : v * sc[c];
+    if (coef != 1.0) v = coef * v;
+    if (accumulate) v += (double)y.v[c];
+    y.v[c] = (D)v;
+  }
+  st_row<D, KP>(dst + r * KP, y);
+}
+
 }  // namespace
 
 bool rk_eligible(int k) { return k == 1 || k == 2 || k == 4; }
@@ -769,6 +794,27 @@ void rk_rmul(bkts_ctx ctx, int dtype, int64_t N, int k, const void* X, const dou
     BKTS_RK_DISPATCH(k, (rk_rmul_t<double, KP>(ctx, N, X, C, c0, c1, Y)));
   else
     BKTS_RK_DISPATCH(k, (rk_rmul_t<float, KP>(ctx, N, X, C, c0, c1, Y)));
+}
+
+template <typename S, typename D, int KP>
+static void rk_cast_t(bkts_ctx ctx, int64_t N, const void* src, void* dst, const double* s, bool invert,
+                      bool accumulate, bool norm2, double coef) {
+  launch(ctx, (rk_cast_kernel<S, D, KP>), dim3((unsigned)((N + 255) / 256)), dim3(256), 0, N,
+         static_cast<const S*>(src), static_cast<D*>(dst), s, (int)invert, (int)accumulate, (int)norm2, coef);
+  BKTS_HIP(hipGetLastError());
+}
+
+bool rk_cast(bkts_ctx ctx, int64_t N, int k, int src_t, const void* src, int dst_t, void* dst, const double* s,
+             bool invert, bool accumulate, bool norm2, double coef) {
+  auto aligned = [](const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; };
+  if (!rk_eligible(k) || !aligned(src) || !aligned(dst) || N >= ((int64_t)1 << 38)) return false;
+  if (src_t == BKTS_F64 && dst_t == BKTS_F32)
+    BKTS_RK_DISPATCH(k, (rk_cast_t<double, float, KP>(ctx, N, src, dst, s, invert, accumulate, norm2, coef)));
+  else if (src_t == BKTS_F32 && dst_t == BKTS_F64)
+    BKTS_RK_DISPATCH(k, (rk_cast_t<float, double, KP>(ctx, N, src, dst, s, invert, accumulate, norm2, coef)));
+  else
+    return false;
+  return true;
 }
 
 }  // namespace bkts
