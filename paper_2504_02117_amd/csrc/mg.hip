@@ -14,9 +14,12 @@
 //   x = w D^-1 f                     (one damped Jacobi sweep from zero)
 //   f_{l+1} = P^T (f - A x)          (residual and restriction, one pass)
 //   x_{l+1} = V-cycle(l + 1, f_{l+1})
-//   z = x + P x_{l+1};  z += w D^-1 (f - A z)   (prolongation and post-sweep, one pass)
+//   z = x + s P x_{l+1};  z += w D^-1 (f - A z)   (prolongation and post-sweep, one pass)
 // with the pre-smoothed x recomputed wherever it is needed instead of stored, and on the coarsest
-// level (at most 64 cells) a fixed number of damped Jacobi sweeps.
+// level (at most 64 cells) a fixed number of damped Jacobi sweeps.  The scale s > 1 compensates the
+// Galerkin operator of piecewise-constant aggregation, which is too stiff on smooth modes (an
+// aggregate couples to a face neighbour through four fine faces), so an unscaled correction falls
+// short.
 //
 // Launch structure.  The large levels run one multi-workgroup launch per restriction and per
 // prolongation, each workgroup on a contiguous range of the grid that belongs to one XCD (so the
@@ -51,7 +54,9 @@ namespace {
 
 constexpr int kCoarsestMax = 64;  // cells of the coarsest level
 constexpr int kCoarseSweeps = 12;
-constexpr double kOmega = 0.8;
+constexpr double kOmega = 0.9;        // damping of the pre- and post-sweeps
+constexpr double kCoarseScale = 1.4;  // scale of the prolonged coarse correction
+constexpr double kCoarseOmega = 0.8;  // damping of the coarsest level's sweeps
 constexpr int kMaxLevels = 16;
 constexpr int64_t kTailElems = 2048;  // levels with N_l * k <= this run inside the tail launch
 constexpr int kTailThreads = 512;
@@ -146,6 +151,7 @@ struct LvArgs {
   const T* c;   // 5 arrays of N
   const T* di;  // inverse diagonal of A on this level
   T a, b, w;
+  T gc;  // scale of the prolonged coarse correction
   int k;
 };
 
@@ -272,6 +278,12 @@ __device__ __forceinline__ void prolong_row(const LvArgs<T>& L, const Geo& c, co
     const int po = odd ? pos[d] + 1 : pos[d] - 1;  // the neighbour outside the own aggregate
     const int64_t Po = (po >= 0 && po < len[d]) ? (odd ? P0 + cst[d] : P0 - cst[d]) : P0;
     ld_cw<T, CW>(xc + Po * L.k + c0, xo[d]);
+  }
+#pragma unroll
+  for (int j = 0; j < CW; ++j) {
+    xv[j] *= L.gc;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) xo[d][j] *= L.gc;
   }
   auto ycell = [&](int64_t q, int qx, int qy, int qz, T(&y)[CW]) {
     pre_x<T, CW>(L, f, q, c0, y);
@@ -409,7 +421,8 @@ struct TailArgs {
   TailLv<T> lv[kMaxLevels];
   int nl;  // levels in the tail; the last is the coarsest
   int k;
-  T a, b, w;
+  T a, b, w, gc;
+  T wc;  // damping of the coarsest level's sweeps
 };
 
 template <typename T>
@@ -421,6 +434,7 @@ __device__ __forceinline__ LvArgs<T> tail_lv(const TailArgs<T>& A, int l) {
   L.a = A.a;
   L.b = A.b;
   L.w = A.w;
+  L.gc = A.gc;
   L.k = A.k;
   return L;
 }
@@ -511,7 +525,7 @@ __global__ __launch_bounds__(kTailThreads) void mg_tail_kernel(TailArgs<T> A) {
         di[i] = L.di[r];
         dA[i] = T(1) / di[i];
         fv[i] = f[e];
-        xs[0][e] = L.w * fv[i] * di[i];
+        xs[0][e] = A.wc * fv[i] * di[i];
       }
     }
     __syncthreads();
@@ -525,7 +539,7 @@ __global__ __launch_bounds__(kTailThreads) void mg_tail_kernel(TailArgs<T> A) {
           T ay = dA[i] * yr;
 #pragma unroll
           for (int q = 0; q < 6; ++q) ay = fma(cf[i][q], xs[cur][nb[i][q]], ay);
-          xs[cur ^ 1][e] = yr + L.w * (fv[i] - ay) * di[i];
+          xs[cur ^ 1][e] = yr + A.wc * (fv[i] - ay) * di[i];
         }
       }
       __syncthreads();
@@ -579,6 +593,7 @@ LvArgs<T> lv_args(const MgLevel& l, int k, double a, double b) {
   L.a = (T)a;
   L.b = (T)b;
   L.w = (T)kOmega;
+  L.gc = (T)kCoarseScale;
   L.k = k;
   return L;
 }
@@ -658,6 +673,8 @@ void vcycle(bkts_ctx ctx, MgHier& h, int k, double a, double b, const T* f, T* z
     A.a = (T)a;
     A.b = (T)b;
     A.w = (T)kOmega;
+    A.gc = (T)kCoarseScale;
+    A.wc = (T)kCoarseOmega;
     double bytes = 0.0;
     for (int l = t0; l < nl; ++l) {
       const LvArgs<T> L = lv_args<T>(h.lv[l], k, a, b);
