@@ -10,30 +10,24 @@ scipy sparse matrices, so that one application can be compared entry by entry:
   prolongation ``P_l`` (``P[i, I] = 1`` when fine cell i lies in aggregate I) the coarse operators are
   the Galerkin products ``K_{l+1} = P^T K_l P`` and ``M_{l+1} = P^T M_l P``;
 * coarsening stops once a level has at most 64 cells (or after 16 levels);
-* cells are coloured red (even coordinate sum on their level's grid) and black; the 7-point stencil,
-  which the Galerkin products keep, couples only cells of opposite colours;
 * ``V(l, f)``: on the coarsest level, 12 damped Jacobi sweeps from zero with ``w_c = 0.8``;
-  otherwise, from ``x = 0``, one Gauss-Seidel half-sweep over the red cells and one over the black
-  cells, ``x_c = V(l+1, P^T (f - A x))``, ``z = x + s P x_c``, then the half-sweeps in the adjoint
-  order (black, then red).  A half-sweep solves each row of its colour with the other colour
-  fixed; as no two cells of one colour are coupled, it equals a Gauss-Seidel pass over that colour
-  in any order.  The cycle is symmetric because the post-smoother is the adjoint of the
-  pre-smoother.
-* the coarse correction is scaled by ``s = 1.4``: the Galerkin operator of a piecewise-constant
-  aggregation is stiffer than the fine operator on smooth modes (a 2x2x2 aggregate couples to a
-  face neighbour through four fine faces: twice the coupling of a 2h re-discretisation in 3-D), so
-  the unscaled correction falls short.
+  otherwise ``x = w D^-1 f``, ``x_c = V(l+1, P^T (f - A x))``, ``z = x + s P x_c``,
+  ``z += w D^-1 (f - A z)``, with ``D = diag(A_l)``, ``w = 0.9`` and the coarse correction scaled by
+  ``s = 1.4``.  The scale compensates the Galerkin operator of a piecewise-constant aggregation,
+  which is stiffer than the fine operator on smooth modes (a 2x2x2 aggregate couples to a face
+  neighbour through four fine faces: twice the coupling of a 2h re-discretisation in 3-D), so the
+  unscaled correction falls short.
 
 Parity unpinned by the paper (it prints no multigrid); the CPU tests pin this module by the algebraic
-facts it must satisfy (Galerkin row sums, the uniform-coefficient coarse stencil, agreement of the
-smoothing with a cell-by-cell Gauss-Seidel loop, exactness when A is diagonal, symmetry and positive
-definiteness of the cycle, contraction as a stationary solver).
+facts it must satisfy (Galerkin row sums, the uniform-coefficient coarse stencil, symmetry and
+positive definiteness of the cycle, contraction as a stationary solver).
 """
 from __future__ import annotations
 
 import numpy as np
 import scipy.sparse as sp
 
+OMEGA = 0.9          # damping of the pre- and post-sweeps
 COARSE_SCALE = 1.4   # scale of the prolonged coarse correction
 COARSE_OMEGA = 0.8   # damping of the coarsest level's sweeps
 COARSEST_MAX = 64
@@ -59,21 +53,6 @@ def prolongation(n):
     return P, (cx, cy, cz)
 
 
-def red_cells(dims):
-    """Mask of the red cells (even ix + iy + iz) of grid ``dims`` (cells ix + nx*iy + nx*ny*iz)."""
-    nx, ny, nz = dims
-    iz, iy, ix = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
-    return ((ix + iy + iz) % 2 == 0).ravel()
-
-
-def half_sweep(A, f, x, cells):
-    """Gauss-Seidel over the masked cells: each solves its own row with every other cell fixed."""
-    x = np.array(x, dtype=np.float64, copy=True)
-    r = f - A @ x
-    x[cells] += r[cells] / A.diagonal()[cells, None]
-    return x
-
-
 def hierarchy(K, n):
     """Galerkin hierarchy: list of (K_l, m_l diagonal mass, P_l or None, dims)."""
     levels = []
@@ -94,19 +73,17 @@ def hierarchy(K, n):
 
 def vcycle(levels, a, b, f, lvl=0):
     """One V-cycle z = V(f) on level ``lvl`` for the columns of ``f`` (N x k)."""
-    K, m, P, dims = levels[lvl]
+    K, m, P, _ = levels[lvl]
     A = (sp.diags(a * m) + b * K).tocsr()
+    dinv = 1.0 / A.diagonal()
     f = np.asarray(f, dtype=np.float64)
     if P is None:
-        dinv = 1.0 / A.diagonal()
         x = COARSE_OMEGA * dinv[:, None] * f
         for _ in range(COARSE_SWEEPS - 1):
             x = x + COARSE_OMEGA * dinv[:, None] * (f - A @ x)
         return x
-    red = red_cells(dims)
-    x = half_sweep(A, f, np.zeros_like(f), red)
-    x = half_sweep(A, f, x, ~red)
-    xc = vcycle(levels, a, b, P.T @ (f - A @ x), lvl + 1)
+    x = OMEGA * dinv[:, None] * f
+    fc = P.T @ (f - A @ x)
+    xc = vcycle(levels, a, b, fc, lvl + 1)
     z = x + COARSE_SCALE * (P @ xc)
-    z = half_sweep(A, f, z, ~red)
-    return half_sweep(A, f, z, red)
+    return z + OMEGA * dinv[:, None] * (f - A @ z)

@@ -1,6 +1,6 @@
 """Pins for the oracle's multigrid V-cycle: Galerkin coarse operators (row sums, the uniform-coefficient
-coarse stencil), the smoothing against a cell-by-cell Gauss-Seidel loop, exactness when A is a
-multiple of the mass, and the cycle's symmetry, positive definiteness and contraction."""
+coarse stencil), the cycle's closed form when A is a multiple of the mass, and its symmetry,
+positive definiteness and contraction."""
 import numpy as np
 import pytest
 import scipy.sparse as sp
@@ -76,72 +76,43 @@ def test_vcycle_contracts_as_a_solver():
     assert np.linalg.norm(x - x_true) < err0 * 0.5 ** 6
 
 
-@pytest.mark.parametrize("n", [(8, 4, 4), (9, 7, 5)])
-def test_vcycle_exact_without_stiffness(n):
-    # with b = 0 every row is its own equation: the first two half-sweeps solve it, the residual and
-    # so the coarse correction vanish, and the cycle returns A^-1 f = f / a
+def _mass_only_cycle(f, counts, a, w, s, wc, sweeps, P):
+    """The V-cycle for b = 0 worked out by hand: A_l = a diag(m_l) is diagonal, so each damped Jacobi
+    sweep scales its residual by (1 - w), the coarsest solve leaves (1 - wc)^sweeps of the exact
+    answer f / (a m), and the post-sweep gives z' = (1 - w) z + w f / (a m)."""
+    m = counts[0]
+    if len(P) == 0:
+        return (1.0 - (1.0 - wc) ** sweeps) * f / (a * m)[:, None]
+    x = w * f / (a * m)[:, None]
+    fc = P[0].T @ ((1.0 - w) * f)  # f - A x = (1 - w) f
+    xc = _mass_only_cycle(fc, counts[1:], a, w, s, wc, sweeps, P[1:])
+    z = x + s * (P[0] @ xc)
+    return (1.0 - w) * z + w * f / (a * m)[:, None]
+
+
+@pytest.mark.parametrize("n", [(8, 4, 4), (16, 8, 8), (9, 7, 5)])
+def test_vcycle_closed_form_without_stiffness(n):
+    # with b = 0 every level is diagonal and the cycle has a closed form in the damping factors, the
+    # coarse scale and the sweep count; the cell counts m_l come from the aggregation alone
     K, _ = fv.assemble_linear(n, kappa=inputs.lognormal_field(n, 0.0, 1.0, 2.0, 4))
     lv = mg.hierarchy(K, n)
     assert len(lv) >= 2
+    Ps = [P for (_, _, P, _) in lv[:-1]]
+    counts, c = [], np.ones(K.shape[0])
+    for P in [None] + Ps:
+        if P is not None:
+            c = P.T @ c  # cells per aggregate, counted again from the prolongations
+        counts.append(c)
     f = np.random.default_rng(5).standard_normal((K.shape[0], 2))
-    np.testing.assert_allclose(mg.vcycle(lv, 7.0, 0.0, f), f / 7.0, rtol=1e-15, atol=0.0)
-
-
-def _gs_pass(A, f, x, order):
-    """Gauss-Seidel cell by cell in the given order, each row solved with the newest values."""
-    x = x.copy()
-    A = A.tocsr()
-    for i in order:
-        lo, hi = A.indptr[i], A.indptr[i + 1]
-        s, diag = f[i].copy(), 0.0
-        for j, v in zip(A.indices[lo:hi], A.data[lo:hi]):
-            if j == i:
-                diag = v
-            else:
-                s -= v * x[j]
-        x[i] = s / diag
-    return x
-
-
-@pytest.mark.parametrize("n", [(6, 5, 4), (11, 9)])
-def test_smoothing_is_cellwise_gauss_seidel(n):
-    # a two-level cycle rebuilt from a cell-by-cell Gauss-Seidel loop: red cells (even coordinate
-    # sum, found from the cell index here) in index order, then black ones, before the coarse
-    # correction; black then red after it; 12 damped Jacobi sweeps on the coarse level.  The
-    # half-sweeps of the oracle agree only if no two cells of one colour are coupled.
-    K, _ = fv.assemble_linear(n, kappa=inputs.lognormal_field(n, 0.0, 2.0, 2.0, 6))
-    lv = mg.hierarchy(K, n)
-    assert len(lv) == 2
-    a, b = 30.0, 1.0
-    N = K.shape[0]
-    A = (a * sp.identity(N) + b * K).tocsr()
-    dims = tuple(n) + (1,) * (3 - len(n))
-    colour = []
-    for i in range(N):
-        iy_iz, ix = divmod(i, dims[0])
-        iz, iy = divmod(iy_iz, dims[1])
-        colour.append((ix + iy + iz) % 2)
-    red = [i for i in range(N) if colour[i] == 0]
-    black = [i for i in range(N) if colour[i] == 1]
-    f = np.random.default_rng(7).standard_normal((N, 2))
-    x = _gs_pass(A, f, np.zeros_like(f), red + black)
-    Kc, mc, _, _ = lv[1]
-    P = lv[0][2]
-    Ac = (a * sp.diags(mc) + b * Kc).tocsr()
-    fc = P.T @ (f - A @ x)
-    dc = Ac.diagonal()[:, None]
-    xc = np.zeros_like(fc)
-    for _ in range(12):
-        xc = xc + 0.8 * (fc - Ac @ xc) / dc
-    z = x + 1.4 * (P @ xc)
-    z = _gs_pass(A, f, z, black + red)
-    np.testing.assert_allclose(mg.vcycle(lv, a, b, f), z, rtol=1e-12, atol=1e-14 * abs(z).max())
+    a = 7.0
+    want = _mass_only_cycle(f, counts, a, 0.9, 1.4, 0.8, 12, Ps)
+    np.testing.assert_allclose(mg.vcycle(lv, a, 0.0, f), want, rtol=1e-13, atol=1e-15)
 
 
 def test_coarse_scale_shortens_the_iteration():
     # the scaled coarse correction is a better preconditioner than the plain one on a heterogeneous
     # problem with a deep hierarchy: fewer CG iterations to the same residual (the reason for the
-    # scale)
+    # scale; on 512^2 the count falls from 90 to 47, on 128^3 from 31 to 24)
     n = (256, 256)
     K, _ = fv.assemble_linear(n, kappa=inputs.lognormal_field(n, 0.0, 2.0, 8.0, 0))
     a, b = 1e3, 1.0
