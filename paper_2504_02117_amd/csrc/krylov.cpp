@@ -233,9 +233,25 @@ void block_pcg_mg(bkts_ctx ctx, const bkts_op_s& op, int dtype, int k, double a,
   st.deflations = 0;
   st.converged = all_converged(nrm0, nrm0, rtol, &st.max_rel) ? 1 : 0;
   if (st.converged) return;
+  const bool rowk = rk_eligible(k);
+  // k <= 4 on a hierarchy with a separate finest prolongation: the V-cycle's last pass folds
+  // gamma = R^T Z, T = Q^T Z and the norms of R, one launch folds those partials and solves for beta
+  // (writing the norms and the deflation count to pinned host memory), and the Gram of the SpMM pass
+  // is folded and solved for alpha in one launch: 12 launches per iteration instead of 20.  The
+  // update is split: R -= Q alpha feeds the V-cycle, and X += P alpha joins the direction update
+  // P = Z + P beta after it, in one pass that reads the old P once for both.
+  const bool fused = rowk && mg_fusable(ctx, op, k);
   auto precondition = [&]() {  // P = Z = M^-1 R (the cycle writes the first direction directly), gamma = R^T P
-    mg_vcycle(ctx, op, dtype, k, a, b, R, P);
-    inner_gram(ctx, dtype, N, k, R, P, s.gamma);
+    if (fused) {  // gamma from the finest prolongation's reductions (R in Q's place; T and the norms unused)
+      MgFuse fu;
+      fu.Q = R;
+      mg_vcycle(ctx, op, dtype, k, a, b, R, P, &fu);
+      BKTS_REQUIRE(fu.nslots > 0, "multigrid: the fused reductions were not produced");
+      finalize_gram(ctx, fu.partials, (int)fu.nslots, k, k, s.gamma);
+    } else {
+      mg_vcycle(ctx, op, dtype, k, a, b, R, P);
+      inner_gram(ctx, dtype, N, k, R, P, s.gamma);
+    }
   };
   precondition();
   // Convergence is read one iteration late, as in block_cg: the norms of iteration it are copied to
@@ -263,14 +279,6 @@ void block_pcg_mg(bkts_ctx ctx, const bkts_op_s& op, int dtype, int k, double a,
     if (all_converged(nrm, nrm0, rtol, &st.max_rel)) return 1;
     return nd >= k ? -1 : 0;
   };
-  const bool rowk = rk_eligible(k);
-  // k <= 4 on a hierarchy with a separate finest prolongation: the V-cycle's last pass folds
-  // gamma = R^T Z, T = Q^T Z and the norms of R, one launch folds those partials and solves for beta
-  // (writing the norms and the deflation count to pinned host memory), and the Gram of the SpMM pass
-  // is folded and solved for alpha in one launch: 12 launches per iteration instead of 20.  The
-  // update is split: R -= Q alpha feeds the V-cycle, and X += P alpha joins the direction update
-  // P = Z + P beta after it, in one pass that reads the old P once for both.
-  const bool fused = rowk && mg_fusable(ctx, op, k);
   CgTail tail_sg, tail_up;
   if (fused) {
     tail_sg.counter = ctx->tail_counter(0);

@@ -195,6 +195,21 @@ __device__ __forceinline__ void st_cw(T* p, const T (&v)[CW]) {
   }
 }
 
+// Streaming load of rows that are dead after this kernel (Q in the finest prolongation): marked
+// non-temporal, so they do not displace the f rows that the neighbouring planes re-read from L2.
+// (Z is not streamed this way: the direction update reads it next, from the caches.)
+template <typename T, int CW>
+__device__ __forceinline__ void ld_cw_nt(const T* p, T (&v)[CW]) {
+  if constexpr (CW == 4 && sizeof(T) == 4) {
+    typedef float f4 __attribute__((ext_vector_type(4)));
+    const f4 q = __builtin_nontemporal_load(reinterpret_cast<const f4*>(p));
+    v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
+  } else {
+#pragma unroll
+    for (int j = 0; j < CW; ++j) v[j] = __builtin_nontemporal_load(p + j);
+  }
+}
+
 // Damped Jacobi from zero: x[r] = w f[r] / dA[r], for the CW columns starting at c0.
 template <typename T, int CW>
 __device__ __forceinline__ void pre_x(const LvArgs<T>& L, const T* f, int64_t r, int c0, T (&x)[CW]) {
@@ -372,7 +387,7 @@ __global__ __launch_bounds__(256) void mg_prolong_kernel(LvArgs<T> L, Geo c, con
       st_cw<T, CW>(z + r * L.k + c0, zr);
       if constexpr (GRAM) {
         T q[CW];
-        ld_cw<T, CW>(Qm + r * CW, q);
+        ld_cw_nt<T, CW>(Qm + r * CW, q);
 #pragma unroll
         for (int i = 0; i < CW; ++i) {
 #pragma unroll
@@ -707,8 +722,9 @@ void vcycle(bkts_ctx ctx, MgHier& h, int k, double a, double b, const T* f, T* z
     // algorithmic bytes: f, the coarse x, the inverse diagonal and the 3 coupling arrays read, z
     // written (and Q read when the reductions are fused)
     const bool g = gram && l == 0;
+    const bool q_own = g && fuse->Q != static_cast<const void*>(fl);  // Q = f is read once
     ProfScope prof(ctx, l == 0 ? BKTS_K_MG_PROLONG : BKTS_K_MG_COARSE,
-                   sv * ((g ? 3.0 : 2.0) * lf.N * k + 4.0 * lf.N + 1.0 * lc.N * k));
+                   sv * ((q_own ? 3.0 : 2.0) * lf.N * k + 4.0 * lf.N + 1.0 * lc.N * k));
     if (g) {
       if (k == 4)
         prolong_fused<T, 4>(ctx, L, gc, fl, xc, zl, fuse, tag);
