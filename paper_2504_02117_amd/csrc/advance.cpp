@@ -20,10 +20,9 @@
 
 namespace bkts {
 
-void upload_window(bkts_ctx ctx, const bkts_tc_s& tc, int phase, int off, double* A1p, double* A2p, double* rsp) {
+// The window matrices of (phase, off) in physical column order: A1, A2 and the row sums of A2.
+void window_mats(const bkts_tc_s& tc, int phase, int off, double* h) {
   const int k = tc.k;
-  double* h = ctx->host_stage(2 * k * k + k);
-  ctx->sync();  // the staging buffer may still be the target of an earlier read-back
   for (int i = 0; i < k; ++i) {
     const int pi = (off + i) % k;
     double rs = 0.0;
@@ -35,6 +34,13 @@ void upload_window(bkts_ctx ctx, const bkts_tc_s& tc, int phase, int off, double
     }
     h[2 * k * k + pi] = rs;
   }
+}
+
+void upload_window(bkts_ctx ctx, const bkts_tc_s& tc, int phase, int off, double* A1p, double* A2p, double* rsp) {
+  const int k = tc.k;
+  double* h = ctx->host_stage(2 * k * k + k);
+  ctx->sync();  // the staging buffer may still be the target of an earlier read-back
+  window_mats(tc, phase, off, h);
   BKTS_HIP(hipMemcpyAsync(A1p, h, sizeof(double) * (2 * k * k + k), hipMemcpyHostToDevice, ctx->stream));
   (void)A2p;
   (void)rsp;
@@ -78,7 +84,17 @@ bkts_stepper_s::bkts_stepper_s(bkts_ctx c, bkts_op o, bkts_tc t, const double* y
   fyn.alloc(sizeof(double) * N);
   tmp.alloc(sizeof(double) * N);
   nrm.alloc(sizeof(double) * (k + 1));
-  mats.alloc(sizeof(double) * (2 * k * k + k));
+  // the window matrices of every (phase, off), uploaded once: the window shifts without a host
+  // round trip
+  {
+    const size_t per = (size_t)(2 * k * k + k);
+    std::vector<double> h(per * mi * k);
+    for (int ph = 0; ph < mi; ++ph)
+      for (int o = 0; o < k; ++o) window_mats(*tc, ph, o, h.data() + per * (ph * k + o));
+    mats.alloc(sizeof(double) * h.size());
+    BKTS_HIP(hipMemcpyAsync(mats.p, h.data(), sizeof(double) * h.size(), hipMemcpyHostToDevice, ctx->stream));
+    ctx->sync();  // h is pageable and goes out of scope
+  }
   // Algorithm 1 starts from Y = (y0, ..., y0)
   broadcast_cols(ctx, N, k, y0, Y.as<double>(), k);
   BKTS_HIP(hipMemcpyAsync(yprev.p, y0, sizeof(double) * N, hipMemcpyDeviceToDevice, ctx->stream));
@@ -178,7 +194,7 @@ bkts_status bkts_stepper_s::advance(int n_steps, const bkts_solve_opts& inner, d
       lincomb(ctx, N, lc, tmp.as<double>(), 1);
       colnorms2(ctx, BKTS_F64, N, 1, tmp.as<double>(), 1, nrmp + k);
     }
-    upload_window(ctx, *tc, phase, off, mats.as<double>(), nullptr, nullptr);
+    double* matsp = mats.as<double>() + (size_t)(2 * k * k + k) * (phase * k + off);
     const double beta = tc_beta(*tc, phase);
     // A DIRK window whose diagonal coefficients differ (a custom tableau with distinct a_ii): with a
     // column-wise inner method, each column keeps its own diagonal block M/tau + A2_jj K, the
@@ -202,10 +218,10 @@ bkts_status bkts_stepper_s::advance(int n_steps, const bkts_solve_opts& inner, d
       if (nl) {
         int cols[8];
         for (int i = 0; i < nb0 && i < 8; ++i) cols[i] = (off + i) % k;
-        double* m = mats.as<double>();
+        double* m = matsp;
         nl_residual(ctx, *nl, k, Yp, k, m, m + k * k, B0p, mi, nb0, cols, Rp, k, nrmp);
       } else {
-        window_residual(ctx, *op, *tc, phase, off, Yp, k, B0p, mi, nb0, Rp, k, nrmp, mats.as<double>());
+        window_residual(ctx, *op, *tc, phase, off, Yp, k, B0p, mi, nb0, Rp, k, nrmp, matsp);
       }
       read_vec(ctx, nrmp, k + 1, hn);
       const double rhs0 = std::sqrt(hn[k]);

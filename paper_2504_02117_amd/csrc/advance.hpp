@@ -11,7 +11,8 @@ struct bkts_stepper_s {
   bkts_op op;          // linear operator K, or the Jacobian storage of `nl`
   bkts_tc tc;
   bkts_nlop nl = nullptr;  // nonlinear problem (Newton form) or null
-  bkts::DevBuf Y, R, V, B0, fst, yprev, fyn, tmp, nrm, mats;
+  bkts::DevBuf Y, R, V, B0, fst, yprev, fyn, tmp, nrm;
+  bkts::DevBuf mats;  // window matrices (A1, A2, row sums of A2) of every (phase, off), in that order
   int off = 0;       // physical column of logical column 0
   int phase = 0;     // implicit-stage index of the front column within its step
   long accepted = 0; // accepted steps since creation
@@ -25,6 +26,7 @@ struct bkts_stepper_s {
 
 namespace bkts {
 
+void window_mats(const bkts_tc_s& tc, int phase, int off, double* h);
 void upload_window(bkts_ctx ctx, const bkts_tc_s& tc, int phase, int off, double* A1p, double* A2p, double* rsp);
 
 // Residual of the window whose logical column 0 is physical column `off` (ring layout).  `mats`

@@ -255,9 +255,10 @@ void block_pcg_mg(bkts_ctx ctx, const bkts_op_s& op, int dtype, int k, double a,
   };
   precondition();
   // Convergence is read one iteration late, as in block_cg: the norms of iteration it are copied to
-  // pinned memory behind an event while iteration it+1 is enqueued.
+  // pinned memory behind an event while iteration it+1 is enqueued.  No read-back into the staging
+  // buffer is pending here (every earlier one was waited for, and a fused solve leaves none in
+  // flight), so the first V-cycle runs on while the loop is set up.
   double* hbuf = ctx->host_stage(2 * (k + 2));
-  ctx->sync();
   hipEvent_t ev[2];
   // The kernels write the norms and the deflation count straight into coherent pinned memory, so the
   // events that pace the host need no system-scope fence (which would write back the whole L2 once
@@ -324,7 +325,10 @@ void block_pcg_mg(bkts_ctx ctx, const bkts_op_s& op, int dtype, int k, double a,
     // this iteration's X += P alpha on its own when no direction update follows
     if (fused && state != 0) rk_cg_x_update(ctx, dtype, N, k, X, P, s.alpha);
     if (state == 1) {
-      ctx->sync();  // iteration `it` is in flight; it only improves X
+      // iteration `it` is in flight and only improves X; the caller's next kernels follow it on the
+      // stream.  The fused form has no event or read-back of this iteration outstanding, so it
+      // returns at once; the other form waits for the norms it records into the staging buffer.
+      if (!fused) ctx->sync();
       st.iterations = it;
       st.converged = 1;
       return;
