@@ -267,8 +267,14 @@ bkts_status bkts_stepper_s::advance(int n_steps, const bkts_solve_opts& inner, d
       std::fill(active.begin(), active.end(), 1);
     }
     // accept the front stage (the whole front step for a fully implicit tableau)
+    bool shifted = false;  // the front slot already holds the duplicated last column
     if (tc->fully_implicit || phase == mi - 1) {
-      extract_col(ctx, N, Yp, k, (off + nacc - 1) % k, yp);
+      if (nacc == 1) {  // take the front column and duplicate the last into its slot, in one pass
+        take_and_replace_col(ctx, N, Yp, k, off, (off + k - 1) % k, yp);
+        shifted = true;
+      } else {
+        extract_col(ctx, N, Yp, k, (off + nacc - 1) % k, yp);
+      }
       ++done;
       ++accepted;
       if (y_hist)
@@ -285,7 +291,7 @@ bkts_status bkts_stepper_s::advance(int n_steps, const bkts_solve_opts& inner, d
       ++phase;
     }
     for (int i = 0; i < nacc; ++i) {  // shift: duplicate the last column
-      copy_col(ctx, N, Yp, k, (off + k - 1) % k, off);
+      if (!shifted) copy_col(ctx, N, Yp, k, (off + k - 1) % k, off);
       off = (off + 1) % k;
     }
   }

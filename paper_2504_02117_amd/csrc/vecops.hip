@@ -24,6 +24,15 @@ __global__ void extract_col_kernel(int64_t N, const double* Y, int ld, int c, do
   if (r < N) out[r] = Y[r * ld + c];
 }
 
+// out = column c of Y, then column c = column src (one pass over the rows).
+__global__ void take_and_replace_col_kernel(int64_t N, double* Y, int ld, int c, int src, double* out) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= N) return;
+  const double v = Y[r * ld + c], w = Y[r * ld + src];
+  out[r] = v;
+  Y[r * ld + c] = w;
+}
+
 __global__ void lincomb_kernel(int64_t N, LinComb lc, double* out, int ldo) {
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= N) return;
@@ -95,6 +104,13 @@ void copy_col(bkts_ctx ctx, int64_t N, double* Y, int ld, int src, int dst) {
   if (N == 0 || src == dst) return;
   ProfScope prof(ctx, BKTS_K_OTHER, 16.0 * N);
   launch(ctx, copy_col_kernel, grid1(N), dim3(256), 0, N, Y, ld, src, dst);
+  BKTS_HIP(hipGetLastError());
+}
+
+void take_and_replace_col(bkts_ctx ctx, int64_t N, double* Y, int ld, int c, int src, double* out) {
+  if (N == 0) return;
+  ProfScope prof(ctx, BKTS_K_OTHER, 32.0 * N);
+  launch(ctx, take_and_replace_col_kernel, grid1(N), dim3(256), 0, N, Y, ld, c, src, out);
   BKTS_HIP(hipGetLastError());
 }
 

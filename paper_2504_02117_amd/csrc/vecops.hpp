@@ -23,6 +23,8 @@ struct LinComb {
 void broadcast_cols(bkts_ctx ctx, int64_t N, int k, const double* y, double* Y, int ld);
 void copy_col(bkts_ctx ctx, int64_t N, double* Y, int ld, int src, int dst);
 void extract_col(bkts_ctx ctx, int64_t N, const double* Y, int ld, int c, double* out);
+// out = column c of Y; then column c = column src
+void take_and_replace_col(bkts_ctx ctx, int64_t N, double* Y, int ld, int c, int src, double* out);
 void lincomb(bkts_ctx ctx, int64_t N, const LinComb& lc, double* out, int ldo);
 void axpby(bkts_ctx ctx, int64_t n, double a, const double* x, double b, double* y);  // y = a x + b y
 // Y = diag(dinv) X for N x k contiguous blocks of type dtype (dinv null: copy)
