@@ -445,12 +445,14 @@ def run_nonlinear(torch, bkts, ctx, a):
 
     from paper_2504_02117_amd import inputs
 
-    def form(n, k, precision, steps, warmup, profile, tol, hist=False):
+    def form(n, k, precision, steps, warmup, profile, tol, hist=False, precond=None):
         nl = bkts.bkts_nlop_create(ctx, n, dcoef=(1, 0, 1, 0), rcoef=(0, 0, 0, -1))
         tc = bkts.bkts_tc_create(ctx, bkts.BKTS_SDIRK2, k, 1e-4)
         y0 = torch.from_numpy(inputs.smooth_random(n, 0)).cuda()
         st = bkts.bkts_nl_stepper_create(ctx, nl, tc, y0)
         inner = bkts.solve_opts(krylov=bkts.BKTS_BICGSTAB, precision=precision, rtol=tol, inner_rtol=tol, maxit=20000)
+        if precond is not None:
+            inner.precond = precond
         N = n[0] * n[1]
         try:
             if warmup:
@@ -483,6 +485,12 @@ def run_nonlinear(torch, bkts, ctx, a):
     best = max(plains, key=lambda t: plains[t]["value"])
     pl = plains[best]
     log(f"  plain k=1 FP64: " + ", ".join(f"inner {t:g}: {v['value']:.4g}" for t, v in plains.items()))
+    # BiCGStab preconditioned by the V-cycle of each Jacobian's symmetric part
+    MG = bkts.BKTS_PREC_MG
+    mg_k4 = form(n, 4, F32, a.nl_steps, 2, False, a.nl_inner_rtol, precond=MG)
+    mg_plain = form(n, 1, F64, max(2, a.nl_steps // 2), 1, False, a.nl_inner_rtol, precond=MG)
+    log(f"  multigrid: block k=4 {mg_k4['value']:.4g}, plain k=1 FP64 {mg_plain['value']:.4g} DOF*steps/s "
+        f"(krylov {mg_k4['info'].krylov_iterations} and {mg_plain['info'].krylov_iterations})")
     # parity of the same configuration at 256^2 against the oracle's per-stage Newton
     from oracle import fv as ofv, stepping
     m = (256, 256)
@@ -500,12 +508,16 @@ def run_nonlinear(torch, bkts, ctx, a):
                           "norms": "coldots_kernel (BiCGStab column dots) and colnorm_kernel"}.get(dom, roof["kernel"])
     return {"workload": f"nonlinear diffusion-reaction {a.nl_n}^2 FV, D(u)=1+u^2, r(u)=-u^3, zero flux, SDIRK2 "
                         f"tau=1e-4, {a.nl_k} columns ({a.nl_k // 2} steps x 2 stages), Newton to 1e-8, per-column "
-                        f"(vectorized) BiCGStab inner {a.nl_inner_rtol:g} in FP32, Jacobi, seeded smooth u0 in [0,1]",
+                        f"(vectorized) BiCGStab inner {a.nl_inner_rtol:g} in FP32, Jacobi (multigrid: the V-cycle of the "
+                        f"symmetric part of each Newton Jacobian), seeded smooth u0 in [0,1]",
             "value": blk["value"], "unit": "DOF*timesteps/s", "ms_per_step": 1e3 * blk["seconds"] / a.nl_steps,
             "outer_iterations": blk["info"].outer_iterations, "krylov_iterations": blk["info"].krylov_iterations,
             "paper_inner_1e-5": {"value": paper["value"], "outer_iterations": paper["info"].outer_iterations,
                                  "krylov_iterations": paper["info"].krylov_iterations},
             "k4": {"value": narrow["value"], "outer_iterations": narrow["info"].outer_iterations},
+            "multigrid": {"k4": mg_k4["value"], "plain": mg_plain["value"],
+                          "krylov_iterations": {"k4": mg_k4["info"].krylov_iterations,
+                                                "plain": mg_plain["info"].krylov_iterations}},
             "plain": {"value": pl["value"], "config": f"k=1 (stage by stage), FP64 BiCGStab, inner {best:g} (the "
                                                       f"faster of 1e-5 and {a.nl_inner_rtol:g}), outer 1e-8",
                       "all": {f"{t:g}": v["value"] for t, v in plains.items()}},
@@ -664,13 +676,15 @@ def run_richards(torch, bkts, ctx, a):
         y0 = np.ascontiguousarray(np.broadcast_to(-z[:, None, None], inputs.field_shape(n)).ravel())
         return ks, y0
 
-    def form(n, ks, y0, k, krylov, precision, steps, warmup, profile, hist=False):
+    def form(n, ks, y0, k, krylov, precision, steps, warmup, profile, hist=False, precond=None):
         nl = bkts.bkts_richards_create(ctx, n, ks, top=bkts.BKTS_RI_DIRICHLET, top_value=g,
                                        bottom=bkts.BKTS_RI_FREE_DRAINAGE)
         tc = bkts.bkts_tc_create(ctx, bkts.BKTS_IE, k, tau)
         st = bkts.bkts_nl_stepper_create(ctx, nl, tc, torch.from_numpy(y0).cuda())
         inner = bkts.solve_opts(krylov=krylov, precision=precision, rtol=a.ri_inner_rtol,
                                 inner_rtol=a.ri_inner_rtol, maxit=4000, restart=30)
+        if precond is not None:
+            inner.precond = precond
         N = n[0] * n[1] * n[2]
         t_start = time.perf_counter()
 
@@ -698,12 +712,16 @@ def run_richards(torch, bkts, ctx, a):
     F32, F64 = bkts.BKTS_PRECISION_F32_REFINE, bkts.BKTS_PRECISION_F64
     n = (a.ri_n,) * 3
     ks, y0 = setup(n, 8.0)
+    MG = bkts.BKTS_PREC_MG
     res = {}
-    for name, k, kry, prec in (("block_gmres", a.ri_k, GM, F32), ("block_bicgstab", a.ri_k, BI, F32),
-                               ("block_bicgstab_k4", 4, BI, F32),  # the width the paper finds best
-                               ("plain_gmres", 1, GM, F64), ("plain_bicgstab", 1, BI, F64)):
+    # Jacobi forms, then BiCGStab preconditioned by the V-cycle of the Jacobian's symmetric part
+    for name, k, kry, prec, pc in (("block_gmres", a.ri_k, GM, F32, None), ("block_bicgstab", a.ri_k, BI, F32, None),
+                                   ("block_bicgstab_k4", 4, BI, F32, None),  # the width the paper finds best
+                                   ("plain_gmres", 1, GM, F64, None), ("plain_bicgstab", 1, BI, F64, None),
+                                   ("block_bicgstab_mg", a.ri_k, BI, F32, MG), ("block_bicgstab_k4_mg", 4, BI, F32, MG),
+                                   ("plain_bicgstab_mg", 1, BI, F64, MG)):
         log(f"Richards leg {n}: {name} k={k}, inner {a.ri_inner_rtol:g}, {a.ri_steps} steps")
-        r = form(n, ks, y0, k, kry, prec, a.ri_steps, 1, True)
+        r = form(n, ks, y0, k, kry, prec, a.ri_steps, 1, True, precond=pc)
         log(f"  {r['value']:.4g} DOF*steps/s, outer={r['info'].outer_iterations} "
             f"krylov={r['info'].krylov_iterations}")
         res[name] = r
@@ -728,7 +746,8 @@ def run_richards(torch, bkts, ctx, a):
     return {"workload": f"Richards' equation {a.ri_n}^3 FV, van Genuchten alpha=2 n=2 theta_r=0.05 theta_s=0.4, "
                         f"lognormal Ks (log-std 1.5, corr. 8 cells), psi0=-z, Dirichlet psi=-0.3 on top, free "
                         f"drainage below, implicit Euler tau=1e-3, {a.ri_k} columns, Newton to 1e-8, block GMRES(30) "
-                        f"inner {a.ri_inner_rtol:g} in FP32 with FP64 residuals, Jacobi",
+                        f"inner {a.ri_inner_rtol:g} in FP32 with FP64 residuals, Jacobi; the *_mg forms: BiCGStab preconditioned "
+                        f"by the multigrid V-cycle of the symmetric part of each Newton Jacobian",
             "value": blk["value"], "unit": "DOF*timesteps/s", "ms_per_step": 1e3 * blk["seconds"] / a.ri_steps,
             "forms": {kk: {"value": v["value"], "outer_iterations": v["info"].outer_iterations,
                            "krylov_iterations": v["info"].krylov_iterations,
@@ -736,6 +755,8 @@ def run_richards(torch, bkts, ctx, a):
                                        for c, x in v["kernels"].items()}} for kk, v in res.items()},
             "fastest_form": best,
             "speedup_vs_plain": blk["value"] / max(res["plain_gmres"]["value"], res["plain_bicgstab"]["value"]),
+            "best_block_vs_best_plain": max(v["value"] for kk, v in res.items() if kk.startswith("block"))
+            / max(v["value"] for kk, v in res.items() if kk.startswith("plain")),
             "oracle_max_rel_err_16x16x20": err, "roofline": roof,
             "kernels": {kk: {"avg_us": vv["avg_us"], "GBps": vv["GBps"]} for kk, vv in blk["kernels"].items()}}
 
@@ -827,6 +848,8 @@ def compact_line(out, full_path):
         nl = out["nonlinear"]
         legs["nonlinear_1024sq_k16"] = {"value": nl["value"], "k4": nl["k4"]["value"], "plain": nl["plain"]["value"],
                                         "oracle_err_256sq": nl["oracle_max_rel_err_256"]}
+        if "multigrid" in nl:
+            legs["nonlinear_1024sq_k16"].update(k4_mg=nl["multigrid"]["k4"], plain_mg=nl["multigrid"]["plain"])
     if out.get("richards"):
         ri = out["richards"]
         legs["richards_96cubed_k16"] = {f: v["value"] for f, v in ri["forms"].items()}

@@ -160,6 +160,11 @@ struct bkts_op_s {
   bkts::DevBuf st_coef, st_coef32;
   // Galerkin multigrid hierarchy of K and the mass (built on first use by a multigrid solve)
   mutable std::shared_ptr<bkts::MgHier> mg;
+  // A Newton Jacobian (CSR on the stencil sparsity, not symmetric) keeps the stencil form of its
+  // symmetric part (J + J^T) / 2 here, the operator BKTS_PREC_MG builds its hierarchy from; stale
+  // once the Jacobian's values change, rebuilt on the next multigrid solve.
+  mutable std::shared_ptr<bkts_op_s> mg_sym;
+  mutable bool mg_sym_stale = true;
 };
 
 // Nonlinear FV operator (nonlinear.hip).
@@ -272,6 +277,15 @@ void mg_vcycle(bkts_ctx ctx, const bkts_op_s& op, int dtype, int k, double a, do
 // Whether a V-cycle of width k on this operator has a separate finest prolongation that can fold the
 // block-CG reductions (builds the hierarchy on first use).
 bool mg_fusable(bkts_ctx ctx, const bkts_op_s& op, int k);
+// Recompute the hierarchy of an operator whose stencil values changed (no-op before its first use).
+void mg_refresh(bkts_ctx ctx, const bkts_op_s& op);
+// The operator a multigrid preconditioner for `op` is built from: op itself in the stencil form,
+// the stencil form of the symmetric part of a Newton Jacobian (refreshed when stale), else null.
+const bkts_op_s* mg_source(bkts_ctx ctx, const bkts_op_s& op);
+// The empty stencil-form holder of the symmetric part of J (grid operators only, else null), and its
+// refresh from J's current CSR values: diagonal J_rr, couplings (J[r, r+s] + J[r+s, r]) / 2.
+std::shared_ptr<bkts_op_s> sym_stencil_create(const bkts_op_s& J);
+void sym_stencil_refresh(bkts_ctx ctx, const bkts_op_s& J, bkts_op_s& S);
 
 // ---- nonlinear operator (nonlinear.hip)
 bkts_nlop nlop_create(bkts_ctx ctx, const bkts_grid* grid, const bkts_nl_coeffs* c);

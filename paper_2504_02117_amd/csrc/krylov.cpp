@@ -387,7 +387,7 @@ static void krylov_run(bkts_ctx ctx, const bkts_op_s& op, const bkts_solve_opts&
   const bool jacobi = o.precond == BKTS_PREC_JACOBI;
   BKTS_REQUIRE(!cop || o.krylov == BKTS_BICGSTAB, "per-column operators need the vectorized BiCGStab");
   BKTS_REQUIRE(o.precond >= BKTS_PREC_NONE && o.precond <= BKTS_PREC_MG, "unknown preconditioner %d", o.precond);
-  BKTS_REQUIRE(o.precond != BKTS_PREC_MG || o.krylov == BKTS_CG, "multigrid preconditions block CG only");
+  BKTS_REQUIRE(o.precond != BKTS_PREC_MG || o.krylov != BKTS_GMRES, "multigrid preconditions block CG and BiCGStab");
   switch (o.krylov) {
     case BKTS_CG:
       if (o.precond == BKTS_PREC_MG)
@@ -396,7 +396,16 @@ static void krylov_run(bkts_ctx ctx, const bkts_op_s& op, const bkts_solve_opts&
         block_cg(ctx, op, dtype, k, a, b, B, X, x0_zero, jacobi, rtol, maxit, st);
       break;
     case BKTS_GMRES: block_gmres(ctx, op, dtype, k, a, b, B, X, x0_zero, jacobi, rtol, o.restart, maxit, st); break;
-    case BKTS_BICGSTAB: block_bicgstab(ctx, op, dtype, k, a, b, B, X, x0_zero, jacobi, rtol, maxit, st, cop); break;
+    case BKTS_BICGSTAB: {
+      const bkts_op_s* mop = nullptr;
+      if (o.precond == BKTS_PREC_MG) {
+        BKTS_REQUIRE(!cop, "multigrid does not precondition per-column operators");
+        mop = mg_source(ctx, op);
+        BKTS_REQUIRE(mop, "multigrid needs the stencil form (BKTS_FMT_STENCIL) or a Newton Jacobian on a grid");
+      }
+      block_bicgstab(ctx, op, dtype, k, a, b, B, X, x0_zero, jacobi, rtol, maxit, st, cop, mop);
+      break;
+    }
     default: throw Error{BKTS_EINVAL, fmt("unknown Krylov method %d", o.krylov)};
   }
 }

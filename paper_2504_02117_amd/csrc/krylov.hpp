@@ -48,9 +48,11 @@ struct GmresOps {
 void gmres_core(bkts_ctx ctx, int dtype, int64_t N, int k, const GmresOps& ops, const void* B, void* X,
                 bool x0_zero, double rtol, int restart, int maxit, KrylovStats& st);
 // cop != nullptr: column j's operator is cop->a[j] I + cop->b[j] K (the Jacobi scaling stays that
-// of a I + b K)
+// of a I + b K).  mgop != nullptr: right-preconditioned by one multigrid V-cycle for a I + b K_mg,
+// with K_mg the stencil form of mgop (the operator itself, or the symmetric part of a Jacobian).
 void block_bicgstab(bkts_ctx ctx, const bkts_op_s& op, int dtype, int k, double a, double b, const void* B, void* X,
-                    bool x0_zero, bool jacobi, double rtol, int maxit, KrylovStats& st, const ColOp* cop = nullptr);
+                    bool x0_zero, bool jacobi, double rtol, int maxit, KrylovStats& st, const ColOp* cop = nullptr,
+                    const bkts_op_s* mgop = nullptr);
 
 // What a caller already knows about a solve's right-hand side: its squared column norms (host; only
 // with a zero initial guess), and that it is scratch the solver may overwrite.

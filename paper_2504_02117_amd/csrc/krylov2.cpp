@@ -212,7 +212,8 @@ void block_gmres(bkts_ctx ctx, const bkts_op_s& op, int dtype, int k, double a, 
 // vectorized solver).  Coupling the columns through k x k solves (the block form) needs a
 // well-conditioned residual block at every step, which FP32 windows of Algorithm 1 do not keep.
 void block_bicgstab(bkts_ctx ctx, const bkts_op_s& op, int dtype, int k, double a, double b, const void* B, void* X,
-                   bool x0_zero, bool jacobi, double rtol, int maxit, KrylovStats& st, const ColOp* cop) {
+                   bool x0_zero, bool jacobi, double rtol, int maxit, KrylovStats& st, const ColOp* cop,
+                   const bkts_op_s* mgop) {
   const int64_t N = op.N;
   const size_t es = esize(dtype);
   const size_t blk = es * N * k;
@@ -232,11 +233,16 @@ void block_bicgstab(bkts_ctx ctx, const bkts_op_s& op, int dtype, int k, double 
   double *al = sm, *be = al + kk, *W = be + kk;
   double *m1 = W + kk, *mr = m1 + k, *ts = mr + k, *tt = ts + k, *m3 = tt + k, *nrmd = m3 + k;
   const double* dinv = nullptr;
-  if (jacobi) {
+  if (jacobi && !mgop) {
     double* d = ctx->ws.get<double>("bs_dinv", N);
     jacobi_inverse(ctx, op, a, b, d);
     dinv = d;
   }
+  // right preconditioner M^-1: the Jacobi scaling (fused into the update kernels), or one V-cycle of
+  // the multigrid built from mgop for a I + b K_mg, applied after the kernel has formed the vector
+  auto precondition = [&](const void* in, void* out) {
+    if (mgop) mg_vcycle(ctx, *mgop, dtype, k, a, b, in, out);
+  };
   // out = A in, column by column: one SpMM for K in, then each column's own a_j, b_j
   auto apply = [&](const void* in, void* out) {
     if (!cop) return spmm(ctx, op, dtype, k, 0.0, nullptr, k, a, in, k, b, out, k);
@@ -262,7 +268,10 @@ void block_bicgstab(bkts_ctx ctx, const bkts_op_s& op, int dtype, int k, double 
     st.converged = 1;
     return;
   }
-  scale_rows(ctx, dtype, N, k, dinv, P, Ph);
+  if (mgop)
+    precondition(P, Ph);
+  else
+    scale_rows(ctx, dtype, N, k, dinv, P, Ph);
   // Convergence is read one iteration late: the norms of iteration it land in pinned host memory
   // behind an event, and the host reads them after it has enqueued the residual half of iteration
   // it + 1, before that iteration's X update, so the iterates are those of a synchronous check.
@@ -303,6 +312,7 @@ void block_bicgstab(bkts_ctx ctx, const bkts_op_s& op, int dtype, int k, double 
     }
     small_diag_ratio(ctx, k, mr, m1, 1.0, al);           // alpha_j = (rt_j^T r_j) / (rt_j^T v_j)
     bicg_s_step(ctx, dtype, N, k, R, V, al, dinv, Sb, Sh);  // S = R - V alpha, Sh = D^-1 S
+    precondition(Sb, Sh);
     apply(Sh, T);  // T = A D^-1 S
     {
       const void* xs[3] = {T, T, Rt};
@@ -325,6 +335,7 @@ void block_bicgstab(bkts_ctx ctx, const bkts_op_s& op, int dtype, int k, double 
     bicg_x_step(ctx, dtype, N, k, Ph, Sh, al, W, nrmd, X);  // X += D^-1 P alpha + D^-1 S omega
     small_diag_ratio(ctx, k, m3, m1, -1.0, be);  // beta_j = -(rt_j^T t_j) / (rt_j^T v_j)
     bicg_p_step(ctx, dtype, N, k, R, V, W, be, dinv, P, Ph);  // P = R + (P - V omega) beta, Ph = D^-1 P
+    precondition(P, Ph);
   }
   finish(maxit >= 1 ? check(maxit) : 0);
 }

@@ -30,6 +30,7 @@
 // elements' couplings in registers across the sweeps.  The finest
 // prolongation can also fold the block-CG reductions that follow the preconditioner
 // (gamma = R^T Z, T = Q^T Z and the column norms of R), since it already holds R and Z per row.
+#include <limits>
 #include <memory>
 #include <vector>
 
@@ -788,6 +789,107 @@ static MgHier* mg_build(bkts_op op) {
   ctx->sync();
   BKTS_REQUIRE(h->lv.back().N <= kCoarsestMax, "multigrid: coarsest level too large");
   return h.release();
+}
+
+// Level 0 and the Galerkin products of every coarser level from the operator's current stencil
+// values, into the buffers of an existing hierarchy; the inverse diagonals follow on the next cycle.
+void mg_refresh(bkts_ctx ctx, const bkts_op_s& op) {
+  if (!op.mg) return;
+  MgHier& h = *op.mg;
+  MgLevel& l0 = h.lv[0];
+  int sel[3] = {-1, -1, -1};
+  int64_t s = 1;
+  for (int d = 0; d < 3; ++d) {
+    if (l0.n[d] >= 2)
+      for (int q = 0; q < op.st_na; ++q)
+        if (op.st_off[q] == s) sel[d] = q;
+    s *= l0.n[d];
+  }
+  launch(ctx, mg_level0, dim3((unsigned)((l0.N + 255) / 256)), dim3(256), 0, l0.N, op.st_na, op.st_coef.as<double>(),
+         sel[0], sel[1], sel[2], l0.c64.as<double>());
+  for (size_t l = 0; l + 1 < h.lv.size(); ++l) {
+    const MgLevel& f = h.lv[l];
+    MgLevel& c = h.lv[l + 1];
+    launch(ctx, mg_coarsen, dim3((unsigned)((c.N + 255) / 256)), dim3(256), 0, geo_of(f), geo_of(c),
+           f.c64.as<double>(), c.c64.as<double>());
+  }
+  for (auto& l : h.lv)
+    launch(ctx, mg_to_f32, dim3((unsigned)((5 * l.N + 255) / 256)), dim3(256), 0, 5 * l.N, l.c64.as<double>(),
+           l.c32.as<float>());
+  BKTS_HIP(hipGetLastError());
+  h.a = h.b = std::numeric_limits<double>::quiet_NaN();  // compares unequal: the next cycle recomputes
+}
+
+namespace {
+
+// Stencil form of (J + J^T) / 2 from J's CSR rows (structurally symmetric stencil sparsity): the
+// diagonal, then for each offset s the coupling to r + s, zero where r + s is not a neighbour.
+__global__ void sym_stencil_kernel(int64_t N, int na, int64_t s0, int64_t s1, int64_t s2,
+                                   const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
+                                   const double* __restrict__ val, double* __restrict__ st) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= N) return;
+  const int64_t so[3] = {s0, s1, s2};
+  double dg = 0.0, up[3] = {0.0, 0.0, 0.0};
+  bool has[3] = {false, false, false};
+  for (int32_t p = rowptr[r]; p < rowptr[r + 1]; ++p) {
+    const int64_t c = col[p];
+    if (c == r) dg = val[p];
+    for (int q = 0; q < na; ++q)
+      if (c == r + so[q]) {
+        up[q] = val[p];
+        has[q] = true;
+      }
+  }
+  st[r] = dg;
+  for (int q = 0; q < na; ++q) {
+    double lo = 0.0;
+    if (has[q]) {
+      const int64_t rq = r + so[q];
+      for (int32_t p = rowptr[rq]; p < rowptr[rq + 1]; ++p)
+        if (col[p] == r) lo = val[p];
+    }
+    st[(int64_t)(1 + q) * N + r] = has[q] ? 0.5 * (up[q] + lo) : 0.0;
+  }
+}
+
+}  // namespace
+
+std::shared_ptr<bkts_op_s> sym_stencil_create(const bkts_op_s& J) {
+  if (J.grid.dim < 1) return nullptr;
+  auto S = std::make_shared<bkts_op_s>();
+  S->ctx = J.ctx;
+  S->N = J.N;
+  S->grid = J.grid;
+  S->format = BKTS_FMT_STENCIL;
+  int64_t stride = 1;
+  for (int d = 0; d < J.grid.dim; ++d) {
+    if (J.grid.n[d] >= 2) S->st_off[S->st_na++] = stride;
+    stride *= J.grid.n[d];
+  }
+  if (S->st_na == 0) return nullptr;
+  S->st_coef.alloc(sizeof(double) * (1 + S->st_na) * J.N);
+  return S;
+}
+
+void sym_stencil_refresh(bkts_ctx ctx, const bkts_op_s& J, bkts_op_s& S) {
+  BKTS_REQUIRE(S.N == J.N && S.st_na > 0, "symmetric stencil form does not match its Jacobian");
+  ProfScope prof(ctx, BKTS_K_OTHER, 12.0 * J.nnz * 2 + 8.0 * (1 + S.st_na) * J.N);
+  launch(ctx, sym_stencil_kernel, dim3((unsigned)((J.N + 255) / 256)), dim3(256), 0, J.N, S.st_na, S.st_off[0],
+         S.st_off[1], S.st_off[2], J.rowptr.as<int32_t>(), J.col.as<int32_t>(), J.val.as<double>(),
+         S.st_coef.as<double>());
+  BKTS_HIP(hipGetLastError());
+}
+
+const bkts_op_s* mg_source(bkts_ctx ctx, const bkts_op_s& op) {
+  if (op.st_na > 0) return &op;
+  if (!op.mg_sym) return nullptr;
+  if (op.mg_sym_stale) {
+    sym_stencil_refresh(ctx, op, *op.mg_sym);
+    mg_refresh(ctx, *op.mg_sym);
+    op.mg_sym_stale = false;
+  }
+  return op.mg_sym.get();
 }
 
 bool mg_fusable(bkts_ctx ctx, const bkts_op_s& op, int k) {

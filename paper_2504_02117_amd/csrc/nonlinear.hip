@@ -470,6 +470,7 @@ bkts_nlop nlop_create(bkts_ctx ctx, const bkts_grid* grid, const bkts_nl_coeffs*
       lc.bc_type[f] = c->bc_type[f];
     }
     nl->jac = fv_assemble(ctx, grid, &lc, BKTS_FMT_SELL);  // the stencil sparsity
+    nl->jac->mg_sym = sym_stencil_create(*nl->jac);          // for BKTS_PREC_MG
   } catch (...) {
     delete nl;
     throw;
@@ -544,6 +545,7 @@ bkts_nlop richards_create(bkts_ctx ctx, const bkts_grid* grid, const double* ks,
     lc.kappa_const = 1.0;
     for (int f = 0; f < 6; ++f) lc.bc_type[f] = BKTS_BC_NEUMANN;
     nl->jac = fv_assemble(ctx, grid, &lc, BKTS_FMT_SELL);  // the stencil sparsity
+    nl->jac->mg_sym = sym_stencil_create(*nl->jac);          // for BKTS_PREC_MG
   } catch (...) {
     delete nl;
     throw;
@@ -560,6 +562,7 @@ void nl_jacobian(bkts_ctx ctx, bkts_nlop_s& nl, const double* u, int ldu, double
     BKTS_HIP(hipGetLastError());
   }
   op_refresh_values(J);
+  J->mg_sym_stale = true;
 }
 
 void nl_residual(bkts_ctx ctx, const bkts_nlop_s& nl, int k, const double* Y, int ldy, const double* A1,

@@ -40,7 +40,8 @@ def _record():
                          "sample": "3 implicit-Euler steps of the 128^3 workload, Jacobi-PCG to a 1e-8 relative "
                                    "residual per step, 5.0 s (plain C oracle, OpenMP, 16 threads)",
                          "one_core": {"value": 4e5}, "cpu_model": "AMD EPYC 9575F 64-Core Processor"},
-        "nonlinear": {"value": 4e7, "k4": {"value": 1.1e8}, "plain": {"value": 5e7}, "oracle_max_rel_err_256": 7e-9},
+        "nonlinear": {"value": 4e7, "k4": {"value": 1.1e8}, "plain": {"value": 5e7}, "oracle_max_rel_err_256": 7e-9,
+                      "multigrid": {"k4": 2.6e8, "plain": 7.6e7}},
         "richards": {"forms": {f: {"value": 1e6} for f in ("block_gmres", "block_bicgstab", "plain_gmres",
                                                             "plain_bicgstab")},
                      "oracle_max_rel_err_16x16x20": 5e-9},

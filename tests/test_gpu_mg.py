@@ -89,6 +89,33 @@ def test_mg_block_solve_matches_direct(env, gi, k, precision):
         bkts.bkts_op_destroy(op)
 
 
+@pytest.mark.parametrize("gi", range(len(GRIDS)))
+@pytest.mark.parametrize("k", [1, 4])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_mg_bicgstab_block_solve_matches_direct(env, gi, k, precision):
+    """BiCGStab right-preconditioned by the V-cycle reaches the direct solution."""
+    torch, bkts, ctx = env
+    n, bc = GRIDS[gi]
+    say(f"mg bicgstab block solve n={n} k={k} precision={precision}")
+    kap = inputs.lognormal_field(n, 0.0, 2.0, 2.0, 4) if len(n) > 1 else np.exp(np.linspace(-3, 3, n[0]))
+    op, K, _ = stencil_op(env, n, kap, bc)
+    try:
+        N = K.shape[0]
+        tau, beta = 1e-3, 0.7
+        B = inputs.random_block(N, k, 60 + k)
+        want = blockops.block_solve(K, 1.0 / tau, beta, B)
+        Xd = torch.zeros((N, k), dtype=torch.float64, device="cuda")
+        opts = bkts.solve_opts(krylov=bkts.BKTS_BICGSTAB, precond=bkts.BKTS_PREC_MG, precision=precision,
+                               rtol=1e-11, inner_rtol=1e-4)
+        info = bkts.bkts_block_solve(ctx, op, 1.0 / tau, beta, dev(torch, B), Xd, opts)
+        got = Xd.cpu().numpy()
+        assert info.converged == 1
+        err = np.linalg.norm(got - want, axis=0) / np.linalg.norm(want, axis=0)
+        assert err.max() < 1e-9, err.max()
+    finally:
+        bkts.bkts_op_destroy(op)
+
+
 @pytest.mark.parametrize("k", [1, 4])
 def test_mg_needs_fewer_iterations_than_jacobi(env, k):
     """Lognormal coefficient (log-std 2) on 40^3 with a weak mass term: the V-cycle must cut the
@@ -152,7 +179,7 @@ def test_mg_rejections(env):
         N = K.shape[0]
         B = dev(torch, inputs.random_block(N, 2, 1))
         X = torch.zeros((N, 2), dtype=torch.float64, device="cuda")
-        with pytest.raises(bkts.BktsError) as e:  # multigrid preconditions block CG only
+        with pytest.raises(bkts.BktsError) as e:  # multigrid preconditions block CG and BiCGStab only
             bkts.bkts_block_solve(ctx, op, 1.0, 1.0, B, X, bkts.solve_opts(krylov=bkts.BKTS_GMRES,
                                                                             precond=bkts.BKTS_PREC_MG))
         assert e.value.status == bkts.BKTS_EINVAL

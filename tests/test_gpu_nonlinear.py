@@ -153,14 +153,15 @@ def test_nl_residual_matches_oracle(env, k, phase):
         bkts.bkts_nlop_destroy(nl)
 
 
-@pytest.mark.parametrize("krylov", [1, 2])
+@pytest.mark.parametrize("krylov,mg", [(1, False), (2, False), (2, True)])
 @pytest.mark.parametrize("precision", [0, 1])
-def test_newton_step_matches_direct(env, krylov, precision):
-    """One Newton iteration: Y - J^{-1} R(Y) with J = I/tau + a_kk Df(Y_0), J^{-1} by a direct solve."""
+def test_newton_step_matches_direct(env, krylov, mg, precision):
+    """One Newton iteration: Y - J^{-1} R(Y) with J = I/tau + a_kk Df(Y_0), J^{-1} by a direct solve
+    (mg: BiCGStab preconditioned by the V-cycle of the symmetric part of J)."""
     torch, bkts, ctx = env
     n = (48, 40)
     k, tau = 4, 5e-3
-    say(f"newton_step krylov={krylov} precision={precision}")
+    say(f"newton_step krylov={krylov} mg={mg} precision={precision}")
     nl, ref = make(env, n)
     tc = bkts.bkts_tc_create(ctx, bkts.BKTS_SDIRK2, k, tau)
     try:
@@ -176,6 +177,8 @@ def test_newton_step_matches_direct(env, krylov, precision):
         want = Y - np.column_stack([lu.solve(R[:, j]) for j in range(k)])
         Yd = dev(torch, Y)
         opts = bkts.solve_opts(krylov=krylov, precision=precision, rtol=1e-13, inner_rtol=1e-6, maxit=4000)
+        if mg:
+            opts.precond = bkts.BKTS_PREC_MG
         norms, info = bkts.bkts_newton_step(ctx, nl, tc, Yd, B0=dev(torch, B0[:, :2]), phase=0, opts=opts)
         np.testing.assert_allclose(norms, (R ** 2).sum(0), rtol=1e-11)
         got = Yd.cpu().numpy()
@@ -187,14 +190,17 @@ def test_newton_step_matches_direct(env, krylov, precision):
         bkts.bkts_nlop_destroy(nl)
 
 
-@pytest.mark.parametrize("k,krylov,precision", [(2, 2, 1), (4, 2, 1), (16, 2, 1), (4, 1, 0), (3, 2, 0)])
-def test_nl_stepper_matches_sequential_newton(env, k, krylov, precision):
+@pytest.mark.parametrize("k,krylov,precision,mg", [(2, 2, 1, False), (4, 2, 1, False), (16, 2, 1, False),
+                                                    (4, 1, 0, False), (3, 2, 0, False), (4, 2, 1, True),
+                                                    (3, 2, 0, True)])
+def test_nl_stepper_matches_sequential_newton(env, k, krylov, precision, mg):
     """Algorithm 1 in Newton form (SDIRK2, D = 1 + u^2, r = -u^3, zero flux, smooth initial data in
-    [0, 1]) against per-stage Newton with exact Jacobians and direct solves."""
+    [0, 1]) against per-stage Newton with exact Jacobians and direct solves (mg: BiCGStab
+    preconditioned by the V-cycle of the symmetric part of each Jacobian)."""
     torch, bkts, ctx = env
     n = (36, 30)
     steps, tau = 6, 2e-3
-    say(f"nl stepper k={k} krylov={krylov} precision={precision}")
+    say(f"nl stepper k={k} krylov={krylov} precision={precision} mg={mg}")
     nl, ref = make(env, n)
     tc = bkts.bkts_tc_create(ctx, bkts.BKTS_SDIRK2, k, tau)
     st = None
@@ -205,6 +211,8 @@ def test_nl_stepper_matches_sequential_newton(env, k, krylov, precision):
         st = bkts.bkts_nl_stepper_create(ctx, nl, tc, dev(torch, y0))
         hist = torch.zeros((steps, N), dtype=torch.float64, device="cuda")
         inner = bkts.solve_opts(krylov=krylov, precision=precision, rtol=1e-3, inner_rtol=1e-3, maxit=2000)
+        if mg:
+            inner.precond = bkts.BKTS_PREC_MG
         info = bkts.bkts_stepper_advance(st, steps, inner=inner, outer_rtol=1e-12, max_outer=100, y_hist=hist)
         assert info.accepted_steps == steps
         got = hist.cpu().numpy()
@@ -234,6 +242,10 @@ def test_nl_argument_errors(env):
             bkts.bkts_nl_residual(ctx, nl, tc, Y, Y)  # aliasing
         with pytest.raises(bkts.BktsError):
             bkts.bkts_nl_residual(ctx, nl, tc, Y, torch.empty_like(Y), phase=2)
+        gm = bkts.solve_opts(krylov=1, rtol=1e-6)
+        gm.precond = bkts.BKTS_PREC_MG
+        with pytest.raises(bkts.BktsError):  # multigrid preconditions block CG and BiCGStab only
+            bkts.bkts_newton_step(ctx, nl, tc, Y.clone(), phase=0, opts=gm)
     finally:
         bkts.bkts_tc_destroy(tc)
         bkts.bkts_nlop_destroy(nl)

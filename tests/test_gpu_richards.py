@@ -176,10 +176,22 @@ def test_window_residual_matches_oracle(env, k, closure):
 def test_stepper_matches_sequential_implicit_euler(env, k, krylov, precision, lin_L):
     """Infiltration into a column at hydrostatic rest (psi0 = -z) through a Dirichlet top at
     psi = 0 with free drainage below, lognormal Ks; Algorithm 1 against implicit Euler."""
+    _stepper_case(env, k, krylov, precision, lin_L, None)
+
+
+@pytest.mark.parametrize("k,precision", [(4, 1), (1, 0), (16, 1)])
+def test_stepper_multigrid_matches_sequential_implicit_euler(env, k, precision):
+    """The same infiltration with BiCGStab preconditioned by the V-cycle of the Jacobian's symmetric
+    part (rebuilt at every Newton iteration): the accepted steps are those of implicit Euler."""
+    torch, bkts, ctx = env
+    _stepper_case(env, k, 2, precision, 0.0, bkts.BKTS_PREC_MG)
+
+
+def _stepper_case(env, k, krylov, precision, lin_L, precond):
     torch, bkts, ctx = env
     n = (10, 9, 14)
     steps, tau = 8, 1e-3
-    say(f"richards stepper k={k} krylov={krylov} precision={precision} L={lin_L}")
+    say(f"richards stepper k={k} krylov={krylov} precision={precision} L={lin_L} precond={precond}")
     vg = VG
     if isinstance(lin_L, str):
         vg, lin_L = CLOSURES[lin_L], 0.0
@@ -194,6 +206,8 @@ def test_stepper_matches_sequential_implicit_euler(env, k, krylov, precision, li
         hist = torch.zeros((steps, N), dtype=torch.float64, device="cuda")
         inner = bkts.solve_opts(krylov=krylov, precision=precision, rtol=1e-3, inner_rtol=1e-3, maxit=3000,
                                 restart=30)
+        if precond is not None:
+            inner.precond = precond
         info = bkts.bkts_stepper_advance(st, steps, inner=inner, outer_rtol=1e-12, max_outer=300, y_hist=hist)
         assert info.accepted_steps == steps
         got = hist.cpu().numpy()
