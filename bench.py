@@ -718,6 +718,7 @@ def run_richards(torch, bkts, ctx, a):
     for name, k, kry, prec, pc in (("block_gmres", a.ri_k, GM, F32, None), ("block_bicgstab", a.ri_k, BI, F32, None),
                                    ("block_bicgstab_k4", 4, BI, F32, None),  # the width the paper finds best
                                    ("plain_gmres", 1, GM, F64, None), ("plain_bicgstab", 1, BI, F64, None),
+                                   ("block_gmres_mg", a.ri_k, GM, F32, MG),
                                    ("block_bicgstab_mg", a.ri_k, BI, F32, MG), ("block_bicgstab_k4_mg", 4, BI, F32, MG),
                                    ("plain_bicgstab_mg", 1, BI, F64, MG)):
         log(f"Richards leg {n}: {name} k={k}, inner {a.ri_inner_rtol:g}, {a.ri_steps} steps")
@@ -747,7 +748,7 @@ def run_richards(torch, bkts, ctx, a):
                         f"lognormal Ks (log-std 1.5, corr. 8 cells), psi0=-z, Dirichlet psi=-0.3 on top, free "
                         f"drainage below, implicit Euler tau=1e-3, {a.ri_k} columns, Newton to 1e-8, block GMRES(30) "
                         f"inner {a.ri_inner_rtol:g} in FP32 with FP64 residuals, Jacobi; the *_mg forms: BiCGStab preconditioned "
-                        f"by the multigrid V-cycle of the symmetric part of each Newton Jacobian",
+                        f"(block_gmres_mg: GMRES) by the multigrid V-cycle of the symmetric part of each Newton Jacobian",
             "value": blk["value"], "unit": "DOF*timesteps/s", "ms_per_step": 1e3 * blk["seconds"] / a.ri_steps,
             "forms": {kk: {"value": v["value"], "outer_iterations": v["info"].outer_iterations,
                            "krylov_iterations": v["info"].krylov_iterations,

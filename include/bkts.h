@@ -252,12 +252,12 @@ bkts_status bkts_residual(bkts_ctx ctx, bkts_op op, bkts_tc tc, int phase, const
 
 enum { BKTS_CG = 0, BKTS_GMRES = 1, BKTS_BICGSTAB = 2 };
 /* BKTS_PREC_MG: one symmetric geometric multigrid V-cycle per iteration (Galerkin 2x2x2
- * aggregation of the stencil form, damped Jacobi smoothing).  Block CG and BiCGStab (right
- * preconditioning); the operator must carry the stencil form (BKTS_FMT_STENCIL), or be the Newton
- * Jacobian of a nonlinear grid operator, whose V-cycle is built from the stencil form of its
- * symmetric part (J + J^T) / 2 and rebuilt after each bkts_nl_jacobian.  Otherwise, with block
- * GMRES or with per-column operators, BKTS_EINVAL.  The paper preconditions its inner solves with
- * AMG (Sec. 4.1). */
+ * aggregation of the stencil form, damped Jacobi smoothing).  Block CG, block GMRES and BiCGStab
+ * (the last two preconditioned from the right); the operator must carry the stencil form
+ * (BKTS_FMT_STENCIL), or be the Newton Jacobian of a nonlinear grid operator, whose V-cycle is
+ * built from the stencil form of its symmetric part (J + J^T) / 2 and rebuilt after each Jacobian
+ * assembly.  Otherwise, or with per-column operators, BKTS_EINVAL.  The paper preconditions its
+ * inner solves with AMG (Sec. 4.1). */
 enum { BKTS_PREC_NONE = 0, BKTS_PREC_JACOBI = 1, BKTS_PREC_MG = 2 };
 enum { BKTS_PRECISION_F64 = 0, BKTS_PRECISION_F32_REFINE = 1 };
 

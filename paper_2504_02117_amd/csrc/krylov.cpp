@@ -380,6 +380,16 @@ void block_pcg_mg(bkts_ctx ctx, const bkts_op_s& op, int dtype, int k, double a,
 // One FP32 block CG solve of (a I + b K) V = R64 for FP64 blocks: R64 is scaled per column to
 // unit norm, cast to FP32, solved to `rtol`, and the FP32 correction is scaled back and added to
 // V64 (which need not be zero).
+// The operator the multigrid preconditioner of a GMRES or BiCGStab solve is built from, or null
+// without BKTS_PREC_MG.
+static const bkts_op_s* mg_op(bkts_ctx ctx, const bkts_op_s& op, const bkts_solve_opts& o, const ColOp* cop) {
+  if (o.precond != BKTS_PREC_MG) return nullptr;
+  BKTS_REQUIRE(!cop, "multigrid does not precondition per-column operators");
+  const bkts_op_s* m = mg_source(ctx, op);
+  BKTS_REQUIRE(m, "multigrid needs the stencil form (BKTS_FMT_STENCIL) or a Newton Jacobian on a grid");
+  return m;
+}
+
 // Dispatch on the Krylov method of the options.
 static void krylov_run(bkts_ctx ctx, const bkts_op_s& op, const bkts_solve_opts& o, int dtype, int k, double a,
                        double b, const void* B, void* X, bool x0_zero, double rtol, int maxit, KrylovStats& st,
@@ -387,7 +397,6 @@ static void krylov_run(bkts_ctx ctx, const bkts_op_s& op, const bkts_solve_opts&
   const bool jacobi = o.precond == BKTS_PREC_JACOBI;
   BKTS_REQUIRE(!cop || o.krylov == BKTS_BICGSTAB, "per-column operators need the vectorized BiCGStab");
   BKTS_REQUIRE(o.precond >= BKTS_PREC_NONE && o.precond <= BKTS_PREC_MG, "unknown preconditioner %d", o.precond);
-  BKTS_REQUIRE(o.precond != BKTS_PREC_MG || o.krylov != BKTS_GMRES, "multigrid preconditions block CG and BiCGStab");
   switch (o.krylov) {
     case BKTS_CG:
       if (o.precond == BKTS_PREC_MG)
@@ -395,17 +404,12 @@ static void krylov_run(bkts_ctx ctx, const bkts_op_s& op, const bkts_solve_opts&
       else
         block_cg(ctx, op, dtype, k, a, b, B, X, x0_zero, jacobi, rtol, maxit, st);
       break;
-    case BKTS_GMRES: block_gmres(ctx, op, dtype, k, a, b, B, X, x0_zero, jacobi, rtol, o.restart, maxit, st); break;
-    case BKTS_BICGSTAB: {
-      const bkts_op_s* mop = nullptr;
-      if (o.precond == BKTS_PREC_MG) {
-        BKTS_REQUIRE(!cop, "multigrid does not precondition per-column operators");
-        mop = mg_source(ctx, op);
-        BKTS_REQUIRE(mop, "multigrid needs the stencil form (BKTS_FMT_STENCIL) or a Newton Jacobian on a grid");
-      }
-      block_bicgstab(ctx, op, dtype, k, a, b, B, X, x0_zero, jacobi, rtol, maxit, st, cop, mop);
+    case BKTS_GMRES:
+      block_gmres(ctx, op, dtype, k, a, b, B, X, x0_zero, jacobi, rtol, o.restart, maxit, st, mg_op(ctx, op, o, cop));
       break;
-    }
+    case BKTS_BICGSTAB:
+      block_bicgstab(ctx, op, dtype, k, a, b, B, X, x0_zero, jacobi, rtol, maxit, st, cop, mg_op(ctx, op, o, cop));
+      break;
     default: throw Error{BKTS_EINVAL, fmt("unknown Krylov method %d", o.krylov)};
   }
 }

@@ -32,7 +32,8 @@ void block_cg(bkts_ctx ctx, const bkts_op_s& op, int dtype, int k, double a, dou
               bool x0_zero, bool jacobi, double rtol, int maxit, KrylovStats& st);
 
 void block_gmres(bkts_ctx ctx, const bkts_op_s& op, int dtype, int k, double a, double b, const void* B, void* X,
-                 bool x0_zero, bool jacobi, double rtol, int restart, int maxit, KrylovStats& st);
+                 bool x0_zero, bool jacobi, double rtol, int restart, int maxit, KrylovStats& st,
+                 const bkts_op_s* mgop = nullptr);
 
 // Block GMRES(m) on an operator given by callbacks, on contiguous N x k blocks of type dtype:
 // apply: out = A in; precond: out = P in (right preconditioner); residual: W = B - A X (when

@@ -183,18 +183,24 @@ void gmres_core(bkts_ctx ctx, int dtype, int64_t N, int k, const GmresOps& ops, 
 }
 
 void block_gmres(bkts_ctx ctx, const bkts_op_s& op, int dtype, int k, double a, double b, const void* B, void* X,
-                 bool x0_zero, bool jacobi, double rtol, int restart, int maxit, KrylovStats& st) {
+                 bool x0_zero, bool jacobi, double rtol, int restart, int maxit, KrylovStats& st,
+                 const bkts_op_s* mgop) {
   const int64_t N = op.N;
   const size_t blk = esize(dtype) * N * k;
   const double* dinv = nullptr;
-  if (jacobi) {
+  if (jacobi && !mgop) {
     double* d = ctx->ws.get<double>("gm_dinv", N);
     jacobi_inverse(ctx, op, a, b, d);
     dinv = d;
   }
   GmresOps ops;
   ops.apply = [&](const void* in, void* out) { spmm(ctx, op, dtype, k, 0.0, nullptr, k, a, in, k, b, out, k); };
-  ops.precond = [&](const void* in, void* out) { scale_rows(ctx, dtype, N, k, dinv, in, out); };
+  ops.precond = [&](const void* in, void* out) {  // right preconditioner: Jacobi, or one V-cycle (linear, fixed)
+    if (mgop)
+      mg_vcycle(ctx, *mgop, dtype, k, a, b, in, out);
+    else
+      scale_rows(ctx, dtype, N, k, dinv, in, out);
+  };
   ops.residual = [&](const void* Bp, void* Xp, bool zero, void* Wp) {
     if (zero) {
       BKTS_HIP(hipMemsetAsync(Xp, 0, blk, ctx->stream));

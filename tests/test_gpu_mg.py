@@ -91,12 +91,15 @@ def test_mg_block_solve_matches_direct(env, gi, k, precision):
 
 @pytest.mark.parametrize("gi", range(len(GRIDS)))
 @pytest.mark.parametrize("k", [1, 4])
-@pytest.mark.parametrize("precision", [0, 1])
-def test_mg_bicgstab_block_solve_matches_direct(env, gi, k, precision):
-    """BiCGStab right-preconditioned by the V-cycle reaches the direct solution."""
+@pytest.mark.parametrize("krylov,precision", [(2, 0), (2, 1), (1, 0)])
+def test_mg_gmres_bicgstab_block_solve_matches_direct(env, gi, k, precision, krylov):
+    """Block GMRES and BiCGStab right-preconditioned by the V-cycle reach the direct solution.  (FP32
+    GMRES(m) is left out at this 1e-11 target: a restart recomputes the residual in FP32, which on
+    these operators (condition near 1e5) cannot reach the inner 1e-4; the Krylov methods that update
+    their residual recursively can, and the Newton tests cover FP32 GMRES at their tolerances.)"""
     torch, bkts, ctx = env
     n, bc = GRIDS[gi]
-    say(f"mg bicgstab block solve n={n} k={k} precision={precision}")
+    say(f"mg krylov={krylov} block solve n={n} k={k} precision={precision}")
     kap = inputs.lognormal_field(n, 0.0, 2.0, 2.0, 4) if len(n) > 1 else np.exp(np.linspace(-3, 3, n[0]))
     op, K, _ = stencil_op(env, n, kap, bc)
     try:
@@ -105,8 +108,8 @@ def test_mg_bicgstab_block_solve_matches_direct(env, gi, k, precision):
         B = inputs.random_block(N, k, 60 + k)
         want = blockops.block_solve(K, 1.0 / tau, beta, B)
         Xd = torch.zeros((N, k), dtype=torch.float64, device="cuda")
-        opts = bkts.solve_opts(krylov=bkts.BKTS_BICGSTAB, precond=bkts.BKTS_PREC_MG, precision=precision,
-                               rtol=1e-11, inner_rtol=1e-4)
+        opts = bkts.solve_opts(krylov=krylov, precond=bkts.BKTS_PREC_MG, precision=precision,
+                               rtol=1e-11, inner_rtol=1e-4, restart=30)
         info = bkts.bkts_block_solve(ctx, op, 1.0 / tau, beta, dev(torch, B), Xd, opts)
         got = Xd.cpu().numpy()
         assert info.converged == 1
@@ -179,10 +182,6 @@ def test_mg_rejections(env):
         N = K.shape[0]
         B = dev(torch, inputs.random_block(N, 2, 1))
         X = torch.zeros((N, 2), dtype=torch.float64, device="cuda")
-        with pytest.raises(bkts.BktsError) as e:  # multigrid preconditions block CG and BiCGStab only
-            bkts.bkts_block_solve(ctx, op, 1.0, 1.0, B, X, bkts.solve_opts(krylov=bkts.BKTS_GMRES,
-                                                                            precond=bkts.BKTS_PREC_MG))
-        assert e.value.status == bkts.BKTS_EINVAL
         with pytest.raises(bkts.BktsError) as e:  # the hierarchy is built from the stencil form
             bkts.bkts_block_solve(ctx, op_sell, 1.0, 1.0, B, X, bkts.solve_opts(precond=bkts.BKTS_PREC_MG))
         assert e.value.status == bkts.BKTS_EINVAL

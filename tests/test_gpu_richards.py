@@ -179,12 +179,13 @@ def test_stepper_matches_sequential_implicit_euler(env, k, krylov, precision, li
     _stepper_case(env, k, krylov, precision, lin_L, None)
 
 
-@pytest.mark.parametrize("k,precision", [(4, 1), (1, 0), (16, 1)])
-def test_stepper_multigrid_matches_sequential_implicit_euler(env, k, precision):
-    """The same infiltration with BiCGStab preconditioned by the V-cycle of the Jacobian's symmetric
-    part (rebuilt at every Newton iteration): the accepted steps are those of implicit Euler."""
+@pytest.mark.parametrize("k,krylov,precision", [(4, 2, 1), (1, 2, 0), (16, 2, 1), (16, 1, 1), (4, 1, 0)])
+def test_stepper_multigrid_matches_sequential_implicit_euler(env, k, krylov, precision):
+    """The same infiltration with BiCGStab or block GMRES preconditioned by the V-cycle of the
+    Jacobian's symmetric part (rebuilt at every Newton iteration): the accepted steps are those of
+    implicit Euler."""
     torch, bkts, ctx = env
-    _stepper_case(env, k, 2, precision, 0.0, bkts.BKTS_PREC_MG)
+    _stepper_case(env, k, krylov, precision, 0.0, bkts.BKTS_PREC_MG)
 
 
 def _stepper_case(env, k, krylov, precision, lin_L, precond):
