@@ -363,9 +363,9 @@ void rk_cg_xr_update(bkts_ctx ctx, int dtype, int64_t N, int k, void* X, const v
 // The two halves on their own: R -= Q alpha, and X += P alpha
 void rk_cg_r_update(bkts_ctx ctx, int dtype, int64_t N, int k, void* R, const void* Q, const double* alpha);
 void rk_cg_x_update(bkts_ctx ctx, int dtype, int64_t N, int k, void* X, const void* P, const double* alpha);
-// X += P alpha and P = Z + P beta in one pass (both read the old P)
+// X += P alpha and P = Z + P beta in one pass (both read the old P); x_init: X = P alpha (X not read)
 void rk_cg_xp_update(bkts_ctx ctx, int dtype, int64_t N, int k, void* X, void* P, const void* Z, const double* alpha,
-                     const double* beta);
+                     const double* beta, bool x_init = false);
 void rk_gram(bkts_ctx ctx, int dtype, int64_t N, int k, const void* X, const void* Y, double* G);
 // G1 = X1^T Y and G2 = X2^T Y in one pass (k in {1, 2, 4}, contiguous blocks)
 void rk_gram2(bkts_ctx ctx, int dtype, int64_t N, int k, const void* X1, const void* X2, const void* Y, double* G1,

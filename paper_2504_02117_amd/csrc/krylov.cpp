@@ -216,8 +216,23 @@ void block_pcg_mg(bkts_ctx ctx, const bkts_op_s& op, int dtype, int k, double a,
   void* Z = ctx->ws.get("mgcg_Z_" + tag, es * N * k);
   Small s = small_bufs(ctx, "mgcg" + tag, k);
   const double eps = cg_pivot_floor(dtype);
+  const bool rowk = rk_eligible(k);
+  // k <= 4 on a hierarchy with a separate finest prolongation: the V-cycle's last pass folds
+  // gamma = R^T Z, T = Q^T Z and the norms of R, one launch folds those partials and solves for beta
+  // (writing the norms and the deflation count to pinned host memory), and the Gram of the SpMM pass
+  // is folded and solved for alpha in one launch: 12 launches per iteration instead of 20.  The
+  // update is split: R -= Q alpha feeds the V-cycle, and X += P alpha joins the direction update
+  // P = Z + P beta after it, in one pass that reads the old P once for both.
+  const bool fused = rowk && mg_fusable(ctx, op, k);
+  // from zero, the fused form's first direction update writes X = P alpha, so X is not cleared
+  // (a return before that update clears it)
+  bool x_pending = x0_zero && fused;
+  auto clear_x = [&]() {
+    if (x_pending) BKTS_HIP(hipMemsetAsync(X, 0, es * N * k, ctx->stream));
+    x_pending = false;
+  };
   if (x0_zero) {
-    BKTS_HIP(hipMemsetAsync(X, 0, es * N * k, ctx->stream));
+    if (!fused) BKTS_HIP(hipMemsetAsync(X, 0, es * N * k, ctx->stream));
     if (!take_b) BKTS_HIP(hipMemcpyAsync(R, B, es * N * k, hipMemcpyDeviceToDevice, ctx->stream));
   } else {
     spmm(ctx, op, dtype, k, 1.0, B, k, -a, X, k, -b, R, k);
@@ -232,15 +247,10 @@ void block_pcg_mg(bkts_ctx ctx, const bkts_op_s& op, int dtype, int k, double a,
   st.iterations = 0;
   st.deflations = 0;
   st.converged = all_converged(nrm0, nrm0, rtol, &st.max_rel) ? 1 : 0;
-  if (st.converged) return;
-  const bool rowk = rk_eligible(k);
-  // k <= 4 on a hierarchy with a separate finest prolongation: the V-cycle's last pass folds
-  // gamma = R^T Z, T = Q^T Z and the norms of R, one launch folds those partials and solves for beta
-  // (writing the norms and the deflation count to pinned host memory), and the Gram of the SpMM pass
-  // is folded and solved for alpha in one launch: 12 launches per iteration instead of 20.  The
-  // update is split: R -= Q alpha feeds the V-cycle, and X += P alpha joins the direction update
-  // P = Z + P beta after it, in one pass that reads the old P once for both.
-  const bool fused = rowk && mg_fusable(ctx, op, k);
+  if (st.converged) {
+    clear_x();
+    return;
+  }
   auto precondition = [&]() {  // P = Z = M^-1 R (the cycle writes the first direction directly), gamma = R^T P
     if (fused) {  // gamma from the finest prolongation's reductions (R in Q's place; T and the norms unused)
       MgFuse fu;
@@ -356,7 +366,8 @@ void block_pcg_mg(bkts_ctx ctx, const bkts_op_s& op, int dtype, int k, double a,
       tail_up.host = hn;
       fold_solve(ctx, 1, k, k, fu.partials, fu.nslots, tail_up);  // gamma, T, nrm, then beta = -G^+ T
       BKTS_HIP(hipEventRecord(ev[slot], ctx->stream));
-      rk_cg_xp_update(ctx, dtype, N, k, X, P, Z, s.alpha, s.beta);  // X += P alpha; P = Z + P beta
+      rk_cg_xp_update(ctx, dtype, N, k, X, P, Z, s.alpha, s.beta, x_pending);  // X += P alpha; P = Z + P beta
+      x_pending = false;
       continue;
     } else {
       mg_vcycle(ctx, op, dtype, k, a, b, R, Z);
@@ -370,6 +381,7 @@ void block_pcg_mg(bkts_ctx ctx, const bkts_op_s& op, int dtype, int k, double a,
     }
     cg_pupdate(ctx, dtype, N, k, P, Z, s.beta, nullptr);
   }
+  clear_x();  // maxit < 1: no direction update ran
   if (check(maxit) == 1) {
     st.converged = 1;
     return;

@@ -383,7 +383,7 @@ __global__ __launch_bounds__(256) void rk_cg_xr_kernel(int64_t N, T* __restrict_
 template <typename T, int KP>
 __global__ __launch_bounds__(256) void rk_cg_xp_kernel(int64_t N, T* __restrict__ X, T* __restrict__ P,
                                                        const T* __restrict__ Z, const double* alpha,
-                                                       const double* beta) {
+                                                       const double* beta, int x_init) {
   double al[KP * KP], be[KP * KP];
 #pragma unroll
   for (int e = 0; e < KP * KP; ++e) {
@@ -393,7 +393,13 @@ __global__ __launch_bounds__(256) void rk_cg_xp_kernel(int64_t N, T* __restrict_
   const RowRange rr = block_rows(N);
   for (int64_t r = rr.begin + threadIdx.x; r < rr.end; r += dev::kThreads) {
     const Row<T, KP> p = ld_row<T, KP>(P + r * KP, KP);
-    Row<T, KP> x = ld_row<T, KP>(X + r * KP, KP);
+    Row<T, KP> x;
+    if (x_init) {  // the first update of a solve from zero: X = P alpha, X not read
+#pragma unroll
+      for (int c = 0; c < KP; ++c) x.v[c] = T(0);
+    } else {
+      x = ld_row<T, KP>(X + r * KP, KP);
+    }
     Row<T, KP> z = ld_row<T, KP>(Z + r * KP, KP);
 #pragma unroll
     for (int c = 0; c < KP; ++c) {
@@ -705,20 +711,20 @@ void rk_cg_x_update(bkts_ctx ctx, int dtype, int64_t N, int k, void* X, const vo
 
 template <typename T, int KP>
 static void rk_cg_xp_t(bkts_ctx ctx, int64_t N, void* X, void* P, const void* Z, const double* alpha,
-                       const double* beta) {
+                       const double* beta, bool x_init) {
   const int64_t nb = rk_grid(ctx, rk_cg_xp_kernel<T, KP>, N);
-  ProfScope prof(ctx, BKTS_K_CG_PUPDATE, 5.0 * N * KP * sizeof(T));
+  ProfScope prof(ctx, BKTS_K_CG_PUPDATE, (x_init ? 4.0 : 5.0) * N * KP * sizeof(T));
   launch(ctx, (rk_cg_xp_kernel<T, KP>), dim3(nb), dim3(256), 0, N, static_cast<T*>(X), static_cast<T*>(P),
-         static_cast<const T*>(Z), alpha, beta);
+         static_cast<const T*>(Z), alpha, beta, x_init ? 1 : 0);
   BKTS_HIP(hipGetLastError());
 }
 
 void rk_cg_xp_update(bkts_ctx ctx, int dtype, int64_t N, int k, void* X, void* P, const void* Z, const double* alpha,
-                     const double* beta) {
+                     const double* beta, bool x_init) {
   if (dtype == BKTS_F64)
-    BKTS_RK_DISPATCH(k, (rk_cg_xp_t<double, KP>(ctx, N, X, P, Z, alpha, beta)));
+    BKTS_RK_DISPATCH(k, (rk_cg_xp_t<double, KP>(ctx, N, X, P, Z, alpha, beta, x_init)));
   else
-    BKTS_RK_DISPATCH(k, (rk_cg_xp_t<float, KP>(ctx, N, X, P, Z, alpha, beta)));
+    BKTS_RK_DISPATCH(k, (rk_cg_xp_t<float, KP>(ctx, N, X, P, Z, alpha, beta, x_init)));
 }
 
 template <typename T, int KP>

@@ -230,6 +230,35 @@ def test_nl_stepper_matches_sequential_newton(env, k, krylov, precision, mg):
         bkts.bkts_nlop_destroy(nl)
 
 
+def test_nl_stepper_multigrid_is_repeatable(env):
+    """The multigrid-preconditioned Newton form reduces in a fixed order: two runs from the same
+    state give the same bits (the hierarchy of the Jacobian's symmetric part is rebuilt in place)."""
+    torch, bkts, ctx = env
+    n = (36, 30)
+    steps, tau = 4, 2e-3
+    nl, _ = make(env, n)
+    tc = bkts.bkts_tc_create(ctx, bkts.BKTS_SDIRK2, 4, tau)
+    try:
+        N = int(np.prod(n))
+        y0 = inputs.smooth_random(n, 4)
+        inner = bkts.solve_opts(krylov=2, precision=1, rtol=1e-3, inner_rtol=1e-3, maxit=2000)
+        inner.precond = bkts.BKTS_PREC_MG
+        runs = []
+        for _ in range(2):
+            st = bkts.bkts_nl_stepper_create(ctx, nl, tc, dev(torch, y0))
+            try:
+                hist = torch.zeros((steps, N), dtype=torch.float64, device="cuda")
+                info = bkts.bkts_stepper_advance(st, steps, inner=inner, outer_rtol=1e-12, max_outer=100, y_hist=hist)
+                assert info.accepted_steps == steps
+                runs.append(hist.cpu().numpy())
+            finally:
+                bkts.bkts_stepper_destroy(st)
+        np.testing.assert_array_equal(runs[0], runs[1])
+    finally:
+        bkts.bkts_tc_destroy(tc)
+        bkts.bkts_nlop_destroy(nl)
+
+
 def test_nl_argument_errors(env):
     torch, bkts, ctx = env
     with pytest.raises(bkts.BktsError):
