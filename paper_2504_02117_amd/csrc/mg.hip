@@ -322,15 +322,18 @@ __device__ __forceinline__ void prolong_row(const LvArgs<T>& L, const Geo& c, co
 // cells of one grid line), each forms its own residual, and the 8 residuals of an aggregate are
 // summed through LDS in a fixed order.  One-dimensional grid of gx * ncy * ncz strips, x fastest,
 // remapped so that each XCD takes one contiguous range of strips.
-template <typename T, int CW>
+template <typename T, int CW, bool FLAT>
 __global__ __launch_bounds__(256) void mg_restrict_kernel(LvArgs<T> L, Geo c, int gx, const T* __restrict__ f,
                                                           T* __restrict__ fc) {
   __shared__ T red[CW][256];
   const int t = threadIdx.x;
-  const int x = t & 63, y = (t >> 6) & 1, z = t >> 7;
+  // 3-D: the 64 x 2 x 2 fine cells of 32 aggregates; FLAT (one cell along z): 64 x 4 cells, the 32 x 2
+  // aggregates of two coarse rows, so no thread sits on the absent second z layer
+  const int x = t & 63, y = FLAT ? (t >> 6) : ((t >> 6) & 1), z = FLAT ? 0 : (t >> 7);
   const int64_t unit = dev::xcd_slot(blockIdx.x, gridDim.x);
   const int64_t yz = unit / gx;
-  const int X0 = (int)(unit - yz * gx) * 32, Y = (int)(yz % c.ny), Z = (int)(yz / c.ny);
+  const int X0 = (int)(unit - yz * gx) * 32;
+  const int Y = FLAT ? 2 * (int)yz : (int)(yz % c.ny), Z = FLAT ? 0 : (int)(yz / c.ny);
   const Geo& g = L.g;
   const int ix = 2 * X0 + x, iy = 2 * Y + y, iz = 2 * Z + z;
   const bool in = ix < g.nx && iy < g.ny && iz < g.nz;
@@ -343,7 +346,19 @@ __global__ __launch_bounds__(256) void mg_restrict_kernel(LvArgs<T> L, Geo c, in
 #pragma unroll
     for (int j = 0; j < CW; ++j) red[j][t] = v[j];
     __syncthreads();
-    if (t < 32 && X0 + t < c.nx) {
+    if (FLAT) {  // 64 aggregates: two coarse rows of 32, four children each, in the order of the 3-D sum
+      const int ta = t & 31, tb = t >> 5;
+      if (t < 64 && X0 + ta < c.nx && Y + tb < c.ny) {
+        const int64_t R = (X0 + ta) + c.sy * (Y + tb);
+#pragma unroll
+        for (int j = 0; j < CW; ++j) {
+          T sum = T(0);
+#pragma unroll
+          for (int q = 0; q < 4; ++q) sum += red[j][(2 * ta + (q & 1)) + 64 * (2 * tb + (q >> 1))];
+          fc[R * L.k + c0 + j] = sum;
+        }
+      }
+    } else if (t < 32 && X0 + t < c.nx) {
       const int64_t R = (X0 + t) + c.sy * Y + c.sz * Z;
 #pragma unroll
       for (int j = 0; j < CW; ++j) {
@@ -669,18 +684,20 @@ void vcycle(bkts_ctx ctx, MgHier& h, int k, double a, double b, const T* f, T* z
     const LvArgs<T> L = lv_args<T>(lf, k, a, b);
     const Geo gc = geo_of(lc);
     const int gx = (lc.n[0] + 31) / 32;
-    const int64_t nbr = (int64_t)gx * lc.n[1] * lc.n[2];
+    const bool flat = lf.n[2] == 1;  // 2-D (or 1-D) level: strips of two coarse rows
+    const int64_t nbr = flat ? (int64_t)gx * ((lc.n[1] + 1) / 2) : (int64_t)gx * lc.n[1] * lc.n[2];
     BKTS_REQUIRE(nbr < ((int64_t)1 << 31), "multigrid: grid too large for the restriction launch");
     // algorithmic bytes: f, the inverse diagonal and the 3 coupling arrays read, the coarse f written
     ProfScope prof(ctx, l == 0 ? BKTS_K_MG_RESTRICT : BKTS_K_MG_COARSE,
                    sv * (1.0 * lf.N * k + 4.0 * lf.N + 1.0 * lc.N * k));
     const dim3 gr((unsigned)nbr);
+    auto go = [&](auto kernel) { launch(ctx, kernel, gr, dim3(256), 0, L, gc, gx, (const T*)fb[l], fb[l + 1]); };
     if (cw == 4)
-      launch(ctx, (mg_restrict_kernel<T, 4>), gr, dim3(256), 0, L, gc, gx, (const T*)fb[l], fb[l + 1]);
+      flat ? go(mg_restrict_kernel<T, 4, true>) : go(mg_restrict_kernel<T, 4, false>);
     else if (cw == 2)
-      launch(ctx, (mg_restrict_kernel<T, 2>), gr, dim3(256), 0, L, gc, gx, (const T*)fb[l], fb[l + 1]);
+      flat ? go(mg_restrict_kernel<T, 2, true>) : go(mg_restrict_kernel<T, 2, false>);
     else
-      launch(ctx, (mg_restrict_kernel<T, 1>), gr, dim3(256), 0, L, gc, gx, (const T*)fb[l], fb[l + 1]);
+      flat ? go(mg_restrict_kernel<T, 1, true>) : go(mg_restrict_kernel<T, 1, false>);
   }
   {
     TailArgs<T> A{};
