@@ -89,9 +89,9 @@ def test_mg_block_solve_matches_direct(env, gi, k, precision):
         bkts.bkts_op_destroy(op)
 
 
-@pytest.mark.parametrize("gi", range(len(GRIDS)))
-@pytest.mark.parametrize("k", [1, 4])
-@pytest.mark.parametrize("krylov,precision", [(2, 0), (2, 1), (1, 0)])
+@pytest.mark.parametrize("gi,k,krylov,precision", [(gi, k, kr, pr) for gi in range(len(GRIDS)) for k in (1, 4)
+                                                    for kr, pr in ((2, 0), (2, 1), (1, 0))]
+                         + [(0, 32, 2, 1), (7, 32, 2, 1), (1, 12, 1, 0)])
 def test_mg_gmres_bicgstab_block_solve_matches_direct(env, gi, k, precision, krylov):
     """Block GMRES and BiCGStab right-preconditioned by the V-cycle reach the direct solution.  (FP32
     GMRES(m) is left out at this 1e-11 target: a restart recomputes the residual in FP32, which on
