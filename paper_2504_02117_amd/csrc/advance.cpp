@@ -95,6 +95,16 @@ bkts_stepper_s::bkts_stepper_s(bkts_ctx c, bkts_op o, bkts_tc t, const double* y
     BKTS_HIP(hipMemcpyAsync(mats.p, h.data(), sizeof(double) * h.size(), hipMemcpyHostToDevice, ctx->stream));
     ctx->sync();  // h is pageable and goes out of scope
   }
+  if (mi == 1 && !tc->fully_implicit && !tc->explicit_first && k >= 2) {
+    const double it = 1.0 / tc->tau;
+    bool ie = true;
+    for (int i = 0; i < k && ie; ++i)
+      for (int j = 0; j < k && ie; ++j) {
+        const double a1 = i == j ? it : (j == i - 1 ? -it : 0.0), a2 = i == j ? 1.0 : 0.0;
+        ie = std::fabs(tc->A1[0][i * k + j] - a1) <= 1e-14 * it && tc->A2[0][i * k + j] == a2;
+      }
+    ie_window = ie;
+  }
   // Algorithm 1 starts from Y = (y0, ..., y0)
   broadcast_cols(ctx, N, k, y0, Y.as<double>(), k);
   BKTS_HIP(hipMemcpyAsync(yprev.p, y0, sizeof(double) * N, hipMemcpyDeviceToDevice, ctx->stream));
@@ -167,6 +177,7 @@ bkts_status bkts_stepper_s::advance(int n_steps, const bkts_solve_opts& inner, d
   std::vector<char> active(k, 1), frozen(k, 0);
   bkts_status status = BKTS_OK;
   int done = 0;
+  bool shifted = false;  // the window was shifted after a full residual of the unshifted window
   while (done < n_steps) {
     // B0 columns of the window: stages q = phase + i of the front step (Sec. 2.2)
     const int nb0 = std::min(mi - phase, k);
@@ -220,6 +231,13 @@ bkts_status bkts_stepper_s::advance(int n_steps, const bkts_solve_opts& inner, d
         for (int i = 0; i < nb0 && i < 8; ++i) cols[i] = (off + i) % k;
         double* m = matsp;
         nl_residual(ctx, *nl, k, Yp, k, m, m + k * k, B0p, mi, nb0, cols, Rp, k, nrmp);
+      } else if (it == 0 && shifted && ie_window) {
+        // after an implicit-Euler shift the kept columns, the new front included (its B0 term is the
+        // accepted column it was coupled to), keep their residuals and norms; only the duplicated
+        // last column, whose time difference is zero, needs R = K y - b
+        const int c = (off + k - 1) % k;
+        spmm(ctx, *op, BKTS_F64, 1, -1.0, bsrc, 1, 0.0, Yp + c, k, 1.0, Rp + c, k);
+        colnorms2(ctx, BKTS_F64, N, 1, Rp + c, k, nrmp + c);
       } else {
         window_residual(ctx, *op, *tc, phase, off, Yp, k, B0p, mi, nb0, Rp, k, nrmp, matsp);
       }
@@ -267,11 +285,11 @@ bkts_status bkts_stepper_s::advance(int n_steps, const bkts_solve_opts& inner, d
       std::fill(active.begin(), active.end(), 1);
     }
     // accept the front stage (the whole front step for a fully implicit tableau)
-    bool shifted = false;  // the front slot already holds the duplicated last column
+    bool shifted_now = false;  // the front slot already holds the duplicated last column
     if (tc->fully_implicit || phase == mi - 1) {
       if (nacc == 1) {  // take the front column and duplicate the last into its slot, in one pass
         take_and_replace_col(ctx, N, Yp, k, off, (off + k - 1) % k, yp);
-        shifted = true;
+        shifted_now = true;
       } else {
         extract_col(ctx, N, Yp, k, (off + nacc - 1) % k, yp);
       }
@@ -291,9 +309,10 @@ bkts_status bkts_stepper_s::advance(int n_steps, const bkts_solve_opts& inner, d
       ++phase;
     }
     for (int i = 0; i < nacc; ++i) {  // shift: duplicate the last column
-      if (!shifted) copy_col(ctx, N, Yp, k, (off + k - 1) % k, off);
+      if (!shifted_now) copy_col(ctx, N, Yp, k, (off + k - 1) % k, off);
       off = (off + 1) % k;
     }
+    shifted = true;
   }
   ctx->sync();
   ri.accepted_steps = done;

@@ -14,6 +14,9 @@ struct bkts_stepper_s {
   bkts::DevBuf Y, R, V, B0, fst, yprev, fyn, tmp, nrm;
   bkts::DevBuf mats;  // window matrices (A1, A2, row sums of A2) of every (phase, off), in that order
   int off = 0;       // physical column of logical column 0
+  // implicit Euler windows (A1 = (I - L)/tau, A2 = I, one stage): a shift leaves the residual of
+  // every kept column unchanged, and the duplicated last column's residual is K y - b
+  bool ie_window = false;
   int phase = 0;     // implicit-stage index of the front column within its step
   long accepted = 0; // accepted steps since creation
   bkts_stepper_s(bkts_ctx c, bkts_op o, bkts_tc t, const double* y0, bkts_nlop n = nullptr);
