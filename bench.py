@@ -46,7 +46,7 @@ def parse():
                    help="timed runs of the headline (fresh stepper, warmup + timed steps each); value = median")
     p.add_argument("--err-steps", type=int, default=3,
                    help="untimed headline steps from u0 checked against the oracle (0 = skip)")
-    p.add_argument("--full-out", default="gpurun_out/bench_full.json",
+    p.add_argument("--full-out", default="bench_out/bench_full.json",
                    help="where the full JSON record goes (the stdout line is the compact summary)")
     p.add_argument("--n", type=int, default=128)
     p.add_argument("--k", type=int, default=4)
@@ -895,7 +895,7 @@ def compact_line(out, full_path):
 def main():
     a = parse()
     if a.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only: the sharded path (halo exchange over RCCL, "
+        print(json.dumps({"error": "bench.py runs on one GPU only: the sharded path (halo exchange over RCCL, "
                                    "k x k all-reduce) is designed but not built; run with --gpus 1"}))
         sys.exit(2)
     import numpy as np

@@ -57,7 +57,7 @@ def _record():
 
 def test_compact_line_fields_and_size():
     out = _record()
-    line = bench.compact_line(out, os.path.join(ROOT, "gpurun_out", "bench_full.json"))
+    line = bench.compact_line(out, os.path.join(ROOT, "bench_out", "bench_full.json"))
     assert "\n" not in line
     assert len(line.encode()) < 4096, len(line.encode())
     d = json.loads(line)
