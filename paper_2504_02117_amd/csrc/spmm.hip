@@ -35,6 +35,13 @@ __device__ __forceinline__ Vec<T, V> vload(const T* p) {
       r.v[2] = q.z;
       r.v[3] = q.w;
     }
+  } else if constexpr (sizeof(T) * V == 32) {  // two 16-byte loads
+    const Vec<T, V / 2> lo = vload<T, V / 2>(p), hi = vload<T, V / 2>(p + V / 2);
+#pragma unroll
+    for (int i = 0; i < V / 2; ++i) {
+      r.v[i] = lo.v[i];
+      r.v[V / 2 + i] = hi.v[i];
+    }
   } else {
 #pragma unroll
     for (int i = 0; i < V; ++i) r.v[i] = p[i];
@@ -72,6 +79,15 @@ __device__ __forceinline__ void vstore_nt(T* p, const Vec<T, V>& r) {
       const f4 q = {r.v[0], r.v[1], r.v[2], r.v[3]};
       __builtin_nontemporal_store(q, reinterpret_cast<f4*>(p));
     }
+  } else if constexpr (sizeof(T) * V == 32) {  // two 16-byte stores
+    Vec<T, V / 2> lo, hi;
+#pragma unroll
+    for (int i = 0; i < V / 2; ++i) {
+      lo.v[i] = r.v[i];
+      hi.v[i] = r.v[V / 2 + i];
+    }
+    vstore_nt<T, V / 2>(p, lo);
+    vstore_nt<T, V / 2>(p + V / 2, hi);
   } else {
 #pragma unroll
     for (int i = 0; i < V; ++i) __builtin_nontemporal_store(r.v[i], p + i);
@@ -355,7 +371,18 @@ template <typename T, int KP>
 void launch_kp(bkts_ctx ctx, const bkts_op_s& op, const SpmmArgs<T>& a, bool vec_ok) {
   constexpr int VMAX = 16 / sizeof(T);
   if constexpr (KP >= VMAX) {
-    if (vec_ok) return launch_fmt<T, KP, VMAX>(ctx, op, a);
+    if (vec_ok) {
+      // Rows of 64 bytes or more on the uniform-width SELL path: 32 bytes per lane (two 16-byte
+      // loads), half the lanes per row and twice the rows per workgroup.  On the 128^3 7-point
+      // operator against 16 bytes per lane: FP64 k = 8 99 us (117), k = 16 181 us (201), k = 32
+      // 363 us (435); FP32 k = 16 89 us (94), k = 32 154 us (187).  Rows of 32 bytes lose with it
+      // (FP64 k = 4 69 us against 65.5, FP32 k = 8 55 us against 46).
+      if constexpr (KP * sizeof(T) >= 64) {
+        if (op.format == BKTS_FMT_SELL && op.sell_uniform_w > 0 && op.sell_uniform_w <= kUnroll)
+          return launch_fmt<T, KP, 2 * VMAX>(ctx, op, a);
+      }
+      return launch_fmt<T, KP, VMAX>(ctx, op, a);
+    }
   }
   launch_fmt<T, KP, 1>(ctx, op, a);
 }
